@@ -1,0 +1,37 @@
+"""FP64 CPU oracle for the idealized binned power spectrum and bispectrum.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()``
+and the ``cpu_baseline`` leg of ``bench.py``, never by the product package.
+It shares no code with the HIP path.
+
+Parity status of each function (what pins it is in ``tests/test_oracle.py``):
+
+* ``power_spectrum``       pinned: Parseval, plane-wave closed form,
+                           invariances, statistical recovery of the input P.
+* ``triangle_triplets``    pinned: the 196 (= 2 x 98) configurations printed
+                           for 8 bins in the bispectrum validation set-up.
+* ``triangle_counts``      pinned: brute-force mode counting, integrality.
+* ``bispectrum``           pinned: brute-force k-triplet sums, plane-wave
+                           closed form, invariances, Gaussian null and the
+                           tree-level bispectrum of a quadratic field.
+"""
+
+from .polyspec import (  # noqa: F401
+    Result,
+    bin_of_modes,
+    bispectrum,
+    count_sample,
+    dft,
+    filtered_fields,
+    freqs,
+    idft,
+    kmag2,
+    max_component,
+    mode_counts,
+    power_spectrum,
+    triangle_counts,
+    triangle_triplets,
+    triplet_sums_sample,
+    unit_fields,
+)
+from .brute import brute_sums  # noqa: F401

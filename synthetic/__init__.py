@@ -1,0 +1,92 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the bench.
+
+This module only *creates* inputs: Gaussian random fields with a prescribed
+power spectrum and the quadratic (local-type) non-Gaussian field built from
+them.  It holds none of the estimator's arithmetic (no binning, no shell
+filtering, no triplet sums); the oracle and the HIP path each implement that
+on their own.
+
+Field model (the workloads of the validation section, Sec. VI, are Gaussian
+random fields with a known power spectrum; the quadratic term gives a known
+tree-level bispectrum):
+
+    g  : Gaussian, <|g(k)|^2> = V P(k), P(k) = 2e4 (k/0.02)^-1.5 exp(-(k/0.3)^2)
+    d  = g + f_NL (g^2 - mean(g^2))
+
+The generator draws ``numpy.random.default_rng(seed).standard_normal`` white
+noise in float64, shapes it in Fourier space with sqrt(P N_pix / V), and
+returns float64; callers that feed the GPU round it to float32 once and give
+the same float32 array to the oracle.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "pk_model",
+    "gaussian_field",
+    "quadratic_field",
+    "kf_edges",
+    "field_for",
+    "CONFIGS",
+]
+
+
+def pk_model(k: np.ndarray) -> np.ndarray:
+    """Input power spectrum P(k) in (Mpc/h)^3, k in h/Mpc; P(0) = 0."""
+    k = np.asarray(k, dtype=np.float64)
+    out = np.zeros_like(k)
+    m = k > 0
+    out[m] = 2e4 * (k[m] / 0.02) ** -1.5 * np.exp(-((k[m] / 0.3) ** 2))
+    return out
+
+
+def _kmag(n: int, box: float) -> np.ndarray:
+    """|k| on the rfft half-grid, in h/Mpc."""
+    kf = 2.0 * np.pi / box
+    f = np.fft.fftfreq(n, d=1.0 / n)
+    fz = np.arange(n // 2 + 1, dtype=np.float64)
+    return kf * np.sqrt(f[:, None, None] ** 2 + f[None, :, None] ** 2 + fz[None, None, :] ** 2)
+
+
+def gaussian_field(n: int, box: float, seed: int, pk=pk_model) -> np.ndarray:
+    """Gaussian random field on an n^3 periodic grid of side ``box`` (float64)."""
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal((n, n, n))
+    wk = np.fft.rfftn(w)
+    npix = float(n) ** 3
+    vol = float(box) ** 3
+    amp = np.sqrt(pk(_kmag(n, box)) * npix / vol)
+    amp[0, 0, 0] = 0.0
+    return np.fft.irfftn(wk * amp, s=(n, n, n), axes=(0, 1, 2))
+
+
+def quadratic_field(n: int, box: float, fnl: float, seed: int, pk=pk_model) -> np.ndarray:
+    """d = g + f_NL (g^2 - mean(g^2)) with g from :func:`gaussian_field`."""
+    g = gaussian_field(n, box, seed, pk)
+    return g + fnl * (g * g - np.mean(g * g))
+
+
+def kf_edges(n_bins: int, width: float = 2.0, start: float = 1.0) -> np.ndarray:
+    """Linear bin edges in units of the fundamental k_f: start + width*j."""
+    return start + width * np.arange(n_bins + 1, dtype=np.float64)
+
+
+# The five workloads (grid, box in Mpc/h, bins, f_NL, seed).  Bins are of
+# width 2 k_f starting at k_f.
+CONFIGS = {
+    "c1": dict(n=32, box=1000.0, n_bins=8, fnl=0.5, seed=0),
+    "c2": dict(n=128, box=2000.0, n_bins=20, fnl=1.0, seed=1),
+    "c3": dict(n=256, box=2000.0, n_bins=30, fnl=1.0, seed=2),
+}
+
+
+def field_for(name: str, seed: int | None = None) -> tuple[np.ndarray, dict]:
+    """Float32 input field for a named workload, plus its parameters."""
+    cfg = dict(CONFIGS[name])
+    if seed is not None:
+        cfg["seed"] = seed
+    d = quadratic_field(cfg["n"], cfg["box"], cfg["fnl"], cfg["seed"]).astype(np.float32)
+    cfg["edges"] = kf_edges(cfg["n_bins"])
+    return d, cfg

@@ -1,0 +1,333 @@
+"""Pins for the FP64 oracle against what the paper and mathematics fix.
+
+None of these re-type the oracle's formulas: each compares it with an
+independent route (brute-force mode loops, closed forms for plane waves,
+exact invariances, the count printed in the paper, statistical recovery of
+a known input power spectrum and tree-level bispectrum).
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from synthetic import gaussian_field, kf_edges, pk_model, quadratic_field
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _golden(name):
+    vals = {}
+    with open(os.path.join(HERE, "golden", name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, v = line.split("=")
+            vals[k.strip()] = [float(x) for x in v.split()]
+    return vals
+
+
+# ---------------------------------------------------------------- binning
+
+
+def test_triplet_count_matches_paper_setup():
+    g = _golden("bk_validation_setup.txt")
+    edges = np.array(g["edges"])
+    trips = oracle.triangle_triplets(edges)
+    assert len(trips) * int(g["n_multipoles"][0]) == int(g["n_configurations"][0])
+
+
+def test_triplet_count_is_scale_free_and_ordered():
+    # config-1 edges (width 2 k_f from k_f) give the same triangle rule
+    trips = oracle.triangle_triplets(kf_edges(8))
+    assert len(trips) == 98
+    # order: c fastest, then b, then a; a <= b <= c
+    assert np.all(trips[:, 0] <= trips[:, 1]) and np.all(trips[:, 1] <= trips[:, 2])
+    keys = trips[:, 0] * 10000 + trips[:, 1] * 100 + trips[:, 2]
+    assert np.all(np.diff(keys) > 0)
+    # larger configurations
+    assert len(oracle.triangle_triplets(kf_edges(20))) == 1015
+    assert len(oracle.triangle_triplets(kf_edges(30))) == 3035
+
+
+def test_mode_counts_by_explicit_loops():
+    n = 12
+    edges = np.array([1.0, 2.5, 4.0, 6.0])
+    want = np.zeros(3, dtype=np.int64)
+    for i in range(n):
+        for j in range(n):
+            for k in range(n):
+                f = [v if v < n // 2 else v - n for v in (i, j, k)]
+                r = np.sqrt(f[0] ** 2 + f[1] ** 2 + f[2] ** 2)
+                for b in range(3):
+                    if edges[b] <= r < edges[b + 1]:
+                        want[b] += 1
+    assert np.array_equal(oracle.mode_counts(n, edges), want)
+    # a mode exactly on an edge goes to the upper bin (half-open bins)
+    idx = oracle.bin_of_modes(n, np.array([1.0, 3.0, 5.0]))
+    assert idx[3, 0, 0] == 1 and idx[1, 0, 0] == 0
+
+
+# ------------------------------------------------------ brute-force pins
+
+
+@pytest.mark.parametrize(
+    "n,edges",
+    [
+        (8, [1.0, 2.0, 3.0, 4.0]),  # aliases: closure wraps modulo N
+        (12, [1.0, 2.5, 4.0, 5.5]),
+        (16, [2.0, 3.0, 4.5]),
+    ],
+)
+def test_separable_form_equals_brute_force(n, edges):
+    edges = np.array(edges)
+    rng = np.random.default_rng(n)
+    d = rng.standard_normal((n, n, n))
+    trips = oracle.triangle_triplets(edges)
+    sums, cnt = oracle.brute_sums(d, edges, trips)
+    # counts: exact integers
+    T, raw = oracle.triangle_counts(n, edges, trips)
+    assert np.array_equal(T, cnt)
+    assert np.max(np.abs(raw - T)) < 1e-6
+    # the imaginary part of the closed-triangle sum vanishes for a real field
+    assert np.all(np.abs(sums.imag) <= 1e-9 * np.abs(sums).max())
+    # separable real-space sum  N_pix^2 sum_x G_a G_b G_c  ==  sum_closed D D D
+    G = oracle.filtered_fields(d, edges)
+    npix = float(n) ** 3
+    sep = np.array([npix**2 * np.sum(G[a] * G[b] * G[c]) for a, b, c in trips])
+    scale = np.abs(sums.real).max()
+    assert np.max(np.abs(sep - sums.real)) <= 1e-12 * scale
+    # and the estimator normalisation B = V^2/N_pix^3 sum DDD / T
+    box = 100.0
+    res = oracle.bispectrum(d.astype(np.float64), box, edges)
+    keep = cnt > 0
+    want = box**6 / npix**3 * sums.real[keep] / cnt[keep]
+    assert np.allclose(res.bk, want, rtol=1e-11, atol=1e-12 * np.abs(want).max())
+
+
+def test_counts_are_integers_at_32():
+    edges = kf_edges(8)
+    T, raw = oracle.triangle_counts(32, edges)
+    assert np.max(np.abs(raw - T)) < 1e-6
+    assert T.min() > 0
+
+
+# ---------------------------------------------------- closed-form pins
+
+
+def test_power_parseval_full_cover():
+    n, box = 16, 300.0
+    rng = np.random.default_rng(3)
+    d = rng.standard_normal((n, n, n))
+    # bins covering every non-zero mode: |n| in [0.5, N sqrt(3)/2 + 1)
+    edges = np.arange(0.5, n * np.sqrt(3) / 2 + 1.5, 1.0)
+    nm = oracle.mode_counts(n, edges)
+    keep = nm > 0
+    edges_ok = np.concatenate([edges[:-1][keep], [edges[-1]]])
+    # merge empty bins away by rebuilding edges from non-empty shells
+    nm2 = oracle.mode_counts(n, edges_ok)
+    assert nm2.sum() == n**3 - 1
+    pk = oracle.power_spectrum(d, box, edges_ok)
+    npix = float(n) ** 3
+    lhs = np.sum(nm2 * pk) * npix**2 / box**3
+    rhs = npix * np.sum(d * d) - np.sum(d) ** 2
+    assert abs(lhs - rhs) <= 1e-12 * rhs
+
+
+def test_power_plane_wave():
+    n, box = 32, 1000.0
+    edges = kf_edges(8)
+    x = np.arange(n)
+    n0 = (2, 3, 1)  # |n0| = sqrt(14) = 3.74 -> bin 1, [3, 5)
+    ph = 2 * np.pi * (n0[0] * x[:, None, None] + n0[1] * x[None, :, None] + n0[2] * x[None, None, :]) / n
+    d = np.cos(ph)
+    pk = oracle.power_spectrum(d, box, edges)
+    nm = oracle.mode_counts(n, edges)
+    want = np.zeros(8)
+    want[1] = box**3 / (2 * nm[1])
+    assert np.allclose(pk, want, rtol=1e-12, atol=1e-12 * want.max())
+
+
+def _plane_wave_triple(n, edges):
+    """Three non-collinear waves n1 + n2 + n3 = 0 in three distinct bins."""
+    idx = oracle.bin_of_modes(n, edges)
+    rng = np.random.default_rng(11)
+    for _ in range(10000):
+        n1 = rng.integers(-6, 7, size=3)
+        n2 = rng.integers(-6, 7, size=3)
+        n3 = -(n1 + n2)
+        if np.linalg.matrix_rank(np.stack([n1, n2])) < 2:
+            continue
+        bins = [int(idx[tuple(v % n)]) for v in (n1, n2, n3)]
+        if min(bins) < 0 or len(set(bins)) < 3:
+            continue
+        # no other sign combination closes
+        ok = True
+        for s in [(1, 1, -1), (1, -1, 1), (-1, 1, 1)]:
+            if np.all((s[0] * n1 + s[1] * n2 + s[2] * n3) % n == 0):
+                ok = False
+        if ok:
+            return (n1, n2, n3), bins
+    raise RuntimeError("no triple found")
+
+
+def test_bispectrum_plane_waves():
+    n, box = 32, 1000.0
+    edges = kf_edges(8)
+    (n1, n2, n3), bins = _plane_wave_triple(n, edges)
+    x = np.arange(n)
+    d = np.zeros((n, n, n))
+    for v in (n1, n2, n3):
+        ph = 2 * np.pi * (v[0] * x[:, None, None] + v[1] * x[None, :, None] + v[2] * x[None, None, :]) / n
+        d += np.cos(ph)
+    res = oracle.bispectrum(d, box, edges)
+    a, b, c = sorted(bins)
+    t = [i for i, tr in enumerate(res.triplets) if tuple(tr) == (a, b, c)]
+    assert len(t) == 1
+    want = box**6 / (4.0 * res.counts[t[0]])
+    assert abs(res.bk[t[0]] - want) <= 1e-11 * want
+
+
+# ------------------------------------------------------------ invariances
+
+
+def test_invariances_and_scaling():
+    n, box = 32, 1000.0
+    edges = kf_edges(8)
+    d = quadratic_field(n, box, 0.5, 7)
+    base = oracle.bispectrum(d, box, edges)
+    T = None
+    variants = [
+        np.roll(d, (3, -5, 7), axis=(0, 1, 2)),  # integer translation
+        np.transpose(d, (2, 0, 1)),  # axis permutation
+        np.roll(d[::-1, ::-1, ::-1], 1, axis=(0, 1, 2)),  # reflection x -> -x
+        d + 0.37,  # a constant only touches k = 0, which lies in no bin
+    ]
+    for v in variants:
+        r = oracle.bispectrum(np.ascontiguousarray(v), box, edges, counts=T)
+        sc = np.abs(base.absnorm)
+        assert np.all(np.abs(r.bk - base.bk) <= 1e-12 * sc)
+        assert np.allclose(r.pk, base.pk, rtol=1e-12)
+    # scaling by 2 is exact in binary floating point
+    r2 = oracle.bispectrum(2.0 * d, box, edges)
+    assert np.array_equal(r2.pk, 4.0 * base.pk)
+    assert np.array_equal(r2.bk, 8.0 * base.bk)
+
+
+# ------------------------------------------------------------ statistics
+
+
+def _grid_binned_pk(n, box, edges):
+    kf = 2 * np.pi / box
+    k = kf * np.sqrt(oracle.kmag2(n).astype(np.float64))
+    idx = oracle.bin_of_modes(n, edges)
+    p = pk_model(k)
+    return np.array([p[idx == b].mean() for b in range(len(edges) - 1)])
+
+
+def test_power_recovers_input_statistically():
+    n, box = 32, 1000.0
+    edges = kf_edges(8)
+    runs = np.array([oracle.power_spectrum(gaussian_field(n, box, s), box, edges) for s in range(100)])
+    want = _grid_binned_pk(n, box, edges)
+    z = (runs.mean(0) - want) / (runs.std(0, ddof=1) / np.sqrt(len(runs)))
+    assert np.all(np.abs(z) < 4.5), z
+
+
+def test_tree_level_bispectrum_and_gaussian_null():
+    """Linear-in-f_NL coefficient of B for d = g + f(g^2 - <g^2>) has mean
+    2 (P1 P2 + P2 P3 + P3 P1) averaged over the closed triangles in the bin;
+    the f-independent part (a Gaussian field) has mean zero."""
+    n, box, f = 32, 1000.0, 0.5
+    edges = kf_edges(8)
+    trips = oracle.triangle_triplets(edges)
+    T, _ = oracle.triangle_counts(n, edges, trips)
+    c0s, c1s = [], []
+    for s in range(120):
+        g = gaussian_field(n, box, s)
+        g2 = g * g - np.mean(g * g)
+        B = {}
+        for m in (-2, -1, 1, 2):
+            B[m] = oracle.bispectrum(g + m * f * g2, box, edges, trips, T).bk
+        c1s.append((8 * (B[1] - B[-1]) - (B[2] - B[-2])) / (12 * f))
+        c0s.append((4 * (B[1] + B[-1]) - (B[2] + B[-2])) / 6)
+    c1s, c0s = np.array(c1s), np.array(c0s)
+    # expectation: sum over closed triangles of 2(P1P2+...) / T, computed as
+    # a direct sum over mode pairs binned by |n| (brute force over shells)
+    kf = 2 * np.pi / box
+    P = pk_model(kf * np.sqrt(oracle.kmag2(n).astype(np.float64)))
+    idx = oracle.bin_of_modes(n, edges)
+    H = oracle.unit_fields(n, edges)
+    A = np.stack([oracle.idft(np.where(idx == b, P, 0.0)).real for b in range(len(edges) - 1)])
+    want = np.array(
+        [
+            2
+            * (np.sum(A[a] * A[b] * H[c]) + np.sum(A[a] * H[b] * A[c]) + np.sum(H[a] * A[b] * A[c]))
+            / np.sum(H[a] * H[b] * H[c])
+            for a, b, c in trips
+        ]
+    )
+    se1 = c1s.std(0, ddof=1) / np.sqrt(len(c1s))
+    z1 = (c1s.mean(0) - want) / se1
+    assert np.all(np.abs(z1) < 4.5), np.abs(z1).max()
+    se0 = c0s.std(0, ddof=1) / np.sqrt(len(c0s))
+    z0 = c0s.mean(0) / se0
+    assert np.all(np.abs(z0) < 4.5), np.abs(z0).max()
+    # the signal is detected: the tree-level term is many standard errors
+    assert np.median(np.abs(want) / se1) > 3
+
+
+def test_tree_expectation_matches_mode_sum_on_tiny_grid():
+    """The separable expectation used above equals an explicit loop over
+    closed mode triangles (n = 8, all bins)."""
+    n, box = 8, 200.0
+    edges = np.array([1.0, 2.0, 3.0, 4.0])
+    kf = 2 * np.pi / box
+    P = pk_model(kf * np.sqrt(oracle.kmag2(n).astype(np.float64)))
+    idx = oracle.bin_of_modes(n, edges)
+    trips = oracle.triangle_triplets(edges)
+    H = oracle.unit_fields(n, edges)
+    A = np.stack([oracle.idft(np.where(idx == b, P, 0.0)).real for b in range(3)])
+    for a, b, c in trips:
+        tot, cnt = 0.0, 0
+        for i1 in np.argwhere(idx == a):
+            for i2 in np.argwhere(idx == b):
+                i3 = (-i1 - i2) % n
+                if idx[tuple(i3)] == c:
+                    p1, p2, p3 = P[tuple(i1)], P[tuple(i2)], P[tuple(i3)]
+                    tot += 2 * (p1 * p2 + p2 * p3 + p1 * p3)
+                    cnt += 1
+        if cnt == 0:
+            continue
+        sep = 2 * (np.sum(A[a] * A[b] * H[c]) + np.sum(A[a] * H[b] * A[c]) + np.sum(H[a] * A[b] * A[c])) / np.sum(
+            H[a] * H[b] * H[c]
+        )
+        assert abs(sep - tot / cnt) <= 1e-10 * abs(tot / cnt)
+
+
+def test_aliasing_reading_modulo_n():
+    """At N = 32 with e_top = 17 some closures wrap around the grid
+    (3 * 16 >= 32): the count includes them, matching the brute force."""
+    n = 8
+    edges = np.array([2.0, 3.0, 3.5])
+    trips = oracle.triangle_triplets(edges)
+    d = np.random.default_rng(5).standard_normal((n, n, n))
+    _, cnt = oracle.brute_sums(d, edges, trips)
+    T, _ = oracle.triangle_counts(n, edges, trips)
+    assert np.array_equal(T, cnt)
+    # without wrap-around the count would differ for at least one triplet
+    idx = oracle.bin_of_modes(n, edges)
+    f = oracle.freqs(n)
+    nowrap = []
+    for a, b, c in trips:
+        m = 0
+        for i1 in np.argwhere(idx == a):
+            for i2 in np.argwhere(idx == b):
+                v = -(f[i1] + f[i2])
+                if np.all(np.abs(v) < n // 2) or np.all((v >= -n // 2) & (v < n // 2)):
+                    if idx[tuple(v % n)] == c:
+                        m += 1
+        nowrap.append(m)
+    assert not np.array_equal(np.array(nowrap), cnt)
