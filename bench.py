@@ -1,0 +1,232 @@
+#!/usr/bin/env python3
+"""Throughput of the idealized P(k) + bispectrum hot path on one MI355X.
+
+One step = one pass of the whole path over one synthetic field: forward r2c
+FFT, shell-binned power spectrum, per-bin shell-filtered inverse FFTs,
+triplet contraction and normalisation (pb3_polyspectra).  The plan (bins,
+triplets, FP64 triangle counts) is built once, outside the timed region;
+the input field is resident in HBM before timing starts.
+
+Workload: 256^3 grid, L = 2000 Mpc/h, 30 bins of width 2 k_f from k_f
+(3035 triangle-valid triplets), d = g + f_NL (g^2 - <g^2>) with f_NL = 1.
+
+Prints ONE JSON line (rank 0).  ``--gpus`` above 1 is refused: this build
+runs on one GPU.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "bispectra/s at 256³×30 bins, mixed vs FP32 at fixed error; p50/p99 latency"
+
+HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
+# plain (non-packed) FP32 vector FMA: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+FP32_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def _cores() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def stage_work(plan_info: dict, precision: str) -> dict:
+    """Algorithmic bytes (HBM-bound stages) or flops (contraction) of one
+    launch of each stage, from the plan geometry."""
+    n, kz, lc, m, nb = plan_info["N"], plan_info["Kz"], plan_info["Lc"], plan_info["M"], plan_info["nb"]
+    geom = plan_info["geom"]
+    c8, f4 = 8, 4
+    w = {}
+    w["fwd_z"] = ("hbm", n**3 * f4 + n * n * kz * c8)
+    w["fwd_y"] = ("hbm", n * n * kz * c8 + n * lc * kz * c8)
+    w["fwd_x"] = ("hbm", n * lc * kz * c8 + lc * lc * kz * c8)
+    w["power"] = ("hbm", plan_info["n_modes_half"] * (4 + c8))
+    w["inv_x"] = ("hbm", sum(ly * ly * kzn * c8 + m * ly * kzn * c8 for ly, kzn in geom))
+    w["inv_y"] = ("hbm", sum(m * ly * kzn * c8 + m * m * kzn * c8 for ly, kzn in geom))
+    w["inv_z"] = ("hbm", sum(m * m * kzn * c8 + m**3 * f4 for ly, kzn in geom))
+    # the recast GEMM: every pair a <= b against every c, over the M^3 voxels
+    n_pairs = nb * (nb + 1) // 2
+    w["contract"] = ("flops", 2.0 * n_pairs * nb * m**3)
+    w["reduce"] = ("hbm", 0)
+    return w
+
+
+def plan_geometry(n, box, edges):
+    """Host-side geometry the stage model needs (same rules as the library)."""
+    import paper_2404_07249_amd as pb3
+
+    hp = pb3.Plan(n, box, edges, host_only=True)
+    m = hp.contract_grid
+    e = np.asarray(edges, dtype=np.float64)
+    thr = np.ceil(e * e).astype(np.int64)
+    k = int(np.floor(np.sqrt(max(thr[-1] - 1, 0))))
+    k = min(k, n // 2)
+    full = k >= n // 2
+    kz = n // 2 + 1 if full else k + 1
+    lc = n if full else 2 * k + 1
+    geom = []
+    for b in range(len(e) - 1):
+        kb = min(int(np.floor(np.sqrt(max(thr[b + 1] - 1, 0)))), n // 2)
+        kpos = n // 2 - 1 if (full and kb == n // 2) else kb
+        geom.append((kb + kpos + 1, kb + 1))
+    _, _, nm = hp.bins()
+    return dict(N=n, M=m, Kz=kz, Lc=lc, nb=len(e) - 1, geom=geom, n_modes_half=int((nm.sum() + 1) // 2))
+
+
+def cpu_baseline(d32: np.ndarray, box: float, edges, n_trip_full: int, sample_trips: int = 300) -> dict:
+    """The FP64 oracle on the host cores: the forward FFT, the power
+    spectrum and all filtered fields in full, and the triplet sums for the
+    first ``sample_trips`` triplets, scaled to the full triplet count."""
+    import oracle
+
+    os.environ.setdefault("ORACLE_FFT_WORKERS", str(_cores()))
+    d = d32.astype(np.float64)
+    t0 = time.perf_counter()
+    oracle.power_spectrum(d, box, edges)
+    G = oracle.filtered_fields(d, edges)
+    t_fft = time.perf_counter() - t0
+    trips = oracle.triangle_triplets(edges)[:sample_trips]
+    t1 = time.perf_counter()
+    oracle.triple_sums(G, trips)
+    t_c = time.perf_counter() - t1
+    per = t_fft + t_c * (n_trip_full / len(trips))
+    return {
+        "value": 1.0 / per,
+        "unit": "bispectra/s",
+        "cores": _cores(),
+        "kind": "oracle",
+        "sample": (
+            f"one 256^3 field: FP64 forward FFT, P(k) and all {len(edges) - 1} filtered fields in full "
+            f"({t_fft:.2f} s), triplet sums for the first {len(trips)} of {n_trip_full} triplets "
+            f"({t_c:.2f} s) scaled to all; FFTs on {_cores()} threads, triplet sums numpy/BLAS"
+        ),
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--precision", choices=["mixed", "fp32"], default="mixed")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--latency-calls", type=int, default=50)
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(
+            json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported", "n_gpus": args.gpus}),
+            flush=True,
+        )
+        return 2
+
+    import torch
+
+    import paper_2404_07249_amd as pb3
+    from synthetic import field_for
+
+    d32, cfg = field_for("c3")
+    n, box, edges = cfg["n"], cfg["box"], cfg["edges"]
+    plan = pb3.Plan(n, box, edges, stage_timing=True)
+    info = plan_geometry(n, box, edges)
+    x = torch.from_numpy(d32).cuda()
+    pk = torch.empty(plan.n_bins, dtype=torch.float64, device="cuda")
+    bk = torch.empty(plan.n_triplets, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step(prec):
+        plan.polyspectra(x, precision=prec, pk_out=pk, bk_out=bk, stream=stream)
+
+    results = {}
+    for prec in (["fp32", "mixed"] if args.precision == "mixed" else ["mixed", "fp32"]):
+        for _ in range(args.warmup):
+            step(prec)
+        torch.cuda.synchronize()
+        plan.reset_stage_times()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        stages = plan.stage_times()
+        # per-call latency (each call synchronised), after the timed region
+        lat = []
+        for _ in range(args.latency_calls):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            step(prec)
+            b.record(stream)
+            b.synchronize()
+            lat.append(a.elapsed_time(b))
+        results[prec] = dict(dt=dt, stages=stages, lat=np.array(lat))
+    main_p = args.precision
+    r = results[main_p]
+    value = args.steps / r["dt"]
+    work = stage_work(info, main_p)
+    dom = max(r["stages"], key=lambda k: r["stages"][k][0])
+    kind, amount = work[dom]
+    ms = r["stages"][dom][0]
+    if kind == "flops":
+        peak = BF16_PEAK_TFLOPS if main_p == "mixed" else FP32_MFMA_PEAK_TFLOPS
+        achieved = amount / (ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": None}
+    else:
+        achieved = amount / (ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    roof["kernel"] = dom
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "bispectra/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * r["dt"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x3" if main_p == "mixed" else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "256^3 grid, L=2000 Mpc/h, 30 bins of width 2k_f from k_f, 3035 triplets, "
+            "quadratic field f_NL=1; P(k)+B(k1,k2,k3) per step",
+            "grid": n,
+            "contract_grid": plan.contract_grid,
+            "bins": plan.n_bins,
+            "triplets": plan.n_triplets,
+            "precision": main_p,
+        },
+        "latency_ms": {"p50": float(np.percentile(r["lat"], 50)), "p99": float(np.percentile(r["lat"], 99))},
+        "other_precision": {
+            p: {"value": args.steps / results[p]["dt"],
+                "latency_ms": {"p50": float(np.percentile(results[p]["lat"], 50)),
+                               "p99": float(np.percentile(results[p]["lat"], 99))}}
+            for p in results if p != main_p
+        },
+        "stages_ms": {k: round(v[0], 5) for k, v in r["stages"].items()},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(d32, box, edges, plan.n_triplets)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,139 @@
+/*
+ * pb3.h -- C ABI of the MI355X binned power-spectrum / bispectrum library.
+ *
+ * The library computes the idealized (periodic-box, uniform density,
+ * global line of sight, ell = 0) estimators of PolyBin3D (Philcox & Floss,
+ * arXiv:2404.07249) on one gfx950 GPU:
+ *
+ *   P_b     = (V / N_pix^2) (1/N_b) sum_{n in b} |D(n)|^2
+ *             -- eq. (pk-limit) over the ideal Fisher (bin volume,
+ *                eq. fish-ideal-continuous), Sec. III.D.1;
+ *   B_abc   = (V^2 / N_pix^3) (1/T_abc) sum_{n1+n2+n3=0} D(n1) D(n2) D(n3)
+ *           = (V^2 / N_pix) sum_x G_a G_b G_c / T_abc on the N grid
+ *             -- eq. (ideal-bk) and the closing full estimator of
+ *                Sec. IV.D.1, evaluated through the separable form
+ *                eq. (beta-def) with G_b = IDFT[Theta_b D] (eq. g-ell-def);
+ *   T_abc   = number of closed mode triangles in the three shells
+ *             -- N_0 of eq. (N-ell-def) with P_fid = 1 (Sec. IV.C.1).
+ *
+ * D(n) is the unnormalised DFT of the real field on the N^3 grid, n the
+ * integer wave-vector, |k| = k_f |n| with k_f = 2 pi / L.  Bins are half-open
+ * shells [e_b, e_{b+1}) in units of k_f, decided on the integer |n|^2.
+ * Triplets are (a <= b <= c) with e_c < e_{a+1} + e_{b+1}, ordered with c
+ * fastest; triplets with T_abc = 0 are dropped from the plan.
+ *
+ * Conventions for every entry point:
+ *  - every function returns pb3_status and never aborts; on failure
+ *    pb3_last_error() gives a thread-local message;
+ *  - device pointers are caller-owned; work is enqueued asynchronously on
+ *    the given HIP stream (a hipStream_t passed as void*, NULL = default
+ *    stream); host outputs are written before the call returns;
+ *  - a plan may have one call in flight at a time (its workspace is
+ *    shared); different plans may run concurrently on different streams.
+ */
+#ifndef PB3_H
+#define PB3_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pb3_plan pb3_plan;
+
+typedef enum {
+  PB3_OK = 0,
+  PB3_EINVAL = 1,        /* bad argument: null pointer, bad grid, unsorted edges, empty bin */
+  PB3_ENOMEM = 2,        /* device or host allocation failed, or bound workspace too small */
+  PB3_EDEVICE = 3,       /* a HIP call failed; message carries hipGetErrorString */
+  PB3_EUNSUPPORTED = 4,  /* grid length or bin count outside what the kernels implement */
+  PB3_EBUSY = 5          /* reserved */
+} pb3_status;
+
+typedef enum {
+  PB3_FP32 = 0,          /* FP32 FFTs and FP32 MFMA contraction */
+  PB3_MIXED_BF16X3 = 1   /* FP32 FFTs, contraction as split-BF16 (hi*hi + hi*lo + lo*hi) MFMA, FP32 accumulation */
+} pb3_precision;
+
+/* plan flags */
+#define PB3_FLAG_EDGES_HMPC   0x1u  /* edges are in h/Mpc (else in units of k_f) */
+#define PB3_FLAG_HOST_ONLY    0x2u  /* build host tables only (no device, no counts) */
+#define PB3_FLAG_FULL_GRID    0x4u  /* contract on the N grid even when a smaller alias-free grid exists */
+#define PB3_FLAG_STRICT       0x8u  /* fail with PB3_EINVAL if a triangle-valid triplet has T = 0 */
+#define PB3_FLAG_EXT_WORKSPACE 0x10u /* never allocate the large workspace; caller binds one */
+#define PB3_FLAG_STAGE_TIMING 0x20u /* record a HIP event pair around every kernel launch */
+
+/* Build a plan for a cubic grid.
+ *   grid[3]   grid points per side; all three equal, even, with prime
+ *             factors in {2, 3} (the FFT radices implemented);
+ *   box[3]    box side in Mpc/h; all three equal;
+ *   edges     n_edges >= 2 strictly increasing bin edges (k_f units, or
+ *             h/Mpc with PB3_FLAG_EDGES_HMPC, then snapped to the nearest
+ *             multiple of k_f/2 when within 1e-9 relative);
+ *   flags     PB3_FLAG_*.
+ * On the device (unless PB3_FLAG_HOST_ONLY) it uploads the bin and triplet
+ * tables and computes the triangle counts T_abc once in FP64 (N_0 is
+ * data-independent, Sec. IV.D.1), on the default stream, synchronously.
+ * Errors: PB3_EINVAL (bad grid/box/edges, a bin with no modes, strict-mode
+ * empty triplet), PB3_EUNSUPPORTED (grid length or > 48 bins), PB3_ENOMEM,
+ * PB3_EDEVICE.  *out is NULL on failure. */
+pb3_status pb3_plan_create(const int grid[3], const double box[3], const double* edges, int n_edges,
+                           unsigned flags, pb3_plan** out);
+pb3_status pb3_plan_destroy(pb3_plan* plan);
+
+/* Bytes of device workspace one call needs (FP32 filtered fields on the
+ * contraction grid, FFT intermediates, partial sums). */
+size_t pb3_plan_workspace_bytes(const pb3_plan* plan);
+/* Bind caller-owned device memory (>= pb3_plan_workspace_bytes) as the
+ * workspace; replaces (and frees) any workspace the plan allocated. */
+pb3_status pb3_plan_bind_workspace(pb3_plan* plan, void* dev, size_t bytes);
+
+int pb3_n_bins(const pb3_plan* plan);
+int pb3_n_triplets(const pb3_plan* plan);  /* after dropping T = 0 (host-only plans: before) */
+int pb3_grid(const pb3_plan* plan);        /* N */
+int pb3_contract_grid(const pb3_plan* plan); /* M: N, or the smaller alias-free grid */
+
+/* Bin edges (k_f units, n_bins+1), bin centres |k| in h/Mpc (mean |k| of
+ * the modes in the bin) and mode counts N_b; any pointer may be NULL. */
+pb3_status pb3_get_bins(const pb3_plan* plan, double* edges_kf_out, double* kmean_out, int64_t* n_modes_out);
+/* Triplets (n_trip x 3 int32, a <= b <= c, c fastest). */
+pb3_status pb3_get_triplets(const pb3_plan* plan, int32_t* abc_out);
+/* Host copies of N_b (n_bins) and T_abc (n_trip, exact integers stored as
+ * double); either pointer may be NULL.  Needs a device plan. */
+pb3_status pb3_norm(const pb3_plan* plan, int64_t* n_modes_out, double* counts_out);
+
+/* P_b for every bin.  delta_dev: N^3 float32, C order (x slowest, z
+ * fastest), device memory.  pk_dev: n_bins float64, device memory, (Mpc/h)^3. */
+pb3_status pb3_power(pb3_plan* plan, const float* delta_dev, double* pk_dev, void* stream);
+
+/* B_abc for every plan triplet: bk_dev n_trip float64 device memory,
+ * (Mpc/h)^6. */
+pb3_status pb3_bispectrum(pb3_plan* plan, const float* delta_dev, double* bk_dev, pb3_precision prec,
+                          void* stream);
+
+/* Both statistics from one forward FFT (pk_dev or bk_dev may be NULL). */
+pb3_status pb3_polyspectra(pb3_plan* plan, const float* delta_dev, double* pk_dev, double* bk_dev,
+                           pb3_precision prec, void* stream);
+
+/* Stage timing (plans made with PB3_FLAG_STAGE_TIMING): every call records
+ * a HIP event pair around each kernel launch on the call's stream.
+ * pb3_stage_times writes, per stage, the mean milliseconds over the calls
+ * made since the last pb3_stage_timing_reset (at most the latest 256),
+ * in the order fwd_z, fwd_y, fwd_x, power, inv_x, inv_y, inv_z, contract,
+ * reduce (0 for stages that did not run); counts_out (may be NULL)
+ * receives how many calls each mean covers.  It synchronises on the
+ * recorded events.  n_out receives the number of stages written. */
+pb3_status pb3_stage_times(pb3_plan* plan, float* ms_out, int* counts_out, int capacity, int* n_out);
+pb3_status pb3_stage_timing_reset(pb3_plan* plan);
+const char* pb3_stage_name(int stage);
+
+const char* pb3_status_string(pb3_status s);
+const char* pb3_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PB3_H */

@@ -31,6 +31,7 @@ from .polyspec import (  # noqa: F401
     power_spectrum,
     triangle_counts,
     triangle_triplets,
+    triple_sums,
     triplet_sums_sample,
     unit_fields,
 )

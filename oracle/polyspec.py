@@ -71,6 +71,7 @@ __all__ = [
     "unit_fields",
     "triangle_counts",
     "bispectrum",
+    "triple_sums",
     "Result",
 ]
 
@@ -183,6 +184,11 @@ def unit_fields(n: int, edges, bins=None) -> np.ndarray:
     nb = len(edges) - 1
     bins = range(nb) if bins is None else bins
     return np.stack([idft((idx == b).astype(np.float64)).real for b in bins])
+
+
+def triple_sums(fields: np.ndarray, trips: np.ndarray, absolute: bool = False):
+    """sum_x F_a F_b F_c for each triplet (and optionally sum_x |F_a F_b F_c|)."""
+    return _triple_sums(fields, trips, absolute)
 
 
 def _triple_sums(fields: np.ndarray, trips: np.ndarray, absolute: bool = False):

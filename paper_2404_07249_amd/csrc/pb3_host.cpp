@@ -1,0 +1,699 @@
+// Host side of the MI355X polyspectrum library: plan construction (bins,
+// triplets, contraction grid, tables, triangle counts), workspace
+// management and the C ABI declared in include/pb3.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pb3_internal.h"
+
+namespace pb3 {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+pb3_status hip_fail(hipError_t e, const char* what) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return PB3_EDEVICE;
+}
+
+static bool len_supported(int n) {
+  static const int ok[] = {16, 24, 32, 48, 64, 96, 128, 192, 256, 384};
+  for (int v : ok)
+    if (v == n) return true;
+  return false;
+}
+
+// smallest supported length strictly above lo and not above hi (0 if none)
+static int smallest_len_above(int lo, int hi) {
+  static const int ok[] = {16, 24, 32, 48, 64, 96, 128, 192, 256, 384};
+  for (int v : ok)
+    if (v > lo && v <= hi) return v;
+  return 0;
+}
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+void build_tiles(const pb3_plan& p, int tbx, int tby, int tbz, std::vector<BinTile>& vx, std::vector<BinTile>& vy,
+                 std::vector<BinTile>& vz) {
+  vx.clear();
+  vy.clear();
+  vz.clear();
+  for (int b = 0; b < p.nb; ++b) {
+    const BinGeom& g = p.geom[b];
+    int nx = g.ly * g.kzn;
+    for (int c = 0; c < nx; c += tbx) vx.push_back(BinTile{b, c});
+    int ny = p.M * g.kzn;
+    for (int c = 0; c < ny; c += tby) vy.push_back(BinTile{b, c});
+    int nz = p.M * p.M;
+    for (int c = 0; c < nz; c += tbz) vz.push_back(BinTile{b, c});
+  }
+}
+
+// FP64 twiddle table W_n^j = exp(-2 pi i j / n), j < n
+static std::vector<double> twiddles(int n) {
+  std::vector<double> w(2 * (size_t)n);
+  for (int j = 0; j < n; ++j) {
+    // exact angles via the reduced fraction j/n; sin/cos of multiples of pi/2 exact
+    double a = -2.0 * M_PI * (double)j / (double)n;
+    double c = std::cos(a), s = std::sin(a);
+    if (4 * j % n == 0) {
+      int q = 4 * j / n;
+      c = (q == 0) ? 1.0 : (q == 2) ? -1.0 : 0.0;
+      s = (q == 1) ? -1.0 : (q == 3) ? 1.0 : 0.0;
+    }
+    w[2 * j] = c;
+    w[2 * j + 1] = s;
+  }
+  return w;
+}
+
+template <typename T> static pb3_status dalloc(T** ptr, size_t count) {
+  hipError_t e = hipMalloc((void**)ptr, sizeof(T) * (count ? count : 1));
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
+    return PB3_ENOMEM;
+  }
+  return PB3_OK;
+}
+
+template <typename T> static pb3_status upload(T** ptr, const T* src, size_t count) {
+  pb3_status st = dalloc(ptr, count);
+  if (st != PB3_OK) return st;
+  if (count == 0) return PB3_OK;
+  hipError_t e = hipMemcpy(*ptr, src, sizeof(T) * count, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  return PB3_OK;
+}
+
+static pb3_status upload_twiddles_f(float2** out, int n) {
+  std::vector<double> w = twiddles(n);
+  std::vector<float2> f(n);
+  for (int j = 0; j < n; ++j) f[j] = make_float2((float)w[2 * j], (float)w[2 * j + 1]);
+  return upload(out, f.data(), f.size());
+}
+
+static pb3_status upload_twiddles_d(double2** out, int n) {
+  std::vector<double> w = twiddles(n);
+  std::vector<double2> f(n);
+  for (int j = 0; j < n; ++j) f[j] = make_double2(w[2 * j], w[2 * j + 1]);
+  return upload(out, f.data(), f.size());
+}
+
+static void free_device(pb3_plan* p) {
+  DeviceTables& d = p->d;
+  void* ptrs[] = {d.lut,        d.modes,    d.chunk, d.geom,  d.tiles,   d.trip_all, d.out_map,
+                  d.inv_counts, d.pk_scale, d.tw_n,  d.tw_n2, d.tw_m,    d.tw_m2,    d.tw_m_d,
+                  d.tw_m2_d};
+  for (void* q : ptrs)
+    if (q) hipFree(q);
+  d = DeviceTables{};
+  if (p->ws.owned && p->ws.base) hipFree(p->ws.base);
+  p->ws = Workspace{};
+  for (hipEvent_t e : p->ev)
+    if (e) hipEventDestroy(e);
+  p->ev.clear();
+}
+
+// ------------------------------------------------------------ host plan
+static pb3_status build_host(pb3_plan* p, const int grid[3], const double box[3], const double* edges, int n_edges,
+                             unsigned flags) {
+  if (!grid || !box || !edges) {
+    set_error("null argument");
+    return PB3_EINVAL;
+  }
+  if (grid[0] != grid[1] || grid[0] != grid[2] || grid[0] <= 0) {
+    set_error("only cubic grids are supported");
+    return PB3_EINVAL;
+  }
+  if (!(box[0] > 0) || box[0] != box[1] || box[0] != box[2]) {
+    set_error("box must be cubic and positive");
+    return PB3_EINVAL;
+  }
+  const int N = grid[0];
+  if (N % 2) {
+    set_error("grid side must be even");
+    return PB3_EINVAL;
+  }
+  if (!len_supported(N)) {
+    set_error("grid side " + std::to_string(N) + " not implemented (supported: 16..384 of the form 2^a 3^b)");
+    return PB3_EUNSUPPORTED;
+  }
+  if (n_edges < 2) {
+    set_error("need at least two bin edges");
+    return PB3_EINVAL;
+  }
+  p->N = N;
+  p->L = box[0];
+  p->flags = flags;
+  const double kf = 2.0 * M_PI / p->L;
+  p->edges.resize(n_edges);
+  for (int i = 0; i < n_edges; ++i) {
+    double e = edges[i];
+    if (!std::isfinite(e) || e < 0) {
+      set_error("bin edges must be finite and non-negative");
+      return PB3_EINVAL;
+    }
+    if (flags & PB3_FLAG_EDGES_HMPC) {
+      e /= kf;
+      double h = std::round(2.0 * e) / 2.0;
+      if (std::fabs(e - h) <= 1e-9 * std::max(1.0, std::fabs(e))) e = h;
+    }
+    p->edges[i] = e;
+    if (i > 0 && !(p->edges[i] > p->edges[i - 1])) {
+      set_error("bin edges must be strictly increasing");
+      return PB3_EINVAL;
+    }
+  }
+  const int nb = n_edges - 1;
+  if (nb > 48) {
+    set_error("more than 48 bins not implemented");
+    return PB3_EUNSUPPORTED;
+  }
+  p->nb = nb;
+  p->nb_pad = (nb + 15) / 16 * 16;
+  // integer thresholds: |n|^2 in bin b  <=>  thr[b] <= |n|^2 < thr[b+1]
+  p->thr.resize(nb + 1);
+  for (int i = 0; i <= nb; ++i) {
+    double e2 = p->edges[i] * p->edges[i];
+    int64_t t = (int64_t)std::ceil(e2);
+    // guard against e2 just above an integer through rounding of the square
+    while (t > 0 && (double)(t - 1) >= e2) --t;
+    while ((double)t < e2) ++t;
+    p->thr[i] = t;
+  }
+  const int64_t nmax2 = 3LL * (N / 2) * (N / 2);
+  // largest component any binned mode can have
+  int K = 0;
+  {
+    int64_t top = p->thr[nb] - 1;  // largest |n|^2 inside the top edge
+    if (top < 0) top = 0;
+    K = (int)std::floor(std::sqrt((double)top));
+    while ((int64_t)(K + 1) * (K + 1) <= top) ++K;
+    while ((int64_t)K * K > top) --K;
+    if (K > N / 2) K = N / 2;
+  }
+  p->K = K;
+  p->full = (K >= N / 2);
+  if (p->full) {
+    p->Kc = N / 2;
+    p->Lc = N;
+    p->Kz = N / 2 + 1;
+  } else {
+    p->Kc = K;
+    p->Lc = 2 * K + 1;
+    p->Kz = K + 1;
+  }
+  // contraction grid: alias-free smaller grid when 3K < N
+  p->M = N;
+  if (!(flags & PB3_FLAG_FULL_GRID) && 3 * K < N) {
+    int m = smallest_len_above(3 * K, N);
+    if (m) p->M = m;
+  }
+  // bin lookup by |n|^2
+  p->lut_len = (int)std::min<int64_t>(nmax2, 3LL * K * K) + 1;
+  p->lut.assign(p->lut_len, (int8_t)-1);
+  for (int64_t n2 = 0; n2 < p->lut_len; ++n2) {
+    for (int b = 0; b < nb; ++b)
+      if (n2 >= p->thr[b] && n2 < p->thr[b + 1]) p->lut[n2] = (int8_t)b;
+  }
+  // modes of the compact half spectrum, per bin
+  std::vector<std::vector<int32_t>> per(nb);
+  p->nmodes.assign(nb, 0);
+  std::vector<double> ksum(nb, 0.0);
+  for (int cx = 0; cx < p->Lc; ++cx) {
+    int kx = cx - p->Kc;
+    for (int cy = 0; cy < p->Lc; ++cy) {
+      int ky = cy - p->Kc;
+      for (int kz = 0; kz < p->Kz; ++kz) {
+        int64_t n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
+        if (n2 >= p->lut_len) continue;
+        int b = p->lut[n2];
+        if (b < 0) continue;
+        bool self = (kz == 0) || (p->full && kz == N / 2);
+        int32_t idx = (int32_t)(((int64_t)cx * p->Lc + cy) * p->Kz + kz);
+        per[b].push_back(self ? (int32_t)(idx | 0x80000000u) : idx);
+        int w = self ? 1 : 2;
+        p->nmodes[b] += w;
+        ksum[b] += w * std::sqrt((double)n2) * kf;
+      }
+    }
+  }
+  for (int b = 0; b < nb; ++b) {
+    if (p->nmodes[b] == 0) {
+      set_error("bin " + std::to_string(b) + " contains no grid modes");
+      return PB3_EINVAL;
+    }
+  }
+  p->kmean.resize(nb);
+  for (int b = 0; b < nb; ++b) p->kmean[b] = ksum[b] / (double)p->nmodes[b];
+  p->modes.clear();
+  p->chunks.clear();
+  const int CH = 8192;
+  for (int b = 0; b < nb; ++b) {
+    int start = (int)p->modes.size();
+    p->modes.insert(p->modes.end(), per[b].begin(), per[b].end());
+    int end = (int)p->modes.size();
+    for (int s = start; s < end; s += CH) {
+      p->chunks.push_back(b);
+      p->chunks.push_back(s);
+      p->chunks.push_back(std::min(end, s + CH));
+    }
+  }
+  p->n_chunks = (int)(p->chunks.size() / 3);
+  // per-bin spectrum rectangles and intermediate offsets
+  p->geom.resize(nb);
+  int64_t o1 = 0, o2 = 0;
+  for (int b = 0; b < nb; ++b) {
+    int64_t top = p->thr[b + 1] - 1;
+    int kb = (int)std::floor(std::sqrt((double)std::max<int64_t>(top, 0)));
+    while ((int64_t)(kb + 1) * (kb + 1) <= top) ++kb;
+    while ((int64_t)kb * kb > top) --kb;
+    if (kb > N / 2) kb = N / 2;
+    BinGeom g{};
+    g.kneg = kb;
+    g.kpos = (p->full && kb == N / 2) ? N / 2 - 1 : kb;
+    g.ly = g.kneg + g.kpos + 1;
+    g.kzn = kb + 1;
+    g.a1_off = o1;
+    g.a2_off = o2;
+    o1 += (int64_t)p->M * g.ly * g.kzn;
+    o2 += (int64_t)p->M * p->M * g.kzn;
+    p->geom[b] = g;
+  }
+  p->a1_len = o1;
+  p->a2_len = o2;
+  // triangle-valid triplets, c fastest
+  p->trip_all.clear();
+  for (int a = 0; a < nb; ++a)
+    for (int b = a; b < nb; ++b)
+      for (int c = b; c < nb; ++c)
+        if (p->edges[c] < p->edges[a + 1] + p->edges[b + 1]) {
+          p->trip_all.push_back(a);
+          p->trip_all.push_back(b);
+          p->trip_all.push_back(c);
+        }
+  if (p->trip_all.size() / 3 > 8192) {
+    set_error("more than 8192 triplets not implemented");
+    return PB3_EUNSUPPORTED;
+  }
+  p->trip = p->trip_all;
+  p->contract_wgs = 1024;
+  p->part_len = (int)(p->trip_all.size() / 3);
+  return PB3_OK;
+}
+
+static size_t workspace_bytes(const pb3_plan* p) {
+  size_t b = 0;
+  const size_t A = 256;
+  b += align_up(sizeof(float2) * (size_t)p->N * p->N * p->Kz, A);
+  b += align_up(sizeof(float2) * (size_t)p->N * p->Lc * p->Kz, A);
+  b += align_up(sizeof(float2) * (size_t)p->Lc * p->Lc * p->Kz, A);
+  b += align_up(sizeof(float2) * (size_t)p->a1_len, A);
+  b += align_up(sizeof(float2) * (size_t)p->a2_len, A);
+  b += align_up(sizeof(float) * (size_t)p->nb_pad * p->M * p->M * p->M, A);
+  b += align_up(sizeof(float) * (size_t)p->contract_wgs * p->part_len, A);
+  b += align_up(sizeof(double) * (size_t)std::max(p->n_chunks, 1), A);
+  return b;
+}
+
+static void carve_workspace(pb3_plan* p, void* base, size_t bytes, bool owned) {
+  Workspace& w = p->ws;
+  w.base = base;
+  w.bytes = bytes;
+  w.owned = owned;
+  char* c = (char*)base;
+  const size_t A = 256;
+  auto take = [&](size_t n) {
+    char* r = c;
+    c += align_up(n, A);
+    return (void*)r;
+  };
+  w.f1 = (float2*)take(sizeof(float2) * (size_t)p->N * p->N * p->Kz);
+  w.f2 = (float2*)take(sizeof(float2) * (size_t)p->N * p->Lc * p->Kz);
+  w.dc = (float2*)take(sizeof(float2) * (size_t)p->Lc * p->Lc * p->Kz);
+  w.a1 = (float2*)take(sizeof(float2) * (size_t)p->a1_len);
+  w.a2 = (float2*)take(sizeof(float2) * (size_t)p->a2_len);
+  w.g = (float*)take(sizeof(float) * (size_t)p->nb_pad * p->M * p->M * p->M);
+  w.part = (float*)take(sizeof(float) * (size_t)p->contract_wgs * p->part_len);
+  w.ppart = (double*)take(sizeof(double) * (size_t)std::max(p->n_chunks, 1));
+}
+
+static pb3_status ensure_workspace(pb3_plan* p) {
+  if (p->ws.base) return PB3_OK;
+  if (p->flags & PB3_FLAG_EXT_WORKSPACE) {
+    set_error("plan needs a bound workspace (PB3_FLAG_EXT_WORKSPACE)");
+    return PB3_EINVAL;
+  }
+  size_t bytes = workspace_bytes(p);
+  void* base = nullptr;
+  hipError_t e = hipMalloc(&base, bytes);
+  if (e != hipSuccess) {
+    set_error("workspace hipMalloc of " + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
+    return PB3_ENOMEM;
+  }
+  carve_workspace(p, base, bytes, true);
+  return PB3_OK;
+}
+
+static pb3_status build_device(pb3_plan* p) {
+  pb3_status st;
+  hipError_t e = hipGetDevice(&p->device_id);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  DeviceTables& d = p->d;
+  if ((st = upload(&d.lut, p->lut.data(), p->lut.size())) != PB3_OK) return st;
+  if ((st = upload(&d.modes, p->modes.data(), p->modes.size())) != PB3_OK) return st;
+  if ((st = upload(&d.chunk, p->chunks.data(), p->chunks.size())) != PB3_OK) return st;
+  if ((st = upload(&d.geom, p->geom.data(), p->geom.size())) != PB3_OK) return st;
+  if ((st = upload(&d.trip_all, p->trip_all.data(), p->trip_all.size())) != PB3_OK) return st;
+  if ((st = upload_twiddles_f(&d.tw_n, p->N)) != PB3_OK) return st;
+  if ((st = upload_twiddles_f(&d.tw_n2, p->N / 2)) != PB3_OK) return st;
+  if ((st = upload_twiddles_f(&d.tw_m, p->M)) != PB3_OK) return st;
+  if ((st = upload_twiddles_f(&d.tw_m2, p->M / 2)) != PB3_OK) return st;
+  if ((st = upload_twiddles_d(&d.tw_m_d, p->M)) != PB3_OK) return st;
+  if ((st = upload_twiddles_d(&d.tw_m2_d, p->M / 2)) != PB3_OK) return st;
+  // FP32 inverse-pass tiles
+  int tbx = tile_width_x(p->M, false), tbz = tile_width_z(p->M, false);
+  if (tbx <= 0 || tbz <= 0) {
+    set_error("contraction grid not implemented");
+    return PB3_EUNSUPPORTED;
+  }
+  std::vector<BinTile> vx, vy, vz;
+  build_tiles(*p, tbx, tbx, tbz, vx, vy, vz);
+  std::vector<BinTile> all(vx);
+  all.insert(all.end(), vy.begin(), vy.end());
+  all.insert(all.end(), vz.begin(), vz.end());
+  if ((st = upload(&d.tiles, all.data(), all.size())) != PB3_OK) return st;
+  p->tx = TileSet{d.tiles, (int)vx.size(), tbx};
+  p->ty = TileSet{d.tiles + vx.size(), (int)vy.size(), tbx};
+  p->tz = TileSet{d.tiles + vx.size() + vy.size(), (int)vz.size(), tbz};
+  // power normalisation V / (N^6 N_b)
+  const double V = p->L * p->L * p->L;
+  const double n3 = (double)p->N * p->N * p->N;
+  std::vector<double> pks(p->nb);
+  for (int b = 0; b < p->nb; ++b) pks[b] = V / (n3 * n3 * (double)p->nmodes[b]);
+  if ((st = upload(&d.pk_scale, pks.data(), pks.size())) != PB3_OK) return st;
+  // triangle counts in FP64 on the contraction grid
+  std::vector<double> raw;
+  if ((st = compute_counts_fp64(*p, raw)) != PB3_OK) return st;
+  const int n_cand = (int)(p->trip_all.size() / 3);
+  p->trip.clear();
+  p->counts.clear();
+  std::vector<int32_t> map;
+  std::vector<double> fac;
+  const double m3 = (double)p->M * p->M * p->M;
+  const double scale = V * V * (m3 * m3) / (n3 * n3 * n3);
+  for (int t = 0; t < n_cand; ++t) {
+    double T = std::nearbyint(raw[t]);
+    if (std::fabs(raw[t] - T) > 1e-3) {
+      set_error("triangle count not integral (" + std::to_string(raw[t]) + ")");
+      return PB3_EDEVICE;
+    }
+    if (T <= 0) {
+      if (p->flags & PB3_FLAG_STRICT) {
+        set_error("a triangle-valid triplet has no closed triangle on the grid");
+        return PB3_EINVAL;
+      }
+      continue;
+    }
+    for (int k = 0; k < 3; ++k) p->trip.push_back(p->trip_all[3 * t + k]);
+    p->counts.push_back(T);
+    map.push_back(t);
+    fac.push_back(scale / T);
+  }
+  p->map_simple = map;
+  if ((st = upload(&d.out_map, map.data(), map.size())) != PB3_OK) return st;
+  if ((st = upload(&d.inv_counts, fac.data(), fac.size())) != PB3_OK) return st;
+  if (p->flags & PB3_FLAG_STAGE_TIMING) {
+    p->ev.assign((size_t)pb3_plan::kTimingRing * ST_COUNT * 2, nullptr);
+    p->ev_used.assign((size_t)pb3_plan::kTimingRing * ST_COUNT, 0);
+    for (auto& ev : p->ev) {
+      e = hipEventCreate(&ev);
+      if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    }
+  }
+  p->device = true;
+  return PB3_OK;
+}
+
+// run one stage, bracketed by events when timing is on
+template <typename F> static pb3_status stage(pb3_plan* p, int id, hipStream_t s, const char* name, F&& fn) {
+  const bool timed = !p->ev.empty();
+  const size_t slot = (size_t)(p->n_calls % pb3_plan::kTimingRing) * ST_COUNT + id;
+  if (timed) {
+    hipError_t e = hipEventRecord(p->ev[2 * slot], s);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  }
+  hipError_t e = fn();
+  if (e != hipSuccess) return hip_fail(e, name);
+  if (timed) {
+    e = hipEventRecord(p->ev[2 * slot + 1], s);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    p->ev_used[slot] = 1;
+  }
+  return PB3_OK;
+}
+
+static pb3_status check_ready(pb3_plan* p) {
+  if (!p) {
+    set_error("null plan");
+    return PB3_EINVAL;
+  }
+  if (!p->device) {
+    set_error("plan has no device state (created with PB3_FLAG_HOST_ONLY)");
+    return PB3_EINVAL;
+  }
+  int dev = -1;
+  hipGetDevice(&dev);
+  if (dev != p->device_id) {
+    set_error("plan was created on another device");
+    return PB3_EINVAL;
+  }
+  return ensure_workspace(p);
+}
+
+static pb3_status run(pb3_plan* p, const float* delta, double* pk, double* bk, pb3_precision prec, hipStream_t s) {
+  pb3_status st = check_ready(p);
+  if (st != PB3_OK) return st;
+  if (!delta || (!pk && !bk)) {
+    set_error("null device pointer");
+    return PB3_EINVAL;
+  }
+  if (prec != PB3_FP32 && prec != PB3_MIXED_BF16X3) {
+    set_error("unknown precision");
+    return PB3_EINVAL;
+  }
+  if (!p->ev.empty()) {
+    size_t slot = (size_t)(p->n_calls % pb3_plan::kTimingRing) * ST_COUNT;
+    std::fill(p->ev_used.begin() + slot, p->ev_used.begin() + slot + ST_COUNT, 0);
+  }
+  p->last_stream = s;
+  if ((st = stage(p, ST_FWD_Z, s, "fwd_z", [&] { return launch_fwd_z(*p, delta, s); })) != PB3_OK) return st;
+  if ((st = stage(p, ST_FWD_Y, s, "fwd_y", [&] { return launch_fwd_y(*p, s); })) != PB3_OK) return st;
+  if ((st = stage(p, ST_FWD_X, s, "fwd_x", [&] { return launch_fwd_x(*p, s); })) != PB3_OK) return st;
+  if (pk) {
+    if ((st = stage(p, ST_POWER, s, "power", [&] { return launch_power(*p, pk, s); })) != PB3_OK) return st;
+  }
+  if (bk) {
+    if ((st = stage(p, ST_INV_X, s, "inv_x", [&] { return launch_inv_x(*p, s); })) != PB3_OK) return st;
+    if ((st = stage(p, ST_INV_Y, s, "inv_y", [&] { return launch_inv_y(*p, s); })) != PB3_OK) return st;
+    if ((st = stage(p, ST_INV_Z, s, "inv_z", [&] { return launch_inv_z(*p, s); })) != PB3_OK) return st;
+    if ((st = stage(p, ST_CONTRACT, s, "contract", [&] { return launch_contract(*p, prec, s); })) != PB3_OK)
+      return st;
+    if ((st = stage(p, ST_REDUCE, s, "reduce", [&] { return launch_reduce(*p, prec, bk, s); })) != PB3_OK) return st;
+  }
+  p->last_prec = prec;
+  ++p->n_calls;
+  return PB3_OK;
+}
+
+}  // namespace pb3
+
+using namespace pb3;
+
+extern "C" {
+
+pb3_status pb3_plan_create(const int grid[3], const double box[3], const double* edges, int n_edges, unsigned flags,
+                           pb3_plan** out) {
+  if (!out) {
+    set_error("null output pointer");
+    return PB3_EINVAL;
+  }
+  *out = nullptr;
+  pb3_plan* p = new (std::nothrow) pb3_plan();
+  if (!p) {
+    set_error("host allocation failed");
+    return PB3_ENOMEM;
+  }
+  pb3_status st = build_host(p, grid, box, edges, n_edges, flags);
+  if (st == PB3_OK && !(flags & PB3_FLAG_HOST_ONLY)) st = build_device(p);
+  if (st != PB3_OK) {
+    free_device(p);
+    delete p;
+    return st;
+  }
+  *out = p;
+  return PB3_OK;
+}
+
+pb3_status pb3_plan_destroy(pb3_plan* plan) {
+  if (!plan) return PB3_OK;
+  free_device(plan);
+  delete plan;
+  return PB3_OK;
+}
+
+size_t pb3_plan_workspace_bytes(const pb3_plan* plan) { return plan ? workspace_bytes(plan) : 0; }
+
+pb3_status pb3_plan_bind_workspace(pb3_plan* plan, void* dev, size_t bytes) {
+  if (!plan || !dev) {
+    set_error("null argument");
+    return PB3_EINVAL;
+  }
+  size_t need = workspace_bytes(plan);
+  if (bytes < need) {
+    set_error("workspace too small: need " + std::to_string(need) + " bytes");
+    return PB3_ENOMEM;
+  }
+  if (((uintptr_t)dev) % 256) {
+    set_error("workspace must be 256-byte aligned");
+    return PB3_EINVAL;
+  }
+  if (plan->ws.owned && plan->ws.base) hipFree(plan->ws.base);
+  carve_workspace(plan, dev, bytes, false);
+  return PB3_OK;
+}
+
+int pb3_n_bins(const pb3_plan* plan) { return plan ? plan->nb : 0; }
+int pb3_n_triplets(const pb3_plan* plan) { return plan ? (int)(plan->trip.size() / 3) : 0; }
+int pb3_grid(const pb3_plan* plan) { return plan ? plan->N : 0; }
+int pb3_contract_grid(const pb3_plan* plan) { return plan ? plan->M : 0; }
+
+pb3_status pb3_get_bins(const pb3_plan* plan, double* edges_kf_out, double* kmean_out, int64_t* n_modes_out) {
+  if (!plan) {
+    set_error("null plan");
+    return PB3_EINVAL;
+  }
+  if (edges_kf_out) std::copy(plan->edges.begin(), plan->edges.end(), edges_kf_out);
+  if (kmean_out) std::copy(plan->kmean.begin(), plan->kmean.end(), kmean_out);
+  if (n_modes_out) std::copy(plan->nmodes.begin(), plan->nmodes.end(), n_modes_out);
+  return PB3_OK;
+}
+
+pb3_status pb3_get_triplets(const pb3_plan* plan, int32_t* abc_out) {
+  if (!plan || !abc_out) {
+    set_error("null argument");
+    return PB3_EINVAL;
+  }
+  std::copy(plan->trip.begin(), plan->trip.end(), abc_out);
+  return PB3_OK;
+}
+
+pb3_status pb3_norm(const pb3_plan* plan, int64_t* n_modes_out, double* counts_out) {
+  if (!plan) {
+    set_error("null plan");
+    return PB3_EINVAL;
+  }
+  if (!plan->device) {
+    set_error("triangle counts need a device plan");
+    return PB3_EINVAL;
+  }
+  if (n_modes_out) std::copy(plan->nmodes.begin(), plan->nmodes.end(), n_modes_out);
+  if (counts_out) std::copy(plan->counts.begin(), plan->counts.end(), counts_out);
+  return PB3_OK;
+}
+
+pb3_status pb3_power(pb3_plan* plan, const float* delta_dev, double* pk_dev, void* stream) {
+  if (!pk_dev) {
+    set_error("null output pointer");
+    return PB3_EINVAL;
+  }
+  return run(plan, delta_dev, pk_dev, nullptr, PB3_FP32, (hipStream_t)stream);
+}
+
+pb3_status pb3_bispectrum(pb3_plan* plan, const float* delta_dev, double* bk_dev, pb3_precision prec, void* stream) {
+  if (!bk_dev) {
+    set_error("null output pointer");
+    return PB3_EINVAL;
+  }
+  return run(plan, delta_dev, nullptr, bk_dev, prec, (hipStream_t)stream);
+}
+
+pb3_status pb3_polyspectra(pb3_plan* plan, const float* delta_dev, double* pk_dev, double* bk_dev, pb3_precision prec,
+                           void* stream) {
+  return run(plan, delta_dev, pk_dev, bk_dev, prec, (hipStream_t)stream);
+}
+
+static const char* kStageNames[ST_COUNT] = {"fwd_z", "fwd_y", "fwd_x",    "power", "inv_x",
+                                            "inv_y", "inv_z", "contract", "reduce"};
+
+const char* pb3_stage_name(int stage) {
+  if (stage < 0 || stage >= ST_COUNT) return "";
+  return kStageNames[stage];
+}
+
+pb3_status pb3_stage_times(pb3_plan* plan, float* ms_out, int* counts_out, int capacity, int* n_out) {
+  if (!plan || !ms_out) {
+    set_error("null argument");
+    return PB3_EINVAL;
+  }
+  if (plan->ev.empty()) {
+    set_error("plan was not created with PB3_FLAG_STAGE_TIMING");
+    return PB3_EINVAL;
+  }
+  const int n = std::min(capacity, (int)ST_COUNT);
+  const long calls = std::min<long>(plan->n_calls, pb3_plan::kTimingRing);
+  for (int i = 0; i < n; ++i) {
+    double sum = 0.0;
+    int cnt = 0;
+    for (long c = 0; c < calls; ++c) {
+      size_t slot = (size_t)((plan->n_calls - 1 - c) % pb3_plan::kTimingRing) * ST_COUNT + i;
+      if (!plan->ev_used[slot]) continue;
+      hipError_t e = hipEventSynchronize(plan->ev[2 * slot + 1]);
+      if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, plan->ev[2 * slot], plan->ev[2 * slot + 1]);
+      if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+      sum += ms;
+      ++cnt;
+    }
+    ms_out[i] = cnt ? (float)(sum / cnt) : 0.f;
+    if (counts_out) counts_out[i] = cnt;
+  }
+  if (n_out) *n_out = n;
+  return PB3_OK;
+}
+
+pb3_status pb3_stage_timing_reset(pb3_plan* plan) {
+  if (!plan) {
+    set_error("null plan");
+    return PB3_EINVAL;
+  }
+  plan->n_calls = 0;
+  std::fill(plan->ev_used.begin(), plan->ev_used.end(), 0);
+  return PB3_OK;
+}
+
+const char* pb3_status_string(pb3_status s) {
+  switch (s) {
+    case PB3_OK: return "ok";
+    case PB3_EINVAL: return "invalid argument";
+    case PB3_ENOMEM: return "out of memory";
+    case PB3_EDEVICE: return "device error";
+    case PB3_EUNSUPPORTED: return "unsupported";
+    case PB3_EBUSY: return "busy";
+  }
+  return "unknown status";
+}
+
+const char* pb3_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,168 @@
+// Internal declarations shared by the host plan (pb3_host.cpp) and the
+// kernel launchers (pb3_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pb3.h"
+
+namespace pb3 {
+
+// Stage indices for the optional per-kernel timing.
+enum Stage {
+  ST_FWD_Z = 0,
+  ST_FWD_Y,
+  ST_FWD_X,
+  ST_POWER,
+  ST_INV_X,
+  ST_INV_Y,
+  ST_INV_Z,
+  ST_CONTRACT,
+  ST_REDUCE,
+  ST_COUNT
+};
+
+// One work tile of the per-bin inverse passes: bin b, first column.
+struct BinTile {
+  int32_t bin;
+  int32_t col0;
+};
+
+// Geometry of bin b's pruned spectrum: |kx|,|ky| <= kneg, kz in [0, kz_n),
+// with the positive side possibly one shorter (Nyquist) -- ky in
+// [-kneg, kpos], kz in [0, kz_n).
+struct BinGeom {
+  int32_t kneg;     // most negative component magnitude
+  int32_t kpos;     // most positive component
+  int32_t ly;       // kneg + kpos + 1
+  int32_t kzn;      // number of kz planes (kpos_z + 1)
+  int64_t a1_off;   // float2 offset of this bin's x-pass output  [M][ly][kzn]
+  int64_t a2_off;   // float2 offset of this bin's y-pass output  [M][M][kzn]
+};
+
+// Output tile of the MFMA contraction: pair block (p, q, s) x column block cb.
+struct ContractTile {
+  int8_t p, q, s, cb;
+};
+
+// A device tile table for one inverse pass and the tile width it was built for.
+struct TileSet {
+  BinTile* d;
+  int n;
+  int tb;
+};
+
+struct DeviceTables {
+  int8_t* lut = nullptr;          // bin of |n|^2 (int8, -1 outside), size lut_len
+  int32_t* modes = nullptr;       // compact D index of every binned half-spectrum mode (bit 31: weight 1)
+  int32_t* chunk = nullptr;       // power chunks: (bin, start, end) triples
+  BinGeom* geom = nullptr;        // per bin
+  BinTile* tiles = nullptr;       // all FP32 inverse-pass tiles (x, then y, then z)
+  int32_t* trip_all = nullptr;    // candidate triplets (3 ints each), simple contraction
+  int32_t* out_map = nullptr;     // per kept triplet: index into one WG's partial vector
+  double* inv_counts = nullptr;   // per kept triplet: scale / T
+  double* pk_scale = nullptr;     // per bin: V / (N^6 N_b)
+  float2* tw_n = nullptr;         // W_N^j, j < N
+  float2* tw_n2 = nullptr;        // W_{N/2}^j
+  float2* tw_m = nullptr;         // W_M^j
+  float2* tw_m2 = nullptr;        // W_{M/2}^j
+  double2* tw_m_d = nullptr;      // FP64 twiddles for the count pass
+  double2* tw_m2_d = nullptr;
+};
+
+struct Workspace {
+  void* base = nullptr;
+  size_t bytes = 0;
+  bool owned = false;
+  float2* f1 = nullptr;     // [N][N][Kz]
+  float2* f2 = nullptr;     // [N][Lc][Kz]
+  float2* dc = nullptr;     // [Lc][Lc][Kz]
+  float2* a1 = nullptr;     // per-bin x-pass outputs
+  float2* a2 = nullptr;     // per-bin y-pass outputs
+  float* g = nullptr;       // [nb_pad][M^3]
+  float* part = nullptr;    // contraction partials
+  double* ppart = nullptr;  // power partials
+};
+
+}  // namespace pb3
+
+struct pb3_plan {
+  // geometry
+  int N = 0;
+  double L = 0;
+  unsigned flags = 0;
+  int nb = 0;
+  int nb_pad = 0;  // bins rounded up to the contraction's 16-bin groups
+  std::vector<double> edges;   // k_f units
+  std::vector<int64_t> thr;    // smallest |n|^2 in bin b (b <= nb: thr[nb] = first |n|^2 above the top)
+  int K = 0;                   // max |n_i| over binned modes
+  bool full = false;           // compact spectrum == full spectrum (K reaches N/2)
+  int Kc = 0;                  // centred offset of the compact x/y index
+  int Lc = 0;                  // compact x/y length
+  int Kz = 0;                  // compact z length
+  int M = 0;                   // contraction grid
+  int lut_len = 0;
+  std::vector<int8_t> lut;
+  std::vector<int64_t> nmodes;
+  std::vector<double> kmean;
+  std::vector<pb3::BinGeom> geom;
+  int64_t a1_len = 0, a2_len = 0;  // float2 counts
+  std::vector<int32_t> trip_all;   // candidates (a,b,c)
+  std::vector<int32_t> trip;       // kept
+  std::vector<double> counts;      // kept T
+  std::vector<int32_t> modes;
+  std::vector<int32_t> chunks;
+  int n_chunks = 0;
+  pb3::TileSet tx{}, ty{}, tz{};   // FP32 inverse-pass tiles (device)
+  // contraction
+  int contract_wgs = 0;
+  int part_len = 0;            // floats per WG partial vector (simple: n candidates; mfma: tiles*256)
+  int n_ctiles = 0;
+  std::vector<pb3::ContractTile> ctiles;
+  std::vector<int32_t> map_simple, map_mfma;  // per kept triplet
+  pb3_precision last_prec = PB3_FP32;
+  bool device = false;
+  int device_id = 0;
+  pb3::DeviceTables d;
+  pb3::Workspace ws;
+  int32_t* d_map_simple = nullptr;
+  int32_t* d_map_mfma = nullptr;
+  pb3::ContractTile* d_ctiles = nullptr;
+  // timing: ring of event pairs, slot = call index mod kTimingRing
+  static constexpr int kTimingRing = 256;
+  std::vector<hipEvent_t> ev;              // [ring][stage][2]
+  std::vector<uint8_t> ev_used;            // [ring][stage]
+  long n_calls = 0;                        // calls since the last reset
+  hipStream_t last_stream = nullptr;
+};
+
+namespace pb3 {
+
+void set_error(const std::string& msg);
+pb3_status hip_fail(hipError_t e, const char* what);
+
+// kernel launchers (pb3_kernels.hip); all return hipGetLastError()
+hipError_t launch_fwd_z(const pb3_plan& p, const float* delta, hipStream_t s);
+hipError_t launch_fwd_y(const pb3_plan& p, hipStream_t s);
+hipError_t launch_fwd_x(const pb3_plan& p, hipStream_t s);
+hipError_t launch_power(const pb3_plan& p, double* pk, hipStream_t s);
+hipError_t launch_inv_x(const pb3_plan& p, hipStream_t s);
+hipError_t launch_inv_y(const pb3_plan& p, hipStream_t s);
+hipError_t launch_inv_z(const pb3_plan& p, hipStream_t s);
+hipError_t launch_contract(const pb3_plan& p, pb3_precision prec, hipStream_t s);
+hipError_t launch_reduce(const pb3_plan& p, pb3_precision prec, double* bk, hipStream_t s);
+// FP64 triangle counts on the contraction grid: writes raw M^6 sum HHH for
+// every candidate triplet into counts_out (host), using temporary memory.
+pb3_status compute_counts_fp64(pb3_plan& p, std::vector<double>& counts_out);
+// tile widths of the inverse passes for FP32 (dbl = false) or FP64 lines
+int tile_width_x(int M, bool dbl);
+int tile_width_z(int M, bool dbl);
+// per-bin tile tables for the three inverse passes (host)
+void build_tiles(const pb3_plan& p, int tbx, int tby, int tbz, std::vector<BinTile>& vx, std::vector<BinTile>& vy,
+                 std::vector<BinTile>& vz);
+
+}  // namespace pb3

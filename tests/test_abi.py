@@ -1,0 +1,123 @@
+"""CPU checks of the native library: it loads, exports every symbol the
+public header declares, and its host-side plan logic (bins, triplets,
+contraction grid, argument errors) agrees with the oracle.  No kernel is
+launched here."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from synthetic import kf_edges
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2404_07249_amd", "libpb3.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libpb3.so not built (run __graft_entry__.build())")
+
+
+def _header_symbols():
+    txt = open(os.path.join(ROOT, "include", "pb3.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pb3_[a-z_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol():
+    from paper_2404_07249_amd import _lib
+
+    lib = C.CDLL(LIB)
+    syms = _header_symbols()
+    assert len(syms) >= 15
+    for s in syms:
+        assert hasattr(lib, s), s
+    # and the binding declares each one
+    declared = {n for n, _, _ in _lib.SIGNATURES}
+    assert set(syms) == declared
+
+
+def _plan(n, box, edges, **kw):
+    import paper_2404_07249_amd as pb3
+
+    return pb3.Plan(n, box, edges, host_only=True, **kw)
+
+
+@pytest.mark.parametrize("n,nb,ntrip,m", [(32, 8, 98, 32), (128, 20, 1015, 128), (256, 30, 3035, 192)])
+def test_host_plan_matches_oracle(n, nb, ntrip, m):
+    edges = kf_edges(nb)
+    p = _plan(n, 1000.0, edges)
+    assert p.n_bins == nb
+    assert p.n_triplets == ntrip  # host-only plans report the candidates
+    assert np.array_equal(p.triplets, oracle.triangle_triplets(edges))
+    e, kmean, nm = p.bins()
+    assert np.array_equal(e, edges)
+    if n <= 128:
+        assert np.array_equal(nm, oracle.mode_counts(n, edges))
+    assert p.contract_grid == m
+
+
+def test_mode_counts_full_spectrum_with_nyquist():
+    # top edge beyond N/2: the compact spectrum is the full one, Nyquist modes binned
+    n = 16
+    edges = np.array([1.0, 4.0, 7.0, 9.5, 14.0])
+    p = _plan(n, 100.0, edges)
+    _, _, nm = p.bins()
+    assert np.array_equal(nm, oracle.mode_counts(n, edges))
+    assert p.contract_grid == n
+
+
+def test_edges_in_hmpc_are_snapped():
+    n, box = 64, 1500.0
+    kf = 2 * np.pi / box
+    edges_kf = kf_edges(10)
+    p = _plan(n, box, edges_kf * kf, edges_hmpc=True)
+    e, _, nm = p.bins()
+    assert np.array_equal(e, edges_kf)
+    assert np.array_equal(nm, oracle.mode_counts(n, edges_kf))
+
+
+@pytest.mark.parametrize(
+    "n,edges,status",
+    [
+        (33, [1.0, 3.0], "EINVAL"),  # odd grid
+        (100, [1.0, 3.0], "EUNSUPPORTED"),  # factor 5
+        (32, [3.0, 1.0], "EINVAL"),  # unsorted
+        (32, [1.0], "EINVAL"),  # one edge
+        (32, [1.2, 1.3], "EINVAL"),  # a bin with no modes
+        (32, list(range(1, 51)), "EUNSUPPORTED"),  # 49 bins
+    ],
+)
+def test_plan_errors(n, edges, status):
+    import paper_2404_07249_amd as pb3
+
+    with pytest.raises(pb3.Pb3Error) as ei:
+        _plan(n, 100.0, np.array(edges, dtype=float))
+    assert status in str(ei.value)
+
+
+def test_non_cubic_rejected():
+    from paper_2404_07249_amd import _lib
+
+    lib = _lib.load()
+    g = (C.c_int * 3)(32, 32, 64)
+    b = (C.c_double * 3)(1.0, 1.0, 1.0)
+    e = (C.c_double * 2)(1.0, 3.0)
+    h = C.c_void_p()
+    st = lib.pb3_plan_create(g, b, e, 2, _lib.FLAG_HOST_ONLY, C.byref(h))
+    assert st == 1 and not h.value
+    assert b"cubic" in lib.pb3_last_error()
+
+
+def test_host_only_plan_refuses_compute():
+    import paper_2404_07249_amd as pb3
+    from paper_2404_07249_amd import _lib
+
+    p = _plan(32, 100.0, kf_edges(4))
+    lib = _lib.load()
+    pk = (C.c_double * 4)()
+    st = lib.pb3_power(p._h, C.c_void_p(1), pk, None)
+    assert st == 1
+    with pytest.raises(pb3.Pb3Error):
+        p.norm()

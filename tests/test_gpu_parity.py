@@ -1,0 +1,214 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerance (FP32 FFTs, FP32 contraction, FP64 normalisation):
+  P:  |dP| <= 1e-5 |P|                      for every bin
+  B:  |dB| <= 1e-5 |B| + 1e-6 A             for every triplet
+where A is the oracle's normalisation applied to sum_x |G_a G_b G_c|.  The
+A term covers triplets whose B is a near-cancelling sum (A/|B| up to 1e4);
+for well-conditioned triplets the relative bound 1e-5 is what binds.
+Triangle counts are integers and must match exactly.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from synthetic import field_for, kf_edges, quadratic_field
+
+pytestmark = pytest.mark.gpu
+
+P_RTOL = 1e-5
+B_RTOL = 1e-5
+B_ATOL_A = 1e-6
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _gpu(torch, arr):
+    return torch.from_numpy(np.ascontiguousarray(arr, dtype=np.float32)).cuda()
+
+
+def _check_pb(res, pk, bk, trips, label):
+    assert np.array_equal(trips, res.triplets), label
+    dp = np.abs(pk - res.pk)
+    assert np.all(dp <= P_RTOL * np.abs(res.pk)), (label, (dp / np.abs(res.pk)).max())
+    db = np.abs(bk - res.bk)
+    lim = B_RTOL * np.abs(res.bk) + B_ATOL_A * res.absnorm
+    bad = db > lim
+    assert not bad.any(), (label, int(bad.sum()), (db / res.absnorm).max())
+
+
+def _run_case(torch, n, box, edges, delta32, prec="fp32", **plan_kw):
+    import paper_2404_07249_amd as pb3
+
+    _say(f"[case] n={n} box={box} bins={len(edges) - 1} prec={prec} {plan_kw}")
+    plan = pb3.Plan(n, box, edges, **plan_kw)
+    d = _gpu(torch, delta32)
+    pk, bk = plan.polyspectra(d, precision=prec)
+    torch.cuda.synchronize()
+    return plan, pk.cpu().numpy(), bk.cpu().numpy()
+
+
+def test_config1_32cubed_parity(torch_cuda):
+    torch = torch_cuda
+    d, cfg = field_for("c1")
+    plan, pk, bk = _run_case(torch, cfg["n"], cfg["box"], cfg["edges"], d)
+    res = oracle.bispectrum(d.astype(np.float64), cfg["box"], cfg["edges"])
+    nm, cnt = plan.norm()
+    assert np.array_equal(nm, res.n_modes)
+    assert np.array_equal(cnt.astype(np.int64), res.counts)
+    assert plan.n_triplets == 98
+    _check_pb(res, pk, bk, plan.triplets, "c1")
+
+
+def test_config2_128cubed_parity(torch_cuda):
+    torch = torch_cuda
+    d, cfg = field_for("c2")
+    plan, pk, bk = _run_case(torch, cfg["n"], cfg["box"], cfg["edges"], d)
+    res = oracle.bispectrum(d.astype(np.float64), cfg["box"], cfg["edges"])
+    _, cnt = plan.norm()
+    assert np.array_equal(cnt.astype(np.int64), res.counts)
+    _check_pb(res, pk, bk, plan.triplets, "c2")
+
+
+@pytest.mark.parametrize(
+    "n,box,edges",
+    [
+        (48, 700.0, 1.5 + 2.5 * np.arange(7)),  # radix-3 grid, non-integer edges, ragged tiles
+        (96, 2000.0, kf_edges(10)),  # alias-free reduced contraction grid (M = 64 < N)
+        (64, 1000.0, kf_edges(24)),  # full spectrum incl. Nyquist; triplets with T = 0 are dropped
+        (16, 300.0, np.array([1.0, 3.0, 5.0, 7.0, 9.0, 13.9])),  # tiny grid, heavy aliasing
+        (32, 500.0, np.array([2.0, 4.5])),  # a single bin
+    ],
+)
+def test_ragged_and_edge_cases(torch_cuda, n, box, edges):
+    torch = torch_cuda
+    d = quadratic_field(n, box, 1.0, 123 + n).astype(np.float32)
+    plan, pk, bk = _run_case(torch, n, box, edges, d)
+    res = oracle.bispectrum(d.astype(np.float64), box, edges)
+    _, cnt = plan.norm()
+    assert np.array_equal(cnt.astype(np.int64), res.counts)
+    _check_pb(res, pk, bk, plan.triplets, f"n={n}")
+
+
+def test_full_grid_flag_matches_reduced_grid(torch_cuda):
+    torch = torch_cuda
+    n, box = 96, 2000.0
+    edges = kf_edges(10)
+    d = quadratic_field(n, box, 1.0, 7).astype(np.float32)
+    p1, pk1, bk1 = _run_case(torch, n, box, edges, d)
+    p2, pk2, bk2 = _run_case(torch, n, box, edges, d, full_grid=True)
+    assert p1.contract_grid == 64 and p2.contract_grid == 96
+    assert np.array_equal(p1.norm()[1], p2.norm()[1])
+    res = oracle.bispectrum(d.astype(np.float64), box, edges)
+    _check_pb(res, pk2, bk2, p2.triplets, "full grid")
+
+
+def test_config3_256cubed_sampled(torch_cuda):
+    """Headline size, FP32: P for every bin and B on a sample of triplets the
+    oracle computes one by one (only the filtered fields they touch)."""
+    torch = torch_cuda
+    d, cfg = field_for("c3")
+    plan, pk, bk = _run_case(torch, cfg["n"], cfg["box"], cfg["edges"], d)
+    assert plan.contract_grid == 192
+    trips = plan.triplets
+    assert len(trips) == 3035
+    pk_ref = oracle.power_spectrum(d.astype(np.float64), cfg["box"], cfg["edges"])
+    assert np.all(np.abs(pk - pk_ref) <= P_RTOL * np.abs(pk_ref))
+    # sample triplets drawn from 8 of the 30 bins (the oracle only builds the
+    # filtered fields of those bins), always including the extreme bins
+    rng = np.random.default_rng(0)
+    bins = set(rng.choice(np.arange(1, 29), 6, replace=False).tolist()) | {0, 29}
+    cand = [i for i, t in enumerate(trips) if set(t.tolist()) <= bins]
+    pick = np.array(sorted(rng.choice(cand, min(16, len(cand)), replace=False)))
+    sample = trips[pick]
+    s, sa = oracle.triplet_sums_sample(d.astype(np.float64), cfg["edges"], sample)
+    T = oracle.count_sample(cfg["n"], cfg["edges"], sample)
+    _, cnt = plan.norm()
+    assert np.array_equal(cnt[pick].astype(np.int64), T)
+    n3 = float(cfg["n"]) ** 3
+    scale = cfg["box"] ** 6 / n3
+    bref = scale * s / T
+    aref = scale * sa / T
+    lim = B_RTOL * np.abs(bref) + B_ATOL_A * aref
+    assert np.all(np.abs(bk[pick] - bref) <= lim), np.abs(bk[pick] - bref) / aref
+
+
+def test_determinism_and_exact_scaling(torch_cuda):
+    """Fixed-order reductions: repeated calls are bitwise equal, and 2*delta
+    gives exactly 4 P and 8 B (power-of-two scaling is exact in binary FP)."""
+    import paper_2404_07249_amd as pb3
+
+    torch = torch_cuda
+    d, cfg = field_for("c2")
+    plan = pb3.Plan(cfg["n"], cfg["box"], cfg["edges"])
+    x = _gpu(torch, d)
+    pk1, bk1 = [t.cpu().numpy() for t in plan.polyspectra(x)]
+    pk2, bk2 = [t.cpu().numpy() for t in plan.polyspectra(x)]
+    assert np.array_equal(pk1, pk2) and np.array_equal(bk1, bk2)
+    pk3, bk3 = [t.cpu().numpy() for t in plan.polyspectra(2 * x)]
+    assert np.array_equal(pk3, 4 * pk1)
+    assert np.array_equal(bk3, 8 * bk1)
+
+
+def test_translation_invariance_full_size(torch_cuda):
+    import paper_2404_07249_amd as pb3
+
+    torch = torch_cuda
+    d, cfg = field_for("c3")
+    plan = pb3.Plan(cfg["n"], cfg["box"], cfg["edges"])
+    pk1, bk1 = [t.cpu().numpy() for t in plan.polyspectra(_gpu(torch, d))]
+    pk2, bk2 = [t.cpu().numpy() for t in plan.polyspectra(_gpu(torch, np.roll(d, (17, -3, 101), axis=(0, 1, 2))))]
+    assert np.allclose(pk1, pk2, rtol=2e-6)
+    scale = np.abs(bk1).max()
+    assert np.all(np.abs(bk1 - bk2) <= 1e-5 * np.abs(bk1) + 1e-6 * scale)
+
+
+def test_power_alone_equals_polyspectra_and_streams(torch_cuda):
+    import paper_2404_07249_amd as pb3
+
+    torch = torch_cuda
+    d, cfg = field_for("c1")
+    plan = pb3.Plan(cfg["n"], cfg["box"], cfg["edges"], ext_workspace=True)
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+    plan.bind_workspace(ws)
+    x = _gpu(torch, d)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        pk_a = plan.power(x, stream=s)
+        pk_b, bk_b = plan.polyspectra(x, stream=s)
+    s.synchronize()
+    assert np.array_equal(pk_a.cpu().numpy(), pk_b.cpu().numpy())
+    bk_c = plan.bispectrum(x)
+    torch.cuda.synchronize()
+    assert np.array_equal(bk_b.cpu().numpy(), bk_c.cpu().numpy())
+
+
+def test_argument_errors_on_device(torch_cuda):
+    import paper_2404_07249_amd as pb3
+
+    torch = torch_cuda
+    plan = pb3.Plan(32, 1000.0, kf_edges(8))
+    with pytest.raises(ValueError):
+        plan.power(torch.zeros((32, 32, 16), device="cuda"))
+    with pytest.raises(ValueError):
+        plan.power(torch.zeros((32, 32, 32), dtype=torch.float64, device="cuda"))
+    with pytest.raises(TypeError):
+        plan.power(np.zeros((32, 32, 32), dtype=np.float32))
+    p2 = pb3.Plan(32, 1000.0, kf_edges(8), ext_workspace=True)
+    with pytest.raises(pb3.Pb3Error):
+        p2.power(torch.zeros((32, 32, 32), device="cuda"))
