@@ -1,0 +1,270 @@
+// Triplet contraction on the matrix cores (gfx950).
+//
+// S_abc = sum_x G_a(x) G_b(x) G_c(x) for all pairs (a <= b) against all c,
+// as a GEMM  C[pair][c] += A[pair][x] B[x][c]  with the voxels x as the
+// reduction dimension.  The pair products A = G_a G_b are formed on the fly
+// in registers and never stored.
+//
+// Lane layout (wave of 64, lane = 16 g + i): lane (i, g) holds, for every
+// 16-bin group q, the field of bin 16 q + i at its voxels (8 per K-step of
+// 32).  That is exactly the B operand of the MFMA for column block q, and
+// the A operand of a 16-row pair block is one multiplication away: row i
+// of block (p, q, s) is the pair (16 p + i, 16 q + ((i - s) mod 16)), whose
+// second factor arrives from lane (i - s) mod 16 of the same row of 16
+// lanes through a DPP row rotation.  Rotations s = 0..8 cover every
+// unordered pair inside one 16-bin group (s = 8 twice), s = 0..15 every
+// pair across two groups.  Column blocks below the pair's larger group
+// (c < b) are skipped.
+//
+// Mixed precision: A and B are split into bf16 hi + lo (hi by round to
+// nearest even, lo = x - hi exactly in FP32, then rounded), and each tile
+// takes hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16 with FP32
+// accumulation.  FP32: v_mfma_f32_16x16x4_f32 on the unsplit values.
+//
+// Each wave accumulates its K-steps in FP32 registers; the work-group's
+// waves are summed in LDS in a fixed order and written as one FP32 partial
+// per work-group; the fixed-order FP64 reduction over work-groups follows.
+
+#include <hip/hip_runtime.h>
+
+#include "pb3_internal.h"
+
+namespace pb3 {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
+typedef float f2_t __attribute__((ext_vector_type(2)));
+typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2_t;
+
+struct PairBlock {
+  int p, q, s;
+};
+
+constexpr PairBlock pair_block(int nq, int k) {
+  for (int p = 0; p < nq; ++p)
+    for (int q = p; q < nq; ++q) {
+      int ns = (p == q) ? 9 : 16;
+      if (k < ns) return PairBlock{p, q, k};
+      k -= ns;
+    }
+  return PairBlock{-1, -1, -1};
+}
+constexpr int n_pair_blocks(int nq) { return nq * 9 + (nq * (nq - 1) / 2) * 16; }
+// tiles (pair block x column block) in pair blocks [0, k)
+constexpr int tiles_before(int nq, int k) {
+  int t = 0;
+  for (int j = 0; j < k; ++j) t += nq - pair_block(nq, j).q;
+  return t;
+}
+constexpr int n_tiles(int nq) { return tiles_before(nq, n_pair_blocks(nq)); }
+
+// Pair-block ranges processed by one launch ("group"); at most ~48 tiles
+// of accumulators per wave.
+constexpr int n_groups(int nq) { return nq <= 2 ? 1 : 3; }
+constexpr int group_begin(int nq, int g) {
+  if (nq <= 2) return g == 0 ? 0 : n_pair_blocks(nq);
+  // nq == 3 pair blocks in order: (0,0)9 (0,1)16 (0,2)16 (1,1)9 (1,2)16 (2,2)9
+  // tiles per block: 3, 2, 1, 2, 1, 1 -> groups of 43, 32, 43 tiles
+  return g == 0 ? 0 : g == 1 ? 9 + 8 : g == 2 ? 9 + 16 + 16 : n_pair_blocks(nq);
+}
+
+__device__ __forceinline__ float ror16(float x, int s) {
+  switch (s) {
+    case 1: return __builtin_amdgcn_update_dpp(0.0f, x, 0x121, 0xf, 0xf, false);
+    case 2: return __builtin_amdgcn_update_dpp(0.0f, x, 0x122, 0xf, 0xf, false);
+    case 3: return __builtin_amdgcn_update_dpp(0.0f, x, 0x123, 0xf, 0xf, false);
+    case 4: return __builtin_amdgcn_update_dpp(0.0f, x, 0x124, 0xf, 0xf, false);
+    case 5: return __builtin_amdgcn_update_dpp(0.0f, x, 0x125, 0xf, 0xf, false);
+    case 6: return __builtin_amdgcn_update_dpp(0.0f, x, 0x126, 0xf, 0xf, false);
+    case 7: return __builtin_amdgcn_update_dpp(0.0f, x, 0x127, 0xf, 0xf, false);
+    case 8: return __builtin_amdgcn_update_dpp(0.0f, x, 0x128, 0xf, 0xf, false);
+    case 9: return __builtin_amdgcn_update_dpp(0.0f, x, 0x129, 0xf, 0xf, false);
+    case 10: return __builtin_amdgcn_update_dpp(0.0f, x, 0x12a, 0xf, 0xf, false);
+    case 11: return __builtin_amdgcn_update_dpp(0.0f, x, 0x12b, 0xf, 0xf, false);
+    case 12: return __builtin_amdgcn_update_dpp(0.0f, x, 0x12c, 0xf, 0xf, false);
+    case 13: return __builtin_amdgcn_update_dpp(0.0f, x, 0x12d, 0xf, 0xf, false);
+    case 14: return __builtin_amdgcn_update_dpp(0.0f, x, 0x12e, 0xf, 0xf, false);
+    case 15: return __builtin_amdgcn_update_dpp(0.0f, x, 0x12f, 0xf, 0xf, false);
+    default: return x;
+  }
+}
+
+// Split 8 FP32 values into bf16 hi (round to nearest even) and bf16 lo of
+// the exact FP32 residual.
+__device__ __forceinline__ void split8(const float* v, bf16x8_t& hi, bf16x8_t& lo) {
+#pragma unroll
+  for (int j = 0; j < 8; j += 2) {
+    f2_t pv = {v[j], v[j + 1]};
+    bf16x2_t h = __builtin_convertvector(pv, bf16x2_t);
+    hi[j] = h[0];
+    hi[j + 1] = h[1];
+    f2_t hf = __builtin_convertvector(h, f2_t);
+    f2_t r = pv - hf;
+    bf16x2_t l = __builtin_convertvector(r, bf16x2_t);
+    lo[j] = l[0];
+    lo[j + 1] = l[1];
+  }
+}
+
+template <int NQ, bool MIXED, int K, int K1, int T0>
+__device__ __forceinline__ void do_blocks(const float (&gv)[NQ][8], const bf16x8_t (&bh)[NQ], const bf16x8_t (&bl)[NQ],
+                                          f32x4_t* acc) {
+  if constexpr (K < K1) {
+    constexpr PairBlock pb = pair_block(NQ, K);
+    constexpr int tb = tiles_before(NQ, K) - T0;
+    float a[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a[j] = gv[pb.p][j] * ror16(gv[pb.q][j], pb.s);
+    if constexpr (MIXED) {
+      bf16x8_t ah, al;
+      split8(a, ah, al);
+#pragma unroll
+      for (int cb = pb.q; cb < NQ; ++cb) {
+        f32x4_t c = acc[tb + cb - pb.q];
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[cb], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[cb], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[cb], c, 0, 0, 0);
+        acc[tb + cb - pb.q] = c;
+      }
+    } else {
+#pragma unroll
+      for (int cb = pb.q; cb < NQ; ++cb) {
+        f32x4_t c = acc[tb + cb - pb.q];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], gv[cb][j], c, 0, 0, 0);
+        acc[tb + cb - pb.q] = c;
+      }
+    }
+    do_blocks<NQ, MIXED, K + 1, K1, T0>(gv, bh, bl, acc);
+  }
+}
+
+// One launch covers pair blocks [K0, K1) (tiles [T0, T1)).  Work-group =
+// 4 waves; work-group w takes voxels [w*vpw, (w+1)*vpw), its waves
+// interleave K-steps of 32 voxels.  part: [n_wg][n_tiles_total*256] FP32.
+template <int NQ, bool MIXED, int K0, int K1>
+__global__ void __launch_bounds__(256) k_contract_mfma(const float* __restrict__ g, long mvox, long vpw,
+                                                       float* __restrict__ part, int part_len) {
+  constexpr int T0 = tiles_before(NQ, K0);
+  constexpr int T1 = tiles_before(NQ, K1);
+  constexpr int NT = T1 - T0;
+  __shared__ float red[NT * 256];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int i = lane & 15, grp = lane >> 4;
+  f32x4_t acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  const long vb = (long)blockIdx.x * vpw;
+  long ve = vb + vpw;
+  if (ve > mvox) ve = mvox;
+  const float* gl[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) gl[q] = g + (size_t)(16 * q + i) * mvox + 8 * grp;
+  for (long v0 = vb + 32 * wave; v0 < ve; v0 += 128) {
+    float gv[NQ][8];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const float4* src = reinterpret_cast<const float4*>(gl[q] + v0);
+      float4 x0 = src[0], x1 = src[1];
+      gv[q][0] = x0.x; gv[q][1] = x0.y; gv[q][2] = x0.z; gv[q][3] = x0.w;
+      gv[q][4] = x1.x; gv[q][5] = x1.y; gv[q][6] = x1.z; gv[q][7] = x1.w;
+    }
+    bf16x8_t bh[NQ], bl[NQ];
+    if constexpr (MIXED) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) split8(gv[q], bh[q], bl[q]);
+    }
+    do_blocks<NQ, MIXED, K0, K1, T0>(gv, bh, bl, acc);
+  }
+  // fixed-order sum of the four waves in LDS
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int idx = t * 256 + (4 * grp + r) * 16 + i;
+          red[idx] = (w == 0) ? acc[t][r] : red[idx] + acc[t][r];
+        }
+    }
+    __syncthreads();
+  }
+  float* dst = part + (size_t)blockIdx.x * part_len + (size_t)T0 * 256;
+  for (int e = threadIdx.x; e < NT * 256; e += 256) dst[e] = red[e];
+}
+
+template <int NQ, bool MIXED, int G>
+static hipError_t launch_group(const float* g, long mvox, int n_wg, long vpw, float* part, int part_len,
+                               hipStream_t s) {
+  constexpr int K0 = group_begin(NQ, G), K1 = group_begin(NQ, G + 1);
+  hipLaunchKernelGGL((k_contract_mfma<NQ, MIXED, K0, K1>), dim3(n_wg), dim3(256), 0, s, g, mvox, vpw, part, part_len);
+  return hipGetLastError();
+}
+
+template <int NQ, bool MIXED>
+static hipError_t launch_nq(const float* g, long mvox, int n_wg, long vpw, float* part, int part_len, hipStream_t s) {
+  hipError_t e = launch_group<NQ, MIXED, 0>(g, mvox, n_wg, vpw, part, part_len, s);
+  if constexpr (n_groups(NQ) > 1) {
+    if (e == hipSuccess) e = launch_group<NQ, MIXED, 1>(g, mvox, n_wg, vpw, part, part_len, s);
+    if (e == hipSuccess) e = launch_group<NQ, MIXED, 2>(g, mvox, n_wg, vpw, part, part_len, s);
+  }
+  return e;
+}
+
+int mfma_tiles(int nq) {
+  switch (nq) {
+    case 1: return n_tiles(1);
+    case 2: return n_tiles(2);
+    case 3: return n_tiles(3);
+    default: return -1;
+  }
+}
+
+// (tile, row) of the pair (a, b), a <= b, and the tile list order.
+int mfma_locate(int nq, int a, int b, int c) {
+  int p = a / 16, q = b / 16, ia = a % 16, ib = b % 16;
+  int row, s;
+  if (p == q) {
+    int d = ((ia - ib) % 16 + 16) % 16;
+    if (d <= 8) {
+      row = ia;
+      s = d;
+    } else {
+      row = ib;
+      s = 16 - d;
+    }
+  } else {
+    row = ia;
+    s = ((ia - ib) % 16 + 16) % 16;
+  }
+  int cb = c / 16, col = c % 16;
+  if (cb < q) return -1;
+  int npb = n_pair_blocks(nq);
+  for (int k = 0; k < npb; ++k) {
+    PairBlock pb = pair_block(nq, k);
+    if (pb.p == p && pb.q == q && pb.s == s) return (tiles_before(nq, k) + (cb - q)) * 256 + row * 16 + col;
+  }
+  return -1;
+}
+
+hipError_t launch_contract_mfma(const pb3_plan& p, bool mixed, hipStream_t s) {
+  const long mvox = (long)p.M * p.M * p.M;
+  const int nq = p.nb_pad / 16;
+  const int n_wg = p.contract_wgs;
+  long vpw = (mvox + n_wg - 1) / n_wg;
+  vpw = (vpw + 127) / 128 * 128;
+  float* part = p.ws.part;
+  const int pl = p.part_len;
+  switch (nq) {
+    case 1: return mixed ? launch_nq<1, true>(p.ws.g, mvox, n_wg, vpw, part, pl, s)
+                         : launch_nq<1, false>(p.ws.g, mvox, n_wg, vpw, part, pl, s);
+    case 2: return mixed ? launch_nq<2, true>(p.ws.g, mvox, n_wg, vpw, part, pl, s)
+                         : launch_nq<2, false>(p.ws.g, mvox, n_wg, vpw, part, pl, s);
+    case 3: return mixed ? launch_nq<3, true>(p.ws.g, mvox, n_wg, vpw, part, pl, s)
+                         : launch_nq<3, false>(p.ws.g, mvox, n_wg, vpw, part, pl, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace pb3

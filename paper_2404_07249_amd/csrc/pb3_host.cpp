@@ -306,8 +306,8 @@ static pb3_status build_host(pb3_plan* p, const int grid[3], const double box[3]
     return PB3_EUNSUPPORTED;
   }
   p->trip = p->trip_all;
-  p->contract_wgs = 1024;
-  p->part_len = (int)(p->trip_all.size() / 3);
+  p->contract_wgs = 512;
+  p->part_len = mfma_tiles(p->nb_pad / 16) * 256;
   return PB3_OK;
 }
 
@@ -347,6 +347,16 @@ static void carve_workspace(pb3_plan* p, void* base, size_t bytes, bool owned) {
   w.ppart = (double*)take(sizeof(double) * (size_t)std::max(p->n_chunks, 1));
 }
 
+// The contraction reads the bins [nb, nb_pad) of G as zero fields.
+static pb3_status clear_padding(pb3_plan* p) {
+  size_t m3 = (size_t)p->M * p->M * p->M;
+  if (p->nb_pad > p->nb) {
+    hipError_t e = hipMemset(p->ws.g + (size_t)p->nb * m3, 0, sizeof(float) * (size_t)(p->nb_pad - p->nb) * m3);
+    if (e != hipSuccess) return hip_fail(e, "hipMemset");
+  }
+  return PB3_OK;
+}
+
 static pb3_status ensure_workspace(pb3_plan* p) {
   if (p->ws.base) return PB3_OK;
   if (p->flags & PB3_FLAG_EXT_WORKSPACE) {
@@ -361,7 +371,7 @@ static pb3_status ensure_workspace(pb3_plan* p) {
     return PB3_ENOMEM;
   }
   carve_workspace(p, base, bytes, true);
-  return PB3_OK;
+  return clear_padding(p);
 }
 
 static pb3_status build_device(pb3_plan* p) {
@@ -426,10 +436,14 @@ static pb3_status build_device(pb3_plan* p) {
     }
     for (int k = 0; k < 3; ++k) p->trip.push_back(p->trip_all[3 * t + k]);
     p->counts.push_back(T);
-    map.push_back(t);
+    int loc = mfma_locate(p->nb_pad / 16, p->trip_all[3 * t], p->trip_all[3 * t + 1], p->trip_all[3 * t + 2]);
+    if (loc < 0 || loc >= p->part_len) {
+      set_error("internal: triplet not covered by the contraction tiles");
+      return PB3_EDEVICE;
+    }
+    map.push_back(loc);
     fac.push_back(scale / T);
   }
-  p->map_simple = map;
   if ((st = upload(&d.out_map, map.data(), map.size())) != PB3_OK) return st;
   if ((st = upload(&d.inv_counts, fac.data(), fac.size())) != PB3_OK) return st;
   if (p->flags & PB3_FLAG_STAGE_TIMING) {
@@ -569,7 +583,7 @@ pb3_status pb3_plan_bind_workspace(pb3_plan* plan, void* dev, size_t bytes) {
   }
   if (plan->ws.owned && plan->ws.base) hipFree(plan->ws.base);
   carve_workspace(plan, dev, bytes, false);
-  return PB3_OK;
+  return plan->device ? clear_padding(plan) : PB3_OK;
 }
 
 int pb3_n_bins(const pb3_plan* plan) { return plan ? plan->nb : 0; }

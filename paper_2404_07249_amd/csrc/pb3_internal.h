@@ -44,11 +44,6 @@ struct BinGeom {
   int64_t a2_off;   // float2 offset of this bin's y-pass output  [M][M][kzn]
 };
 
-// Output tile of the MFMA contraction: pair block (p, q, s) x column block cb.
-struct ContractTile {
-  int8_t p, q, s, cb;
-};
-
 // A device tile table for one inverse pass and the tile width it was built for.
 struct TileSet {
   BinTile* d;
@@ -63,7 +58,7 @@ struct DeviceTables {
   BinGeom* geom = nullptr;        // per bin
   BinTile* tiles = nullptr;       // all FP32 inverse-pass tiles (x, then y, then z)
   int32_t* trip_all = nullptr;    // candidate triplets (3 ints each), simple contraction
-  int32_t* out_map = nullptr;     // per kept triplet: index into one WG's partial vector
+  int32_t* out_map = nullptr;     // per kept triplet: index into one work-group's MFMA partial vector
   double* inv_counts = nullptr;   // per kept triplet: scale / T
   double* pk_scale = nullptr;     // per bin: V / (N^6 N_b)
   float2* tw_n = nullptr;         // W_N^j, j < N
@@ -84,7 +79,7 @@ struct Workspace {
   float2* a1 = nullptr;     // per-bin x-pass outputs
   float2* a2 = nullptr;     // per-bin y-pass outputs
   float* g = nullptr;       // [nb_pad][M^3]
-  float* part = nullptr;    // contraction partials
+  float* part = nullptr;    // contraction partials [work-group][tile*256]
   double* ppart = nullptr;  // power partials
 };
 
@@ -120,18 +115,12 @@ struct pb3_plan {
   pb3::TileSet tx{}, ty{}, tz{};   // FP32 inverse-pass tiles (device)
   // contraction
   int contract_wgs = 0;
-  int part_len = 0;            // floats per WG partial vector (simple: n candidates; mfma: tiles*256)
-  int n_ctiles = 0;
-  std::vector<pb3::ContractTile> ctiles;
-  std::vector<int32_t> map_simple, map_mfma;  // per kept triplet
+  int part_len = 0;            // floats per work-group partial vector (MFMA tiles * 256)
   pb3_precision last_prec = PB3_FP32;
   bool device = false;
   int device_id = 0;
   pb3::DeviceTables d;
   pb3::Workspace ws;
-  int32_t* d_map_simple = nullptr;
-  int32_t* d_map_mfma = nullptr;
-  pb3::ContractTile* d_ctiles = nullptr;
   // timing: ring of event pairs, slot = call index mod kTimingRing
   static constexpr int kTimingRing = 256;
   std::vector<hipEvent_t> ev;              // [ring][stage][2]
@@ -158,6 +147,11 @@ hipError_t launch_reduce(const pb3_plan& p, pb3_precision prec, double* bk, hipS
 // FP64 triangle counts on the contraction grid: writes raw M^6 sum HHH for
 // every candidate triplet into counts_out (host), using temporary memory.
 pb3_status compute_counts_fp64(pb3_plan& p, std::vector<double>& counts_out);
+// MFMA contraction (contract_mfma.hip): tiles for nq 16-bin groups, the
+// partial-vector index of triplet (a, b, c) (-1 if not produced), launch
+int mfma_tiles(int nq);
+int mfma_locate(int nq, int a, int b, int c);
+hipError_t launch_contract_mfma(const pb3_plan& p, bool mixed, hipStream_t s);
 // tile widths of the inverse passes for FP32 (dbl = false) or FP64 lines
 int tile_width_x(int M, bool dbl);
 int tile_width_z(int M, bool dbl);

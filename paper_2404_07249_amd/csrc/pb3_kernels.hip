@@ -299,21 +299,23 @@ __global__ void __launch_bounds__(512) k_inv_z(const typename Cx<Rl>::type* __re
 // ------------------------------------------------ simple triplet contraction
 // Reference-structure contraction: every work-group takes a contiguous
 // voxel range, stages VT voxels of all bins in LDS and each thread
-// accumulates up to TPT triplets sum_x G_a G_b G_c in registers.
-// partial[wg][t] for every candidate triplet t.
+// accumulates up to TPT triplets sum_x G_a G_b G_c.  Each VT-voxel tile is
+// summed in the working precision and flushed into an FP64 running sum, so
+// the rounding error does not grow with the number of voxels per thread.
+// partial[wg][t] (FP64) for every candidate triplet t.
 template <typename Rl, int TPT>
 __global__ void __launch_bounds__(256) k_contract_simple(const Rl* __restrict__ g, int nb, long mvox,
                                                          const int32_t* __restrict__ trips, int n_trip,
-                                                         long vox_per_wg, Rl* __restrict__ part) {
+                                                         long vox_per_wg, double* __restrict__ part) {
   constexpr int VT = 64;
   extern __shared__ unsigned char smem_raw[];
   Rl* tileg = reinterpret_cast<Rl*>(smem_raw);  // [nb][VT]
   const int tid = threadIdx.x;
-  Rl acc[TPT];
+  double acc[TPT];
   int ta[TPT], tbb[TPT], tc[TPT];
 #pragma unroll
   for (int i = 0; i < TPT; ++i) {
-    acc[i] = Rl(0);
+    acc[i] = 0.0;
     int t = tid + i * 256;
     if (t < n_trip) {
       ta[i] = trips[3 * t];
@@ -340,9 +342,9 @@ __global__ void __launch_bounds__(256) k_contract_simple(const Rl* __restrict__ 
         const Rl* pa = tileg + ta[i] * VT;
         const Rl* pb = tileg + tbb[i] * VT;
         const Rl* pc = tileg + tc[i] * VT;
-        Rl s = acc[i];
+        Rl s = Rl(0);
         for (int j = 0; j < VT; ++j) s += pa[j] * pb[j] * pc[j];
-        acc[i] = s;
+        acc[i] += (double)s;
       }
     }
   }
@@ -550,7 +552,7 @@ static int tpt_for(int n) {
 
 template <typename Rl>
 static hipError_t contract_simple(const Rl* g, int nb, long mvox, const int32_t* trips, int n_trip, int n_wg,
-                                  Rl* part, hipStream_t s) {
+                                  double* part, hipStream_t s) {
   long per = (mvox + n_wg - 1) / n_wg;
   size_t sh = (size_t)nb * 64 * sizeof(Rl);
   switch (tpt_for(n_trip)) {
@@ -575,10 +577,7 @@ static hipError_t contract_simple(const Rl* g, int nb, long mvox, const int32_t*
 }
 
 hipError_t launch_contract(const pb3_plan& p, pb3_precision prec, hipStream_t s) {
-  (void)prec;
-  long mvox = (long)p.M * p.M * p.M;
-  return contract_simple<float>(p.ws.g, p.nb, mvox, p.d.trip_all, (int)(p.trip_all.size() / 3), p.contract_wgs,
-                                p.ws.part, s);
+  return launch_contract_mfma(p, prec == PB3_MIXED_BF16X3, s);
 }
 
 hipError_t launch_reduce(const pb3_plan& p, pb3_precision prec, double* bk, hipStream_t s) {
