@@ -70,21 +70,21 @@ constexpr int group_begin(int nq, int g) {
 
 __device__ __forceinline__ float ror16(float x, int s) {
   switch (s) {
-    case 1: return __builtin_amdgcn_update_dpp(0.0f, x, 0x121, 0xf, 0xf, false);
-    case 2: return __builtin_amdgcn_update_dpp(0.0f, x, 0x122, 0xf, 0xf, false);
-    case 3: return __builtin_amdgcn_update_dpp(0.0f, x, 0x123, 0xf, 0xf, false);
-    case 4: return __builtin_amdgcn_update_dpp(0.0f, x, 0x124, 0xf, 0xf, false);
-    case 5: return __builtin_amdgcn_update_dpp(0.0f, x, 0x125, 0xf, 0xf, false);
-    case 6: return __builtin_amdgcn_update_dpp(0.0f, x, 0x126, 0xf, 0xf, false);
-    case 7: return __builtin_amdgcn_update_dpp(0.0f, x, 0x127, 0xf, 0xf, false);
-    case 8: return __builtin_amdgcn_update_dpp(0.0f, x, 0x128, 0xf, 0xf, false);
-    case 9: return __builtin_amdgcn_update_dpp(0.0f, x, 0x129, 0xf, 0xf, false);
-    case 10: return __builtin_amdgcn_update_dpp(0.0f, x, 0x12a, 0xf, 0xf, false);
-    case 11: return __builtin_amdgcn_update_dpp(0.0f, x, 0x12b, 0xf, 0xf, false);
-    case 12: return __builtin_amdgcn_update_dpp(0.0f, x, 0x12c, 0xf, 0xf, false);
-    case 13: return __builtin_amdgcn_update_dpp(0.0f, x, 0x12d, 0xf, 0xf, false);
-    case 14: return __builtin_amdgcn_update_dpp(0.0f, x, 0x12e, 0xf, 0xf, false);
-    case 15: return __builtin_amdgcn_update_dpp(0.0f, x, 0x12f, 0xf, 0xf, false);
+    case 1: return __builtin_amdgcn_update_dpp(0.0f, x, 0x121, 0xf, 0xf, true);
+    case 2: return __builtin_amdgcn_update_dpp(0.0f, x, 0x122, 0xf, 0xf, true);
+    case 3: return __builtin_amdgcn_update_dpp(0.0f, x, 0x123, 0xf, 0xf, true);
+    case 4: return __builtin_amdgcn_update_dpp(0.0f, x, 0x124, 0xf, 0xf, true);
+    case 5: return __builtin_amdgcn_update_dpp(0.0f, x, 0x125, 0xf, 0xf, true);
+    case 6: return __builtin_amdgcn_update_dpp(0.0f, x, 0x126, 0xf, 0xf, true);
+    case 7: return __builtin_amdgcn_update_dpp(0.0f, x, 0x127, 0xf, 0xf, true);
+    case 8: return __builtin_amdgcn_update_dpp(0.0f, x, 0x128, 0xf, 0xf, true);
+    case 9: return __builtin_amdgcn_update_dpp(0.0f, x, 0x129, 0xf, 0xf, true);
+    case 10: return __builtin_amdgcn_update_dpp(0.0f, x, 0x12a, 0xf, 0xf, true);
+    case 11: return __builtin_amdgcn_update_dpp(0.0f, x, 0x12b, 0xf, 0xf, true);
+    case 12: return __builtin_amdgcn_update_dpp(0.0f, x, 0x12c, 0xf, 0xf, true);
+    case 13: return __builtin_amdgcn_update_dpp(0.0f, x, 0x12d, 0xf, 0xf, true);
+    case 14: return __builtin_amdgcn_update_dpp(0.0f, x, 0x12e, 0xf, 0xf, true);
+    case 15: return __builtin_amdgcn_update_dpp(0.0f, x, 0x12f, 0xf, 0xf, true);
     default: return x;
   }
 }
@@ -139,29 +139,25 @@ __device__ __forceinline__ void do_blocks(const float (&gv)[NQ][8], const bf16x8
   }
 }
 
-// One launch covers pair blocks [K0, K1) (tiles [T0, T1)).  Work-group =
-// 4 waves; work-group w takes voxels [w*vpw, (w+1)*vpw), its waves
-// interleave K-steps of 32 voxels.  part: [n_wg][n_tiles_total*256] FP32.
-template <int NQ, bool MIXED, int K0, int K1>
-__global__ void __launch_bounds__(256) k_contract_mfma(const float* __restrict__ g, long mvox, long vpw,
-                                                       float* __restrict__ part, int part_len) {
+// Balanced split of pair blocks [k0, k1) between two wave-halves: cost of
+// a block ~ its split (VALU) plus its tiles (MFMA).
+constexpr int block_cost(int nq, int k) { return 128 + 48 * (nq - pair_block(nq, k).q); }
+constexpr int split_point(int nq, int k0, int k1) {
+  int total = 0;
+  for (int k = k0; k < k1; ++k) total += block_cost(nq, k);
+  int acc = 0;
+  for (int k = k0; k < k1; ++k) {
+    acc += block_cost(nq, k);
+    if (2 * acc >= total) return k + 1 < k1 ? k + 1 : k1;
+  }
+  return k1;
+}
+
+template <int NQ, bool MIXED, int K0, int K1, int NTMAX>
+__device__ __forceinline__ void contract_loop(const float* const (&gl)[NQ], long v_begin, long v_end,
+                                              f32x4_t (&acc)[NTMAX]) {
   constexpr int T0 = tiles_before(NQ, K0);
-  constexpr int T1 = tiles_before(NQ, K1);
-  constexpr int NT = T1 - T0;
-  __shared__ float red[NT * 256];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int i = lane & 15, grp = lane >> 4;
-  f32x4_t acc[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  const long vb = (long)blockIdx.x * vpw;
-  long ve = vb + vpw;
-  if (ve > mvox) ve = mvox;
-  const float* gl[NQ];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) gl[q] = g + (size_t)(16 * q + i) * mvox + 8 * grp;
-  for (long v0 = vb + 32 * wave; v0 < ve; v0 += 128) {
+  for (long v0 = v_begin; v0 < v_end; v0 += 128) {
     float gv[NQ][8];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -177,28 +173,66 @@ __global__ void __launch_bounds__(256) k_contract_mfma(const float* __restrict__
     }
     do_blocks<NQ, MIXED, K0, K1, T0>(gv, bh, bl, acc);
   }
-  // fixed-order sum of the four waves in LDS
+}
+
+// One launch covers pair blocks [K0, K1) (tiles [T0, T1)), split at KM
+// between two halves of 4 waves each; both halves stream the same voxels.
+// Work-group w takes voxels [w*vpw, (w+1)*vpw); the 4 waves of a half
+// interleave K-steps of 32 voxels.  part: [n_wg][n_tiles_total*256] FP32.
+template <int NQ, bool MIXED, int K0, int KM, int K1>
+__global__ void __launch_bounds__(512) k_contract_mfma(const float* __restrict__ g, long mvox, long vpw,
+                                                       float* __restrict__ part, int part_len) {
+  constexpr int T0 = tiles_before(NQ, K0);
+  constexpr int TM = tiles_before(NQ, KM);
+  constexpr int T1 = tiles_before(NQ, K1);
+  constexpr int NTA = TM - T0, NTB = T1 - TM;
+  constexpr int NTMAX = NTA > NTB ? NTA : NTB;
+  __shared__ float red[(T1 - T0) * 256];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int half = wave >> 2, wq = wave & 3;
+  const int i = lane & 15, grp = lane >> 4;
+  f32x4_t acc[NTMAX];
+#pragma unroll
+  for (int t = 0; t < NTMAX; ++t) acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  const long vb = (long)blockIdx.x * vpw;
+  long ve = vb + vpw;
+  if (ve > mvox) ve = mvox;
+  const float* gl[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) gl[q] = g + (size_t)(16 * q + i) * mvox + 8 * grp;
+  if (half == 0)
+    contract_loop<NQ, MIXED, K0, KM>(gl, vb + 32 * wq, ve, acc);
+  else
+    contract_loop<NQ, MIXED, KM, K1>(gl, vb + 32 * wq, ve, acc);
+  // fixed-order sum of the four waves of each half in LDS
   for (int w = 0; w < 4; ++w) {
-    if (wave == w) {
+    if (wq == w) {
+      const int nt = half == 0 ? NTA : NTB;
+      float* r = red + (half == 0 ? 0 : NTA * 256);
 #pragma unroll
-      for (int t = 0; t < NT; ++t)
+      for (int t = 0; t < NTMAX; ++t)
+        if (t < nt) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          int idx = t * 256 + (4 * grp + r) * 16 + i;
-          red[idx] = (w == 0) ? acc[t][r] : red[idx] + acc[t][r];
+          for (int q = 0; q < 4; ++q) {
+            int idx = t * 256 + (4 * grp + q) * 16 + i;
+            r[idx] = (w == 0) ? acc[t][q] : r[idx] + acc[t][q];
+          }
         }
     }
     __syncthreads();
   }
   float* dst = part + (size_t)blockIdx.x * part_len + (size_t)T0 * 256;
-  for (int e = threadIdx.x; e < NT * 256; e += 256) dst[e] = red[e];
+  for (int e = threadIdx.x; e < (T1 - T0) * 256; e += 512) dst[e] = red[e];
 }
 
 template <int NQ, bool MIXED, int G>
 static hipError_t launch_group(const float* g, long mvox, int n_wg, long vpw, float* part, int part_len,
                                hipStream_t s) {
   constexpr int K0 = group_begin(NQ, G), K1 = group_begin(NQ, G + 1);
-  hipLaunchKernelGGL((k_contract_mfma<NQ, MIXED, K0, K1>), dim3(n_wg), dim3(256), 0, s, g, mvox, vpw, part, part_len);
+  constexpr int KM = split_point(NQ, K0, K1);
+  hipLaunchKernelGGL((k_contract_mfma<NQ, MIXED, K0, KM, K1>), dim3(n_wg), dim3(512), 0, s, g, mvox, vpw, part,
+                     part_len);
   return hipGetLastError();
 }
 
@@ -246,6 +280,29 @@ int mfma_locate(int nq, int a, int b, int c) {
     if (pb.p == p && pb.q == q && pb.s == s) return (tiles_before(nq, k) + (cb - q)) * 256 + row * 16 + col;
   }
   return -1;
+}
+
+// Work-groups that fill the device once: CUs x resident 8-wave groups.
+int mfma_grid(int nq, int n_cu) {
+  int per = 1;
+  hipError_t e = hipErrorInvalidValue;
+  switch (nq) {
+    case 1:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per, (const void*)k_contract_mfma<1, true, 0, split_point(1, 0, 9), 9>, 512, 0);
+      break;
+    case 2:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per, (const void*)k_contract_mfma<2, true, 0, split_point(2, 0, 34), 34>, 512, 0);
+      break;
+    default:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per, (const void*)k_contract_mfma<3, true, 0, split_point(3, 0, 17), 17>, 512, 0);
+      break;
+  }
+  if (e != hipSuccess || per < 1) per = 1;
+  if (per > 4) per = 4;
+  return n_cu * per;
 }
 
 hipError_t launch_contract_mfma(const pb3_plan& p, bool mixed, hipStream_t s) {

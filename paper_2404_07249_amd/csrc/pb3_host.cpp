@@ -322,6 +322,7 @@ static size_t workspace_bytes(const pb3_plan* p) {
   b += align_up(sizeof(float) * (size_t)p->nb_pad * p->M * p->M * p->M, A);
   b += align_up(sizeof(float) * (size_t)p->contract_wgs * p->part_len, A);
   b += align_up(sizeof(double) * (size_t)std::max(p->n_chunks, 1), A);
+  b += align_up(sizeof(double) * (size_t)kReduceSlices * p->part_len, A);
   return b;
 }
 
@@ -345,6 +346,7 @@ static void carve_workspace(pb3_plan* p, void* base, size_t bytes, bool owned) {
   w.g = (float*)take(sizeof(float) * (size_t)p->nb_pad * p->M * p->M * p->M);
   w.part = (float*)take(sizeof(float) * (size_t)p->contract_wgs * p->part_len);
   w.ppart = (double*)take(sizeof(double) * (size_t)std::max(p->n_chunks, 1));
+  w.rsl = (double*)take(sizeof(double) * (size_t)kReduceSlices * p->part_len);
 }
 
 // The contraction reads the bins [nb, nb_pad) of G as zero fields.
@@ -378,6 +380,10 @@ static pb3_status build_device(pb3_plan* p) {
   pb3_status st;
   hipError_t e = hipGetDevice(&p->device_id);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  int n_cu = 0;
+  e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, p->device_id);
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+  p->contract_wgs = mfma_grid(p->nb_pad / 16, n_cu);
   DeviceTables& d = p->d;
   if ((st = upload(&d.lut, p->lut.data(), p->lut.size())) != PB3_OK) return st;
   if ((st = upload(&d.modes, p->modes.data(), p->modes.size())) != PB3_OK) return st;

@@ -12,6 +12,8 @@
 
 namespace pb3 {
 
+constexpr int kReduceSlices = 16;
+
 // Stage indices for the optional per-kernel timing.
 enum Stage {
   ST_FWD_Z = 0,
@@ -80,6 +82,7 @@ struct Workspace {
   float2* a2 = nullptr;     // per-bin y-pass outputs
   float* g = nullptr;       // [nb_pad][M^3]
   float* part = nullptr;    // contraction partials [work-group][tile*256]
+  double* rsl = nullptr;    // reduction slices [kReduceSlices][tile*256]
   double* ppart = nullptr;  // power partials
 };
 
@@ -152,6 +155,7 @@ pb3_status compute_counts_fp64(pb3_plan& p, std::vector<double>& counts_out);
 int mfma_tiles(int nq);
 int mfma_locate(int nq, int a, int b, int c);
 hipError_t launch_contract_mfma(const pb3_plan& p, bool mixed, hipStream_t s);
+int mfma_grid(int nq, int n_cu);
 // tile widths of the inverse passes for FP32 (dbl = false) or FP64 lines
 int tile_width_x(int M, bool dbl);
 int tile_width_z(int M, bool dbl);

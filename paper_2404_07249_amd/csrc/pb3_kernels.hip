@@ -43,9 +43,13 @@ __global__ void __launch_bounds__(512) k_fwd_z(const float* __restrict__ delta, 
   constexpr int LP = H + 1;
   constexpr int TB = lines_per_wg(T, LP * 8);
   __shared__ float2 buf[TB * LP];
+  __shared__ float2 twh[H];
+  __shared__ float2 twn[N];
   const int tid = threadIdx.x;
   const int l0 = blockIdx.x * TB;
   const float2* in2 = reinterpret_cast<const float2*>(delta);
+  for (int e = tid; e < H; e += TB * T) twh[e] = tw_h[e];
+  for (int e = tid; e < N; e += TB * T) twn[e] = tw_n[e];
   for (int e = tid; e < TB * H; e += TB * T) {
     int line = e / H, p = e % H;
     float2 v = make_float2(0.f, 0.f);
@@ -54,7 +58,7 @@ __global__ void __launch_bounds__(512) k_fwd_z(const float* __restrict__ delta, 
   }
   __syncthreads();
   const int line = tid / T, t = tid % T;
-  stockham<H, -1, T>(buf + line * LP, t, tw_h);
+  stockham<H, -1, T>(buf + line * LP, t, twh);
   if (l0 + line < n_lines) {
     const float2* z = buf + line * LP;
     for (int k = t; k < Kz; k += T) {
@@ -64,7 +68,7 @@ __global__ void __launch_bounds__(512) k_fwd_z(const float* __restrict__ delta, 
       float2 e = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
       float2 d = make_float2(zk.x - zc.x, zk.y - zc.y);
       float2 o = make_float2(0.5f * d.y, -0.5f * d.x);  // -i d / 2
-      float2 w = tw_n[k % N];
+      float2 w = twn[k % N];
       float2 x = make_float2(e.x + w.x * o.x - w.y * o.y, e.y + w.x * o.y + w.y * o.x);
       f1[(size_t)(l0 + line) * Kz + k] = x;
     }
@@ -83,9 +87,11 @@ __global__ void __launch_bounds__(512) k_fwd_col(const float2* __restrict__ in, 
   constexpr int TB0 = 256 / T < 16 ? 16 : 256 / T;
   constexpr int TB = (TB0 * LP * 8 > 64 * 1024) ? (64 * 1024) / (LP * 8) : TB0;
   __shared__ float2 buf[TB * LP];
+  __shared__ float2 tws[N];
   const int tid = threadIdx.x;
   const int nth = TB * T;
   const int i0 = blockIdx.x * TB;
+  for (int e = tid; e < N; e += nth) tws[e] = tw[e];
   const float2* src = in + (size_t)blockIdx.y * in_outer;
   for (int e = tid; e < N * TB; e += nth) {
     int p = e / TB, col = e % TB;
@@ -94,7 +100,7 @@ __global__ void __launch_bounds__(512) k_fwd_col(const float2* __restrict__ in, 
     buf[col * LP + p] = v;
   }
   __syncthreads();
-  stockham<N, -1, T>(buf + (tid / T) * LP, tid % T, tw);
+  stockham<N, -1, T>(buf + (tid / T) * LP, tid % T, tws);
   float2* dst = out + (size_t)blockIdx.y * out_outer;
   for (int e = tid; e < Lo * TB; e += nth) {
     int c = e / TB, col = e % TB;
@@ -157,8 +163,10 @@ __global__ void __launch_bounds__(512) k_inv_x(const float2* __restrict__ dc, ty
   constexpr int TB0 = 256 / T < 16 ? 16 : 256 / T;
   constexpr int TB = (TB0 * LP * (int)sizeof(C) > 64 * 1024) ? (64 * 1024) / (LP * (int)sizeof(C)) : TB0;
   __shared__ C buf[TB * LP];
+  __shared__ C tws[M];
   const int tid = threadIdx.x;
   const int nth = TB * T;
+  for (int e = tid; e < M; e += nth) tws[e] = tw[e];
   const BinTile tile = tiles[blockIdx.x];
   const int b = tile.bin;
   const BinGeom g = geom[b];
@@ -184,7 +192,7 @@ __global__ void __launch_bounds__(512) k_inv_x(const float2* __restrict__ dc, ty
     buf[col * LP + p] = v;
   }
   __syncthreads();
-  stockham<M, 1, T>(buf + (tid / T) * LP, tid % T, tw);
+  stockham<M, 1, T>(buf + (tid / T) * LP, tid % T, tws);
   C* dst = a1 + g.a1_off;
   for (int e = tid; e < M * TB; e += nth) {
     int x = e / TB, col = e % TB;
@@ -206,8 +214,10 @@ __global__ void __launch_bounds__(512) k_inv_y(const typename Cx<Rl>::type* __re
   constexpr int TB0 = 256 / T < 16 ? 16 : 256 / T;
   constexpr int TB = (TB0 * LP * (int)sizeof(C) > 64 * 1024) ? (64 * 1024) / (LP * (int)sizeof(C)) : TB0;
   __shared__ C buf[TB * LP];
+  __shared__ C tws[M];
   const int tid = threadIdx.x;
   const int nth = TB * T;
+  for (int e = tid; e < M; e += nth) tws[e] = tw[e];
   const BinTile tile = tiles[blockIdx.x];
   const BinGeom g = geom[tile.bin];
   const int ncol = M * g.kzn;
@@ -224,7 +234,7 @@ __global__ void __launch_bounds__(512) k_inv_y(const typename Cx<Rl>::type* __re
     buf[col * LP + p] = v;
   }
   __syncthreads();
-  stockham<M, 1, T>(buf + (tid / T) * LP, tid % T, tw);
+  stockham<M, 1, T>(buf + (tid / T) * LP, tid % T, tws);
   C* dst = a2 + g.a2_off;
   for (int e = tid; e < M * TB; e += nth) {
     int y = e / TB, col = e % TB;
@@ -255,8 +265,12 @@ __global__ void __launch_bounds__(512) k_inv_z(const typename Cx<Rl>::type* __re
   constexpr int TB = lines_per_wg(T, (LX + LZ) * (int)sizeof(C));
   __shared__ C xb[TB * LX];
   __shared__ C zb[TB * LZ];
+  __shared__ C twh[H];
+  __shared__ C twm[M];
   const int tid = threadIdx.x;
   const int nth = TB * T;
+  for (int e = tid; e < H; e += nth) twh[e] = tw_h[e];
+  for (int e = tid; e < M; e += nth) twm[e] = tw_m[e];
   const BinTile tile = tiles[blockIdx.x];
   const BinGeom g = geom[tile.bin];
   const int nlines = M * M;
@@ -277,13 +291,13 @@ __global__ void __launch_bounds__(512) k_inv_z(const typename Cx<Rl>::type* __re
     b.y = -b.y;  // conj X_{M/2-k}
     C s = cadd(a, b);
     C d = csub(a, b);
-    C w = tw_m[k];  // W_M^k; multiply by its conjugate
+    C w = twm[k];  // W_M^k; multiply by its conjugate
     C dw = cmulc(d, w);
     // Z = s + i dw
     zb[line * LZ + k] = cx<C>(s.x - dw.y, s.y + dw.x);
   }
   __syncthreads();
-  stockham<H, 1, T>(zb + (tid / T) * LZ, tid % T, tw_h);
+  stockham<H, 1, T>(zb + (tid / T) * LZ, tid % T, twh);
   Rl* dst = gout + (size_t)tile.bin * ((size_t)M * M * M);
   for (int e = tid; e < TB * H; e += nth) {
     int line = e / H, n = e % H;
@@ -367,6 +381,29 @@ __global__ void k_reduce(const Rl* __restrict__ part, int n_wg, int part_len, co
   double s = 0.0;
   for (int w = 0; w < n_wg; ++w) s += (double)part[(size_t)w * part_len + idx];
   out[t] = fac ? s * fac[t] : s;
+}
+
+// Two-stage form for the MFMA partials: slice s of the work-groups is
+// summed per element (FP64), then the slices per kept triplet.
+__global__ void k_reduce_slices(const float* __restrict__ part, int n_wg, int part_len, double* __restrict__ rsl) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= part_len) return;
+  int s = blockIdx.y;
+  int w0 = (int)((long)n_wg * s / kReduceSlices), w1 = (int)((long)n_wg * (s + 1) / kReduceSlices);
+  double acc = 0.0;
+  for (int w = w0; w < w1; ++w) acc += (double)part[(size_t)w * part_len + e];
+  rsl[(size_t)s * part_len + e] = acc;
+}
+
+__global__ void k_reduce_final(const double* __restrict__ rsl, int part_len, const int32_t* __restrict__ map,
+                               const double* __restrict__ fac, int n_out, double* __restrict__ out) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_out) return;
+  int idx = map[t];
+  double acc = 0.0;
+#pragma unroll
+  for (int s = 0; s < kReduceSlices; ++s) acc += rsl[(size_t)s * part_len + idx];
+  out[t] = acc * fac[t];
 }
 
 // ================================================================ launchers
@@ -584,8 +621,12 @@ hipError_t launch_reduce(const pb3_plan& p, pb3_precision prec, double* bk, hipS
   (void)prec;
   int n_out = (int)(p.trip.size() / 3);
   if (n_out == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_reduce<float>), dim3((n_out + 255) / 256), dim3(256), 0, s, p.ws.part, p.contract_wgs,
-                     p.part_len, p.d.out_map, p.d.inv_counts, n_out, bk);
+  hipLaunchKernelGGL(k_reduce_slices, dim3((p.part_len + 255) / 256, kReduceSlices), dim3(256), 0, s, p.ws.part,
+                     p.contract_wgs, p.part_len, p.ws.rsl);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_final, dim3((n_out + 255) / 256), dim3(256), 0, s, p.ws.rsl, p.part_len, p.d.out_map,
+                     p.d.inv_counts, n_out, bk);
   return hipGetLastError();
 }
 
