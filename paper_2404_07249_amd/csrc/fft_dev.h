@@ -175,7 +175,18 @@ constexpr int fft_threads(int n) { return n / radix_at(n, 0); }
 // radix of the stage that follows LS points already transformed
 constexpr int radix_at_ls(int n, int ls) { return next_radix(n / ls); }
 
-// One Stockham stage on a line in LDS (stride 1), executed by T threads
+// LDS layout of a line: element i lives at px(i) = i + i/16, one pad slot
+// per 16 elements, so the first stage's stride-16 writes fall on distinct
+// banks.  Lines are line_pitch() apart: at least the padded span and
+// congruent to the threads per line modulo 32, so that neighbouring lines
+// of a wave do not alias onto the same banks.
+__host__ __device__ constexpr int px(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int line_span(int n) { return n + (n >> 4); }
+__host__ __device__ constexpr int line_pitch(int n, int t) {
+  return line_span(n) + (((t - line_span(n)) % 32) + 32) % 32;
+}
+
+// One Stockham stage on a line in LDS (layout px), executed by T threads
 // (index t) of the line; every thread of the work-group must call it (it
 // contains barriers).  LS = product of the radices already applied.
 template <int N, int S, int LS, int T, typename C>
@@ -189,7 +200,7 @@ __device__ __forceinline__ void stockham_stage(C* buf, int t, const C* __restric
     int j = t + it * T;
     if (NB % T == 0 || j < NB) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[it][r] = buf[j + r * NB];
+      for (int r = 0; r < R; ++r) v[it][r] = buf[px(j + r * NB)];
     }
   }
   __syncthreads();
@@ -209,7 +220,7 @@ __device__ __forceinline__ void stockham_stage(C* buf, int t, const C* __restric
       dft<R, S>(v[it]);
       int base = (j / LS) * LS * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[base + r * LS] = v[it][r];
+      for (int r = 0; r < R; ++r) buf[px(base + r * LS)] = v[it][r];
     }
   }
   __syncthreads();

@@ -29,6 +29,30 @@ __host__ __device__ constexpr int lines_per_wg(int t, int lp_bytes) {
   return tb;
 }
 
+// Work-group shapes, shared by the kernels and their launchers.
+// z passes: TB contiguous lines of T threads each.
+template <int N> struct FwdZGeom {
+  static constexpr int H = N / 2;
+  static constexpr int T = fft_threads(H);
+  static constexpr int LP = line_pitch(H, T);
+  static constexpr int TB = lines_per_wg(T, LP * 8);
+};
+// strided passes: TB columns (consecutive inner indices) of T threads; CS =
+// bytes per complex element
+template <int N, int CS> struct ColGeom {
+  static constexpr int T = fft_threads(N);
+  static constexpr int LP = line_pitch(N, T);
+  static constexpr int TB0 = 256 / T < 16 ? 16 : 256 / T;
+  static constexpr int TB = (TB0 * LP * CS > 64 * 1024) ? (64 * 1024) / (LP * CS) : TB0;
+};
+template <int M, int CS> struct InvZGeom {
+  static constexpr int H = M / 2;
+  static constexpr int T = fft_threads(H);
+  static constexpr int LX = H + 2;  // X_0..X_{M/2} plus pad
+  static constexpr int LZ = line_pitch(H, T);
+  static constexpr int TB = lines_per_wg(T, (LX + LZ) * CS);
+};
+
 // ------------------------------------------------------------ forward z
 // r2c along z of N^2 contiguous lines, keeping kz in [0, Kz).  A real line
 // of length N is transformed as a complex line of length N/2
@@ -38,10 +62,8 @@ __host__ __device__ constexpr int lines_per_wg(int t, int lp_bytes) {
 template <int N>
 __global__ void __launch_bounds__(512) k_fwd_z(const float* __restrict__ delta, float2* __restrict__ f1, int n_lines,
                                                int Kz, const float2* __restrict__ tw_h, const float2* __restrict__ tw_n) {
-  constexpr int H = N / 2;
-  constexpr int T = fft_threads(H);
-  constexpr int LP = H + 1;
-  constexpr int TB = lines_per_wg(T, LP * 8);
+  using Gm = FwdZGeom<N>;
+  constexpr int H = Gm::H, T = Gm::T, LP = Gm::LP, TB = Gm::TB;
   __shared__ float2 buf[TB * LP];
   __shared__ float2 twh[H];
   __shared__ float2 twn[N];
@@ -54,7 +76,7 @@ __global__ void __launch_bounds__(512) k_fwd_z(const float* __restrict__ delta, 
     int line = e / H, p = e % H;
     float2 v = make_float2(0.f, 0.f);
     if (l0 + line < n_lines) v = in2[(size_t)(l0 + line) * H + p];
-    buf[line * LP + p] = v;
+    buf[line * LP + px(p)] = v;
   }
   __syncthreads();
   const int line = tid / T, t = tid % T;
@@ -62,8 +84,8 @@ __global__ void __launch_bounds__(512) k_fwd_z(const float* __restrict__ delta, 
   if (l0 + line < n_lines) {
     const float2* z = buf + line * LP;
     for (int k = t; k < Kz; k += T) {
-      float2 zk = z[k % H];
-      float2 zc = z[(H - k) % H];
+      float2 zk = z[px(k % H)];
+      float2 zc = z[px((H - k) % H)];
       zc.y = -zc.y;  // conj Z_{N/2-k}
       float2 e = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
       float2 d = make_float2(zk.x - zc.x, zk.y - zc.y);
@@ -82,10 +104,8 @@ template <int N>
 __global__ void __launch_bounds__(512) k_fwd_col(const float2* __restrict__ in, float2* __restrict__ out, int n_inner,
                                                  long in_outer, long out_outer, int Lo, int Ko,
                                                  const float2* __restrict__ tw) {
-  constexpr int T = fft_threads(N);
-  constexpr int LP = N + 1;
-  constexpr int TB0 = 256 / T < 16 ? 16 : 256 / T;
-  constexpr int TB = (TB0 * LP * 8 > 64 * 1024) ? (64 * 1024) / (LP * 8) : TB0;
+  using Gm = ColGeom<N, 8>;
+  constexpr int T = Gm::T, LP = Gm::LP, TB = Gm::TB;
   __shared__ float2 buf[TB * LP];
   __shared__ float2 tws[N];
   const int tid = threadIdx.x;
@@ -97,7 +117,7 @@ __global__ void __launch_bounds__(512) k_fwd_col(const float2* __restrict__ in, 
     int p = e / TB, col = e % TB;
     float2 v = make_float2(0.f, 0.f);
     if (i0 + col < n_inner) v = src[(size_t)p * n_inner + i0 + col];
-    buf[col * LP + p] = v;
+    buf[col * LP + px(p)] = v;
   }
   __syncthreads();
   stockham<N, -1, T>(buf + (tid / T) * LP, tid % T, tws);
@@ -107,7 +127,7 @@ __global__ void __launch_bounds__(512) k_fwd_col(const float2* __restrict__ in, 
     if (i0 + col < n_inner) {
       int f = c - Ko;
       int p = f < 0 ? f + N : f;
-      dst[(size_t)c * n_inner + i0 + col] = buf[col * LP + p];
+      dst[(size_t)c * n_inner + i0 + col] = buf[col * LP + px(p)];
     }
   }
 }
@@ -158,10 +178,8 @@ __global__ void __launch_bounds__(512) k_inv_x(const float2* __restrict__ dc, ty
                                                const int8_t* __restrict__ lut, int Kc, int Lc, int Kz,
                                                const typename Cx<Rl>::type* __restrict__ tw) {
   using C = typename Cx<Rl>::type;
-  constexpr int T = fft_threads(M);
-  constexpr int LP = M + 1;
-  constexpr int TB0 = 256 / T < 16 ? 16 : 256 / T;
-  constexpr int TB = (TB0 * LP * (int)sizeof(C) > 64 * 1024) ? (64 * 1024) / (LP * (int)sizeof(C)) : TB0;
+  using Gm = ColGeom<M, (int)sizeof(C)>;
+  constexpr int T = Gm::T, LP = Gm::LP, TB = Gm::TB;
   __shared__ C buf[TB * LP];
   __shared__ C tws[M];
   const int tid = threadIdx.x;
@@ -189,7 +207,7 @@ __global__ void __launch_bounds__(512) k_inv_x(const float2* __restrict__ dc, ty
         }
       }
     }
-    buf[col * LP + p] = v;
+    buf[col * LP + px(p)] = v;
   }
   __syncthreads();
   stockham<M, 1, T>(buf + (tid / T) * LP, tid % T, tws);
@@ -197,7 +215,7 @@ __global__ void __launch_bounds__(512) k_inv_x(const float2* __restrict__ dc, ty
   for (int e = tid; e < M * TB; e += nth) {
     int x = e / TB, col = e % TB;
     int q = tile.col0 + col;
-    if (q < ncol) dst[(size_t)x * ncol + q] = buf[col * LP + x];
+    if (q < ncol) dst[(size_t)x * ncol + q] = buf[col * LP + px(x)];
   }
 }
 
@@ -209,10 +227,8 @@ __global__ void __launch_bounds__(512) k_inv_y(const typename Cx<Rl>::type* __re
                                                const BinGeom* __restrict__ geom, const BinTile* __restrict__ tiles,
                                                const typename Cx<Rl>::type* __restrict__ tw) {
   using C = typename Cx<Rl>::type;
-  constexpr int T = fft_threads(M);
-  constexpr int LP = M + 1;
-  constexpr int TB0 = 256 / T < 16 ? 16 : 256 / T;
-  constexpr int TB = (TB0 * LP * (int)sizeof(C) > 64 * 1024) ? (64 * 1024) / (LP * (int)sizeof(C)) : TB0;
+  using Gm = ColGeom<M, (int)sizeof(C)>;
+  constexpr int T = Gm::T, LP = Gm::LP, TB = Gm::TB;
   __shared__ C buf[TB * LP];
   __shared__ C tws[M];
   const int tid = threadIdx.x;
@@ -231,7 +247,7 @@ __global__ void __launch_bounds__(512) k_inv_y(const typename Cx<Rl>::type* __re
       int x = q / g.kzn, jz = q % g.kzn;
       v = src[((size_t)x * g.ly + (ky + g.kneg)) * g.kzn + jz];
     }
-    buf[col * LP + p] = v;
+    buf[col * LP + px(p)] = v;
   }
   __syncthreads();
   stockham<M, 1, T>(buf + (tid / T) * LP, tid % T, tws);
@@ -241,7 +257,7 @@ __global__ void __launch_bounds__(512) k_inv_y(const typename Cx<Rl>::type* __re
     int q = tile.col0 + col;
     if (q < ncol) {
       int x = q / g.kzn, jz = q % g.kzn;
-      dst[((size_t)x * M + y) * g.kzn + jz] = buf[col * LP + y];
+      dst[((size_t)x * M + y) * g.kzn + jz] = buf[col * LP + px(y)];
     }
   }
 }
@@ -258,11 +274,8 @@ __global__ void __launch_bounds__(512) k_inv_z(const typename Cx<Rl>::type* __re
                                                const typename Cx<Rl>::type* __restrict__ tw_h,
                                                const typename Cx<Rl>::type* __restrict__ tw_m, Rl scale) {
   using C = typename Cx<Rl>::type;
-  constexpr int H = M / 2;
-  constexpr int T = fft_threads(H);
-  constexpr int LX = H + 2;  // X_0..X_{M/2} plus pad
-  constexpr int LZ = H + 1;
-  constexpr int TB = lines_per_wg(T, (LX + LZ) * (int)sizeof(C));
+  using Gm = InvZGeom<M, (int)sizeof(C)>;
+  constexpr int H = Gm::H, T = Gm::T, LX = Gm::LX, LZ = Gm::LZ, TB = Gm::TB;
   __shared__ C xb[TB * LX];
   __shared__ C zb[TB * LZ];
   __shared__ C twh[H];
@@ -294,7 +307,7 @@ __global__ void __launch_bounds__(512) k_inv_z(const typename Cx<Rl>::type* __re
     C w = twm[k];  // W_M^k; multiply by its conjugate
     C dw = cmulc(d, w);
     // Z = s + i dw
-    zb[line * LZ + k] = cx<C>(s.x - dw.y, s.y + dw.x);
+    zb[line * LZ + px(k)] = cx<C>(s.x - dw.y, s.y + dw.x);
   }
   __syncthreads();
   stockham<H, 1, T>(zb + (tid / T) * LZ, tid % T, twh);
@@ -303,7 +316,7 @@ __global__ void __launch_bounds__(512) k_inv_z(const typename Cx<Rl>::type* __re
     int line = e / H, n = e % H;
     int l = tile.col0 + line;
     if (l < nlines) {
-      C z = zb[line * LZ + n];
+      C z = zb[line * LZ + px(n)];
       typename Cx<Rl>::type o = cx<C>(z.x * scale, z.y * scale);
       reinterpret_cast<typename Cx<Rl>::type*>(dst + (size_t)l * M)[n] = o;
     }
@@ -430,9 +443,7 @@ static hipError_t fwd_z_impl(const pb3_plan& p, const float* delta, hipStream_t 
   if constexpr (N < 16) {
     return hipErrorInvalidValue;
   } else {
-    constexpr int H = N / 2;
-    constexpr int T = fft_threads(H);
-    constexpr int TB = lines_per_wg(T, (H + 1) * 8);
+    constexpr int T = FwdZGeom<N>::T, TB = FwdZGeom<N>::TB;
     int n_lines = N * N;
     dim3 grid((n_lines + TB - 1) / TB);
     hipLaunchKernelGGL(k_fwd_z<N>, grid, dim3(TB * T), 0, s, delta, p.ws.f1, n_lines, p.Kz, p.d.tw_n2, p.d.tw_n);
@@ -446,10 +457,7 @@ hipError_t launch_fwd_z(const pb3_plan& p, const float* delta, hipStream_t s) {
 template <int N>
 static hipError_t fwd_col_impl(const float2* in, float2* out, int n_inner, long in_outer, long out_outer, int n_outer,
                                int Lo, int Ko, const float2* tw, hipStream_t s) {
-  constexpr int T = fft_threads(N);
-  constexpr int LP = N + 1;
-  constexpr int TB0 = 256 / T < 16 ? 16 : 256 / T;
-  constexpr int TB = (TB0 * LP * 8 > 64 * 1024) ? (64 * 1024) / (LP * 8) : TB0;
+  constexpr int T = ColGeom<N, 8>::T, TB = ColGeom<N, 8>::TB;
   dim3 grid((n_inner + TB - 1) / TB, n_outer);
   hipLaunchKernelGGL(k_fwd_col<N>, grid, dim3(TB * T), 0, s, in, out, n_inner, in_outer, out_outer, Lo, Ko, tw);
   return hipGetLastError();
@@ -476,12 +484,8 @@ hipError_t launch_power(const pb3_plan& p, double* pk, hipStream_t s) {
 template <int M, typename Rl, bool UNIT>
 static hipError_t inv_x_impl2(const pb3_plan& p, typename Cx<Rl>::type* a1, const typename Cx<Rl>::type* tw,
                               const TileSet& ts, hipStream_t s) {
-  constexpr int T = fft_threads(M);
-  constexpr int LP = M + 1;
-  constexpr int TB0 = 256 / T < 16 ? 16 : 256 / T;
-  constexpr int TB = (TB0 * LP * (int)sizeof(typename Cx<Rl>::type) > 64 * 1024)
-                         ? (64 * 1024) / (LP * (int)sizeof(typename Cx<Rl>::type))
-                         : TB0;
+  using Gm = ColGeom<M, (int)sizeof(typename Cx<Rl>::type)>;
+  constexpr int T = Gm::T, TB = Gm::TB;
   if (TB != ts.tb) return hipErrorInvalidConfiguration;
   if (ts.n == 0) return hipSuccess;
   hipLaunchKernelGGL((k_inv_x<M, Rl, UNIT>), dim3(ts.n), dim3(TB * T), 0, s, p.ws.dc, a1, p.d.geom, ts.d, p.d.lut,
@@ -492,12 +496,8 @@ static hipError_t inv_x_impl2(const pb3_plan& p, typename Cx<Rl>::type* a1, cons
 template <int M, typename Rl>
 static hipError_t inv_y_impl2(const pb3_plan& p, const typename Cx<Rl>::type* a1, typename Cx<Rl>::type* a2,
                               const typename Cx<Rl>::type* tw, const TileSet& ts, hipStream_t s) {
-  constexpr int T = fft_threads(M);
-  constexpr int LP = M + 1;
-  constexpr int TB0 = 256 / T < 16 ? 16 : 256 / T;
-  constexpr int TB = (TB0 * LP * (int)sizeof(typename Cx<Rl>::type) > 64 * 1024)
-                         ? (64 * 1024) / (LP * (int)sizeof(typename Cx<Rl>::type))
-                         : TB0;
+  using Gm = ColGeom<M, (int)sizeof(typename Cx<Rl>::type)>;
+  constexpr int T = Gm::T, TB = Gm::TB;
   if (TB != ts.tb) return hipErrorInvalidConfiguration;
   if (ts.n == 0) return hipSuccess;
   hipLaunchKernelGGL((k_inv_y<M, Rl>), dim3(ts.n), dim3(TB * T), 0, s, a1, a2, p.d.geom, ts.d, tw);
@@ -511,9 +511,8 @@ static hipError_t inv_z_impl2(const pb3_plan& p, const typename Cx<Rl>::type* a2
   if constexpr (M < 16) {
     return hipErrorInvalidValue;
   } else {
-    constexpr int H = M / 2;
-    constexpr int T = fft_threads(H);
-    constexpr int TB = lines_per_wg(T, (H + 2 + H + 1) * (int)sizeof(typename Cx<Rl>::type));
+    using Gm = InvZGeom<M, (int)sizeof(typename Cx<Rl>::type)>;
+    constexpr int T = Gm::T, TB = Gm::TB;
     if (TB != ts.tb) return hipErrorInvalidConfiguration;
     if (ts.n == 0) return hipSuccess;
     Rl scale = Rl(1.0 / ((double)M * M * M));
@@ -523,21 +522,12 @@ static hipError_t inv_z_impl2(const pb3_plan& p, const typename Cx<Rl>::type* a2
 }
 
 // tile widths the host needs to build the tile tables (same formulas)
-template <int M> static int tb_x_of(bool dbl) {
-  constexpr int T = fft_threads(M);
-  constexpr int LP = M + 1;
-  constexpr int TB0 = 256 / T < 16 ? 16 : 256 / T;
-  int cs = dbl ? 16 : 8;
-  return (TB0 * LP * cs > 64 * 1024) ? (64 * 1024) / (LP * cs) : TB0;
-}
+template <int M> static int tb_x_of(bool dbl) { return dbl ? ColGeom<M, 16>::TB : ColGeom<M, 8>::TB; }
 template <int M> static int tb_z_of(bool dbl) {
   if constexpr (M < 16) {
     return 0;
   } else {
-    constexpr int H = M / 2;
-    constexpr int T = fft_threads(H);
-    int cs = dbl ? 16 : 8;
-    return lines_per_wg(T, (H + 2 + H + 1) * cs);
+    return dbl ? InvZGeom<M, 16>::TB : InvZGeom<M, 8>::TB;
   }
 }
 
