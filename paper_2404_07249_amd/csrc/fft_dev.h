@@ -1,13 +1,10 @@
-// Device-side FFT building blocks for gfx950: register DFT codelets and a
-// Stockham (self-sorting) multi-stage FFT on lines held in LDS.
-//
-// A line of length N (N = 2^a 3^b) is transformed by radix stages taken
-// greedily from {16, 8, 4, 3, 2}; each stage reads R values per butterfly
-// from LDS, applies the inter-stage twiddle, runs an R-point DFT in
-// registers and writes back in Stockham order, so the result is in natural
-// order.  Twiddles come from a table W_N^j = exp(-2 pi i j / N) computed in
-// FP64 on the host (and rounded once to the working precision); the inverse
-// transform uses their conjugates.  No device transcendental is evaluated.
+// Device-side FFT building blocks for gfx950: register DFT codelets
+// (2, 3, 4, 8, 16 by Cooley-Tukey with constant twiddles; 6, 12, 24 by the
+// prime-factor mapping) and a two-phase line FFT of length N = R1 R2 with
+// one LDS exchange.  Twiddles come from a table W_N^j = exp(-2 pi i j / N)
+// computed in FP64 on the host (and rounded once to the working
+// precision); the inverse transform uses their conjugates.  No device
+// transcendental is evaluated.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -136,8 +133,48 @@ template <int S, typename C> __device__ __forceinline__ void dft16(C* v) {
   for (int i = 0; i < 16; ++i) v[i] = o[i];
 }
 
+template <int R, int S, typename C> __device__ __forceinline__ void dft(C* v);
+
+// Good-Thomas prime-factor DFT of length N1*N2 (coprime): input n =
+// (N2 n1 + N1 n2) mod N, output k with k = k1 (mod N1), k = k2 (mod N2);
+// no twiddles between the two short DFTs.
+constexpr int crt_index(int n1, int n2, int k1, int k2) {
+  for (int k = 0; k < n1 * n2; ++k)
+    if (k % n1 == k1 && k % n2 == k2) return k;
+  return -1;
+}
+template <int N1, int N2, int S, typename C> __device__ __forceinline__ void dft_pfa(C* v) {
+  constexpr int N = N1 * N2;
+  C w[N];
+#pragma unroll
+  for (int n2 = 0; n2 < N2; ++n2) {
+    C a[N1];
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) a[n1] = v[(N2 * n1 + N1 * n2) % N];
+    dft<N1, S>(a);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) w[k1 * N2 + n2] = a[k1];
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < N1; ++k1) {
+    C b[N2];
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) b[n2] = w[k1 * N2 + n2];
+    dft<N2, S>(b);
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) v[crt_index(N1, N2, k1, k2)] = b[k2];
+  }
+}
+
 template <int R, int S, typename C> __device__ __forceinline__ void dft(C* v) {
-  if constexpr (R == 2) {
+  if constexpr (R == 1) {
+  } else if constexpr (R == 6) {
+    dft_pfa<2, 3, S>(v);
+  } else if constexpr (R == 12) {
+    dft_pfa<4, 3, S>(v);
+  } else if constexpr (R == 24) {
+    dft_pfa<8, 3, S>(v);
+  } else if constexpr (R == 2) {
     dft2<S>(v[0], v[1]);
   } else if constexpr (R == 3) {
     dft3<S>(v);
@@ -152,86 +189,45 @@ template <int R, int S, typename C> __device__ __forceinline__ void dft(C* v) {
   }
 }
 
-// ------------------------------------------------------- radix schedule
-constexpr int next_radix(int rem) {
-  return (rem % 16 == 0) ? 16 : (rem % 8 == 0) ? 8 : (rem % 4 == 0) ? 4 : (rem % 3 == 0) ? 3 : (rem % 2 == 0) ? 2 : 1;
+// ------------------------------------------------- two-phase line FFT
+// Length N = R1 * R2.  Phase 1: thread t < R2 of the line takes inputs
+// n = t + R2 j (j < R1) in registers, runs a DFT of length R1 over j,
+// multiplies output k1 by exp(S 2 pi i t k1 / N) and writes it to the
+// line's LDS scratch s[k1 R2 + t].  Phase 2: thread k1 < R1 reads
+// s[k1 R2 + t] (t < R2), runs a DFT of length R2 over t and delivers
+// output k = k1 + R1 k2.  One LDS exchange, one barrier (every thread of
+// the work-group must call it).  tw holds W_N^m = exp(-2 pi i m / N).
+constexpr int fft2_r1(int n) {
+  return n == 16 ? 4 : n == 24 ? 8 : n == 32 ? 8 : n == 64 ? 8 : 16;
 }
-constexpr int radix_at(int n, int stage) {
-  int rem = n;
-  for (int s = 0; s < stage; ++s) rem /= next_radix(rem);
-  return next_radix(rem);
-}
-constexpr bool fft_len_ok(int n) {
-  int rem = n;
-  while (rem > 1) {
-    int r = next_radix(rem);
-    if (r == 1) return false;
-    rem /= r;
-  }
-  return n >= 2;
-}
-// threads per line: one radix-R0 butterfly each in the first stage
-constexpr int fft_threads(int n) { return n / radix_at(n, 0); }
-// radix of the stage that follows LS points already transformed
-constexpr int radix_at_ls(int n, int ls) { return next_radix(n / ls); }
+constexpr int fft2_r2(int n) { return n / fft2_r1(n); }
+constexpr int fft2_threads(int n) { return fft2_r1(n) > fft2_r2(n) ? fft2_r1(n) : fft2_r2(n); }
 
-// LDS layout of a line: element i lives at px(i) = i + i/16, one pad slot
-// per 16 elements, so the first stage's stride-16 writes fall on distinct
-// banks.  Lines are line_pitch() apart: at least the padded span and
-// congruent to the threads per line modulo 32, so that neighbouring lines
-// of a wave do not alias onto the same banks.
-__host__ __device__ constexpr int px(int i) { return i + (i >> 4); }
-__host__ __device__ constexpr int line_span(int n) { return n + (n >> 4); }
-__host__ __device__ constexpr int line_pitch(int n, int t) {
-  return line_span(n) + (((t - line_span(n)) % 32) + 32) % 32;
-}
-
-// One Stockham stage on a line in LDS (layout px), executed by T threads
-// (index t) of the line; every thread of the work-group must call it (it
-// contains barriers).  LS = product of the radices already applied.
-template <int N, int S, int LS, int T, typename C>
-__device__ __forceinline__ void stockham_stage(C* buf, int t, const C* __restrict__ tw) {
-  constexpr int R = radix_at_ls(N, LS);
-  constexpr int NB = N / R;                  // butterflies
-  constexpr int IT = (NB + T - 1) / T;       // butterflies per thread
-  C v[IT][R];
+template <int N, int S, typename C, typename LoadF, typename StoreF>
+__device__ __forceinline__ void fft2_line(C* s, int tl, const C* __restrict__ tw, LoadF&& load, StoreF&& store) {
+  constexpr int R1 = fft2_r1(N), R2 = fft2_r2(N);
+  static_assert(R1 * R2 == N, "bad factorisation");
+  if (tl < R2) {
+    C v[R1];
 #pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    int j = t + it * T;
-    if (NB % T == 0 || j < NB) {
+    for (int j = 0; j < R1; ++j) v[j] = load(tl + R2 * j);
+    dft<R1, S>(v);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[it][r] = buf[px(j + r * NB)];
+    for (int k1 = 1; k1 < R1; ++k1) {
+      C w = tw[tl * k1];
+      v[k1] = (S < 0) ? cmul(v[k1], w) : cmulc(v[k1], w);
     }
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) s[k1 * R2 + tl] = v[k1];
   }
   __syncthreads();
+  if (tl < R1) {
+    C u[R2];
 #pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    int j = t + it * T;
-    if (NB % T == 0 || j < NB) {
-      int k = (LS == 1) ? 0 : (j % LS);
-      if constexpr (LS > 1) {
-        constexpr int STEP = N / (LS * R);
+    for (int t = 0; t < R2; ++t) u[t] = s[tl * R2 + t];
+    dft<R2, S>(u);
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-          C w = tw[r * k * STEP];
-          v[it][r] = (S < 0) ? cmul(v[it][r], w) : cmulc(v[it][r], w);
-        }
-      }
-      dft<R, S>(v[it]);
-      int base = (j / LS) * LS * R + k;
-#pragma unroll
-      for (int r = 0; r < R; ++r) buf[px(base + r * LS)] = v[it][r];
-    }
-  }
-  __syncthreads();
-}
-
-// Full Stockham FFT (all stages) of one LDS line of length N.
-template <int N, int S, int T, int LS = 1, typename C>
-__device__ __forceinline__ void stockham(C* buf, int t, const C* __restrict__ tw) {
-  if constexpr (LS < N) {
-    stockham_stage<N, S, LS, T>(buf, t, tw);
-    stockham<N, S, T, LS * radix_at_ls(N, LS)>(buf, t, tw);
+    for (int k2 = 0; k2 < R2; ++k2) store(tl + R1 * k2, u[k2]);
   }
 }
 

@@ -1,0 +1,375 @@
+// FFT passes of the estimator (gfx950), built on the two-phase register FFT
+// fft2_line (fft_dev.h):
+//
+//   forward  z  r2c  delta[x][y][:]            -> f1[x][y][kz < Kz]
+//   forward  y  c2c  f1[x][:][kz]              -> f2[x][kyc][kz]   (centred-compact rows kept)
+//   forward  x  c2c  f2[:][kyc][kz]            -> dc[kxc][kyc][kz]
+//   inverse  x  c2c  Theta_b D, gathered per bin -> a1_b[x][jy][jz]
+//   inverse  y  c2c  a1_b[x][:][jz]            -> a2_b[x][y][jz]
+//   inverse  z  c2r  a2_b[x][y][:]             -> G_b[x][y][z]  (scaled by 1/M^3)
+//
+// The z passes transform two real lines with one complex FFT: forward,
+// z = x_A + i x_B and X_A = (Z_k + conj Z_{N-k})/2, X_B = (Z_k - conj Z_{N-k})/(2i);
+// inverse, Y = F_A + i F_B (each extended by Hermitian symmetry), whose
+// transform has G_A as real part and G_B as imaginary part.  Strided passes
+// take TB neighbouring columns per work-group so that every global access
+// is coalesced across the columns.
+
+#include <hip/hip_runtime.h>
+
+#include "fft_dev.h"
+#include "pb3_internal.h"
+
+namespace pb3 {
+
+// Strided passes: TB columns per work-group, TL threads per column.
+template <int N, int CS> struct ColShape {
+  static constexpr int TL = fft2_threads(N);
+  static constexpr int TB = CS == 8 ? 16 : 8;
+  static constexpr int LS = N + 1;  // odd LDS stride between columns
+  static constexpr int NT = TB * TL;
+};
+// z passes: TP pairs of lines per work-group, TL threads per pair.
+template <int N, int CS> struct PairShape {
+  static constexpr int TL = fft2_threads(N);
+  static constexpr int TP = ((CS == 8 ? 256 : 128) / TL) < 1 ? 1 : ((CS == 8 ? 256 : 128) / TL);
+  static constexpr int LS = N + 1;
+  static constexpr int NT = TP * TL;
+};
+
+// ------------------------------------------------------------ forward z
+template <int N>
+__global__ void __launch_bounds__(512) k_fwd_z2(const float* __restrict__ delta, float2* __restrict__ f1, int n_pairs,
+                                                int Kz, const float2* __restrict__ tw) {
+  using S = PairShape<N, 8>;
+  constexpr int TL = S::TL, TP = S::TP, LS = S::LS;
+  __shared__ float2 tws[N];
+  __shared__ float2 scr[TP * LS];
+  __shared__ float2 zb[TP * LS];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < N; e += S::NT) tws[e] = tw[e];
+  __syncthreads();
+  const int pl = tid / TL, tl = tid % TL;
+  const int pair = blockIdx.x * TP + pl;
+  const bool live = pair < n_pairs;
+  const float* xa = delta + (size_t)(2 * (live ? pair : 0)) * N;
+  const float* xb = xa + N;
+  float2* z = zb + pl * LS;
+  fft2_line<N, -1>(
+      scr + pl * LS, tl, tws,
+      [&](int n) { return live ? make_float2(xa[n], xb[n]) : make_float2(0.f, 0.f); },
+      [&](int k, float2 v) { z[k] = v; });
+  __syncthreads();
+  const int line0 = 2 * blockIdx.x * TP;
+  int nl = 2 * n_pairs - line0;
+  if (nl > 2 * TP) nl = 2 * TP;
+  for (int e = tid; e < nl * Kz; e += S::NT) {
+    int ll = e / Kz, k = e % Kz;
+    const float2* zz = zb + (ll >> 1) * LS;
+    float2 a = zz[k % N], b = zz[(N - k) % N];
+    float2 o = (ll & 1) == 0 ? make_float2(0.5f * (a.x + b.x), 0.5f * (a.y - b.y))
+                             : make_float2(0.5f * (a.y + b.y), 0.5f * (b.x - a.x));
+    f1[(size_t)(line0 + ll) * Kz + k] = o;
+  }
+}
+
+// --------------------------------------------------- forward strided c2c
+// out row c <- frequency f = c - Ko (kept when 0 <= c < Lo).
+template <int N>
+__global__ void __launch_bounds__(512) k_fwd_col2(const float2* __restrict__ in, float2* __restrict__ out, int n_inner,
+                                                  long in_outer, long out_outer, int Lo, int Ko,
+                                                  const float2* __restrict__ tw) {
+  using S = ColShape<N, 8>;
+  constexpr int TB = S::TB, LS = S::LS;
+  __shared__ float2 tws[N];
+  __shared__ float2 scr[TB * LS];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < N; e += S::NT) tws[e] = tw[e];
+  __syncthreads();
+  const int tl = tid / TB, col = tid % TB;
+  const int inner = blockIdx.x * TB + col;
+  const bool live = inner < n_inner;
+  const float2* src = in + (size_t)blockIdx.y * in_outer + (live ? inner : 0);
+  float2* dst = out + (size_t)blockIdx.y * out_outer + inner;
+  fft2_line<N, -1>(
+      scr + col * LS, tl, tws, [&](int n) { return live ? src[(size_t)n * n_inner] : make_float2(0.f, 0.f); },
+      [&](int k, float2 v) {
+        int f = k >= N - Ko ? k - N : k;
+        int c = f + Ko;
+        if (live && c >= 0 && c < Lo) dst[(size_t)c * n_inner] = v;
+      });
+}
+
+// ---------------------------------------------------------- inverse x
+// Per bin b: columns q = (jy, jz) of the bin's rectangle; the kx line of
+// Theta_b D (Theta_b alone when UNIT) enters at FFT positions kx mod M.
+template <int M, typename Rl, bool UNIT>
+__global__ void __launch_bounds__(512) k_inv_x2(const float2* __restrict__ dc, typename Cx<Rl>::type* __restrict__ a1,
+                                                const BinGeom* __restrict__ geom, const BinTile* __restrict__ tiles,
+                                                const int8_t* __restrict__ lut, int Kc, int Lc, int Kz,
+                                                const typename Cx<Rl>::type* __restrict__ tw) {
+  using C = typename Cx<Rl>::type;
+  using S = ColShape<M, (int)sizeof(C)>;
+  constexpr int TB = S::TB, LS = S::LS;
+  __shared__ C tws[M];
+  __shared__ C scr[TB * LS];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < M; e += S::NT) tws[e] = tw[e];
+  __syncthreads();
+  const int tl = tid / TB, col = tid % TB;
+  const BinTile tile = tiles[blockIdx.x];
+  const int b = tile.bin;
+  const BinGeom g = geom[b];
+  const int ncol = g.ly * g.kzn;
+  const int q = tile.col0 + col;
+  const bool live = q < ncol;
+  const int ky = live ? q / g.kzn - g.kneg : 0;
+  const int kz = live ? q % g.kzn : 0;
+  C* dst = a1 + g.a1_off + q;
+  fft2_line<M, 1>(
+      scr + col * LS, tl, tws,
+      [&](int n) {
+        C v = cx<C>(Rl(0), Rl(0));
+        int kx = n <= g.kpos ? n : (n >= M - g.kneg ? n - M : 0x40000000);
+        if (live && kx != 0x40000000 && lut[kx * kx + ky * ky + kz * kz] == b) {
+          if constexpr (UNIT) {
+            v = cx<C>(Rl(1), Rl(0));
+          } else {
+            float2 d = dc[((size_t)(kx + Kc) * Lc + (ky + Kc)) * Kz + kz];
+            v = cx<C>(Rl(d.x), Rl(d.y));
+          }
+        }
+        return v;
+      },
+      [&](int x, C v) {
+        if (live) dst[(size_t)x * ncol] = v;
+      });
+}
+
+// ---------------------------------------------------------- inverse y
+// Per bin: columns q = (x, jz); inverse transform along y.
+template <int M, typename Rl>
+__global__ void __launch_bounds__(512) k_inv_y2(const typename Cx<Rl>::type* __restrict__ a1,
+                                                typename Cx<Rl>::type* __restrict__ a2,
+                                                const BinGeom* __restrict__ geom, const BinTile* __restrict__ tiles,
+                                                const typename Cx<Rl>::type* __restrict__ tw) {
+  using C = typename Cx<Rl>::type;
+  using S = ColShape<M, (int)sizeof(C)>;
+  constexpr int TB = S::TB, LS = S::LS;
+  __shared__ C tws[M];
+  __shared__ C scr[TB * LS];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < M; e += S::NT) tws[e] = tw[e];
+  __syncthreads();
+  const int tl = tid / TB, col = tid % TB;
+  const BinTile tile = tiles[blockIdx.x];
+  const BinGeom g = geom[tile.bin];
+  const int ncol = M * g.kzn;
+  const int q = tile.col0 + col;
+  const bool live = q < ncol;
+  const int x = live ? q / g.kzn : 0, jz = live ? q % g.kzn : 0;
+  const C* src = a1 + g.a1_off + ((size_t)x * g.ly + g.kneg) * g.kzn + jz;  // ky = 0 row
+  C* dst = a2 + g.a2_off + (size_t)x * M * g.kzn + jz;
+  fft2_line<M, 1>(
+      scr + col * LS, tl, tws,
+      [&](int n) {
+        int ky = n <= g.kpos ? n : (n >= M - g.kneg ? n - M : 0x40000000);
+        return (live && ky != 0x40000000) ? src[(long)ky * g.kzn] : cx<C>(Rl(0), Rl(0));
+      },
+      [&](int y, C v) {
+        if (live) dst[(size_t)y * g.kzn] = v;
+      });
+}
+
+// ---------------------------------------------------------- inverse z
+// Per bin: 2*TP consecutive lines (x, y) per work-group, kz in [0, kzn).
+// The input block is staged in LDS with coalesced loads; each pair of
+// lines is one complex inverse FFT; the real outputs are staged in LDS and
+// written back as one contiguous block.
+template <int M, typename Rl>
+__global__ void __launch_bounds__(512) k_inv_z2(const typename Cx<Rl>::type* __restrict__ a2, Rl* __restrict__ gout,
+                                                const BinGeom* __restrict__ geom, const BinTile* __restrict__ tiles,
+                                                const typename Cx<Rl>::type* __restrict__ tw, Rl scale) {
+  using C = typename Cx<Rl>::type;
+  using S = PairShape<M, (int)sizeof(C)>;
+  constexpr int TL = S::TL, TP = S::TP, LS = S::LS;
+  __shared__ C tws[M];
+  __shared__ C scr[TP * LS];
+  __shared__ C stage[TP * (M + 2)];  // input 2TP x kzn complex, then output 2TP x M reals
+  const int tid = threadIdx.x;
+  for (int e = tid; e < M; e += S::NT) tws[e] = tw[e];
+  const BinTile tile = tiles[blockIdx.x];
+  const BinGeom g = geom[tile.bin];
+  const int kzn = g.kzn;
+  const int nlines = M * M;
+  const int line0 = tile.col0;
+  int nl = nlines - line0;
+  if (nl > 2 * TP) nl = 2 * TP;
+  const C* src = a2 + g.a2_off + (size_t)line0 * kzn;
+  for (int e = tid; e < nl * kzn; e += S::NT) stage[e] = src[e];
+  __syncthreads();
+  const int pl = tid / TL, tl = tid % TL;
+  const bool has_a = 2 * pl < nl, has_b = 2 * pl + 1 < nl;
+  const C* xa = stage + 2 * pl * kzn;
+  const C* xb = xa + kzn;
+  Rl* outr = reinterpret_cast<Rl*>(stage);
+  fft2_line<M, 1>(
+      scr + pl * LS, tl, tws,
+      [&](int k) {
+        C a = cx<C>(Rl(0), Rl(0)), b = cx<C>(Rl(0), Rl(0));
+        if (k < kzn) {
+          if (has_a) a = xa[k];
+          if (has_b) b = xb[k];
+          return cx<C>(a.x - b.y, a.y + b.x);  // F_A + i F_B
+        }
+        int m = M - k;
+        if (m < kzn) {
+          if (has_a) a = xa[m];
+          if (has_b) b = xb[m];
+          return cx<C>(a.x + b.y, b.x - a.y);  // conj F_A(m) + i conj F_B(m)
+        }
+        return cx<C>(Rl(0), Rl(0));
+      },
+      [&](int z, C v) {
+        outr[(2 * pl) * M + z] = v.x * scale;
+        outr[(2 * pl + 1) * M + z] = v.y * scale;
+      });
+  __syncthreads();
+  Rl* dst = gout + (size_t)tile.bin * ((size_t)M * M * M) + (size_t)line0 * M;
+  for (int e = tid; e < nl * M / 2; e += S::NT)
+    reinterpret_cast<C*>(dst)[e] = reinterpret_cast<const C*>(outr)[e];
+}
+
+// ================================================================ launchers
+
+#define PB3_FFT_LEN(len, ...)                          \
+  switch (len) {                                       \
+    case 16: { constexpr int LL = 16; __VA_ARGS__; }   \
+    case 24: { constexpr int LL = 24; __VA_ARGS__; }   \
+    case 32: { constexpr int LL = 32; __VA_ARGS__; }   \
+    case 48: { constexpr int LL = 48; __VA_ARGS__; }   \
+    case 64: { constexpr int LL = 64; __VA_ARGS__; }   \
+    case 96: { constexpr int LL = 96; __VA_ARGS__; }   \
+    case 128: { constexpr int LL = 128; __VA_ARGS__; } \
+    case 192: { constexpr int LL = 192; __VA_ARGS__; } \
+    case 256: { constexpr int LL = 256; __VA_ARGS__; } \
+    case 384: { constexpr int LL = 384; __VA_ARGS__; } \
+    default: break;                                    \
+  }
+
+int tile_width_x(int M, bool dbl) {
+  PB3_FFT_LEN(M, return dbl ? ColShape<LL, 16>::TB : ColShape<LL, 8>::TB);
+  return 0;
+}
+int tile_width_z(int M, bool dbl) {
+  PB3_FFT_LEN(M, return 2 * (dbl ? PairShape<LL, 16>::TP : PairShape<LL, 8>::TP));
+  return 0;
+}
+
+hipError_t launch_fwd_z(const pb3_plan& p, const float* delta, hipStream_t s) {
+  const int n_pairs = p.N * p.N / 2;
+  PB3_FFT_LEN(p.N, {
+    using S = PairShape<LL, 8>;
+    hipLaunchKernelGGL(k_fwd_z2<LL>, dim3((n_pairs + S::TP - 1) / S::TP), dim3(S::NT), 0, s, delta, p.ws.f1, n_pairs,
+                       p.Kz, p.d.tw_n);
+    return hipGetLastError();
+  });
+  return hipErrorInvalidValue;
+}
+
+static hipError_t fwd_col(const pb3_plan& p, const float2* in, float2* out, int n_inner, long in_outer,
+                          long out_outer, int n_outer, hipStream_t s) {
+  PB3_FFT_LEN(p.N, {
+    using S = ColShape<LL, 8>;
+    dim3 grid((n_inner + S::TB - 1) / S::TB, n_outer);
+    hipLaunchKernelGGL(k_fwd_col2<LL>, grid, dim3(S::NT), 0, s, in, out, n_inner, in_outer, out_outer, p.Lc, p.Kc,
+                       p.d.tw_n);
+    return hipGetLastError();
+  });
+  return hipErrorInvalidValue;
+}
+hipError_t launch_fwd_y(const pb3_plan& p, hipStream_t s) {
+  // f1[x][y][kz] -> f2[x][kyc][kz]
+  return fwd_col(p, p.ws.f1, p.ws.f2, p.Kz, (long)p.N * p.Kz, (long)p.Lc * p.Kz, p.N, s);
+}
+hipError_t launch_fwd_x(const pb3_plan& p, hipStream_t s) {
+  // f2[x][kyc][kz] -> dc[kxc][kyc][kz]
+  return fwd_col(p, p.ws.f2, p.ws.dc, p.Lc * p.Kz, 0L, 0L, 1, s);
+}
+
+hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, void* a1, const void* tw, const TileSet& ts,
+                     hipStream_t s) {
+  if (ts.n == 0) return hipSuccess;
+  PB3_FFT_LEN(p.M, {
+    if (dbl) {
+      using S = ColShape<LL, 16>;
+      if (ts.tb != S::TB) return hipErrorInvalidConfiguration;
+      if (unit)
+        hipLaunchKernelGGL((k_inv_x2<LL, double, true>), dim3(ts.n), dim3(S::NT), 0, s, p.ws.dc, (double2*)a1,
+                           p.d.geom, ts.d, p.d.lut, p.Kc, p.Lc, p.Kz, (const double2*)tw);
+      else
+        return hipErrorInvalidValue;
+    } else {
+      using S = ColShape<LL, 8>;
+      if (ts.tb != S::TB) return hipErrorInvalidConfiguration;
+      if (unit) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_inv_x2<LL, float, false>), dim3(ts.n), dim3(S::NT), 0, s, p.ws.dc, (float2*)a1, p.d.geom,
+                         ts.d, p.d.lut, p.Kc, p.Lc, p.Kz, (const float2*)tw);
+    }
+    return hipGetLastError();
+  });
+  return hipErrorInvalidValue;
+}
+
+hipError_t run_inv_y(const pb3_plan& p, bool dbl, const void* a1, void* a2, const void* tw, const TileSet& ts,
+                     hipStream_t s) {
+  if (ts.n == 0) return hipSuccess;
+  PB3_FFT_LEN(p.M, {
+    if (dbl) {
+      using S = ColShape<LL, 16>;
+      if (ts.tb != S::TB) return hipErrorInvalidConfiguration;
+      hipLaunchKernelGGL((k_inv_y2<LL, double>), dim3(ts.n), dim3(S::NT), 0, s, (const double2*)a1, (double2*)a2,
+                         p.d.geom, ts.d, (const double2*)tw);
+    } else {
+      using S = ColShape<LL, 8>;
+      if (ts.tb != S::TB) return hipErrorInvalidConfiguration;
+      hipLaunchKernelGGL((k_inv_y2<LL, float>), dim3(ts.n), dim3(S::NT), 0, s, (const float2*)a1, (float2*)a2,
+                         p.d.geom, ts.d, (const float2*)tw);
+    }
+    return hipGetLastError();
+  });
+  return hipErrorInvalidValue;
+}
+
+hipError_t run_inv_z(const pb3_plan& p, bool dbl, const void* a2, void* gout, const void* tw, const TileSet& ts,
+                     hipStream_t s) {
+  if (ts.n == 0) return hipSuccess;
+  const double sc = 1.0 / ((double)p.M * p.M * p.M);
+  PB3_FFT_LEN(p.M, {
+    if (dbl) {
+      using S = PairShape<LL, 16>;
+      if (ts.tb != 2 * S::TP) return hipErrorInvalidConfiguration;
+      hipLaunchKernelGGL((k_inv_z2<LL, double>), dim3(ts.n), dim3(S::NT), 0, s, (const double2*)a2, (double*)gout,
+                         p.d.geom, ts.d, (const double2*)tw, sc);
+    } else {
+      using S = PairShape<LL, 8>;
+      if (ts.tb != 2 * S::TP) return hipErrorInvalidConfiguration;
+      hipLaunchKernelGGL((k_inv_z2<LL, float>), dim3(ts.n), dim3(S::NT), 0, s, (const float2*)a2, (float*)gout,
+                         p.d.geom, ts.d, (const float2*)tw, (float)sc);
+    }
+    return hipGetLastError();
+  });
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_inv_x(const pb3_plan& p, hipStream_t s) {
+  return run_inv_x(p, false, false, p.ws.a1, p.d.tw_m, p.tx, s);
+}
+hipError_t launch_inv_y(const pb3_plan& p, hipStream_t s) {
+  return run_inv_y(p, false, p.ws.a1, p.ws.a2, p.d.tw_m, p.ty, s);
+}
+hipError_t launch_inv_z(const pb3_plan& p, hipStream_t s) {
+  return run_inv_z(p, false, p.ws.a2, p.ws.g, p.d.tw_m, p.tz, s);
+}
+
+}  // namespace pb3

@@ -110,9 +110,8 @@ static pb3_status upload_twiddles_d(double2** out, int n) {
 
 static void free_device(pb3_plan* p) {
   DeviceTables& d = p->d;
-  void* ptrs[] = {d.lut,        d.modes,    d.chunk, d.geom,  d.tiles,   d.trip_all, d.out_map,
-                  d.inv_counts, d.pk_scale, d.tw_n,  d.tw_n2, d.tw_m,    d.tw_m2,    d.tw_m_d,
-                  d.tw_m2_d};
+  void* ptrs[] = {d.lut,     d.modes,      d.chunk,    d.geom, d.tiles, d.trip_all,
+                  d.out_map, d.inv_counts, d.pk_scale, d.tw_n, d.tw_m,  d.tw_m_d};
   for (void* q : ptrs)
     if (q) hipFree(q);
   d = DeviceTables{};
@@ -391,11 +390,8 @@ static pb3_status build_device(pb3_plan* p) {
   if ((st = upload(&d.geom, p->geom.data(), p->geom.size())) != PB3_OK) return st;
   if ((st = upload(&d.trip_all, p->trip_all.data(), p->trip_all.size())) != PB3_OK) return st;
   if ((st = upload_twiddles_f(&d.tw_n, p->N)) != PB3_OK) return st;
-  if ((st = upload_twiddles_f(&d.tw_n2, p->N / 2)) != PB3_OK) return st;
   if ((st = upload_twiddles_f(&d.tw_m, p->M)) != PB3_OK) return st;
-  if ((st = upload_twiddles_f(&d.tw_m2, p->M / 2)) != PB3_OK) return st;
   if ((st = upload_twiddles_d(&d.tw_m_d, p->M)) != PB3_OK) return st;
-  if ((st = upload_twiddles_d(&d.tw_m2_d, p->M / 2)) != PB3_OK) return st;
   // FP32 inverse-pass tiles
   int tbx = tile_width_x(p->M, false), tbz = tile_width_z(p->M, false);
   if (tbx <= 0 || tbz <= 0) {

@@ -64,11 +64,8 @@ struct DeviceTables {
   double* inv_counts = nullptr;   // per kept triplet: scale / T
   double* pk_scale = nullptr;     // per bin: V / (N^6 N_b)
   float2* tw_n = nullptr;         // W_N^j, j < N
-  float2* tw_n2 = nullptr;        // W_{N/2}^j
   float2* tw_m = nullptr;         // W_M^j
-  float2* tw_m2 = nullptr;        // W_{M/2}^j
   double2* tw_m_d = nullptr;      // FP64 twiddles for the count pass
-  double2* tw_m2_d = nullptr;
 };
 
 struct Workspace {
@@ -156,6 +153,14 @@ int mfma_tiles(int nq);
 int mfma_locate(int nq, int a, int b, int c);
 hipError_t launch_contract_mfma(const pb3_plan& p, bool mixed, hipStream_t s);
 int mfma_grid(int nq, int n_cu);
+// inverse passes (fft_passes.hip) on FP32 (dbl = false) or FP64 lines;
+// unit = the shell indicator instead of Theta_b D (count pass, FP64 only)
+hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, void* a1, const void* tw, const TileSet& ts,
+                     hipStream_t s);
+hipError_t run_inv_y(const pb3_plan& p, bool dbl, const void* a1, void* a2, const void* tw, const TileSet& ts,
+                     hipStream_t s);
+hipError_t run_inv_z(const pb3_plan& p, bool dbl, const void* a2, void* gout, const void* tw, const TileSet& ts,
+                     hipStream_t s);
 // tile widths of the inverse passes for FP32 (dbl = false) or FP64 lines
 int tile_width_x(int M, bool dbl);
 int tile_width_z(int M, bool dbl);
