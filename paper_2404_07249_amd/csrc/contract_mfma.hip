@@ -90,16 +90,25 @@ __device__ __forceinline__ float ror16(float x, int s) {
 }
 
 // Split 8 FP32 values into bf16 hi (round to nearest even) and bf16 lo of
-// the exact FP32 residual.
-__device__ __forceinline__ void split8(const float* v, bf16x8_t& hi, bf16x8_t& lo) {
+// the FP32 residual x - hi.  The residual is exactly representable; it is
+// formed by v_dot2_f32_bf16 as x + (-1) * hi + 0 * hi' with the selector
+// pairs sel.lo = (-1, 0) and sel.hi = (0, -1).  The selectors arrive as
+// kernel arguments so that the compiler cannot fold them into an inline
+// constant (whose packed-bf16 reading differs).
+struct SplitSel {
+  bf16x2_t lo, hi;
+};
+
+__device__ __forceinline__ void split8(const float* v, bf16x8_t& hi, bf16x8_t& lo, const SplitSel& sel) {
 #pragma unroll
   for (int j = 0; j < 8; j += 2) {
     f2_t pv = {v[j], v[j + 1]};
     bf16x2_t h = __builtin_convertvector(pv, bf16x2_t);
     hi[j] = h[0];
     hi[j + 1] = h[1];
-    f2_t hf = __builtin_convertvector(h, f2_t);
-    f2_t r = pv - hf;
+    f2_t r;
+    r.x = __builtin_amdgcn_fdot2_f32_bf16(h, sel.lo, v[j], false);
+    r.y = __builtin_amdgcn_fdot2_f32_bf16(h, sel.hi, v[j + 1], false);
     bf16x2_t l = __builtin_convertvector(r, bf16x2_t);
     lo[j] = l[0];
     lo[j + 1] = l[1];
@@ -108,7 +117,8 @@ __device__ __forceinline__ void split8(const float* v, bf16x8_t& hi, bf16x8_t& l
 
 template <int NQ, bool MIXED, int K, int K1, int T0>
 __device__ __forceinline__ void do_blocks(const float (&gv)[NQ][8], const bf16x8_t (&bh)[NQ], const bf16x8_t (&bl)[NQ],
-                                          f32x4_t* acc) {
+                                          f32x4_t* acc, const SplitSel& sel) {
+#pragma clang fp contract(off)
   if constexpr (K < K1) {
     constexpr PairBlock pb = pair_block(NQ, K);
     constexpr int tb = tiles_before(NQ, K) - T0;
@@ -117,7 +127,7 @@ __device__ __forceinline__ void do_blocks(const float (&gv)[NQ][8], const bf16x8
     for (int j = 0; j < 8; ++j) a[j] = gv[pb.p][j] * ror16(gv[pb.q][j], pb.s);
     if constexpr (MIXED) {
       bf16x8_t ah, al;
-      split8(a, ah, al);
+      split8(a, ah, al, sel);
 #pragma unroll
       for (int cb = pb.q; cb < NQ; ++cb) {
         f32x4_t c = acc[tb + cb - pb.q];
@@ -126,16 +136,31 @@ __device__ __forceinline__ void do_blocks(const float (&gv)[NQ][8], const bf16x8
         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[cb], c, 0, 0, 0);
         acc[tb + cb - pb.q] = c;
       }
+      do_blocks<NQ, MIXED, K + 1, K1, T0>(gv, bh, bl, acc, sel);
     } else {
+      // FP32: interleave this block's MFMA chains with the next block's so
+      // consecutive MFMAs do not wait on the same accumulator
+      constexpr bool PAIRED = K + 1 < K1;
+      constexpr PairBlock pn = pair_block(NQ, PAIRED ? K + 1 : K);
+      constexpr int tn = tiles_before(NQ, PAIRED ? K + 1 : K) - T0;
+      float an[8];
+      if constexpr (PAIRED) {
 #pragma unroll
-      for (int cb = pb.q; cb < NQ; ++cb) {
-        f32x4_t c = acc[tb + cb - pb.q];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], gv[cb][j], c, 0, 0, 0);
-        acc[tb + cb - pb.q] = c;
+        for (int j = 0; j < 8; ++j) an[j] = gv[pn.p][j] * ror16(gv[pn.q][j], pn.s);
       }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+#pragma unroll
+        for (int cb = pb.q; cb < NQ; ++cb)
+          acc[tb + cb - pb.q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], gv[cb][j], acc[tb + cb - pb.q], 0, 0, 0);
+        if constexpr (PAIRED) {
+#pragma unroll
+          for (int cb = pn.q; cb < NQ; ++cb)
+            acc[tn + cb - pn.q] = __builtin_amdgcn_mfma_f32_16x16x4f32(an[j], gv[cb][j], acc[tn + cb - pn.q], 0, 0, 0);
+        }
+      }
+      do_blocks<NQ, MIXED, (PAIRED ? K + 2 : K + 1), K1, T0>(gv, bh, bl, acc, sel);
     }
-    do_blocks<NQ, MIXED, K + 1, K1, T0>(gv, bh, bl, acc);
   }
 }
 
@@ -153,25 +178,42 @@ constexpr int split_point(int nq, int k0, int k1) {
   return k1;
 }
 
+template <int NQ>
+__device__ __forceinline__ void load_fields(const float* const (&gl)[NQ], long v0, float (&gv)[NQ][8]) {
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const float4* src = reinterpret_cast<const float4*>(gl[q] + v0);
+    float4 x0 = src[0], x1 = src[1];
+    gv[q][0] = x0.x; gv[q][1] = x0.y; gv[q][2] = x0.z; gv[q][3] = x0.w;
+    gv[q][4] = x1.x; gv[q][5] = x1.y; gv[q][6] = x1.z; gv[q][7] = x1.w;
+  }
+}
+
+// K-steps of 32 voxels, 128 apart (the four waves of a half interleave);
+// the next step's fields are loaded while the current one is contracted.
 template <int NQ, bool MIXED, int K0, int K1, int NTMAX>
 __device__ __forceinline__ void contract_loop(const float* const (&gl)[NQ], long v_begin, long v_end,
-                                              f32x4_t (&acc)[NTMAX]) {
+                                              f32x4_t (&acc)[NTMAX], const SplitSel& sel) {
   constexpr int T0 = tiles_before(NQ, K0);
+  if (v_begin >= v_end) return;
+  float gv[NQ][8];
+  load_fields<NQ>(gl, v_begin, gv);
   for (long v0 = v_begin; v0 < v_end; v0 += 128) {
-    float gv[NQ][8];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const float4* src = reinterpret_cast<const float4*>(gl[q] + v0);
-      float4 x0 = src[0], x1 = src[1];
-      gv[q][0] = x0.x; gv[q][1] = x0.y; gv[q][2] = x0.z; gv[q][3] = x0.w;
-      gv[q][4] = x1.x; gv[q][5] = x1.y; gv[q][6] = x1.z; gv[q][7] = x1.w;
-    }
+    float gn[NQ][8];
+    const bool more = v0 + 128 < v_end;
+    if (more) load_fields<NQ>(gl, v0 + 128, gn);
     bf16x8_t bh[NQ], bl[NQ];
     if constexpr (MIXED) {
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) split8(gv[q], bh[q], bl[q]);
+      for (int q = 0; q < NQ; ++q) split8(gv[q], bh[q], bl[q], sel);
     }
-    do_blocks<NQ, MIXED, K0, K1, T0>(gv, bh, bl, acc);
+    do_blocks<NQ, MIXED, K0, K1, T0>(gv, bh, bl, acc, sel);
+    if (more) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) gv[q][j] = gn[q][j];
+    }
   }
 }
 
@@ -181,7 +223,8 @@ __device__ __forceinline__ void contract_loop(const float* const (&gl)[NQ], long
 // interleave K-steps of 32 voxels.  part: [n_wg][n_tiles_total*256] FP32.
 template <int NQ, bool MIXED, int K0, int KM, int K1>
 __global__ void __launch_bounds__(512) k_contract_mfma(const float* __restrict__ g, long mvox, long vpw,
-                                                       float* __restrict__ part, int part_len) {
+                                                       float* __restrict__ part, int part_len, unsigned sel_lo,
+                                                       unsigned sel_hi) {
   constexpr int T0 = tiles_before(NQ, K0);
   constexpr int TM = tiles_before(NQ, KM);
   constexpr int T1 = tiles_before(NQ, K1);
@@ -201,10 +244,13 @@ __global__ void __launch_bounds__(512) k_contract_mfma(const float* __restrict__
   const float* gl[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) gl[q] = g + (size_t)(16 * q + i) * mvox + 8 * grp;
+  SplitSel sel;
+  __builtin_memcpy(&sel.lo, &sel_lo, 4);
+  __builtin_memcpy(&sel.hi, &sel_hi, 4);
   if (half == 0)
-    contract_loop<NQ, MIXED, K0, KM>(gl, vb + 32 * wq, ve, acc);
+    contract_loop<NQ, MIXED, K0, KM>(gl, vb + 32 * wq, ve, acc, sel);
   else
-    contract_loop<NQ, MIXED, KM, K1>(gl, vb + 32 * wq, ve, acc);
+    contract_loop<NQ, MIXED, KM, K1>(gl, vb + 32 * wq, ve, acc, sel);
   // fixed-order sum of the four waves of each half in LDS
   for (int w = 0; w < 4; ++w) {
     if (wq == w) {
@@ -231,8 +277,10 @@ static hipError_t launch_group(const float* g, long mvox, int n_wg, long vpw, fl
                                hipStream_t s) {
   constexpr int K0 = group_begin(NQ, G), K1 = group_begin(NQ, G + 1);
   constexpr int KM = split_point(NQ, K0, K1);
+  // bf16 pairs (element 0 in the low half): (-1, 0) and (0, -1)
+  const unsigned sel_lo = 0x0000BF80u, sel_hi = 0xBF800000u;
   hipLaunchKernelGGL((k_contract_mfma<NQ, MIXED, K0, KM, K1>), dim3(n_wg), dim3(512), 0, s, g, mvox, vpw, part,
-                     part_len);
+                     part_len, sel_lo, sel_hi);
   return hipGetLastError();
 }
 
