@@ -164,123 +164,207 @@ __device__ __forceinline__ void do_blocks(const float (&gv)[NQ][8], const bf16x8
   }
 }
 
-// Balanced split of pair blocks [k0, k1) between two wave-halves: cost of
-// a block ~ its split (VALU) plus its tiles (MFMA).
-constexpr int block_cost(int nq, int k) { return 128 + 48 * (nq - pair_block(nq, k).q); }
-constexpr int split_point(int nq, int k0, int k1) {
+// Pair blocks [k0, k1) are shared out between NG wave groups that stream
+// the same voxels; boundaries balance an estimated cost per block (its
+// split on the VALU plus its tiles on the matrix core).
+constexpr int block_cost(int nq, int k) { return 96 + 48 * (nq - pair_block(nq, k).q); }
+constexpr int group_bound(int nq, int k0, int k1, int ng, int g) {
+  if (g <= 0) return k0;
+  if (g >= ng) return k1;
   int total = 0;
   for (int k = k0; k < k1; ++k) total += block_cost(nq, k);
   int acc = 0;
   for (int k = k0; k < k1; ++k) {
+    if (acc * ng >= total * g) return k;
     acc += block_cost(nq, k);
-    if (2 * acc >= total) return k + 1 < k1 ? k + 1 : k1;
   }
   return k1;
 }
 
-template <int NQ>
-__device__ __forceinline__ void load_fields(const float* const (&gl)[NQ], long v0, float (&gv)[NQ][8]) {
+// One launch covers pair blocks [K0, K1) (tiles [T0, T1)), shared out
+// between kGroups groups of kWavesPerGroup waves.  Work-group w takes the
+// voxels [w*vpw, (w+1)*vpw) in tiles of kTileVox voxels: each tile of all
+// bins is loaded once per work-group into LDS (double-buffered, the next
+// tile's global loads in flight during the current tile's math) together
+// with its bf16 hi/lo split, then every group contracts it for its own
+// pair blocks, wave w of a group taking voxels [32 w, 32 w + 32) of the
+// tile.  part: [n_wg][n_tiles_total*256] FP32.
+constexpr int kGroups = 4, kWavesPerGroup = 2, kContractThreads = 64 * kGroups * kWavesPerGroup;
+constexpr int kTileVox = 32 * kWavesPerGroup;
+constexpr int kPitchF = kTileVox + 4;  // floats per bin row of the staged tile
+constexpr int kPitchH = kTileVox + 8;  // bf16 per bin row of the staged split
+
+template <int NQ> struct TileStage {
+  float f[16 * NQ * kPitchF];
+  __bf16 hi[16 * NQ * kPitchH];
+  __bf16 lo[16 * NQ * kPitchH];
+};
+
+template <int NQ, int K0, int K1, int G> struct GroupRange {
+  static constexpr int b = group_bound(NQ, K0, K1, kGroups, G);
+  static constexpr int e = group_bound(NQ, K0, K1, kGroups, G + 1);
+  static constexpr int t0 = tiles_before(NQ, b) - tiles_before(NQ, K0);  // offset in this launch's tiles
+  static constexpr int nt = tiles_before(NQ, e) - tiles_before(NQ, b);
+  static constexpr int qmin = b < e ? pair_block(NQ, b).q : NQ;         // lowest column block used
+};
+
+template <int NQ, bool MIXED, int K0, int K1, int G, int NTMAX>
+__device__ __forceinline__ void contract_tile(const TileStage<NQ>& st, int i, int grp, int wig, f32x4_t (&acc)[NTMAX],
+                                              const SplitSel& sel) {
+  using R = GroupRange<NQ, K0, K1, G>;
+  float gv[NQ][8];
+  bf16x8_t bh[NQ], bl[NQ];
+  const int off = 32 * wig + 8 * grp;
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
-    const float4* src = reinterpret_cast<const float4*>(gl[q] + v0);
-    float4 x0 = src[0], x1 = src[1];
+    const float4* pf = reinterpret_cast<const float4*>(st.f + (16 * q + i) * kPitchF + off);
+    float4 x0 = pf[0], x1 = pf[1];
     gv[q][0] = x0.x; gv[q][1] = x0.y; gv[q][2] = x0.z; gv[q][3] = x0.w;
     gv[q][4] = x1.x; gv[q][5] = x1.y; gv[q][6] = x1.z; gv[q][7] = x1.w;
-  }
-}
-
-// K-steps of 32 voxels, 128 apart (the four waves of a half interleave);
-// the next step's fields are loaded while the current one is contracted.
-template <int NQ, bool MIXED, int K0, int K1, int NTMAX>
-__device__ __forceinline__ void contract_loop(const float* const (&gl)[NQ], long v_begin, long v_end,
-                                              f32x4_t (&acc)[NTMAX], const SplitSel& sel) {
-  constexpr int T0 = tiles_before(NQ, K0);
-  if (v_begin >= v_end) return;
-  float gv[NQ][8];
-  load_fields<NQ>(gl, v_begin, gv);
-  for (long v0 = v_begin; v0 < v_end; v0 += 128) {
-    float gn[NQ][8];
-    const bool more = v0 + 128 < v_end;
-    if (more) load_fields<NQ>(gl, v0 + 128, gn);
-    bf16x8_t bh[NQ], bl[NQ];
     if constexpr (MIXED) {
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) split8(gv[q], bh[q], bl[q], sel);
+      if (q >= R::qmin) {
+        bh[q] = *reinterpret_cast<const bf16x8_t*>(st.hi + (16 * q + i) * kPitchH + off);
+        bl[q] = *reinterpret_cast<const bf16x8_t*>(st.lo + (16 * q + i) * kPitchH + off);
+      }
     }
-    do_blocks<NQ, MIXED, K0, K1, T0>(gv, bh, bl, acc, sel);
-    if (more) {
+  }
+  do_blocks<NQ, MIXED, R::b, R::e, tiles_before(NQ, R::b)>(gv, bh, bl, acc, sel);
+}
+
+template <int NQ, int K0, int K1, int G, int NTMAX>
+__device__ __forceinline__ void reduce_group(float* red, const f32x4_t (&acc)[NTMAX], int w, int i, int grp) {
+  using R = GroupRange<NQ, K0, K1, G>;
+  float* r = red + R::t0 * 256;
 #pragma unroll
-      for (int q = 0; q < NQ; ++q)
+  for (int t = 0; t < R::nt; ++t)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) gv[q][j] = gn[q][j];
+    for (int q = 0; q < 4; ++q) {
+      int idx = t * 256 + (4 * grp + q) * 16 + i;
+      r[idx] = (w == 0) ? acc[t][q] : r[idx] + acc[t][q];
+    }
+}
+
+template <int NQ, int K0, int K1> constexpr int max_group_tiles() {
+  int m = GroupRange<NQ, K0, K1, 0>::nt;
+  m = GroupRange<NQ, K0, K1, 1>::nt > m ? GroupRange<NQ, K0, K1, 1>::nt : m;
+  m = GroupRange<NQ, K0, K1, 2>::nt > m ? GroupRange<NQ, K0, K1, 2>::nt : m;
+  m = GroupRange<NQ, K0, K1, 3>::nt > m ? GroupRange<NQ, K0, K1, 3>::nt : m;
+  return m < 1 ? 1 : m;
+}
+
+// Cooperative load of one voxel tile (all 16*NQ bins) into registers.
+template <int NQ> struct TileRegs {
+  static constexpr int N4 = 16 * NQ * kTileVox / 4;  // float4 per tile
+  static constexpr int PER = (N4 + kContractThreads - 1) / kContractThreads;
+  float4 v[PER];
+};
+
+template <int NQ>
+__device__ __forceinline__ void tile_load(const float* __restrict__ g, long mvox, long v0, TileRegs<NQ>& r) {
+#pragma unroll
+  for (int k = 0; k < TileRegs<NQ>::PER; ++k) {
+    int e = threadIdx.x + k * kContractThreads;
+    if (e < TileRegs<NQ>::N4) {
+      int bin = e / (kTileVox / 4), c4 = e % (kTileVox / 4);
+      r.v[k] = *reinterpret_cast<const float4*>(g + (size_t)bin * mvox + v0 + 4 * c4);
     }
   }
 }
 
-// One launch covers pair blocks [K0, K1) (tiles [T0, T1)), split at KM
-// between two halves of 4 waves each; both halves stream the same voxels.
-// Work-group w takes voxels [w*vpw, (w+1)*vpw); the 4 waves of a half
-// interleave K-steps of 32 voxels.  part: [n_wg][n_tiles_total*256] FP32.
-template <int NQ, bool MIXED, int K0, int KM, int K1>
-__global__ void __launch_bounds__(512) k_contract_mfma(const float* __restrict__ g, long mvox, long vpw,
-                                                       float* __restrict__ part, int part_len, unsigned sel_lo,
-                                                       unsigned sel_hi) {
+template <int NQ, bool MIXED>
+__device__ __forceinline__ void tile_store(TileStage<NQ>& st, const TileRegs<NQ>& r, const SplitSel& sel) {
+#pragma unroll
+  for (int k = 0; k < TileRegs<NQ>::PER; ++k) {
+    int e = threadIdx.x + k * kContractThreads;
+    if (e < TileRegs<NQ>::N4) {
+      int bin = e / (kTileVox / 4), c4 = e % (kTileVox / 4);
+      *reinterpret_cast<float4*>(st.f + bin * kPitchF + 4 * c4) = r.v[k];
+      if constexpr (MIXED) {
+        float x[8] = {r.v[k].x, r.v[k].y, r.v[k].z, r.v[k].w, 0.f, 0.f, 0.f, 0.f};
+        bf16x8_t h8, l8;
+        split8(x, h8, l8, sel);
+        __bf16* ph = st.hi + bin * kPitchH + 4 * c4;
+        __bf16* pl = st.lo + bin * kPitchH + 4 * c4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          ph[j] = h8[j];
+          pl[j] = l8[j];
+        }
+      }
+    }
+  }
+}
+
+template <int NQ, bool MIXED, int K0, int K1>
+__global__ void __launch_bounds__(kContractThreads) k_contract_mfma(const float* __restrict__ g, long mvox, long vpw,
+                                                                    float* __restrict__ part, int part_len,
+                                                                    unsigned sel_lo, unsigned sel_hi) {
+  static_assert(kGroups == 4, "group dispatch below assumes four groups");
   constexpr int T0 = tiles_before(NQ, K0);
-  constexpr int TM = tiles_before(NQ, KM);
   constexpr int T1 = tiles_before(NQ, K1);
-  constexpr int NTA = TM - T0, NTB = T1 - TM;
-  constexpr int NTMAX = NTA > NTB ? NTA : NTB;
-  __shared__ float red[(T1 - T0) * 256];
+  constexpr int NTMAX = max_group_tiles<NQ, K0, K1>();
+  constexpr int RED = (T1 - T0) * 256;
+  constexpr int STAGE_FLOATS = (2 * sizeof(TileStage<NQ>) + 3) / 4;
+  __shared__ __align__(16) float smem[RED > STAGE_FLOATS ? RED : STAGE_FLOATS];
+  TileStage<NQ>* stage = reinterpret_cast<TileStage<NQ>*>(smem);
+  float* red = smem;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int half = wave >> 2, wq = wave & 3;
+  const int gi = wave / kWavesPerGroup, wig = wave % kWavesPerGroup;
   const int i = lane & 15, grp = lane >> 4;
   f32x4_t acc[NTMAX];
 #pragma unroll
   for (int t = 0; t < NTMAX; ++t) acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  const long vb = (long)blockIdx.x * vpw;
-  long ve = vb + vpw;
-  if (ve > mvox) ve = mvox;
-  const float* gl[NQ];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) gl[q] = g + (size_t)(16 * q + i) * mvox + 8 * grp;
   SplitSel sel;
   __builtin_memcpy(&sel.lo, &sel_lo, 4);
   __builtin_memcpy(&sel.hi, &sel_hi, 4);
-  if (half == 0)
-    contract_loop<NQ, MIXED, K0, KM>(gl, vb + 32 * wq, ve, acc, sel);
-  else
-    contract_loop<NQ, MIXED, KM, K1>(gl, vb + 32 * wq, ve, acc, sel);
-  // fixed-order sum of the four waves of each half in LDS
-  for (int w = 0; w < 4; ++w) {
-    if (wq == w) {
-      const int nt = half == 0 ? NTA : NTB;
-      float* r = red + (half == 0 ? 0 : NTA * 256);
-#pragma unroll
-      for (int t = 0; t < NTMAX; ++t)
-        if (t < nt) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            int idx = t * 256 + (4 * grp + q) * 16 + i;
-            r[idx] = (w == 0) ? acc[t][q] : r[idx] + acc[t][q];
-          }
-        }
+  const long vb = (long)blockIdx.x * vpw;
+  long ve = vb + vpw;
+  if (ve > mvox) ve = mvox;
+  const int n_tiles_wg = ve > vb ? (int)((ve - vb) / kTileVox) : 0;
+  TileRegs<NQ> regs;
+  if (n_tiles_wg > 0) {
+    tile_load<NQ>(g, mvox, vb, regs);
+    tile_store<NQ, MIXED>(stage[0], regs, sel);
+  }
+  __syncthreads();
+  for (int m = 0; m < n_tiles_wg; ++m) {
+    const bool more = m + 1 < n_tiles_wg;
+    if (more) tile_load<NQ>(g, mvox, vb + (long)(m + 1) * kTileVox, regs);
+    const TileStage<NQ>& cur = stage[m & 1];
+    switch (gi) {
+      case 0: contract_tile<NQ, MIXED, K0, K1, 0>(cur, i, grp, wig, acc, sel); break;
+      case 1: contract_tile<NQ, MIXED, K0, K1, 1>(cur, i, grp, wig, acc, sel); break;
+      case 2: contract_tile<NQ, MIXED, K0, K1, 2>(cur, i, grp, wig, acc, sel); break;
+      default: contract_tile<NQ, MIXED, K0, K1, 3>(cur, i, grp, wig, acc, sel); break;
+    }
+    if (more) tile_store<NQ, MIXED>(stage[(m + 1) & 1], regs, sel);
+    __syncthreads();
+  }
+  // fixed-order sum of the waves of each group in LDS (reuses the stage)
+  for (int w = 0; w < kWavesPerGroup; ++w) {
+    if (wig == w) {
+      switch (gi) {
+        case 0: reduce_group<NQ, K0, K1, 0>(red, acc, w, i, grp); break;
+        case 1: reduce_group<NQ, K0, K1, 1>(red, acc, w, i, grp); break;
+        case 2: reduce_group<NQ, K0, K1, 2>(red, acc, w, i, grp); break;
+        default: reduce_group<NQ, K0, K1, 3>(red, acc, w, i, grp); break;
+      }
     }
     __syncthreads();
   }
   float* dst = part + (size_t)blockIdx.x * part_len + (size_t)T0 * 256;
-  for (int e = threadIdx.x; e < (T1 - T0) * 256; e += 512) dst[e] = red[e];
+  for (int e = threadIdx.x; e < RED; e += kContractThreads) dst[e] = red[e];
 }
 
 template <int NQ, bool MIXED, int G>
 static hipError_t launch_group(const float* g, long mvox, int n_wg, long vpw, float* part, int part_len,
                                hipStream_t s) {
   constexpr int K0 = group_begin(NQ, G), K1 = group_begin(NQ, G + 1);
-  constexpr int KM = split_point(NQ, K0, K1);
   // bf16 pairs (element 0 in the low half): (-1, 0) and (0, -1)
   const unsigned sel_lo = 0x0000BF80u, sel_hi = 0xBF800000u;
-  hipLaunchKernelGGL((k_contract_mfma<NQ, MIXED, K0, KM, K1>), dim3(n_wg), dim3(512), 0, s, g, mvox, vpw, part,
-                     part_len, sel_lo, sel_hi);
+  hipLaunchKernelGGL((k_contract_mfma<NQ, MIXED, K0, K1>), dim3(n_wg), dim3(kContractThreads), 0, s, g, mvox, vpw,
+                     part, part_len, sel_lo, sel_hi);
   return hipGetLastError();
 }
 
@@ -337,15 +421,15 @@ int mfma_grid(int nq, int n_cu) {
   switch (nq) {
     case 1:
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per, (const void*)k_contract_mfma<1, true, 0, split_point(1, 0, 9), 9>, 512, 0);
+          &per, (const void*)k_contract_mfma<1, true, 0, 9>, kContractThreads, 0);
       break;
     case 2:
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per, (const void*)k_contract_mfma<2, true, 0, split_point(2, 0, 34), 34>, 512, 0);
+          &per, (const void*)k_contract_mfma<2, true, 0, 34>, kContractThreads, 0);
       break;
     default:
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per, (const void*)k_contract_mfma<3, true, 0, split_point(3, 0, 17), 17>, 512, 0);
+          &per, (const void*)k_contract_mfma<3, true, 0, 17>, kContractThreads, 0);
       break;
   }
   if (e != hipSuccess || per < 1) per = 1;
@@ -358,7 +442,7 @@ hipError_t launch_contract_mfma(const pb3_plan& p, bool mixed, hipStream_t s) {
   const int nq = p.nb_pad / 16;
   const int n_wg = p.contract_wgs;
   long vpw = (mvox + n_wg - 1) / n_wg;
-  vpw = (vpw + 127) / 128 * 128;
+  vpw = (vpw + kTileVox - 1) / kTileVox * kTileVox;
   float* part = p.ws.part;
   const int pl = p.part_len;
   switch (nq) {
