@@ -64,6 +64,9 @@ typedef enum {
 #define PB3_FLAG_STRICT       0x8u  /* fail with PB3_EINVAL if a triangle-valid triplet has T = 0 */
 #define PB3_FLAG_EXT_WORKSPACE 0x10u /* never allocate the large workspace; caller binds one */
 #define PB3_FLAG_STAGE_TIMING 0x20u /* record a HIP event pair around every kernel launch */
+#define PB3_FLAG_NO_FUSION    0x40u /* run the inverse z pass as its own kernel and keep G in HBM
+                                       (otherwise it is fused into the contraction when the
+                                       contraction grid is 32..192 and there are <= 32 bins) */
 
 /* Build a plan for a cubic grid.
  *   grid[3]   grid points per side; all three equal, even, with prime

@@ -55,6 +55,7 @@ class Plan:
         strict: bool = False,
         stage_timing: bool = False,
         ext_workspace: bool = False,
+        fuse: bool = True,
     ):
         lib = _lib.load()
         self._lib = lib
@@ -69,6 +70,7 @@ class Plan:
         flags |= _lib.FLAG_STRICT if strict else 0
         flags |= _lib.FLAG_STAGE_TIMING if stage_timing else 0
         flags |= _lib.FLAG_EXT_WORKSPACE if ext_workspace else 0
+        flags |= 0 if fuse else _lib.FLAG_NO_FUSION
         h = C.c_void_p()
         _lib.check(
             lib.pb3_plan_create(g, b, e.ctypes.data_as(C.POINTER(C.c_double)), int(e.size), flags, C.byref(h))

@@ -17,6 +17,7 @@ FLAG_FULL_GRID = 0x4
 FLAG_STRICT = 0x8
 FLAG_EXT_WORKSPACE = 0x10
 FLAG_STAGE_TIMING = 0x20
+FLAG_NO_FUSION = 0x40
 
 PREC_FP32 = 0
 PREC_MIXED_BF16X3 = 1

@@ -27,6 +27,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "fft_dev.h"
 #include "pb3_internal.h"
 
 namespace pb3 {
@@ -376,6 +377,239 @@ static hipError_t launch_nq(const float* g, long mvox, int n_wg, long vpw, float
     if (e == hipSuccess) e = launch_group<NQ, MIXED, 2>(g, mvox, n_wg, vpw, part, part_len, s);
   }
   return e;
+}
+
+// ===================================================================
+// Fused inverse z pass + contraction.
+//
+// Work-group w takes whole z-lines (x, y) of the contraction grid, lines
+// [w*lpw, (w+1)*lpw).  Besides the 8 contraction waves it has 4 producer
+// waves: while the contraction waves work on line m from one LDS stage, the
+// producers build line m+1 in the other: for every bin pair (b, b+1) one
+// complex M-point inverse FFT of F_b + i F_{b+1} (each extended by
+// Hermitian symmetry from the y-pass output kz < kzn_b) gives G_b and
+// G_{b+1} on the line as real and imaginary parts; the rows are scaled by
+// 1/M^3, written to the stage and split into bf16 hi/lo there.  The
+// filtered fields therefore never go to HBM.  Each FFT lives inside one
+// wavefront, so producers synchronise per wave and only the per-line
+// work-group barrier couples them to the contraction waves.
+constexpr int kProducerThreads = 256;
+constexpr int kFusedThreads = kContractThreads + kProducerThreads;
+
+template <int NQ, int M> struct LineStage {
+  static constexpr int PF = M + 4, PH = M + 8;
+  float f[16 * NQ * PF];
+  __bf16 hi[16 * NQ * PH];
+  __bf16 lo[16 * NQ * PH];
+};
+
+template <int NQ, bool MIXED, int K0, int K1, int G, int M, int NTMAX>
+__device__ __forceinline__ void contract_line_group(const LineStage<NQ, M>& st, int i, int grp, int wig,
+                                                    f32x4_t (&acc)[NTMAX], const SplitSel& sel) {
+  using R = GroupRange<NQ, K0, K1, G>;
+  constexpr int PF = LineStage<NQ, M>::PF, PH = LineStage<NQ, M>::PH;
+  for (int ks = wig; ks < M / 32; ks += kWavesPerGroup) {
+    const int off = 32 * ks + 8 * grp;
+    float gv[NQ][8];
+    bf16x8_t bh[NQ], bl[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const float4* pf = reinterpret_cast<const float4*>(st.f + (16 * q + i) * PF + off);
+      float4 x0 = pf[0], x1 = pf[1];
+      gv[q][0] = x0.x; gv[q][1] = x0.y; gv[q][2] = x0.z; gv[q][3] = x0.w;
+      gv[q][4] = x1.x; gv[q][5] = x1.y; gv[q][6] = x1.z; gv[q][7] = x1.w;
+      if constexpr (MIXED) {
+        if (q >= R::qmin) {
+          bh[q] = *reinterpret_cast<const bf16x8_t*>(st.hi + (16 * q + i) * PH + off);
+          bl[q] = *reinterpret_cast<const bf16x8_t*>(st.lo + (16 * q + i) * PH + off);
+        }
+      }
+    }
+    do_blocks<NQ, MIXED, R::b, R::e, tiles_before(NQ, R::b)>(gv, bh, bl, acc, sel);
+  }
+}
+
+// Producer: build the stage for one line.  ptid in [0, kProducerThreads).
+template <int NQ, bool MIXED, int M>
+__device__ __forceinline__ void produce_line(LineStage<NQ, M>& st, const float2* __restrict__ a2,
+                                             const BinGeom* __restrict__ geom, int nb, long line,
+                                             const float2* tws, float2* scr, int ptid, float scale,
+                                             const SplitSel& sel) {
+  constexpr int TL = fft2_threads(M), NSLOT = kProducerThreads / TL;
+  constexpr int R1 = fft2_r1(M), R2 = fft2_r2(M);
+  constexpr int PF = LineStage<NQ, M>::PF, PH = LineStage<NQ, M>::PH;
+  const int slot = ptid / TL, tl = ptid % TL;
+  const int npairs = (nb + 1) / 2;
+  for (int pr = slot; pr < npairs; pr += NSLOT) {
+    const int b0 = 2 * pr, b1 = 2 * pr + 1;
+    const BinGeom g0 = geom[b0];
+    const bool has1 = b1 < nb;
+    const BinGeom g1 = has1 ? geom[b1] : g0;
+    const float2* x0 = a2 + g0.a2_off + line * g0.kzn;
+    const float2* x1 = a2 + g1.a2_off + line * g1.kzn;
+    const int k0n = g0.kzn, k1n = has1 ? g1.kzn : 0;
+    fft2_line_wave<M, 1>(
+        scr + slot * (M + 1), tl, tws,
+        [&](int k) {
+          float2 a = make_float2(0.f, 0.f), c = make_float2(0.f, 0.f);
+          const int m = M - k;
+          if (k < k0n) a = x0[k];
+          else if (m < k0n) { a = x0[m]; a.y = -a.y; }
+          if (k < k1n) c = x1[k];
+          else if (m < k1n) { c = x1[m]; c.y = -c.y; }
+          return make_float2(a.x - c.y, a.y + c.x);  // F_b + i F_{b+1}
+        },
+        [&](int k1, const float2 (&u)[R2]) {
+#pragma unroll
+          for (int k2 = 0; k2 < R2; k2 += 2) {
+            const int z0 = k1 + R1 * k2, z1 = z0 + R1;
+            float r0 = u[k2].x * scale, r1 = u[k2 + 1].x * scale;
+            float i0 = u[k2].y * scale, i1 = u[k2 + 1].y * scale;
+            st.f[b0 * PF + z0] = r0;
+            st.f[b0 * PF + z1] = r1;
+            st.f[b1 * PF + z0] = i0;
+            st.f[b1 * PF + z1] = i1;
+            if constexpr (MIXED) {
+              float rv[8] = {r0, r1, i0, i1, 0.f, 0.f, 0.f, 0.f};
+              bf16x8_t h8, l8;
+              split8(rv, h8, l8, sel);
+              st.hi[b0 * PH + z0] = h8[0];
+              st.hi[b0 * PH + z1] = h8[1];
+              st.hi[b1 * PH + z0] = h8[2];
+              st.hi[b1 * PH + z1] = h8[3];
+              st.lo[b0 * PH + z0] = l8[0];
+              st.lo[b0 * PH + z1] = l8[1];
+              st.lo[b1 * PH + z0] = l8[2];
+              st.lo[b1 * PH + z1] = l8[3];
+            }
+          }
+        });
+  }
+}
+
+template <int NQ, bool MIXED, int M>
+__global__ void __launch_bounds__(kFusedThreads) k_zcontract(const float2* __restrict__ a2,
+                                                             const BinGeom* __restrict__ geom, int nb,
+                                                             const float2* __restrict__ tw, float scale, long lpw,
+                                                             float* __restrict__ part, int part_len, unsigned sel_lo,
+                                                             unsigned sel_hi) {
+  constexpr int K0 = 0, K1 = n_pair_blocks(NQ);
+  constexpr int NT = n_tiles(NQ);
+  constexpr int NTMAX = max_group_tiles<NQ, K0, K1>();
+  constexpr int TL = fft2_threads(M), NSLOT = kProducerThreads / TL;
+  constexpr int STAGE_BYTES = (int)sizeof(LineStage<NQ, M>);
+  constexpr int RED_BYTES = NT * 256 * 4;
+  constexpr int MAIN = 2 * STAGE_BYTES > RED_BYTES ? 2 * STAGE_BYTES : RED_BYTES;
+  __shared__ __align__(16) unsigned char smem[MAIN];
+  __shared__ float2 tws[M];
+  __shared__ float2 scr[NSLOT * (M + 1)];
+  LineStage<NQ, M>* stage = reinterpret_cast<LineStage<NQ, M>*>(smem);
+  float* red = reinterpret_cast<float*>(smem);
+  const int tid = threadIdx.x;
+  const bool producer = tid >= kContractThreads;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int gi = wave / kWavesPerGroup, wig = wave % kWavesPerGroup;
+  const int i = lane & 15, grp = lane >> 4;
+  SplitSel sel;
+  __builtin_memcpy(&sel.lo, &sel_lo, 4);
+  __builtin_memcpy(&sel.hi, &sel_hi, 4);
+  f32x4_t acc[NTMAX];
+#pragma unroll
+  for (int t = 0; t < NTMAX; ++t) acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  // zero both stages (rows of padding bins stay zero), twiddles to LDS
+  for (int e = tid; e < 2 * STAGE_BYTES / 4; e += kFusedThreads) reinterpret_cast<float*>(smem)[e] = 0.f;
+  for (int e = tid; e < M; e += kFusedThreads) tws[e] = tw[e];
+  __syncthreads();
+  const long nlines = (long)M * M;
+  const long l0 = (long)blockIdx.x * lpw;
+  long l1 = l0 + lpw;
+  if (l1 > nlines) l1 = nlines;
+  const int n = l1 > l0 ? (int)(l1 - l0) : 0;
+  if (producer && n > 0) produce_line<NQ, MIXED, M>(stage[0], a2, geom, nb, l0, tws, scr, tid - kContractThreads, scale, sel);
+  __syncthreads();
+  for (int m = 0; m < n; ++m) {
+    if (producer) {
+      if (m + 1 < n)
+        produce_line<NQ, MIXED, M>(stage[(m + 1) & 1], a2, geom, nb, l0 + m + 1, tws, scr, tid - kContractThreads,
+                                   scale, sel);
+    } else {
+      const LineStage<NQ, M>& cur = stage[m & 1];
+      switch (gi) {
+        case 0: contract_line_group<NQ, MIXED, K0, K1, 0, M>(cur, i, grp, wig, acc, sel); break;
+        case 1: contract_line_group<NQ, MIXED, K0, K1, 1, M>(cur, i, grp, wig, acc, sel); break;
+        case 2: contract_line_group<NQ, MIXED, K0, K1, 2, M>(cur, i, grp, wig, acc, sel); break;
+        default: contract_line_group<NQ, MIXED, K0, K1, 3, M>(cur, i, grp, wig, acc, sel); break;
+      }
+    }
+    __syncthreads();
+  }
+  // fixed-order sum of the waves of each group in LDS (reuses the stages)
+  for (int w = 0; w < kWavesPerGroup; ++w) {
+    if (!producer && wig == w) {
+      switch (gi) {
+        case 0: reduce_group<NQ, K0, K1, 0>(red, acc, w, i, grp); break;
+        case 1: reduce_group<NQ, K0, K1, 1>(red, acc, w, i, grp); break;
+        case 2: reduce_group<NQ, K0, K1, 2>(red, acc, w, i, grp); break;
+        default: reduce_group<NQ, K0, K1, 3>(red, acc, w, i, grp); break;
+      }
+    }
+    __syncthreads();
+  }
+  float* dst = part + (size_t)blockIdx.x * part_len;
+  for (int e = tid; e < NT * 256; e += kFusedThreads) dst[e] = red[e];
+}
+
+template <int NQ, bool MIXED, int M>
+static hipError_t launch_fused_m(const pb3_plan& p, hipStream_t s) {
+  const long nlines = (long)M * M;
+  const long lpw = (nlines + p.contract_wgs - 1) / p.contract_wgs;
+  const unsigned sel_lo = 0x0000BF80u, sel_hi = 0xBF800000u;
+  const float scale = (float)(1.0 / ((double)M * M * M));
+  hipLaunchKernelGGL((k_zcontract<NQ, MIXED, M>), dim3(p.contract_wgs), dim3(kFusedThreads), 0, s, p.ws.a2, p.d.geom,
+                     p.nb, p.d.tw_m, scale, lpw, p.ws.part, p.part_len, sel_lo, sel_hi);
+  return hipGetLastError();
+}
+
+template <int NQ, bool MIXED>
+static hipError_t launch_fused_nq(const pb3_plan& p, hipStream_t s) {
+  switch (p.M) {
+    case 32: return launch_fused_m<NQ, MIXED, 32>(p, s);
+    case 64: return launch_fused_m<NQ, MIXED, 64>(p, s);
+    case 96: return launch_fused_m<NQ, MIXED, 96>(p, s);
+    case 128: return launch_fused_m<NQ, MIXED, 128>(p, s);
+    case 192: return launch_fused_m<NQ, MIXED, 192>(p, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int fused_grid(int nq, int m, int n_cu) {
+  int per = 1;
+  hipError_t e = hipErrorInvalidValue;
+  const void* fn = nullptr;
+  if (nq == 1) {
+    fn = m == 32 ? (const void*)k_zcontract<1, true, 32> : m == 64 ? (const void*)k_zcontract<1, true, 64>
+       : m == 96 ? (const void*)k_zcontract<1, true, 96> : m == 128 ? (const void*)k_zcontract<1, true, 128>
+                 : (const void*)k_zcontract<1, true, 192>;
+  } else {
+    fn = m == 32 ? (const void*)k_zcontract<2, true, 32> : m == 64 ? (const void*)k_zcontract<2, true, 64>
+       : m == 96 ? (const void*)k_zcontract<2, true, 96> : m == 128 ? (const void*)k_zcontract<2, true, 128>
+                 : (const void*)k_zcontract<2, true, 192>;
+  }
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kFusedThreads, 0);
+  if (e != hipSuccess || per < 1) per = 1;
+  if (per > 4) per = 4;
+  return n_cu * per;
+}
+
+bool fused_supported(int nq, int m) {
+  return nq >= 1 && nq <= 2 && (m == 32 || m == 64 || m == 96 || m == 128 || m == 192);
+}
+
+hipError_t launch_zcontract(const pb3_plan& p, bool mixed, hipStream_t s) {
+  const int nq = p.nb_pad / 16;
+  if (nq == 1) return mixed ? launch_fused_nq<1, true>(p, s) : launch_fused_nq<1, false>(p, s);
+  if (nq == 2) return mixed ? launch_fused_nq<2, true>(p, s) : launch_fused_nq<2, false>(p, s);
+  return hipErrorInvalidValue;
 }
 
 int mfma_tiles(int nq) {

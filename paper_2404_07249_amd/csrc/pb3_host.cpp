@@ -110,7 +110,7 @@ static pb3_status upload_twiddles_d(double2** out, int n) {
 
 static void free_device(pb3_plan* p) {
   DeviceTables& d = p->d;
-  void* ptrs[] = {d.lut,     d.modes,      d.chunk,    d.geom, d.tiles, d.trip_all,
+  void* ptrs[] = {d.lut,     d.modes,      d.chunk,    d.chunk_first, d.geom, d.tiles, d.trip_all,
                   d.out_map, d.inv_counts, d.pk_scale, d.tw_n, d.tw_m,  d.tw_m_d};
   for (void* q : ptrs)
     if (q) hipFree(q);
@@ -256,7 +256,7 @@ static pb3_status build_host(pb3_plan* p, const int grid[3], const double box[3]
   for (int b = 0; b < nb; ++b) p->kmean[b] = ksum[b] / (double)p->nmodes[b];
   p->modes.clear();
   p->chunks.clear();
-  const int CH = 8192;
+  const int CH = 1024;
   for (int b = 0; b < nb; ++b) {
     int start = (int)p->modes.size();
     p->modes.insert(p->modes.end(), per[b].begin(), per[b].end());
@@ -268,6 +268,11 @@ static pb3_status build_host(pb3_plan* p, const int grid[3], const double box[3]
     }
   }
   p->n_chunks = (int)(p->chunks.size() / 3);
+  p->chunk_first.assign(nb + 1, 0);
+  for (int c = 0, b = 0; b <= nb; ++b) {
+    while (c < p->n_chunks && p->chunks[3 * c] < b) ++c;
+    p->chunk_first[b] = c;
+  }
   // per-bin spectrum rectangles and intermediate offsets
   p->geom.resize(nb);
   int64_t o1 = 0, o2 = 0;
@@ -305,6 +310,7 @@ static pb3_status build_host(pb3_plan* p, const int grid[3], const double box[3]
     return PB3_EUNSUPPORTED;
   }
   p->trip = p->trip_all;
+  p->fused = !(flags & PB3_FLAG_NO_FUSION) && fused_supported(p->nb_pad / 16, p->M);
   p->contract_wgs = 512;
   p->part_len = mfma_tiles(p->nb_pad / 16) * 256;
   return PB3_OK;
@@ -318,7 +324,7 @@ static size_t workspace_bytes(const pb3_plan* p) {
   b += align_up(sizeof(float2) * (size_t)p->Lc * p->Lc * p->Kz, A);
   b += align_up(sizeof(float2) * (size_t)p->a1_len, A);
   b += align_up(sizeof(float2) * (size_t)p->a2_len, A);
-  b += align_up(sizeof(float) * (size_t)p->nb_pad * p->M * p->M * p->M, A);
+  b += p->fused ? 0 : align_up(sizeof(float) * (size_t)p->nb_pad * p->M * p->M * p->M, A);
   b += align_up(sizeof(float) * (size_t)p->contract_wgs * p->part_len, A);
   b += align_up(sizeof(double) * (size_t)std::max(p->n_chunks, 1), A);
   b += align_up(sizeof(double) * (size_t)kReduceSlices * p->part_len, A);
@@ -342,7 +348,7 @@ static void carve_workspace(pb3_plan* p, void* base, size_t bytes, bool owned) {
   w.dc = (float2*)take(sizeof(float2) * (size_t)p->Lc * p->Lc * p->Kz);
   w.a1 = (float2*)take(sizeof(float2) * (size_t)p->a1_len);
   w.a2 = (float2*)take(sizeof(float2) * (size_t)p->a2_len);
-  w.g = (float*)take(sizeof(float) * (size_t)p->nb_pad * p->M * p->M * p->M);
+  w.g = p->fused ? nullptr : (float*)take(sizeof(float) * (size_t)p->nb_pad * p->M * p->M * p->M);
   w.part = (float*)take(sizeof(float) * (size_t)p->contract_wgs * p->part_len);
   w.ppart = (double*)take(sizeof(double) * (size_t)std::max(p->n_chunks, 1));
   w.rsl = (double*)take(sizeof(double) * (size_t)kReduceSlices * p->part_len);
@@ -351,7 +357,7 @@ static void carve_workspace(pb3_plan* p, void* base, size_t bytes, bool owned) {
 // The contraction reads the bins [nb, nb_pad) of G as zero fields.
 static pb3_status clear_padding(pb3_plan* p) {
   size_t m3 = (size_t)p->M * p->M * p->M;
-  if (p->nb_pad > p->nb) {
+  if (p->ws.g && p->nb_pad > p->nb) {
     hipError_t e = hipMemset(p->ws.g + (size_t)p->nb * m3, 0, sizeof(float) * (size_t)(p->nb_pad - p->nb) * m3);
     if (e != hipSuccess) return hip_fail(e, "hipMemset");
   }
@@ -382,11 +388,12 @@ static pb3_status build_device(pb3_plan* p) {
   int n_cu = 0;
   e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, p->device_id);
   if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
-  p->contract_wgs = mfma_grid(p->nb_pad / 16, n_cu);
+  p->contract_wgs = p->fused ? fused_grid(p->nb_pad / 16, p->M, n_cu) : mfma_grid(p->nb_pad / 16, n_cu);
   DeviceTables& d = p->d;
   if ((st = upload(&d.lut, p->lut.data(), p->lut.size())) != PB3_OK) return st;
   if ((st = upload(&d.modes, p->modes.data(), p->modes.size())) != PB3_OK) return st;
   if ((st = upload(&d.chunk, p->chunks.data(), p->chunks.size())) != PB3_OK) return st;
+  if ((st = upload(&d.chunk_first, p->chunk_first.data(), p->chunk_first.size())) != PB3_OK) return st;
   if ((st = upload(&d.geom, p->geom.data(), p->geom.size())) != PB3_OK) return st;
   if ((st = upload(&d.trip_all, p->trip_all.data(), p->trip_all.size())) != PB3_OK) return st;
   if ((st = upload_twiddles_f(&d.tw_n, p->N)) != PB3_OK) return st;
@@ -521,9 +528,16 @@ static pb3_status run(pb3_plan* p, const float* delta, double* pk, double* bk, p
   if (bk) {
     if ((st = stage(p, ST_INV_X, s, "inv_x", [&] { return launch_inv_x(*p, s); })) != PB3_OK) return st;
     if ((st = stage(p, ST_INV_Y, s, "inv_y", [&] { return launch_inv_y(*p, s); })) != PB3_OK) return st;
-    if ((st = stage(p, ST_INV_Z, s, "inv_z", [&] { return launch_inv_z(*p, s); })) != PB3_OK) return st;
-    if ((st = stage(p, ST_CONTRACT, s, "contract", [&] { return launch_contract(*p, prec, s); })) != PB3_OK)
-      return st;
+    if (p->fused) {
+      if ((st = stage(p, ST_CONTRACT, s, "contract", [&] {
+             return launch_zcontract(*p, prec == PB3_MIXED_BF16X3, s);
+           })) != PB3_OK)
+        return st;
+    } else {
+      if ((st = stage(p, ST_INV_Z, s, "inv_z", [&] { return launch_inv_z(*p, s); })) != PB3_OK) return st;
+      if ((st = stage(p, ST_CONTRACT, s, "contract", [&] { return launch_contract(*p, prec, s); })) != PB3_OK)
+        return st;
+    }
     if ((st = stage(p, ST_REDUCE, s, "reduce", [&] { return launch_reduce(*p, prec, bk, s); })) != PB3_OK) return st;
   }
   p->last_prec = prec;

@@ -12,7 +12,7 @@
 
 namespace pb3 {
 
-constexpr int kReduceSlices = 16;
+constexpr int kReduceSlices = 32;
 
 // Stage indices for the optional per-kernel timing.
 enum Stage {
@@ -57,6 +57,7 @@ struct DeviceTables {
   int8_t* lut = nullptr;          // bin of |n|^2 (int8, -1 outside), size lut_len
   int32_t* modes = nullptr;       // compact D index of every binned half-spectrum mode (bit 31: weight 1)
   int32_t* chunk = nullptr;       // power chunks: (bin, start, end) triples
+  int32_t* chunk_first = nullptr; // per bin: index of its first chunk (n_bins + 1 entries)
   BinGeom* geom = nullptr;        // per bin
   BinTile* tiles = nullptr;       // all FP32 inverse-pass tiles (x, then y, then z)
   int32_t* trip_all = nullptr;    // candidate triplets (3 ints each), simple contraction
@@ -100,6 +101,7 @@ struct pb3_plan {
   int Lc = 0;                  // compact x/y length
   int Kz = 0;                  // compact z length
   int M = 0;                   // contraction grid
+  bool fused = false;          // inverse z pass fused into the contraction (no G in HBM)
   int lut_len = 0;
   std::vector<int8_t> lut;
   std::vector<int64_t> nmodes;
@@ -112,6 +114,7 @@ struct pb3_plan {
   std::vector<int32_t> modes;
   std::vector<int32_t> chunks;
   int n_chunks = 0;
+  std::vector<int32_t> chunk_first;
   pb3::TileSet tx{}, ty{}, tz{};   // FP32 inverse-pass tiles (device)
   // contraction
   int contract_wgs = 0;
@@ -153,6 +156,10 @@ int mfma_tiles(int nq);
 int mfma_locate(int nq, int a, int b, int c);
 hipError_t launch_contract_mfma(const pb3_plan& p, bool mixed, hipStream_t s);
 int mfma_grid(int nq, int n_cu);
+// fused inverse z pass + contraction (contract_mfma.hip)
+bool fused_supported(int nq, int m);
+int fused_grid(int nq, int m, int n_cu);
+hipError_t launch_zcontract(const pb3_plan& p, bool mixed, hipStream_t s);
 // inverse passes (fft_passes.hip) on FP32 (dbl = false) or FP64 lines;
 // unit = the shell indicator instead of Theta_b D (count pass, FP64 only)
 hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, void* a1, const void* tw, const TileSet& ts,

@@ -46,13 +46,12 @@ __global__ void __launch_bounds__(256) k_power_chunks(const float2* __restrict__
   if (threadIdx.x == 0) part[c] = red[0];
 }
 
-__global__ void k_power_final(const double* __restrict__ part, const int32_t* __restrict__ chunks, int n_chunks, int nb,
+__global__ void k_power_final(const double* __restrict__ part, const int32_t* __restrict__ chunk_first, int nb,
                               const double* __restrict__ scale, double* __restrict__ pk) {
   int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb) return;
   double s = 0.0;
-  for (int c = 0; c < n_chunks; ++c)
-    if (chunks[3 * c] == b) s += part[c];
+  for (int c = chunk_first[b]; c < chunk_first[b + 1]; ++c) s += part[c];
   pk[b] = s * scale[b];
 }
 
@@ -158,7 +157,7 @@ hipError_t launch_power(const pb3_plan& p, double* pk, hipStream_t s) {
   hipLaunchKernelGGL(k_power_chunks, dim3(p.n_chunks), dim3(256), 0, s, p.ws.dc, p.d.modes, p.d.chunk, p.ws.ppart);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_power_final, dim3((p.nb + 63) / 64), dim3(64), 0, s, p.ws.ppart, p.d.chunk, p.n_chunks, p.nb,
+  hipLaunchKernelGGL(k_power_final, dim3((p.nb + 63) / 64), dim3(64), 0, s, p.ws.ppart, p.d.chunk_first, p.nb,
                      p.d.pk_scale, pk);
   return hipGetLastError();
 }

@@ -235,3 +235,26 @@ def test_argument_errors_on_device(torch_cuda):
     p2 = pb3.Plan(32, 1000.0, kf_edges(8), ext_workspace=True)
     with pytest.raises(pb3.Pb3Error):
         p2.power(torch.zeros((32, 32, 32), device="cuda"))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize(
+    "n,box,edges",
+    [
+        (128, 2000.0, kf_edges(20)),  # contraction grid 128, two 16-bin groups
+        (96, 2000.0, kf_edges(10)),  # contraction grid 64, one group
+        (64, 1000.0, kf_edges(9)),  # contraction grid 64 = N, one 16-bin group
+    ],
+)
+def test_fused_and_separate_z_pass_agree(torch_cuda, prec, n, box, edges):
+    """The inverse z pass fused into the contraction (fields never in HBM)
+    and the separate z-pass kernel both meet the parity bound."""
+    torch = torch_cuda
+    d = quadratic_field(n, box, 1.0, 99 + n).astype(np.float32)
+    res = oracle.bispectrum(d.astype(np.float64), box, edges)
+    p1, pk1, bk1 = _run_case(torch, n, box, edges, d, prec)
+    p2, pk2, bk2 = _run_case(torch, n, box, edges, d, prec, fuse=False)
+    assert p1.contract_grid == p2.contract_grid
+    assert p1.workspace_bytes < p2.workspace_bytes  # no filtered fields in the fused workspace
+    _check_pb(res, pk1, bk1, p1.triplets, "fused")
+    _check_pb(res, pk2, bk2, p2.triplets, "separate")
