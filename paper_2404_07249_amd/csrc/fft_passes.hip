@@ -101,8 +101,11 @@ __global__ void __launch_bounds__(512) k_fwd_col2(const float2* __restrict__ in,
 }
 
 // ---------------------------------------------------------- inverse x
-// Per bin b: columns q = (jy, jz) of the bin's rectangle; the kx line of
+// Per bin b, one work-group per (row jy of the bin's rectangle, chunk of TB
+// columns kz); the chunks of one row have consecutive tile indices, so they
+// run together and their partial cache lines combine.  The kx line of
 // Theta_b D (Theta_b alone when UNIT) enters at FFT positions kx mod M.
+// Output a1_b[x][jy][jz].  Tile col0 = row * 256 + first column.
 template <int M, typename Rl, bool UNIT>
 __global__ void __launch_bounds__(512) k_inv_x2(const float2* __restrict__ dc, typename Cx<Rl>::type* __restrict__ a1,
                                                 const BinGeom* __restrict__ geom, const BinTile* __restrict__ tiles,
@@ -120,34 +123,38 @@ __global__ void __launch_bounds__(512) k_inv_x2(const float2* __restrict__ dc, t
   const BinTile tile = tiles[blockIdx.x];
   const int b = tile.bin;
   const BinGeom g = geom[b];
+  const int jy = tile.col0 >> 8;
+  const int ky = jy - g.kneg;
   const int ncol = g.ly * g.kzn;
-  const int q = tile.col0 + col;
-  const bool live = q < ncol;
-  const int ky = live ? q / g.kzn - g.kneg : 0;
-  const int kz = live ? q % g.kzn : 0;
-  C* dst = a1 + g.a1_off + q;
-  fft2_line<M, 1>(
-      scr + col * LS, tl, tws,
-      [&](int n) {
-        C v = cx<C>(Rl(0), Rl(0));
-        int kx = n <= g.kpos ? n : (n >= M - g.kneg ? n - M : 0x40000000);
-        if (live && kx != 0x40000000 && lut[kx * kx + ky * ky + kz * kz] == b) {
-          if constexpr (UNIT) {
-            v = cx<C>(Rl(1), Rl(0));
-          } else {
-            float2 d = dc[((size_t)(kx + Kc) * Lc + (ky + Kc)) * Kz + kz];
-            v = cx<C>(Rl(d.x), Rl(d.y));
+  {
+    const int kz = (tile.col0 & 255) + col;
+    const bool live = kz < g.kzn;
+    C* dst = a1 + g.a1_off + (size_t)jy * g.kzn + kz;
+    fft2_line<M, 1>(
+        scr + col * LS, tl, tws,
+        [&](int n) {
+          C v = cx<C>(Rl(0), Rl(0));
+          int kx = n <= g.kpos ? n : (n >= M - g.kneg ? n - M : 0x40000000);
+          if (live && kx != 0x40000000 && lut[kx * kx + ky * ky + kz * kz] == b) {
+            if constexpr (UNIT) {
+              v = cx<C>(Rl(1), Rl(0));
+            } else {
+              float2 d = dc[((size_t)(kx + Kc) * Lc + (ky + Kc)) * Kz + kz];
+              v = cx<C>(Rl(d.x), Rl(d.y));
+            }
           }
-        }
-        return v;
-      },
-      [&](int x, C v) {
-        if (live) dst[(size_t)x * ncol] = v;
-      });
+          return v;
+        },
+        [&](int x, C v) {
+          if (live) dst[(size_t)x * ncol] = v;
+        });
+  }
 }
 
 // ---------------------------------------------------------- inverse y
-// Per bin: columns q = (x, jz); inverse transform along y.
+// Per bin, one work-group per (x-plane, chunk of TB columns jz), chunks of
+// a plane consecutive; inverse transform along y.  Tile col0 = x * 256 +
+// first column.
 template <int M, typename Rl>
 __global__ void __launch_bounds__(512) k_inv_y2(const typename Cx<Rl>::type* __restrict__ a1,
                                                 typename Cx<Rl>::type* __restrict__ a2,
@@ -164,21 +171,22 @@ __global__ void __launch_bounds__(512) k_inv_y2(const typename Cx<Rl>::type* __r
   const int tl = tid / TB, col = tid % TB;
   const BinTile tile = tiles[blockIdx.x];
   const BinGeom g = geom[tile.bin];
-  const int ncol = M * g.kzn;
-  const int q = tile.col0 + col;
-  const bool live = q < ncol;
-  const int x = live ? q / g.kzn : 0, jz = live ? q % g.kzn : 0;
-  const C* src = a1 + g.a1_off + ((size_t)x * g.ly + g.kneg) * g.kzn + jz;  // ky = 0 row
-  C* dst = a2 + g.a2_off + (size_t)x * M * g.kzn + jz;
-  fft2_line<M, 1>(
-      scr + col * LS, tl, tws,
-      [&](int n) {
-        int ky = n <= g.kpos ? n : (n >= M - g.kneg ? n - M : 0x40000000);
-        return (live && ky != 0x40000000) ? src[(long)ky * g.kzn] : cx<C>(Rl(0), Rl(0));
-      },
-      [&](int y, C v) {
-        if (live) dst[(size_t)y * g.kzn] = v;
-      });
+  const int x = tile.col0 >> 8;
+  {
+    const int jz = (tile.col0 & 255) + col;
+    const bool live = jz < g.kzn;
+    const C* src = a1 + g.a1_off + ((size_t)x * g.ly + g.kneg) * g.kzn + jz;  // ky = 0 row
+    C* dst = a2 + g.a2_off + (size_t)x * M * g.kzn + jz;
+    fft2_line<M, 1>(
+        scr + col * LS, tl, tws,
+        [&](int n) {
+          int ky = n <= g.kpos ? n : (n >= M - g.kneg ? n - M : 0x40000000);
+          return (live && ky != 0x40000000) ? src[(long)ky * g.kzn] : cx<C>(Rl(0), Rl(0));
+        },
+        [&](int y, C v) {
+          if (live) dst[(size_t)y * g.kzn] = v;
+        });
+  }
 }
 
 // ---------------------------------------------------------- inverse z
@@ -303,7 +311,6 @@ hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, void* a1, const voi
   PB3_FFT_LEN(p.M, {
     if (dbl) {
       using S = ColShape<LL, 16>;
-      if (ts.tb != S::TB) return hipErrorInvalidConfiguration;
       if (unit)
         hipLaunchKernelGGL((k_inv_x2<LL, double, true>), dim3(ts.n), dim3(S::NT), 0, s, p.ws.dc, (double2*)a1,
                            p.d.geom, ts.d, p.d.lut, p.Kc, p.Lc, p.Kz, (const double2*)tw);
@@ -311,7 +318,6 @@ hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, void* a1, const voi
         return hipErrorInvalidValue;
     } else {
       using S = ColShape<LL, 8>;
-      if (ts.tb != S::TB) return hipErrorInvalidConfiguration;
       if (unit) return hipErrorInvalidValue;
       hipLaunchKernelGGL((k_inv_x2<LL, float, false>), dim3(ts.n), dim3(S::NT), 0, s, p.ws.dc, (float2*)a1, p.d.geom,
                          ts.d, p.d.lut, p.Kc, p.Lc, p.Kz, (const float2*)tw);
@@ -327,12 +333,10 @@ hipError_t run_inv_y(const pb3_plan& p, bool dbl, const void* a1, void* a2, cons
   PB3_FFT_LEN(p.M, {
     if (dbl) {
       using S = ColShape<LL, 16>;
-      if (ts.tb != S::TB) return hipErrorInvalidConfiguration;
       hipLaunchKernelGGL((k_inv_y2<LL, double>), dim3(ts.n), dim3(S::NT), 0, s, (const double2*)a1, (double2*)a2,
                          p.d.geom, ts.d, (const double2*)tw);
     } else {
       using S = ColShape<LL, 8>;
-      if (ts.tb != S::TB) return hipErrorInvalidConfiguration;
       hipLaunchKernelGGL((k_inv_y2<LL, float>), dim3(ts.n), dim3(S::NT), 0, s, (const float2*)a1, (float2*)a2,
                          p.d.geom, ts.d, (const float2*)tw);
     }

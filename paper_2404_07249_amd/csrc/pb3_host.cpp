@@ -41,17 +41,18 @@ static int smallest_len_above(int lo, int hi) {
 
 static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-void build_tiles(const pb3_plan& p, int tbx, int tby, int tbz, std::vector<BinTile>& vx, std::vector<BinTile>& vy,
+void build_tiles(const pb3_plan& p, int tbxy, int tbz, std::vector<BinTile>& vx, std::vector<BinTile>& vy,
                  std::vector<BinTile>& vz) {
   vx.clear();
   vy.clear();
   vz.clear();
   for (int b = 0; b < p.nb; ++b) {
     const BinGeom& g = p.geom[b];
-    int nx = g.ly * g.kzn;
-    for (int c = 0; c < nx; c += tbx) vx.push_back(BinTile{b, c});
-    int ny = p.M * g.kzn;
-    for (int c = 0; c < ny; c += tby) vy.push_back(BinTile{b, c});
+    // x pass: (row jy, column chunk); y pass: (x-plane, column chunk)
+    for (int jy = 0; jy < g.ly; ++jy)
+      for (int c = 0; c < g.kzn; c += tbxy) vx.push_back(BinTile{b, jy * 256 + c});
+    for (int x = 0; x < p.M; ++x)
+      for (int c = 0; c < g.kzn; c += tbxy) vy.push_back(BinTile{b, x * 256 + c});
     int nz = p.M * p.M;
     for (int c = 0; c < nz; c += tbz) vz.push_back(BinTile{b, c});
   }
@@ -406,7 +407,7 @@ static pb3_status build_device(pb3_plan* p) {
     return PB3_EUNSUPPORTED;
   }
   std::vector<BinTile> vx, vy, vz;
-  build_tiles(*p, tbx, tbx, tbz, vx, vy, vz);
+  build_tiles(*p, tbx, tbz, vx, vy, vz);
   std::vector<BinTile> all(vx);
   all.insert(all.end(), vy.begin(), vy.end());
   all.insert(all.end(), vz.begin(), vz.end());

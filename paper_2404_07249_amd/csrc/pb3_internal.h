@@ -171,8 +171,9 @@ hipError_t run_inv_z(const pb3_plan& p, bool dbl, const void* a2, void* gout, co
 // tile widths of the inverse passes for FP32 (dbl = false) or FP64 lines
 int tile_width_x(int M, bool dbl);
 int tile_width_z(int M, bool dbl);
-// per-bin tile tables for the three inverse passes (host)
-void build_tiles(const pb3_plan& p, int tbx, int tby, int tbz, std::vector<BinTile>& vx, std::vector<BinTile>& vy,
+// per-bin tile tables of the three inverse passes (host): x pass (row jy,
+// chunk of tbxy columns), y pass (x-plane, chunk), z pass tbz lines
+void build_tiles(const pb3_plan& p, int tbxy, int tbz, std::vector<BinTile>& vx, std::vector<BinTile>& vy,
                  std::vector<BinTile>& vz);
 
 }  // namespace pb3

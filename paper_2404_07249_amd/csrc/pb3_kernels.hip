@@ -257,7 +257,7 @@ pb3_status compute_counts_fp64(pb3_plan& p, std::vector<double>& counts_out) {
       goto done;
     }
     std::vector<BinTile> vx, vy, vz;
-    build_tiles(p, tbx, tbx, tbz, vx, vy, vz);
+    build_tiles(p, tbx, tbz, vx, vy, vz);
     size_t nt = vx.size() + vy.size() + vz.size();
     if (!alloc((void**)&tiles, sizeof(BinTile) * (nt ? nt : 1))) {
       st = PB3_ENOMEM;
