@@ -37,6 +37,42 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 FP32_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 
+# HBM traffic of the dominant kernel at this workload from two rocprofv3
+# counter passes (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), scaled by what
+# the same counters read for a device copy of known size (reads x2.0,
+# writes x1.0).  Valid only for the kernel sources it was taken on: the
+# figure is dropped (null) once their hash differs.
+MEASURED_TRAFFIC = {
+    ("contract", "mixed"): {
+        "kernel": "k_zcontract<2, true, 192>",
+        "fetch_kib": 141582.2, "write_kib": 22528.0, "fetch_factor": 2.0, "write_factor": 1.0,
+        "sources": {
+            "paper_2404_07249_amd/csrc/contract_mfma.hip":
+                "4391e5c1690c4387cdd4f3037750c341f5582050c893bd276200d6c890ae36a3",
+            "paper_2404_07249_amd/csrc/fft_dev.h":
+                "445483e27faf3491134cb99e4822494520ab3d6b22f80871c30bdb01f5151c73",
+        },
+    },
+}
+
+
+def measured_traffic(stage: str, precision: str):
+    """HBM bytes per launch of ``stage`` from the counter passes, or None."""
+    import hashlib
+
+    t = MEASURED_TRAFFIC.get((stage, precision))
+    if t is None:
+        return None
+    for rel, digest in t["sources"].items():
+        try:
+            with open(os.path.join(ROOT, rel), "rb") as fh:
+                if hashlib.sha256(fh.read()).hexdigest() != digest:
+                    return None
+        except OSError:
+            return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"])
+
+
 def _cores() -> int:
     try:
         return len(os.sched_getaffinity(0))
@@ -63,6 +99,25 @@ def stage_work(plan_info: dict, precision: str) -> dict:
     w["contract"] = ("flops", 2.0 * n_pairs * nb * m**3)
     w["reduce"] = ("hbm", 0)
     return w
+
+
+def stage_rates(work: dict, stages: dict, precision: str) -> dict:
+    """Achieved rate of every timed stage against its roofline: GB/s of
+    algorithmic bytes for the HBM-bound passes, TFLOP/s of the recast GEMM
+    for the contraction (which also carries the fused inverse z pass)."""
+    out = {}
+    for k, (kind, amount) in work.items():
+        ms = stages.get(k, (0.0, 0))[0]
+        if ms <= 0 or amount <= 0:
+            continue
+        if kind == "flops":
+            peak = BF16_PEAK_TFLOPS if precision == "mixed" else FP32_MFMA_PEAK_TFLOPS
+            a = amount / (ms * 1e-3) / 1e12
+            out[k] = {"TFLOP/s": round(a, 2), "frac": round(a / peak, 4)}
+        else:
+            a = amount / (ms * 1e-3) / 1e9
+            out[k] = {"GB/s": round(a, 1), "frac": round(a / HBM_PEAK_GBS, 4)}
+    return out
 
 
 def plan_geometry(n, box, edges):
@@ -184,11 +239,11 @@ def main(argv=None):
         peak = BF16_PEAK_TFLOPS if main_p == "mixed" else FP32_MFMA_PEAK_TFLOPS
         achieved = amount / (ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": None}
+                "traffic": measured_traffic(dom, main_p)}
     else:
         achieved = amount / (ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, main_p)}
     roof["kernel"] = dom
     line = {
         "metric": METRIC,
@@ -220,6 +275,7 @@ def main(argv=None):
             for p in results if p != main_p
         },
         "stages_ms": {k: round(v[0], 5) for k, v in r["stages"].items()},
+        "stage_rates": stage_rates(work, r["stages"], main_p),
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
