@@ -120,6 +120,74 @@ def stage_rates(work: dict, stages: dict, precision: str) -> dict:
     return out
 
 
+def batched_bench(reps: int = 10, warmup: int = 2, precision: str = "mixed") -> dict:
+    """The batched workload (64 realizations on 64^3/96^3/128^3 grids with
+    16-24 bins, nine distinct plans): throughput of one call per field on
+    one stream, of the batch (shared launches, concurrent plan groups) and
+    of the batch replayed from a HIP graph.  P and B for every field."""
+    import torch
+
+    import paper_2404_07249_amd as pb3
+    from synthetic import batch_jobs
+
+    jobs = batch_jobs(64)
+    cache = {}
+    plans = []
+    for jb in jobs:
+        key = (jb["n"], jb["n_bins"])
+        if key not in cache:
+            cache[key] = pb3.Plan(jb["n"], jb["box"], jb["edges"])
+        plans.append(cache[key])
+    xs = [torch.from_numpy(jb["field"]).cuda() for jb in jobs]
+    pk = [torch.empty(p.n_bins, dtype=torch.float64, device="cuda") for p in plans]
+    bk = [torch.empty(p.n_triplets, dtype=torch.float64, device="cuda") for p in plans]
+    stream = torch.cuda.current_stream()
+    eager = pb3.Batch(plans)
+    graph = pb3.Batch(plans, graph=True)
+    n_l = {id(p): p_launches(p) for p in cache.values()}
+
+    def singles():
+        for p, x, a, b in zip(plans, xs, pk, bk):
+            p.polyspectra(x, precision, pk_out=a, bk_out=b, stream=stream)
+
+    modes = {
+        "single_calls": singles,
+        "batch": lambda: eager.run(xs, precision, pk_outs=pk, bk_outs=bk, stream=stream),
+        "batch_graph": lambda: graph.run(xs, precision, pk_outs=pk, bk_outs=bk, stream=stream),
+    }
+    rates, ms = {}, {}
+    for name, fn in modes.items():
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rates[name] = len(jobs) * reps / dt
+        ms[name] = 1e3 * dt / reps
+    return {
+        "workload": "64 realizations, grids 64^3/96^3/128^3 (job i: grid (64,96,128)[i%3], 16+(i%9) bins of "
+                    "width 2k_f), L=2000 Mpc/h, f_NL=1; P+B per field",
+        "precision": precision,
+        "plans": len(cache),
+        "launch_groups": graph.groups,
+        "launches_per_run": graph.launches(),
+        "launches_single_calls": sum(n_l[id(p)] for p in plans),
+        "bispectra_per_s": rates,
+        "ms_per_batch": ms,
+        "speedup_graph_vs_single": rates["batch_graph"] / rates["single_calls"],
+    }
+
+
+def p_launches(plan) -> int:
+    """Kernel launches of one single P+B call (a one-job batch)."""
+    import paper_2404_07249_amd as pb3
+
+    return pb3.Batch([plan], ext_workspace=True).launches()
+
+
 def plan_geometry(n, box, edges):
     """Host-side geometry the stage model needs (same rules as the library)."""
     import paper_2404_07249_amd as pb3
@@ -180,6 +248,7 @@ def main(argv=None):
     ap.add_argument("--precision", choices=["mixed", "fp32"], default="mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-calls", type=int, default=50)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-workload measurement")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(
@@ -278,6 +347,8 @@ def main(argv=None):
         "stage_rates": stage_rates(work, r["stages"], main_p),
         "roofline": roof,
     }
+    if not args.no_batched:
+        line["batched"] = batched_bench(precision=main_p)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(d32, box, edges, plan.n_triplets)
     print(json.dumps(line), flush=True)

@@ -132,6 +132,55 @@ pb3_status pb3_stage_times(pb3_plan* plan, float* ms_out, int* counts_out, int c
 pb3_status pb3_stage_timing_reset(pb3_plan* plan);
 const char* pb3_stage_name(int stage);
 
+/* ---------------------------------------------------------------- batches
+ * Many fields through one or more plans in few launches.  The paper runs
+ * its estimators independently over many simulations (Sec. VI); here those
+ * evaluations share kernel launches:
+ *  - jobs that use the same plan object run in the same launches, up to 8
+ *    per launch (grid dimension z enumerates the jobs, each with its own
+ *    workspace slice);
+ *  - groups of different plans run concurrently on internal streams
+ *    (default priority), forked from and joined back into the caller's
+ *    stream, so the run is ordered on that stream like one call;
+ *  - with PB3_BATCH_GRAPH the fork, all launch sequences and the join are
+ *    captured once into a HIP graph that later runs replay; a run with other
+ *    pointers, outputs or precision captures again and updates the graph.
+ * Every job's results equal, bit for bit, those of pb3_polyspectra on the
+ * same plan and field: the kernels and reduction orders are the same.
+ * A batch has one run in flight at a time; its plans must outlive it and
+ * must not be destroyed or re-bound while it exists. */
+typedef struct pb3_batch pb3_batch;
+
+#define PB3_BATCH_GRAPH         0x1u  /* capture the run into a HIP graph, replay afterwards */
+#define PB3_BATCH_EXT_WORKSPACE 0x2u  /* do not allocate; caller binds pb3_batch_workspace_bytes */
+
+/* plans: host array of n_jobs device plans (current device; repeats share
+ * launches).  Allocates the workspace unless PB3_BATCH_EXT_WORKSPACE.
+ * Errors: PB3_EINVAL (null or host-only plan, n_jobs < 1, unknown flag),
+ * PB3_ENOMEM, PB3_EDEVICE. */
+pb3_status pb3_batch_create(pb3_plan* const* plans, int n_jobs, unsigned flags, pb3_batch** out);
+pb3_status pb3_batch_destroy(pb3_batch* batch);
+/* Sum over jobs of their plans' workspace sizes. */
+size_t pb3_batch_workspace_bytes(const pb3_batch* batch);
+/* Caller-owned device memory, 256-byte aligned, >= pb3_batch_workspace_bytes. */
+pb3_status pb3_batch_bind_workspace(pb3_batch* batch, void* dev, size_t bytes);
+/* Run every job.  deltas: host array of n_jobs device pointers (N^3 float32
+ * of the job's plan); pk / bk: host arrays of n_jobs device outputs
+ * (n_bins / n_trip float64 of the job's plan), or NULL to skip that
+ * statistic for all jobs (not both).  Enqueued on `stream`. */
+pb3_status pb3_batch_run(pb3_batch* batch, const float* const* deltas, double* const* pk, double* const* bk,
+                         pb3_precision prec, void* stream);
+/* Kernel launches one run issues (with or without each statistic) and the
+ * number of launch groups (plan, up to 8 jobs). */
+int pb3_batch_launches(const pb3_batch* batch, int with_pk, int with_bk);
+int pb3_batch_groups(const pb3_batch* batch);
+
+/* One-shot form: builds a batch for plans[0..n_jobs), runs the bispectra of
+ * all fields, waits for `stream` and frees the batch (allocates and
+ * synchronises on every call; repeated use should keep a pb3_batch). */
+pb3_status pb3_bispectrum_batched(pb3_plan* const* plans, const float* const* deltas, double* const* bk_outs,
+                                  int n_jobs, pb3_precision prec, void* stream);
+
 const char* pb3_status_string(pb3_status s);
 const char* pb3_last_error(void);
 

@@ -18,7 +18,7 @@ import numpy as np
 from . import _lib
 from ._lib import Pb3Error  # noqa: F401
 
-__all__ = ["Plan", "Pb3Error", "load_library"]
+__all__ = ["Plan", "Batch", "Pb3Error", "load_library"]
 
 _PREC = {"fp32": _lib.PREC_FP32, "mixed": _lib.PREC_MIXED_BF16X3, "bf16x3": _lib.PREC_MIXED_BF16X3}
 
@@ -195,3 +195,100 @@ class Plan:
 
     def reset_stage_times(self):
         _lib.check(self._lib.pb3_stage_timing_reset(self._h))
+
+
+def _ptr_array(values):
+    arr = (C.c_void_p * len(values))()
+    for i, v in enumerate(values):
+        arr[i] = v
+    return arr
+
+
+class Batch:
+    """Many fields through one or more plans in shared launches
+    (``pb3_batch``).  Jobs that use the same ``Plan`` object run in the same
+    kernel launches (up to 8 per launch); different plans run concurrently
+    on internal streams.  ``graph=True`` captures the run into a HIP graph
+    and replays it while the arguments stay the same.  The plans must stay
+    alive as long as the batch.
+    """
+
+    def __init__(self, plans, *, graph: bool = False, ext_workspace: bool = False):
+        lib = _lib.load()
+        self._lib = lib
+        self._h = None
+        self.plans = list(plans)
+        arr = _ptr_array([p._h.value for p in self.plans])
+        flags = (_lib.BATCH_GRAPH if graph else 0) | (_lib.BATCH_EXT_WORKSPACE if ext_workspace else 0)
+        h = C.c_void_p()
+        _lib.check(lib.pb3_batch_create(arr, len(self.plans), flags, C.byref(h)))
+        self._h = h
+        self._workspace = None
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.pb3_batch_destroy(self._h)
+            self._h = None
+
+    def close(self):
+        self.__del__()
+
+    @property
+    def n_jobs(self) -> int:
+        return len(self.plans)
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self._lib.pb3_batch_workspace_bytes(self._h))
+
+    def launches(self, power: bool = True, bispectrum: bool = True) -> int:
+        return int(self._lib.pb3_batch_launches(self._h, int(power), int(bispectrum)))
+
+    @property
+    def groups(self) -> int:
+        return int(self._lib.pb3_batch_groups(self._h))
+
+    def bind_workspace(self, tensor):
+        nbytes = tensor.numel() * tensor.element_size()
+        _lib.check(self._lib.pb3_batch_bind_workspace(self._h, C.c_void_p(tensor.data_ptr()), nbytes))
+        self._workspace = tensor
+
+    def run(self, deltas, precision: str = "mixed", pk_outs=None, bk_outs=None, power: bool = True,
+            bispectrum: bool = True, stream=None):
+        """Run every job; returns (list of P tensors or None, list of B tensors or None)."""
+        import torch
+
+        if len(deltas) != self.n_jobs:
+            raise ValueError("one field per job")
+        for p, d in zip(self.plans, deltas):
+            p._check_field(d)
+        pks = bks = None
+        if power:
+            pks = pk_outs if pk_outs is not None else [
+                torch.empty(p.n_bins, dtype=torch.float64, device=d.device) for p, d in zip(self.plans, deltas)]
+            for p, o, d in zip(self.plans, pks, deltas):
+                p._out(o, p.n_bins, d)
+        if bispectrum:
+            bks = bk_outs if bk_outs is not None else [
+                torch.empty(p.n_triplets, dtype=torch.float64, device=d.device) for p, d in zip(self.plans, deltas)]
+            for p, o, d in zip(self.plans, bks, deltas):
+                p._out(o, p.n_triplets, d)
+        da = _ptr_array([d.data_ptr() for d in deltas])
+        pa = _ptr_array([o.data_ptr() for o in pks]) if pks is not None else None
+        ba = _ptr_array([o.data_ptr() for o in bks]) if bks is not None else None
+        _lib.check(self._lib.pb3_batch_run(self._h, da, pa, ba, _PREC[precision], _stream_handle(stream)))
+        return pks, bks
+
+
+def bispectrum_batched(plans, deltas, precision: str = "mixed", stream=None):
+    """One-shot ``pb3_bispectrum_batched``: allocates, runs, synchronises."""
+    import torch
+
+    lib = _lib.load()
+    for p, d in zip(plans, deltas):
+        p._check_field(d)
+    outs = [torch.empty(p.n_triplets, dtype=torch.float64, device=d.device) for p, d in zip(plans, deltas)]
+    _lib.check(lib.pb3_bispectrum_batched(
+        _ptr_array([p._h.value for p in plans]), _ptr_array([d.data_ptr() for d in deltas]),
+        _ptr_array([o.data_ptr() for o in outs]), len(plans), _PREC[precision], _stream_handle(stream)))
+    return outs

@@ -18,6 +18,8 @@ FLAG_STRICT = 0x8
 FLAG_EXT_WORKSPACE = 0x10
 FLAG_STAGE_TIMING = 0x20
 FLAG_NO_FUSION = 0x40
+BATCH_GRAPH = 0x1
+BATCH_EXT_WORKSPACE = 0x2
 
 PREC_FP32 = 0
 PREC_MIXED_BF16X3 = 1
@@ -42,6 +44,16 @@ SIGNATURES = [
     ("pb3_stage_times", C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_int)]),
     ("pb3_stage_timing_reset", C.c_int, [C.c_void_p]),
     ("pb3_stage_name", C.c_char_p, [C.c_int]),
+    ("pb3_batch_create", C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_uint, C.POINTER(C.c_void_p)]),
+    ("pb3_batch_destroy", C.c_int, [C.c_void_p]),
+    ("pb3_batch_workspace_bytes", C.c_size_t, [C.c_void_p]),
+    ("pb3_batch_bind_workspace", C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    ("pb3_batch_run", C.c_int,
+     [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int, C.c_void_p]),
+    ("pb3_batch_launches", C.c_int, [C.c_void_p, C.c_int, C.c_int]),
+    ("pb3_batch_groups", C.c_int, [C.c_void_p]),
+    ("pb3_bispectrum_batched", C.c_int,
+     [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_void_p]),
     ("pb3_status_string", C.c_char_p, [C.c_int]),
     ("pb3_last_error", C.c_char_p, []),
 ]

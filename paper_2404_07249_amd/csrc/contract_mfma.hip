@@ -28,6 +28,7 @@
 #include <hip/hip_runtime.h>
 
 #include "fft_dev.h"
+#include "job.h"
 #include "pb3_internal.h"
 
 namespace pb3 {
@@ -299,8 +300,11 @@ __device__ __forceinline__ void tile_store(TileStage<NQ>& st, const TileRegs<NQ>
 template <int NQ, bool MIXED, int K0, int K1>
 __global__ void __launch_bounds__(kContractThreads) k_contract_mfma(const float* __restrict__ g, long mvox, long vpw,
                                                                     float* __restrict__ part, int part_len,
-                                                                    unsigned sel_lo, unsigned sel_hi) {
+                                                                    unsigned sel_lo, unsigned sel_hi,
+                                                                    size_t wstride) {
   static_assert(kGroups == 4, "group dispatch below assumes four groups");
+  g = job_ptr(g, wstride);
+  part = job_ptr(part, wstride);
   constexpr int T0 = tiles_before(NQ, K0);
   constexpr int T1 = tiles_before(NQ, K1);
   constexpr int NTMAX = max_group_tiles<NQ, K0, K1>();
@@ -359,22 +363,23 @@ __global__ void __launch_bounds__(kContractThreads) k_contract_mfma(const float*
 }
 
 template <int NQ, bool MIXED, int G>
-static hipError_t launch_group(const float* g, long mvox, int n_wg, long vpw, float* part, int part_len,
-                               hipStream_t s) {
+static hipError_t launch_group(const float* g, long mvox, int n_wg, long vpw, float* part, int part_len, int n_jobs,
+                               size_t wstride, hipStream_t s) {
   constexpr int K0 = group_begin(NQ, G), K1 = group_begin(NQ, G + 1);
   // bf16 pairs (element 0 in the low half): (-1, 0) and (0, -1)
   const unsigned sel_lo = 0x0000BF80u, sel_hi = 0xBF800000u;
-  hipLaunchKernelGGL((k_contract_mfma<NQ, MIXED, K0, K1>), dim3(n_wg), dim3(kContractThreads), 0, s, g, mvox, vpw,
-                     part, part_len, sel_lo, sel_hi);
+  hipLaunchKernelGGL((k_contract_mfma<NQ, MIXED, K0, K1>), dim3(n_wg, 1, n_jobs), dim3(kContractThreads), 0, s, g,
+                     mvox, vpw, part, part_len, sel_lo, sel_hi, wstride);
   return hipGetLastError();
 }
 
 template <int NQ, bool MIXED>
-static hipError_t launch_nq(const float* g, long mvox, int n_wg, long vpw, float* part, int part_len, hipStream_t s) {
-  hipError_t e = launch_group<NQ, MIXED, 0>(g, mvox, n_wg, vpw, part, part_len, s);
+static hipError_t launch_nq(const float* g, long mvox, int n_wg, long vpw, float* part, int part_len, int n_jobs,
+                            size_t wstride, hipStream_t s) {
+  hipError_t e = launch_group<NQ, MIXED, 0>(g, mvox, n_wg, vpw, part, part_len, n_jobs, wstride, s);
   if constexpr (n_groups(NQ) > 1) {
-    if (e == hipSuccess) e = launch_group<NQ, MIXED, 1>(g, mvox, n_wg, vpw, part, part_len, s);
-    if (e == hipSuccess) e = launch_group<NQ, MIXED, 2>(g, mvox, n_wg, vpw, part, part_len, s);
+    if (e == hipSuccess) e = launch_group<NQ, MIXED, 1>(g, mvox, n_wg, vpw, part, part_len, n_jobs, wstride, s);
+    if (e == hipSuccess) e = launch_group<NQ, MIXED, 2>(g, mvox, n_wg, vpw, part, part_len, n_jobs, wstride, s);
   }
   return e;
 }
@@ -492,7 +497,9 @@ __global__ void __launch_bounds__(kFusedThreads) k_zcontract(const float2* __res
                                                              const BinGeom* __restrict__ geom, int nb,
                                                              const float2* __restrict__ tw, float scale, long lpw,
                                                              float* __restrict__ part, int part_len, unsigned sel_lo,
-                                                             unsigned sel_hi) {
+                                                             unsigned sel_hi, size_t wstride) {
+  a2 = job_ptr(a2, wstride);
+  part = job_ptr(part, wstride);
   constexpr int K0 = 0, K1 = n_pair_blocks(NQ);
   constexpr int NT = n_tiles(NQ);
   constexpr int NTMAX = max_group_tiles<NQ, K0, K1>();
@@ -560,24 +567,25 @@ __global__ void __launch_bounds__(kFusedThreads) k_zcontract(const float2* __res
 }
 
 template <int NQ, bool MIXED, int M>
-static hipError_t launch_fused_m(const pb3_plan& p, hipStream_t s) {
+static hipError_t launch_fused_m(const pb3_plan& p, const Exec& x, hipStream_t s) {
   const long nlines = (long)M * M;
   const long lpw = (nlines + p.contract_wgs - 1) / p.contract_wgs;
   const unsigned sel_lo = 0x0000BF80u, sel_hi = 0xBF800000u;
   const float scale = (float)(1.0 / ((double)M * M * M));
-  hipLaunchKernelGGL((k_zcontract<NQ, MIXED, M>), dim3(p.contract_wgs), dim3(kFusedThreads), 0, s, p.ws.a2, p.d.geom,
-                     p.nb, p.d.tw_m, scale, lpw, p.ws.part, p.part_len, sel_lo, sel_hi);
+  hipLaunchKernelGGL((k_zcontract<NQ, MIXED, M>), dim3(p.contract_wgs, 1, x.n_jobs), dim3(kFusedThreads), 0, s,
+                     x.ws.a2, p.d.geom, p.nb, p.d.tw_m, scale, lpw, x.ws.part, p.part_len, sel_lo, sel_hi,
+                     x.wstride);
   return hipGetLastError();
 }
 
 template <int NQ, bool MIXED>
-static hipError_t launch_fused_nq(const pb3_plan& p, hipStream_t s) {
+static hipError_t launch_fused_nq(const pb3_plan& p, const Exec& x, hipStream_t s) {
   switch (p.M) {
-    case 32: return launch_fused_m<NQ, MIXED, 32>(p, s);
-    case 64: return launch_fused_m<NQ, MIXED, 64>(p, s);
-    case 96: return launch_fused_m<NQ, MIXED, 96>(p, s);
-    case 128: return launch_fused_m<NQ, MIXED, 128>(p, s);
-    case 192: return launch_fused_m<NQ, MIXED, 192>(p, s);
+    case 32: return launch_fused_m<NQ, MIXED, 32>(p, x, s);
+    case 64: return launch_fused_m<NQ, MIXED, 64>(p, x, s);
+    case 96: return launch_fused_m<NQ, MIXED, 96>(p, x, s);
+    case 128: return launch_fused_m<NQ, MIXED, 128>(p, x, s);
+    case 192: return launch_fused_m<NQ, MIXED, 192>(p, x, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -605,10 +613,10 @@ bool fused_supported(int nq, int m) {
   return nq >= 1 && nq <= 2 && (m == 32 || m == 64 || m == 96 || m == 128 || m == 192);
 }
 
-hipError_t launch_zcontract(const pb3_plan& p, bool mixed, hipStream_t s) {
+hipError_t launch_zcontract(const pb3_plan& p, const Exec& x, bool mixed, hipStream_t s) {
   const int nq = p.nb_pad / 16;
-  if (nq == 1) return mixed ? launch_fused_nq<1, true>(p, s) : launch_fused_nq<1, false>(p, s);
-  if (nq == 2) return mixed ? launch_fused_nq<2, true>(p, s) : launch_fused_nq<2, false>(p, s);
+  if (nq == 1) return mixed ? launch_fused_nq<1, true>(p, x, s) : launch_fused_nq<1, false>(p, x, s);
+  if (nq == 2) return mixed ? launch_fused_nq<2, true>(p, x, s) : launch_fused_nq<2, false>(p, x, s);
   return hipErrorInvalidValue;
 }
 
@@ -671,21 +679,23 @@ int mfma_grid(int nq, int n_cu) {
   return n_cu * per;
 }
 
-hipError_t launch_contract_mfma(const pb3_plan& p, bool mixed, hipStream_t s) {
+hipError_t launch_contract_mfma(const pb3_plan& p, const Exec& x, bool mixed, hipStream_t s) {
   const long mvox = (long)p.M * p.M * p.M;
   const int nq = p.nb_pad / 16;
   const int n_wg = p.contract_wgs;
   long vpw = (mvox + n_wg - 1) / n_wg;
   vpw = (vpw + kTileVox - 1) / kTileVox * kTileVox;
-  float* part = p.ws.part;
-  const int pl = p.part_len;
+  float* part = x.ws.part;
+  const float* g = x.ws.g;
+  const int pl = p.part_len, nj = x.n_jobs;
+  const size_t ws = x.wstride;
   switch (nq) {
-    case 1: return mixed ? launch_nq<1, true>(p.ws.g, mvox, n_wg, vpw, part, pl, s)
-                         : launch_nq<1, false>(p.ws.g, mvox, n_wg, vpw, part, pl, s);
-    case 2: return mixed ? launch_nq<2, true>(p.ws.g, mvox, n_wg, vpw, part, pl, s)
-                         : launch_nq<2, false>(p.ws.g, mvox, n_wg, vpw, part, pl, s);
-    case 3: return mixed ? launch_nq<3, true>(p.ws.g, mvox, n_wg, vpw, part, pl, s)
-                         : launch_nq<3, false>(p.ws.g, mvox, n_wg, vpw, part, pl, s);
+    case 1: return mixed ? launch_nq<1, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, s)
+                         : launch_nq<1, false>(g, mvox, n_wg, vpw, part, pl, nj, ws, s);
+    case 2: return mixed ? launch_nq<2, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, s)
+                         : launch_nq<2, false>(g, mvox, n_wg, vpw, part, pl, nj, ws, s);
+    case 3: return mixed ? launch_nq<3, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, s)
+                         : launch_nq<3, false>(g, mvox, n_wg, vpw, part, pl, nj, ws, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include "fft_dev.h"
+#include "job.h"
 #include "pb3_internal.h"
 
 namespace pb3 {
@@ -39,8 +40,10 @@ template <int N, int CS> struct PairShape {
 
 // ------------------------------------------------------------ forward z
 template <int N>
-__global__ void __launch_bounds__(512) k_fwd_z2(const float* __restrict__ delta, float2* __restrict__ f1, int n_pairs,
-                                                int Kz, const float2* __restrict__ tw) {
+__global__ void __launch_bounds__(512) k_fwd_z2(const JobIO io, float2* __restrict__ f1, size_t wstride,
+                                                int n_pairs, int Kz, const float2* __restrict__ tw) {
+  const float* __restrict__ delta = io.delta[blockIdx.z];
+  f1 = job_ptr(f1, wstride);
   using S = PairShape<N, 8>;
   constexpr int TL = S::TL, TP = S::TP, LS = S::LS;
   __shared__ float2 tws[N];
@@ -78,7 +81,9 @@ __global__ void __launch_bounds__(512) k_fwd_z2(const float* __restrict__ delta,
 template <int N>
 __global__ void __launch_bounds__(512) k_fwd_col2(const float2* __restrict__ in, float2* __restrict__ out, int n_inner,
                                                   long in_outer, long out_outer, int Lo, int Ko,
-                                                  const float2* __restrict__ tw) {
+                                                  const float2* __restrict__ tw, size_t wstride) {
+  in = job_ptr(in, wstride);
+  out = job_ptr(out, wstride);
   using S = ColShape<N, 8>;
   constexpr int TB = S::TB, LS = S::LS;
   __shared__ float2 tws[N];
@@ -110,7 +115,9 @@ template <int M, typename Rl, bool UNIT>
 __global__ void __launch_bounds__(512) k_inv_x2(const float2* __restrict__ dc, typename Cx<Rl>::type* __restrict__ a1,
                                                 const BinGeom* __restrict__ geom, const BinTile* __restrict__ tiles,
                                                 const int8_t* __restrict__ lut, int Kc, int Lc, int Kz,
-                                                const typename Cx<Rl>::type* __restrict__ tw) {
+                                                const typename Cx<Rl>::type* __restrict__ tw, size_t wstride) {
+  dc = job_ptr(dc, wstride);
+  a1 = job_ptr(a1, wstride);
   using C = typename Cx<Rl>::type;
   using S = ColShape<M, (int)sizeof(C)>;
   constexpr int TB = S::TB, LS = S::LS;
@@ -159,7 +166,9 @@ template <int M, typename Rl>
 __global__ void __launch_bounds__(512) k_inv_y2(const typename Cx<Rl>::type* __restrict__ a1,
                                                 typename Cx<Rl>::type* __restrict__ a2,
                                                 const BinGeom* __restrict__ geom, const BinTile* __restrict__ tiles,
-                                                const typename Cx<Rl>::type* __restrict__ tw) {
+                                                const typename Cx<Rl>::type* __restrict__ tw, size_t wstride) {
+  a1 = job_ptr(a1, wstride);
+  a2 = job_ptr(a2, wstride);
   using C = typename Cx<Rl>::type;
   using S = ColShape<M, (int)sizeof(C)>;
   constexpr int TB = S::TB, LS = S::LS;
@@ -197,7 +206,10 @@ __global__ void __launch_bounds__(512) k_inv_y2(const typename Cx<Rl>::type* __r
 template <int M, typename Rl>
 __global__ void __launch_bounds__(512) k_inv_z2(const typename Cx<Rl>::type* __restrict__ a2, Rl* __restrict__ gout,
                                                 const BinGeom* __restrict__ geom, const BinTile* __restrict__ tiles,
-                                                const typename Cx<Rl>::type* __restrict__ tw, Rl scale) {
+                                                const typename Cx<Rl>::type* __restrict__ tw, Rl scale,
+                                                size_t wstride) {
+  a2 = job_ptr(a2, wstride);
+  gout = job_ptr(gout, wstride);
   using C = typename Cx<Rl>::type;
   using S = PairShape<M, (int)sizeof(C)>;
   constexpr int TL = S::TL, TP = S::TP, LS = S::LS;
@@ -274,53 +286,53 @@ int tile_width_z(int M, bool dbl) {
   return 0;
 }
 
-hipError_t launch_fwd_z(const pb3_plan& p, const float* delta, hipStream_t s) {
+hipError_t launch_fwd_z(const pb3_plan& p, const Exec& x, hipStream_t s) {
   const int n_pairs = p.N * p.N / 2;
   PB3_FFT_LEN(p.N, {
     using S = PairShape<LL, 8>;
-    hipLaunchKernelGGL(k_fwd_z2<LL>, dim3((n_pairs + S::TP - 1) / S::TP), dim3(S::NT), 0, s, delta, p.ws.f1, n_pairs,
-                       p.Kz, p.d.tw_n);
+    hipLaunchKernelGGL(k_fwd_z2<LL>, dim3((n_pairs + S::TP - 1) / S::TP, 1, x.n_jobs), dim3(S::NT), 0, s, x.io,
+                       x.ws.f1, x.wstride, n_pairs, p.Kz, p.d.tw_n);
     return hipGetLastError();
   });
   return hipErrorInvalidValue;
 }
 
-static hipError_t fwd_col(const pb3_plan& p, const float2* in, float2* out, int n_inner, long in_outer,
-                          long out_outer, int n_outer, hipStream_t s) {
+static hipError_t fwd_col(const pb3_plan& p, const Exec& x, const float2* in, float2* out, int n_inner,
+                          long in_outer, long out_outer, int n_outer, hipStream_t s) {
   PB3_FFT_LEN(p.N, {
     using S = ColShape<LL, 8>;
-    dim3 grid((n_inner + S::TB - 1) / S::TB, n_outer);
+    dim3 grid((n_inner + S::TB - 1) / S::TB, n_outer, x.n_jobs);
     hipLaunchKernelGGL(k_fwd_col2<LL>, grid, dim3(S::NT), 0, s, in, out, n_inner, in_outer, out_outer, p.Lc, p.Kc,
-                       p.d.tw_n);
+                       p.d.tw_n, x.wstride);
     return hipGetLastError();
   });
   return hipErrorInvalidValue;
 }
-hipError_t launch_fwd_y(const pb3_plan& p, hipStream_t s) {
+hipError_t launch_fwd_y(const pb3_plan& p, const Exec& x, hipStream_t s) {
   // f1[x][y][kz] -> f2[x][kyc][kz]
-  return fwd_col(p, p.ws.f1, p.ws.f2, p.Kz, (long)p.N * p.Kz, (long)p.Lc * p.Kz, p.N, s);
+  return fwd_col(p, x, x.ws.f1, x.ws.f2, p.Kz, (long)p.N * p.Kz, (long)p.Lc * p.Kz, p.N, s);
 }
-hipError_t launch_fwd_x(const pb3_plan& p, hipStream_t s) {
+hipError_t launch_fwd_x(const pb3_plan& p, const Exec& x, hipStream_t s) {
   // f2[x][kyc][kz] -> dc[kxc][kyc][kz]
-  return fwd_col(p, p.ws.f2, p.ws.dc, p.Lc * p.Kz, 0L, 0L, 1, s);
+  return fwd_col(p, x, x.ws.f2, x.ws.dc, p.Lc * p.Kz, 0L, 0L, 1, s);
 }
 
-hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, void* a1, const void* tw, const TileSet& ts,
-                     hipStream_t s) {
+hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, const float2* dc, void* a1, const void* tw,
+                     const TileSet& ts, int n_jobs, size_t wstride, hipStream_t s) {
   if (ts.n == 0) return hipSuccess;
   PB3_FFT_LEN(p.M, {
     if (dbl) {
       using S = ColShape<LL, 16>;
       if (unit)
-        hipLaunchKernelGGL((k_inv_x2<LL, double, true>), dim3(ts.n), dim3(S::NT), 0, s, p.ws.dc, (double2*)a1,
-                           p.d.geom, ts.d, p.d.lut, p.Kc, p.Lc, p.Kz, (const double2*)tw);
+        hipLaunchKernelGGL((k_inv_x2<LL, double, true>), dim3(ts.n, 1, n_jobs), dim3(S::NT), 0, s, dc,
+                           (double2*)a1, p.d.geom, ts.d, p.d.lut, p.Kc, p.Lc, p.Kz, (const double2*)tw, wstride);
       else
         return hipErrorInvalidValue;
     } else {
       using S = ColShape<LL, 8>;
       if (unit) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((k_inv_x2<LL, float, false>), dim3(ts.n), dim3(S::NT), 0, s, p.ws.dc, (float2*)a1, p.d.geom,
-                         ts.d, p.d.lut, p.Kc, p.Lc, p.Kz, (const float2*)tw);
+      hipLaunchKernelGGL((k_inv_x2<LL, float, false>), dim3(ts.n, 1, n_jobs), dim3(S::NT), 0, s, dc, (float2*)a1,
+                         p.d.geom, ts.d, p.d.lut, p.Kc, p.Lc, p.Kz, (const float2*)tw, wstride);
     }
     return hipGetLastError();
   });
@@ -328,17 +340,17 @@ hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, void* a1, const voi
 }
 
 hipError_t run_inv_y(const pb3_plan& p, bool dbl, const void* a1, void* a2, const void* tw, const TileSet& ts,
-                     hipStream_t s) {
+                     int n_jobs, size_t wstride, hipStream_t s) {
   if (ts.n == 0) return hipSuccess;
   PB3_FFT_LEN(p.M, {
     if (dbl) {
       using S = ColShape<LL, 16>;
-      hipLaunchKernelGGL((k_inv_y2<LL, double>), dim3(ts.n), dim3(S::NT), 0, s, (const double2*)a1, (double2*)a2,
-                         p.d.geom, ts.d, (const double2*)tw);
+      hipLaunchKernelGGL((k_inv_y2<LL, double>), dim3(ts.n, 1, n_jobs), dim3(S::NT), 0, s, (const double2*)a1,
+                         (double2*)a2, p.d.geom, ts.d, (const double2*)tw, wstride);
     } else {
       using S = ColShape<LL, 8>;
-      hipLaunchKernelGGL((k_inv_y2<LL, float>), dim3(ts.n), dim3(S::NT), 0, s, (const float2*)a1, (float2*)a2,
-                         p.d.geom, ts.d, (const float2*)tw);
+      hipLaunchKernelGGL((k_inv_y2<LL, float>), dim3(ts.n, 1, n_jobs), dim3(S::NT), 0, s, (const float2*)a1,
+                         (float2*)a2, p.d.geom, ts.d, (const float2*)tw, wstride);
     }
     return hipGetLastError();
   });
@@ -346,34 +358,34 @@ hipError_t run_inv_y(const pb3_plan& p, bool dbl, const void* a1, void* a2, cons
 }
 
 hipError_t run_inv_z(const pb3_plan& p, bool dbl, const void* a2, void* gout, const void* tw, const TileSet& ts,
-                     hipStream_t s) {
+                     int n_jobs, size_t wstride, hipStream_t s) {
   if (ts.n == 0) return hipSuccess;
   const double sc = 1.0 / ((double)p.M * p.M * p.M);
   PB3_FFT_LEN(p.M, {
     if (dbl) {
       using S = PairShape<LL, 16>;
       if (ts.tb != 2 * S::TP) return hipErrorInvalidConfiguration;
-      hipLaunchKernelGGL((k_inv_z2<LL, double>), dim3(ts.n), dim3(S::NT), 0, s, (const double2*)a2, (double*)gout,
-                         p.d.geom, ts.d, (const double2*)tw, sc);
+      hipLaunchKernelGGL((k_inv_z2<LL, double>), dim3(ts.n, 1, n_jobs), dim3(S::NT), 0, s, (const double2*)a2,
+                         (double*)gout, p.d.geom, ts.d, (const double2*)tw, sc, wstride);
     } else {
       using S = PairShape<LL, 8>;
       if (ts.tb != 2 * S::TP) return hipErrorInvalidConfiguration;
-      hipLaunchKernelGGL((k_inv_z2<LL, float>), dim3(ts.n), dim3(S::NT), 0, s, (const float2*)a2, (float*)gout,
-                         p.d.geom, ts.d, (const float2*)tw, (float)sc);
+      hipLaunchKernelGGL((k_inv_z2<LL, float>), dim3(ts.n, 1, n_jobs), dim3(S::NT), 0, s, (const float2*)a2,
+                         (float*)gout, p.d.geom, ts.d, (const float2*)tw, (float)sc, wstride);
     }
     return hipGetLastError();
   });
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_inv_x(const pb3_plan& p, hipStream_t s) {
-  return run_inv_x(p, false, false, p.ws.a1, p.d.tw_m, p.tx, s);
+hipError_t launch_inv_x(const pb3_plan& p, const Exec& x, hipStream_t s) {
+  return run_inv_x(p, false, false, x.ws.dc, x.ws.a1, p.d.tw_m, p.tx, x.n_jobs, x.wstride, s);
 }
-hipError_t launch_inv_y(const pb3_plan& p, hipStream_t s) {
-  return run_inv_y(p, false, p.ws.a1, p.ws.a2, p.d.tw_m, p.ty, s);
+hipError_t launch_inv_y(const pb3_plan& p, const Exec& x, hipStream_t s) {
+  return run_inv_y(p, false, x.ws.a1, x.ws.a2, p.d.tw_m, p.ty, x.n_jobs, x.wstride, s);
 }
-hipError_t launch_inv_z(const pb3_plan& p, hipStream_t s) {
-  return run_inv_z(p, false, p.ws.a2, p.ws.g, p.d.tw_m, p.tz, s);
+hipError_t launch_inv_z(const pb3_plan& p, const Exec& x, hipStream_t s) {
+  return run_inv_z(p, false, x.ws.a2, x.ws.g, p.d.tw_m, p.tz, x.n_jobs, x.wstride, s);
 }
 
 }  // namespace pb3

@@ -317,7 +317,7 @@ static pb3_status build_host(pb3_plan* p, const int grid[3], const double box[3]
   return PB3_OK;
 }
 
-static size_t workspace_bytes(const pb3_plan* p) {
+size_t workspace_bytes(const pb3_plan* p) {
   size_t b = 0;
   const size_t A = 256;
   b += align_up(sizeof(float2) * (size_t)p->N * p->N * p->Kz, A);
@@ -332,11 +332,11 @@ static size_t workspace_bytes(const pb3_plan* p) {
   return b;
 }
 
-static void carve_workspace(pb3_plan* p, void* base, size_t bytes, bool owned) {
-  Workspace& w = p->ws;
+Workspace carve(const pb3_plan* p, void* base, size_t bytes) {
+  Workspace w;
   w.base = base;
   w.bytes = bytes;
-  w.owned = owned;
+  w.owned = false;
   char* c = (char*)base;
   const size_t A = 256;
   auto take = [&](size_t n) {
@@ -353,17 +353,24 @@ static void carve_workspace(pb3_plan* p, void* base, size_t bytes, bool owned) {
   w.part = (float*)take(sizeof(float) * (size_t)p->contract_wgs * p->part_len);
   w.ppart = (double*)take(sizeof(double) * (size_t)std::max(p->n_chunks, 1));
   w.rsl = (double*)take(sizeof(double) * (size_t)kReduceSlices * p->part_len);
+  return w;
+}
+
+static void carve_workspace(pb3_plan* p, void* base, size_t bytes, bool owned) {
+  p->ws = carve(p, base, bytes);
+  p->ws.owned = owned;
 }
 
 // The contraction reads the bins [nb, nb_pad) of G as zero fields.
-static pb3_status clear_padding(pb3_plan* p) {
+pb3_status clear_padding(const pb3_plan* p, const Workspace& w) {
   size_t m3 = (size_t)p->M * p->M * p->M;
-  if (p->ws.g && p->nb_pad > p->nb) {
-    hipError_t e = hipMemset(p->ws.g + (size_t)p->nb * m3, 0, sizeof(float) * (size_t)(p->nb_pad - p->nb) * m3);
+  if (w.g && p->nb_pad > p->nb) {
+    hipError_t e = hipMemset(w.g + (size_t)p->nb * m3, 0, sizeof(float) * (size_t)(p->nb_pad - p->nb) * m3);
     if (e != hipSuccess) return hip_fail(e, "hipMemset");
   }
   return PB3_OK;
 }
+static pb3_status clear_padding(pb3_plan* p) { return clear_padding(p, p->ws); }
 
 static pb3_status ensure_workspace(pb3_plan* p) {
   if (p->ws.base) return PB3_OK;
@@ -504,6 +511,61 @@ static pb3_status check_ready(pb3_plan* p) {
   return ensure_workspace(p);
 }
 
+// The launch sequence of one plan over the jobs of x (all stages on
+// stream s).  wrap(stage, name, fn) runs fn, optionally timed.
+template <typename W>
+static pb3_status enqueue_w(const pb3_plan& p, const Exec& x, bool do_pk, bool do_bk, pb3_precision prec,
+                            hipStream_t s, W&& wrap) {
+  pb3_status st;
+  if ((st = wrap(ST_FWD_Z, "fwd_z", [&] { return launch_fwd_z(p, x, s); })) != PB3_OK) return st;
+  if ((st = wrap(ST_FWD_Y, "fwd_y", [&] { return launch_fwd_y(p, x, s); })) != PB3_OK) return st;
+  if ((st = wrap(ST_FWD_X, "fwd_x", [&] { return launch_fwd_x(p, x, s); })) != PB3_OK) return st;
+  if (do_pk) {
+    if ((st = wrap(ST_POWER, "power", [&] { return launch_power(p, x, s); })) != PB3_OK) return st;
+  }
+  if (do_bk) {
+    if ((st = wrap(ST_INV_X, "inv_x", [&] { return launch_inv_x(p, x, s); })) != PB3_OK) return st;
+    if ((st = wrap(ST_INV_Y, "inv_y", [&] { return launch_inv_y(p, x, s); })) != PB3_OK) return st;
+    if (p.fused) {
+      if ((st = wrap(ST_CONTRACT, "contract",
+                     [&] { return launch_zcontract(p, x, prec == PB3_MIXED_BF16X3, s); })) != PB3_OK)
+        return st;
+    } else {
+      if ((st = wrap(ST_INV_Z, "inv_z", [&] { return launch_inv_z(p, x, s); })) != PB3_OK) return st;
+      if ((st = wrap(ST_CONTRACT, "contract", [&] { return launch_contract(p, x, prec, s); })) != PB3_OK) return st;
+    }
+    if ((st = wrap(ST_REDUCE, "reduce", [&] { return launch_reduce(p, x, s); })) != PB3_OK) return st;
+  }
+  return PB3_OK;
+}
+
+pb3_status enqueue(const pb3_plan& p, const Exec& x, bool do_pk, bool do_bk, pb3_precision prec, hipStream_t s) {
+  return enqueue_w(p, x, do_pk, do_bk, prec, s, [](int, const char* name, auto&& fn) -> pb3_status {
+    hipError_t e = fn();
+    return e == hipSuccess ? PB3_OK : hip_fail(e, name);
+  });
+}
+
+// kernel launches of one enqueue (for reporting)
+int launches_per_sequence(const pb3_plan& p, bool do_pk, bool do_bk) {
+  int n = 3;
+  if (do_pk) n += 2;
+  if (do_bk) {
+    n += 2 + 2;
+    if (p.fused) n += 1;
+    else n += 1 + ((p.nb_pad / 16) >= 2 ? 3 : 1);
+  }
+  return n;
+}
+
+pb3_status check_prec(pb3_precision prec) {
+  if (prec != PB3_FP32 && prec != PB3_MIXED_BF16X3) {
+    set_error("unknown precision");
+    return PB3_EINVAL;
+  }
+  return PB3_OK;
+}
+
 static pb3_status run(pb3_plan* p, const float* delta, double* pk, double* bk, pb3_precision prec, hipStream_t s) {
   pb3_status st = check_ready(p);
   if (st != PB3_OK) return st;
@@ -511,36 +573,20 @@ static pb3_status run(pb3_plan* p, const float* delta, double* pk, double* bk, p
     set_error("null device pointer");
     return PB3_EINVAL;
   }
-  if (prec != PB3_FP32 && prec != PB3_MIXED_BF16X3) {
-    set_error("unknown precision");
-    return PB3_EINVAL;
-  }
+  if ((st = check_prec(prec)) != PB3_OK) return st;
   if (!p->ev.empty()) {
     size_t slot = (size_t)(p->n_calls % pb3_plan::kTimingRing) * ST_COUNT;
     std::fill(p->ev_used.begin() + slot, p->ev_used.begin() + slot + ST_COUNT, 0);
   }
   p->last_stream = s;
-  if ((st = stage(p, ST_FWD_Z, s, "fwd_z", [&] { return launch_fwd_z(*p, delta, s); })) != PB3_OK) return st;
-  if ((st = stage(p, ST_FWD_Y, s, "fwd_y", [&] { return launch_fwd_y(*p, s); })) != PB3_OK) return st;
-  if ((st = stage(p, ST_FWD_X, s, "fwd_x", [&] { return launch_fwd_x(*p, s); })) != PB3_OK) return st;
-  if (pk) {
-    if ((st = stage(p, ST_POWER, s, "power", [&] { return launch_power(*p, pk, s); })) != PB3_OK) return st;
-  }
-  if (bk) {
-    if ((st = stage(p, ST_INV_X, s, "inv_x", [&] { return launch_inv_x(*p, s); })) != PB3_OK) return st;
-    if ((st = stage(p, ST_INV_Y, s, "inv_y", [&] { return launch_inv_y(*p, s); })) != PB3_OK) return st;
-    if (p->fused) {
-      if ((st = stage(p, ST_CONTRACT, s, "contract", [&] {
-             return launch_zcontract(*p, prec == PB3_MIXED_BF16X3, s);
-           })) != PB3_OK)
-        return st;
-    } else {
-      if ((st = stage(p, ST_INV_Z, s, "inv_z", [&] { return launch_inv_z(*p, s); })) != PB3_OK) return st;
-      if ((st = stage(p, ST_CONTRACT, s, "contract", [&] { return launch_contract(*p, prec, s); })) != PB3_OK)
-        return st;
-    }
-    if ((st = stage(p, ST_REDUCE, s, "reduce", [&] { return launch_reduce(*p, prec, bk, s); })) != PB3_OK) return st;
-  }
+  Exec x;
+  x.ws = p->ws;
+  x.io.delta[0] = delta;
+  x.io.pk[0] = pk;
+  x.io.bk[0] = bk;
+  st = enqueue_w(*p, x, pk != nullptr, bk != nullptr, prec, s,
+                 [&](int id, const char* name, auto&& fn) { return stage(p, id, s, name, fn); });
+  if (st != PB3_OK) return st;
   p->last_prec = prec;
   ++p->n_calls;
   return PB3_OK;

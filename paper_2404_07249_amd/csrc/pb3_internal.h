@@ -53,6 +53,16 @@ struct TileSet {
   int tb;
 };
 
+// Jobs of one plan launched together (grid z = job index, at most kMaxJobs):
+// their inputs and outputs by value, and the byte stride between their
+// workspaces.  A single call is one job with stride 0.
+constexpr int kMaxJobs = 8;
+struct JobIO {
+  const float* delta[kMaxJobs];
+  double* pk[kMaxJobs];
+  double* bk[kMaxJobs];
+};
+
 struct DeviceTables {
   int8_t* lut = nullptr;          // bin of |n|^2 (int8, -1 outside), size lut_len
   int32_t* modes = nullptr;       // compact D index of every binned half-spectrum mode (bit 31: weight 1)
@@ -82,6 +92,15 @@ struct Workspace {
   float* part = nullptr;    // contraction partials [work-group][tile*256]
   double* rsl = nullptr;    // reduction slices [kReduceSlices][tile*256]
   double* ppart = nullptr;  // power partials
+};
+
+// Execution context of one launch sequence: job 0's workspace, the stride
+// to the next job's, the number of jobs and their I/O.
+struct Exec {
+  Workspace ws;
+  size_t wstride = 0;
+  int n_jobs = 1;
+  JobIO io{};
 };
 
 }  // namespace pb3
@@ -137,16 +156,25 @@ namespace pb3 {
 void set_error(const std::string& msg);
 pb3_status hip_fail(hipError_t e, const char* what);
 
+// plan workspace (pb3_host.cpp): size, layout at base, zero padding bins
+size_t workspace_bytes(const pb3_plan* p);
+Workspace carve(const pb3_plan* p, void* base, size_t bytes);
+pb3_status clear_padding(const pb3_plan* p, const Workspace& w);
+pb3_status check_prec(pb3_precision prec);
+// the whole launch sequence of one plan for the jobs of x, on stream s
+pb3_status enqueue(const pb3_plan& p, const Exec& x, bool do_pk, bool do_bk, pb3_precision prec, hipStream_t s);
+int launches_per_sequence(const pb3_plan& p, bool do_pk, bool do_bk);
+
 // kernel launchers (pb3_kernels.hip); all return hipGetLastError()
-hipError_t launch_fwd_z(const pb3_plan& p, const float* delta, hipStream_t s);
-hipError_t launch_fwd_y(const pb3_plan& p, hipStream_t s);
-hipError_t launch_fwd_x(const pb3_plan& p, hipStream_t s);
-hipError_t launch_power(const pb3_plan& p, double* pk, hipStream_t s);
-hipError_t launch_inv_x(const pb3_plan& p, hipStream_t s);
-hipError_t launch_inv_y(const pb3_plan& p, hipStream_t s);
-hipError_t launch_inv_z(const pb3_plan& p, hipStream_t s);
-hipError_t launch_contract(const pb3_plan& p, pb3_precision prec, hipStream_t s);
-hipError_t launch_reduce(const pb3_plan& p, pb3_precision prec, double* bk, hipStream_t s);
+hipError_t launch_fwd_z(const pb3_plan& p, const Exec& x, hipStream_t s);
+hipError_t launch_fwd_y(const pb3_plan& p, const Exec& x, hipStream_t s);
+hipError_t launch_fwd_x(const pb3_plan& p, const Exec& x, hipStream_t s);
+hipError_t launch_power(const pb3_plan& p, const Exec& x, hipStream_t s);
+hipError_t launch_inv_x(const pb3_plan& p, const Exec& x, hipStream_t s);
+hipError_t launch_inv_y(const pb3_plan& p, const Exec& x, hipStream_t s);
+hipError_t launch_inv_z(const pb3_plan& p, const Exec& x, hipStream_t s);
+hipError_t launch_contract(const pb3_plan& p, const Exec& x, pb3_precision prec, hipStream_t s);
+hipError_t launch_reduce(const pb3_plan& p, const Exec& x, hipStream_t s);
 // FP64 triangle counts on the contraction grid: writes raw M^6 sum HHH for
 // every candidate triplet into counts_out (host), using temporary memory.
 pb3_status compute_counts_fp64(pb3_plan& p, std::vector<double>& counts_out);
@@ -154,20 +182,21 @@ pb3_status compute_counts_fp64(pb3_plan& p, std::vector<double>& counts_out);
 // partial-vector index of triplet (a, b, c) (-1 if not produced), launch
 int mfma_tiles(int nq);
 int mfma_locate(int nq, int a, int b, int c);
-hipError_t launch_contract_mfma(const pb3_plan& p, bool mixed, hipStream_t s);
+hipError_t launch_contract_mfma(const pb3_plan& p, const Exec& x, bool mixed, hipStream_t s);
 int mfma_grid(int nq, int n_cu);
 // fused inverse z pass + contraction (contract_mfma.hip)
 bool fused_supported(int nq, int m);
 int fused_grid(int nq, int m, int n_cu);
-hipError_t launch_zcontract(const pb3_plan& p, bool mixed, hipStream_t s);
+hipError_t launch_zcontract(const pb3_plan& p, const Exec& x, bool mixed, hipStream_t s);
 // inverse passes (fft_passes.hip) on FP32 (dbl = false) or FP64 lines;
-// unit = the shell indicator instead of Theta_b D (count pass, FP64 only)
-hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, void* a1, const void* tw, const TileSet& ts,
-                     hipStream_t s);
+// unit = the shell indicator instead of Theta_b D (count pass, FP64 only);
+// n_jobs jobs whose buffers are wstride bytes apart
+hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, const float2* dc, void* a1, const void* tw,
+                     const TileSet& ts, int n_jobs, size_t wstride, hipStream_t s);
 hipError_t run_inv_y(const pb3_plan& p, bool dbl, const void* a1, void* a2, const void* tw, const TileSet& ts,
-                     hipStream_t s);
+                     int n_jobs, size_t wstride, hipStream_t s);
 hipError_t run_inv_z(const pb3_plan& p, bool dbl, const void* a2, void* gout, const void* tw, const TileSet& ts,
-                     hipStream_t s);
+                     int n_jobs, size_t wstride, hipStream_t s);
 // tile widths of the inverse passes for FP32 (dbl = false) or FP64 lines
 int tile_width_x(int M, bool dbl);
 int tile_width_z(int M, bool dbl);

@@ -16,6 +16,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "job.h"
 #include "pb3_internal.h"
 
 namespace pb3 {
@@ -25,7 +26,10 @@ namespace pb3 {
 // FP64 (w = 2 for modes whose conjugate partner is not stored, bit 31 of
 // the index marks w = 1), then reduces with a fixed tree.
 __global__ void __launch_bounds__(256) k_power_chunks(const float2* __restrict__ dc, const int32_t* __restrict__ modes,
-                                                      const int32_t* __restrict__ chunks, double* __restrict__ part) {
+                                                      const int32_t* __restrict__ chunks, double* __restrict__ part,
+                                                      size_t wstride) {
+  dc = job_ptr(dc, wstride);
+  part = job_ptr(part, wstride);
   __shared__ double red[256];
   const int c = blockIdx.x;
   const int start = chunks[3 * c + 1], end = chunks[3 * c + 2];
@@ -47,7 +51,9 @@ __global__ void __launch_bounds__(256) k_power_chunks(const float2* __restrict__
 }
 
 __global__ void k_power_final(const double* __restrict__ part, const int32_t* __restrict__ chunk_first, int nb,
-                              const double* __restrict__ scale, double* __restrict__ pk) {
+                              const double* __restrict__ scale, const JobIO io, size_t wstride) {
+  part = job_ptr(part, wstride);
+  double* __restrict__ pk = io.pk[blockIdx.z];
   int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb) return;
   double s = 0.0;
@@ -130,7 +136,10 @@ __global__ void k_reduce(const Rl* __restrict__ part, int n_wg, int part_len, co
 
 // Two-stage form for the MFMA partials: slice s of the work-groups is
 // summed per element (FP64), then the slices per kept triplet.
-__global__ void k_reduce_slices(const float* __restrict__ part, int n_wg, int part_len, double* __restrict__ rsl) {
+__global__ void k_reduce_slices(const float* __restrict__ part, int n_wg, int part_len, double* __restrict__ rsl,
+                                size_t wstride) {
+  part = job_ptr(part, wstride);
+  rsl = job_ptr(rsl, wstride);
   int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= part_len) return;
   int s = blockIdx.y;
@@ -141,7 +150,9 @@ __global__ void k_reduce_slices(const float* __restrict__ part, int n_wg, int pa
 }
 
 __global__ void k_reduce_final(const double* __restrict__ rsl, int part_len, const int32_t* __restrict__ map,
-                               const double* __restrict__ fac, int n_out, double* __restrict__ out) {
+                               const double* __restrict__ fac, int n_out, const JobIO io, size_t wstride) {
+  rsl = job_ptr(rsl, wstride);
+  double* __restrict__ out = io.bk[blockIdx.z];
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_out) return;
   int idx = map[t];
@@ -153,12 +164,13 @@ __global__ void k_reduce_final(const double* __restrict__ rsl, int part_len, con
 
 // ================================================================ launchers
 
-hipError_t launch_power(const pb3_plan& p, double* pk, hipStream_t s) {
-  hipLaunchKernelGGL(k_power_chunks, dim3(p.n_chunks), dim3(256), 0, s, p.ws.dc, p.d.modes, p.d.chunk, p.ws.ppart);
+hipError_t launch_power(const pb3_plan& p, const Exec& x, hipStream_t s) {
+  hipLaunchKernelGGL(k_power_chunks, dim3(p.n_chunks, 1, x.n_jobs), dim3(256), 0, s, x.ws.dc, p.d.modes, p.d.chunk,
+                     x.ws.ppart, x.wstride);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_power_final, dim3((p.nb + 63) / 64), dim3(64), 0, s, p.ws.ppart, p.d.chunk_first, p.nb,
-                     p.d.pk_scale, pk);
+  hipLaunchKernelGGL(k_power_final, dim3((p.nb + 63) / 64, 1, x.n_jobs), dim3(64), 0, s, x.ws.ppart,
+                     p.d.chunk_first, p.nb, p.d.pk_scale, x.io, x.wstride);
   return hipGetLastError();
 }
 
@@ -197,20 +209,19 @@ static hipError_t contract_simple(const Rl* g, int nb, long mvox, const int32_t*
   return hipGetLastError();
 }
 
-hipError_t launch_contract(const pb3_plan& p, pb3_precision prec, hipStream_t s) {
-  return launch_contract_mfma(p, prec == PB3_MIXED_BF16X3, s);
+hipError_t launch_contract(const pb3_plan& p, const Exec& x, pb3_precision prec, hipStream_t s) {
+  return launch_contract_mfma(p, x, prec == PB3_MIXED_BF16X3, s);
 }
 
-hipError_t launch_reduce(const pb3_plan& p, pb3_precision prec, double* bk, hipStream_t s) {
-  (void)prec;
+hipError_t launch_reduce(const pb3_plan& p, const Exec& x, hipStream_t s) {
   int n_out = (int)(p.trip.size() / 3);
   if (n_out == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce_slices, dim3((p.part_len + 255) / 256, kReduceSlices), dim3(256), 0, s, p.ws.part,
-                     p.contract_wgs, p.part_len, p.ws.rsl);
+  hipLaunchKernelGGL(k_reduce_slices, dim3((p.part_len + 255) / 256, kReduceSlices, x.n_jobs), dim3(256), 0, s,
+                     x.ws.part, p.contract_wgs, p.part_len, x.ws.rsl, x.wstride);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce_final, dim3((n_out + 255) / 256), dim3(256), 0, s, p.ws.rsl, p.part_len, p.d.out_map,
-                     p.d.inv_counts, n_out, bk);
+  hipLaunchKernelGGL(k_reduce_final, dim3((n_out + 255) / 256, 1, x.n_jobs), dim3(256), 0, s, x.ws.rsl, p.part_len,
+                     p.d.out_map, p.d.inv_counts, n_out, x.io, x.wstride);
   return hipGetLastError();
 }
 
@@ -274,11 +285,11 @@ pb3_status compute_counts_fp64(pb3_plan& p, std::vector<double>& counts_out) {
     tsz = TileSet{tiles + vx.size() + vy.size(), (int)vz.size(), tbz};
   }
   {
-    hipError_t r = run_inv_x(p, true, true, a1, p.d.tw_m_d, tsx, nullptr);
+    hipError_t r = run_inv_x(p, true, true, nullptr, a1, p.d.tw_m_d, tsx, 1, 0, nullptr);
     if (r != hipSuccess) { st = hip_fail(r, "count inverse x pass"); goto done; }
-    r = run_inv_y(p, true, a1, a2, p.d.tw_m_d, tsy, nullptr);
+    r = run_inv_y(p, true, a1, a2, p.d.tw_m_d, tsy, 1, 0, nullptr);
     if (r != hipSuccess) { st = hip_fail(r, "count inverse y pass"); goto done; }
-    r = run_inv_z(p, true, a2, h, p.d.tw_m_d, tsz, nullptr);
+    r = run_inv_z(p, true, a2, h, p.d.tw_m_d, tsz, 1, 0, nullptr);
     if (r != hipSuccess) { st = hip_fail(r, "count inverse z pass"); goto done; }
     r = contract_simple<double>(h, p.nb, mvox, p.d.trip_all, n_cand, nwg, part, nullptr);
     if (r != hipSuccess) { st = hip_fail(r, "count contraction"); goto done; }

@@ -30,6 +30,7 @@ __all__ = [
     "kf_edges",
     "field_for",
     "CONFIGS",
+    "batch_jobs",
 ]
 
 
@@ -90,3 +91,20 @@ def field_for(name: str, seed: int | None = None) -> tuple[np.ndarray, dict]:
     d = quadratic_field(cfg["n"], cfg["box"], cfg["fnl"], cfg["seed"]).astype(np.float32)
     cfg["edges"] = kf_edges(cfg["n_bins"])
     return d, cfg
+
+
+def batch_jobs(n_jobs: int = 64, grids=(64, 96, 128), box: float = 2000.0, fnl: float = 1.0,
+               seed0: int = 1000, with_fields: bool = True):
+    """The batched workload: job i has grid grids[i mod 3], 16 + (i mod 9)
+    bins of width 2 k_f from k_f (bins fixed in k_f units, so one box side
+    serves every grid), seed seed0 + i.  Returns a list of dicts (n, box,
+    edges, seed, and the float32 field when ``with_fields``)."""
+    jobs = []
+    for i in range(n_jobs):
+        n = grids[i % len(grids)]
+        job = dict(n=n, box=box, n_bins=16 + (i % 9), fnl=fnl, seed=seed0 + i)
+        job["edges"] = kf_edges(job["n_bins"])
+        if with_fields:
+            job["field"] = quadratic_field(n, box, fnl, job["seed"]).astype(np.float32)
+        jobs.append(job)
+    return jobs

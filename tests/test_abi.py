@@ -121,3 +121,21 @@ def test_host_only_plan_refuses_compute():
     assert st == 1
     with pytest.raises(pb3.Pb3Error):
         p.norm()
+
+
+def test_batch_rejects_host_only_and_empty():
+    """Batch argument checks that need no device: an empty job list and a
+    host-only plan are EINVAL."""
+    import paper_2404_07249_amd as pb3
+    from paper_2404_07249_amd import _lib
+
+    lib = _lib.load()
+    h = C.c_void_p()
+    assert lib.pb3_batch_create(None, 0, 0, C.byref(h)) == 1
+    p = _plan(32, 100.0, kf_edges(4))
+    arr = (C.c_void_p * 2)(p._h.value, p._h.value)
+    assert lib.pb3_batch_create(arr, 2, 0, C.byref(h)) == 1
+    assert not h.value
+    assert lib.pb3_batch_create(arr, 2, 0x80, C.byref(h)) == 1  # unknown flag
+    with pytest.raises(pb3.Pb3Error):
+        pb3.Batch([p])
