@@ -120,6 +120,18 @@ pb3_status pb3_bispectrum(pb3_plan* plan, const float* delta_dev, double* bk_dev
 pb3_status pb3_polyspectra(pb3_plan* plan, const float* delta_dev, double* pk_dev, double* bk_dev,
                            pb3_precision prec, void* stream);
 
+/* Conventional windowed normalisation for masked data d = w * delta
+ * (the FKP-limit estimators of Sec. III.D.2 and Sec. IV.D.2 with the
+ * linear and noise terms dropped): divides the plan's P by <w^2> and B by
+ * <w^3> in place, the means taken over the N^3 voxels in FP64 with a fixed
+ * summation order.  w_dev: N^3 float32 window (device); pk_dev / bk_dev:
+ * outputs of pb3_polyspectra for d (either may be NULL, not both);
+ * scratch_dev: PB3_WINDOW_SCRATCH doubles of device memory, whose first two
+ * entries receive <w^2> and <w^3>.  Enqueued on `stream`. */
+#define PB3_WINDOW_SCRATCH 514
+pb3_status pb3_window_normalize(const pb3_plan* plan, const float* w_dev, double* pk_dev, double* bk_dev,
+                                double* scratch_dev, void* stream);
+
 /* Stage timing (plans made with PB3_FLAG_STAGE_TIMING): every call records
  * a HIP event pair around each kernel launch on the call's stream.
  * pb3_stage_times writes, per stage, the mean milliseconds over the calls

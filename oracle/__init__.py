@@ -14,6 +14,8 @@ Parity status of each function (what pins it is in ``tests/test_oracle.py``):
 * ``bispectrum``           pinned: brute-force k-triplet sums, plane-wave
                            closed form, invariances, Gaussian null and the
                            tree-level bispectrum of a quadratic field.
+* ``windowed_polyspectra`` pinned: unbiased means for a field with local
+                           2- and 3-point functions under random windows.
 """
 
 from .polyspec import (  # noqa: F401
@@ -28,6 +30,8 @@ from .polyspec import (  # noqa: F401
     kmag2,
     max_component,
     mode_counts,
+    window_moments,
+    windowed_polyspectra,
     power_spectrum,
     triangle_counts,
     triangle_triplets,

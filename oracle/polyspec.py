@@ -300,3 +300,22 @@ def max_component(edges) -> int:
     if k * k >= e_top * e_top:
         k -= 1
     return max(k, 0)
+
+
+# ------------------------------------------------------------------ masked
+def window_moments(w: np.ndarray) -> tuple[float, float]:
+    """Means of w^2 and w^3 over the grid (float64)."""
+    w = np.asarray(w, dtype=np.float64)
+    return float(np.mean(w * w)), float(np.mean(w * w * w))
+
+
+def windowed_polyspectra(data: np.ndarray, w: np.ndarray, box: float, edges):
+    """Conventional windowed estimators for masked data d = w * delta: the
+    box estimators of d divided by <w^2> (power) and <w^3> (bispectrum).
+    These are the FKP-limit forms of Sec. III.D.2 (normalisation by the
+    integral of n^2) and Sec. IV.D.2 (by the integral of n^3), with uniform
+    weights and the linear and noise terms dropped.  Returns
+    (P, B, (<w^2>, <w^3>), Result of the unnormalised box estimator)."""
+    res = bispectrum(np.asarray(data, dtype=np.float64), box, edges)
+    m2, m3 = window_moments(w)
+    return res.pk / m2, res.bk / m3, (m2, m3), res

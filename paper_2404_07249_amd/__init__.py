@@ -184,6 +184,24 @@ class Plan:
         )
         return pk, bk
 
+    def window_normalize(self, window, pk=None, bk=None, scratch=None, stream=None):
+        """Divide P by <w^2> and B by <w^3> in place (masked data d = w delta);
+        returns (<w^2>, <w^3>) as a float64 CUDA tensor of two entries."""
+        import torch
+
+        self._check_field(window)
+        if pk is None and bk is None:
+            raise ValueError("nothing to normalise")
+        if scratch is None:
+            scratch = torch.empty(_lib.WINDOW_SCRATCH, dtype=torch.float64, device=window.device)
+        elif scratch.dtype != torch.float64 or scratch.numel() < _lib.WINDOW_SCRATCH:
+            raise ValueError("scratch must hold PB3_WINDOW_SCRATCH float64 values")
+        _lib.check(self._lib.pb3_window_normalize(
+            self._h, C.c_void_p(window.data_ptr()), C.c_void_p(pk.data_ptr() if pk is not None else 0),
+            C.c_void_p(bk.data_ptr() if bk is not None else 0), C.c_void_p(scratch.data_ptr()),
+            _stream_handle(stream)))
+        return scratch[:2]
+
     def stage_times(self) -> dict:
         """Mean milliseconds per kernel stage over the calls since the last
         reset (plans made with ``stage_timing=True``): {stage: (ms, calls)}."""

@@ -19,6 +19,7 @@ FLAG_EXT_WORKSPACE = 0x10
 FLAG_STAGE_TIMING = 0x20
 FLAG_NO_FUSION = 0x40
 BATCH_GRAPH = 0x1
+WINDOW_SCRATCH = 514
 BATCH_EXT_WORKSPACE = 0x2
 
 PREC_FP32 = 0
@@ -41,6 +42,7 @@ SIGNATURES = [
     ("pb3_power", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("pb3_bispectrum", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     ("pb3_polyspectra", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
+    ("pb3_window_normalize", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("pb3_stage_times", C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_int)]),
     ("pb3_stage_timing_reset", C.c_int, [C.c_void_p]),
     ("pb3_stage_name", C.c_char_p, [C.c_int]),

@@ -709,6 +709,22 @@ pb3_status pb3_polyspectra(pb3_plan* plan, const float* delta_dev, double* pk_de
   return run(plan, delta_dev, pk_dev, bk_dev, prec, (hipStream_t)stream);
 }
 
+pb3_status pb3_window_normalize(const pb3_plan* plan, const float* w_dev, double* pk_dev, double* bk_dev,
+                                double* scratch_dev, void* stream) {
+  if (!plan || !w_dev || !scratch_dev || (!pk_dev && !bk_dev)) {
+    set_error("null argument");
+    return PB3_EINVAL;
+  }
+  if (!plan->device) {
+    set_error("plan has no device state (created with PB3_FLAG_HOST_ONLY)");
+    return PB3_EINVAL;
+  }
+  const long n = (long)plan->N * plan->N * plan->N;
+  hipError_t e = launch_window(n, w_dev, pk_dev, plan->nb, bk_dev, (int)(plan->trip.size() / 3), scratch_dev,
+                               (hipStream_t)stream);
+  return e == hipSuccess ? PB3_OK : hip_fail(e, "window normalisation");
+}
+
 static const char* kStageNames[ST_COUNT] = {"fwd_z", "fwd_y", "fwd_x",    "power", "inv_x",
                                             "inv_y", "inv_z", "contract", "reduce"};
 

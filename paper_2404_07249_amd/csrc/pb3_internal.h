@@ -13,6 +13,7 @@
 namespace pb3 {
 
 constexpr int kReduceSlices = 32;
+constexpr int kWindowBlocks = 256;  // PB3_WINDOW_SCRATCH = 2 + 2 * kWindowBlocks doubles
 
 // Stage indices for the optional per-kernel timing.
 enum Stage {
@@ -175,6 +176,10 @@ hipError_t launch_inv_y(const pb3_plan& p, const Exec& x, hipStream_t s);
 hipError_t launch_inv_z(const pb3_plan& p, const Exec& x, hipStream_t s);
 hipError_t launch_contract(const pb3_plan& p, const Exec& x, pb3_precision prec, hipStream_t s);
 hipError_t launch_reduce(const pb3_plan& p, const Exec& x, hipStream_t s);
+// window moments and P / <w^2>, B / <w^3> (scratch: 2 + 2 kWindowBlocks doubles;
+// scratch[0..1] receive <w^2>, <w^3>)
+hipError_t launch_window(long n, const float* w, double* pk, int nb, double* bk, int nt, double* scratch,
+                         hipStream_t s);
 // FP64 triangle counts on the contraction grid: writes raw M^6 sum HHH for
 // every candidate triplet into counts_out (host), using temporary memory.
 pb3_status compute_counts_fp64(pb3_plan& p, std::vector<double>& counts_out);

@@ -162,7 +162,75 @@ __global__ void k_reduce_final(const double* __restrict__ rsl, int part_len, con
   out[t] = acc * fac[t];
 }
 
+// ---------------------------------------------------- window moments
+// Conventional normalisation of masked data: sums of w^2 and w^3 over the
+// grid (FP64; each block a contiguous range and a fixed tree, then the
+// blocks in order), and P / <w^2>, B / <w^3> in place.
+__global__ void __launch_bounds__(256) k_window_partial(const float* __restrict__ w, long n, long per_block,
+                                                        double* __restrict__ part) {
+  __shared__ double r2[256], r3[256];
+  const long v0 = (long)blockIdx.x * per_block;
+  long v1 = v0 + per_block;
+  if (v1 > n) v1 = n;
+  double s2 = 0.0, s3 = 0.0;
+  for (long v = v0 + threadIdx.x; v < v1; v += 256) {
+    double x = w[v];
+    double x2 = x * x;
+    s2 += x2;
+    s3 += x2 * x;
+  }
+  r2[threadIdx.x] = s2;
+  r3[threadIdx.x] = s3;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      r2[threadIdx.x] += r2[threadIdx.x + s];
+      r3[threadIdx.x] += r3[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = r2[0];
+    part[2 * blockIdx.x + 1] = r3[0];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_window_apply(const double* __restrict__ part, int nblk, double npix,
+                                                      double* __restrict__ pk, int nb, double* __restrict__ bk,
+                                                      int nt, double* __restrict__ moments) {
+  __shared__ double m[2];
+  if (threadIdx.x == 0) {
+    double s2 = 0.0, s3 = 0.0;
+    for (int i = 0; i < nblk; ++i) {
+      s2 += part[2 * i];
+      s3 += part[2 * i + 1];
+    }
+    m[0] = s2 / npix;
+    m[1] = s3 / npix;
+    if (moments) {
+      moments[0] = m[0];
+      moments[1] = m[1];
+    }
+  }
+  __syncthreads();
+  if (pk)
+    for (int i = threadIdx.x; i < nb; i += 256) pk[i] /= m[0];
+  if (bk)
+    for (int i = threadIdx.x; i < nt; i += 256) bk[i] /= m[1];
+}
+
 // ================================================================ launchers
+
+hipError_t launch_window(long n, const float* w, double* pk, int nb, double* bk, int nt, double* scratch,
+                         hipStream_t s) {
+  const long per = (n + kWindowBlocks - 1) / kWindowBlocks;
+  hipLaunchKernelGGL(k_window_partial, dim3(kWindowBlocks), dim3(256), 0, s, w, n, per, scratch + 2);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_window_apply, dim3(1), dim3(256), 0, s, (const double*)(scratch + 2), kWindowBlocks,
+                     (double)n, pk, nb, bk, nt, scratch);
+  return hipGetLastError();
+}
 
 hipError_t launch_power(const pb3_plan& p, const Exec& x, hipStream_t s) {
   hipLaunchKernelGGL(k_power_chunks, dim3(p.n_chunks, 1, x.n_jobs), dim3(256), 0, s, x.ws.dc, p.d.modes, p.d.chunk,

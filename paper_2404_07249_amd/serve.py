@@ -1,0 +1,315 @@
+"""Request loop for P(k) + bispectrum jobs on one GPU (continuous batching).
+
+Requests carry a field already on the device (for masked surveys the data
+d = w * delta and the window w) and ask for the binned power spectrum and
+bispectrum on their own grid and binning.  The server
+
+* keeps one device-resident plan per (grid, box, edges): bin tables and
+  the FP64 triangle counts are computed once and reused by every request
+  with that geometry;
+* admits requests in arrival order while a slot is free and the HBM the
+  job needs (its workspace and outputs) fits the budget; queued requests
+  with the same plan as the one being admitted join it in one batched
+  launch sequence (up to 8 jobs share the launches);
+* runs every admitted batch on its own slot stream, so work of different
+  requests overlaps on the device, and retires it when its completion
+  event has fired, freeing the slot and the memory;
+* normalises masked requests by the window moments (P / <w^2>,
+  B / <w^3>: the conventional windowed estimators of Sec. III.D.2 and
+  Sec. IV.D.2);
+* records arrival, admission and completion times per request.
+
+Each job's result depends only on its own inputs: the kernels and their
+reduction orders do not depend on what else is in flight, so a result in
+the mix equals the result computed alone, bit for bit.  The loop is
+single-threaded: call :meth:`Server.poll` (or :meth:`Server.run_until_idle`)
+to make progress.  Every device computation goes through the C ABI of
+``libpb3.so``; this module only schedules.
+"""
+
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import Batch, Plan, Pb3Error, _lib
+
+__all__ = ["Request", "Completed", "Server"]
+
+_MAX_JOBS_PER_LAUNCH = 8
+
+
+@dataclass
+class Request:
+    """One estimator job.  ``data`` is an N^3 float32 CUDA tensor; ``window``
+    (same shape, or None for an unmasked box) is the mask that multiplied it.
+    ``edges`` are bin edges in units of k_f.  ``arrival`` is a
+    ``time.perf_counter`` stamp (defaults to submission time); ``ready`` an
+    optional CUDA event after which the inputs are valid; ``deadline`` an
+    optional perf_counter stamp after which a request that is still queued
+    expires."""
+
+    rid: int
+    grid: int
+    box: float
+    edges: np.ndarray
+    data: object
+    window: object = None
+    precision: str = "mixed"
+    arrival: float | None = None
+    ready: object = None
+    deadline: float | None = None
+
+
+@dataclass
+class Completed:
+    rid: int
+    status: str  # "ok", "rejected", "cancelled", "expired", "error"
+    pk: np.ndarray | None = None
+    bk: np.ndarray | None = None
+    moments: np.ndarray | None = None  # (<w^2>, <w^3>) for masked requests
+    arrival: float = 0.0
+    admitted: float = 0.0
+    done: float = 0.0
+    batch_size: int = 0
+    message: str = ""
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+    @property
+    def wait(self) -> float:
+        return self.admitted - self.arrival
+
+
+@dataclass
+class _Running:
+    reqs: list
+    slot: int
+    batch: object
+    workspace: object
+    pks: list
+    bks: list
+    scratch: list
+    event: object
+    nbytes: int
+    admitted: float
+
+
+@dataclass
+class _Stats:
+    admitted: int = 0
+    launches: int = 0
+    max_in_flight: int = 0
+    max_queue: int = 0
+    bytes_peak: int = 0
+    batch_sizes: list = field(default_factory=list)
+
+
+class Server:
+    """Continuous-batching request loop (see the module docstring).
+
+    hbm_budget: bytes of device memory the server may hold for running
+    jobs (workspaces, outputs, scratch); max_slots: batches in flight at
+    once, each on its own stream.
+    """
+
+    def __init__(self, hbm_budget: int, max_slots: int = 4, merge_same_plan: bool = True):
+        import torch
+
+        _lib.load()
+        self.torch = torch
+        self.budget = int(hbm_budget)
+        self.max_slots = int(max_slots)
+        self.merge = merge_same_plan
+        self.streams = [torch.cuda.Stream() for _ in range(self.max_slots)]
+        self.free_slots = list(range(self.max_slots))
+        self.queue: deque = deque()
+        self.running: list[_Running] = []
+        self.done: dict[int, Completed] = {}
+        self.plans: dict = {}
+        self.bytes_in_use = 0
+        self.stats = _Stats()
+
+    # ------------------------------------------------------------ plans
+    def plan_for(self, grid: int, box: float, edges) -> Plan:
+        key = (int(grid), float(box), tuple(np.asarray(edges, dtype=np.float64).tolist()))
+        p = self.plans.get(key)
+        if p is None:
+            p = Plan(grid, box, edges, ext_workspace=True)
+            self.plans[key] = p
+        return p
+
+    @staticmethod
+    def _plan_key(req: Request):
+        return (int(req.grid), float(req.box), tuple(np.asarray(req.edges, dtype=np.float64).tolist()))
+
+    def job_bytes(self, plan: Plan, masked: bool) -> int:
+        """HBM one job holds while it runs: its workspace, outputs and the
+        window scratch."""
+        out = 8 * (plan.n_bins + plan.n_triplets)
+        scr = 8 * _lib.WINDOW_SCRATCH if masked else 0
+        return int(plan.workspace_bytes) + out + scr + 512
+
+    # ----------------------------------------------------------- submit
+    def submit(self, req: Request):
+        if req.arrival is None:
+            req.arrival = time.perf_counter()
+        n = req.grid
+        if tuple(req.data.shape) != (n, n, n):
+            raise ValueError("data shape does not match the grid")
+        if req.window is not None and tuple(req.window.shape) != (n, n, n):
+            raise ValueError("window shape does not match the grid")
+        self.queue.append(req)
+        self.stats.max_queue = max(self.stats.max_queue, len(self.queue))
+
+    def cancel(self, rid: int) -> bool:
+        """Remove a still-queued request; running ones finish."""
+        for r in list(self.queue):
+            if r.rid == rid:
+                self.queue.remove(r)
+                self.done[rid] = Completed(rid, "cancelled", arrival=r.arrival, done=time.perf_counter())
+                return True
+        return False
+
+    # ------------------------------------------------------------- loop
+    def poll(self) -> int:
+        """Retire finished batches, expire and admit queued requests;
+        returns the number of requests retired."""
+        n = self._retire()
+        self._expire()
+        self._admit()
+        return n
+
+    def run_until_idle(self, sleep: float = 5e-5):
+        while self.queue or self.running:
+            if self.poll() == 0 and self.running:
+                time.sleep(sleep)
+
+    @property
+    def idle(self) -> bool:
+        return not self.queue and not self.running
+
+    def _expire(self):
+        now = time.perf_counter()
+        for r in list(self.queue):
+            if r.deadline is not None and now > r.deadline:
+                self.queue.remove(r)
+                self.done[r.rid] = Completed(r.rid, "expired", arrival=r.arrival, done=now)
+
+    def _admit(self):
+        torch = self.torch
+        while self.queue and self.free_slots:
+            head = self.queue[0]
+            try:
+                plan = self.plan_for(head.grid, head.box, head.edges)
+            except Pb3Error as e:
+                self.queue.popleft()
+                self.done[head.rid] = Completed(head.rid, "error", arrival=head.arrival,
+                                                done=time.perf_counter(), message=str(e))
+                continue
+            need_one = self.job_bytes(plan, head.window is not None)
+            if need_one > self.budget:
+                self.queue.popleft()
+                self.done[head.rid] = Completed(head.rid, "rejected", arrival=head.arrival,
+                                                done=time.perf_counter(),
+                                                message=f"needs {need_one} bytes, budget {self.budget}")
+                continue
+            if self.bytes_in_use + need_one > self.budget:
+                break  # wait for memory (arrival order is kept)
+            # the head plus queued requests of the same plan and precision
+            group = [head]
+            used = need_one
+            if self.merge:
+                key = self._plan_key(head)
+                for r in list(self.queue)[1:]:
+                    if len(group) >= _MAX_JOBS_PER_LAUNCH:
+                        break
+                    if self._plan_key(r) == key and r.precision == head.precision:
+                        nb = self.job_bytes(plan, r.window is not None)
+                        if self.bytes_in_use + used + nb > self.budget:
+                            break
+                        group.append(r)
+                        used += nb
+            for r in group:
+                self.queue.remove(r)
+            self._launch(plan, group, used)
+
+    def _launch(self, plan: Plan, group: list, nbytes: int):
+        torch = self.torch
+        slot = self.free_slots.pop(0)
+        stream = self.streams[slot]
+        now = time.perf_counter()
+        batch = Batch([plan] * len(group), ext_workspace=True)
+        with torch.cuda.stream(stream):
+            for r in group:
+                if r.ready is not None:
+                    stream.wait_event(r.ready)
+            ws = torch.empty(max(batch.workspace_bytes, 1), dtype=torch.uint8, device="cuda")
+            batch.bind_workspace(ws)
+            pks = [torch.empty(plan.n_bins, dtype=torch.float64, device="cuda") for _ in group]
+            bks = [torch.empty(plan.n_triplets, dtype=torch.float64, device="cuda") for _ in group]
+            batch.run([r.data for r in group], group[0].precision, pk_outs=pks, bk_outs=bks, stream=stream)
+            scratch = []
+            for r, pk, bk in zip(group, pks, bks):
+                if r.window is not None:
+                    sc = torch.empty(_lib.WINDOW_SCRATCH, dtype=torch.float64, device="cuda")
+                    plan.window_normalize(r.window, pk, bk, scratch=sc, stream=stream)
+                    scratch.append(sc)
+                else:
+                    scratch.append(None)
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        self.running.append(_Running(group, slot, batch, ws, pks, bks, scratch, ev, nbytes, now))
+        self.bytes_in_use += nbytes
+        st = self.stats
+        st.admitted += len(group)
+        st.launches += batch.launches()
+        st.batch_sizes.append(len(group))
+        st.max_in_flight = max(st.max_in_flight, len(self.running))
+        st.bytes_peak = max(st.bytes_peak, self.bytes_in_use)
+
+    def _retire(self) -> int:
+        n = 0
+        for run in list(self.running):
+            if not run.event.query():
+                continue
+            now = time.perf_counter()
+            for r, pk, bk, sc in zip(run.reqs, run.pks, run.bks, run.scratch):
+                self.done[r.rid] = Completed(
+                    r.rid, "ok", pk=pk.cpu().numpy(), bk=bk.cpu().numpy(),
+                    moments=None if sc is None else sc[:2].cpu().numpy(),
+                    arrival=r.arrival, admitted=run.admitted, done=now, batch_size=len(run.reqs))
+                n += 1
+            self.running.remove(run)
+            self.free_slots.append(run.slot)
+            self.bytes_in_use -= run.nbytes
+            run.batch.close()
+        return n
+
+    # ---------------------------------------------------------- reports
+    def summary(self, rids=None) -> dict:
+        res = [c for c in self.done.values() if c.status == "ok" and (rids is None or c.rid in rids)]
+        if not res:
+            return {"completed": 0}
+        lat = np.array([c.latency for c in res]) * 1e3
+        wait = np.array([c.wait for c in res]) * 1e3
+        t0 = min(c.arrival for c in res)
+        t1 = max(c.done for c in res)
+        return {
+            "completed": len(res),
+            "rejected": sum(1 for c in self.done.values() if c.status == "rejected"),
+            "throughput_per_s": len(res) / max(t1 - t0, 1e-9),
+            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                           "max": float(lat.max())},
+            "admission_wait_ms": {"p50": float(np.percentile(wait, 50)), "p99": float(np.percentile(wait, 99))},
+            "max_in_flight_batches": self.stats.max_in_flight,
+            "max_queue": self.stats.max_queue,
+            "mean_batch_size": float(np.mean(self.stats.batch_sizes)) if self.stats.batch_sizes else 0.0,
+            "peak_bytes": self.stats.bytes_peak,
+            "plans": len(self.plans),
+        }

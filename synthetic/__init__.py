@@ -31,6 +31,8 @@ __all__ = [
     "field_for",
     "CONFIGS",
     "batch_jobs",
+    "window_mask",
+    "serve_schedule",
 ]
 
 
@@ -108,3 +110,35 @@ def batch_jobs(n_jobs: int = 64, grids=(64, 96, 128), box: float = 2000.0, fnl: 
             job["field"] = quadratic_field(n, box, fnl, job["seed"]).astype(np.float32)
         jobs.append(job)
     return jobs
+
+
+def window_mask(n: int, seed: int, radius: float = 0.45, keep: float = 0.95) -> np.ndarray:
+    """Binary survey-like window on an n^3 grid: voxels whose centre lies
+    within ``radius`` box sides of the box centre, each kept with
+    probability ``keep`` (independent holes).  float32."""
+    c = (np.arange(n, dtype=np.float64) + 0.5) / n - 0.5
+    r2 = c[:, None, None] ** 2 + c[None, :, None] ** 2 + c[None, None, :] ** 2
+    rng = np.random.default_rng(seed)
+    holes = rng.random((n, n, n)) < keep
+    return ((r2 < radius * radius) & holes).astype(np.float32)
+
+
+def serve_schedule(n_requests: int, rate: float = 20.0, seed: int = 5, grids=(64, 128, 256, 384),
+                   min_bins: int = 10, max_bins: int = 40, max_bins_64: int = 28):
+    """A Poisson request stream: exponential inter-arrival times of mean
+    1/rate seconds, grid uniform over ``grids``, bin count uniform in
+    [min_bins, max_bins] (at most ``max_bins_64`` on 64^3, whose shells
+    above |n| = 32 sqrt(3) are empty); field seed 10000 + i, window seed
+    20000 + i.  Returns dicts (arrival offset in s, grid, n_bins, edges,
+    field_seed, window_seed)."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(n_requests):
+        t += rng.exponential(1.0 / rate)
+        n = int(rng.choice(grids))
+        hi = max_bins_64 if n == 64 else max_bins
+        nb = int(rng.integers(min_bins, hi + 1))
+        out.append(dict(rid=i, arrival=t, n=n, n_bins=nb, edges=kf_edges(nb), field_seed=10000 + i,
+                        window_seed=20000 + i))
+    return out

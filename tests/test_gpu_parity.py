@@ -258,3 +258,42 @@ def test_fused_and_separate_z_pass_agree(torch_cuda, prec, n, box, edges):
     assert p1.workspace_bytes < p2.workspace_bytes  # no filtered fields in the fused workspace
     _check_pb(res, pk1, bk1, p1.triplets, "fused")
     _check_pb(res, pk2, bk2, p2.triplets, "separate")
+
+
+@pytest.mark.parametrize(
+    "n,nbins,m",
+    [
+        (384, 10, 64),   # largest forward grid, small alias-free contraction grid
+        (384, 40, 256),  # 40 bins: three 16-bin groups, separate z pass, G in HBM
+        (256, 40, 256),  # contraction on the full grid (3K = 240 < 256 = N)
+    ],
+)
+def test_large_grids_sampled(torch_cuda, n, nbins, m):
+    """Serving-size grids: P for every bin against the oracle, B on a
+    sample of triplets drawn from four bins (the oracle builds only those
+    filtered fields), exact triangle counts on the sample."""
+    import paper_2404_07249_amd as pb3
+
+    torch = torch_cuda
+    box = 2000.0
+    edges = kf_edges(nbins)
+    d = quadratic_field(n, box, 1.0, 10000 + n + nbins).astype(np.float32)
+    _say(f"[case] large n={n} bins={nbins}")
+    plan = pb3.Plan(n, box, edges)
+    assert plan.contract_grid == m
+    pk, bk = [t.cpu().numpy() for t in plan.polyspectra(_gpu(torch, d), "mixed")]
+    d64 = d.astype(np.float64)
+    pk_ref = oracle.power_spectrum(d64, box, edges)
+    assert np.all(np.abs(pk - pk_ref) <= P_RTOL * np.abs(pk_ref))
+    trips = plan.triplets
+    rng = np.random.default_rng(n + nbins)
+    bins = set(rng.choice(np.arange(1, nbins - 1), 2, replace=False).tolist()) | {0, nbins - 1}
+    cand = [i for i, t in enumerate(trips) if set(t.tolist()) <= bins]
+    pick = np.array(sorted(rng.choice(cand, min(10, len(cand)), replace=False)))
+    s, sa = oracle.triplet_sums_sample(d64, edges, trips[pick])
+    T = oracle.count_sample(n, edges, trips[pick])
+    _, cnt = plan.norm()
+    assert np.array_equal(cnt[pick].astype(np.int64), T)
+    scale = box**6 / float(n) ** 3
+    bref, aref = scale * s / T, scale * sa / T
+    assert np.all(np.abs(bk[pick] - bref) <= B_RTOL * np.abs(bref) + B_ATOL_A * aref)
