@@ -187,8 +187,9 @@ def serving_bench(n_requests: int = 200, rate: float = 20.0, budget_gb: float = 
     uniform over 64^3..384^3, 10-40 bins (<= 28 on 64^3), each field times a
     sphere-with-holes window (radius 0.45 L, 5% holes, drawn per request on
     the device), windowed normalisation.  Plans for every geometry in the
-    stream are built before the clock starts (device-resident plans);
-    fields come from a pool of two realizations per grid (one at 384^3)."""
+    stream are built and run once before the clock starts (device-resident
+    plans, kernels loaded); fields come from a pool of two realizations per
+    grid (one at 384^3)."""
     import torch
 
     from paper_2404_07249_amd.serve import Request, Server
@@ -207,33 +208,51 @@ def serving_bench(n_requests: int = 200, rate: float = 20.0, budget_gb: float = 
         r2 = c[:, None, None] ** 2 + c[None, :, None] ** 2 + c[None, None, :] ** 2
         spheres[n] = r2 < 0.45**2
     srv = Server(hbm_budget=int(budget_gb * (1 << 30)), max_slots=slots)
-    t_plans = time.perf_counter()
-    for q in sched:
-        srv.plan_for(q["n"], box, q["edges"])
-    t_plans = time.perf_counter() - t_plans
     client = torch.cuda.Stream()
     gen = torch.Generator(device="cuda")
+
+    def make_request(q, arrival):
+        n = q["n"]
+        with torch.cuda.stream(client):
+            gen.manual_seed(q["window_seed"])
+            holes = torch.rand((n, n, n), generator=gen, device="cuda") < 0.95
+            w = (spheres[n] & holes).to(torch.float32)
+            data = pool[n][q["field_seed"] % len(pool[n])] * w
+            ev = torch.cuda.Event()
+            ev.record(client)
+        return Request(rid=q["rid"], grid=n, box=box, edges=q["edges"], data=data, window=w,
+                       precision=precision, arrival=arrival, ready=ev)
+
+    # device-resident plans for every geometry of the stream, each run once
+    # (kernels loaded, allocator segments cached) before the clock starts
+    t_plans = time.perf_counter()
+    seen = set()
+    for q in sched:
+        key = (q["n"], q["n_bins"])
+        if key in seen:
+            continue
+        seen.add(key)
+        srv.plan_for(q["n"], box, q["edges"])
+        srv.submit(make_request(dict(q, rid=-1 - len(seen)), None))
+        srv.run_until_idle()
+    t_plans = time.perf_counter() - t_plans
+    srv.reset_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     k = 0
     while k < len(sched) or not srv.idle:
         now = time.perf_counter() - t0
         while k < len(sched) and sched[k]["arrival"] <= now:
-            q = sched[k]
-            n = q["n"]
-            with torch.cuda.stream(client):
-                gen.manual_seed(q["window_seed"])
-                holes = torch.rand((n, n, n), generator=gen, device="cuda") < 0.95
-                w = (spheres[n] & holes).to(torch.float32)
-                data = pool[n][q["field_seed"] % len(pool[n])] * w
-                ev = torch.cuda.Event()
-                ev.record(client)
-            srv.submit(Request(rid=q["rid"], grid=n, box=box, edges=q["edges"], data=data, window=w,
-                               precision=precision, arrival=t0 + q["arrival"], ready=ev))
+            srv.submit(make_request(sched[k], t0 + sched[k]["arrival"]))
             k += 1
         if srv.poll() == 0:
             time.sleep(5e-5)
     out = srv.summary()
+    slow = sorted((c for c in srv.done.values() if c.status == "ok"), key=lambda c: -c.latency)[:5]
+    by_rid = {q["rid"]: q for q in sched}
+    out["slowest"] = [dict(rid=c.rid, grid=by_rid[c.rid]["n"], bins=by_rid[c.rid]["n_bins"],
+                           latency_ms=round(1e3 * c.latency, 3), service_ms=round(1e3 * c.service, 3),
+                           wait_ms=round(1e3 * c.wait, 3)) for c in slow]
     out.update({
         "workload": f"Poisson stream, mean {rate:g} req/s, {n_requests} requests; grid uniform over "
                     "64^3/128^3/256^3/384^3, 10-40 bins of width 2k_f (<= 28 at 64^3), L=2000 Mpc/h; "
@@ -242,7 +261,7 @@ def serving_bench(n_requests: int = 200, rate: float = 20.0, budget_gb: float = 
         "precision": precision,
         "budget_bytes": srv.budget,
         "slots": slots,
-        "plan_build_s": t_plans,
+        "plan_build_and_warm_s": t_plans,
         "offered_rate_per_s": rate,
     })
     return out

@@ -261,14 +261,18 @@ template <int NQ> struct TileRegs {
   float4 v[PER];
 };
 
+// Bins at or above nb (the padding of the last 16-bin group) are zero
+// fields and are not read.
 template <int NQ>
-__device__ __forceinline__ void tile_load(const float* __restrict__ g, long mvox, long v0, TileRegs<NQ>& r) {
+__device__ __forceinline__ void tile_load(const float* __restrict__ g, long mvox, long v0, int nb,
+                                          TileRegs<NQ>& r) {
 #pragma unroll
   for (int k = 0; k < TileRegs<NQ>::PER; ++k) {
     int e = threadIdx.x + k * kContractThreads;
     if (e < TileRegs<NQ>::N4) {
       int bin = e / (kTileVox / 4), c4 = e % (kTileVox / 4);
-      r.v[k] = *reinterpret_cast<const float4*>(g + (size_t)bin * mvox + v0 + 4 * c4);
+      r.v[k] = bin < nb ? *reinterpret_cast<const float4*>(g + (size_t)bin * mvox + v0 + 4 * c4)
+                        : make_float4(0.f, 0.f, 0.f, 0.f);
     }
   }
 }
@@ -301,7 +305,7 @@ template <int NQ, bool MIXED, int K0, int K1>
 __global__ void __launch_bounds__(kContractThreads) k_contract_mfma(const float* __restrict__ g, long mvox, long vpw,
                                                                     float* __restrict__ part, int part_len,
                                                                     unsigned sel_lo, unsigned sel_hi,
-                                                                    size_t wstride) {
+                                                                    size_t wstride, int nb) {
   static_assert(kGroups == 4, "group dispatch below assumes four groups");
   g = job_ptr(g, wstride);
   part = job_ptr(part, wstride);
@@ -329,13 +333,13 @@ __global__ void __launch_bounds__(kContractThreads) k_contract_mfma(const float*
   const int n_tiles_wg = ve > vb ? (int)((ve - vb) / kTileVox) : 0;
   TileRegs<NQ> regs;
   if (n_tiles_wg > 0) {
-    tile_load<NQ>(g, mvox, vb, regs);
+    tile_load<NQ>(g, mvox, vb, nb, regs);
     tile_store<NQ, MIXED>(stage[0], regs, sel);
   }
   __syncthreads();
   for (int m = 0; m < n_tiles_wg; ++m) {
     const bool more = m + 1 < n_tiles_wg;
-    if (more) tile_load<NQ>(g, mvox, vb + (long)(m + 1) * kTileVox, regs);
+    if (more) tile_load<NQ>(g, mvox, vb + (long)(m + 1) * kTileVox, nb, regs);
     const TileStage<NQ>& cur = stage[m & 1];
     switch (gi) {
       case 0: contract_tile<NQ, MIXED, K0, K1, 0>(cur, i, grp, wig, acc, sel); break;
@@ -364,22 +368,22 @@ __global__ void __launch_bounds__(kContractThreads) k_contract_mfma(const float*
 
 template <int NQ, bool MIXED, int G>
 static hipError_t launch_group(const float* g, long mvox, int n_wg, long vpw, float* part, int part_len, int n_jobs,
-                               size_t wstride, hipStream_t s) {
+                               size_t wstride, int nb, hipStream_t s) {
   constexpr int K0 = group_begin(NQ, G), K1 = group_begin(NQ, G + 1);
   // bf16 pairs (element 0 in the low half): (-1, 0) and (0, -1)
   const unsigned sel_lo = 0x0000BF80u, sel_hi = 0xBF800000u;
   hipLaunchKernelGGL((k_contract_mfma<NQ, MIXED, K0, K1>), dim3(n_wg, 1, n_jobs), dim3(kContractThreads), 0, s, g,
-                     mvox, vpw, part, part_len, sel_lo, sel_hi, wstride);
+                     mvox, vpw, part, part_len, sel_lo, sel_hi, wstride, nb);
   return hipGetLastError();
 }
 
 template <int NQ, bool MIXED>
 static hipError_t launch_nq(const float* g, long mvox, int n_wg, long vpw, float* part, int part_len, int n_jobs,
-                            size_t wstride, hipStream_t s) {
-  hipError_t e = launch_group<NQ, MIXED, 0>(g, mvox, n_wg, vpw, part, part_len, n_jobs, wstride, s);
+                            size_t wstride, int nb, hipStream_t s) {
+  hipError_t e = launch_group<NQ, MIXED, 0>(g, mvox, n_wg, vpw, part, part_len, n_jobs, wstride, nb, s);
   if constexpr (n_groups(NQ) > 1) {
-    if (e == hipSuccess) e = launch_group<NQ, MIXED, 1>(g, mvox, n_wg, vpw, part, part_len, n_jobs, wstride, s);
-    if (e == hipSuccess) e = launch_group<NQ, MIXED, 2>(g, mvox, n_wg, vpw, part, part_len, n_jobs, wstride, s);
+    if (e == hipSuccess) e = launch_group<NQ, MIXED, 1>(g, mvox, n_wg, vpw, part, part_len, n_jobs, wstride, nb, s);
+    if (e == hipSuccess) e = launch_group<NQ, MIXED, 2>(g, mvox, n_wg, vpw, part, part_len, n_jobs, wstride, nb, s);
   }
   return e;
 }
@@ -690,12 +694,12 @@ hipError_t launch_contract_mfma(const pb3_plan& p, const Exec& x, bool mixed, hi
   const int pl = p.part_len, nj = x.n_jobs;
   const size_t ws = x.wstride;
   switch (nq) {
-    case 1: return mixed ? launch_nq<1, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, s)
-                         : launch_nq<1, false>(g, mvox, n_wg, vpw, part, pl, nj, ws, s);
-    case 2: return mixed ? launch_nq<2, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, s)
-                         : launch_nq<2, false>(g, mvox, n_wg, vpw, part, pl, nj, ws, s);
-    case 3: return mixed ? launch_nq<3, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, s)
-                         : launch_nq<3, false>(g, mvox, n_wg, vpw, part, pl, nj, ws, s);
+    case 1: return mixed ? launch_nq<1, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, s)
+                         : launch_nq<1, false>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, s);
+    case 2: return mixed ? launch_nq<2, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, s)
+                         : launch_nq<2, false>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, s);
+    case 3: return mixed ? launch_nq<3, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, s)
+                         : launch_nq<3, false>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -70,18 +70,6 @@ static void release(pb3_batch* b) {
   if (b->ws_owned && b->ws_base) hipFree(b->ws_base);
 }
 
-static pb3_status clear_group_padding(pb3_batch* b) {
-  for (const Group& g : b->groups) {
-    for (size_t k = 0; k < g.jobs.size(); ++k) {
-      char* base = (char*)b->ws_base + g.offset + k * g.stride;
-      Workspace w = carve(g.plan, base, g.stride);
-      pb3_status st = clear_padding(g.plan, w);
-      if (st != PB3_OK) return st;
-    }
-  }
-  return PB3_OK;
-}
-
 static void set_workspace(pb3_batch* b, void* base, bool owned) {
   if (b->ws_owned && b->ws_base) hipFree(b->ws_base);
   b->ws_base = base;
@@ -279,7 +267,6 @@ pb3_status pb3_batch_create(pb3_plan* const* plans, int n_jobs, unsigned flags, 
       st = PB3_ENOMEM;
     } else {
       set_workspace(b, base, true);
-      st = clear_group_padding(b);
     }
   }
   if (st != PB3_OK) {
@@ -307,7 +294,7 @@ pb3_status pb3_batch_bind_workspace(pb3_batch* batch, void* dev, size_t bytes) {
     return PB3_EINVAL;
   }
   set_workspace(batch, dev, false);
-  return clear_group_padding(batch);
+  return PB3_OK;
 }
 
 pb3_status pb3_batch_run(pb3_batch* batch, const float* const* deltas, double* const* pk, double* const* bk,

@@ -325,7 +325,7 @@ size_t workspace_bytes(const pb3_plan* p) {
   b += align_up(sizeof(float2) * (size_t)p->Lc * p->Lc * p->Kz, A);
   b += align_up(sizeof(float2) * (size_t)p->a1_len, A);
   b += align_up(sizeof(float2) * (size_t)p->a2_len, A);
-  b += p->fused ? 0 : align_up(sizeof(float) * (size_t)p->nb_pad * p->M * p->M * p->M, A);
+  b += p->fused ? 0 : align_up(sizeof(float) * (size_t)p->nb * p->M * p->M * p->M, A);
   b += align_up(sizeof(float) * (size_t)p->contract_wgs * p->part_len, A);
   b += align_up(sizeof(double) * (size_t)std::max(p->n_chunks, 1), A);
   b += align_up(sizeof(double) * (size_t)kReduceSlices * p->part_len, A);
@@ -349,7 +349,7 @@ Workspace carve(const pb3_plan* p, void* base, size_t bytes) {
   w.dc = (float2*)take(sizeof(float2) * (size_t)p->Lc * p->Lc * p->Kz);
   w.a1 = (float2*)take(sizeof(float2) * (size_t)p->a1_len);
   w.a2 = (float2*)take(sizeof(float2) * (size_t)p->a2_len);
-  w.g = p->fused ? nullptr : (float*)take(sizeof(float) * (size_t)p->nb_pad * p->M * p->M * p->M);
+  w.g = p->fused ? nullptr : (float*)take(sizeof(float) * (size_t)p->nb * p->M * p->M * p->M);
   w.part = (float*)take(sizeof(float) * (size_t)p->contract_wgs * p->part_len);
   w.ppart = (double*)take(sizeof(double) * (size_t)std::max(p->n_chunks, 1));
   w.rsl = (double*)take(sizeof(double) * (size_t)kReduceSlices * p->part_len);
@@ -361,16 +361,7 @@ static void carve_workspace(pb3_plan* p, void* base, size_t bytes, bool owned) {
   p->ws.owned = owned;
 }
 
-// The contraction reads the bins [nb, nb_pad) of G as zero fields.
-pb3_status clear_padding(const pb3_plan* p, const Workspace& w) {
-  size_t m3 = (size_t)p->M * p->M * p->M;
-  if (w.g && p->nb_pad > p->nb) {
-    hipError_t e = hipMemset(w.g + (size_t)p->nb * m3, 0, sizeof(float) * (size_t)(p->nb_pad - p->nb) * m3);
-    if (e != hipSuccess) return hip_fail(e, "hipMemset");
-  }
-  return PB3_OK;
-}
-static pb3_status clear_padding(pb3_plan* p) { return clear_padding(p, p->ws); }
+
 
 static pb3_status ensure_workspace(pb3_plan* p) {
   if (p->ws.base) return PB3_OK;
@@ -386,7 +377,7 @@ static pb3_status ensure_workspace(pb3_plan* p) {
     return PB3_ENOMEM;
   }
   carve_workspace(p, base, bytes, true);
-  return clear_padding(p);
+  return PB3_OK;
 }
 
 static pb3_status build_device(pb3_plan* p) {
@@ -646,7 +637,7 @@ pb3_status pb3_plan_bind_workspace(pb3_plan* plan, void* dev, size_t bytes) {
   }
   if (plan->ws.owned && plan->ws.base) hipFree(plan->ws.base);
   carve_workspace(plan, dev, bytes, false);
-  return plan->device ? clear_padding(plan) : PB3_OK;
+  return PB3_OK;
 }
 
 int pb3_n_bins(const pb3_plan* plan) { return plan ? plan->nb : 0; }

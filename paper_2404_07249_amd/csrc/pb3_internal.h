@@ -89,7 +89,7 @@ struct Workspace {
   float2* dc = nullptr;     // [Lc][Lc][Kz]
   float2* a1 = nullptr;     // per-bin x-pass outputs
   float2* a2 = nullptr;     // per-bin y-pass outputs
-  float* g = nullptr;       // [nb_pad][M^3]
+  float* g = nullptr;       // [nb][M^3] (separate z pass only)
   float* part = nullptr;    // contraction partials [work-group][tile*256]
   double* rsl = nullptr;    // reduction slices [kReduceSlices][tile*256]
   double* ppart = nullptr;  // power partials
@@ -157,10 +157,9 @@ namespace pb3 {
 void set_error(const std::string& msg);
 pb3_status hip_fail(hipError_t e, const char* what);
 
-// plan workspace (pb3_host.cpp): size, layout at base, zero padding bins
+// plan workspace (pb3_host.cpp): size and layout at base
 size_t workspace_bytes(const pb3_plan* p);
 Workspace carve(const pb3_plan* p, void* base, size_t bytes);
-pb3_status clear_padding(const pb3_plan* p, const Workspace& w);
 pb3_status check_prec(pb3_precision prec);
 // the whole launch sequence of one plan for the jobs of x, on stream s
 pb3_status enqueue(const pb3_plan& p, const Exec& x, bool do_pk, bool do_bk, pb3_precision prec, hipStream_t s);

@@ -11,7 +11,7 @@
 //   dc     float2 [Lc][Lc][Kz]       compact spectrum D(n), |n_i| <= K
 //   a1_b   float2 [M][ly_b][kzn_b]   bin b after the inverse x pass
 //   a2_b   float2 [M][M][kzn_b]      bin b after the inverse y pass
-//   g      float  [nb_pad][M][M][M]  filtered fields G_b on the contraction grid
+//   g      float  [nb][M][M][M]      filtered fields G_b on the contraction grid (separate z pass)
 // A centred-compact index c holds frequency f = c - Kc.
 
 #include <hip/hip_runtime.h>

@@ -85,6 +85,10 @@ class Completed:
     def wait(self) -> float:
         return self.admitted - self.arrival
 
+    @property
+    def service(self) -> float:
+        return self.done - self.admitted
+
 
 @dataclass
 class _Running:
@@ -98,6 +102,7 @@ class _Running:
     event: object
     nbytes: int
     admitted: float
+    pool_key: tuple
 
 
 @dataclass
@@ -132,6 +137,7 @@ class Server:
         self.running: list[_Running] = []
         self.done: dict[int, Completed] = {}
         self.plans: dict = {}
+        self.pool: dict = {}  # (plan key, jobs) -> idle Batch objects (no workspace held)
         self.bytes_in_use = 0
         self.stats = _Stats()
 
@@ -244,7 +250,9 @@ class Server:
         slot = self.free_slots.pop(0)
         stream = self.streams[slot]
         now = time.perf_counter()
-        batch = Batch([plan] * len(group), ext_workspace=True)
+        pkey = (self._plan_key(group[0]), len(group))
+        idle = self.pool.get(pkey)
+        batch = idle.pop() if idle else Batch([plan] * len(group), ext_workspace=True)
         with torch.cuda.stream(stream):
             for r in group:
                 if r.ready is not None:
@@ -264,7 +272,7 @@ class Server:
                     scratch.append(None)
             ev = torch.cuda.Event()
             ev.record(stream)
-        self.running.append(_Running(group, slot, batch, ws, pks, bks, scratch, ev, nbytes, now))
+        self.running.append(_Running(group, slot, batch, ws, pks, bks, scratch, ev, nbytes, now, pkey))
         self.bytes_in_use += nbytes
         st = self.stats
         st.admitted += len(group)
@@ -288,8 +296,14 @@ class Server:
             self.running.remove(run)
             self.free_slots.append(run.slot)
             self.bytes_in_use -= run.nbytes
-            run.batch.close()
+            self.pool.setdefault(run.pool_key, []).append(run.batch)
         return n
+
+    def reset_stats(self):
+        """Forget completed requests and counters (plans, pooled batches and
+        cached memory stay)."""
+        self.done.clear()
+        self.stats = _Stats()
 
     # ---------------------------------------------------------- reports
     def summary(self, rids=None) -> dict:
@@ -298,6 +312,7 @@ class Server:
             return {"completed": 0}
         lat = np.array([c.latency for c in res]) * 1e3
         wait = np.array([c.wait for c in res]) * 1e3
+        svc = np.array([c.service for c in res]) * 1e3
         t0 = min(c.arrival for c in res)
         t1 = max(c.done for c in res)
         return {
@@ -307,6 +322,8 @@ class Server:
             "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                            "max": float(lat.max())},
             "admission_wait_ms": {"p50": float(np.percentile(wait, 50)), "p99": float(np.percentile(wait, 99))},
+            "service_ms": {"p50": float(np.percentile(svc, 50)), "p99": float(np.percentile(svc, 99)),
+                           "max": float(svc.max())},
             "max_in_flight_batches": self.stats.max_in_flight,
             "max_queue": self.stats.max_queue,
             "mean_batch_size": float(np.mean(self.stats.batch_sizes)) if self.stats.batch_sizes else 0.0,
