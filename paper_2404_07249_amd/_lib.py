@@ -79,6 +79,12 @@ def load(path: str = LIB_PATH):
             f"{path} not found: build the HIP library first (python -m paper_2404_07249_amd.build); "
             "there is no CPU fallback"
         )
+    # torch first: the library then binds to the HIP runtime torch already
+    # loaded, so both share one runtime (device memory and streams pass
+    # between them); loading the library first would let torch find a
+    # second, mismatched runtime and fail to initialise the GPU.
+    import torch  # noqa: F401
+
     lib = C.CDLL(path)
     for name, res, args in SIGNATURES:
         fn = getattr(lib, name)
