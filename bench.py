@@ -120,7 +120,7 @@ def stage_rates(work: dict, stages: dict, precision: str) -> dict:
     return out
 
 
-def batched_bench(reps: int = 10, warmup: int = 2, precision: str = "mixed") -> dict:
+def batched_bench(reps: int = 10, warmup: int = 2, precision: str = "mixed", autotune: bool = True) -> dict:
     """The batched workload (64 realizations on 64^3/96^3/128^3 grids with
     16-24 bins, nine distinct plans): throughput of one call per field on
     one stream, of the batch (shared launches, concurrent plan groups) and
@@ -136,7 +136,7 @@ def batched_bench(reps: int = 10, warmup: int = 2, precision: str = "mixed") -> 
     for jb in jobs:
         key = (jb["n"], jb["n_bins"])
         if key not in cache:
-            cache[key] = pb3.Plan(jb["n"], jb["box"], jb["edges"])
+            cache[key] = pb3.Plan(jb["n"], jb["box"], jb["edges"], autotune=autotune)
         plans.append(cache[key])
     xs = [torch.from_numpy(jb["field"]).cuda() for jb in jobs]
     pk = [torch.empty(p.n_bins, dtype=torch.float64, device="cuda") for p in plans]
@@ -178,6 +178,8 @@ def batched_bench(reps: int = 10, warmup: int = 2, precision: str = "mixed") -> 
         "bispectra_per_s": rates,
         "ms_per_batch": ms,
         "speedup_graph_vs_single": rates["batch_graph"] / rates["single_calls"],
+        "launch_shapes": {f"{k[0]}^3x{k[1]}": [int(p.launch_shape["fused"]), p.launch_shape["contract_wgs"]]
+                          for k, p in cache.items()},
     }
 
 
@@ -335,6 +337,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-calls", type=int, default=50)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-workload measurement")
+    ap.add_argument("--no-autotune", action="store_true", help="default launch shapes instead of timed ones")
     ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests in the serving measurement (0 skips it; 2000 for the full stream)")
     args = ap.parse_args(argv)
@@ -352,7 +355,7 @@ def main(argv=None):
 
     d32, cfg = field_for("c3")
     n, box, edges = cfg["n"], cfg["box"], cfg["edges"]
-    plan = pb3.Plan(n, box, edges, stage_timing=True)
+    plan = pb3.Plan(n, box, edges, stage_timing=True, autotune=not args.no_autotune)
     info = plan_geometry(n, box, edges)
     x = torch.from_numpy(d32).cuda()
     pk = torch.empty(plan.n_bins, dtype=torch.float64, device="cuda")
@@ -423,6 +426,7 @@ def main(argv=None):
             "bins": plan.n_bins,
             "triplets": plan.n_triplets,
             "precision": main_p,
+            "launch_shape": plan.launch_shape,
         },
         "latency_ms": {"p50": float(np.percentile(r["lat"], 50)), "p99": float(np.percentile(r["lat"], 99))},
         "other_precision": {
@@ -436,7 +440,7 @@ def main(argv=None):
         "roofline": roof,
     }
     if not args.no_batched:
-        line["batched"] = batched_bench(precision=main_p)
+        line["batched"] = batched_bench(precision=main_p, autotune=not args.no_autotune)
     if args.serve_requests > 0:
         line["serving"] = serving_bench(args.serve_requests, precision=main_p)
     if not args.no_cpu_baseline:

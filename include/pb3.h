@@ -67,6 +67,12 @@ typedef enum {
 #define PB3_FLAG_NO_FUSION    0x40u /* run the inverse z pass as its own kernel and keep G in HBM
                                        (otherwise it is fused into the contraction when the
                                        contraction grid is 32..192 and there are <= 32 bins) */
+#define PB3_FLAG_AUTOTUNE     0x80u /* choose the launch shape (fused or separate z pass, number of
+                                       contraction work-groups) by timing the candidates on this
+                                       device at plan creation; with the environment variable
+                                       PB3_AUTOTUNE_CACHE naming a text file, choices are read
+                                       from it and new ones appended (key: architecture, N, M,
+                                       bin thresholds).  Overrides PB3_FLAG_NO_FUSION. */
 
 /* Build a plan for a cubic grid.
  *   grid[3]   grid points per side; all three equal, even, with prime
@@ -97,6 +103,10 @@ int pb3_n_bins(const pb3_plan* plan);
 int pb3_n_triplets(const pb3_plan* plan);  /* after dropping T = 0 (host-only plans: before) */
 int pb3_grid(const pb3_plan* plan);        /* N */
 int pb3_contract_grid(const pb3_plan* plan); /* M: N, or the smaller alias-free grid */
+/* Launch shape in use: fused (1) or separate (0) inverse z pass, contraction
+ * work-groups, and how it was chosen (0 default, 1 autotune cache, 2 timed).
+ * Any output pointer may be NULL. */
+pb3_status pb3_plan_launch_shape(const pb3_plan* plan, int* fused_out, int* contract_wgs_out, int* tuned_out);
 
 /* Bin edges (k_f units, n_bins+1), bin centres |k| in h/Mpc (mean |k| of
  * the modes in the bin) and mode counts N_b; any pointer may be NULL. */

@@ -56,6 +56,7 @@ class Plan:
         stage_timing: bool = False,
         ext_workspace: bool = False,
         fuse: bool = True,
+        autotune: bool = False,
     ):
         lib = _lib.load()
         self._lib = lib
@@ -71,6 +72,7 @@ class Plan:
         flags |= _lib.FLAG_STAGE_TIMING if stage_timing else 0
         flags |= _lib.FLAG_EXT_WORKSPACE if ext_workspace else 0
         flags |= 0 if fuse else _lib.FLAG_NO_FUSION
+        flags |= _lib.FLAG_AUTOTUNE if autotune else 0
         h = C.c_void_p()
         _lib.check(
             lib.pb3_plan_create(g, b, e.ctypes.data_as(C.POINTER(C.c_double)), int(e.size), flags, C.byref(h))
@@ -104,6 +106,14 @@ class Plan:
     @property
     def workspace_bytes(self) -> int:
         return int(self._lib.pb3_plan_workspace_bytes(self._h))
+
+    @property
+    def launch_shape(self) -> dict:
+        """{"fused": bool, "contract_wgs": int, "tuned": "default"|"cache"|"timed"}."""
+        f, w, t = C.c_int(), C.c_int(), C.c_int()
+        _lib.check(self._lib.pb3_plan_launch_shape(self._h, C.byref(f), C.byref(w), C.byref(t)))
+        return {"fused": bool(f.value), "contract_wgs": int(w.value),
+                "tuned": {0: "default", 1: "cache", 2: "timed"}[t.value]}
 
     def bins(self):
         """(edges in k_f units, mean |k| per bin in h/Mpc, mode counts N_b)."""

@@ -18,6 +18,7 @@ FLAG_STRICT = 0x8
 FLAG_EXT_WORKSPACE = 0x10
 FLAG_STAGE_TIMING = 0x20
 FLAG_NO_FUSION = 0x40
+FLAG_AUTOTUNE = 0x80
 BATCH_GRAPH = 0x1
 WINDOW_SCRATCH = 514
 BATCH_EXT_WORKSPACE = 0x2
@@ -36,6 +37,7 @@ SIGNATURES = [
     ("pb3_n_triplets", C.c_int, [C.c_void_p]),
     ("pb3_grid", C.c_int, [C.c_void_p]),
     ("pb3_contract_grid", C.c_int, [C.c_void_p]),
+    ("pb3_plan_launch_shape", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("pb3_get_bins", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("pb3_get_triplets", C.c_int, [C.c_void_p, C.c_void_p]),
     ("pb3_norm", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),

@@ -6,8 +6,11 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -311,7 +314,8 @@ static pb3_status build_host(pb3_plan* p, const int grid[3], const double box[3]
     return PB3_EUNSUPPORTED;
   }
   p->trip = p->trip_all;
-  p->fused = !(flags & PB3_FLAG_NO_FUSION) && fused_supported(p->nb_pad / 16, p->M);
+  p->fused_ok = fused_supported(p->nb_pad / 16, p->M);
+  p->fused = !(flags & PB3_FLAG_NO_FUSION) && p->fused_ok;
   p->contract_wgs = 512;
   p->part_len = mfma_tiles(p->nb_pad / 16) * 256;
   return PB3_OK;
@@ -377,6 +381,136 @@ static pb3_status ensure_workspace(pb3_plan* p) {
     return PB3_ENOMEM;
   }
   carve_workspace(p, base, bytes, true);
+  return PB3_OK;
+}
+
+// ------------------------------------------------------------ autotune
+// Launch-shape choice per plan: the inverse z pass fused into the
+// contraction or separate, and the number of contraction work-groups
+// (multiples of the CU count).  Each candidate runs the whole bispectrum
+// path a few times on a zero field; the fastest median wins.  Results are
+// cached in a text file (PB3_AUTOTUNE_CACHE) keyed by device architecture,
+// grid, contraction grid and the bin thresholds.
+static std::string tune_key(const pb3_plan* p) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, p->device_id) == hipSuccess) arch = prop.gcnArchName;
+  std::ostringstream k;
+  k << arch << " N" << p->N << " M" << p->M << " thr";
+  for (int64_t t : p->thr) k << ":" << t;
+  return k.str();
+}
+
+static bool tune_lookup(const std::string& path, const std::string& key, int& fused, int& wgs) {
+  std::ifstream f(path);
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {
+    size_t bar = line.rfind(" | ");
+    if (bar == std::string::npos || line.compare(0, bar, key) != 0 || bar != key.size()) continue;
+    std::istringstream v(line.substr(bar + 3));
+    int a = -1, b = -1;
+    if (v >> a >> b && (a == 0 || a == 1) && b > 0) {
+      fused = a;
+      wgs = b;
+      found = true;  // the last entry for a key wins
+    }
+  }
+  return found;
+}
+
+static pb3_status autotune(pb3_plan* p, int n_cu) {
+  const char* path = std::getenv("PB3_AUTOTUNE_CACHE");
+  const std::string key = tune_key(p);
+  int c_fused = -1, c_wgs = -1;
+  if (path && tune_lookup(path, key, c_fused, c_wgs) && (!c_fused || p->fused_ok)) {
+    p->fused = c_fused == 1;
+    p->contract_wgs = c_wgs;
+    p->tuned = 1;
+    return PB3_OK;
+  }
+  struct Cand {
+    bool fused;
+    int wgs;
+  };
+  std::vector<Cand> cands;
+  const int nq = p->nb_pad / 16;
+  if (p->fused_ok) {
+    const int base = fused_grid(nq, p->M, n_cu);
+    for (int mult : {1, 2}) cands.push_back({true, base * mult});
+  }
+  for (int mult : {1, 2, 3, 4}) cands.push_back({false, n_cu * mult});
+  // scratch: the largest workspace, a zero field and outputs
+  size_t ws_max = 0;
+  const bool keep_fused = p->fused;
+  const int keep_wgs = p->contract_wgs;
+  for (const Cand& c : cands) {
+    p->fused = c.fused;
+    p->contract_wgs = c.wgs;
+    ws_max = std::max(ws_max, workspace_bytes(p));
+  }
+  p->fused = keep_fused;
+  p->contract_wgs = keep_wgs;
+  const size_t n3 = (size_t)p->N * p->N * p->N;
+  const int nt = (int)(p->trip.size() / 3);
+  void *ws = nullptr, *fld = nullptr, *bk = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  pb3_status st = PB3_OK;
+  hipError_t e;
+  if ((e = hipMalloc(&ws, ws_max)) != hipSuccess || (e = hipMalloc(&fld, sizeof(float) * n3)) != hipSuccess ||
+      (e = hipMalloc(&bk, sizeof(double) * std::max(nt, 1))) != hipSuccess) {
+    st = PB3_ENOMEM;
+    set_error("autotune allocation failed");
+  }
+  if (st == PB3_OK && ((e = hipMemset(fld, 0, sizeof(float) * n3)) != hipSuccess ||
+                       (e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess))
+    st = hip_fail(e, "autotune set-up");
+  float best = 1e30f;
+  Cand pick{keep_fused, keep_wgs};
+  for (size_t ci = 0; ci < cands.size() && st == PB3_OK; ++ci) {
+    p->fused = cands[ci].fused;
+    p->contract_wgs = cands[ci].wgs;
+    Exec x;
+    x.ws = carve(p, ws, ws_max);
+    x.io.delta[0] = (const float*)fld;
+    x.io.bk[0] = (double*)bk;
+    std::vector<float> ms;
+    for (int r = 0; r < 4 && st == PB3_OK; ++r) {
+      if ((e = hipEventRecord(e0, nullptr)) != hipSuccess) {
+        st = hip_fail(e, "hipEventRecord");
+        break;
+      }
+      st = enqueue(*p, x, false, true, PB3_MIXED_BF16X3, nullptr);
+      if (st != PB3_OK) break;
+      if ((e = hipEventRecord(e1, nullptr)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess) {
+        st = hip_fail(e, "autotune timing");
+        break;
+      }
+      float t = 0.f;
+      hipEventElapsedTime(&t, e0, e1);
+      if (r > 0) ms.push_back(t);  // the first run warms up
+    }
+    if (st != PB3_OK) break;
+    std::sort(ms.begin(), ms.end());
+    const float med = ms[ms.size() / 2];
+    if (med < best) {
+      best = med;
+      pick = cands[ci];
+    }
+  }
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  hipFree(ws);
+  hipFree(fld);
+  hipFree(bk);
+  if (st != PB3_OK) return st;
+  p->fused = pick.fused;
+  p->contract_wgs = pick.wgs;
+  p->tuned = 2;
+  if (path) {
+    std::ofstream f(path, std::ios::app);
+    if (f) f << key << " | " << (pick.fused ? 1 : 0) << " " << pick.wgs << " " << best << "\n";
+  }
   return PB3_OK;
 }
 
@@ -463,6 +597,7 @@ static pb3_status build_device(pb3_plan* p) {
     }
   }
   p->device = true;
+  if (p->flags & PB3_FLAG_AUTOTUNE) return autotune(p, n_cu);
   return PB3_OK;
 }
 
@@ -644,6 +779,17 @@ int pb3_n_bins(const pb3_plan* plan) { return plan ? plan->nb : 0; }
 int pb3_n_triplets(const pb3_plan* plan) { return plan ? (int)(plan->trip.size() / 3) : 0; }
 int pb3_grid(const pb3_plan* plan) { return plan ? plan->N : 0; }
 int pb3_contract_grid(const pb3_plan* plan) { return plan ? plan->M : 0; }
+
+pb3_status pb3_plan_launch_shape(const pb3_plan* plan, int* fused_out, int* contract_wgs_out, int* tuned_out) {
+  if (!plan) {
+    set_error("null plan");
+    return PB3_EINVAL;
+  }
+  if (fused_out) *fused_out = plan->fused ? 1 : 0;
+  if (contract_wgs_out) *contract_wgs_out = plan->contract_wgs;
+  if (tuned_out) *tuned_out = plan->tuned;
+  return PB3_OK;
+}
 
 pb3_status pb3_get_bins(const pb3_plan* plan, double* edges_kf_out, double* kmean_out, int64_t* n_modes_out) {
   if (!plan) {

@@ -122,6 +122,8 @@ struct pb3_plan {
   int Kz = 0;                  // compact z length
   int M = 0;                   // contraction grid
   bool fused = false;          // inverse z pass fused into the contraction (no G in HBM)
+  bool fused_ok = false;       // the fused kernel supports this plan
+  int tuned = 0;               // launch shape: 0 default, 1 from the autotune cache, 2 measured
   int lut_len = 0;
   std::vector<int8_t> lut;
   std::vector<int64_t> nmodes;

@@ -139,3 +139,9 @@ def test_batch_rejects_host_only_and_empty():
     assert lib.pb3_batch_create(arr, 2, 0x80, C.byref(h)) == 1  # unknown flag
     with pytest.raises(pb3.Pb3Error):
         pb3.Batch([p])
+
+
+def test_launch_shape_query_on_host_plan():
+    p = _plan(64, 1000.0, kf_edges(8))
+    shape = p.launch_shape
+    assert shape["tuned"] == "default" and shape["contract_wgs"] > 0

@@ -297,3 +297,28 @@ def test_large_grids_sampled(torch_cuda, n, nbins, m):
     scale = box**6 / float(n) ** 3
     bref, aref = scale * s / T, scale * sa / T
     assert np.all(np.abs(bk[pick] - bref) <= B_RTOL * np.abs(bref) + B_ATOL_A * aref)
+
+
+def test_autotune_with_cache(torch_cuda, tmp_path, monkeypatch):
+    """PB3_FLAG_AUTOTUNE times the launch shapes once and records the choice;
+    a second plan of the same geometry reads it from the cache.  The tuned
+    plan meets the same parity bound against the oracle."""
+    import paper_2404_07249_amd as pb3
+
+    torch = torch_cuda
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("PB3_AUTOTUNE_CACHE", str(cache))
+    d, cfg = field_for("c2")
+    p1 = pb3.Plan(cfg["n"], cfg["box"], cfg["edges"], autotune=True)
+    assert p1.launch_shape["tuned"] == "timed"
+    lines = cache.read_text().strip().splitlines()
+    assert len(lines) == 1 and " | " in lines[0]
+    p2 = pb3.Plan(cfg["n"], cfg["box"], cfg["edges"], autotune=True)
+    assert p2.launch_shape["tuned"] == "cache"
+    assert p2.launch_shape["fused"] == p1.launch_shape["fused"]
+    assert p2.launch_shape["contract_wgs"] == p1.launch_shape["contract_wgs"]
+    _say(f"[case] autotune choice {p1.launch_shape}")
+    res = oracle.bispectrum(d.astype(np.float64), cfg["box"], cfg["edges"])
+    for prec in PRECS:
+        pk, bk = [t.cpu().numpy() for t in p2.polyspectra(_gpu(torch, d), prec)]
+        _check_pb(res, pk, bk, p2.triplets, f"tuned {prec}")
