@@ -16,6 +16,12 @@ Parity status of each function (what pins it is in ``tests/test_oracle.py``):
                            tree-level bispectrum of a quadratic field.
 * ``windowed_polyspectra`` pinned: unbiased means for a field with local
                            2- and 3-point functions under random windows.
+* ``masked`` (Monte Carlo Fisher of the masked power spectrum) pinned: the
+                           exact expectation equals (1/2) diag(N_b) without a
+                           window and a brute-force double sum with one; the
+                           Monte Carlo average converges to it; the
+                           unwindowed estimate is unbiased for a flat
+                           spectrum under a window.
 """
 
 from .polyspec import (  # noqa: F401
@@ -40,3 +46,4 @@ from .polyspec import (  # noqa: F401
     unit_fields,
 )
 from .brute import brute_sums  # noqa: F401
+from . import masked  # noqa: F401,E402
