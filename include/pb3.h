@@ -142,6 +142,36 @@ pb3_status pb3_polyspectra(pb3_plan* plan, const float* delta_dev, double* pk_de
 pb3_status pb3_window_normalize(const pb3_plan* plan, const float* w_dev, double* pk_dev, double* bk_dev,
                                 double* scratch_dev, void* stream);
 
+/* Masked power spectrum with a Monte Carlo Fisher matrix (Sec. III.C.2:
+ * eq. fish-from-Q with the Girard-Hutchinson trace of eq. girard-hutchinson;
+ * global line of sight (eq. Q-alpha-global), l = 0, unit weighting, the
+ * window as pointing matrix):
+ *   p_b   = N_b P_box_b(d) / 2                       (numerator)
+ *   F_ab  = (1 / 2 n_grf) sum_i sum_x w g_a^i v_b^i,  g_a = IDFT[Theta_a DFT[w a_i]],
+ *                                                      v_b = IDFT[Theta_b DFT[a_i]]
+ *   P_b   = (F^-1 p)_b                               (unwindowed estimate)
+ * for white unit-variance random fields a_i (so the A^-1 of the paper is the
+ * identity; with w = 1 the expectation of F is diag(N_b) / 2 and P is the
+ * box estimator).  The plan must contract on its own grid
+ * (PB3_FLAG_FULL_GRID), since w is not band-limited.
+ *   data_dev   N^3 float32, the masked data d = w * delta
+ *   window_dev N^3 float32, w
+ *   grfs_dev   host array of n_grf device pointers to N^3 float32 fields
+ *              (the caller draws them: white, zero mean, unit variance)
+ *   pk_dev     n_bins float64 output, (Mpc/h)^3
+ *   fisher_dev n_bins x n_bins float64 output (row a, column b) or NULL
+ *   workspace  >= pb3_masked_power_workspace_bytes, 256-byte aligned
+ *              ((2 n_bins + 1) N^3 floats of filtered fields plus the plan's
+ *              FFT buffers and partial sums)
+ * Enqueued on `stream`; the first call on a plan also uploads two small
+ * tables synchronously.  Errors: PB3_EINVAL (null argument, host-only plan,
+ * plan without the full grid, n_grf < 1), PB3_EUNSUPPORTED (> 48 bins),
+ * PB3_ENOMEM (workspace too small), PB3_EDEVICE. */
+size_t pb3_masked_power_workspace_bytes(const pb3_plan* plan);
+pb3_status pb3_masked_power(pb3_plan* plan, const float* data_dev, const float* window_dev,
+                            const float* const* grfs_dev, int n_grf, double* pk_dev, double* fisher_dev,
+                            void* workspace_dev, size_t workspace_bytes, void* stream);
+
 /* Stage timing (plans made with PB3_FLAG_STAGE_TIMING): every call records
  * a HIP event pair around each kernel launch on the call's stream.
  * pb3_stage_times writes, per stage, the mean milliseconds over the calls

@@ -212,6 +212,33 @@ class Plan:
             _stream_handle(stream)))
         return scratch[:2]
 
+    @property
+    def masked_workspace_bytes(self) -> int:
+        return int(self._lib.pb3_masked_power_workspace_bytes(self._h))
+
+    def masked_power(self, data, window, grfs, pk_out=None, fisher_out=None, workspace=None, stream=None):
+        """Unwindowed P of masked data d = w delta with the Monte Carlo Fisher
+        matrix from the white unit-variance fields ``grfs`` (plans made with
+        ``full_grid=True``).  Returns (P, F)."""
+        import torch
+
+        self._check_field(data)
+        self._check_field(window)
+        for g in grfs:
+            self._check_field(g)
+        pk = self._out(pk_out, self.n_bins, data)
+        nb = self.n_bins
+        fm = fisher_out if fisher_out is not None else torch.empty((nb, nb), dtype=torch.float64,
+                                                                   device=data.device)
+        if workspace is None:
+            workspace = torch.empty(self.masked_workspace_bytes, dtype=torch.uint8, device=data.device)
+        ga = (C.c_void_p * len(grfs))(*[g.data_ptr() for g in grfs])
+        _lib.check(self._lib.pb3_masked_power(
+            self._h, C.c_void_p(data.data_ptr()), C.c_void_p(window.data_ptr()), ga, len(grfs),
+            C.c_void_p(pk.data_ptr()), C.c_void_p(fm.data_ptr()), C.c_void_p(workspace.data_ptr()),
+            workspace.numel() * workspace.element_size(), _stream_handle(stream)))
+        return pk, fm
+
     def stage_times(self) -> dict:
         """Mean milliseconds per kernel stage over the calls since the last
         reset (plans made with ``stage_timing=True``): {stage: (ms, calls)}."""

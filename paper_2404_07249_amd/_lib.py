@@ -45,6 +45,10 @@ SIGNATURES = [
     ("pb3_bispectrum", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     ("pb3_polyspectra", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     ("pb3_window_normalize", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("pb3_masked_power_workspace_bytes", C.c_size_t, [C.c_void_p]),
+    ("pb3_masked_power", C.c_int,
+     [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p), C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+      C.c_size_t, C.c_void_p]),
     ("pb3_stage_times", C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_int)]),
     ("pb3_stage_timing_reset", C.c_int, [C.c_void_p]),
     ("pb3_stage_name", C.c_char_p, [C.c_int]),

@@ -114,8 +114,9 @@ static pb3_status upload_twiddles_d(double2** out, int n) {
 
 static void free_device(pb3_plan* p) {
   DeviceTables& d = p->d;
-  void* ptrs[] = {d.lut,     d.modes,      d.chunk,    d.chunk_first, d.geom, d.tiles, d.trip_all,
-                  d.out_map, d.inv_counts, d.pk_scale, d.tw_n, d.tw_m,  d.tw_m_d};
+  void* ptrs[] = {d.lut,      d.modes,      d.chunk,    d.chunk_first, d.geom,   d.tiles,        d.trip_all,
+                  d.out_map,  d.inv_counts, d.pk_scale, d.tw_n,        d.tw_m,   d.tw_m_d,       d.fisher_trips,
+                  d.nmodes_d};
   for (void* q : ptrs)
     if (q) hipFree(q);
   d = DeviceTables{};
@@ -860,6 +861,51 @@ pb3_status pb3_window_normalize(const pb3_plan* plan, const float* w_dev, double
   hipError_t e = launch_window(n, w_dev, pk_dev, plan->nb, bk_dev, (int)(plan->trip.size() / 3), scratch_dev,
                                (hipStream_t)stream);
   return e == hipSuccess ? PB3_OK : hip_fail(e, "window normalisation");
+}
+
+size_t pb3_masked_power_workspace_bytes(const pb3_plan* plan) { return plan ? masked_workspace_bytes(*plan) : 0; }
+
+pb3_status pb3_masked_power(pb3_plan* plan, const float* data_dev, const float* window_dev,
+                            const float* const* grfs_dev, int n_grf, double* pk_dev, double* fisher_dev,
+                            void* workspace_dev, size_t workspace_bytes_, void* stream) {
+  if (!plan || !data_dev || !window_dev || !grfs_dev || !pk_dev || !workspace_dev) {
+    set_error("null argument");
+    return PB3_EINVAL;
+  }
+  if (!plan->device) {
+    set_error("plan has no device state (created with PB3_FLAG_HOST_ONLY)");
+    return PB3_EINVAL;
+  }
+  if (plan->M != plan->N) {
+    set_error("the masked power spectrum needs the full grid (create the plan with PB3_FLAG_FULL_GRID)");
+    return PB3_EINVAL;
+  }
+  if (n_grf < 1) {
+    set_error("at least one random field is needed");
+    return PB3_EINVAL;
+  }
+  for (int i = 0; i < n_grf; ++i)
+    if (!grfs_dev[i]) {
+      set_error("null random field");
+      return PB3_EINVAL;
+    }
+  if (plan->nb > 48) {
+    set_error("the masked power spectrum is implemented for at most 48 bins");
+    return PB3_EUNSUPPORTED;
+  }
+  if (workspace_bytes_ < masked_workspace_bytes(*plan) || ((uintptr_t)workspace_dev) % 256) {
+    set_error("workspace too small or not 256-byte aligned: need " +
+              std::to_string(masked_workspace_bytes(*plan)) + " bytes");
+    return PB3_ENOMEM;
+  }
+  int dev = -1;
+  hipGetDevice(&dev);
+  if (dev != plan->device_id) {
+    set_error("plan was created on another device");
+    return PB3_EINVAL;
+  }
+  return run_masked_power(*plan, data_dev, window_dev, grfs_dev, n_grf, pk_dev, fisher_dev, workspace_dev,
+                          (hipStream_t)stream);
 }
 
 static const char* kStageNames[ST_COUNT] = {"fwd_z", "fwd_y", "fwd_x",    "power", "inv_x",

@@ -78,6 +78,8 @@ struct DeviceTables {
   float2* tw_n = nullptr;         // W_N^j, j < N
   float2* tw_m = nullptr;         // W_M^j
   double2* tw_m_d = nullptr;      // FP64 twiddles for the count pass
+  int32_t* fisher_trips = nullptr; // masked power: (window, g_a, v_b) field triplets (made on first use)
+  double* nmodes_d = nullptr;      // masked power: N_b as double
 };
 
 struct Workspace {
@@ -184,6 +186,10 @@ hipError_t launch_window(long n, const float* w, double* pk, int nb, double* bk,
 // FP64 triangle counts on the contraction grid: writes raw M^6 sum HHH for
 // every candidate triplet into counts_out (host), using temporary memory.
 pb3_status compute_counts_fp64(pb3_plan& p, std::vector<double>& counts_out);
+// masked power spectrum with the Monte Carlo Fisher matrix (pb3_kernels.hip)
+size_t masked_workspace_bytes(const pb3_plan& p);
+pb3_status run_masked_power(pb3_plan& p, const float* data, const float* window, const float* const* grfs, int n_grf,
+                            double* pk_out, double* f_out, void* workspace, hipStream_t s);
 // MFMA contraction (contract_mfma.hip): tiles for nq 16-bin groups, the
 // partial-vector index of triplet (a, b, c) (-1 if not produced), launch
 int mfma_tiles(int nq);

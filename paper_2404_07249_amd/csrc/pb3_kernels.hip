@@ -219,6 +219,79 @@ __global__ void __launch_bounds__(256) k_window_apply(const double* __restrict__
     for (int i = threadIdx.x; i < nt; i += 256) bk[i] /= m[1];
 }
 
+// ------------------------------------------- masked power spectrum (MC)
+// out[i] = w[i] * a[i]
+__global__ void k_mul_window(const float* __restrict__ w, const float* __restrict__ a, float* __restrict__ out,
+                             long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    out[i] = w[i] * a[i];
+}
+
+__global__ void k_fill_zero(double* __restrict__ x, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0.0;
+}
+
+// out[t] += sum over work-groups (fixed order) of part[w][t]
+__global__ void k_reduce_accum(const double* __restrict__ part, int n_wg, int n_out, double* __restrict__ out) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_out) return;
+  double s = 0.0;
+  for (int w = 0; w < n_wg; ++w) s += part[(size_t)w * n_out + t];
+  out[t] += s;
+}
+
+// F = scale * acc (nb x nb), p_b = N_b P_box_b / 2, solve F x = p by
+// Gaussian elimination with partial pivoting in FP64 (one work-group).
+__global__ void __launch_bounds__(64) k_masked_solve(const double* __restrict__ acc, double scale,
+                                                     const double* __restrict__ pbox,
+                                                     const double* __restrict__ nmodes, int nb,
+                                                     double* __restrict__ pk_out, double* __restrict__ f_out) {
+  extern __shared__ double A[];  // [nb][nb + 1]
+  __shared__ int piv;
+  const int ld = nb + 1, tid = threadIdx.x;
+  for (int e = tid; e < nb * nb; e += 64) {
+    const int r = e / nb, c = e % nb;
+    const double v = scale * acc[e];
+    A[r * ld + c] = v;
+    if (f_out) f_out[e] = v;
+  }
+  for (int r = tid; r < nb; r += 64) A[r * ld + nb] = 0.5 * nmodes[r] * pbox[r];
+  __syncthreads();
+  for (int k = 0; k < nb; ++k) {
+    if (tid == 0) {
+      int best = k;
+      for (int r = k + 1; r < nb; ++r)
+        if (fabs(A[r * ld + k]) > fabs(A[best * ld + k])) best = r;
+      piv = best;
+    }
+    __syncthreads();
+    const int pr = piv;
+    if (pr != k)
+      for (int c = tid; c <= nb; c += 64) {
+        const double t = A[k * ld + c];
+        A[k * ld + c] = A[pr * ld + c];
+        A[pr * ld + c] = t;
+      }
+    __syncthreads();
+    const double d = A[k * ld + k];
+    for (int r = k + 1 + tid; r < nb; r += 64) {
+      const double f = A[r * ld + k] / d;
+      for (int c = k; c <= nb; ++c) A[r * ld + c] -= f * A[k * ld + c];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    for (int r = nb - 1; r >= 0; --r) {
+      double v = A[r * ld + nb];
+      for (int c = r + 1; c < nb; ++c) v -= A[r * ld + c] * A[c * ld + nb];
+      A[r * ld + nb] = v / A[r * ld + r];
+    }
+  }
+  __syncthreads();
+  for (int r = tid; r < nb; r += 64) pk_out[r] = A[r * ld + nb];
+}
+
 // ================================================================ launchers
 
 hipError_t launch_window(long n, const float* w, double* pk, int nb, double* bk, int nt, double* scratch,
@@ -291,6 +364,106 @@ hipError_t launch_reduce(const pb3_plan& p, const Exec& x, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_final, dim3((n_out + 255) / 256, 1, x.n_jobs), dim3(256), 0, s, x.ws.rsl, p.part_len,
                      p.d.out_map, p.d.inv_counts, n_out, x.io, x.wstride);
   return hipGetLastError();
+}
+
+// ------------------------------------------- masked power spectrum (MC)
+// Workspace: the plan's workspace, then fields [2 nb + 1][N^3] (window,
+// g_b = IDFT[Theta_b DFT[w a]], v_b = IDFT[Theta_b DFT[a]]), work-group
+// partials [kMaskedWgs][nb^2], the accumulated Fisher sums [nb^2] and the
+// box power spectrum of the data [nb].
+constexpr int kMaskedWgs = 512;
+
+size_t masked_workspace_bytes(const pb3_plan& p) {
+  const size_t A = 256, n3 = (size_t)p.N * p.N * p.N, nb = (size_t)p.nb;
+  auto up = [&](size_t b) { return (b + A - 1) / A * A; };
+  return up(workspace_bytes(&p)) + up(sizeof(float) * (2 * nb + 1) * n3) +
+         up(sizeof(double) * kMaskedWgs * nb * nb) + up(sizeof(double) * nb * nb) + up(sizeof(double) * nb);
+}
+
+static pb3_status masked_tables(pb3_plan& p) {
+  if (p.d.fisher_trips) return PB3_OK;
+  const int nb = p.nb;
+  std::vector<int32_t> t;
+  for (int a = 0; a < nb; ++a)
+    for (int b = 0; b < nb; ++b) {
+      t.push_back(0);
+      t.push_back(1 + a);
+      t.push_back(1 + nb + b);
+    }
+  std::vector<double> nm(p.nmodes.begin(), p.nmodes.end());
+  hipError_t e = hipMalloc((void**)&p.d.fisher_trips, sizeof(int32_t) * t.size());
+  if (e == hipSuccess) e = hipMemcpy(p.d.fisher_trips, t.data(), sizeof(int32_t) * t.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc((void**)&p.d.nmodes_d, sizeof(double) * nb);
+  if (e == hipSuccess) e = hipMemcpy(p.d.nmodes_d, nm.data(), sizeof(double) * nb, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "masked power tables");
+  return PB3_OK;
+}
+
+pb3_status run_masked_power(pb3_plan& p, const float* data, const float* window, const float* const* grfs, int n_grf,
+                            double* pk_out, double* f_out, void* workspace, hipStream_t s) {
+  pb3_status st = masked_tables(p);
+  if (st != PB3_OK) return st;
+  const size_t A = 256, n3 = (size_t)p.N * p.N * p.N;
+  const int nb = p.nb, nt = nb * nb, nf = 2 * nb + 1;
+  auto up = [&](size_t b) { return (b + A - 1) / A * A; };
+  char* c = (char*)workspace;
+  Exec x;
+  x.ws = carve(&p, c, workspace_bytes(&p));
+  c += up(workspace_bytes(&p));
+  float* fields = (float*)c;
+  c += up(sizeof(float) * nf * n3);
+  double* part = (double*)c;
+  c += up(sizeof(double) * kMaskedWgs * nt);
+  double* acc = (double*)c;
+  c += up(sizeof(double) * nt);
+  double* pbox = (double*)c;
+  hipError_t e;
+  auto chk = [&](hipError_t r, const char* what) {
+    if (r != hipSuccess) st = hip_fail(r, what);
+    return r == hipSuccess;
+  };
+  hipLaunchKernelGGL(k_fill_zero, dim3((nt + 255) / 256), dim3(256), 0, s, acc, nt);
+  if (!chk(hipGetLastError(), "masked power: clear")) return st;
+  if (!chk(hipMemcpyAsync(fields, window, sizeof(float) * n3, hipMemcpyDeviceToDevice, s), "masked power: copy"))
+    return st;
+  float* slot_g = fields + n3;              // g_b, also the staging of w a
+  float* slot_v = fields + (size_t)(1 + nb) * n3;
+  const int mul_blocks = (int)std::min<size_t>((n3 + 255) / 256, 8192);
+  for (int i = 0; i < n_grf; ++i) {
+    // g_b = IDFT[Theta_b DFT[w a]]
+    hipLaunchKernelGGL(k_mul_window, dim3(mul_blocks), dim3(256), 0, s, window, grfs[i], slot_g, (long)n3);
+    if (!chk(hipGetLastError(), "masked power: window")) return st;
+    x.io.delta[0] = slot_g;
+    if (!chk(launch_fwd_z(p, x, s), "masked power: fwd_z") || !chk(launch_fwd_y(p, x, s), "masked power: fwd_y") ||
+        !chk(launch_fwd_x(p, x, s), "masked power: fwd_x") || !chk(launch_inv_x(p, x, s), "masked power: inv_x") ||
+        !chk(launch_inv_y(p, x, s), "masked power: inv_y") ||
+        !chk(run_inv_z(p, false, x.ws.a2, slot_g, p.d.tw_m, p.tz, 1, 0, s), "masked power: inv_z"))
+      return st;
+    // v_b = IDFT[Theta_b DFT[a]]
+    x.io.delta[0] = grfs[i];
+    if (!chk(launch_fwd_z(p, x, s), "masked power: fwd_z") || !chk(launch_fwd_y(p, x, s), "masked power: fwd_y") ||
+        !chk(launch_fwd_x(p, x, s), "masked power: fwd_x") || !chk(launch_inv_x(p, x, s), "masked power: inv_x") ||
+        !chk(launch_inv_y(p, x, s), "masked power: inv_y") ||
+        !chk(run_inv_z(p, false, x.ws.a2, slot_v, p.d.tw_m, p.tz, 1, 0, s), "masked power: inv_z"))
+      return st;
+    // sum_x w g_a v_b for every (a, b)
+    if (!chk(contract_simple<float>(fields, nf, (long)n3, p.d.fisher_trips, nt, kMaskedWgs, part, s),
+             "masked power: contraction"))
+      return st;
+    hipLaunchKernelGGL(k_reduce_accum, dim3((nt + 255) / 256), dim3(256), 0, s, part, kMaskedWgs, nt, acc);
+    if (!chk(hipGetLastError(), "masked power: reduce")) return st;
+  }
+  // numerator from the data's box power spectrum, then the solve
+  x.io.delta[0] = data;
+  x.io.pk[0] = pbox;
+  if (!chk(launch_fwd_z(p, x, s), "masked power: fwd_z") || !chk(launch_fwd_y(p, x, s), "masked power: fwd_y") ||
+      !chk(launch_fwd_x(p, x, s), "masked power: fwd_x") || !chk(launch_power(p, x, s), "masked power: power"))
+    return st;
+  hipLaunchKernelGGL(k_masked_solve, dim3(1), dim3(64), sizeof(double) * nb * (nb + 1), s, acc, 0.5 / n_grf, pbox,
+                     p.d.nmodes_d, nb, pk_out, f_out);
+  e = hipGetLastError();
+  if (!chk(e, "masked power: solve")) return st;
+  return PB3_OK;
 }
 
 // -------------------------------------------------------- FP64 counts
