@@ -183,12 +183,14 @@ def batched_bench(reps: int = 10, warmup: int = 2, precision: str = "mixed", aut
     }
 
 
-def serving_bench(n_requests: int = 200, rate: float = 20.0, budget_gb: float = 64.0, slots: int = 4,
-                  precision: str = "mixed") -> dict:
+def serving_bench(n_requests: int = 200, rate: float = 20.0, budget_gb: float = 96.0, slots: int = 4,
+                  precision: str = "mixed", n_mc: int = 8) -> dict:
     """Poisson request stream through the continuous-batching server: grids
     uniform over 64^3..384^3, 10-40 bins (<= 28 on 64^3), each field times a
     sphere-with-holes window (radius 0.45 L, 5% holes, drawn per request on
-    the device), windowed normalisation.  Plans for every geometry in the
+    the device), windowed normalisation, and the unwindowed power spectrum
+    with a Monte Carlo Fisher matrix from ``n_mc`` white random fields per
+    request (drawn on the device, seeds 30000 + 8 i + j).  Plans for every geometry in the
     stream are built and run once before the clock starts (device-resident
     plans, kernels loaded); fields come from a pool of two realizations per
     grid (one at 384^3)."""
@@ -220,10 +222,14 @@ def serving_bench(n_requests: int = 200, rate: float = 20.0, budget_gb: float = 
             holes = torch.rand((n, n, n), generator=gen, device="cuda") < 0.95
             w = (spheres[n] & holes).to(torch.float32)
             data = pool[n][q["field_seed"] % len(pool[n])] * w
+            grfs = []
+            for j in range(n_mc):
+                gen.manual_seed(30000 + 8 * max(q["rid"], 0) + j)
+                grfs.append(torch.randn((n, n, n), generator=gen, device="cuda"))
             ev = torch.cuda.Event()
             ev.record(client)
         return Request(rid=q["rid"], grid=n, box=box, edges=q["edges"], data=data, window=w,
-                       precision=precision, arrival=arrival, ready=ev)
+                       precision=precision, arrival=arrival, ready=ev, grfs=grfs or None)
 
     # device-resident plans for every geometry of the stream, each run once
     # (kernels loaded, allocator segments cached) before the clock starts
@@ -259,8 +265,10 @@ def serving_bench(n_requests: int = 200, rate: float = 20.0, budget_gb: float = 
         "workload": f"Poisson stream, mean {rate:g} req/s, {n_requests} requests; grid uniform over "
                     "64^3/128^3/256^3/384^3, 10-40 bins of width 2k_f (<= 28 at 64^3), L=2000 Mpc/h; "
                     "data = window x field, window = sphere r<0.45L with 5% voxel holes; P+B per request, "
-                    "windowed normalisation",
+                    f"windowed normalisation, unwindowed P with a Monte Carlo Fisher matrix from {n_mc} random "
+                    "fields per request",
         "precision": precision,
+        "n_mc": n_mc,
         "budget_bytes": srv.budget,
         "slots": slots,
         "plan_build_and_warm_s": t_plans,
@@ -338,6 +346,7 @@ def main(argv=None):
     ap.add_argument("--latency-calls", type=int, default=50)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-workload measurement")
     ap.add_argument("--no-autotune", action="store_true", help="default launch shapes instead of timed ones")
+    ap.add_argument("--serve-mc", type=int, default=8, help="random fields per serving request (0: windowed only)")
     ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests in the serving measurement (0 skips it; 2000 for the full stream)")
     args = ap.parse_args(argv)
@@ -442,7 +451,7 @@ def main(argv=None):
     if not args.no_batched:
         line["batched"] = batched_bench(precision=main_p, autotune=not args.no_autotune)
     if args.serve_requests > 0:
-        line["serving"] = serving_bench(args.serve_requests, precision=main_p)
+        line["serving"] = serving_bench(args.serve_requests, precision=main_p, n_mc=args.serve_mc)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(d32, box, edges, plan.n_triplets)
     print(json.dumps(line), flush=True)

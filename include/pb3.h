@@ -73,6 +73,9 @@ typedef enum {
                                        PB3_AUTOTUNE_CACHE naming a text file, choices are read
                                        from it and new ones appended (key: architecture, N, M,
                                        bin thresholds).  Overrides PB3_FLAG_NO_FUSION. */
+#define PB3_FLAG_POWER_ONLY   0x100u /* power spectra only (pb3_power, pb3_masked_power): no
+                                        triplets, no triangle counts, no contraction buffers;
+                                        pb3_bispectrum and batches refuse such a plan */
 
 /* Build a plan for a cubic grid.
  *   grid[3]   grid points per side; all three equal, even, with prime
@@ -147,8 +150,8 @@ pb3_status pb3_window_normalize(const pb3_plan* plan, const float* w_dev, double
  * global line of sight (eq. Q-alpha-global), l = 0, unit weighting, the
  * window as pointing matrix):
  *   p_b   = N_b P_box_b(d) / 2                       (numerator)
- *   F_ab  = (1 / 2 n_grf) sum_i sum_x w g_a^i v_b^i,  g_a = IDFT[Theta_a DFT[w a_i]],
- *                                                      v_b = IDFT[Theta_b DFT[a_i]]
+ *   F_ab  = (1 / 2 n_grf N_pix) sum_i sum_{n in b} conj(DFT[w g_a^i](n)) DFT[a_i](n),
+ *           g_a = IDFT[Theta_a DFT[w a_i]]  (sum over the full spectrum of bin b)
  *   P_b   = (F^-1 p)_b                               (unwindowed estimate)
  * for white unit-variance random fields a_i (so the A^-1 of the paper is the
  * identity; with w = 1 the expectation of F is diag(N_b) / 2 and P is the
@@ -161,10 +164,10 @@ pb3_status pb3_window_normalize(const pb3_plan* plan, const float* w_dev, double
  *   pk_dev     n_bins float64 output, (Mpc/h)^3
  *   fisher_dev n_bins x n_bins float64 output (row a, column b) or NULL
  *   workspace  >= pb3_masked_power_workspace_bytes, 256-byte aligned
- *              ((2 n_bins + 1) N^3 floats of filtered fields plus the plan's
- *              FFT buffers and partial sums)
- * Enqueued on `stream`; the first call on a plan also uploads two small
- * tables synchronously.  Errors: PB3_EINVAL (null argument, host-only plan,
+ *              (n_bins N^3 floats of filtered fields plus the plan's FFT
+ *              buffers and partial sums)
+ * Enqueued on `stream`; the first call on a plan also uploads a small
+ * table synchronously.  Errors: PB3_EINVAL (null argument, host-only plan,
  * plan without the full grid, n_grf < 1), PB3_EUNSUPPORTED (> 48 bins),
  * PB3_ENOMEM (workspace too small), PB3_EDEVICE. */
 size_t pb3_masked_power_workspace_bytes(const pb3_plan* plan);

@@ -57,6 +57,7 @@ class Plan:
         ext_workspace: bool = False,
         fuse: bool = True,
         autotune: bool = False,
+        power_only: bool = False,
     ):
         lib = _lib.load()
         self._lib = lib
@@ -73,6 +74,7 @@ class Plan:
         flags |= _lib.FLAG_EXT_WORKSPACE if ext_workspace else 0
         flags |= 0 if fuse else _lib.FLAG_NO_FUSION
         flags |= _lib.FLAG_AUTOTUNE if autotune else 0
+        flags |= _lib.FLAG_POWER_ONLY if power_only else 0
         h = C.c_void_p()
         _lib.check(
             lib.pb3_plan_create(g, b, e.ctypes.data_as(C.POINTER(C.c_double)), int(e.size), flags, C.byref(h))

@@ -19,6 +19,7 @@ FLAG_EXT_WORKSPACE = 0x10
 FLAG_STAGE_TIMING = 0x20
 FLAG_NO_FUSION = 0x40
 FLAG_AUTOTUNE = 0x80
+FLAG_POWER_ONLY = 0x100
 BATCH_GRAPH = 0x1
 WINDOW_SCRATCH = 514
 BATCH_EXT_WORKSPACE = 0x2

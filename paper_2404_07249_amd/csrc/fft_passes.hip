@@ -55,12 +55,22 @@ __global__ void __launch_bounds__(512) k_fwd_z2(const JobIO io, float2* __restri
   const int pl = tid / TL, tl = tid % TL;
   const int pair = blockIdx.x * TP + pl;
   const bool live = pair < n_pairs;
-  const float* xa = delta + (size_t)(2 * (live ? pair : 0)) * N;
+  const size_t off = (size_t)(2 * (live ? pair : 0)) * N;
+  const float* xa = delta + off;
   const float* xb = xa + N;
+  const float* wa = io.window ? io.window + off : nullptr;  // optional window multiplying the field
   float2* z = zb + pl * LS;
   fft2_line<N, -1>(
       scr + pl * LS, tl, tws,
-      [&](int n) { return live ? make_float2(xa[n], xb[n]) : make_float2(0.f, 0.f); },
+      [&](int n) {
+        if (!live) return make_float2(0.f, 0.f);
+        float2 v = make_float2(xa[n], xb[n]);
+        if (wa) {
+          v.x *= wa[n];
+          v.y *= wa[N + n];
+        }
+        return v;
+      },
       [&](int k, float2 v) { z[k] = v; });
   __syncthreads();
   const int line0 = 2 * blockIdx.x * TP;

@@ -193,6 +193,10 @@ pb3_status pb3_batch_create(pb3_plan* const* plans, int n_jobs, unsigned flags, 
       set_error("batch plans must be device plans (not PB3_FLAG_HOST_ONLY)");
       return PB3_EINVAL;
     }
+    if (plans[j]->flags & PB3_FLAG_POWER_ONLY) {
+      set_error("batch plans must carry bispectrum tables (not PB3_FLAG_POWER_ONLY)");
+      return PB3_EINVAL;
+    }
   }
   int dev = -1;
   hipError_t e = hipGetDevice(&dev);

@@ -114,9 +114,8 @@ static pb3_status upload_twiddles_d(double2** out, int n) {
 
 static void free_device(pb3_plan* p) {
   DeviceTables& d = p->d;
-  void* ptrs[] = {d.lut,      d.modes,      d.chunk,    d.chunk_first, d.geom,   d.tiles,        d.trip_all,
-                  d.out_map,  d.inv_counts, d.pk_scale, d.tw_n,        d.tw_m,   d.tw_m_d,       d.fisher_trips,
-                  d.nmodes_d};
+  void* ptrs[] = {d.lut,     d.modes,      d.chunk,    d.chunk_first, d.geom, d.tiles,  d.trip_all,
+                  d.out_map, d.inv_counts, d.pk_scale, d.tw_n,        d.tw_m, d.tw_m_d, d.nmodes_d};
   for (void* q : ptrs)
     if (q) hipFree(q);
   d = DeviceTables{};
@@ -310,15 +309,16 @@ static pb3_status build_host(pb3_plan* p, const int grid[3], const double box[3]
           p->trip_all.push_back(b);
           p->trip_all.push_back(c);
         }
+  if (flags & PB3_FLAG_POWER_ONLY) p->trip_all.clear();
   if (p->trip_all.size() / 3 > 8192) {
     set_error("more than 8192 triplets not implemented");
     return PB3_EUNSUPPORTED;
   }
   p->trip = p->trip_all;
-  p->fused_ok = fused_supported(p->nb_pad / 16, p->M);
+  p->fused_ok = !(flags & PB3_FLAG_POWER_ONLY) && fused_supported(p->nb_pad / 16, p->M);
   p->fused = !(flags & PB3_FLAG_NO_FUSION) && p->fused_ok;
   p->contract_wgs = 512;
-  p->part_len = mfma_tiles(p->nb_pad / 16) * 256;
+  p->part_len = (flags & PB3_FLAG_POWER_ONLY) ? 0 : mfma_tiles(p->nb_pad / 16) * 256;
   return PB3_OK;
 }
 
@@ -330,7 +330,8 @@ size_t workspace_bytes(const pb3_plan* p) {
   b += align_up(sizeof(float2) * (size_t)p->Lc * p->Lc * p->Kz, A);
   b += align_up(sizeof(float2) * (size_t)p->a1_len, A);
   b += align_up(sizeof(float2) * (size_t)p->a2_len, A);
-  b += p->fused ? 0 : align_up(sizeof(float) * (size_t)p->nb * p->M * p->M * p->M, A);
+  const bool has_g = !p->fused && !(p->flags & PB3_FLAG_POWER_ONLY);
+  b += has_g ? align_up(sizeof(float) * (size_t)p->nb * p->M * p->M * p->M, A) : 0;
   b += align_up(sizeof(float) * (size_t)p->contract_wgs * p->part_len, A);
   b += align_up(sizeof(double) * (size_t)std::max(p->n_chunks, 1), A);
   b += align_up(sizeof(double) * (size_t)kReduceSlices * p->part_len, A);
@@ -354,7 +355,8 @@ Workspace carve(const pb3_plan* p, void* base, size_t bytes) {
   w.dc = (float2*)take(sizeof(float2) * (size_t)p->Lc * p->Lc * p->Kz);
   w.a1 = (float2*)take(sizeof(float2) * (size_t)p->a1_len);
   w.a2 = (float2*)take(sizeof(float2) * (size_t)p->a2_len);
-  w.g = p->fused ? nullptr : (float*)take(sizeof(float) * (size_t)p->nb * p->M * p->M * p->M);
+  const bool has_g = !p->fused && !(p->flags & PB3_FLAG_POWER_ONLY);
+  w.g = has_g ? (float*)take(sizeof(float) * (size_t)p->nb * p->M * p->M * p->M) : nullptr;
   w.part = (float*)take(sizeof(float) * (size_t)p->contract_wgs * p->part_len);
   w.ppart = (double*)take(sizeof(double) * (size_t)std::max(p->n_chunks, 1));
   w.rsl = (double*)take(sizeof(double) * (size_t)kReduceSlices * p->part_len);
@@ -556,7 +558,7 @@ static pb3_status build_device(pb3_plan* p) {
   if ((st = upload(&d.pk_scale, pks.data(), pks.size())) != PB3_OK) return st;
   // triangle counts in FP64 on the contraction grid
   std::vector<double> raw;
-  if ((st = compute_counts_fp64(*p, raw)) != PB3_OK) return st;
+  if (!(p->flags & PB3_FLAG_POWER_ONLY) && (st = compute_counts_fp64(*p, raw)) != PB3_OK) return st;
   const int n_cand = (int)(p->trip_all.size() / 3);
   p->trip.clear();
   p->counts.clear();
@@ -598,7 +600,7 @@ static pb3_status build_device(pb3_plan* p) {
     }
   }
   p->device = true;
-  if (p->flags & PB3_FLAG_AUTOTUNE) return autotune(p, n_cu);
+  if ((p->flags & PB3_FLAG_AUTOTUNE) && !(p->flags & PB3_FLAG_POWER_ONLY)) return autotune(p, n_cu);
   return PB3_OK;
 }
 
@@ -698,6 +700,10 @@ static pb3_status run(pb3_plan* p, const float* delta, double* pk, double* bk, p
   if (st != PB3_OK) return st;
   if (!delta || (!pk && !bk)) {
     set_error("null device pointer");
+    return PB3_EINVAL;
+  }
+  if (bk && (p->flags & PB3_FLAG_POWER_ONLY)) {
+    set_error("plan was created with PB3_FLAG_POWER_ONLY (no bispectrum tables)");
     return PB3_EINVAL;
   }
   if ((st = check_prec(prec)) != PB3_OK) return st;

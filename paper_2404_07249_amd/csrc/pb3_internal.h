@@ -62,6 +62,7 @@ struct JobIO {
   const float* delta[kMaxJobs];
   double* pk[kMaxJobs];
   double* bk[kMaxJobs];
+  const float* window;  // optional (single job): the forward pass transforms window * delta
 };
 
 struct DeviceTables {
@@ -78,8 +79,7 @@ struct DeviceTables {
   float2* tw_n = nullptr;         // W_N^j, j < N
   float2* tw_m = nullptr;         // W_M^j
   double2* tw_m_d = nullptr;      // FP64 twiddles for the count pass
-  int32_t* fisher_trips = nullptr; // masked power: (window, g_a, v_b) field triplets (made on first use)
-  double* nmodes_d = nullptr;      // masked power: N_b as double
+  double* nmodes_d = nullptr;      // masked power: N_b as double (made on first use)
 };
 
 struct Workspace {

@@ -73,8 +73,9 @@ __global__ void __launch_bounds__(256) k_contract_simple(const Rl* __restrict__ 
                                                          const int32_t* __restrict__ trips, int n_trip,
                                                          long vox_per_wg, double* __restrict__ part) {
   constexpr int VT = 64;
+  constexpr int VS = VT + 1;  // odd row stride: threads reading different rows hit different banks
   extern __shared__ unsigned char smem_raw[];
-  Rl* tileg = reinterpret_cast<Rl*>(smem_raw);  // [nb][VT]
+  Rl* tileg = reinterpret_cast<Rl*>(smem_raw);  // [nb][VS]
   const int tid = threadIdx.x;
   double acc[TPT];
   int ta[TPT], tbb[TPT], tc[TPT];
@@ -98,15 +99,15 @@ __global__ void __launch_bounds__(256) k_contract_simple(const Rl* __restrict__ 
     for (int e = tid; e < nb * VT; e += 256) {
       int b = e / VT, j = e % VT;
       long v = v0 + j;
-      tileg[e] = (v < v_end) ? g[(size_t)b * mvox + v] : Rl(0);
+      tileg[b * VS + j] = (v < v_end) ? g[(size_t)b * mvox + v] : Rl(0);
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < TPT; ++i) {
       if (ta[i] >= 0) {
-        const Rl* pa = tileg + ta[i] * VT;
-        const Rl* pb = tileg + tbb[i] * VT;
-        const Rl* pc = tileg + tc[i] * VT;
+        const Rl* pa = tileg + ta[i] * VS;
+        const Rl* pb = tileg + tbb[i] * VS;
+        const Rl* pc = tileg + tc[i] * VS;
         Rl s = Rl(0);
         for (int j = 0; j < VT; ++j) s += pa[j] * pb[j] * pc[j];
         acc[i] += (double)s;
@@ -220,25 +221,44 @@ __global__ void __launch_bounds__(256) k_window_apply(const double* __restrict__
 }
 
 // ------------------------------------------- masked power spectrum (MC)
-// out[i] = w[i] * a[i]
-__global__ void k_mul_window(const float* __restrict__ w, const float* __restrict__ a, float* __restrict__ out,
-                             long n) {
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-    out[i] = w[i] * a[i];
+// Cross spectrum of two compact spectra per bin: each work-group sums
+// w Re(conj(V) A) over one chunk of one bin's mode list in FP64 (w as in
+// the power kernel), then per bin over its chunks in order, accumulated
+// into row[b].
+__global__ void __launch_bounds__(256) k_cross_chunks(const float2* __restrict__ dv, const float2* __restrict__ da,
+                                                      const int32_t* __restrict__ modes,
+                                                      const int32_t* __restrict__ chunks, double* __restrict__ part) {
+  __shared__ double red[256];
+  const int c = blockIdx.x;
+  const int start = chunks[3 * c + 1], end = chunks[3 * c + 2];
+  double acc = 0.0;
+  for (int i = start + threadIdx.x; i < end; i += 256) {
+    const int32_t m = modes[i];
+    const double w = (m < 0) ? 1.0 : 2.0;
+    const float2 v = dv[m & 0x7fffffff], a = da[m & 0x7fffffff];
+    acc += w * ((double)v.x * a.x + (double)v.y * a.y);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[c] = red[0];
+}
+
+__global__ void k_cross_final(const double* __restrict__ part, const int32_t* __restrict__ chunk_first, int nb,
+                              double* __restrict__ row) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  double s = 0.0;
+  for (int c = chunk_first[b]; c < chunk_first[b + 1]; ++c) s += part[c];
+  row[b] += s;
 }
 
 __global__ void k_fill_zero(double* __restrict__ x, int n) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = 0.0;
-}
-
-// out[t] += sum over work-groups (fixed order) of part[w][t]
-__global__ void k_reduce_accum(const double* __restrict__ part, int n_wg, int n_out, double* __restrict__ out) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_out) return;
-  double s = 0.0;
-  for (int w = 0; w < n_wg; ++w) s += part[(size_t)w * n_out + t];
-  out[t] += s;
 }
 
 // F = scale * acc (nb x nb), p_b = N_b P_box_b / 2, solve F x = p by
@@ -328,7 +348,7 @@ template <typename Rl>
 static hipError_t contract_simple(const Rl* g, int nb, long mvox, const int32_t* trips, int n_trip, int n_wg,
                                   double* part, hipStream_t s) {
   long per = (mvox + n_wg - 1) / n_wg;
-  size_t sh = (size_t)nb * 64 * sizeof(Rl);
+  size_t sh = (size_t)nb * 65 * sizeof(Rl);
   switch (tpt_for(n_trip)) {
     case 4:
       hipLaunchKernelGGL((k_contract_simple<Rl, 4>), dim3(n_wg), dim3(256), sh, s, g, nb, mvox, trips, n_trip, per, part);
@@ -367,34 +387,26 @@ hipError_t launch_reduce(const pb3_plan& p, const Exec& x, hipStream_t s) {
 }
 
 // ------------------------------------------- masked power spectrum (MC)
-// Workspace: the plan's workspace, then fields [2 nb + 1][N^3] (window,
-// g_b = IDFT[Theta_b DFT[w a]], v_b = IDFT[Theta_b DFT[a]]), work-group
-// partials [kMaskedWgs][nb^2], the accumulated Fisher sums [nb^2] and the
-// box power spectrum of the data [nb].
-constexpr int kMaskedWgs = 512;
-
+// Per random field a:  g_b = IDFT[Theta_b DFT[w a]] for every bin (inverse
+// passes on the full grid), A = DFT[a] (compact), and for every bin a the
+// compact DFT of w g_a (the window applied in the forward z pass), whose
+// cross spectrum with A over bin b's modes is the Fourier-space dot
+// product of the Fisher estimate (Q^asym_b[a] = Theta_b A).
+// Workspace: the plan's workspace, fields [nb][N^3], the compact A,
+// chunk partials, the Fisher sums [nb^2] and the data's box P [nb].
 size_t masked_workspace_bytes(const pb3_plan& p) {
   const size_t A = 256, n3 = (size_t)p.N * p.N * p.N, nb = (size_t)p.nb;
   auto up = [&](size_t b) { return (b + A - 1) / A * A; };
-  return up(workspace_bytes(&p)) + up(sizeof(float) * (2 * nb + 1) * n3) +
-         up(sizeof(double) * kMaskedWgs * nb * nb) + up(sizeof(double) * nb * nb) + up(sizeof(double) * nb);
+  const size_t dc = (size_t)p.Lc * p.Lc * p.Kz;
+  return up(workspace_bytes(&p)) + up(sizeof(float) * nb * n3) + up(sizeof(float2) * dc) +
+         up(sizeof(double) * std::max(p.n_chunks, 1)) + up(sizeof(double) * nb * nb) + up(sizeof(double) * nb);
 }
 
 static pb3_status masked_tables(pb3_plan& p) {
-  if (p.d.fisher_trips) return PB3_OK;
-  const int nb = p.nb;
-  std::vector<int32_t> t;
-  for (int a = 0; a < nb; ++a)
-    for (int b = 0; b < nb; ++b) {
-      t.push_back(0);
-      t.push_back(1 + a);
-      t.push_back(1 + nb + b);
-    }
+  if (p.d.nmodes_d) return PB3_OK;
   std::vector<double> nm(p.nmodes.begin(), p.nmodes.end());
-  hipError_t e = hipMalloc((void**)&p.d.fisher_trips, sizeof(int32_t) * t.size());
-  if (e == hipSuccess) e = hipMemcpy(p.d.fisher_trips, t.data(), sizeof(int32_t) * t.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMalloc((void**)&p.d.nmodes_d, sizeof(double) * nb);
-  if (e == hipSuccess) e = hipMemcpy(p.d.nmodes_d, nm.data(), sizeof(double) * nb, hipMemcpyHostToDevice);
+  hipError_t e = hipMalloc((void**)&p.d.nmodes_d, sizeof(double) * p.nb);
+  if (e == hipSuccess) e = hipMemcpy(p.d.nmodes_d, nm.data(), sizeof(double) * p.nb, hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "masked power tables");
   return PB3_OK;
 }
@@ -403,66 +415,62 @@ pb3_status run_masked_power(pb3_plan& p, const float* data, const float* window,
                             double* pk_out, double* f_out, void* workspace, hipStream_t s) {
   pb3_status st = masked_tables(p);
   if (st != PB3_OK) return st;
-  const size_t A = 256, n3 = (size_t)p.N * p.N * p.N;
-  const int nb = p.nb, nt = nb * nb, nf = 2 * nb + 1;
+  const size_t A = 256, n3 = (size_t)p.N * p.N * p.N, dcn = (size_t)p.Lc * p.Lc * p.Kz;
+  const int nb = p.nb, nt = nb * nb;
   auto up = [&](size_t b) { return (b + A - 1) / A * A; };
   char* c = (char*)workspace;
   Exec x;
   x.ws = carve(&p, c, workspace_bytes(&p));
   c += up(workspace_bytes(&p));
   float* fields = (float*)c;
-  c += up(sizeof(float) * nf * n3);
-  double* part = (double*)c;
-  c += up(sizeof(double) * kMaskedWgs * nt);
+  c += up(sizeof(float) * nb * n3);
+  float2* dca = (float2*)c;
+  c += up(sizeof(float2) * dcn);
+  double* cpart = (double*)c;
+  c += up(sizeof(double) * std::max(p.n_chunks, 1));
   double* acc = (double*)c;
   c += up(sizeof(double) * nt);
   double* pbox = (double*)c;
-  hipError_t e;
   auto chk = [&](hipError_t r, const char* what) {
     if (r != hipSuccess) st = hip_fail(r, what);
     return r == hipSuccess;
   };
+  auto forward = [&](const float* f, const float* w) {
+    x.io.delta[0] = f;
+    x.io.window = w;
+    return chk(launch_fwd_z(p, x, s), "masked power: fwd_z") && chk(launch_fwd_y(p, x, s), "masked power: fwd_y") &&
+           chk(launch_fwd_x(p, x, s), "masked power: fwd_x");
+  };
   hipLaunchKernelGGL(k_fill_zero, dim3((nt + 255) / 256), dim3(256), 0, s, acc, nt);
   if (!chk(hipGetLastError(), "masked power: clear")) return st;
-  if (!chk(hipMemcpyAsync(fields, window, sizeof(float) * n3, hipMemcpyDeviceToDevice, s), "masked power: copy"))
-    return st;
-  float* slot_g = fields + n3;              // g_b, also the staging of w a
-  float* slot_v = fields + (size_t)(1 + nb) * n3;
-  const int mul_blocks = (int)std::min<size_t>((n3 + 255) / 256, 8192);
   for (int i = 0; i < n_grf; ++i) {
-    // g_b = IDFT[Theta_b DFT[w a]]
-    hipLaunchKernelGGL(k_mul_window, dim3(mul_blocks), dim3(256), 0, s, window, grfs[i], slot_g, (long)n3);
-    if (!chk(hipGetLastError(), "masked power: window")) return st;
-    x.io.delta[0] = slot_g;
-    if (!chk(launch_fwd_z(p, x, s), "masked power: fwd_z") || !chk(launch_fwd_y(p, x, s), "masked power: fwd_y") ||
-        !chk(launch_fwd_x(p, x, s), "masked power: fwd_x") || !chk(launch_inv_x(p, x, s), "masked power: inv_x") ||
+    // A = DFT[a], kept aside
+    if (!forward(grfs[i], nullptr)) return st;
+    if (!chk(hipMemcpyAsync(dca, x.ws.dc, sizeof(float2) * dcn, hipMemcpyDeviceToDevice, s), "masked power: copy"))
+      return st;
+    // g_b = IDFT[Theta_b DFT[w a]] on the full grid
+    if (!forward(grfs[i], window) || !chk(launch_inv_x(p, x, s), "masked power: inv_x") ||
         !chk(launch_inv_y(p, x, s), "masked power: inv_y") ||
-        !chk(run_inv_z(p, false, x.ws.a2, slot_g, p.d.tw_m, p.tz, 1, 0, s), "masked power: inv_z"))
+        !chk(run_inv_z(p, false, x.ws.a2, fields, p.d.tw_m, p.tz, 1, 0, s), "masked power: inv_z"))
       return st;
-    // v_b = IDFT[Theta_b DFT[a]]
-    x.io.delta[0] = grfs[i];
-    if (!chk(launch_fwd_z(p, x, s), "masked power: fwd_z") || !chk(launch_fwd_y(p, x, s), "masked power: fwd_y") ||
-        !chk(launch_fwd_x(p, x, s), "masked power: fwd_x") || !chk(launch_inv_x(p, x, s), "masked power: inv_x") ||
-        !chk(launch_inv_y(p, x, s), "masked power: inv_y") ||
-        !chk(run_inv_z(p, false, x.ws.a2, slot_v, p.d.tw_m, p.tz, 1, 0, s), "masked power: inv_z"))
-      return st;
-    // sum_x w g_a v_b for every (a, b)
-    if (!chk(contract_simple<float>(fields, nf, (long)n3, p.d.fisher_trips, nt, kMaskedWgs, part, s),
-             "masked power: contraction"))
-      return st;
-    hipLaunchKernelGGL(k_reduce_accum, dim3((nt + 255) / 256), dim3(256), 0, s, part, kMaskedWgs, nt, acc);
-    if (!chk(hipGetLastError(), "masked power: reduce")) return st;
+    // row a: cross spectrum of DFT[w g_a] with A per bin
+    for (int a = 0; a < nb; ++a) {
+      if (!forward(fields + (size_t)a * n3, window)) return st;
+      hipLaunchKernelGGL(k_cross_chunks, dim3(p.n_chunks), dim3(256), 0, s, x.ws.dc, dca, p.d.modes, p.d.chunk,
+                         cpart);
+      if (!chk(hipGetLastError(), "masked power: cross")) return st;
+      hipLaunchKernelGGL(k_cross_final, dim3((nb + 63) / 64), dim3(64), 0, s, cpart, p.d.chunk_first, nb,
+                         acc + (size_t)a * nb);
+      if (!chk(hipGetLastError(), "masked power: cross")) return st;
+    }
   }
   // numerator from the data's box power spectrum, then the solve
-  x.io.delta[0] = data;
   x.io.pk[0] = pbox;
-  if (!chk(launch_fwd_z(p, x, s), "masked power: fwd_z") || !chk(launch_fwd_y(p, x, s), "masked power: fwd_y") ||
-      !chk(launch_fwd_x(p, x, s), "masked power: fwd_x") || !chk(launch_power(p, x, s), "masked power: power"))
-    return st;
-  hipLaunchKernelGGL(k_masked_solve, dim3(1), dim3(64), sizeof(double) * nb * (nb + 1), s, acc, 0.5 / n_grf, pbox,
+  if (!forward(data, nullptr) || !chk(launch_power(p, x, s), "masked power: power")) return st;
+  const double scale = 0.5 / ((double)n3 * n_grf);
+  hipLaunchKernelGGL(k_masked_solve, dim3(1), dim3(64), sizeof(double) * nb * (nb + 1), s, acc, scale, pbox,
                      p.d.nmodes_d, nb, pk_out, f_out);
-  e = hipGetLastError();
-  if (!chk(e, "masked power: solve")) return st;
+  if (!chk(hipGetLastError(), "masked power: solve")) return st;
   return PB3_OK;
 }
 

@@ -16,7 +16,9 @@ bispectrum on their own grid and binning.  The server
   event has fired, freeing the slot and the memory;
 * normalises masked requests by the window moments (P / <w^2>,
   B / <w^3>: the conventional windowed estimators of Sec. III.D.2 and
-  Sec. IV.D.2);
+  Sec. IV.D.2), and, when the request brings random fields, also returns
+  the unwindowed power spectrum with the Monte Carlo Fisher matrix of
+  Sec. III.C.2 (pb3_masked_power, on a full-grid power-only plan);
 * records arrival, admission and completion times per request.
 
 Each job's result depends only on its own inputs: the kernels and their
@@ -62,6 +64,7 @@ class Request:
     arrival: float | None = None
     ready: object = None
     deadline: float | None = None
+    grfs: list | None = None  # white unit-variance N^3 CUDA fields for the Monte Carlo Fisher matrix
 
 
 @dataclass
@@ -71,6 +74,8 @@ class Completed:
     pk: np.ndarray | None = None
     bk: np.ndarray | None = None
     moments: np.ndarray | None = None  # (<w^2>, <w^3>) for masked requests
+    pk_unwindowed: np.ndarray | None = None  # F^-1 p with the Monte Carlo Fisher matrix
+    fisher: np.ndarray | None = None
     arrival: float = 0.0
     admitted: float = 0.0
     done: float = 0.0
@@ -99,6 +104,7 @@ class _Running:
     pks: list
     bks: list
     scratch: list
+    unw: list
     event: object
     nbytes: int
     admitted: float
@@ -137,6 +143,7 @@ class Server:
         self.running: list[_Running] = []
         self.done: dict[int, Completed] = {}
         self.plans: dict = {}
+        self.full_plans: dict = {}  # full-grid power-only plans for the Monte Carlo Fisher matrix
         self.pool: dict = {}  # (plan key, jobs) -> idle Batch objects (no workspace held)
         self.bytes_in_use = 0
         self.stats = _Stats()
@@ -150,16 +157,29 @@ class Server:
             self.plans[key] = p
         return p
 
+    def full_plan_for(self, grid: int, box: float, edges) -> Plan:
+        key = (int(grid), float(box), tuple(np.asarray(edges, dtype=np.float64).tolist()))
+        p = self.full_plans.get(key)
+        if p is None:
+            p = Plan(grid, box, edges, full_grid=True, power_only=True, ext_workspace=True)
+            self.full_plans[key] = p
+        return p
+
     @staticmethod
     def _plan_key(req: Request):
         return (int(req.grid), float(req.box), tuple(np.asarray(req.edges, dtype=np.float64).tolist()))
 
-    def job_bytes(self, plan: Plan, masked: bool) -> int:
-        """HBM one job holds while it runs: its workspace, outputs and the
-        window scratch."""
+    def job_bytes(self, plan: Plan, masked: bool, full: Plan | None = None) -> int:
+        """HBM one job holds while it runs: its workspace, outputs, the
+        window scratch and, with random fields, the Monte Carlo workspace."""
         out = 8 * (plan.n_bins + plan.n_triplets)
         scr = 8 * _lib.WINDOW_SCRATCH if masked else 0
-        return int(plan.workspace_bytes) + out + scr + 512
+        mc = 0 if full is None else int(full.masked_workspace_bytes) + 8 * plan.n_bins * (plan.n_bins + 1) + 512
+        return int(plan.workspace_bytes) + out + scr + mc + 512
+
+    def _req_bytes(self, plan: Plan, r: Request) -> int:
+        full = self.full_plan_for(r.grid, r.box, r.edges) if r.grfs else None
+        return self.job_bytes(plan, r.window is not None, full)
 
     # ----------------------------------------------------------- submit
     def submit(self, req: Request):
@@ -170,6 +190,8 @@ class Server:
             raise ValueError("data shape does not match the grid")
         if req.window is not None and tuple(req.window.shape) != (n, n, n):
             raise ValueError("window shape does not match the grid")
+        if req.grfs and req.window is None:
+            raise ValueError("random fields are for masked requests (a window is needed)")
         self.queue.append(req)
         self.stats.max_queue = max(self.stats.max_queue, len(self.queue))
 
@@ -218,7 +240,13 @@ class Server:
                 self.done[head.rid] = Completed(head.rid, "error", arrival=head.arrival,
                                                 done=time.perf_counter(), message=str(e))
                 continue
-            need_one = self.job_bytes(plan, head.window is not None)
+            try:
+                need_one = self._req_bytes(plan, head)
+            except Pb3Error as e:
+                self.queue.popleft()
+                self.done[head.rid] = Completed(head.rid, "error", arrival=head.arrival,
+                                                done=time.perf_counter(), message=str(e))
+                continue
             if need_one > self.budget:
                 self.queue.popleft()
                 self.done[head.rid] = Completed(head.rid, "rejected", arrival=head.arrival,
@@ -236,7 +264,7 @@ class Server:
                     if len(group) >= _MAX_JOBS_PER_LAUNCH:
                         break
                     if self._plan_key(r) == key and r.precision == head.precision:
-                        nb = self.job_bytes(plan, r.window is not None)
+                        nb = self._req_bytes(plan, r)
                         if self.bytes_in_use + used + nb > self.budget:
                             break
                         group.append(r)
@@ -262,8 +290,15 @@ class Server:
             pks = [torch.empty(plan.n_bins, dtype=torch.float64, device="cuda") for _ in group]
             bks = [torch.empty(plan.n_triplets, dtype=torch.float64, device="cuda") for _ in group]
             batch.run([r.data for r in group], group[0].precision, pk_outs=pks, bk_outs=bks, stream=stream)
-            scratch = []
+            scratch, unw = [], []
             for r, pk, bk in zip(group, pks, bks):
+                mc = None
+                if r.grfs:
+                    # before the window normalisation, which rescales pk in place
+                    full = self.full_plan_for(r.grid, r.box, r.edges)
+                    mws = torch.empty(full.masked_workspace_bytes, dtype=torch.uint8, device="cuda")
+                    mc = full.masked_power(r.data, r.window, r.grfs, workspace=mws, stream=stream)
+                unw.append(mc)
                 if r.window is not None:
                     sc = torch.empty(_lib.WINDOW_SCRATCH, dtype=torch.float64, device="cuda")
                     plan.window_normalize(r.window, pk, bk, scratch=sc, stream=stream)
@@ -272,7 +307,7 @@ class Server:
                     scratch.append(None)
             ev = torch.cuda.Event()
             ev.record(stream)
-        self.running.append(_Running(group, slot, batch, ws, pks, bks, scratch, ev, nbytes, now, pkey))
+        self.running.append(_Running(group, slot, batch, ws, pks, bks, scratch, unw, ev, nbytes, now, pkey))
         self.bytes_in_use += nbytes
         st = self.stats
         st.admitted += len(group)
@@ -287,10 +322,12 @@ class Server:
             if not run.event.query():
                 continue
             now = time.perf_counter()
-            for r, pk, bk, sc in zip(run.reqs, run.pks, run.bks, run.scratch):
+            for r, pk, bk, sc, mc in zip(run.reqs, run.pks, run.bks, run.scratch, run.unw):
                 self.done[r.rid] = Completed(
                     r.rid, "ok", pk=pk.cpu().numpy(), bk=bk.cpu().numpy(),
                     moments=None if sc is None else sc[:2].cpu().numpy(),
+                    pk_unwindowed=None if mc is None else mc[0].cpu().numpy(),
+                    fisher=None if mc is None else mc[1].cpu().numpy(),
                     arrival=r.arrival, admitted=run.admitted, done=now, batch_size=len(run.reqs))
                 n += 1
             self.running.remove(run)

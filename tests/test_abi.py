@@ -145,3 +145,12 @@ def test_launch_shape_query_on_host_plan():
     p = _plan(64, 1000.0, kf_edges(8))
     shape = p.launch_shape
     assert shape["tuned"] == "default" and shape["contract_wgs"] > 0
+
+
+def test_power_only_plan_has_no_triplets():
+    import paper_2404_07249_amd as pb3
+
+    p = pb3.Plan(128, 1000.0, kf_edges(40), host_only=True, power_only=True)
+    full = pb3.Plan(128, 1000.0, kf_edges(40), host_only=True)
+    assert p.n_triplets == 0 and full.n_triplets > 0
+    assert p.workspace_bytes < full.workspace_bytes

@@ -49,7 +49,7 @@ def test_masked_power_matches_oracle(torch_cuda, n, box, nbins, ngrf):
     d = (quadratic_field(n, box, 1.0, 10000 + n) * w).astype(np.float32)
     rng = np.random.default_rng(30000 + n)
     grfs = [rng.standard_normal((n, n, n)).astype(np.float32) for _ in range(ngrf)]
-    plan = pb3.Plan(n, box, edges, full_grid=True)
+    plan = pb3.Plan(n, box, edges, full_grid=True, power_only=n >= 64)
     pk, F = plan.masked_power(_gpu(torch, d), _gpu(torch, w), [_gpu(torch, g) for g in grfs])
     pk, F = pk.cpu().numpy(), F.cpu().numpy()
     F_ref = masked.mc_fisher_power(w.astype(np.float64), [g.astype(np.float64) for g in grfs], edges)
@@ -98,8 +98,12 @@ def test_masked_power_argument_errors(torch_cuda):
     x = torch.zeros((n, n, n), dtype=torch.float32, device="cuda")
     with pytest.raises(pb3.Pb3Error):
         plan.masked_power(x, x, [x])
-    full = pb3.Plan(32, 500.0, kf_edges(4), full_grid=True)
+    full = pb3.Plan(32, 500.0, kf_edges(4), full_grid=True, power_only=True)
+    assert full.n_triplets == 0
     y = torch.zeros((32, 32, 32), dtype=torch.float32, device="cuda")
     small = torch.empty(16, dtype=torch.uint8, device="cuda")
     with pytest.raises(pb3.Pb3Error):
         full.masked_power(y, y, [y], workspace=small)
+    with pytest.raises(pb3.Pb3Error):
+        full.bispectrum(y)  # no bispectrum tables
+    full.power(y)

@@ -48,10 +48,14 @@ def _requests(torch, count=14, masked_every=2, seed0=300):
         d = quadratic_field(n, box, 1.0, seed0 + i).astype(np.float32)
         w = window_mask(n, seed0 + 1000 + i) if i % masked_every == 0 else None
         data = d * w if w is not None else d
+        grfs = None
+        if w is not None and i % 4 == 0:
+            rng = np.random.default_rng(seed0 + 2000 + i)
+            grfs = [torch.from_numpy(rng.standard_normal((n, n, n)).astype(np.float32)).cuda() for _ in range(2)]
         reqs.append(Request(rid=i, grid=n, box=box, edges=e,
                             data=torch.from_numpy(data).cuda(),
                             window=None if w is None else torch.from_numpy(w).cuda(),
-                            precision="mixed" if i % 3 else "fp32"))
+                            precision="mixed" if i % 3 else "fp32", grfs=grfs))
         host.append((data, w))
     return reqs, host
 
@@ -70,6 +74,7 @@ def _alone(server, torch, r):
 
 
 def test_serve_mix_equals_alone_and_oracle(torch_cuda):
+    import paper_2404_07249_amd as pb3
     from paper_2404_07249_amd.serve import Server
 
     torch = torch_cuda
@@ -87,6 +92,12 @@ def test_serve_mix_equals_alone_and_oracle(torch_cuda):
         c = srv.done[r.rid]
         assert np.array_equal(c.pk, pk), r.rid
         assert np.array_equal(c.bk, bk), r.rid
+        if r.grfs:
+            full = pb3.Plan(r.grid, r.box, r.edges, full_grid=True, power_only=True)
+            pu, F = full.masked_power(r.data, r.window, r.grfs)
+            assert np.array_equal(c.pk_unwindowed, pu.cpu().numpy()), r.rid
+            assert np.array_equal(c.fisher, F.cpu().numpy()), r.rid
+    assert sum(1 for r in reqs if r.grfs) >= 2
     # masked requests against the oracle's windowed estimators
     for i in (0, 2):
         r = reqs[i]
