@@ -22,6 +22,12 @@ Parity status of each function (what pins it is in ``tests/test_oracle.py``):
                            Monte Carlo average converges to it; the
                            unwindowed estimate is unbiased for a flat
                            spectrum under a window.
+* ``multipoles`` (global line of sight) pinned: the separable bispectrum
+                           multipole sum equals explicit mode-triangle loops
+                           with the Legendre weight on k_3; the power
+                           multipoles with the discrete Fisher matrix are
+                           unbiased for an anisotropic Gaussian field;
+                           invariance under x-y exchange and z reflection.
 """
 
 from .polyspec import (  # noqa: F401
@@ -47,3 +53,4 @@ from .polyspec import (  # noqa: F401
 )
 from .brute import brute_sums  # noqa: F401
 from . import masked  # noqa: F401,E402
+from . import multipoles  # noqa: F401,E402
