@@ -45,12 +45,14 @@ FP32_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 MEASURED_TRAFFIC = {
     ("contract", "mixed"): {
         "kernel": "k_zcontract<2, true, 192>",
-        "fetch_kib": 141582.2, "write_kib": 22528.0, "fetch_factor": 2.0, "write_factor": 1.0,
+        "fetch_kib": 141602.0, "write_kib": 22528.0, "fetch_factor": 2.0, "write_factor": 1.0,
         "sources": {
             "paper_2404_07249_amd/csrc/contract_mfma.hip":
-                "4391e5c1690c4387cdd4f3037750c341f5582050c893bd276200d6c890ae36a3",
+                "44a4149a8586b25d04672896a20440383182d2f7ad9c1ae5e08d22ed4952eee6",
             "paper_2404_07249_amd/csrc/fft_dev.h":
                 "445483e27faf3491134cb99e4822494520ab3d6b22f80871c30bdb01f5151c73",
+            "paper_2404_07249_amd/csrc/job.h":
+                "4d45c966d118d35d1d6f480aab9a46b0d40c3d5f1aef4f07cadd0a64b11be044",
         },
     },
 }
