@@ -73,6 +73,8 @@ typedef enum {
                                        PB3_AUTOTUNE_CACHE naming a text file, choices are read
                                        from it and new ones appended (key: architecture, N, M,
                                        bin thresholds).  Overrides PB3_FLAG_NO_FUSION. */
+#define PB3_FLAG_LMAX2        0x200u /* multipoles up to l = 2 (pb3_multipoles) */
+#define PB3_FLAG_LMAX4        0x400u /* multipoles up to l = 4 (pb3_multipoles) */
 #define PB3_FLAG_POWER_ONLY   0x100u /* power spectra only (pb3_power, pb3_masked_power): no
                                         triplets, no triangle counts, no contraction buffers;
                                         pb3_bispectrum and batches refuse such a plan */
@@ -174,6 +176,29 @@ size_t pb3_masked_power_workspace_bytes(const pb3_plan* plan);
 pb3_status pb3_masked_power(pb3_plan* plan, const float* data_dev, const float* window_dev,
                             const float* const* grfs_dev, int n_grf, double* pk_dev, double* fisher_dev,
                             void* workspace_dev, size_t workspace_bytes, void* stream);
+
+/* Multipoles l = 0, 2 (, 4) with a global line of sight along the grid's z
+ * axis, for plans made with PB3_FLAG_LMAX2 or PB3_FLAG_LMAX4:
+ *   P_{b,l}   = sum_l' (F_b^-1)_{l l'} p_{b,l'},  p_{b,l} = (V/N_pix^2) sum_{n in b} L_l(mu_n) |D(n)|^2,
+ *               F_b[l][l'] = sum_{n in b} L_l(mu_n) L_l'(mu_n)  -- eq. (pk-limit) with its
+ *               discrete Fisher matrix, which keeps the l-l' couplings of the finite
+ *               Fourier grid (Sec. III.D.1); mu_n = n_z / |n|;
+ *   B_{abc,l} = (2l + 1) (V^2/N_pix) sum_x G_a G_b g_{c,l} / T_abc,
+ *               g_{c,l} = IDFT[Theta_c L_l(mu) D]  -- eq. (ideal-bk), the Legendre weight on
+ *               k_3 (the mode in the largest bin), evaluated through the separable
+ *               form of Sec. IV.D.1 (l = 0 is pb3_bispectrum's B).
+ * pb3_n_ell gives the number of multipoles (lmax/2 + 1).  pk_dev: n_ell x n_bins
+ * float64 (row l/2), bk_dev: n_ell x n_trip float64; either may be NULL (not
+ * both).  The contraction runs in FP32 with FP64 accumulation of its tile
+ * sums.  workspace: >= pb3_multipoles_workspace_bytes, 256-byte aligned
+ * (n_ell x n_bins filtered fields on the contraction grid plus partial sums).
+ * Errors: PB3_EINVAL (plan without multipoles, null arguments, power-only
+ * plan asked for B; at creation: a bin whose modes cannot separate the
+ * multipoles), PB3_ENOMEM (workspace too small), PB3_EDEVICE. */
+int pb3_n_ell(const pb3_plan* plan);
+size_t pb3_multipoles_workspace_bytes(const pb3_plan* plan);
+pb3_status pb3_multipoles(pb3_plan* plan, const float* delta_dev, double* pk_dev, double* bk_dev,
+                          void* workspace_dev, size_t workspace_bytes, void* stream);
 
 /* Stage timing (plans made with PB3_FLAG_STAGE_TIMING): every call records
  * a HIP event pair around each kernel launch on the call's stream.

@@ -58,6 +58,7 @@ class Plan:
         fuse: bool = True,
         autotune: bool = False,
         power_only: bool = False,
+        lmax: int = 0,
     ):
         lib = _lib.load()
         self._lib = lib
@@ -75,6 +76,9 @@ class Plan:
         flags |= 0 if fuse else _lib.FLAG_NO_FUSION
         flags |= _lib.FLAG_AUTOTUNE if autotune else 0
         flags |= _lib.FLAG_POWER_ONLY if power_only else 0
+        if lmax not in (0, 2, 4):
+            raise ValueError("lmax must be 0, 2 or 4")
+        flags |= {0: 0, 2: _lib.FLAG_LMAX2, 4: _lib.FLAG_LMAX4}[lmax]
         h = C.c_void_p()
         _lib.check(
             lib.pb3_plan_create(g, b, e.ctypes.data_as(C.POINTER(C.c_double)), int(e.size), flags, C.byref(h))
@@ -240,6 +244,28 @@ class Plan:
             C.c_void_p(pk.data_ptr()), C.c_void_p(fm.data_ptr()), C.c_void_p(workspace.data_ptr()),
             workspace.numel() * workspace.element_size(), _stream_handle(stream)))
         return pk, fm
+
+    @property
+    def n_ell(self) -> int:
+        return int(self._lib.pb3_n_ell(self._h))
+
+    def multipoles(self, delta, power: bool = True, bispectrum: bool = True, workspace=None, stream=None):
+        """(P_l [n_ell, n_bins] or None, B_l [n_ell, n_trip] or None) for
+        l = 0, 2, (4) with the line of sight along z (plans made with lmax > 0)."""
+        import torch
+
+        self._check_field(delta)
+        ne = self.n_ell
+        pk = torch.empty((ne, self.n_bins), dtype=torch.float64, device=delta.device) if power else None
+        bk = torch.empty((ne, self.n_triplets), dtype=torch.float64, device=delta.device) if bispectrum else None
+        if workspace is None:
+            nbytes = int(self._lib.pb3_multipoles_workspace_bytes(self._h))
+            workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=delta.device)
+        _lib.check(self._lib.pb3_multipoles(
+            self._h, C.c_void_p(delta.data_ptr()), C.c_void_p(pk.data_ptr() if pk is not None else 0),
+            C.c_void_p(bk.data_ptr() if bk is not None else 0), C.c_void_p(workspace.data_ptr()),
+            workspace.numel() * workspace.element_size(), _stream_handle(stream)))
+        return pk, bk
 
     def stage_times(self) -> dict:
         """Mean milliseconds per kernel stage over the calls since the last

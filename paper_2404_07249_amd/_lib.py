@@ -20,6 +20,8 @@ FLAG_STAGE_TIMING = 0x20
 FLAG_NO_FUSION = 0x40
 FLAG_AUTOTUNE = 0x80
 FLAG_POWER_ONLY = 0x100
+FLAG_LMAX2 = 0x200
+FLAG_LMAX4 = 0x400
 BATCH_GRAPH = 0x1
 WINDOW_SCRATCH = 514
 BATCH_EXT_WORKSPACE = 0x2
@@ -50,6 +52,9 @@ SIGNATURES = [
     ("pb3_masked_power", C.c_int,
      [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p), C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
       C.c_size_t, C.c_void_p]),
+    ("pb3_n_ell", C.c_int, [C.c_void_p]),
+    ("pb3_multipoles_workspace_bytes", C.c_size_t, [C.c_void_p]),
+    ("pb3_multipoles", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     ("pb3_stage_times", C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_int)]),
     ("pb3_stage_timing_reset", C.c_int, [C.c_void_p]),
     ("pb3_stage_name", C.c_char_p, [C.c_int]),

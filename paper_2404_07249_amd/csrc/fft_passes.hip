@@ -125,7 +125,8 @@ template <int M, typename Rl, bool UNIT>
 __global__ void __launch_bounds__(512) k_inv_x2(const float2* __restrict__ dc, typename Cx<Rl>::type* __restrict__ a1,
                                                 const BinGeom* __restrict__ geom, const BinTile* __restrict__ tiles,
                                                 const int8_t* __restrict__ lut, int Kc, int Lc, int Kz,
-                                                const typename Cx<Rl>::type* __restrict__ tw, size_t wstride) {
+                                                const typename Cx<Rl>::type* __restrict__ tw, size_t wstride,
+                                                int ell) {
   dc = job_ptr(dc, wstride);
   a1 = job_ptr(a1, wstride);
   using C = typename Cx<Rl>::type;
@@ -157,6 +158,13 @@ __global__ void __launch_bounds__(512) k_inv_x2(const float2* __restrict__ dc, t
               v = cx<C>(Rl(1), Rl(0));
             } else {
               float2 d = dc[((size_t)(kx + Kc) * Lc + (ky + Kc)) * Kz + kz];
+              if (ell) {  // Legendre weight L_ell(mu), mu = kz / |k| (line of sight along z)
+                const float k2 = (float)(kx * kx + ky * ky + kz * kz);
+                const float m2 = k2 > 0.f ? (float)(kz * kz) / k2 : 0.f;
+                const float L = ell == 2 ? 1.5f * m2 - 0.5f : (35.f * m2 * m2 - 30.f * m2 + 3.f) * 0.125f;
+                d.x *= L;
+                d.y *= L;
+              }
               v = cx<C>(Rl(d.x), Rl(d.y));
             }
           }
@@ -328,21 +336,22 @@ hipError_t launch_fwd_x(const pb3_plan& p, const Exec& x, hipStream_t s) {
 }
 
 hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, const float2* dc, void* a1, const void* tw,
-                     const TileSet& ts, int n_jobs, size_t wstride, hipStream_t s) {
+                     const TileSet& ts, int n_jobs, size_t wstride, hipStream_t s, int ell) {
   if (ts.n == 0) return hipSuccess;
   PB3_FFT_LEN(p.M, {
     if (dbl) {
       using S = ColShape<LL, 16>;
       if (unit)
         hipLaunchKernelGGL((k_inv_x2<LL, double, true>), dim3(ts.n, 1, n_jobs), dim3(S::NT), 0, s, dc,
-                           (double2*)a1, p.d.geom, ts.d, p.d.lut, p.Kc, p.Lc, p.Kz, (const double2*)tw, wstride);
+                           (double2*)a1, p.d.geom, ts.d, p.d.lut, p.Kc, p.Lc, p.Kz, (const double2*)tw, wstride,
+                           0);
       else
         return hipErrorInvalidValue;
     } else {
       using S = ColShape<LL, 8>;
       if (unit) return hipErrorInvalidValue;
       hipLaunchKernelGGL((k_inv_x2<LL, float, false>), dim3(ts.n, 1, n_jobs), dim3(S::NT), 0, s, dc, (float2*)a1,
-                         p.d.geom, ts.d, p.d.lut, p.Kc, p.Lc, p.Kz, (const float2*)tw, wstride);
+                         p.d.geom, ts.d, p.d.lut, p.Kc, p.Lc, p.Kz, (const float2*)tw, wstride, ell);
     }
     return hipGetLastError();
   });

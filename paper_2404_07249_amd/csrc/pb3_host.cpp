@@ -114,8 +114,9 @@ static pb3_status upload_twiddles_d(double2** out, int n) {
 
 static void free_device(pb3_plan* p) {
   DeviceTables& d = p->d;
-  void* ptrs[] = {d.lut,     d.modes,      d.chunk,    d.chunk_first, d.geom, d.tiles,  d.trip_all,
-                  d.out_map, d.inv_counts, d.pk_scale, d.tw_n,        d.tw_m, d.tw_m_d, d.nmodes_d};
+  void* ptrs[] = {d.lut,      d.modes,      d.chunk,    d.chunk_first, d.geom,    d.tiles,  d.trip_all,
+                  d.out_map,  d.inv_counts, d.pk_scale, d.tw_n,        d.tw_m,    d.tw_m_d, d.nmodes_d,
+                  d.pml_inv,  d.ml_trips,   d.ml_fac,   d.ml_map};
   for (void* q : ptrs)
     if (q) hipFree(q);
   d = DeviceTables{};
@@ -231,6 +232,9 @@ static pb3_status build_host(pb3_plan* p, const int grid[3], const double box[3]
   // modes of the compact half spectrum, per bin
   std::vector<std::vector<int32_t>> per(nb);
   p->nmodes.assign(nb, 0);
+  p->lmax = (flags & PB3_FLAG_LMAX4) ? 4 : (flags & PB3_FLAG_LMAX2) ? 2 : 0;
+  const int ne = p->lmax / 2 + 1;
+  std::vector<double> msum((size_t)nb * ne * ne, 0.0);  // per bin: sum over its modes of L_i L_j
   std::vector<double> ksum(nb, 0.0);
   for (int cx = 0; cx < p->Lc; ++cx) {
     int kx = cx - p->Kc;
@@ -247,6 +251,12 @@ static pb3_status build_host(pb3_plan* p, const int grid[3], const double box[3]
         int w = self ? 1 : 2;
         p->nmodes[b] += w;
         ksum[b] += w * std::sqrt((double)n2) * kf;
+        if (ne > 1) {
+          const double m2 = n2 > 0 ? (double)kz * kz / (double)n2 : 0.0;
+          const double L[3] = {1.0, 1.5 * m2 - 0.5, (35.0 * m2 * m2 - 30.0 * m2 + 3.0) / 8.0};
+          for (int i = 0; i < ne; ++i)
+            for (int j = 0; j < ne; ++j) msum[((size_t)b * ne + i) * ne + j] += w * L[i] * L[j];
+        }
       }
     }
   }
@@ -258,6 +268,39 @@ static pb3_status build_host(pb3_plan* p, const int grid[3], const double box[3]
   }
   p->kmean.resize(nb);
   for (int b = 0; b < nb; ++b) p->kmean[b] = ksum[b] / (double)p->nmodes[b];
+  // power multipoles: per bin, the inverse of the discrete Fisher matrix
+  // (1/2) sum_n L_i L_j (its 1/2 cancels the numerator's), times V / N_pix^2
+  if (ne > 1) {
+    const double npix = (double)N * N * N;
+    const double sc = box[0] * box[0] * box[0] / (npix * npix);
+    p->pml_inv.assign((size_t)nb * ne * ne, 0.0);
+    for (int b = 0; b < nb; ++b) {
+      double a[3][6] = {};
+      for (int i = 0; i < ne; ++i) {
+        for (int j = 0; j < ne; ++j) a[i][j] = msum[((size_t)b * ne + i) * ne + j];
+        a[i][ne + i] = 1.0;
+      }
+      for (int k = 0; k < ne; ++k) {  // Gauss-Jordan with partial pivoting
+        int pr = k;
+        for (int r = k + 1; r < ne; ++r)
+          if (std::fabs(a[r][k]) > std::fabs(a[pr][k])) pr = r;
+        if (std::fabs(a[pr][k]) < 1e-9 * (double)p->nmodes[b]) {
+          set_error("bin " + std::to_string(b) + " has too few mode directions to separate the multipoles");
+          return PB3_EINVAL;
+        }
+        for (int c = 0; c < 2 * ne; ++c) std::swap(a[k][c], a[pr][c]);
+        const double d = a[k][k];
+        for (int c = 0; c < 2 * ne; ++c) a[k][c] /= d;
+        for (int r = 0; r < ne; ++r)
+          if (r != k) {
+            const double f = a[r][k];
+            for (int c = 0; c < 2 * ne; ++c) a[r][c] -= f * a[k][c];
+          }
+      }
+      for (int i = 0; i < ne; ++i)
+        for (int j = 0; j < ne; ++j) p->pml_inv[((size_t)b * ne + i) * ne + j] = sc * a[i][ne + j];
+    }
+  }
   p->modes.clear();
   p->chunks.clear();
   const int CH = 1024;
@@ -591,6 +634,23 @@ static pb3_status build_device(pb3_plan* p) {
   }
   if ((st = upload(&d.out_map, map.data(), map.size())) != PB3_OK) return st;
   if ((st = upload(&d.inv_counts, fac.data(), fac.size())) != PB3_OK) return st;
+  if (p->lmax > 0) {
+    const int ne = p->lmax / 2 + 1, nt = (int)(p->trip.size() / 3);
+    std::vector<int32_t> mt, mm(nt);
+    std::vector<double> mf;
+    for (int l = 0; l < ne; ++l)
+      for (int t = 0; t < nt; ++t) {
+        mt.push_back(p->trip[3 * t]);
+        mt.push_back(p->trip[3 * t + 1]);
+        mt.push_back(l * p->nb + p->trip[3 * t + 2]);
+        mf.push_back((4 * l + 1) * fac[t]);  // (2 ell + 1) with ell = 2 l
+      }
+    for (int t = 0; t < nt; ++t) mm[t] = t;
+    if ((st = upload(&d.pml_inv, p->pml_inv.data(), p->pml_inv.size())) != PB3_OK) return st;
+    if ((st = upload(&d.ml_trips, mt.data(), mt.size())) != PB3_OK) return st;
+    if ((st = upload(&d.ml_fac, mf.data(), mf.size())) != PB3_OK) return st;
+    if ((st = upload(&d.ml_map, mm.data(), mm.size())) != PB3_OK) return st;
+  }
   if (p->flags & PB3_FLAG_STAGE_TIMING) {
     p->ev.assign((size_t)pb3_plan::kTimingRing * ST_COUNT * 2, nullptr);
     p->ev_used.assign((size_t)pb3_plan::kTimingRing * ST_COUNT, 0);
@@ -912,6 +972,40 @@ pb3_status pb3_masked_power(pb3_plan* plan, const float* data_dev, const float* 
   }
   return run_masked_power(*plan, data_dev, window_dev, grfs_dev, n_grf, pk_dev, fisher_dev, workspace_dev,
                           (hipStream_t)stream);
+}
+
+int pb3_n_ell(const pb3_plan* plan) { return plan ? plan->lmax / 2 + 1 : 0; }
+
+size_t pb3_multipoles_workspace_bytes(const pb3_plan* plan) {
+  return (plan && plan->lmax > 0) ? multipoles_workspace_bytes(*plan) : 0;
+}
+
+pb3_status pb3_multipoles(pb3_plan* plan, const float* delta_dev, double* pk_dev, double* bk_dev, void* workspace_dev,
+                          size_t workspace_bytes_, void* stream) {
+  if (!plan || !delta_dev || (!pk_dev && !bk_dev) || !workspace_dev) {
+    set_error("null argument");
+    return PB3_EINVAL;
+  }
+  if (!plan->device || plan->lmax == 0) {
+    set_error("multipoles need a device plan created with PB3_FLAG_LMAX2 or PB3_FLAG_LMAX4");
+    return PB3_EINVAL;
+  }
+  if (bk_dev && (plan->flags & PB3_FLAG_POWER_ONLY)) {
+    set_error("plan was created with PB3_FLAG_POWER_ONLY (no bispectrum tables)");
+    return PB3_EINVAL;
+  }
+  if (workspace_bytes_ < multipoles_workspace_bytes(*plan) || ((uintptr_t)workspace_dev) % 256) {
+    set_error("workspace too small or not 256-byte aligned: need " +
+              std::to_string(multipoles_workspace_bytes(*plan)) + " bytes");
+    return PB3_ENOMEM;
+  }
+  int dev = -1;
+  hipGetDevice(&dev);
+  if (dev != plan->device_id) {
+    set_error("plan was created on another device");
+    return PB3_EINVAL;
+  }
+  return run_multipoles(*plan, delta_dev, pk_dev, bk_dev, workspace_dev, (hipStream_t)stream);
 }
 
 static const char* kStageNames[ST_COUNT] = {"fwd_z", "fwd_y", "fwd_x",    "power", "inv_x",

@@ -80,6 +80,10 @@ struct DeviceTables {
   float2* tw_m = nullptr;         // W_M^j
   double2* tw_m_d = nullptr;      // FP64 twiddles for the count pass
   double* nmodes_d = nullptr;      // masked power: N_b as double (made on first use)
+  double* pml_inv = nullptr;       // multipoles: per bin, inverse discrete Fisher x V / N_pix^2 [nb][n_ell^2]
+  int32_t* ml_trips = nullptr;     // multipoles: (a, b, l nb + c) per l and kept triplet
+  double* ml_fac = nullptr;        // multipoles: (2l + 1) V^2 M^6 / (N^9 T) per l and kept triplet
+  int32_t* ml_map = nullptr;       // multipoles: identity map over kept triplets
 };
 
 struct Workspace {
@@ -125,6 +129,8 @@ struct pb3_plan {
   int M = 0;                   // contraction grid
   bool fused = false;          // inverse z pass fused into the contraction (no G in HBM)
   bool fused_ok = false;       // the fused kernel supports this plan
+  int lmax = 0;                // highest multipole (0, 2 or 4)
+  std::vector<double> pml_inv; // per bin inverse discrete Fisher of the power multipoles, x V / N_pix^2
   int tuned = 0;               // launch shape: 0 default, 1 from the autotune cache, 2 measured
   int lut_len = 0;
   std::vector<int8_t> lut;
@@ -188,6 +194,10 @@ hipError_t launch_window(long n, const float* w, double* pk, int nb, double* bk,
 pb3_status compute_counts_fp64(pb3_plan& p, std::vector<double>& counts_out);
 // masked power spectrum with the Monte Carlo Fisher matrix (pb3_kernels.hip)
 size_t masked_workspace_bytes(const pb3_plan& p);
+// multipoles (pb3_kernels.hip)
+size_t multipoles_workspace_bytes(const pb3_plan& p);
+pb3_status run_multipoles(pb3_plan& p, const float* delta, double* pk_out, double* bk_out, void* workspace,
+                          hipStream_t s);
 pb3_status run_masked_power(pb3_plan& p, const float* data, const float* window, const float* const* grfs, int n_grf,
                             double* pk_out, double* f_out, void* workspace, hipStream_t s);
 // MFMA contraction (contract_mfma.hip): tiles for nq 16-bin groups, the
@@ -204,7 +214,7 @@ hipError_t launch_zcontract(const pb3_plan& p, const Exec& x, bool mixed, hipStr
 // unit = the shell indicator instead of Theta_b D (count pass, FP64 only);
 // n_jobs jobs whose buffers are wstride bytes apart
 hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, const float2* dc, void* a1, const void* tw,
-                     const TileSet& ts, int n_jobs, size_t wstride, hipStream_t s);
+                     const TileSet& ts, int n_jobs, size_t wstride, hipStream_t s, int ell = 0);
 hipError_t run_inv_y(const pb3_plan& p, bool dbl, const void* a1, void* a2, const void* tw, const TileSet& ts,
                      int n_jobs, size_t wstride, hipStream_t s);
 hipError_t run_inv_z(const pb3_plan& p, bool dbl, const void* a2, void* gout, const void* tw, const TileSet& ts,

@@ -312,6 +312,56 @@ __global__ void __launch_bounds__(64) k_masked_solve(const double* __restrict__ 
   for (int r = tid; r < nb; r += 64) pk_out[r] = A[r * ld + nb];
 }
 
+// ------------------------------------------------------------ multipoles
+// Power multipoles (line of sight along z): per chunk of one bin's modes,
+// sum_n w L_l(mu_n) |D(n)|^2 for l = 0, 2, .. (FP64), mu decoded from the
+// compact index; then per bin P_l = sum_l' Finv[l][l'] p_l'.
+__global__ void __launch_bounds__(256) k_power_ml_chunks(const float2* __restrict__ dc,
+                                                         const int32_t* __restrict__ modes,
+                                                         const int32_t* __restrict__ chunks, int Lc, int Kz, int Kc,
+                                                         int ne, double* __restrict__ part) {
+  __shared__ double red[3][256];
+  const int c = blockIdx.x;
+  const int start = chunks[3 * c + 1], end = chunks[3 * c + 2];
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int i = start + threadIdx.x; i < end; i += 256) {
+    const int32_t m = modes[i];
+    const double w = (m < 0) ? 1.0 : 2.0;
+    const int idx = m & 0x7fffffff;
+    const int kz = idx % Kz, cxy = idx / Kz;
+    const int ky = cxy % Lc - Kc, kx = cxy / Lc - Kc;
+    const double n2 = (double)kx * kx + (double)ky * ky + (double)kz * kz;
+    const double m2 = n2 > 0 ? (double)kz * kz / n2 : 0.0;
+    const float2 v = dc[idx];
+    const double p2 = w * ((double)v.x * v.x + (double)v.y * v.y);
+    acc[0] += p2;
+    acc[1] += p2 * (1.5 * m2 - 0.5);
+    acc[2] += p2 * ((35.0 * m2 * m2 - 30.0 * m2 + 3.0) * 0.125);
+  }
+  for (int l = 0; l < 3; ++l) red[l][threadIdx.x] = acc[l];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+      for (int l = 0; l < 3; ++l) red[l][threadIdx.x] += red[l][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x < ne) part[(size_t)c * ne + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_power_ml_final(const double* __restrict__ part, const int32_t* __restrict__ chunk_first, int nb,
+                                 int ne, const double* __restrict__ finv, double* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  double p[3] = {0.0, 0.0, 0.0};
+  for (int c = chunk_first[b]; c < chunk_first[b + 1]; ++c)
+    for (int l = 0; l < ne; ++l) p[l] += part[(size_t)c * ne + l];
+  for (int l = 0; l < ne; ++l) {
+    double v = 0.0;
+    for (int j = 0; j < ne; ++j) v += finv[((size_t)b * ne + l) * ne + j] * p[j];
+    out[(size_t)l * nb + b] = v;
+  }
+}
+
 // ================================================================ launchers
 
 hipError_t launch_window(long n, const float* w, double* pk, int nb, double* bk, int nt, double* scratch,
@@ -471,6 +521,74 @@ pb3_status run_masked_power(pb3_plan& p, const float* data, const float* window,
   hipLaunchKernelGGL(k_masked_solve, dim3(1), dim3(64), sizeof(double) * nb * (nb + 1), s, acc, scale, pbox,
                      p.d.nmodes_d, nb, pk_out, f_out);
   if (!chk(hipGetLastError(), "masked power: solve")) return st;
+  return PB3_OK;
+}
+
+// ------------------------------------------------------------ multipoles
+// Bispectrum multipoles: the Legendre-weighted filtered fields
+// g_{c,l} = IDFT_M[Theta_c L_l(mu) D] for l = 0, 2, .. (l = 0 is G),
+// then sum_x G_a G_b g_{c,l} by the simple contraction (FP32 tiles
+// flushed to FP64) and (2l + 1) V^2 M^6 / (N^9 T) per triplet.
+// Workspace: the plan's, fields [n_ell][nb][M^3], partials
+// [kMlWgs][n_trip], power-multipole chunk partials [n_chunks][n_ell].
+constexpr int kMlWgs = 512;
+
+size_t multipoles_workspace_bytes(const pb3_plan& p) {
+  const size_t A = 256, m3 = (size_t)p.M * p.M * p.M, ne = (size_t)(p.lmax / 2 + 1);
+  const size_t nt = p.trip.size() / 3;
+  auto up = [&](size_t b) { return (b + A - 1) / A * A; };
+  return up(workspace_bytes(&p)) + up(sizeof(float) * ne * p.nb * m3) + up(sizeof(double) * kMlWgs * std::max<size_t>(nt, 1)) +
+         up(sizeof(double) * std::max(p.n_chunks, 1) * ne);
+}
+
+pb3_status run_multipoles(pb3_plan& p, const float* delta, double* pk_out, double* bk_out, void* workspace,
+                          hipStream_t s) {
+  const size_t A = 256, m3 = (size_t)p.M * p.M * p.M;
+  const int ne = p.lmax / 2 + 1, nt = (int)(p.trip.size() / 3);
+  auto up = [&](size_t b) { return (b + A - 1) / A * A; };
+  char* c = (char*)workspace;
+  Exec x;
+  x.ws = carve(&p, c, workspace_bytes(&p));
+  c += up(workspace_bytes(&p));
+  float* fields = (float*)c;
+  c += up(sizeof(float) * ne * p.nb * m3);
+  double* part = (double*)c;
+  c += up(sizeof(double) * kMlWgs * std::max(nt, 1));
+  double* mpart = (double*)c;
+  pb3_status st = PB3_OK;
+  auto chk = [&](hipError_t r, const char* what) {
+    if (r != hipSuccess) st = hip_fail(r, what);
+    return r == hipSuccess;
+  };
+  x.io.delta[0] = delta;
+  if (!chk(launch_fwd_z(p, x, s), "multipoles: fwd_z") || !chk(launch_fwd_y(p, x, s), "multipoles: fwd_y") ||
+      !chk(launch_fwd_x(p, x, s), "multipoles: fwd_x"))
+    return st;
+  if (pk_out) {
+    hipLaunchKernelGGL(k_power_ml_chunks, dim3(p.n_chunks), dim3(256), 0, s, x.ws.dc, p.d.modes, p.d.chunk, p.Lc,
+                       p.Kz, p.Kc, ne, mpart);
+    if (!chk(hipGetLastError(), "multipoles: power")) return st;
+    hipLaunchKernelGGL(k_power_ml_final, dim3((p.nb + 63) / 64), dim3(64), 0, s, mpart, p.d.chunk_first, p.nb, ne,
+                       p.d.pml_inv, pk_out);
+    if (!chk(hipGetLastError(), "multipoles: power")) return st;
+  }
+  if (!bk_out || nt == 0) return PB3_OK;
+  for (int l = 0; l < ne; ++l) {
+    float* gl = fields + (size_t)l * p.nb * m3;
+    if (!chk(run_inv_x(p, false, false, x.ws.dc, x.ws.a1, p.d.tw_m, p.tx, 1, 0, s, 2 * l), "multipoles: inv_x") ||
+        !chk(launch_inv_y(p, x, s), "multipoles: inv_y") ||
+        !chk(run_inv_z(p, false, x.ws.a2, gl, p.d.tw_m, p.tz, 1, 0, s), "multipoles: inv_z"))
+      return st;
+  }
+  for (int l = 0; l < ne; ++l) {
+    if (!chk(contract_simple<float>(fields, ne * p.nb, (long)m3, p.d.ml_trips + (size_t)3 * l * nt, nt, kMlWgs, part,
+                                    s),
+             "multipoles: contraction"))
+      return st;
+    hipLaunchKernelGGL((k_reduce<double>), dim3((nt + 255) / 256), dim3(256), 0, s, part, kMlWgs, nt, p.d.ml_map,
+                       p.d.ml_fac + (size_t)l * nt, nt, bk_out + (size_t)l * nt);
+    if (!chk(hipGetLastError(), "multipoles: reduce")) return st;
+  }
   return PB3_OK;
 }
 

@@ -154,3 +154,17 @@ def test_power_only_plan_has_no_triplets():
     full = pb3.Plan(128, 1000.0, kf_edges(40), host_only=True)
     assert p.n_triplets == 0 and full.n_triplets > 0
     assert p.workspace_bytes < full.workspace_bytes
+
+
+def test_multipole_plans_on_host():
+    import paper_2404_07249_amd as pb3
+
+    p = pb3.Plan(32, 500.0, kf_edges(6), host_only=True, lmax=4)
+    assert p.n_ell == 3
+    assert pb3.Plan(32, 500.0, kf_edges(6), host_only=True).n_ell == 1
+    # one shell of the six axis modes has two mu^2 values: l = 0, 2, 4 cannot be separated
+    with pytest.raises(pb3.Pb3Error):
+        pb3.Plan(32, 500.0, np.array([1.0, 1.2]), host_only=True, lmax=4)
+    assert pb3.Plan(32, 500.0, np.array([1.0, 1.2]), host_only=True, lmax=2).n_ell == 2
+    with pytest.raises(ValueError):
+        pb3.Plan(32, 500.0, kf_edges(6), host_only=True, lmax=3)
