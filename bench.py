@@ -279,6 +279,32 @@ def serving_bench(n_requests: int = 200, rate: float = 20.0, budget_gb: float = 
     return out
 
 
+def multipoles_bench(d32, box, edges, reps: int = 10) -> dict:
+    """Power and bispectrum multipoles (l <= 2 and l <= 4, line of sight
+    along z) at the headline workload: milliseconds per call and calls/s."""
+    import torch
+
+    import paper_2404_07249_amd as pb3
+
+    x = torch.from_numpy(d32).cuda()
+    n = d32.shape[0]
+    out = {}
+    for lmax in (2, 4):
+        plan = pb3.Plan(n, box, edges, lmax=lmax)
+        ws = torch.empty(int(plan._lib.pb3_multipoles_workspace_bytes(plan._h)), dtype=torch.uint8, device="cuda")
+        plan.multipoles(x, workspace=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan.multipoles(x, workspace=ws)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / reps
+        out[f"lmax{lmax}"] = {"ms_per_call": round(ms, 3), "calls_per_s": round(1e3 / ms, 2),
+                              "n_ell": plan.n_ell, "triplets": plan.n_triplets,
+                              "workspace_gb": round(ws.numel() / 1e9, 2)}
+    return out
+
+
 def p_launches(plan) -> int:
     """Kernel launches of one single P+B call (a one-job batch)."""
     import paper_2404_07249_amd as pb3
@@ -348,6 +374,7 @@ def main(argv=None):
     ap.add_argument("--latency-calls", type=int, default=50)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-workload measurement")
     ap.add_argument("--no-autotune", action="store_true", help="default launch shapes instead of timed ones")
+    ap.add_argument("--no-multipoles", action="store_true", help="skip the multipole measurement")
     ap.add_argument("--serve-mc", type=int, default=8, help="random fields per serving request (0: windowed only)")
     ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests in the serving measurement (0 skips it; 2000 for the full stream)")
@@ -452,6 +479,8 @@ def main(argv=None):
     }
     if not args.no_batched:
         line["batched"] = batched_bench(precision=main_p, autotune=not args.no_autotune)
+    if not args.no_multipoles:
+        line["multipoles"] = multipoles_bench(d32, box, edges)
     if args.serve_requests > 0:
         line["serving"] = serving_bench(args.serve_requests, precision=main_p, n_mc=args.serve_mc)
     if not args.no_cpu_baseline:
