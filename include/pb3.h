@@ -189,8 +189,9 @@ pb3_status pb3_masked_power(pb3_plan* plan, const float* data_dev, const float* 
  *               form of Sec. IV.D.1 (l = 0 is pb3_bispectrum's B).
  * pb3_n_ell gives the number of multipoles (lmax/2 + 1).  pk_dev: n_ell x n_bins
  * float64 (row l/2), bk_dev: n_ell x n_trip float64; either may be NULL (not
- * both).  The contraction runs in FP32 with FP64 accumulation of its tile
- * sums.  workspace: >= pb3_multipoles_workspace_bytes, 256-byte aligned
+ * both).  prec: PB3_MIXED_BF16X3 runs the contraction on the matrix cores
+ * (pairs of G_a G_b against columns of g_{c,l}, split-bf16 x3), PB3_FP32 on
+ * FP32 FMA tiles flushed to FP64.  workspace: >= pb3_multipoles_workspace_bytes, 256-byte aligned
  * (n_ell x n_bins filtered fields on the contraction grid plus partial sums).
  * Errors: PB3_EINVAL (plan without multipoles, null arguments, power-only
  * plan asked for B; at creation: a bin whose modes cannot separate the
@@ -198,7 +199,7 @@ pb3_status pb3_masked_power(pb3_plan* plan, const float* data_dev, const float* 
 int pb3_n_ell(const pb3_plan* plan);
 size_t pb3_multipoles_workspace_bytes(const pb3_plan* plan);
 pb3_status pb3_multipoles(pb3_plan* plan, const float* delta_dev, double* pk_dev, double* bk_dev,
-                          void* workspace_dev, size_t workspace_bytes, void* stream);
+                          pb3_precision prec, void* workspace_dev, size_t workspace_bytes, void* stream);
 
 /* Stage timing (plans made with PB3_FLAG_STAGE_TIMING): every call records
  * a HIP event pair around each kernel launch on the call's stream.

@@ -249,7 +249,8 @@ class Plan:
     def n_ell(self) -> int:
         return int(self._lib.pb3_n_ell(self._h))
 
-    def multipoles(self, delta, power: bool = True, bispectrum: bool = True, workspace=None, stream=None):
+    def multipoles(self, delta, power: bool = True, bispectrum: bool = True, precision: str = "mixed",
+                   workspace=None, stream=None):
         """(P_l [n_ell, n_bins] or None, B_l [n_ell, n_trip] or None) for
         l = 0, 2, (4) with the line of sight along z (plans made with lmax > 0)."""
         import torch
@@ -263,7 +264,7 @@ class Plan:
             workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=delta.device)
         _lib.check(self._lib.pb3_multipoles(
             self._h, C.c_void_p(delta.data_ptr()), C.c_void_p(pk.data_ptr() if pk is not None else 0),
-            C.c_void_p(bk.data_ptr() if bk is not None else 0), C.c_void_p(workspace.data_ptr()),
+            C.c_void_p(bk.data_ptr() if bk is not None else 0), _PREC[precision], C.c_void_p(workspace.data_ptr()),
             workspace.numel() * workspace.element_size(), _stream_handle(stream)))
         return pk, bk
 

@@ -54,7 +54,8 @@ SIGNATURES = [
       C.c_size_t, C.c_void_p]),
     ("pb3_n_ell", C.c_int, [C.c_void_p]),
     ("pb3_multipoles_workspace_bytes", C.c_size_t, [C.c_void_p]),
-    ("pb3_multipoles", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("pb3_multipoles", C.c_int,
+     [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]),
     ("pb3_stage_times", C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_int)]),
     ("pb3_stage_timing_reset", C.c_int, [C.c_void_p]),
     ("pb3_stage_name", C.c_char_p, [C.c_int]),

@@ -277,8 +277,12 @@ __device__ __forceinline__ void tile_load(const float* __restrict__ g, long mvox
   }
 }
 
+// The FP32 rows (pair factors) come from r, the bf16 column operand from
+// rc: the same fields for the bispectrum, the Legendre-weighted fields
+// for its multipoles.
 template <int NQ, bool MIXED>
-__device__ __forceinline__ void tile_store(TileStage<NQ>& st, const TileRegs<NQ>& r, const SplitSel& sel) {
+__device__ __forceinline__ void tile_store(TileStage<NQ>& st, const TileRegs<NQ>& r, const TileRegs<NQ>& rc,
+                                           const SplitSel& sel) {
 #pragma unroll
   for (int k = 0; k < TileRegs<NQ>::PER; ++k) {
     int e = threadIdx.x + k * kContractThreads;
@@ -286,7 +290,7 @@ __device__ __forceinline__ void tile_store(TileStage<NQ>& st, const TileRegs<NQ>
       int bin = e / (kTileVox / 4), c4 = e % (kTileVox / 4);
       *reinterpret_cast<float4*>(st.f + bin * kPitchF + 4 * c4) = r.v[k];
       if constexpr (MIXED) {
-        float x[8] = {r.v[k].x, r.v[k].y, r.v[k].z, r.v[k].w, 0.f, 0.f, 0.f, 0.f};
+        float x[8] = {rc.v[k].x, rc.v[k].y, rc.v[k].z, rc.v[k].w, 0.f, 0.f, 0.f, 0.f};
         bf16x8_t h8, l8;
         split8(x, h8, l8, sel);
         __bf16* ph = st.hi + bin * kPitchH + 4 * c4;
@@ -305,8 +309,10 @@ template <int NQ, bool MIXED, int K0, int K1>
 __global__ void __launch_bounds__(kContractThreads) k_contract_mfma(const float* __restrict__ g, long mvox, long vpw,
                                                                     float* __restrict__ part, int part_len,
                                                                     unsigned sel_lo, unsigned sel_hi,
-                                                                    size_t wstride, int nb) {
+                                                                    size_t wstride, int nb,
+                                                                    const float* __restrict__ gc) {
   static_assert(kGroups == 4, "group dispatch below assumes four groups");
+  const bool cols = gc != nullptr;  // separate column fields (mixed precision only)
   g = job_ptr(g, wstride);
   part = job_ptr(part, wstride);
   constexpr int T0 = tiles_before(NQ, K0);
@@ -331,15 +337,19 @@ __global__ void __launch_bounds__(kContractThreads) k_contract_mfma(const float*
   long ve = vb + vpw;
   if (ve > mvox) ve = mvox;
   const int n_tiles_wg = ve > vb ? (int)((ve - vb) / kTileVox) : 0;
-  TileRegs<NQ> regs;
+  TileRegs<NQ> regs, regc;
   if (n_tiles_wg > 0) {
     tile_load<NQ>(g, mvox, vb, nb, regs);
-    tile_store<NQ, MIXED>(stage[0], regs, sel);
+    if (cols) tile_load<NQ>(gc, mvox, vb, nb, regc);
+    tile_store<NQ, MIXED>(stage[0], regs, cols ? regc : regs, sel);
   }
   __syncthreads();
   for (int m = 0; m < n_tiles_wg; ++m) {
     const bool more = m + 1 < n_tiles_wg;
-    if (more) tile_load<NQ>(g, mvox, vb + (long)(m + 1) * kTileVox, nb, regs);
+    if (more) {
+      tile_load<NQ>(g, mvox, vb + (long)(m + 1) * kTileVox, nb, regs);
+      if (cols) tile_load<NQ>(gc, mvox, vb + (long)(m + 1) * kTileVox, nb, regc);
+    }
     const TileStage<NQ>& cur = stage[m & 1];
     switch (gi) {
       case 0: contract_tile<NQ, MIXED, K0, K1, 0>(cur, i, grp, wig, acc, sel); break;
@@ -347,7 +357,7 @@ __global__ void __launch_bounds__(kContractThreads) k_contract_mfma(const float*
       case 2: contract_tile<NQ, MIXED, K0, K1, 2>(cur, i, grp, wig, acc, sel); break;
       default: contract_tile<NQ, MIXED, K0, K1, 3>(cur, i, grp, wig, acc, sel); break;
     }
-    if (more) tile_store<NQ, MIXED>(stage[(m + 1) & 1], regs, sel);
+    if (more) tile_store<NQ, MIXED>(stage[(m + 1) & 1], regs, cols ? regc : regs, sel);
     __syncthreads();
   }
   // fixed-order sum of the waves of each group in LDS (reuses the stage)
@@ -368,22 +378,24 @@ __global__ void __launch_bounds__(kContractThreads) k_contract_mfma(const float*
 
 template <int NQ, bool MIXED, int G>
 static hipError_t launch_group(const float* g, long mvox, int n_wg, long vpw, float* part, int part_len, int n_jobs,
-                               size_t wstride, int nb, hipStream_t s) {
+                               size_t wstride, int nb, const float* gc, hipStream_t s) {
   constexpr int K0 = group_begin(NQ, G), K1 = group_begin(NQ, G + 1);
   // bf16 pairs (element 0 in the low half): (-1, 0) and (0, -1)
   const unsigned sel_lo = 0x0000BF80u, sel_hi = 0xBF800000u;
   hipLaunchKernelGGL((k_contract_mfma<NQ, MIXED, K0, K1>), dim3(n_wg, 1, n_jobs), dim3(kContractThreads), 0, s, g,
-                     mvox, vpw, part, part_len, sel_lo, sel_hi, wstride, nb);
+                     mvox, vpw, part, part_len, sel_lo, sel_hi, wstride, nb, gc);
   return hipGetLastError();
 }
 
 template <int NQ, bool MIXED>
 static hipError_t launch_nq(const float* g, long mvox, int n_wg, long vpw, float* part, int part_len, int n_jobs,
-                            size_t wstride, int nb, hipStream_t s) {
-  hipError_t e = launch_group<NQ, MIXED, 0>(g, mvox, n_wg, vpw, part, part_len, n_jobs, wstride, nb, s);
+                            size_t wstride, int nb, const float* gc, hipStream_t s) {
+  hipError_t e = launch_group<NQ, MIXED, 0>(g, mvox, n_wg, vpw, part, part_len, n_jobs, wstride, nb, gc, s);
   if constexpr (n_groups(NQ) > 1) {
-    if (e == hipSuccess) e = launch_group<NQ, MIXED, 1>(g, mvox, n_wg, vpw, part, part_len, n_jobs, wstride, nb, s);
-    if (e == hipSuccess) e = launch_group<NQ, MIXED, 2>(g, mvox, n_wg, vpw, part, part_len, n_jobs, wstride, nb, s);
+    if (e == hipSuccess)
+      e = launch_group<NQ, MIXED, 1>(g, mvox, n_wg, vpw, part, part_len, n_jobs, wstride, nb, gc, s);
+    if (e == hipSuccess)
+      e = launch_group<NQ, MIXED, 2>(g, mvox, n_wg, vpw, part, part_len, n_jobs, wstride, nb, gc, s);
   }
   return e;
 }
@@ -684,22 +696,27 @@ int mfma_grid(int nq, int n_cu) {
 }
 
 hipError_t launch_contract_mfma(const pb3_plan& p, const Exec& x, bool mixed, hipStream_t s) {
+  return launch_contract_cols(p, x, x.ws.g, nullptr, mixed, s);
+}
+
+hipError_t launch_contract_cols(const pb3_plan& p, const Exec& x, const float* g, const float* gc, bool mixed,
+                                hipStream_t s) {
+  if (gc && !mixed) return hipErrorInvalidValue;  // separate column fields: bf16 column operand only
   const long mvox = (long)p.M * p.M * p.M;
   const int nq = p.nb_pad / 16;
   const int n_wg = p.contract_wgs;
   long vpw = (mvox + n_wg - 1) / n_wg;
   vpw = (vpw + kTileVox - 1) / kTileVox * kTileVox;
   float* part = x.ws.part;
-  const float* g = x.ws.g;
   const int pl = p.part_len, nj = x.n_jobs;
   const size_t ws = x.wstride;
   switch (nq) {
-    case 1: return mixed ? launch_nq<1, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, s)
-                         : launch_nq<1, false>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, s);
-    case 2: return mixed ? launch_nq<2, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, s)
-                         : launch_nq<2, false>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, s);
-    case 3: return mixed ? launch_nq<3, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, s)
-                         : launch_nq<3, false>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, s);
+    case 1: return mixed ? launch_nq<1, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s)
+                         : launch_nq<1, false>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s);
+    case 2: return mixed ? launch_nq<2, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s)
+                         : launch_nq<2, false>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s);
+    case 3: return mixed ? launch_nq<3, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s)
+                         : launch_nq<3, false>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -980,8 +980,8 @@ size_t pb3_multipoles_workspace_bytes(const pb3_plan* plan) {
   return (plan && plan->lmax > 0) ? multipoles_workspace_bytes(*plan) : 0;
 }
 
-pb3_status pb3_multipoles(pb3_plan* plan, const float* delta_dev, double* pk_dev, double* bk_dev, void* workspace_dev,
-                          size_t workspace_bytes_, void* stream) {
+pb3_status pb3_multipoles(pb3_plan* plan, const float* delta_dev, double* pk_dev, double* bk_dev, pb3_precision prec,
+                          void* workspace_dev, size_t workspace_bytes_, void* stream) {
   if (!plan || !delta_dev || (!pk_dev && !bk_dev) || !workspace_dev) {
     set_error("null argument");
     return PB3_EINVAL;
@@ -1005,7 +1005,9 @@ pb3_status pb3_multipoles(pb3_plan* plan, const float* delta_dev, double* pk_dev
     set_error("plan was created on another device");
     return PB3_EINVAL;
   }
-  return run_multipoles(*plan, delta_dev, pk_dev, bk_dev, workspace_dev, (hipStream_t)stream);
+  pb3_status pst = check_prec(prec);
+  if (pst != PB3_OK) return pst;
+  return run_multipoles(*plan, delta_dev, pk_dev, bk_dev, prec, workspace_dev, (hipStream_t)stream);
 }
 
 static const char* kStageNames[ST_COUNT] = {"fwd_z", "fwd_y", "fwd_x",    "power", "inv_x",

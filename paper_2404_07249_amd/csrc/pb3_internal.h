@@ -196,8 +196,8 @@ pb3_status compute_counts_fp64(pb3_plan& p, std::vector<double>& counts_out);
 size_t masked_workspace_bytes(const pb3_plan& p);
 // multipoles (pb3_kernels.hip)
 size_t multipoles_workspace_bytes(const pb3_plan& p);
-pb3_status run_multipoles(pb3_plan& p, const float* delta, double* pk_out, double* bk_out, void* workspace,
-                          hipStream_t s);
+pb3_status run_multipoles(pb3_plan& p, const float* delta, double* pk_out, double* bk_out, pb3_precision prec,
+                          void* workspace, hipStream_t s);
 pb3_status run_masked_power(pb3_plan& p, const float* data, const float* window, const float* const* grfs, int n_grf,
                             double* pk_out, double* f_out, void* workspace, hipStream_t s);
 // MFMA contraction (contract_mfma.hip): tiles for nq 16-bin groups, the
@@ -205,6 +205,10 @@ pb3_status run_masked_power(pb3_plan& p, const float* data, const float* window,
 int mfma_tiles(int nq);
 int mfma_locate(int nq, int a, int b, int c);
 hipError_t launch_contract_mfma(const pb3_plan& p, const Exec& x, bool mixed, hipStream_t s);
+// pairs of the fields g against columns of the fields gc (nb bins each, M^3
+// voxels, gc != nullptr: mixed precision only) into x.ws.part
+hipError_t launch_contract_cols(const pb3_plan& p, const Exec& x, const float* g, const float* gc, bool mixed,
+                                hipStream_t s);
 int mfma_grid(int nq, int n_cu);
 // fused inverse z pass + contraction (contract_mfma.hip)
 bool fused_supported(int nq, int m);

@@ -527,8 +527,9 @@ pb3_status run_masked_power(pb3_plan& p, const float* data, const float* window,
 // ------------------------------------------------------------ multipoles
 // Bispectrum multipoles: the Legendre-weighted filtered fields
 // g_{c,l} = IDFT_M[Theta_c L_l(mu) D] for l = 0, 2, .. (l = 0 is G),
-// then sum_x G_a G_b g_{c,l} by the simple contraction (FP32 tiles
-// flushed to FP64) and (2l + 1) V^2 M^6 / (N^9 T) per triplet.
+// then sum_x G_a G_b g_{c,l}: mixed precision on the MFMA contraction
+// (pairs of G, columns of g_l), FP32 by the simple contraction (FP32
+// tiles flushed to FP64); (2l + 1) V^2 M^6 / (N^9 T) per triplet.
 // Workspace: the plan's, fields [n_ell][nb][M^3], partials
 // [kMlWgs][n_trip], power-multipole chunk partials [n_chunks][n_ell].
 constexpr int kMlWgs = 512;
@@ -541,8 +542,8 @@ size_t multipoles_workspace_bytes(const pb3_plan& p) {
          up(sizeof(double) * std::max(p.n_chunks, 1) * ne);
 }
 
-pb3_status run_multipoles(pb3_plan& p, const float* delta, double* pk_out, double* bk_out, void* workspace,
-                          hipStream_t s) {
+pb3_status run_multipoles(pb3_plan& p, const float* delta, double* pk_out, double* bk_out, pb3_precision prec,
+                          void* workspace, hipStream_t s) {
   const size_t A = 256, m3 = (size_t)p.M * p.M * p.M;
   const int ne = p.lmax / 2 + 1, nt = (int)(p.trip.size() / 3);
   auto up = [&](size_t b) { return (b + A - 1) / A * A; };
@@ -579,6 +580,23 @@ pb3_status run_multipoles(pb3_plan& p, const float* delta, double* pk_out, doubl
         !chk(launch_inv_y(p, x, s), "multipoles: inv_y") ||
         !chk(run_inv_z(p, false, x.ws.a2, gl, p.d.tw_m, p.tz, 1, 0, s), "multipoles: inv_z"))
       return st;
+  }
+  if (prec == PB3_MIXED_BF16X3) {
+    // MFMA: pairs of G against columns of g_l, the plan's reduction with (2l + 1) / T
+    for (int l = 0; l < ne; ++l) {
+      if (!chk(launch_contract_cols(p, x, fields, l ? fields + (size_t)l * p.nb * m3 : nullptr, true, s),
+               "multipoles: contraction"))
+        return st;
+      hipLaunchKernelGGL(k_reduce_slices, dim3((p.part_len + 255) / 256, kReduceSlices, 1), dim3(256), 0, s,
+                         x.ws.part, p.contract_wgs, p.part_len, x.ws.rsl, (size_t)0);
+      if (!chk(hipGetLastError(), "multipoles: reduce")) return st;
+      JobIO io{};
+      io.bk[0] = bk_out + (size_t)l * nt;
+      hipLaunchKernelGGL(k_reduce_final, dim3((nt + 255) / 256, 1, 1), dim3(256), 0, s, x.ws.rsl, p.part_len,
+                         p.d.out_map, p.d.ml_fac + (size_t)l * nt, nt, io, (size_t)0);
+      if (!chk(hipGetLastError(), "multipoles: reduce")) return st;
+    }
+    return PB3_OK;
   }
   for (int l = 0; l < ne; ++l) {
     if (!chk(contract_simple<float>(fields, ne * p.nb, (long)m3, p.d.ml_trips + (size_t)3 * l * nt, nt, kMlWgs, part,

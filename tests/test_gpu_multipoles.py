@@ -1,6 +1,7 @@
 """GPU parity of the power and bispectrum multipoles (pb3_multipoles, line
 of sight along z) against the FP64 oracle (oracle.multipoles).
 
+Both precisions: split-bf16 x3 on the matrix cores and FP32 tiles.
 Tolerance: P_l within 1e-4 of P_0 in every bin (the quadrupole and
 hexadecapole of an isotropic field are near zero, so their error is judged
 against the monopole); B_l within 1e-5 |B_l| + 1e-6 A_l with
@@ -34,13 +35,15 @@ def torch_cuda():
     return torch
 
 
-@pytest.mark.parametrize("n,box,nbins,lmax", [(32, 600.0, 8, 4), (64, 1000.0, 12, 2), (96, 2000.0, 10, 4)])
-def test_multipoles_match_oracle(torch_cuda, n, box, nbins, lmax):
+@pytest.mark.parametrize("prec", ["mixed", "fp32"])
+@pytest.mark.parametrize("n,box,nbins,width,lmax", [(32, 600.0, 8, 2.0, 4), (64, 1000.0, 12, 2.0, 2),
+                                                    (96, 2000.0, 10, 2.0, 4), (64, 1500.0, 36, 1.5, 2)])
+def test_multipoles_match_oracle(torch_cuda, n, box, nbins, width, lmax, prec):
     import paper_2404_07249_amd as pb3
 
     torch = torch_cuda
-    edges = kf_edges(nbins)
-    _say(f"[case] multipoles n={n} bins={nbins} lmax={lmax}")
+    edges = kf_edges(nbins, width=width)
+    _say(f"[case] multipoles n={n} bins={nbins} lmax={lmax} prec={prec}")
     # an anisotropic field: stretch the quadratic field's modes along z
     d = quadratic_field(n, box, 1.0, 70 + n)
     D = np.fft.fftn(d)
@@ -48,7 +51,7 @@ def test_multipoles_match_oracle(torch_cuda, n, box, nbins, lmax):
     d = np.fft.ifftn(D * (1.0 + 0.8 * mu * mu)).real.astype(np.float32)
     plan = pb3.Plan(n, box, edges, lmax=lmax)
     assert plan.n_ell == lmax // 2 + 1
-    pk, bk = [t.cpu().numpy() for t in plan.multipoles(torch.from_numpy(d).cuda())]
+    pk, bk = [t.cpu().numpy() for t in plan.multipoles(torch.from_numpy(d).cuda(), precision=prec)]
     d64 = d.astype(np.float64)
     pref = mp.power_multipoles(d64, box, edges, lmax)
     assert np.all(np.abs(pk - pref) <= 1e-4 * np.abs(pref[0])[None, :]), np.abs(pk - pref).max()
