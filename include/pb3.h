@@ -177,6 +177,28 @@ pb3_status pb3_masked_power(pb3_plan* plan, const float* data_dev, const float* 
                             const float* const* grfs_dev, int n_grf, double* pk_dev, double* fisher_dev,
                             void* workspace_dev, size_t workspace_bytes, void* stream);
 
+/* Weighted ideal estimators (Sec. III.D.1 eq. pk-limit and Sec. IV.D.1 with
+ * P_fid, the pixel window m(k) and the Poisson shot-noise terms):
+ *   P_b = (V/N_pix^2) sum_{n in b} |D/m|^2 / P_fid^2 / sum_{n in b} 1 / P_fid^2  -  1/nbar
+ *   B_abc = (V^2/N_pix^3) sum_closed D1 D2 D3 / (m1 m2 m3 P1 P2 P3) / N_0  -  B_shot,
+ *   N_0 = sum_closed 1 / (P1 P2 P3),
+ *   B_shot = 1/nbar^2 + <P1 + P2 + P3>/nbar, averaged with the weights of N_0,
+ *            with the power model P = P_fid - 1/nbar (P_fid includes shot noise).
+ * window_order: pixel window deconvolved, m(n) = prod_i sinc(pi n_i / N)^order
+ * (0 none, 1 nearest grid point, 2 cloud in cell, 3 triangular shaped cloud);
+ * pfid: P_fid in (Mpc/h)^3 at integer |n|^2 = 0 .. n_pfid-1 (n_pfid >=
+ * pb3_weights_table_len, positive at every binned |n|^2), or NULL for P_fid = 1;
+ * nbar: number density in (Mpc/h)^-3, or 0 for no shot-noise terms (nbar > 0
+ * needs pfid unless the plan is power-only).  Call once per plan, before its
+ * first use; recomputes the (now non-integer) triangle sums in FP64
+ * synchronously.  pb3_norm then returns N_0.  Applies to pb3_power,
+ * pb3_bispectrum, pb3_polyspectra, batches and pb3_multipoles (shot noise on
+ * the monopole); pb3_masked_power refuses a weighted plan.
+ * Errors: PB3_EINVAL (host-only plan, weights already set, bad order or
+ * nbar, table too short or not positive), PB3_ENOMEM, PB3_EDEVICE. */
+int pb3_weights_table_len(const pb3_plan* plan);
+pb3_status pb3_plan_set_weights(pb3_plan* plan, int window_order, const double* pfid, int n_pfid, double nbar);
+
 /* Multipoles l = 0, 2 (, 4) with a global line of sight along the grid's z
  * axis, for plans made with PB3_FLAG_LMAX2 or PB3_FLAG_LMAX4:
  *   P_{b,l}   = sum_l' (F_b^-1)_{l l'} p_{b,l'},  p_{b,l} = (V/N_pix^2) sum_{n in b} L_l(mu_n) |D(n)|^2,

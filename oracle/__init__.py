@@ -28,6 +28,12 @@ Parity status of each function (what pins it is in ``tests/test_oracle.py``):
                            multipoles with the discrete Fisher matrix are
                            unbiased for an anisotropic Gaussian field;
                            invariance under x-y exchange and z reflection.
+* ``weighted`` (P_fid weights, pixel window, shot noise) pinned: weighted
+                           sums equal explicit mode-triangle loops; constant
+                           P_fid reduces to the unweighted estimators; window
+                           deconvolution undoes a window applied in Fourier
+                           space; Poisson noise of a uniform field is removed
+                           on average from P and B.
 """
 
 from .polyspec import (  # noqa: F401
@@ -54,3 +60,4 @@ from .polyspec import (  # noqa: F401
 from .brute import brute_sums  # noqa: F401
 from . import masked  # noqa: F401,E402
 from . import multipoles  # noqa: F401,E402
+from . import weighted  # noqa: F401,E402

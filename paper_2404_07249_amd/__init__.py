@@ -246,6 +246,28 @@ class Plan:
         return pk, fm
 
     @property
+    def weights_table_len(self) -> int:
+        """Entries the P_fid table of :meth:`set_weights` needs (|n|^2 = 0 .. len-1)."""
+        return int(self._lib.pb3_weights_table_len(self._h))
+
+    def set_weights(self, window_order: int = 0, pfid=None, nbar: float = 0.0):
+        """Weighted ideal estimators: pixel-window deconvolution of the given
+        order (0 none, 1 NGP, 2 CIC, 3 TSC), P_fid weights (array over integer
+        |n|^2, or a callable of k in h/Mpc), Poisson shot noise for nbar > 0."""
+        tab = None
+        if pfid is not None:
+            n = self.weights_table_len
+            if callable(pfid):
+                kf = 2 * np.pi / self.box
+                tab = np.asarray(pfid(kf * np.sqrt(np.arange(n, dtype=np.float64))), dtype=np.float64)
+                tab[0] = 1.0
+            else:
+                tab = np.ascontiguousarray(np.asarray(pfid, dtype=np.float64))
+        ptr = tab.ctypes.data if tab is not None else None
+        _lib.check(self._lib.pb3_plan_set_weights(self._h, int(window_order), ptr,
+                                                  0 if tab is None else int(tab.size), float(nbar)))
+
+    @property
     def n_ell(self) -> int:
         return int(self._lib.pb3_n_ell(self._h))
 

@@ -53,6 +53,8 @@ SIGNATURES = [
      [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p), C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
       C.c_size_t, C.c_void_p]),
     ("pb3_n_ell", C.c_int, [C.c_void_p]),
+    ("pb3_weights_table_len", C.c_int, [C.c_void_p]),
+    ("pb3_plan_set_weights", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_double]),
     ("pb3_multipoles_workspace_bytes", C.c_size_t, [C.c_void_p]),
     ("pb3_multipoles", C.c_int,
      [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]),

@@ -126,7 +126,8 @@ __global__ void __launch_bounds__(512) k_inv_x2(const float2* __restrict__ dc, t
                                                 const BinGeom* __restrict__ geom, const BinTile* __restrict__ tiles,
                                                 const int8_t* __restrict__ lut, int Kc, int Lc, int Kz,
                                                 const typename Cx<Rl>::type* __restrict__ tw, size_t wstride,
-                                                int ell) {
+                                                int ell, const float* __restrict__ winv, int half,
+                                                const float* __restrict__ pinv, const double* __restrict__ uw) {
   dc = job_ptr(dc, wstride);
   a1 = job_ptr(a1, wstride);
   using C = typename Cx<Rl>::type;
@@ -155,9 +156,15 @@ __global__ void __launch_bounds__(512) k_inv_x2(const float2* __restrict__ dc, t
           int kx = n <= g.kpos ? n : (n >= M - g.kneg ? n - M : 0x40000000);
           if (live && kx != 0x40000000 && lut[kx * kx + ky * ky + kz * kz] == b) {
             if constexpr (UNIT) {
-              v = cx<C>(Rl(1), Rl(0));
+              v = cx<C>(Rl(uw ? uw[kx * kx + ky * ky + kz * kz] : 1.0), Rl(0));  // 1 / P_fid in the weighted count
             } else {
               float2 d = dc[((size_t)(kx + Kc) * Lc + (ky + Kc)) * Kz + kz];
+              if (winv || pinv) {  // weighted estimator: D / (m P_fid)
+                float u = pinv ? pinv[kx * kx + ky * ky + kz * kz] : 1.f;
+                if (winv) u *= winv[kx + half] * winv[ky + half] * winv[kz + half];
+                d.x *= u;
+                d.y *= u;
+              }
               if (ell) {  // Legendre weight L_ell(mu), mu = kz / |k| (line of sight along z)
                 const float k2 = (float)(kx * kx + ky * ky + kz * kz);
                 const float m2 = k2 > 0.f ? (float)(kz * kz) / k2 : 0.f;
@@ -336,7 +343,11 @@ hipError_t launch_fwd_x(const pb3_plan& p, const Exec& x, hipStream_t s) {
 }
 
 hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, const float2* dc, void* a1, const void* tw,
-                     const TileSet& ts, int n_jobs, size_t wstride, hipStream_t s, int ell) {
+                     const TileSet& ts, int n_jobs, size_t wstride, hipStream_t s, int ell, const double* unit_w,
+                     bool weighted) {
+  const float* winv = weighted ? p.d.win_inv : nullptr;
+  const float* pinv = weighted ? p.d.pfid_inv : nullptr;
+  const int half = p.N / 2;
   if (ts.n == 0) return hipSuccess;
   PB3_FFT_LEN(p.M, {
     if (dbl) {
@@ -344,14 +355,15 @@ hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, const float2* dc, v
       if (unit)
         hipLaunchKernelGGL((k_inv_x2<LL, double, true>), dim3(ts.n, 1, n_jobs), dim3(S::NT), 0, s, dc,
                            (double2*)a1, p.d.geom, ts.d, p.d.lut, p.Kc, p.Lc, p.Kz, (const double2*)tw, wstride,
-                           0);
+                           0, (const float*)nullptr, 0, (const float*)nullptr, unit_w);
       else
         return hipErrorInvalidValue;
     } else {
       using S = ColShape<LL, 8>;
       if (unit) return hipErrorInvalidValue;
       hipLaunchKernelGGL((k_inv_x2<LL, float, false>), dim3(ts.n, 1, n_jobs), dim3(S::NT), 0, s, dc, (float2*)a1,
-                         p.d.geom, ts.d, p.d.lut, p.Kc, p.Lc, p.Kz, (const float2*)tw, wstride, ell);
+                         p.d.geom, ts.d, p.d.lut, p.Kc, p.Lc, p.Kz, (const float2*)tw, wstride, ell, winv, half,
+                         pinv, (const double*)nullptr);
     }
     return hipGetLastError();
   });
@@ -398,7 +410,7 @@ hipError_t run_inv_z(const pb3_plan& p, bool dbl, const void* a2, void* gout, co
 }
 
 hipError_t launch_inv_x(const pb3_plan& p, const Exec& x, hipStream_t s) {
-  return run_inv_x(p, false, false, x.ws.dc, x.ws.a1, p.d.tw_m, p.tx, x.n_jobs, x.wstride, s);
+  return run_inv_x(p, false, false, x.ws.dc, x.ws.a1, p.d.tw_m, p.tx, x.n_jobs, x.wstride, s, 0, nullptr, true);
 }
 hipError_t launch_inv_y(const pb3_plan& p, const Exec& x, hipStream_t s) {
   return run_inv_y(p, false, x.ws.a1, x.ws.a2, p.d.tw_m, p.ty, x.n_jobs, x.wstride, s);

@@ -114,9 +114,10 @@ static pb3_status upload_twiddles_d(double2** out, int n) {
 
 static void free_device(pb3_plan* p) {
   DeviceTables& d = p->d;
-  void* ptrs[] = {d.lut,      d.modes,      d.chunk,    d.chunk_first, d.geom,    d.tiles,  d.trip_all,
-                  d.out_map,  d.inv_counts, d.pk_scale, d.tw_n,        d.tw_m,    d.tw_m_d, d.nmodes_d,
-                  d.pml_inv,  d.ml_trips,   d.ml_fac,   d.ml_map};
+  void* ptrs[] = {d.lut,      d.modes,      d.chunk,    d.chunk_first, d.geom,    d.tiles,    d.trip_all,
+                  d.out_map,  d.inv_counts, d.pk_scale, d.tw_n,        d.tw_m,    d.tw_m_d,   d.nmodes_d,
+                  d.pml_inv,  d.ml_trips,   d.ml_fac,   d.ml_map,      d.win_inv, d.pfid_inv, d.pfid_inv_d,
+                  d.mode_w,   d.bk_bias};
   for (void* q : ptrs)
     if (q) hipFree(q);
   d = DeviceTables{};
@@ -946,6 +947,10 @@ pb3_status pb3_masked_power(pb3_plan* plan, const float* data_dev, const float* 
     set_error("the masked power spectrum needs the full grid (create the plan with PB3_FLAG_FULL_GRID)");
     return PB3_EINVAL;
   }
+  if (plan->weighted) {
+    set_error("the masked power spectrum takes unit weights (plan has pb3_plan_set_weights)");
+    return PB3_EINVAL;
+  }
   if (n_grf < 1) {
     set_error("at least one random field is needed");
     return PB3_EINVAL;
@@ -975,6 +980,164 @@ pb3_status pb3_masked_power(pb3_plan* plan, const float* data_dev, const float* 
 }
 
 int pb3_n_ell(const pb3_plan* plan) { return plan ? plan->lmax / 2 + 1 : 0; }
+
+int pb3_weights_table_len(const pb3_plan* plan) { return plan ? (int)plan->thr[plan->nb] : 0; }
+
+pb3_status pb3_plan_set_weights(pb3_plan* plan, int window_order, const double* pfid, int n_pfid, double nbar) {
+  if (!plan || !plan->device) {
+    set_error("weights need a device plan");
+    return PB3_EINVAL;
+  }
+  pb3_plan* p = plan;
+  if (p->weighted) {
+    set_error("weights are already set on this plan");
+    return PB3_EINVAL;
+  }
+  if (window_order < 0 || window_order > 3 || !(nbar >= 0.0)) {
+    set_error("window order must be 0..3 and nbar >= 0");
+    return PB3_EINVAL;
+  }
+  const int need = (int)p->thr[p->nb];  // first |n|^2 above the top bin
+  if (pfid) {
+    if (n_pfid < need) {
+      set_error("P_fid table too short: need " + std::to_string(need) + " entries (|n|^2 = 0.." +
+                std::to_string(need - 1) + ")");
+      return PB3_EINVAL;
+    }
+    for (int j = 1; j < need; ++j)
+      if (!(pfid[j] > 0.0)) {
+        set_error("P_fid must be positive at every binned |n|^2");
+        return PB3_EINVAL;
+      }
+  }
+  if (nbar > 0.0 && !pfid && !(p->flags & PB3_FLAG_POWER_ONLY)) {
+    set_error("the bispectrum shot-noise term needs a P_fid table (it serves as the power model)");
+    return PB3_EINVAL;
+  }
+  const int N = p->N;
+  const double V = p->L * p->L * p->L, n3 = (double)N * N * N;
+  // 1D window inverse per component and 1 / P_fid per |n|^2
+  std::vector<double> winv(N + 1, 1.0);
+  for (int k = -N / 2; k <= N / 2; ++k) {
+    if (window_order == 0 || k == 0) continue;
+    const double x = M_PI * k / N;
+    winv[k + N / 2] = std::pow(x / std::sin(x), window_order);
+  }
+  p->pfid.assign(p->lut_len, 1.0);
+  if (pfid)
+    for (int j = 0; j < p->lut_len && j < n_pfid; ++j) p->pfid[j] = pfid[j] > 0.0 ? pfid[j] : 1.0;
+  std::vector<float> winv_f(winv.begin(), winv.end()), pinv_f(p->lut_len);
+  std::vector<double> pinv_d(p->lut_len);
+  for (int j = 0; j < p->lut_len; ++j) {
+    pinv_d[j] = 1.0 / p->pfid[j];
+    pinv_f[j] = (float)pinv_d[j];
+  }
+  // power: per-mode weight 1 / (m^2 P_fid^2) and the weighted Fisher per bin
+  const int nb = p->nb, ne = p->lmax / 2 + 1;
+  std::vector<double> mw(p->modes.size()), fish(nb, 0.0), msum((size_t)nb * ne * ne, 0.0);
+  for (int c = 0; c < p->n_chunks; ++c) {
+    const int b = p->chunks[3 * c];
+    for (int i = p->chunks[3 * c + 1]; i < p->chunks[3 * c + 2]; ++i) {
+      const int32_t m = p->modes[i];
+      const int idx = m & 0x7fffffff, w = m < 0 ? 1 : 2;
+      const int kz = idx % p->Kz, cxy = idx / p->Kz;
+      const int ky = cxy % p->Lc - p->Kc, kx = cxy / p->Lc - p->Kc;
+      const int64_t n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
+      const double wi = winv[kx + N / 2] * winv[ky + N / 2] * winv[kz + N / 2];
+      const double q = 1.0 / p->pfid[n2];
+      mw[i] = wi * wi * q * q;
+      fish[b] += w * q * q;
+      if (ne > 1) {
+        const double m2 = n2 > 0 ? (double)kz * kz / (double)n2 : 0.0;
+        const double L[3] = {1.0, 1.5 * m2 - 0.5, (35.0 * m2 * m2 - 30.0 * m2 + 3.0) / 8.0};
+        for (int a = 0; a < ne; ++a)
+          for (int bb = 0; bb < ne; ++bb) msum[((size_t)b * ne + a) * ne + bb] += w * q * q * L[a] * L[bb];
+      }
+    }
+  }
+  std::vector<double> pks(nb);
+  for (int b = 0; b < nb; ++b) pks[b] = V / (n3 * n3 * fish[b]);
+  pb3_status st;
+  DeviceTables& d = p->d;
+  if ((st = upload(&d.win_inv, winv_f.data(), winv_f.size())) != PB3_OK) return st;
+  if ((st = upload(&d.pfid_inv, pinv_f.data(), pinv_f.size())) != PB3_OK) return st;
+  if ((st = upload(&d.pfid_inv_d, pinv_d.data(), pinv_d.size())) != PB3_OK) return st;
+  if ((st = upload(&d.mode_w, mw.data(), mw.size())) != PB3_OK) return st;
+  hipError_t e = hipMemcpy(d.pk_scale, pks.data(), sizeof(double) * nb, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  if (window_order == 0) {  // no window: keep the per-component table out of the kernels
+    hipFree(d.win_inv);
+    d.win_inv = nullptr;
+  }
+  if (!pfid) {
+    hipFree(d.pfid_inv);
+    d.pfid_inv = nullptr;
+    hipFree(d.pfid_inv_d);
+    d.pfid_inv_d = nullptr;
+  }
+  p->window_order = window_order;
+  p->nbar = nbar;
+  p->pk_shift = nbar > 0.0 ? 1.0 / nbar : 0.0;
+  if (ne > 1) {  // weighted discrete Fisher of the power multipoles
+    const double sc = V / (n3 * n3);
+    for (int b = 0; b < nb; ++b) {
+      double a[3][6] = {};
+      for (int i = 0; i < ne; ++i) {
+        for (int j = 0; j < ne; ++j) a[i][j] = msum[((size_t)b * ne + i) * ne + j];
+        a[i][ne + i] = 1.0;
+      }
+      for (int k = 0; k < ne; ++k) {
+        int pr = k;
+        for (int r = k + 1; r < ne; ++r)
+          if (std::fabs(a[r][k]) > std::fabs(a[pr][k])) pr = r;
+        for (int c = 0; c < 2 * ne; ++c) std::swap(a[k][c], a[pr][c]);
+        const double dd = a[k][k];
+        for (int c = 0; c < 2 * ne; ++c) a[k][c] /= dd;
+        for (int r = 0; r < ne; ++r)
+          if (r != k) {
+            const double f = a[r][k];
+            for (int c = 0; c < 2 * ne; ++c) a[r][c] -= f * a[k][c];
+          }
+      }
+      for (int i = 0; i < ne; ++i)
+        for (int j = 0; j < ne; ++j) p->pml_inv[((size_t)b * ne + i) * ne + j] = sc * a[i][ne + j];
+    }
+    e = hipMemcpy(d.pml_inv, p->pml_inv.data(), sizeof(double) * p->pml_inv.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  }
+  p->weighted = true;
+  if (p->flags & PB3_FLAG_POWER_ONLY || p->trip.empty()) return PB3_OK;
+  // bispectrum: weighted triangle sums N_0 = sum 1/(P1 P2 P3), the shot-noise sums
+  std::vector<double> n0, q;
+  if ((st = compute_counts_fp64(*p, n0, nbar > 0.0 ? &q : nullptr)) != PB3_OK) return st;
+  const double m3 = (double)p->M * p->M * p->M;
+  const double scale = V * V * (m3 * m3) / (n3 * n3 * n3);
+  std::vector<double> fac, bias, mf;
+  const int nt = (int)(p->trip.size() / 3);
+  for (int t = 0, kept = 0; t < (int)(p->trip_all.size() / 3) && kept < nt; ++t) {
+    if (p->trip_all[3 * t] != p->trip[3 * kept] || p->trip_all[3 * t + 1] != p->trip[3 * kept + 1] ||
+        p->trip_all[3 * t + 2] != p->trip[3 * kept + 2])
+      continue;  // dropped (no closed triangle)
+    fac.push_back(scale / n0[t]);
+    bias.push_back(nbar > 0.0 ? q[t] / n0[t] / nbar - 2.0 / (nbar * nbar) : 0.0);
+    p->counts[kept] = n0[t];
+    ++kept;
+  }
+  if ((int)fac.size() != nt) {
+    set_error("internal: weighted triangle sums do not match the triplet list");
+    return PB3_EDEVICE;
+  }
+  e = hipMemcpy(d.inv_counts, fac.data(), sizeof(double) * nt, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  if (nbar > 0.0 && (st = upload(&d.bk_bias, bias.data(), bias.size())) != PB3_OK) return st;
+  if (p->lmax > 0) {
+    for (int l = 0; l < ne; ++l)
+      for (int t = 0; t < nt; ++t) mf.push_back((4 * l + 1) * fac[t]);
+    e = hipMemcpy(d.ml_fac, mf.data(), sizeof(double) * mf.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  }
+  return PB3_OK;
+}
 
 size_t pb3_multipoles_workspace_bytes(const pb3_plan* plan) {
   return (plan && plan->lmax > 0) ? multipoles_workspace_bytes(*plan) : 0;

@@ -84,6 +84,12 @@ struct DeviceTables {
   int32_t* ml_trips = nullptr;     // multipoles: (a, b, l nb + c) per l and kept triplet
   double* ml_fac = nullptr;        // multipoles: (2l + 1) V^2 M^6 / (N^9 T) per l and kept triplet
   int32_t* ml_map = nullptr;       // multipoles: identity map over kept triplets
+  // weighted estimator (pb3_plan_set_weights); all null when unweighted
+  float* win_inv = nullptr;        // 1 / sinc(pi k / N)^p for k in [-N/2, N/2] (index k + N/2)
+  float* pfid_inv = nullptr;       // 1 / P_fid over integer |n|^2 (lut_len entries)
+  double* pfid_inv_d = nullptr;    // same in FP64 (weighted triangle counts)
+  double* mode_w = nullptr;        // per power mode: 1 / (m^2 P_fid^2)
+  double* bk_bias = nullptr;       // per kept triplet: shot-noise bispectrum
 };
 
 struct Workspace {
@@ -130,6 +136,11 @@ struct pb3_plan {
   bool fused = false;          // inverse z pass fused into the contraction (no G in HBM)
   bool fused_ok = false;       // the fused kernel supports this plan
   int lmax = 0;                // highest multipole (0, 2 or 4)
+  bool weighted = false;       // pb3_plan_set_weights was called
+  int window_order = 0;        // pixel window deconvolved (0 none, 1 NGP, 2 CIC, 3 TSC)
+  double nbar = 0;             // number density for the shot-noise terms (0: none)
+  double pk_shift = 0;         // subtracted from P (shot noise 1 / nbar)
+  std::vector<double> pfid;    // P_fid over integer |n|^2 (weighted plans)
   std::vector<double> pml_inv; // per bin inverse discrete Fisher of the power multipoles, x V / N_pix^2
   int tuned = 0;               // launch shape: 0 default, 1 from the autotune cache, 2 measured
   int lut_len = 0;
@@ -191,7 +202,10 @@ hipError_t launch_window(long n, const float* w, double* pk, int nb, double* bk,
                          hipStream_t s);
 // FP64 triangle counts on the contraction grid: writes raw M^6 sum HHH for
 // every candidate triplet into counts_out (host), using temporary memory.
-pb3_status compute_counts_fp64(pb3_plan& p, std::vector<double>& counts_out);
+// With the plan's P_fid weights set, the weighted counts sum 1/(P_1 P_2 P_3);
+// q_out (may be null) receives the shot-noise sums of the weighted estimator
+// sum over closed triangles of 1/(P_2 P_3) + 1/(P_1 P_3) + 1/(P_1 P_2).
+pb3_status compute_counts_fp64(pb3_plan& p, std::vector<double>& counts_out, std::vector<double>* q_out = nullptr);
 // masked power spectrum with the Monte Carlo Fisher matrix (pb3_kernels.hip)
 size_t masked_workspace_bytes(const pb3_plan& p);
 // multipoles (pb3_kernels.hip)
@@ -217,8 +231,11 @@ hipError_t launch_zcontract(const pb3_plan& p, const Exec& x, bool mixed, hipStr
 // inverse passes (fft_passes.hip) on FP32 (dbl = false) or FP64 lines;
 // unit = the shell indicator instead of Theta_b D (count pass, FP64 only);
 // n_jobs jobs whose buffers are wstride bytes apart
+// weighted: apply the plan's window / P_fid weights (estimator fields);
+// unit_w: per-|n|^2 weight of the unit fields (count pass, may be null)
 hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, const float2* dc, void* a1, const void* tw,
-                     const TileSet& ts, int n_jobs, size_t wstride, hipStream_t s, int ell = 0);
+                     const TileSet& ts, int n_jobs, size_t wstride, hipStream_t s, int ell = 0,
+                     const double* unit_w = nullptr, bool weighted = false);
 hipError_t run_inv_y(const pb3_plan& p, bool dbl, const void* a1, void* a2, const void* tw, const TileSet& ts,
                      int n_jobs, size_t wstride, hipStream_t s);
 hipError_t run_inv_z(const pb3_plan& p, bool dbl, const void* a2, void* gout, const void* tw, const TileSet& ts,

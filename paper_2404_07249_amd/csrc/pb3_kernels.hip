@@ -27,7 +27,7 @@ namespace pb3 {
 // the index marks w = 1), then reduces with a fixed tree.
 __global__ void __launch_bounds__(256) k_power_chunks(const float2* __restrict__ dc, const int32_t* __restrict__ modes,
                                                       const int32_t* __restrict__ chunks, double* __restrict__ part,
-                                                      size_t wstride) {
+                                                      size_t wstride, const double* __restrict__ mw) {
   dc = job_ptr(dc, wstride);
   part = job_ptr(part, wstride);
   __shared__ double red[256];
@@ -37,6 +37,7 @@ __global__ void __launch_bounds__(256) k_power_chunks(const float2* __restrict__
   for (int i = start + threadIdx.x; i < end; i += 256) {
     int32_t m = modes[i];
     double w = (m < 0) ? 1.0 : 2.0;
+    if (mw) w *= mw[i];  // 1 / (m^2 P_fid^2) of the weighted estimator
     float2 v = dc[m & 0x7fffffff];
     double re = v.x, im = v.y;
     acc += w * (re * re + im * im);
@@ -51,14 +52,14 @@ __global__ void __launch_bounds__(256) k_power_chunks(const float2* __restrict__
 }
 
 __global__ void k_power_final(const double* __restrict__ part, const int32_t* __restrict__ chunk_first, int nb,
-                              const double* __restrict__ scale, const JobIO io, size_t wstride) {
+                              const double* __restrict__ scale, const JobIO io, size_t wstride, double shift) {
   part = job_ptr(part, wstride);
   double* __restrict__ pk = io.pk[blockIdx.z];
   int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb) return;
   double s = 0.0;
   for (int c = chunk_first[b]; c < chunk_first[b + 1]; ++c) s += part[c];
-  pk[b] = s * scale[b];
+  pk[b] = s * scale[b] - shift;
 }
 
 // ------------------------------------------------ simple triplet contraction
@@ -126,13 +127,14 @@ __global__ void __launch_bounds__(256) k_contract_simple(const Rl* __restrict__ 
 // triplet, times scale/T (scale = V^2 M^6 / N^9).
 template <typename Rl>
 __global__ void k_reduce(const Rl* __restrict__ part, int n_wg, int part_len, const int32_t* __restrict__ map,
-                         const double* __restrict__ fac, int n_out, double* __restrict__ out) {
+                         const double* __restrict__ fac, int n_out, double* __restrict__ out,
+                         const double* __restrict__ bias = nullptr) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_out) return;
   int idx = map[t];
   double s = 0.0;
   for (int w = 0; w < n_wg; ++w) s += (double)part[(size_t)w * part_len + idx];
-  out[t] = fac ? s * fac[t] : s;
+  out[t] = (fac ? s * fac[t] : s) - (bias ? bias[t] : 0.0);
 }
 
 // Two-stage form for the MFMA partials: slice s of the work-groups is
@@ -151,7 +153,8 @@ __global__ void k_reduce_slices(const float* __restrict__ part, int n_wg, int pa
 }
 
 __global__ void k_reduce_final(const double* __restrict__ rsl, int part_len, const int32_t* __restrict__ map,
-                               const double* __restrict__ fac, int n_out, const JobIO io, size_t wstride) {
+                               const double* __restrict__ fac, int n_out, const JobIO io, size_t wstride,
+                               const double* __restrict__ bias) {
   rsl = job_ptr(rsl, wstride);
   double* __restrict__ out = io.bk[blockIdx.z];
   int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -160,7 +163,7 @@ __global__ void k_reduce_final(const double* __restrict__ rsl, int part_len, con
   double acc = 0.0;
 #pragma unroll
   for (int s = 0; s < kReduceSlices; ++s) acc += rsl[(size_t)s * part_len + idx];
-  out[t] = acc * fac[t];
+  out[t] = acc * fac[t] - (bias ? bias[t] : 0.0);
 }
 
 // ---------------------------------------------------- window moments
@@ -319,7 +322,8 @@ __global__ void __launch_bounds__(64) k_masked_solve(const double* __restrict__ 
 __global__ void __launch_bounds__(256) k_power_ml_chunks(const float2* __restrict__ dc,
                                                          const int32_t* __restrict__ modes,
                                                          const int32_t* __restrict__ chunks, int Lc, int Kz, int Kc,
-                                                         int ne, double* __restrict__ part) {
+                                                         int ne, double* __restrict__ part,
+                                                         const double* __restrict__ mw) {
   __shared__ double red[3][256];
   const int c = blockIdx.x;
   const int start = chunks[3 * c + 1], end = chunks[3 * c + 2];
@@ -333,7 +337,7 @@ __global__ void __launch_bounds__(256) k_power_ml_chunks(const float2* __restric
     const double n2 = (double)kx * kx + (double)ky * ky + (double)kz * kz;
     const double m2 = n2 > 0 ? (double)kz * kz / n2 : 0.0;
     const float2 v = dc[idx];
-    const double p2 = w * ((double)v.x * v.x + (double)v.y * v.y);
+    const double p2 = w * (mw ? mw[i] : 1.0) * ((double)v.x * v.x + (double)v.y * v.y);
     acc[0] += p2;
     acc[1] += p2 * (1.5 * m2 - 0.5);
     acc[2] += p2 * ((35.0 * m2 * m2 - 30.0 * m2 + 3.0) * 0.125);
@@ -349,7 +353,7 @@ __global__ void __launch_bounds__(256) k_power_ml_chunks(const float2* __restric
 }
 
 __global__ void k_power_ml_final(const double* __restrict__ part, const int32_t* __restrict__ chunk_first, int nb,
-                                 int ne, const double* __restrict__ finv, double* __restrict__ out) {
+                                 int ne, const double* __restrict__ finv, double* __restrict__ out, double shift) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb) return;
   double p[3] = {0.0, 0.0, 0.0};
@@ -358,7 +362,7 @@ __global__ void k_power_ml_final(const double* __restrict__ part, const int32_t*
   for (int l = 0; l < ne; ++l) {
     double v = 0.0;
     for (int j = 0; j < ne; ++j) v += finv[((size_t)b * ne + l) * ne + j] * p[j];
-    out[(size_t)l * nb + b] = v;
+    out[(size_t)l * nb + b] = l == 0 ? v - shift : v;  // Poisson noise is isotropic: monopole only
   }
 }
 
@@ -377,11 +381,11 @@ hipError_t launch_window(long n, const float* w, double* pk, int nb, double* bk,
 
 hipError_t launch_power(const pb3_plan& p, const Exec& x, hipStream_t s) {
   hipLaunchKernelGGL(k_power_chunks, dim3(p.n_chunks, 1, x.n_jobs), dim3(256), 0, s, x.ws.dc, p.d.modes, p.d.chunk,
-                     x.ws.ppart, x.wstride);
+                     x.ws.ppart, x.wstride, (const double*)p.d.mode_w);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_power_final, dim3((p.nb + 63) / 64, 1, x.n_jobs), dim3(64), 0, s, x.ws.ppart,
-                     p.d.chunk_first, p.nb, p.d.pk_scale, x.io, x.wstride);
+                     p.d.chunk_first, p.nb, p.d.pk_scale, x.io, x.wstride, p.pk_shift);
   return hipGetLastError();
 }
 
@@ -432,7 +436,7 @@ hipError_t launch_reduce(const pb3_plan& p, const Exec& x, hipStream_t s) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reduce_final, dim3((n_out + 255) / 256, 1, x.n_jobs), dim3(256), 0, s, x.ws.rsl, p.part_len,
-                     p.d.out_map, p.d.inv_counts, n_out, x.io, x.wstride);
+                     p.d.out_map, p.d.inv_counts, n_out, x.io, x.wstride, (const double*)p.d.bk_bias);
   return hipGetLastError();
 }
 
@@ -567,16 +571,17 @@ pb3_status run_multipoles(pb3_plan& p, const float* delta, double* pk_out, doubl
     return st;
   if (pk_out) {
     hipLaunchKernelGGL(k_power_ml_chunks, dim3(p.n_chunks), dim3(256), 0, s, x.ws.dc, p.d.modes, p.d.chunk, p.Lc,
-                       p.Kz, p.Kc, ne, mpart);
+                       p.Kz, p.Kc, ne, mpart, (const double*)p.d.mode_w);
     if (!chk(hipGetLastError(), "multipoles: power")) return st;
     hipLaunchKernelGGL(k_power_ml_final, dim3((p.nb + 63) / 64), dim3(64), 0, s, mpart, p.d.chunk_first, p.nb, ne,
-                       p.d.pml_inv, pk_out);
+                       p.d.pml_inv, pk_out, p.pk_shift);
     if (!chk(hipGetLastError(), "multipoles: power")) return st;
   }
   if (!bk_out || nt == 0) return PB3_OK;
   for (int l = 0; l < ne; ++l) {
     float* gl = fields + (size_t)l * p.nb * m3;
-    if (!chk(run_inv_x(p, false, false, x.ws.dc, x.ws.a1, p.d.tw_m, p.tx, 1, 0, s, 2 * l), "multipoles: inv_x") ||
+    if (!chk(run_inv_x(p, false, false, x.ws.dc, x.ws.a1, p.d.tw_m, p.tx, 1, 0, s, 2 * l, nullptr, true),
+             "multipoles: inv_x") ||
         !chk(launch_inv_y(p, x, s), "multipoles: inv_y") ||
         !chk(run_inv_z(p, false, x.ws.a2, gl, p.d.tw_m, p.tz, 1, 0, s), "multipoles: inv_z"))
       return st;
@@ -593,7 +598,8 @@ pb3_status run_multipoles(pb3_plan& p, const float* delta, double* pk_out, doubl
       JobIO io{};
       io.bk[0] = bk_out + (size_t)l * nt;
       hipLaunchKernelGGL(k_reduce_final, dim3((nt + 255) / 256, 1, 1), dim3(256), 0, s, x.ws.rsl, p.part_len,
-                         p.d.out_map, p.d.ml_fac + (size_t)l * nt, nt, io, (size_t)0);
+                         p.d.out_map, p.d.ml_fac + (size_t)l * nt, nt, io, (size_t)0,
+                         l == 0 ? (const double*)p.d.bk_bias : nullptr);
       if (!chk(hipGetLastError(), "multipoles: reduce")) return st;
     }
     return PB3_OK;
@@ -604,7 +610,8 @@ pb3_status run_multipoles(pb3_plan& p, const float* delta, double* pk_out, doubl
              "multipoles: contraction"))
       return st;
     hipLaunchKernelGGL((k_reduce<double>), dim3((nt + 255) / 256), dim3(256), 0, s, part, kMlWgs, nt, p.d.ml_map,
-                       p.d.ml_fac + (size_t)l * nt, nt, bk_out + (size_t)l * nt);
+                       p.d.ml_fac + (size_t)l * nt, nt, bk_out + (size_t)l * nt,
+                       l == 0 ? (const double*)p.d.bk_bias : nullptr);
     if (!chk(hipGetLastError(), "multipoles: reduce")) return st;
   }
   return PB3_OK;
@@ -613,10 +620,15 @@ pb3_status run_multipoles(pb3_plan& p, const float* delta, double* pk_out, doubl
 // -------------------------------------------------------- FP64 counts
 // T_abc = M^6 sum_x H_a H_b H_c on the contraction grid, H_b = IDFT[Theta_b],
 // all in FP64 (N_0 of eq. N-ell-def with P_fid = 1), once per plan.
-pb3_status compute_counts_fp64(pb3_plan& p, std::vector<double>& counts_out) {
+pb3_status compute_counts_fp64(pb3_plan& p, std::vector<double>& counts_out, std::vector<double>* q_out) {
   const int n_cand = (int)(p.trip_all.size() / 3);
   counts_out.assign(n_cand, 0.0);
+  if (q_out) q_out->assign(n_cand, 0.0);
   if (n_cand == 0) return PB3_OK;
+  // fields: the (weighted) unit fields, then, for the shot-noise sums, the
+  // unweighted ones; the triplet table of each extra sum moves one leg
+  const int nf = q_out ? 2 * p.nb : p.nb;
+  int32_t* qtrips = nullptr;
   const long mvox = (long)p.M * p.M * p.M;
   const int nwg = 512;
   double2 *a1 = nullptr, *a2 = nullptr;
@@ -633,14 +645,15 @@ pb3_status compute_counts_fp64(pb3_plan& p, std::vector<double>& counts_out) {
   std::vector<int32_t> idmap(n_cand);
   for (int i = 0; i < n_cand; ++i) idmap[i] = i;
   if (!alloc((void**)&a1, sizeof(double2) * p.a1_len) || !alloc((void**)&a2, sizeof(double2) * p.a2_len) ||
-      !alloc((void**)&h, sizeof(double) * (size_t)p.nb * mvox) ||
+      !alloc((void**)&h, sizeof(double) * (size_t)nf * mvox) ||
+      (q_out && !alloc((void**)&qtrips, sizeof(int32_t) * 9 * (size_t)n_cand)) ||
       !alloc((void**)&part, sizeof(double) * (size_t)nwg * n_cand) || !alloc((void**)&out, sizeof(double) * n_cand) ||
       !alloc((void**)&map, sizeof(int32_t) * n_cand)) {
     st = PB3_ENOMEM;
     set_error("device allocation failed while computing triangle counts");
     goto done;
   }
-  e = hipMemset(h, 0, sizeof(double) * (size_t)p.nb * mvox);
+  e = hipMemset(h, 0, sizeof(double) * (size_t)nf * mvox);
   if (e != hipSuccess) { st = hip_fail(e, "hipMemset"); goto done; }
   e = hipMemcpy(map, idmap.data(), sizeof(int32_t) * n_cand, hipMemcpyHostToDevice);
   if (e != hipSuccess) { st = hip_fail(e, "hipMemcpy"); goto done; }
@@ -670,16 +683,41 @@ pb3_status compute_counts_fp64(pb3_plan& p, std::vector<double>& counts_out) {
     tsz = TileSet{tiles + vx.size() + vy.size(), (int)vz.size(), tbz};
   }
   {
-    hipError_t r = run_inv_x(p, true, true, nullptr, a1, p.d.tw_m_d, tsx, 1, 0, nullptr);
-    if (r != hipSuccess) { st = hip_fail(r, "count inverse x pass"); goto done; }
-    r = run_inv_y(p, true, a1, a2, p.d.tw_m_d, tsy, 1, 0, nullptr);
-    if (r != hipSuccess) { st = hip_fail(r, "count inverse y pass"); goto done; }
-    r = run_inv_z(p, true, a2, h, p.d.tw_m_d, tsz, 1, 0, nullptr);
-    if (r != hipSuccess) { st = hip_fail(r, "count inverse z pass"); goto done; }
-    r = contract_simple<double>(h, p.nb, mvox, p.d.trip_all, n_cand, nwg, part, nullptr);
+    hipError_t r = hipSuccess;
+    for (int set = 0; set < (q_out ? 2 : 1); ++set) {
+      const double* uw = set == 0 ? p.d.pfid_inv_d : nullptr;  // set 0: 1 / P_fid (null: unit), set 1: unit
+      double* hs = h + (size_t)set * p.nb * mvox;
+      r = run_inv_x(p, true, true, nullptr, a1, p.d.tw_m_d, tsx, 1, 0, nullptr, 0, uw);
+      if (r != hipSuccess) { st = hip_fail(r, "count inverse x pass"); goto done; }
+      r = run_inv_y(p, true, a1, a2, p.d.tw_m_d, tsy, 1, 0, nullptr);
+      if (r != hipSuccess) { st = hip_fail(r, "count inverse y pass"); goto done; }
+      r = run_inv_z(p, true, a2, hs, p.d.tw_m_d, tsz, 1, 0, nullptr);
+      if (r != hipSuccess) { st = hip_fail(r, "count inverse z pass"); goto done; }
+    }
+    if (q_out) {
+      // Q = sum_x (H_a Hw_b Hw_c + Hw_a H_b Hw_c + Hw_a Hw_b H_c)
+      std::vector<int32_t> qt(9 * (size_t)n_cand);
+      for (int leg = 0; leg < 3; ++leg)
+        for (int t = 0; t < n_cand; ++t)
+          for (int k = 0; k < 3; ++k)
+            qt[((size_t)leg * n_cand + t) * 3 + k] = p.trip_all[3 * t + k] + (k == leg ? p.nb : 0);
+      r = hipMemcpy(qtrips, qt.data(), sizeof(int32_t) * qt.size(), hipMemcpyHostToDevice);
+      if (r != hipSuccess) { st = hip_fail(r, "hipMemcpy"); goto done; }
+      std::vector<double> tmp(n_cand);
+      for (int leg = 0; leg < 3; ++leg) {
+        r = contract_simple<double>(h, nf, mvox, qtrips + (size_t)3 * leg * n_cand, n_cand, nwg, part, nullptr);
+        if (r != hipSuccess) { st = hip_fail(r, "shot-noise contraction"); goto done; }
+        hipLaunchKernelGGL((k_reduce<double>), dim3((n_cand + 255) / 256), dim3(256), 0, nullptr, part, nwg, n_cand,
+                           map, (const double*)nullptr, n_cand, out, (const double*)nullptr);
+        r = hipMemcpy(tmp.data(), out, sizeof(double) * n_cand, hipMemcpyDeviceToHost);
+        if (r != hipSuccess) { st = hip_fail(r, "shot-noise copy"); goto done; }
+        for (int t = 0; t < n_cand; ++t) (*q_out)[t] += tmp[t];
+      }
+    }
+    r = contract_simple<double>(h, nf, mvox, p.d.trip_all, n_cand, nwg, part, nullptr);
     if (r != hipSuccess) { st = hip_fail(r, "count contraction"); goto done; }
     hipLaunchKernelGGL((k_reduce<double>), dim3((n_cand + 255) / 256), dim3(256), 0, nullptr, part, nwg, n_cand, map,
-                       (const double*)nullptr, n_cand, out);
+                       (const double*)nullptr, n_cand, out, (const double*)nullptr);
     r = hipGetLastError();
     if (r != hipSuccess) { st = hip_fail(r, "count reduce"); goto done; }
     r = hipMemcpy(counts_out.data(), out, sizeof(double) * n_cand, hipMemcpyDeviceToHost);
@@ -687,8 +725,11 @@ pb3_status compute_counts_fp64(pb3_plan& p, std::vector<double>& counts_out) {
     double m6 = (double)p.M * p.M * p.M;
     m6 *= m6;
     for (auto& v : counts_out) v *= m6;
+    if (q_out)
+      for (auto& v : *q_out) v *= m6;
   }
 done:
+  hipFree(qtrips);
   hipFree(a1);
   hipFree(a2);
   hipFree(h);

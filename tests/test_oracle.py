@@ -510,3 +510,155 @@ def test_multipoles_symmetries():
                            atol=1e-9 * np.abs(B).max())
     Pz = mp.power_multipoles(np.swapaxes(d, 0, 2), box, edges)
     assert not np.allclose(Pz[1], P[1], rtol=1e-3)
+
+
+# ---------------------------------------------- weighted ideal estimators
+
+
+def _pfid_table(n, box, edges):
+    kf = 2 * np.pi / box
+    e2 = int(np.ceil(np.asarray(edges)[-1] ** 2))
+    t = pk_model(kf * np.sqrt(np.arange(e2 + 1, dtype=np.float64))) + 500.0
+    t[0] = 1.0
+    return t
+
+
+def test_weighted_sums_equal_mode_loops():
+    from oracle import weighted as wt
+
+    n, box = 8, 300.0
+    edges = np.array([1.0, 2.0, 3.0, 4.0])
+    d = quadratic_field(n, box, 0.6, 41)
+    pf = _pfid_table(n, box, edges)
+    trips, B, n0, _ = wt.weighted_bispectrum(d, box, edges, order=2, pfid=pf)
+    num, n0b, qb = wt.brute_weighted_sums(d, edges, trips, order=2, pfid=pf)
+    assert np.allclose(n0, n0b, rtol=1e-10)
+    npix = float(n) ** 3
+    assert np.allclose(B, box**6 / npix**3 * num.real / n0b, rtol=1e-9, atol=1e-9 * np.abs(B).max())
+    # shot-noise term through the separable route against the loops
+    nbar = 2e-4
+    _, Bs, _, _ = wt.weighted_bispectrum(d, box, edges, order=2, pfid=pf, nbar=nbar)
+    shot = 1 / nbar**2 + (qb / n0b - 3 / nbar) / nbar
+    assert np.allclose(B - Bs, shot, rtol=1e-10)
+
+
+def test_weighted_reduces_and_deconvolves():
+    """Constant P_fid and no window give the unweighted estimators; a window
+    applied to the field in Fourier space is undone by the deconvolution."""
+    from oracle import weighted as wt
+
+    n, box = 16, 500.0
+    edges = kf_edges(4)
+    d = quadratic_field(n, box, 1.0, 3)
+    res = oracle.bispectrum(d, box, edges)
+    const = np.full(int(np.ceil(edges[-1] ** 2)) + 1, 7.0)
+    assert np.allclose(wt.weighted_power(d, box, edges, 0, const), res.pk, rtol=1e-12)
+    _, B, _, _ = wt.weighted_bispectrum(d, box, edges, 0, const)
+    assert np.allclose(B, res.bk, rtol=1e-10, atol=1e-12 * np.abs(res.bk).max())
+    for order in (1, 2, 3):
+        dw = np.fft.ifftn(np.fft.fftn(d) * wt.window(n, order)).real
+        assert np.allclose(wt.weighted_power(dw, box, edges, order), res.pk, rtol=1e-10)
+        _, Bw, _, _ = wt.weighted_bispectrum(dw, box, edges, order)
+        assert np.allclose(Bw, res.bk, rtol=1e-8, atol=1e-10 * np.abs(res.bk).max())
+
+
+def test_shot_noise_of_poisson_field_is_removed():
+    """Uniform Poisson counts in cells (no clustering): with P_fid = 1/nbar
+    (pure noise, so the power model P_fid - 1/nbar is zero) the shot-noise
+    corrected P and B average to zero; without the correction they are
+    1/nbar and 1/nbar^2."""
+    from oracle import weighted as wt
+
+    n, box = 16, 400.0
+    edges = kf_edges(4)
+    cell = (box / n) ** 3
+    lam = 4.0  # mean count per cell
+    nbar = lam / cell
+    pf = np.full(int(np.ceil(edges[-1] ** 2)) + 1, 1.0 / nbar)
+    Ps, Bs = [], []
+    for s in range(150):
+        cnt = np.random.default_rng(800 + s).poisson(lam, (n, n, n)).astype(np.float64)
+        delta = cnt / lam - 1.0
+        Ps.append(wt.weighted_power(delta, box, edges, 0, pf, nbar))
+        Bs.append(wt.weighted_bispectrum(delta, box, edges, 0, pf, nbar)[1])
+    Ps, Bs = np.array(Ps), np.array(Bs)
+    zp = Ps.mean(0) / (Ps.std(0, ddof=1) / np.sqrt(len(Ps)))
+    zb = Bs.mean(0) / (Bs.std(0, ddof=1) / np.sqrt(len(Bs)))
+    assert np.all(np.abs(zp) < 4.5), zp
+    assert np.all(np.abs(zb) < 4.5), np.abs(zb).max()
+    # the subtracted terms are resolved: without them the means are far from zero
+    assert np.all(np.abs((Ps.mean(0) + 1 / nbar) / (Ps.std(0, ddof=1) / np.sqrt(len(Ps)))) > 10)
+    assert np.median(np.abs((Bs.mean(0) + 1 / nbar**2) / (Bs.std(0, ddof=1) / np.sqrt(len(Bs))))) > 5
+
+
+def _field_with_power(n, box, order, c, seed):
+    """Hermitian Fourier field with |D/m|^2 = (N_pix^2/V) sum_l c_l L_l(mu)
+    exactly (deterministic amplitudes, random phases), returned in real space."""
+    from oracle import weighted as wt
+    from oracle.multipoles import legendre, mu_grid
+
+    npix, vol = float(n) ** 3, float(box) ** 3
+    mu = mu_grid(n)
+    shape = sum(cl * legendre(2 * i, mu) for i, cl in enumerate(c))
+    assert shape.min() > 0
+    amp = wt.window(n, order) * np.sqrt(npix**2 / vol * shape)
+    ph = np.random.default_rng(seed).uniform(-np.pi, np.pi, (n, n, n))
+    neg = (-np.arange(n)) % n
+    ph = 0.5 * (ph - ph[np.ix_(neg, neg, neg)])  # odd phase: D(-n) = conj D(n)
+    D = amp * np.exp(1j * ph)
+    D[0, 0, 0] = 0.0
+    return np.fft.ifftn(D).real
+
+
+def test_weighted_power_multipoles_recover_anisotropic_power():
+    """A field whose deconvolved mode power is exactly c0 + c2 L_2(mu) + c4 L_4(mu)
+    gives P_0 = c0 - 1/nbar, P_2 = c2, P_4 = c4 for any P_fid weights: the
+    discrete Fisher matrix and the numerator carry the same weights."""
+    from oracle import weighted as wt
+    from oracle.multipoles import legendre, mu_grid
+
+    n, box = 16, 400.0
+    edges = kf_edges(5)
+    c0, c2, c4 = 3.0e3, 1.2e3, 4.0e2
+    d = _field_with_power(n, box, 2, (c0, c2, c4), 7)
+    pf = _pfid_table(n, box, edges)
+    nbar = 1e-3
+    P = wt.weighted_power_multipoles(d, box, edges, 4, order=2, pfid=pf, nbar=nbar)
+    assert np.allclose(P[0], c0 - 1 / nbar, rtol=1e-10)
+    assert np.allclose(P[1], c2, rtol=1e-10)
+    assert np.allclose(P[2], c4, rtol=1e-10)
+    # the couplings are real: L_4 does not average out over the bins of a
+    # finite grid, so a diagonal normalisation would bias the monopole
+    idx = oracle.bin_of_modes(n, edges)
+    L4 = legendre(4, mu_grid(n))
+    assert max(abs(L4[idx == b].mean()) for b in range(len(edges) - 1)) > 1e-2
+
+
+def test_weighted_multipoles_reduce_and_match_mode_loops():
+    from oracle import multipoles as ml
+    from oracle import weighted as wt
+
+    n, box = 8, 300.0
+    edges = np.array([1.0, 2.0, 3.0, 4.0])
+    d = quadratic_field(n, box, 0.6, 43)
+    pf = _pfid_table(n, box, edges)
+    nbar = 5e-4
+    trips, Bl = wt.weighted_bispectrum_multipoles(d, box, edges, 4, order=3, pfid=pf, nbar=nbar)
+    _, B0, n0, _ = wt.weighted_bispectrum(d, box, edges, 3, pf, nbar)
+    assert np.array_equal(Bl[0], B0)
+    npix = float(n) ** 3
+    for i, ell in enumerate((2, 4), start=1):
+        num, n0b, _ = wt.brute_weighted_sums(d, edges, trips, order=3, pfid=pf, ell=ell)
+        want = (2 * ell + 1) * box**6 / npix**3 * num.real / n0b
+        assert np.allclose(Bl[i], want, rtol=1e-9, atol=1e-9 * np.abs(want).max())
+    # constant P_fid, no window, no noise: the unweighted multipoles
+    n, box = 16, 500.0
+    edges = kf_edges(4)
+    d = quadratic_field(n, box, 1.0, 5)
+    const = np.full(int(np.ceil(edges[-1] ** 2)) + 1, 3.0)
+    assert np.allclose(wt.weighted_power_multipoles(d, box, edges, 4, 0, const),
+                       ml.power_multipoles(d, box, edges, 4), rtol=1e-10, atol=1e-12)
+    t1, B1 = wt.weighted_bispectrum_multipoles(d, box, edges, 2, 0, const)
+    t2, B2 = ml.bispectrum_multipoles(d, box, edges, 2)
+    assert np.array_equal(t1, t2)
+    assert np.allclose(B1, B2, rtol=1e-9, atol=1e-11 * np.abs(B2).max())
