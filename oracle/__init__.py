@@ -34,6 +34,11 @@ Parity status of each function (what pins it is in ``tests/test_oracle.py``):
                            deconvolution undoes a window applied in Fourier
                            space; Poisson noise of a uniform field is removed
                            on average from P and B.
+* ``injection`` (expectation under an injected bispectrum) pinned: the
+                           separable bin average equals explicit loops over
+                           closed triangles; the oracle estimator's linear
+                           response to the injection averages to it over
+                           seeds.
 """
 
 from .polyspec import (  # noqa: F401
@@ -61,3 +66,4 @@ from .brute import brute_sums  # noqa: F401
 from . import masked  # noqa: F401,E402
 from . import multipoles  # noqa: F401,E402
 from . import weighted  # noqa: F401,E402
+from . import injection  # noqa: F401,E402

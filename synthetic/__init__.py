@@ -33,6 +33,8 @@ __all__ = [
     "batch_jobs",
     "window_mask",
     "serve_schedule",
+    "injection_beta",
+    "injected_field",
 ]
 
 
@@ -63,6 +65,29 @@ def gaussian_field(n: int, box: float, seed: int, pk=pk_model) -> np.ndarray:
     amp = np.sqrt(pk(_kmag(n, box)) * npix / vol)
     amp[0, 0, 0] = 0.0
     return np.fft.irfftn(wk * amp, s=(n, n, n), axes=(0, 1, 2))
+
+
+def injection_beta(k, kmin: float = 0.1, kmax: float = 0.4, pk=pk_model) -> np.ndarray:
+    """beta(k) = P(k)^(2/3) on kmin <= k < kmax, zero elsewhere: the injected
+    bispectrum's factor (validation set-up of Sec. VI.B.1)."""
+    k = np.asarray(k, dtype=np.float64)
+    return np.where((k >= kmin) & (k < kmax), pk(k) ** (2.0 / 3.0), 0.0)
+
+
+def injected_field(n: int, box: float, eps: float, seed: int, kmin: float = 0.1, kmax: float = 0.4,
+                   pk=pk_model) -> np.ndarray:
+    """Gaussian field g with an injected bispectrum eps beta1 beta2 beta3
+    (Sec. VI.B.1): d = g + (eps/6) IDFT[beta DFT[phi^2]], phi = IDFT[(beta/P) DFT[g]]
+    (numpy DFT normalisation, so the volume factors of the continuum form
+    cancel).  The same seed gives the same g for every eps."""
+    g = gaussian_field(n, box, seed, pk)
+    k = _kmag(n, box)
+    beta = injection_beta(k, kmin, kmax, pk)
+    P = pk(k)
+    ratio = np.divide(beta, P, out=np.zeros_like(beta), where=P > 0)
+    phi = np.fft.irfftn(np.fft.rfftn(g) * ratio, s=(n, n, n), axes=(0, 1, 2))
+    extra = np.fft.irfftn(np.fft.rfftn(phi * phi) * beta, s=(n, n, n), axes=(0, 1, 2))
+    return g + (eps / 6.0) * extra
 
 
 def quadratic_field(n: int, box: float, fnl: float, seed: int, pk=pk_model) -> np.ndarray:
