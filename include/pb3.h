@@ -177,6 +177,32 @@ pb3_status pb3_masked_power(pb3_plan* plan, const float* data_dev, const float* 
                             const float* const* grfs_dev, int n_grf, double* pk_dev, double* fisher_dev,
                             void* workspace_dev, size_t workspace_bytes, void* stream);
 
+/* Bispectrum with the linear term of the numerator (eq. b-numerator-practical,
+ * Sec. IV.C), averaged over n_sim fields Delta_i with about the data's
+ * covariance (simulations or Gaussian fields passed through the same window):
+ *   B = (V^2/N_pix) [S(d) - (1/n_sim) sum_i S_lin(d; Delta_i)] / T,
+ *   S_lin = sum_x (G_a[d] G_b[D] G_c[D] + G_a[D] G_b[d] G_c[D] + G_a[D] G_b[D] G_c[d]),
+ * unit weighting, in the units of pb3_bispectrum (divide by <w^3> with
+ * pb3_window_normalize for the windowed form).  The term vanishes in
+ * expectation; it lowers the variance where a window breaks translation
+ * invariance (zero in the ideal limit).  Evaluated as the part of the cubic
+ * S(D + d) with one factor of d, [S(D + d) - S(D - d)] / 2 - S(d), through the
+ * plan's own launch sequence (two jobs per Delta_i, up to 8 jobs per launch)
+ * and combined in FP64.
+ *   data_dev  N^3 float32
+ *   sims_dev  host array of n_sim >= 1 device pointers to N^3 float32 fields
+ *   bk_dev    n_trip float64 output
+ *   workspace >= pb3_bispectrum_linear_workspace_bytes(plan, n_sim), 256-byte
+ *             aligned (up to 8 copies of the plan's workspace, the D +- d
+ *             fields and per-job outputs)
+ * Errors: PB3_EINVAL (null argument, host-only or power-only plan, plan with
+ * pb3_plan_set_weights, n_sim < 1, bad precision), PB3_ENOMEM (workspace too
+ * small), PB3_EDEVICE. */
+size_t pb3_bispectrum_linear_workspace_bytes(const pb3_plan* plan, int n_sim);
+pb3_status pb3_bispectrum_linear(pb3_plan* plan, const float* data_dev, const float* const* sims_dev, int n_sim,
+                                 double* bk_dev, pb3_precision prec, void* workspace_dev, size_t workspace_bytes,
+                                 void* stream);
+
 /* Weighted ideal estimators (Sec. III.D.1 eq. pk-limit and Sec. IV.D.1 with
  * P_fid, the pixel window m(k) and the Poisson shot-noise terms):
  *   P_b = (V/N_pix^2) sum_{n in b} |D/m|^2 / P_fid^2 / sum_{n in b} 1 / P_fid^2  -  1/nbar

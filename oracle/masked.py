@@ -20,13 +20,18 @@ d = IDFT with 1/N_pix):
 
 With w = 1 the Fisher matrix is (1/2) diag(N_b) exactly in expectation and
 P_unw reduces to the box estimator.
+
+The bispectrum's linear term (eq. b-numerator-practical) is averaged over
+fields Delta with covariance close to the data's (simulations through the
+same window); it vanishes in expectation and lowers the variance where the
+window breaks translation invariance.
 """
 
 from __future__ import annotations
 
 import numpy as np
 
-from .polyspec import bin_of_modes, dft, idft, power_spectrum, unit_fields
+from .polyspec import bin_of_modes, dft, idft, power_spectrum, triangle_counts, triangle_triplets, unit_fields
 
 
 def mc_fisher_power(w: np.ndarray, grfs, edges) -> np.ndarray:
@@ -77,3 +82,70 @@ def unwindowed_power(data: np.ndarray, box: float, edges, fisher: np.ndarray) ->
     nm = np.array([np.count_nonzero(idx == b) for b in range(nb)], dtype=np.float64)
     p = 0.5 * nm * power_spectrum(data, box, edges)
     return np.linalg.solve(fisher, p)
+
+
+def bispectrum_linear(data: np.ndarray, sims, box: float, edges):
+    """Bispectrum with the linear term of eq. (b-numerator-practical), unit
+    weighting, normalised like the ideal estimator (divide by <w^3> for the
+    windowed form):
+
+        B = (V^2/N_pix) [S(d) - (1/n_sim) sum_i S_lin(d; Delta_i)] / T,
+        S(d)  = sum_x G_a[d] G_b[d] G_c[d],
+        S_lin = sum_x (G_a[d] G_b[D] G_c[D] + G_a[D] G_b[d] G_c[D] + G_a[D] G_b[D] G_c[d]),
+
+    the linear term being the Monte Carlo average over the given fields
+    Delta_i (covariance close to the data's).  Returns (triplets with T > 0,
+    B with the term, B without it, A = same normalisation of
+    sum_x |G_a G_b G_c| + the mean of the three |mixed| sums)."""
+    d = np.asarray(data, dtype=np.float64)
+    n = d.shape[0]
+    npix, vol = float(n) ** 3, float(box) ** 3
+    trips = triangle_triplets(edges)
+    T, _ = triangle_counts(n, edges, trips)
+    keep = T > 0
+    trips, T = trips[keep], T[keep]
+    idx = bin_of_modes(n, edges)
+    nb = len(edges) - 1
+
+    def fields(f):
+        F = dft(np.asarray(f, dtype=np.float64))
+        return np.stack([idft(np.where(idx == b, F, 0.0)).real for b in range(nb)])
+
+    Gd = fields(d)
+    s = np.array([np.sum(Gd[a] * Gd[b] * Gd[c]) for a, b, c in trips])
+    sa = np.array([np.sum(np.abs(Gd[a] * Gd[b] * Gd[c])) for a, b, c in trips])
+    lin = np.zeros(len(trips))
+    la = np.zeros(len(trips))
+    sims = list(sims)
+    for sim in sims:
+        Ge = fields(sim)
+        for t, (a, b, c) in enumerate(trips):
+            x1, x2, x3 = Gd[a] * Ge[b] * Ge[c], Ge[a] * Gd[b] * Ge[c], Ge[a] * Ge[b] * Gd[c]
+            lin[t] += np.sum(x1) + np.sum(x2) + np.sum(x3)
+            la[t] += np.sum(np.abs(x1)) + np.sum(np.abs(x2)) + np.sum(np.abs(x3))
+    lin /= len(sims)
+    la /= len(sims)
+    fac = vol * vol / npix / T
+    return trips, (s - lin) * fac, s * fac, (sa + la) * fac
+
+
+def brute_linear_sum(data: np.ndarray, sim: np.ndarray, edges, trips) -> np.ndarray:
+    """sum over closed mode triangles of D1 E2 E3 + E1 D2 E3 + E1 E2 D3 with
+    D = DFT[data], E = DFT[sim], by explicit loops (N <= 8)."""
+    d = np.asarray(data, dtype=np.float64)
+    n = d.shape[0]
+    if n > 8:
+        raise ValueError("brute force is for N <= 8")
+    D, E = dft(d), dft(np.asarray(sim, dtype=np.float64))
+    idx = bin_of_modes(n, edges)
+    modes = [np.argwhere(idx == b) for b in range(len(edges) - 1)]
+    out = np.zeros(len(trips), dtype=np.complex128)
+    for t, (a, b, c) in enumerate(trips):
+        for i1 in modes[a]:
+            for i2 in modes[b]:
+                i3 = tuple((-i1 - i2) % n)
+                if idx[i3] != c:
+                    continue
+                j1, j2 = tuple(i1), tuple(i2)
+                out[t] += D[j1] * E[j2] * E[i3] + E[j1] * D[j2] * E[i3] + E[j1] * E[j2] * D[i3]
+    return out

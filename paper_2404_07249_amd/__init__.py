@@ -245,6 +245,27 @@ class Plan:
             workspace.numel() * workspace.element_size(), _stream_handle(stream)))
         return pk, fm
 
+    def linear_workspace_bytes(self, n_sim: int) -> int:
+        return int(self._lib.pb3_bispectrum_linear_workspace_bytes(self._h, int(n_sim)))
+
+    def bispectrum_linear(self, data, sims, precision: str = "mixed", out=None, workspace=None, stream=None):
+        """B with the bispectrum numerator's linear term averaged over the
+        fields ``sims`` (about the data's covariance, e.g. simulations through
+        the same window); units of :meth:`bispectrum`."""
+        import torch
+
+        self._check_field(data)
+        for g in sims:
+            self._check_field(g)
+        bk = self._out(out, self.n_triplets, data)
+        if workspace is None:
+            workspace = torch.empty(self.linear_workspace_bytes(len(sims)), dtype=torch.uint8, device=data.device)
+        sa = (C.c_void_p * len(sims))(*[g.data_ptr() for g in sims])
+        _lib.check(self._lib.pb3_bispectrum_linear(
+            self._h, C.c_void_p(data.data_ptr()), sa, len(sims), C.c_void_p(bk.data_ptr()), _PREC[precision],
+            C.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size(), _stream_handle(stream)))
+        return bk
+
     @property
     def weights_table_len(self) -> int:
         """Entries the P_fid table of :meth:`set_weights` needs (|n|^2 = 0 .. len-1)."""

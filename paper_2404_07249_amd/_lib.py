@@ -49,6 +49,10 @@ SIGNATURES = [
     ("pb3_polyspectra", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     ("pb3_window_normalize", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("pb3_masked_power_workspace_bytes", C.c_size_t, [C.c_void_p]),
+    ("pb3_bispectrum_linear_workspace_bytes", C.c_size_t, [C.c_void_p, C.c_int]),
+    ("pb3_bispectrum_linear", C.c_int,
+     [C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p), C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_size_t,
+      C.c_void_p]),
     ("pb3_masked_power", C.c_int,
      [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p), C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
       C.c_size_t, C.c_void_p]),

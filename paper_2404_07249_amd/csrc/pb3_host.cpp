@@ -932,6 +932,54 @@ pb3_status pb3_window_normalize(const pb3_plan* plan, const float* w_dev, double
 
 size_t pb3_masked_power_workspace_bytes(const pb3_plan* plan) { return plan ? masked_workspace_bytes(*plan) : 0; }
 
+size_t pb3_bispectrum_linear_workspace_bytes(const pb3_plan* plan, int n_sim) {
+  return (plan && n_sim >= 1) ? linear_workspace_bytes(*plan, n_sim) : 0;
+}
+
+pb3_status pb3_bispectrum_linear(pb3_plan* plan, const float* data_dev, const float* const* sims_dev, int n_sim,
+                                 double* bk_dev, pb3_precision prec, void* workspace_dev, size_t workspace_bytes_,
+                                 void* stream) {
+  if (!plan || !data_dev || !sims_dev || !bk_dev || !workspace_dev) {
+    set_error("null argument");
+    return PB3_EINVAL;
+  }
+  if (!plan->device) {
+    set_error("plan has no device state (created with PB3_FLAG_HOST_ONLY)");
+    return PB3_EINVAL;
+  }
+  if (plan->flags & PB3_FLAG_POWER_ONLY) {
+    set_error("plan was created with PB3_FLAG_POWER_ONLY (no bispectrum tables)");
+    return PB3_EINVAL;
+  }
+  if (plan->weighted) {
+    set_error("the linear term takes unit weights (plan has pb3_plan_set_weights)");
+    return PB3_EINVAL;
+  }
+  if (n_sim < 1) {
+    set_error("at least one field is needed for the linear term");
+    return PB3_EINVAL;
+  }
+  for (int i = 0; i < n_sim; ++i)
+    if (!sims_dev[i]) {
+      set_error("null field");
+      return PB3_EINVAL;
+    }
+  pb3_status st = check_prec(prec);
+  if (st != PB3_OK) return st;
+  const size_t need = linear_workspace_bytes(*plan, n_sim);
+  if (workspace_bytes_ < need || ((uintptr_t)workspace_dev) % 256) {
+    set_error("workspace too small or not 256-byte aligned: need " + std::to_string(need) + " bytes");
+    return PB3_ENOMEM;
+  }
+  int dev = -1;
+  hipGetDevice(&dev);
+  if (dev != plan->device_id) {
+    set_error("plan was created on another device");
+    return PB3_EINVAL;
+  }
+  return run_bispectrum_linear(*plan, data_dev, sims_dev, n_sim, bk_dev, prec, workspace_dev, (hipStream_t)stream);
+}
+
 pb3_status pb3_masked_power(pb3_plan* plan, const float* data_dev, const float* window_dev,
                             const float* const* grfs_dev, int n_grf, double* pk_dev, double* fisher_dev,
                             void* workspace_dev, size_t workspace_bytes_, void* stream) {

@@ -214,6 +214,10 @@ pb3_status run_multipoles(pb3_plan& p, const float* delta, double* pk_out, doubl
                           void* workspace, hipStream_t s);
 pb3_status run_masked_power(pb3_plan& p, const float* data, const float* window, const float* const* grfs, int n_grf,
                             double* pk_out, double* f_out, void* workspace, hipStream_t s);
+// bispectrum with the Monte Carlo linear term (pb3_kernels.hip)
+size_t linear_workspace_bytes(const pb3_plan& p, int n_sim);
+pb3_status run_bispectrum_linear(pb3_plan& p, const float* data, const float* const* sims, int n_sim, double* bk_out,
+                                 pb3_precision prec, void* workspace, hipStream_t s);
 // MFMA contraction (contract_mfma.hip): tiles for nq 16-bin groups, the
 // partial-vector index of triplet (a, b, c) (-1 if not produced), launch
 int mfma_tiles(int nq);

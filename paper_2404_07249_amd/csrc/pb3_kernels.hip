@@ -617,6 +617,110 @@ pb3_status run_multipoles(pb3_plan& p, const float* delta, double* pk_out, doubl
   return PB3_OK;
 }
 
+// ----------------------------------------------- bispectrum linear term
+// The linear term of the bispectrum numerator, averaged over fields Delta_i
+// with (about) the data's covariance:
+//   S_lin(d; D) = sum_x (G_a[d] G_b[D] G_c[D] + G_a[D] G_b[d] G_c[D] + G_a[D] G_b[D] G_c[d]).
+// S is cubic and G linear in the field, so the part of S(D + d) with one
+// factor of d is  S_lin = [S(D + d) - S(D - d)] / 2 - S(d);  the fields D +- d
+// run through the plan's own launch sequence, two jobs per Delta_i and up
+// to kMaxJobs jobs per launch, and the normalised results combine in FP64:
+//   B = B(d) - (1/n) sum_i B_lin,i = 2 B(d) - (1/(2n)) sum_i [B(D_i + d) - B(D_i - d)].
+struct LinIO {
+  const float* sim[kMaxJobs / 2];
+};
+
+__global__ void __launch_bounds__(256) k_lin_fields(const float* __restrict__ d, const LinIO io, size_t n3,
+                                                    float* __restrict__ out) {
+  const float* __restrict__ e = io.sim[blockIdx.y];
+  float* __restrict__ plus = out + (size_t)(2 * blockIdx.y) * n3;
+  float* __restrict__ minus = plus + n3;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n3; i += stride) {
+    const float dv = d[i], ev = e[i];
+    plus[i] = ev + dv;
+    minus[i] = ev - dv;
+  }
+}
+
+// acc[t] (+)= sum_j (B(D_j + d) - B(D_j - d)), jobs in order
+__global__ void k_lin_acc(const double* __restrict__ bt, int n_s, int nt, double* __restrict__ acc, int first) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  double s = first ? 0.0 : acc[t];
+  for (int j = 0; j < n_s; ++j) s += bt[(size_t)(2 * j) * nt + t] - bt[(size_t)(2 * j + 1) * nt + t];
+  acc[t] = s;
+}
+
+__global__ void k_lin_final(double* __restrict__ bk, const double* __restrict__ acc, int nt, double inv2n) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  bk[t] = 2.0 * bk[t] - acc[t] * inv2n;
+}
+
+static int lin_jobs(int n_sim) { return std::min(kMaxJobs, 2 * std::max(n_sim, 1)); }
+
+size_t linear_workspace_bytes(const pb3_plan& p, int n_sim) {
+  const size_t A = 256, n3 = (size_t)p.N * p.N * p.N, nt = std::max<size_t>(p.trip.size() / 3, 1);
+  auto up = [&](size_t b) { return (b + A - 1) / A * A; };
+  const size_t J = (size_t)lin_jobs(n_sim);
+  return J * up(workspace_bytes(&p)) + up(sizeof(float) * J * n3) + up(sizeof(double) * J * nt) +
+         up(sizeof(double) * nt);
+}
+
+pb3_status run_bispectrum_linear(pb3_plan& p, const float* data, const float* const* sims, int n_sim, double* bk_out,
+                                 pb3_precision prec, void* workspace, hipStream_t s) {
+  const size_t A = 256, n3 = (size_t)p.N * p.N * p.N;
+  const int nt = (int)(p.trip.size() / 3);
+  auto up = [&](size_t b) { return (b + A - 1) / A * A; };
+  const int J = lin_jobs(n_sim);
+  const size_t stride = up(workspace_bytes(&p));
+  char* c = (char*)workspace;
+  char* wsb = c;
+  c += (size_t)J * stride;
+  float* fields = (float*)c;
+  c += up(sizeof(float) * J * n3);
+  double* bt = (double*)c;
+  c += up(sizeof(double) * J * std::max(nt, 1));
+  double* acc = (double*)c;
+  if (nt == 0) return PB3_OK;
+  pb3_status st;
+  Exec x0;
+  x0.ws = carve(&p, wsb, stride);
+  x0.wstride = stride;
+  x0.n_jobs = 1;
+  x0.io.delta[0] = data;
+  x0.io.bk[0] = bk_out;
+  if ((st = enqueue(p, x0, false, true, prec, s)) != PB3_OK) return st;
+  const int per = J / 2;
+  const unsigned blocks = (unsigned)std::min<size_t>((n3 + 255) / 256, 2048);
+  for (int i0 = 0; i0 < n_sim; i0 += per) {
+    const int ns = std::min(per, n_sim - i0);
+    LinIO io{};
+    for (int j = 0; j < ns; ++j) io.sim[j] = sims[i0 + j];
+    hipLaunchKernelGGL(k_lin_fields, dim3(blocks, ns), dim3(256), 0, s, data, io, n3, fields);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "linear term: fields");
+    Exec x;
+    x.ws = carve(&p, wsb, stride);
+    x.wstride = stride;
+    x.n_jobs = 2 * ns;
+    for (int k = 0; k < 2 * ns; ++k) {
+      x.io.delta[k] = fields + (size_t)k * n3;
+      x.io.bk[k] = bt + (size_t)k * nt;
+    }
+    if ((st = enqueue(p, x, false, true, prec, s)) != PB3_OK) return st;
+    hipLaunchKernelGGL(k_lin_acc, dim3((nt + 255) / 256), dim3(256), 0, s, (const double*)bt, ns, nt, acc,
+                       i0 == 0 ? 1 : 0);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "linear term: accumulate");
+  }
+  hipLaunchKernelGGL(k_lin_final, dim3((nt + 255) / 256), dim3(256), 0, s, bk_out, (const double*)acc, nt,
+                     0.5 / n_sim);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? PB3_OK : hip_fail(e, "linear term: combine");
+}
+
 // -------------------------------------------------------- FP64 counts
 // T_abc = M^6 sum_x H_a H_b H_c on the contraction grid, H_b = IDFT[Theta_b],
 // all in FP64 (N_0 of eq. N-ell-def with P_fid = 1), once per plan.

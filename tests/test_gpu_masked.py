@@ -15,7 +15,7 @@ import pytest
 
 import oracle
 from oracle import masked
-from synthetic import kf_edges, quadratic_field, window_mask
+from synthetic import gaussian_field, kf_edges, quadratic_field, window_mask
 
 pytestmark = pytest.mark.gpu
 
@@ -107,3 +107,67 @@ def test_masked_power_argument_errors(torch_cuda):
     with pytest.raises(pb3.Pb3Error):
         full.bispectrum(y)  # no bispectrum tables
     full.power(y)
+
+
+# --------------------------------------------- bispectrum linear term
+
+
+@pytest.mark.parametrize("n,box,nbins,nsim,prec", [(32, 600.0, 6, 3, "mixed"), (32, 600.0, 6, 5, "fp32"),
+                                                   (64, 1000.0, 10, 4, "mixed"), (96, 2000.0, 10, 2, "fp32")])
+def test_bispectrum_linear_matches_oracle(torch_cuda, n, box, nbins, nsim, prec):
+    """pb3_bispectrum_linear against the FP64 definition (three mixed-leg
+    sums per field).  Bound: the single-call bound on each of the 2 n_sim + 1
+    bispectra the GPU combines, |dB| <= 2 e(d) + (1/(2 n_sim)) sum_i [e(D_i + d)
+    + e(D_i - d)], e(f) = 1e-5 |B(f)| + 1e-6 A(f)."""
+    import paper_2404_07249_amd as pb3
+
+    torch = torch_cuda
+    edges = kf_edges(nbins)
+    _say(f"[case] linear term n={n} bins={nbins} sims={nsim} prec={prec}")
+    w = window_mask(n, 21000 + n, radius=0.35)
+    d = (quadratic_field(n, box, 1.0, 11000 + n) * w).astype(np.float32)
+    sims = [(gaussian_field(n, box, 31000 + 8 * n + i) * w).astype(np.float32) for i in range(nsim)]
+    plan = pb3.Plan(n, box, edges)
+    bk = plan.bispectrum_linear(_gpu(torch, d), [_gpu(torch, e) for e in sims], precision=prec).cpu().numpy()
+    d64 = d.astype(np.float64)
+    trips, bref, bplain, _ = masked.bispectrum_linear(d64, [e.astype(np.float64) for e in sims], box, edges)
+    assert np.array_equal(trips, plan.triplets)
+
+    def e(f):
+        r = oracle.bispectrum(f, box, edges)
+        return 1e-5 * np.abs(r.bk) + 1e-6 * r.absnorm
+
+    lim = 2 * e(d64)
+    for x in sims:
+        x = x.astype(np.float64)
+        lim += (e(x + d64) + e(x - d64)) / (2 * nsim)
+    assert np.all(np.abs(bk - bref) <= lim), (np.abs(bk - bref) / lim).max()
+    assert np.abs(bref - bplain).max() > 100 * lim.max()  # the term is resolved
+
+
+def test_bispectrum_linear_identity_and_errors(torch_cuda):
+    """With the data itself as the only field, S_lin = 3 S(d), so B = -2 B(d)
+    exactly (doubling a field is exact in every kernel); argument errors."""
+    import paper_2404_07249_amd as pb3
+
+    torch = torch_cuda
+    n, box, edges = 64, 1000.0, kf_edges(12)
+    _say("[case] linear term identity / errors")
+    d = _gpu(torch, quadratic_field(n, box, 1.0, 77))
+    plan = pb3.Plan(n, box, edges)
+    for prec in ("mixed", "fp32"):
+        b = plan.bispectrum(d, precision=prec)
+        bl = plan.bispectrum_linear(d, [d], precision=prec)
+        assert torch.equal(bl, -2.0 * b), prec
+    with pytest.raises(pb3.Pb3Error):
+        plan.bispectrum_linear(d, [], precision="mixed")
+    small = torch.empty(256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(pb3.Pb3Error):
+        plan.bispectrum_linear(d, [d], workspace=small)
+    wplan = pb3.Plan(n, box, edges)
+    wplan.set_weights(2, None, 0.0)
+    with pytest.raises(pb3.Pb3Error):
+        wplan.bispectrum_linear(d, [d])
+    ponly = pb3.Plan(n, box, edges, power_only=True)
+    with pytest.raises(pb3.Pb3Error):
+        ponly.bispectrum_linear(d, [d])
