@@ -14,6 +14,8 @@ bispectrum on their own grid and binning.  The server
 * runs every admitted batch on its own slot stream, so work of different
   requests overlaps on the device, and retires it when its completion
   event has fired, freeing the slot and the memory;
+* with simulations attached, gives B the linear term of the numerator
+  (Monte Carlo average, Sec. IV.C) before normalising;
 * normalises masked requests by the window moments (P / <w^2>,
   B / <w^3>: the conventional windowed estimators of Sec. III.D.2 and
   Sec. IV.D.2), and, when the request brings random fields, also returns
@@ -65,6 +67,7 @@ class Request:
     ready: object = None
     deadline: float | None = None
     grfs: list | None = None  # white unit-variance N^3 CUDA fields for the Monte Carlo Fisher matrix
+    sims: list | None = None  # N^3 CUDA fields with about the data's covariance: B gets the linear term
 
 
 @dataclass
@@ -179,7 +182,8 @@ class Server:
 
     def _req_bytes(self, plan: Plan, r: Request) -> int:
         full = self.full_plan_for(r.grid, r.box, r.edges) if r.grfs else None
-        return self.job_bytes(plan, r.window is not None, full)
+        lin = plan.linear_workspace_bytes(len(r.sims)) + 256 if r.sims else 0
+        return self.job_bytes(plan, r.window is not None, full) + lin
 
     # ----------------------------------------------------------- submit
     def submit(self, req: Request):
@@ -192,6 +196,9 @@ class Server:
             raise ValueError("window shape does not match the grid")
         if req.grfs and req.window is None:
             raise ValueError("random fields are for masked requests (a window is needed)")
+        for f in req.sims or []:
+            if tuple(f.shape) != (n, n, n):
+                raise ValueError("simulation shape does not match the grid")
         self.queue.append(req)
         self.stats.max_queue = max(self.stats.max_queue, len(self.queue))
 
@@ -293,6 +300,10 @@ class Server:
             scratch, unw = [], []
             for r, pk, bk in zip(group, pks, bks):
                 mc = None
+                if r.sims:
+                    # B again with the linear term (replaces the batch's B)
+                    lws = torch.empty(plan.linear_workspace_bytes(len(r.sims)), dtype=torch.uint8, device="cuda")
+                    plan.bispectrum_linear(r.data, r.sims, r.precision, out=bk, workspace=lws, stream=stream)
                 if r.grfs:
                     # before the window normalisation, which rescales pk in place
                     full = self.full_plan_for(r.grid, r.box, r.edges)

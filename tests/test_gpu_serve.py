@@ -17,7 +17,8 @@ import numpy as np
 import pytest
 
 import oracle
-from synthetic import kf_edges, quadratic_field, window_mask
+from oracle import masked
+from synthetic import gaussian_field, kf_edges, quadratic_field, window_mask
 
 pytestmark = pytest.mark.gpu
 
@@ -48,15 +49,19 @@ def _requests(torch, count=14, masked_every=2, seed0=300):
         d = quadratic_field(n, box, 1.0, seed0 + i).astype(np.float32)
         w = window_mask(n, seed0 + 1000 + i) if i % masked_every == 0 else None
         data = d * w if w is not None else d
-        grfs = None
+        grfs = sims = None
         if w is not None and i % 4 == 0:
             rng = np.random.default_rng(seed0 + 2000 + i)
             grfs = [torch.from_numpy(rng.standard_normal((n, n, n)).astype(np.float32)).cuda() for _ in range(2)]
+        hs = None
+        if w is not None and i % 4 == 2:  # simulations through the window: B with the linear term
+            hs = [(gaussian_field(n, box, seed0 + 3000 + 8 * i + j) * w).astype(np.float32) for j in range(2)]
+            sims = [torch.from_numpy(x).cuda() for x in hs]
         reqs.append(Request(rid=i, grid=n, box=box, edges=e,
                             data=torch.from_numpy(data).cuda(),
                             window=None if w is None else torch.from_numpy(w).cuda(),
-                            precision="mixed" if i % 3 else "fp32", grfs=grfs))
-        host.append((data, w))
+                            precision="mixed" if i % 3 else "fp32", grfs=grfs, sims=sims))
+        host.append((data, w, hs))
     return reqs, host
 
 
@@ -66,6 +71,8 @@ def _alone(server, torch, r):
 
     solo = pb3.Plan(r.grid, r.box, r.edges)  # own workspace, same geometry
     pk, bk = solo.polyspectra(r.data, r.precision)
+    if r.sims:
+        bk = solo.bispectrum_linear(r.data, r.sims, r.precision)
     if r.window is not None:
         solo.window_normalize(r.window, pk, bk)
     torch.cuda.synchronize()
@@ -98,16 +105,30 @@ def test_serve_mix_equals_alone_and_oracle(torch_cuda):
             assert np.array_equal(c.pk_unwindowed, pu.cpu().numpy()), r.rid
             assert np.array_equal(c.fisher, F.cpu().numpy()), r.rid
     assert sum(1 for r in reqs if r.grfs) >= 2
+    assert sum(1 for r in reqs if r.sims) >= 2
     # masked requests against the oracle's windowed estimators
-    for i in (0, 2):
+    for i in (0, 4):
         r = reqs[i]
-        data, w = host[i]
+        data, w, _ = host[i]
         pw, bw, (m2, m3), res = oracle.windowed_polyspectra(data.astype(np.float64), w, r.box, r.edges)
         c = srv.done[r.rid]
         assert np.allclose(c.moments, [m2, m3], rtol=1e-12, atol=0)
         assert np.all(np.abs(c.pk - pw) <= 1e-5 * np.abs(pw))
         lim = 1e-5 * np.abs(bw) + 1e-6 * res.absnorm / m3
         assert np.all(np.abs(c.bk - bw) <= lim), r.rid
+    # a masked request with simulations: the linear term, windowed
+    r = reqs[2]
+    data, w, hs = host[2]
+    d64 = data.astype(np.float64)
+    _, blin, _, _ = masked.bispectrum_linear(d64, [x.astype(np.float64) for x in hs], r.box, r.edges)
+    m3 = srv.done[r.rid].moments[1]
+
+    def e(f):
+        res = oracle.bispectrum(f, r.box, r.edges)
+        return 1e-5 * np.abs(res.bk) + 1e-6 * res.absnorm
+
+    lim = 2 * e(d64) + sum(e(x + d64) + e(x - d64) for x in [h.astype(np.float64) for h in hs]) / (2 * len(hs))
+    assert np.all(np.abs(srv.done[r.rid].bk - blin / m3) <= lim / m3)
 
 
 def test_serve_budget_cancel_expire(torch_cuda):
