@@ -305,6 +305,34 @@ def multipoles_bench(d32, box, edges, reps: int = 10) -> dict:
     return out
 
 
+def linear_term_bench(d32, box, edges, n_sim: int = 8, reps: int = 5) -> dict:
+    """Bispectrum with the linear term over n_sim simulations (Gaussian
+    fields through a survey-like window, data masked by the same window) at
+    the headline workload, mixed precision: milliseconds per call."""
+    import torch
+
+    import paper_2404_07249_amd as pb3
+    from synthetic import gaussian_field, window_mask
+
+    n = d32.shape[0]
+    w = window_mask(n, 20000)
+    x = torch.from_numpy(d32 * w).cuda()
+    sims = [torch.from_numpy((gaussian_field(n, box, 31000 + i) * w).astype(np.float32)).cuda()
+            for i in range(n_sim)]
+    plan = pb3.Plan(n, box, edges)
+    ws = torch.empty(plan.linear_workspace_bytes(n_sim), dtype=torch.uint8, device="cuda")
+    out = torch.empty(plan.n_triplets, dtype=torch.float64, device="cuda")
+    plan.bispectrum_linear(x, sims, "mixed", out=out, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.bispectrum_linear(x, sims, "mixed", out=out, workspace=ws)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / reps
+    return {"n_sim": n_sim, "ms_per_call": round(ms, 3), "bispectra_per_call": 2 * n_sim + 1,
+            "workspace_gb": round(ws.numel() / 1e9, 2)}
+
+
 def p_launches(plan) -> int:
     """Kernel launches of one single P+B call (a one-job batch)."""
     import paper_2404_07249_amd as pb3
@@ -375,6 +403,7 @@ def main(argv=None):
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-workload measurement")
     ap.add_argument("--no-autotune", action="store_true", help="default launch shapes instead of timed ones")
     ap.add_argument("--no-multipoles", action="store_true", help="skip the multipole measurement")
+    ap.add_argument("--no-linear", action="store_true", help="skip the linear-term measurement")
     ap.add_argument("--serve-mc", type=int, default=8, help="random fields per serving request (0: windowed only)")
     ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests in the serving measurement (0 skips it; 2000 for the full stream)")
@@ -501,6 +530,8 @@ def main(argv=None):
         line["batched"] = batched_bench(precision=main_p, autotune=not args.no_autotune)
     if not args.no_multipoles:
         line["multipoles"] = multipoles_bench(d32, box, edges)
+    if not args.no_linear:
+        line["linear_term"] = linear_term_bench(d32, box, edges)
     if args.serve_requests > 0:
         line["serving"] = serving_bench(args.serve_requests, precision=main_p, n_mc=args.serve_mc)
     if not args.no_cpu_baseline:
