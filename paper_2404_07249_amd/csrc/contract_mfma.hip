@@ -404,7 +404,7 @@ static hipError_t launch_nq(const float* g, long mvox, int n_wg, long vpw, float
 // Fused inverse z pass + contraction.
 //
 // Work-group w takes whole z-lines (x, y) of the contraction grid, lines
-// [w*lpw, (w+1)*lpw).  Besides the 8 contraction waves it has 4 producer
+// [w*lpw, (w+1)*lpw).  Besides its contraction waves it has 4 producer
 // waves: while the contraction waves work on line m from one LDS stage, the
 // producers build line m+1 in the other: for every bin pair (b, b+1) one
 // complex M-point inverse FFT of F_b + i F_{b+1} (each extended by
@@ -414,8 +414,15 @@ static hipError_t launch_nq(const float* g, long mvox, int n_wg, long vpw, float
 // filtered fields therefore never go to HBM.  Each FFT lives inside one
 // wavefront, so producers synchronise per wave and only the per-line
 // work-group barrier couples them to the contraction waves.
+// Contraction waves per group: in mixed precision one (4 waves beside the
+// 4 producers; 8 waves per work-group leave each wave the registers of two
+// waves per SIMD, so neither the FFT nor the tile accumulators spill, where
+// two per group spill and run about 6% slower); in FP32 two, whose second
+// wave hides the dependent chains of the 8x more numerous FP32 MFMAs.
 constexpr int kProducerThreads = 256;
-constexpr int kFusedThreads = kContractThreads + kProducerThreads;
+constexpr int fused_waves(bool mixed) { return mixed ? 1 : 2; }
+constexpr int fused_consumers(bool mixed) { return 64 * kGroups * fused_waves(mixed); }
+constexpr int fused_threads(bool mixed) { return fused_consumers(mixed) + kProducerThreads; }
 
 template <int NQ, int M> struct LineStage {
   static constexpr int PF = M + 4, PH = M + 8;
@@ -429,7 +436,7 @@ __device__ __forceinline__ void contract_line_group(const LineStage<NQ, M>& st, 
                                                     f32x4_t (&acc)[NTMAX], const SplitSel& sel) {
   using R = GroupRange<NQ, K0, K1, G>;
   constexpr int PF = LineStage<NQ, M>::PF, PH = LineStage<NQ, M>::PH;
-  for (int ks = wig; ks < M / 32; ks += kWavesPerGroup) {
+  for (int ks = wig; ks < M / 32; ks += fused_waves(MIXED)) {
     const int off = 32 * ks + 8 * grp;
     float gv[NQ][8];
     bf16x8_t bh[NQ], bl[NQ];
@@ -509,7 +516,7 @@ __device__ __forceinline__ void produce_line(LineStage<NQ, M>& st, const float2*
 }
 
 template <int NQ, bool MIXED, int M>
-__global__ void __launch_bounds__(kFusedThreads) k_zcontract(const float2* __restrict__ a2,
+__global__ void __launch_bounds__(fused_threads(MIXED)) k_zcontract(const float2* __restrict__ a2,
                                                              const BinGeom* __restrict__ geom, int nb,
                                                              const float2* __restrict__ tw, float scale, long lpw,
                                                              float* __restrict__ part, int part_len, unsigned sel_lo,
@@ -529,9 +536,10 @@ __global__ void __launch_bounds__(kFusedThreads) k_zcontract(const float2* __res
   LineStage<NQ, M>* stage = reinterpret_cast<LineStage<NQ, M>*>(smem);
   float* red = reinterpret_cast<float*>(smem);
   const int tid = threadIdx.x;
-  const bool producer = tid >= kContractThreads;
+  constexpr int FW = fused_waves(MIXED), NTHR = fused_threads(MIXED), NCON = fused_consumers(MIXED);
+  const bool producer = tid >= NCON;
   const int lane = tid & 63, wave = tid >> 6;
-  const int gi = wave / kWavesPerGroup, wig = wave % kWavesPerGroup;
+  const int gi = wave / FW, wig = wave % FW;
   const int i = lane & 15, grp = lane >> 4;
   SplitSel sel;
   __builtin_memcpy(&sel.lo, &sel_lo, 4);
@@ -540,20 +548,20 @@ __global__ void __launch_bounds__(kFusedThreads) k_zcontract(const float2* __res
 #pragma unroll
   for (int t = 0; t < NTMAX; ++t) acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
   // zero both stages (rows of padding bins stay zero), twiddles to LDS
-  for (int e = tid; e < 2 * STAGE_BYTES / 4; e += kFusedThreads) reinterpret_cast<float*>(smem)[e] = 0.f;
-  for (int e = tid; e < M; e += kFusedThreads) tws[e] = tw[e];
+  for (int e = tid; e < 2 * STAGE_BYTES / 4; e += NTHR) reinterpret_cast<float*>(smem)[e] = 0.f;
+  for (int e = tid; e < M; e += NTHR) tws[e] = tw[e];
   __syncthreads();
   const long nlines = (long)M * M;
   const long l0 = (long)blockIdx.x * lpw;
   long l1 = l0 + lpw;
   if (l1 > nlines) l1 = nlines;
   const int n = l1 > l0 ? (int)(l1 - l0) : 0;
-  if (producer && n > 0) produce_line<NQ, MIXED, M>(stage[0], a2, geom, nb, l0, tws, scr, tid - kContractThreads, scale, sel);
+  if (producer && n > 0) produce_line<NQ, MIXED, M>(stage[0], a2, geom, nb, l0, tws, scr, tid - NCON, scale, sel);
   __syncthreads();
   for (int m = 0; m < n; ++m) {
     if (producer) {
       if (m + 1 < n)
-        produce_line<NQ, MIXED, M>(stage[(m + 1) & 1], a2, geom, nb, l0 + m + 1, tws, scr, tid - kContractThreads,
+        produce_line<NQ, MIXED, M>(stage[(m + 1) & 1], a2, geom, nb, l0 + m + 1, tws, scr, tid - NCON,
                                    scale, sel);
     } else {
       const LineStage<NQ, M>& cur = stage[m & 1];
@@ -567,7 +575,7 @@ __global__ void __launch_bounds__(kFusedThreads) k_zcontract(const float2* __res
     __syncthreads();
   }
   // fixed-order sum of the waves of each group in LDS (reuses the stages)
-  for (int w = 0; w < kWavesPerGroup; ++w) {
+  for (int w = 0; w < FW; ++w) {
     if (!producer && wig == w) {
       switch (gi) {
         case 0: reduce_group<NQ, K0, K1, 0>(red, acc, w, i, grp); break;
@@ -579,7 +587,7 @@ __global__ void __launch_bounds__(kFusedThreads) k_zcontract(const float2* __res
     __syncthreads();
   }
   float* dst = part + (size_t)blockIdx.x * part_len;
-  for (int e = tid; e < NT * 256; e += kFusedThreads) dst[e] = red[e];
+  for (int e = tid; e < NT * 256; e += NTHR) dst[e] = red[e];
 }
 
 template <int NQ, bool MIXED, int M>
@@ -588,7 +596,7 @@ static hipError_t launch_fused_m(const pb3_plan& p, const Exec& x, hipStream_t s
   const long lpw = (nlines + p.contract_wgs - 1) / p.contract_wgs;
   const unsigned sel_lo = 0x0000BF80u, sel_hi = 0xBF800000u;
   const float scale = (float)(1.0 / ((double)M * M * M));
-  hipLaunchKernelGGL((k_zcontract<NQ, MIXED, M>), dim3(p.contract_wgs, 1, x.n_jobs), dim3(kFusedThreads), 0, s,
+  hipLaunchKernelGGL((k_zcontract<NQ, MIXED, M>), dim3(p.contract_wgs, 1, x.n_jobs), dim3(fused_threads(MIXED)), 0, s,
                      x.ws.a2, p.d.geom, p.nb, p.d.tw_m, scale, lpw, x.ws.part, p.part_len, sel_lo, sel_hi,
                      x.wstride);
   return hipGetLastError();
@@ -619,7 +627,7 @@ int fused_grid(int nq, int m, int n_cu) {
        : m == 96 ? (const void*)k_zcontract<2, true, 96> : m == 128 ? (const void*)k_zcontract<2, true, 128>
                  : (const void*)k_zcontract<2, true, 192>;
   }
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kFusedThreads, 0);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, fused_threads(true), 0);
   if (e != hipSuccess || per < 1) per = 1;
   if (per > 4) per = 4;
   return n_cu * per;

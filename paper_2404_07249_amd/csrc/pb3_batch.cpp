@@ -144,6 +144,11 @@ static pb3_status run_graph(pb3_batch* b, const float* const* deltas, double* co
       hipGraphExecUpdateResult res;
       updated = hipGraphExecUpdate(b->exec, graph, &err_node, &res) == hipSuccess && res == hipGraphExecUpdateSuccess;
       if (!updated) {
+        // a refused update (e.g. a kernel node whose block size changed with
+        // the precision) is not an error: instantiate anew.  The refusal
+        // leaves a sticky last error that the next launch check would
+        // report, so clear it here.
+        (void)hipGetLastError();
         hipGraphExecDestroy(b->exec);
         b->exec = nullptr;
       }
