@@ -39,6 +39,12 @@ Parity status of each function (what pins it is in ``tests/test_oracle.py``):
                            closed triangles; the oracle estimator's linear
                            response to the injection averages to it over
                            seeds.
+* ``noncubic`` (Nx x Ny x Nz grids, Lx x Ly x Lz boxes) pinned: a cubic
+                           geometry reproduces ``polyspec``; separable sums and
+                           counts equal explicit mode-triangle loops on small
+                           grids (cubic and anisotropic boxes); P of Gaussian
+                           fields and the tree-level B of quadratic fields on
+                           an anisotropic box average to their expectations.
 """
 
 from .polyspec import (  # noqa: F401
@@ -67,3 +73,4 @@ from . import masked  # noqa: F401,E402
 from . import multipoles  # noqa: F401,E402
 from . import weighted  # noqa: F401,E402
 from . import injection  # noqa: F401,E402
+from . import noncubic  # noqa: F401,E402

@@ -35,6 +35,8 @@ __all__ = [
     "serve_schedule",
     "injection_beta",
     "injected_field",
+    "gaussian_field3",
+    "quadratic_field3",
 ]
 
 
@@ -65,6 +67,32 @@ def gaussian_field(n: int, box: float, seed: int, pk=pk_model) -> np.ndarray:
     amp = np.sqrt(pk(_kmag(n, box)) * npix / vol)
     amp[0, 0, 0] = 0.0
     return np.fft.irfftn(wk * amp, s=(n, n, n), axes=(0, 1, 2))
+
+
+def gaussian_field3(shape, box, seed: int, pk=pk_model) -> np.ndarray:
+    """Gaussian random field on an Nx x Ny x Nz periodic grid of box sides
+    ``box`` (a number or three), float64: <|D(n)|^2> = (N_pix^2 / V) P(|k|)
+    with k_i = 2 pi n_i / L_i."""
+    shape = tuple(int(s) for s in shape)
+    L = np.broadcast_to(np.asarray(box, dtype=np.float64), (3,))
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal(shape)
+    wk = np.fft.rfftn(w)
+    fx = np.fft.fftfreq(shape[0], d=1.0 / shape[0])
+    fy = np.fft.fftfreq(shape[1], d=1.0 / shape[1])
+    fz = np.arange(shape[2] // 2 + 1, dtype=np.float64)
+    k = np.sqrt((2 * np.pi * fx[:, None, None] / L[0]) ** 2 + (2 * np.pi * fy[None, :, None] / L[1]) ** 2
+                + (2 * np.pi * fz[None, None, :] / L[2]) ** 2)
+    npix = float(np.prod(shape))
+    amp = np.sqrt(pk(k) * npix / float(np.prod(L)))
+    amp[0, 0, 0] = 0.0
+    return np.fft.irfftn(wk * amp, s=shape, axes=(0, 1, 2))
+
+
+def quadratic_field3(shape, box, fnl: float, seed: int, pk=pk_model) -> np.ndarray:
+    """d = g + f_NL (g^2 - mean(g^2)) with g from :func:`gaussian_field3`."""
+    g = gaussian_field3(shape, box, seed, pk)
+    return g + fnl * (g * g - np.mean(g * g))
 
 
 def injection_beta(k, kmin: float = 0.1, kmax: float = 0.4, pk=pk_model) -> np.ndarray:
