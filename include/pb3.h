@@ -16,9 +16,11 @@
  *   T_abc   = number of closed mode triangles in the three shells
  *             -- N_0 of eq. (N-ell-def) with P_fid = 1 (Sec. IV.C.1).
  *
- * D(n) is the unnormalised DFT of the real field on the N^3 grid, n the
- * integer wave-vector, |k| = k_f |n| with k_f = 2 pi / L.  Bins are half-open
- * shells [e_b, e_{b+1}) in units of k_f, decided on the integer |n|^2.
+ * D(n) is the unnormalised DFT of the real field on the Nx x Ny x Nz grid
+ * ("N^3" below: x slowest, z fastest; N_pix = Nx Ny Nz, V = Lx Ly Lz), n the
+ * integer wave-vector, k_i = k_f,i n_i with k_f,i = 2 pi / L_i.  Bins are
+ * half-open shells [e_b, e_{b+1}): for a box with equal sides in units of
+ * k_f, decided on the integer |n|^2; otherwise in h/Mpc on the FP64 |k|^2.
  * Triplets are (a <= b <= c) with e_c < e_{a+1} + e_{b+1}, ordered with c
  * fastest; triplets with T_abc = 0 are dropped from the plan.
  *
@@ -79,19 +81,29 @@ typedef enum {
                                         triplets, no triangle counts, no contraction buffers;
                                         pb3_bispectrum and batches refuse such a plan */
 
-/* Build a plan for a cubic grid.
- *   grid[3]   grid points per side; all three equal, even, with prime
- *             factors in {2, 3} (the FFT radices implemented);
- *   box[3]    box side in Mpc/h; all three equal;
- *   edges     n_edges >= 2 strictly increasing bin edges (k_f units, or
- *             h/Mpc with PB3_FLAG_EDGES_HMPC, then snapped to the nearest
- *             multiple of k_f/2 when within 1e-9 relative);
+/* Build a plan for an Nx x Ny x Nz grid on an Lx x Ly x Lz box (the
+ * estimators hold for any box; the paper's survey grids are non-cubic,
+ * Sec. VI.A).
+ *   grid[3]   grid points along x, y, z; each even with prime factors in
+ *             {2, 3} (the FFT radices implemented), 16..384;
+ *   box[3]    box sides in Mpc/h;
+ *   edges     n_edges >= 2 strictly increasing bin edges.  Box with equal
+ *             sides: k_f units, or h/Mpc with PB3_FLAG_EDGES_HMPC, then
+ *             snapped to the nearest multiple of k_f/2 when within 1e-9
+ *             relative; modes are binned on the integer |n|^2.  Box with
+ *             unequal sides: h/Mpc (PB3_FLAG_EDGES_HMPC required); modes
+ *             are binned on the FP64 value
+ *             k^2 = (kfx^2 nx^2 + kfy^2 ny^2) + kfz^2 nz^2, kf_i = 2 pi / L_i,
+ *             evaluated in that order;
  *   flags     PB3_FLAG_*.
  * On the device (unless PB3_FLAG_HOST_ONLY) it uploads the bin and triplet
  * tables and computes the triangle counts T_abc once in FP64 (N_0 is
  * data-independent, Sec. IV.D.1), on the default stream, synchronously.
+ * The contraction grid is chosen per axis (the smallest implemented length
+ * above 3 K_i, K_i the largest |n_i| of a binned mode, else N_i).
  * Errors: PB3_EINVAL (bad grid/box/edges, a bin with no modes, strict-mode
- * empty triplet), PB3_EUNSUPPORTED (grid length or > 48 bins), PB3_ENOMEM,
+ * empty triplet, unequal box sides without h/Mpc edges), PB3_EUNSUPPORTED
+ * (grid length, more than 2^31 - 1 cells or > 48 bins), PB3_ENOMEM,
  * PB3_EDEVICE.  *out is NULL on failure. */
 pb3_status pb3_plan_create(const int grid[3], const double box[3], const double* edges, int n_edges,
                            unsigned flags, pb3_plan** out);
@@ -106,15 +118,18 @@ pb3_status pb3_plan_bind_workspace(pb3_plan* plan, void* dev, size_t bytes);
 
 int pb3_n_bins(const pb3_plan* plan);
 int pb3_n_triplets(const pb3_plan* plan);  /* after dropping T = 0 (host-only plans: before) */
-int pb3_grid(const pb3_plan* plan);        /* N */
-int pb3_contract_grid(const pb3_plan* plan); /* M: N, or the smaller alias-free grid */
+int pb3_grid(const pb3_plan* plan);        /* Nx */
+int pb3_contract_grid(const pb3_plan* plan); /* Mx: Nx, or the smaller alias-free length */
+/* Grid (Nx, Ny, Nz) and contraction grid (Mx, My, Mz); either pointer may be NULL (not both). */
+pb3_status pb3_grid3(const pb3_plan* plan, int* grid_out, int* contract_out);
 /* Launch shape in use: fused (1) or separate (0) inverse z pass, contraction
  * work-groups, and how it was chosen (0 default, 1 autotune cache, 2 timed).
  * Any output pointer may be NULL. */
 pb3_status pb3_plan_launch_shape(const pb3_plan* plan, int* fused_out, int* contract_wgs_out, int* tuned_out);
 
-/* Bin edges (k_f units, n_bins+1), bin centres |k| in h/Mpc (mean |k| of
- * the modes in the bin) and mode counts N_b; any pointer may be NULL. */
+/* Bin edges (n_bins+1; k_f units for a box with equal sides, h/Mpc
+ * otherwise), bin centres |k| in h/Mpc (mean |k| of the modes in the bin)
+ * and mode counts N_b; any pointer may be NULL. */
 pb3_status pb3_get_bins(const pb3_plan* plan, double* edges_kf_out, double* kmean_out, int64_t* n_modes_out);
 /* Triplets (n_trip x 3 int32, a <= b <= c, c fastest). */
 pb3_status pb3_get_triplets(const pb3_plan* plan, int32_t* abc_out);
@@ -210,7 +225,7 @@ pb3_status pb3_bispectrum_linear(pb3_plan* plan, const float* data_dev, const fl
  *   N_0 = sum_closed 1 / (P1 P2 P3),
  *   B_shot = 1/nbar^2 + <P1 + P2 + P3>/nbar, averaged with the weights of N_0,
  *            with the power model P = P_fid - 1/nbar (P_fid includes shot noise).
- * window_order: pixel window deconvolved, m(n) = prod_i sinc(pi n_i / N)^order
+ * window_order: pixel window deconvolved, m(n) = prod_i sinc(pi n_i / N_i)^order
  * (0 none, 1 nearest grid point, 2 cloud in cell, 3 triangular shaped cloud);
  * pfid: P_fid in (Mpc/h)^3 at integer |n|^2 = 0 .. n_pfid-1 (n_pfid >=
  * pb3_weights_table_len, positive at every binned |n|^2), or NULL for P_fid = 1;
@@ -221,7 +236,9 @@ pb3_status pb3_bispectrum_linear(pb3_plan* plan, const float* data_dev, const fl
  * pb3_bispectrum, pb3_polyspectra, batches and pb3_multipoles (shot noise on
  * the monopole); pb3_masked_power refuses a weighted plan.
  * Errors: PB3_EINVAL (host-only plan, weights already set, bad order or
- * nbar, table too short or not positive), PB3_ENOMEM, PB3_EDEVICE. */
+ * nbar, table too short or not positive), PB3_EUNSUPPORTED (a box with
+ * unequal sides: P_fid is tabulated over integer |n|^2), PB3_ENOMEM,
+ * PB3_EDEVICE. */
 int pb3_weights_table_len(const pb3_plan* plan);
 pb3_status pb3_plan_set_weights(pb3_plan* plan, int window_order, const double* pfid, int n_pfid, double nbar);
 

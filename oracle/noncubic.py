@@ -149,3 +149,76 @@ def brute_sums(delta, box, edges, trips):
                     s[t] += D[tuple(i1)] * D[tuple(i2)] * D[i3]
                     cnt[t] += 1
     return s, cnt
+
+
+# ------------------------------------------------------------ multipoles
+# Line of sight along z; mu = k_z / |k| with the physical wave-vector.  The
+# estimators are those of ``oracle.multipoles`` (discrete Fisher matrix for
+# P, (2l+1)/T with the Legendre weight on k_3 for B).
+
+
+def mu2_grid(shape, box) -> np.ndarray:
+    """mu^2 = k_z^2 / k^2 on the full grid (0 at k = 0)."""
+    L = _box3(box)
+    fx, fy, fz = (_freqs(n).astype(np.float64) for n in shape)
+    # k^2 / k_f,z^2 with the axis scales k_f,i^2 / k_f,z^2
+    sx = (L[2] / L[0]) ** 2
+    sy = (L[2] / L[1]) ** 2
+    den = sx * fx[:, None, None] ** 2 + sy * fy[None, :, None] ** 2 + fz[None, None, :] ** 2
+    num = np.broadcast_to(fz[None, None, :] ** 2, den.shape)
+    out = np.zeros(den.shape)
+    nz = den > 0
+    out[nz] = num[nz] / den[nz]
+    return out
+
+
+def _legendre_m2(ell: int, m2: np.ndarray) -> np.ndarray:
+    if ell == 0:
+        return np.ones_like(m2)
+    if ell == 2:
+        return 1.5 * m2 - 0.5
+    if ell == 4:
+        return (35.0 * m2 * m2 - 30.0 * m2 + 3.0) / 8.0
+    raise ValueError("ell must be 0, 2 or 4")
+
+
+def power_multipoles(delta, box, edges, lmax: int = 4) -> np.ndarray:
+    d = np.asarray(delta, dtype=np.float64)
+    npix, vol = float(d.size), float(np.prod(_box3(box)))
+    D = dft(d)
+    p2 = D.real * D.real + D.imag * D.imag
+    idx = bin_of_modes(d.shape, box, edges)
+    m2 = mu2_grid(d.shape, box)
+    ells = list(range(0, lmax + 1, 2))
+    L = np.stack([_legendre_m2(l, m2) for l in ells])
+    out = np.zeros((len(ells), len(edges) - 1))
+    for b in range(len(edges) - 1):
+        m = idx == b
+        Lb = L[:, m]
+        out[:, b] = np.linalg.solve(Lb @ Lb.T, vol / npix**2 * (Lb * p2[m][None, :]).sum(axis=1))
+    return out
+
+
+def bispectrum_multipoles(delta, box, edges, lmax: int = 2):
+    """(triplets, B [lmax/2 + 1, n_trip], A [lmax/2 + 1, n_trip]) with A the
+    same normalisation of sum_x |G_a G_b g_{c,l}|."""
+    d = np.asarray(delta, dtype=np.float64)
+    npix, vol = float(d.size), float(np.prod(_box3(box)))
+    trips = triangle_triplets(edges)
+    T, _ = triangle_counts(d.shape, box, edges, trips)
+    keep = T > 0
+    trips, T = trips[keep], T[keep]
+    D = dft(d)
+    idx = bin_of_modes(d.shape, box, edges)
+    m2 = mu2_grid(d.shape, box)
+    nb = len(edges) - 1
+    G0 = np.stack([idft(np.where(idx == b, D, 0.0)).real for b in range(nb)])
+    out, absn = [], []
+    for ell in range(0, lmax + 1, 2):
+        Dl = _legendre_m2(ell, m2) * D
+        Gl = G0 if ell == 0 else np.stack([idft(np.where(idx == b, Dl, 0.0)).real for b in range(nb)])
+        s = np.array([np.sum(G0[a] * G0[b] * Gl[c]) for a, b, c in trips])
+        sa = np.array([np.sum(np.abs(G0[a] * G0[b] * Gl[c])) for a, b, c in trips])
+        out.append((2 * ell + 1) * vol * vol / npix * s / T)
+        absn.append((2 * ell + 1) * vol * vol / npix * sa / T)
+    return trips, np.array(out), np.array(absn)

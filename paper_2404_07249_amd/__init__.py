@@ -45,8 +45,8 @@ class Plan:
 
     def __init__(
         self,
-        grid: int,
-        box: float,
+        grid,
+        box,
         edges,
         *,
         edges_hmpc: bool = False,
@@ -64,8 +64,10 @@ class Plan:
         self._lib = lib
         self._h = None
         e = np.ascontiguousarray(np.asarray(edges, dtype=np.float64))
-        g = (C.c_int * 3)(grid, grid, grid)
-        b = (C.c_double * 3)(box, box, box)
+        g3 = tuple(int(v) for v in np.broadcast_to(np.asarray(grid), (3,)))
+        b3 = tuple(float(v) for v in np.broadcast_to(np.asarray(box, dtype=np.float64), (3,)))
+        g = (C.c_int * 3)(*g3)
+        b = (C.c_double * 3)(*b3)
         flags = 0
         flags |= _lib.FLAG_EDGES_HMPC if edges_hmpc else 0
         flags |= _lib.FLAG_HOST_ONLY if host_only else 0
@@ -84,8 +86,11 @@ class Plan:
             lib.pb3_plan_create(g, b, e.ctypes.data_as(C.POINTER(C.c_double)), int(e.size), flags, C.byref(h))
         )
         self._h = h
-        self.grid = int(grid)
-        self.box = float(box)
+        self.shape = g3  # (Nx, Ny, Nz)
+        self.boxes = b3  # (Lx, Ly, Lz)
+        # a cubic geometry keeps the scalar forms
+        self.grid = g3[0] if g3[0] == g3[1] == g3[2] else g3
+        self.box = b3[0] if b3[0] == b3[1] == b3[2] else b3
         self._workspace = None
 
     def __del__(self):
@@ -106,8 +111,12 @@ class Plan:
         return int(self._lib.pb3_n_triplets(self._h))
 
     @property
-    def contract_grid(self) -> int:
-        return int(self._lib.pb3_contract_grid(self._h))
+    def contract_grid(self):
+        """M (cubic contraction grid) or (Mx, My, Mz)."""
+        m = (C.c_int * 3)()
+        _lib.check(self._lib.pb3_grid3(self._h, None, m))
+        m3 = (int(m[0]), int(m[1]), int(m[2]))
+        return m3[0] if m3[0] == m3[1] == m3[2] else m3
 
     @property
     def workspace_bytes(self) -> int:
@@ -122,7 +131,8 @@ class Plan:
                 "tuned": {0: "default", 1: "cache", 2: "timed"}[t.value]}
 
     def bins(self):
-        """(edges in k_f units, mean |k| per bin in h/Mpc, mode counts N_b)."""
+        """(edges in k_f units (a box with equal sides) or h/Mpc, mean |k| per
+        bin in h/Mpc, mode counts N_b)."""
         nb = self.n_bins
         edges = np.zeros(nb + 1)
         kmean = np.zeros(nb)
@@ -154,11 +164,11 @@ class Plan:
     def _check_field(self, delta):
         import torch
 
-        n = self.grid
+        shape = self.shape
         if not isinstance(delta, torch.Tensor) or delta.device.type != "cuda":
             raise TypeError("delta must be a CUDA tensor")
-        if delta.dtype != torch.float32 or tuple(delta.shape) != (n, n, n) or not delta.is_contiguous():
-            raise ValueError(f"delta must be a contiguous float32 tensor of shape ({n}, {n}, {n})")
+        if delta.dtype != torch.float32 or tuple(delta.shape) != shape or not delta.is_contiguous():
+            raise ValueError(f"delta must be a contiguous float32 tensor of shape {shape}")
 
     def _out(self, out, count, like):
         import torch
@@ -276,7 +286,7 @@ class Plan:
         order (0 none, 1 NGP, 2 CIC, 3 TSC), P_fid weights (array over integer
         |n|^2, or a callable of k in h/Mpc), Poisson shot noise for nbar > 0."""
         tab = None
-        if pfid is not None:
+        if pfid is not None and not isinstance(self.box, tuple):  # unequal box sides: the library refuses
             n = self.weights_table_len
             if callable(pfid):
                 kf = 2 * np.pi / self.box

@@ -40,6 +40,7 @@ SIGNATURES = [
     ("pb3_n_triplets", C.c_int, [C.c_void_p]),
     ("pb3_grid", C.c_int, [C.c_void_p]),
     ("pb3_contract_grid", C.c_int, [C.c_void_p]),
+    ("pb3_grid3", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("pb3_plan_launch_shape", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("pb3_get_bins", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("pb3_get_triplets", C.c_int, [C.c_void_p, C.c_void_p]),

@@ -520,7 +520,7 @@ __global__ void __launch_bounds__(fused_threads(MIXED)) k_zcontract(const float2
                                                              const BinGeom* __restrict__ geom, int nb,
                                                              const float2* __restrict__ tw, float scale, long lpw,
                                                              float* __restrict__ part, int part_len, unsigned sel_lo,
-                                                             unsigned sel_hi, size_t wstride) {
+                                                             unsigned sel_hi, size_t wstride, long nlines) {
   a2 = job_ptr(a2, wstride);
   part = job_ptr(part, wstride);
   constexpr int K0 = 0, K1 = n_pair_blocks(NQ);
@@ -551,7 +551,6 @@ __global__ void __launch_bounds__(fused_threads(MIXED)) k_zcontract(const float2
   for (int e = tid; e < 2 * STAGE_BYTES / 4; e += NTHR) reinterpret_cast<float*>(smem)[e] = 0.f;
   for (int e = tid; e < M; e += NTHR) tws[e] = tw[e];
   __syncthreads();
-  const long nlines = (long)M * M;
   const long l0 = (long)blockIdx.x * lpw;
   long l1 = l0 + lpw;
   if (l1 > nlines) l1 = nlines;
@@ -592,19 +591,19 @@ __global__ void __launch_bounds__(fused_threads(MIXED)) k_zcontract(const float2
 
 template <int NQ, bool MIXED, int M>
 static hipError_t launch_fused_m(const pb3_plan& p, const Exec& x, hipStream_t s) {
-  const long nlines = (long)M * M;
+  const long nlines = (long)p.Mx * p.My;  // z lines of length M = Mz
   const long lpw = (nlines + p.contract_wgs - 1) / p.contract_wgs;
   const unsigned sel_lo = 0x0000BF80u, sel_hi = 0xBF800000u;
-  const float scale = (float)(1.0 / ((double)M * M * M));
+  const float scale = (float)(1.0 / ((double)p.Mx * p.My * p.Mz));
   hipLaunchKernelGGL((k_zcontract<NQ, MIXED, M>), dim3(p.contract_wgs, 1, x.n_jobs), dim3(fused_threads(MIXED)), 0, s,
-                     x.ws.a2, p.d.geom, p.nb, p.d.tw_m, scale, lpw, x.ws.part, p.part_len, sel_lo, sel_hi,
-                     x.wstride);
+                     x.ws.a2, p.d.geom, p.nb, p.d.tw_m[2], scale, lpw, x.ws.part, p.part_len, sel_lo, sel_hi,
+                     x.wstride, nlines);
   return hipGetLastError();
 }
 
 template <int NQ, bool MIXED>
 static hipError_t launch_fused_nq(const pb3_plan& p, const Exec& x, hipStream_t s) {
-  switch (p.M) {
+  switch (p.Mz) {
     case 32: return launch_fused_m<NQ, MIXED, 32>(p, x, s);
     case 64: return launch_fused_m<NQ, MIXED, 64>(p, x, s);
     case 96: return launch_fused_m<NQ, MIXED, 96>(p, x, s);
@@ -710,7 +709,7 @@ hipError_t launch_contract_mfma(const pb3_plan& p, const Exec& x, bool mixed, hi
 hipError_t launch_contract_cols(const pb3_plan& p, const Exec& x, const float* g, const float* gc, bool mixed,
                                 hipStream_t s) {
   if (gc && !mixed) return hipErrorInvalidValue;  // separate column fields: bf16 column operand only
-  const long mvox = (long)p.M * p.M * p.M;
+  const long mvox = (long)mpix(p);
   const int nq = p.nb_pad / 16;
   const int n_wg = p.contract_wgs;
   long vpw = (mvox + n_wg - 1) / n_wg;

@@ -1,12 +1,12 @@
 // FFT passes of the estimator (gfx950), built on the two-phase register FFT
 // fft2_line (fft_dev.h):
 //
-//   forward  z  r2c  delta[x][y][:]            -> f1[x][y][kz < Kz]
-//   forward  y  c2c  f1[x][:][kz]              -> f2[x][kyc][kz]   (centred-compact rows kept)
-//   forward  x  c2c  f2[:][kyc][kz]            -> dc[kxc][kyc][kz]
-//   inverse  x  c2c  Theta_b D, gathered per bin -> a1_b[x][jy][jz]
-//   inverse  y  c2c  a1_b[x][:][jz]            -> a2_b[x][y][jz]
-//   inverse  z  c2r  a2_b[x][y][:]             -> G_b[x][y][z]  (scaled by 1/M^3)
+//   forward  z  r2c  delta[x][y][:]            -> f1[x][y][kz < Kz]        (length Nz)
+//   forward  y  c2c  f1[x][:][kz]              -> f2[x][kyc][kz]   (Ny; centred-compact rows kept)
+//   forward  x  c2c  f2[:][kyc][kz]            -> dc[kxc][kyc][kz]         (Nx)
+//   inverse  x  c2c  Theta_b D, gathered per bin -> a1_b[x][jy][jz]        (Mx)
+//   inverse  y  c2c  a1_b[x][:][jz]            -> a2_b[x][y][jz]           (My)
+//   inverse  z  c2r  a2_b[x][y][:]             -> G_b[x][y][z]  (Mz; scaled by 1/(Mx My Mz))
 //
 // The z passes transform two real lines with one complex FFT: forward,
 // z = x_A + i x_B and X_A = (Z_k + conj Z_{N-k})/2, X_B = (Z_k - conj Z_{N-k})/(2i);
@@ -120,14 +120,19 @@ __global__ void __launch_bounds__(512) k_fwd_col2(const float2* __restrict__ in,
 // columns kz); the chunks of one row have consecutive tile indices, so they
 // run together and their partial cache lines combine.  The kx line of
 // Theta_b D (Theta_b alone when UNIT) enters at FFT positions kx mod M.
+// A mode belongs to the bin when the plan's per-mode table bin3 says so.
 // Output a1_b[x][jy][jz].  Tile col0 = row * 256 + first column.
+struct WinOff {
+  int x, y, z;  // offsets of k = 0 of each axis in the window table
+};
 template <int M, typename Rl, bool UNIT>
 __global__ void __launch_bounds__(512) k_inv_x2(const float2* __restrict__ dc, typename Cx<Rl>::type* __restrict__ a1,
                                                 const BinGeom* __restrict__ geom, const BinTile* __restrict__ tiles,
-                                                const int8_t* __restrict__ lut, int Kc, int Lc, int Kz,
+                                                const int8_t* __restrict__ bin3, int Kcx, int Kcy, int Lcy, int Kz,
                                                 const typename Cx<Rl>::type* __restrict__ tw, size_t wstride,
-                                                int ell, const float* __restrict__ winv, int half,
-                                                const float* __restrict__ pinv, const double* __restrict__ uw) {
+                                                int ell, const float* __restrict__ winv, WinOff wo, float sx,
+                                                float sy, const float* __restrict__ pinv,
+                                                const double* __restrict__ uw) {
   dc = job_ptr(dc, wstride);
   a1 = job_ptr(a1, wstride);
   using C = typename Cx<Rl>::type;
@@ -143,7 +148,7 @@ __global__ void __launch_bounds__(512) k_inv_x2(const float2* __restrict__ dc, t
   const int b = tile.bin;
   const BinGeom g = geom[b];
   const int jy = tile.col0 >> 8;
-  const int ky = jy - g.kneg;
+  const int ky = jy - g.knegy;
   const int ncol = g.ly * g.kzn;
   {
     const int kz = (tile.col0 & 255) + col;
@@ -153,20 +158,22 @@ __global__ void __launch_bounds__(512) k_inv_x2(const float2* __restrict__ dc, t
         scr + col * LS, tl, tws,
         [&](int n) {
           C v = cx<C>(Rl(0), Rl(0));
-          int kx = n <= g.kpos ? n : (n >= M - g.kneg ? n - M : 0x40000000);
-          if (live && kx != 0x40000000 && lut[kx * kx + ky * ky + kz * kz] == b) {
+          int kx = n <= g.kposx ? n : (n >= M - g.knegx ? n - M : 0x40000000);
+          const size_t ci = kx != 0x40000000 ? ((size_t)(kx + Kcx) * Lcy + (ky + Kcy)) * Kz + kz : 0;
+          if (live && kx != 0x40000000 && bin3[ci] == b) {
             if constexpr (UNIT) {
               v = cx<C>(Rl(uw ? uw[kx * kx + ky * ky + kz * kz] : 1.0), Rl(0));  // 1 / P_fid in the weighted count
             } else {
-              float2 d = dc[((size_t)(kx + Kc) * Lc + (ky + Kc)) * Kz + kz];
+              float2 d = dc[ci];
               if (winv || pinv) {  // weighted estimator: D / (m P_fid)
                 float u = pinv ? pinv[kx * kx + ky * ky + kz * kz] : 1.f;
-                if (winv) u *= winv[kx + half] * winv[ky + half] * winv[kz + half];
+                if (winv) u *= winv[wo.x + kx] * winv[wo.y + ky] * winv[wo.z + kz];
                 d.x *= u;
                 d.y *= u;
               }
-              if (ell) {  // Legendre weight L_ell(mu), mu = kz / |k| (line of sight along z)
-                const float k2 = (float)(kx * kx + ky * ky + kz * kz);
+              if (ell) {  // Legendre weight L_ell(mu), mu = k_z / |k| (line of sight along z)
+                // k^2 / k_f,z^2 with the axis scales (exact integers for a cubic box)
+                const float k2 = sx * (float)(kx * kx) + sy * (float)(ky * ky) + (float)(kz * kz);
                 const float m2 = k2 > 0.f ? (float)(kz * kz) / k2 : 0.f;
                 const float L = ell == 2 ? 1.5f * m2 - 0.5f : (35.f * m2 * m2 - 30.f * m2 + 3.f) * 0.125f;
                 d.x *= L;
@@ -209,12 +216,12 @@ __global__ void __launch_bounds__(512) k_inv_y2(const typename Cx<Rl>::type* __r
   {
     const int jz = (tile.col0 & 255) + col;
     const bool live = jz < g.kzn;
-    const C* src = a1 + g.a1_off + ((size_t)x * g.ly + g.kneg) * g.kzn + jz;  // ky = 0 row
+    const C* src = a1 + g.a1_off + ((size_t)x * g.ly + g.knegy) * g.kzn + jz;  // ky = 0 row
     C* dst = a2 + g.a2_off + (size_t)x * M * g.kzn + jz;
     fft2_line<M, 1>(
         scr + col * LS, tl, tws,
         [&](int n) {
-          int ky = n <= g.kpos ? n : (n >= M - g.kneg ? n - M : 0x40000000);
+          int ky = n <= g.kposy ? n : (n >= M - g.knegy ? n - M : 0x40000000);
           return (live && ky != 0x40000000) ? src[(long)ky * g.kzn] : cx<C>(Rl(0), Rl(0));
         },
         [&](int y, C v) {
@@ -232,7 +239,7 @@ template <int M, typename Rl>
 __global__ void __launch_bounds__(512) k_inv_z2(const typename Cx<Rl>::type* __restrict__ a2, Rl* __restrict__ gout,
                                                 const BinGeom* __restrict__ geom, const BinTile* __restrict__ tiles,
                                                 const typename Cx<Rl>::type* __restrict__ tw, Rl scale,
-                                                size_t wstride) {
+                                                int nlines, size_t wstride) {
   a2 = job_ptr(a2, wstride);
   gout = job_ptr(gout, wstride);
   using C = typename Cx<Rl>::type;
@@ -246,7 +253,6 @@ __global__ void __launch_bounds__(512) k_inv_z2(const typename Cx<Rl>::type* __r
   const BinTile tile = tiles[blockIdx.x];
   const BinGeom g = geom[tile.bin];
   const int kzn = g.kzn;
-  const int nlines = M * M;
   const int line0 = tile.col0;
   int nl = nlines - line0;
   if (nl > 2 * TP) nl = 2 * TP;
@@ -280,7 +286,7 @@ __global__ void __launch_bounds__(512) k_inv_z2(const typename Cx<Rl>::type* __r
         outr[(2 * pl + 1) * M + z] = v.y * scale;
       });
   __syncthreads();
-  Rl* dst = gout + (size_t)tile.bin * ((size_t)M * M * M) + (size_t)line0 * M;
+  Rl* dst = gout + (size_t)tile.bin * ((size_t)nlines * M) + (size_t)line0 * M;
   for (int e = tid; e < nl * M / 2; e += S::NT)
     reinterpret_cast<C*>(dst)[e] = reinterpret_cast<const C*>(outr)[e];
 }
@@ -312,68 +318,72 @@ int tile_width_z(int M, bool dbl) {
 }
 
 hipError_t launch_fwd_z(const pb3_plan& p, const Exec& x, hipStream_t s) {
-  const int n_pairs = p.N * p.N / 2;
-  PB3_FFT_LEN(p.N, {
+  const int n_pairs = p.Nx * p.Ny / 2;
+  PB3_FFT_LEN(p.Nz, {
     using S = PairShape<LL, 8>;
     hipLaunchKernelGGL(k_fwd_z2<LL>, dim3((n_pairs + S::TP - 1) / S::TP, 1, x.n_jobs), dim3(S::NT), 0, s, x.io,
-                       x.ws.f1, x.wstride, n_pairs, p.Kz, p.d.tw_n);
+                       x.ws.f1, x.wstride, n_pairs, p.Kz, p.d.tw_n[2]);
     return hipGetLastError();
   });
   return hipErrorInvalidValue;
 }
 
-static hipError_t fwd_col(const pb3_plan& p, const Exec& x, const float2* in, float2* out, int n_inner,
-                          long in_outer, long out_outer, int n_outer, hipStream_t s) {
-  PB3_FFT_LEN(p.N, {
+// transform of length len along one axis keeping the centred-compact rows [0, Lo)
+static hipError_t fwd_col(const Exec& x, int len, const float2* tw, int Lo, int Ko, const float2* in, float2* out,
+                          int n_inner, long in_outer, long out_outer, int n_outer, hipStream_t s) {
+  PB3_FFT_LEN(len, {
     using S = ColShape<LL, 8>;
     dim3 grid((n_inner + S::TB - 1) / S::TB, n_outer, x.n_jobs);
-    hipLaunchKernelGGL(k_fwd_col2<LL>, grid, dim3(S::NT), 0, s, in, out, n_inner, in_outer, out_outer, p.Lc, p.Kc,
-                       p.d.tw_n, x.wstride);
+    hipLaunchKernelGGL(k_fwd_col2<LL>, grid, dim3(S::NT), 0, s, in, out, n_inner, in_outer, out_outer, Lo, Ko, tw,
+                       x.wstride);
     return hipGetLastError();
   });
   return hipErrorInvalidValue;
 }
 hipError_t launch_fwd_y(const pb3_plan& p, const Exec& x, hipStream_t s) {
   // f1[x][y][kz] -> f2[x][kyc][kz]
-  return fwd_col(p, x, x.ws.f1, x.ws.f2, p.Kz, (long)p.N * p.Kz, (long)p.Lc * p.Kz, p.N, s);
+  return fwd_col(x, p.Ny, p.d.tw_n[1], p.Lcy, p.Kcy, x.ws.f1, x.ws.f2, p.Kz, (long)p.Ny * p.Kz, (long)p.Lcy * p.Kz,
+                 p.Nx, s);
 }
 hipError_t launch_fwd_x(const pb3_plan& p, const Exec& x, hipStream_t s) {
   // f2[x][kyc][kz] -> dc[kxc][kyc][kz]
-  return fwd_col(p, x, x.ws.f2, x.ws.dc, p.Lc * p.Kz, 0L, 0L, 1, s);
+  return fwd_col(x, p.Nx, p.d.tw_n[0], p.Lcx, p.Kcx, x.ws.f2, x.ws.dc, p.Lcy * p.Kz, 0L, 0L, 1, s);
 }
 
-hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, const float2* dc, void* a1, const void* tw,
-                     const TileSet& ts, int n_jobs, size_t wstride, hipStream_t s, int ell, const double* unit_w,
-                     bool weighted) {
+hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, const float2* dc, void* a1, const TileSet& ts,
+                     int n_jobs, size_t wstride, hipStream_t s, int ell, const double* unit_w, bool weighted) {
   const float* winv = weighted ? p.d.win_inv : nullptr;
   const float* pinv = weighted ? p.d.pfid_inv : nullptr;
-  const int half = p.N / 2;
+  const WinOff wo{p.Nx / 2, p.Nx + 1 + p.Ny / 2, p.Nx + p.Ny + 2 + p.Nz / 2};
+  const float sx = (float)p.msc[0], sy = (float)p.msc[1];
+  const void* tw = dbl ? (const void*)p.d.tw_m_d[0] : (const void*)p.d.tw_m[0];
   if (ts.n == 0) return hipSuccess;
-  PB3_FFT_LEN(p.M, {
+  PB3_FFT_LEN(p.Mx, {
     if (dbl) {
       using S = ColShape<LL, 16>;
       if (unit)
         hipLaunchKernelGGL((k_inv_x2<LL, double, true>), dim3(ts.n, 1, n_jobs), dim3(S::NT), 0, s, dc,
-                           (double2*)a1, p.d.geom, ts.d, p.d.lut, p.Kc, p.Lc, p.Kz, (const double2*)tw, wstride,
-                           0, (const float*)nullptr, 0, (const float*)nullptr, unit_w);
+                           (double2*)a1, p.d.geom, ts.d, p.d.bin3, p.Kcx, p.Kcy, p.Lcy, p.Kz, (const double2*)tw,
+                           wstride, 0, (const float*)nullptr, wo, sx, sy, (const float*)nullptr, unit_w);
       else
         return hipErrorInvalidValue;
     } else {
       using S = ColShape<LL, 8>;
       if (unit) return hipErrorInvalidValue;
       hipLaunchKernelGGL((k_inv_x2<LL, float, false>), dim3(ts.n, 1, n_jobs), dim3(S::NT), 0, s, dc, (float2*)a1,
-                         p.d.geom, ts.d, p.d.lut, p.Kc, p.Lc, p.Kz, (const float2*)tw, wstride, ell, winv, half,
-                         pinv, (const double*)nullptr);
+                         p.d.geom, ts.d, p.d.bin3, p.Kcx, p.Kcy, p.Lcy, p.Kz, (const float2*)tw, wstride, ell, winv,
+                         wo, sx, sy, pinv, (const double*)nullptr);
     }
     return hipGetLastError();
   });
   return hipErrorInvalidValue;
 }
 
-hipError_t run_inv_y(const pb3_plan& p, bool dbl, const void* a1, void* a2, const void* tw, const TileSet& ts,
-                     int n_jobs, size_t wstride, hipStream_t s) {
+hipError_t run_inv_y(const pb3_plan& p, bool dbl, const void* a1, void* a2, const TileSet& ts, int n_jobs,
+                     size_t wstride, hipStream_t s) {
+  const void* tw = dbl ? (const void*)p.d.tw_m_d[1] : (const void*)p.d.tw_m[1];
   if (ts.n == 0) return hipSuccess;
-  PB3_FFT_LEN(p.M, {
+  PB3_FFT_LEN(p.My, {
     if (dbl) {
       using S = ColShape<LL, 16>;
       hipLaunchKernelGGL((k_inv_y2<LL, double>), dim3(ts.n, 1, n_jobs), dim3(S::NT), 0, s, (const double2*)a1,
@@ -388,21 +398,23 @@ hipError_t run_inv_y(const pb3_plan& p, bool dbl, const void* a1, void* a2, cons
   return hipErrorInvalidValue;
 }
 
-hipError_t run_inv_z(const pb3_plan& p, bool dbl, const void* a2, void* gout, const void* tw, const TileSet& ts,
-                     int n_jobs, size_t wstride, hipStream_t s) {
+hipError_t run_inv_z(const pb3_plan& p, bool dbl, const void* a2, void* gout, const TileSet& ts, int n_jobs,
+                     size_t wstride, hipStream_t s) {
+  const void* tw = dbl ? (const void*)p.d.tw_m_d[2] : (const void*)p.d.tw_m[2];
+  const int nlines = p.Mx * p.My;
   if (ts.n == 0) return hipSuccess;
-  const double sc = 1.0 / ((double)p.M * p.M * p.M);
-  PB3_FFT_LEN(p.M, {
+  const double sc = 1.0 / ((double)p.Mx * p.My * p.Mz);
+  PB3_FFT_LEN(p.Mz, {
     if (dbl) {
       using S = PairShape<LL, 16>;
       if (ts.tb != 2 * S::TP) return hipErrorInvalidConfiguration;
       hipLaunchKernelGGL((k_inv_z2<LL, double>), dim3(ts.n, 1, n_jobs), dim3(S::NT), 0, s, (const double2*)a2,
-                         (double*)gout, p.d.geom, ts.d, (const double2*)tw, sc, wstride);
+                         (double*)gout, p.d.geom, ts.d, (const double2*)tw, sc, nlines, wstride);
     } else {
       using S = PairShape<LL, 8>;
       if (ts.tb != 2 * S::TP) return hipErrorInvalidConfiguration;
       hipLaunchKernelGGL((k_inv_z2<LL, float>), dim3(ts.n, 1, n_jobs), dim3(S::NT), 0, s, (const float2*)a2,
-                         (float*)gout, p.d.geom, ts.d, (const float2*)tw, (float)sc, wstride);
+                         (float*)gout, p.d.geom, ts.d, (const float2*)tw, (float)sc, nlines, wstride);
     }
     return hipGetLastError();
   });
@@ -410,13 +422,13 @@ hipError_t run_inv_z(const pb3_plan& p, bool dbl, const void* a2, void* gout, co
 }
 
 hipError_t launch_inv_x(const pb3_plan& p, const Exec& x, hipStream_t s) {
-  return run_inv_x(p, false, false, x.ws.dc, x.ws.a1, p.d.tw_m, p.tx, x.n_jobs, x.wstride, s, 0, nullptr, true);
+  return run_inv_x(p, false, false, x.ws.dc, x.ws.a1, p.tx, x.n_jobs, x.wstride, s, 0, nullptr, true);
 }
 hipError_t launch_inv_y(const pb3_plan& p, const Exec& x, hipStream_t s) {
-  return run_inv_y(p, false, x.ws.a1, x.ws.a2, p.d.tw_m, p.ty, x.n_jobs, x.wstride, s);
+  return run_inv_y(p, false, x.ws.a1, x.ws.a2, p.ty, x.n_jobs, x.wstride, s);
 }
 hipError_t launch_inv_z(const pb3_plan& p, const Exec& x, hipStream_t s) {
-  return run_inv_z(p, false, x.ws.a2, x.ws.g, p.d.tw_m, p.tz, x.n_jobs, x.wstride, s);
+  return run_inv_z(p, false, x.ws.a2, x.ws.g, p.tz, x.n_jobs, x.wstride, s);
 }
 
 }  // namespace pb3

@@ -53,7 +53,7 @@ struct pb3_batch {
 namespace pb3 {
 
 static double plan_cost(const pb3_plan& p) {
-  const double n3 = (double)p.N * p.N * p.N, m3 = (double)p.M * p.M * p.M;
+  const double n3 = (double)npix(p), m3 = (double)mpix(p);
   const double pairs = (double)p.nb_pad * (p.nb_pad + 1) / 2;
   // forward FFT bytes plus the contraction's pair x bin products
   return 40.0 * n3 + pairs * p.nb_pad * m3 / 64.0;

@@ -54,9 +54,9 @@ void build_tiles(const pb3_plan& p, int tbxy, int tbz, std::vector<BinTile>& vx,
     // x pass: (row jy, column chunk); y pass: (x-plane, column chunk)
     for (int jy = 0; jy < g.ly; ++jy)
       for (int c = 0; c < g.kzn; c += tbxy) vx.push_back(BinTile{b, jy * 256 + c});
-    for (int x = 0; x < p.M; ++x)
+    for (int x = 0; x < p.Mx; ++x)
       for (int c = 0; c < g.kzn; c += tbxy) vy.push_back(BinTile{b, x * 256 + c});
-    int nz = p.M * p.M;
+    int nz = p.Mx * p.My;
     for (int c = 0; c < nz; c += tbz) vz.push_back(BinTile{b, c});
   }
 }
@@ -114,10 +114,11 @@ static pb3_status upload_twiddles_d(double2** out, int n) {
 
 static void free_device(pb3_plan* p) {
   DeviceTables& d = p->d;
-  void* ptrs[] = {d.lut,      d.modes,      d.chunk,    d.chunk_first, d.geom,    d.tiles,    d.trip_all,
-                  d.out_map,  d.inv_counts, d.pk_scale, d.tw_n,        d.tw_m,    d.tw_m_d,   d.nmodes_d,
-                  d.pml_inv,  d.ml_trips,   d.ml_fac,   d.ml_map,      d.win_inv, d.pfid_inv, d.pfid_inv_d,
-                  d.mode_w,   d.bk_bias};
+  void* ptrs[] = {d.bin3,      d.modes,      d.chunk,     d.chunk_first, d.geom,      d.tiles,     d.trip_all,
+                  d.out_map,   d.inv_counts, d.pk_scale,  d.tw_n[0],     d.tw_n[1],   d.tw_n[2],   d.tw_m[0],
+                  d.tw_m[1],   d.tw_m[2],    d.tw_m_d[0], d.tw_m_d[1],   d.tw_m_d[2], d.nmodes_d,  d.pml_inv,
+                  d.ml_trips,  d.ml_fac,     d.ml_map,    d.win_inv,     d.pfid_inv,  d.pfid_inv_d, d.mode_w,
+                  d.bk_bias};
   for (void* q : ptrs)
     if (q) hipFree(q);
   d = DeviceTables{};
@@ -135,31 +136,47 @@ static pb3_status build_host(pb3_plan* p, const int grid[3], const double box[3]
     set_error("null argument");
     return PB3_EINVAL;
   }
-  if (grid[0] != grid[1] || grid[0] != grid[2] || grid[0] <= 0) {
-    set_error("only cubic grids are supported");
-    return PB3_EINVAL;
+  for (int a = 0; a < 3; ++a) {
+    if (grid[a] <= 0 || grid[a] % 2) {
+      set_error("grid lengths must be positive and even");
+      return PB3_EINVAL;
+    }
+    if (!len_supported(grid[a])) {
+      set_error("grid length " + std::to_string(grid[a]) +
+                " not implemented (supported: 16..384 of the form 2^a 3^b)");
+      return PB3_EUNSUPPORTED;
+    }
+    if (!(box[a] > 0) || !std::isfinite(box[a])) {
+      set_error("box sides must be positive");
+      return PB3_EINVAL;
+    }
   }
-  if (!(box[0] > 0) || box[0] != box[1] || box[0] != box[2]) {
-    set_error("box must be cubic and positive");
-    return PB3_EINVAL;
-  }
-  const int N = grid[0];
-  if (N % 2) {
-    set_error("grid side must be even");
-    return PB3_EINVAL;
-  }
-  if (!len_supported(N)) {
-    set_error("grid side " + std::to_string(N) + " not implemented (supported: 16..384 of the form 2^a 3^b)");
+  if ((long)grid[0] * grid[1] * grid[2] > (1L << 31) - 1) {
+    set_error("more than 2^31 - 1 grid cells not implemented");
     return PB3_EUNSUPPORTED;
   }
   if (n_edges < 2) {
     set_error("need at least two bin edges");
     return PB3_EINVAL;
   }
-  p->N = N;
-  p->L = box[0];
+  p->Nx = grid[0];
+  p->Ny = grid[1];
+  p->Nz = grid[2];
+  p->Lx = box[0];
+  p->Ly = box[1];
+  p->Lz = box[2];
+  p->aniso = !(box[0] == box[1] && box[0] == box[2]);
   p->flags = flags;
-  const double kf = 2.0 * M_PI / p->L;
+  if (p->aniso && !(flags & PB3_FLAG_EDGES_HMPC)) {
+    set_error("a box with unequal sides needs bin edges in h/Mpc (PB3_FLAG_EDGES_HMPC)");
+    return PB3_EINVAL;
+  }
+  for (int a = 0; a < 3; ++a) {
+    const double kf = 2.0 * M_PI / box[a];
+    p->kf2[a] = kf * kf;
+  }
+  for (int a = 0; a < 3; ++a) p->msc[a] = p->kf2[a] / p->kf2[2];
+  const double kf = 2.0 * M_PI / p->Lx;  // cubic box: the k_f of every axis
   p->edges.resize(n_edges);
   for (int i = 0; i < n_edges; ++i) {
     double e = edges[i];
@@ -167,7 +184,7 @@ static pb3_status build_host(pb3_plan* p, const int grid[3], const double box[3]
       set_error("bin edges must be finite and non-negative");
       return PB3_EINVAL;
     }
-    if (flags & PB3_FLAG_EDGES_HMPC) {
+    if ((flags & PB3_FLAG_EDGES_HMPC) && !p->aniso) {
       e /= kf;
       double h = std::round(2.0 * e) / 2.0;
       if (std::fabs(e - h) <= 1e-9 * std::max(1.0, std::fabs(e))) e = h;
@@ -185,75 +202,118 @@ static pb3_status build_host(pb3_plan* p, const int grid[3], const double box[3]
   }
   p->nb = nb;
   p->nb_pad = (nb + 15) / 16 * 16;
-  // integer thresholds: |n|^2 in bin b  <=>  thr[b] <= |n|^2 < thr[b+1]
-  p->thr.resize(nb + 1);
-  for (int i = 0; i <= nb; ++i) {
-    double e2 = p->edges[i] * p->edges[i];
-    int64_t t = (int64_t)std::ceil(e2);
-    // guard against e2 just above an integer through rounding of the square
-    while (t > 0 && (double)(t - 1) >= e2) --t;
-    while ((double)t < e2) ++t;
-    p->thr[i] = t;
+  const int Ng[3] = {p->Nx, p->Ny, p->Nz};
+  // Bin membership.  Cubic box: integer thresholds, |n|^2 in bin b <=>
+  // thr[b] <= |n|^2 < thr[b+1].  Anisotropic box: the FP64 value
+  // k^2 = (kf2x nx^2 + kf2y ny^2) + kf2z nz^2 against e_b^2 (h/Mpc), in that
+  // order of operations.
+  std::vector<double> e2(nb + 1);
+  for (int i = 0; i <= nb; ++i) e2[i] = p->edges[i] * p->edges[i];
+  if (!p->aniso) {
+    p->thr.resize(nb + 1);
+    for (int i = 0; i <= nb; ++i) {
+      int64_t t = (int64_t)std::ceil(e2[i]);
+      // guard against e2 just above an integer through rounding of the square
+      while (t > 0 && (double)(t - 1) >= e2[i]) --t;
+      while ((double)t < e2[i]) ++t;
+      p->thr[i] = t;
+    }
   }
-  const int64_t nmax2 = 3LL * (N / 2) * (N / 2);
-  // largest component any binned mode can have
-  int K = 0;
-  {
-    int64_t top = p->thr[nb] - 1;  // largest |n|^2 inside the top edge
-    if (top < 0) top = 0;
-    K = (int)std::floor(std::sqrt((double)top));
-    while ((int64_t)(K + 1) * (K + 1) <= top) ++K;
-    while ((int64_t)K * K > top) --K;
-    if (K > N / 2) K = N / 2;
+  // largest |n_i| with the single-axis mode n_i e_i below the top edge (kb
+  // below the edge of bin b's upper side), clamped to the Nyquist index
+  auto axis_max = [&](int a, int b_top) -> int {
+    int k = 0;
+    if (!p->aniso) {
+      const int64_t top = p->thr[b_top] - 1;  // largest |n|^2 inside
+      if (top < 0) return -1;
+      k = (int)std::floor(std::sqrt((double)top));
+      while ((int64_t)(k + 1) * (k + 1) <= top) ++k;
+      while ((int64_t)k * k > top) --k;
+    } else {
+      if (!(e2[b_top] > 0.0)) return -1;
+      k = 0;
+      while (k < Ng[a] / 2 && p->kf2[a] * ((double)(k + 1) * (double)(k + 1)) < e2[b_top]) ++k;
+    }
+    return std::min(k, Ng[a] / 2);
+  };
+  p->Kx = axis_max(0, nb);
+  p->Ky = axis_max(1, nb);
+  p->Kzt = axis_max(2, nb);
+  if (p->Kx < 0 || p->Ky < 0 || p->Kzt < 0) {
+    set_error("the top bin edge is zero");
+    return PB3_EINVAL;
   }
-  p->K = K;
-  p->full = (K >= N / 2);
-  if (p->full) {
-    p->Kc = N / 2;
-    p->Lc = N;
-    p->Kz = N / 2 + 1;
-  } else {
-    p->Kc = K;
-    p->Lc = 2 * K + 1;
-    p->Kz = K + 1;
+  p->fullx = p->Kx >= p->Nx / 2;
+  p->fully = p->Ky >= p->Ny / 2;
+  p->fullz = p->Kzt >= p->Nz / 2;
+  p->Kcx = p->fullx ? p->Nx / 2 : p->Kx;
+  p->Lcx = p->fullx ? p->Nx : 2 * p->Kx + 1;
+  p->Kcy = p->fully ? p->Ny / 2 : p->Ky;
+  p->Lcy = p->fully ? p->Ny : 2 * p->Ky + 1;
+  p->Kz = p->fullz ? p->Nz / 2 + 1 : p->Kzt + 1;
+  // contraction grid per axis: an alias-free smaller grid when 3 K_i < N_i
+  p->Mx = p->Nx;
+  p->My = p->Ny;
+  p->Mz = p->Nz;
+  if (!(flags & PB3_FLAG_FULL_GRID)) {
+    int m;
+    if (3 * p->Kx < p->Nx && (m = smallest_len_above(3 * p->Kx, p->Nx))) p->Mx = m;
+    if (3 * p->Ky < p->Ny && (m = smallest_len_above(3 * p->Ky, p->Ny))) p->My = m;
+    if (3 * p->Kzt < p->Nz && (m = smallest_len_above(3 * p->Kzt, p->Nz))) p->Mz = m;
   }
-  // contraction grid: alias-free smaller grid when 3K < N
-  p->M = N;
-  if (!(flags & PB3_FLAG_FULL_GRID) && 3 * K < N) {
-    int m = smallest_len_above(3 * K, N);
-    if (m) p->M = m;
+  // cubic box: bin lookup by |n|^2
+  if (!p->aniso) {
+    const int64_t kk = (int64_t)p->Kcx * p->Kcx + (int64_t)p->Kcy * p->Kcy + (int64_t)(p->Kz - 1) * (p->Kz - 1);
+    p->lut_len = (int)kk + 1;
+    p->lut.assign(p->lut_len, (int8_t)-1);
+    for (int64_t n2 = 0; n2 < p->lut_len; ++n2)
+      for (int b = 0; b < nb; ++b)
+        if (n2 >= p->thr[b] && n2 < p->thr[b + 1]) p->lut[n2] = (int8_t)b;
   }
-  // bin lookup by |n|^2
-  p->lut_len = (int)std::min<int64_t>(nmax2, 3LL * K * K) + 1;
-  p->lut.assign(p->lut_len, (int8_t)-1);
-  for (int64_t n2 = 0; n2 < p->lut_len; ++n2) {
-    for (int b = 0; b < nb; ++b)
-      if (n2 >= p->thr[b] && n2 < p->thr[b + 1]) p->lut[n2] = (int8_t)b;
-  }
+  auto bin_of = [&](int kx, int ky, int kz) -> int {
+    if (!p->aniso) {
+      const int64_t n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
+      return n2 < p->lut_len ? p->lut[n2] : -1;
+    }
+    double k2 = p->kf2[0] * (double)((int64_t)kx * kx) + p->kf2[1] * (double)((int64_t)ky * ky);
+    k2 = k2 + p->kf2[2] * (double)((int64_t)kz * kz);
+    if (k2 < e2[0] || !(k2 < e2[nb])) return -1;
+    int b = (int)(std::upper_bound(e2.begin(), e2.end(), k2) - e2.begin()) - 1;
+    return b;
+  };
   // modes of the compact half spectrum, per bin
   std::vector<std::vector<int32_t>> per(nb);
   p->nmodes.assign(nb, 0);
+  p->bin3.assign(ncompact(*p), (int8_t)-1);
   p->lmax = (flags & PB3_FLAG_LMAX4) ? 4 : (flags & PB3_FLAG_LMAX2) ? 2 : 0;
   const int ne = p->lmax / 2 + 1;
   std::vector<double> msum((size_t)nb * ne * ne, 0.0);  // per bin: sum over its modes of L_i L_j
   std::vector<double> ksum(nb, 0.0);
-  for (int cx = 0; cx < p->Lc; ++cx) {
-    int kx = cx - p->Kc;
-    for (int cy = 0; cy < p->Lc; ++cy) {
-      int ky = cy - p->Kc;
+  const double* ms = p->msc;
+  for (int cx = 0; cx < p->Lcx; ++cx) {
+    int kx = cx - p->Kcx;
+    for (int cy = 0; cy < p->Lcy; ++cy) {
+      int ky = cy - p->Kcy;
       for (int kz = 0; kz < p->Kz; ++kz) {
-        int64_t n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
-        if (n2 >= p->lut_len) continue;
-        int b = p->lut[n2];
+        const int b = bin_of(kx, ky, kz);
         if (b < 0) continue;
-        bool self = (kz == 0) || (p->full && kz == N / 2);
-        int32_t idx = (int32_t)(((int64_t)cx * p->Lc + cy) * p->Kz + kz);
+        const bool self = (kz == 0) || (p->fullz && kz == p->Nz / 2);
+        const int32_t idx = (int32_t)(((int64_t)cx * p->Lcy + cy) * p->Kz + kz);
+        p->bin3[idx] = (int8_t)b;
         per[b].push_back(self ? (int32_t)(idx | 0x80000000u) : idx);
-        int w = self ? 1 : 2;
+        const int w = self ? 1 : 2;
         p->nmodes[b] += w;
-        ksum[b] += w * std::sqrt((double)n2) * kf;
+        if (!p->aniso) {
+          ksum[b] += w * std::sqrt((double)((int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz)) * kf;
+        } else {
+          double k2 = p->kf2[0] * (double)((int64_t)kx * kx) + p->kf2[1] * (double)((int64_t)ky * ky);
+          k2 = k2 + p->kf2[2] * (double)((int64_t)kz * kz);
+          ksum[b] += w * std::sqrt(k2);
+        }
         if (ne > 1) {
-          const double m2 = n2 > 0 ? (double)kz * kz / (double)n2 : 0.0;
+          // mu^2 = k_z^2 / k^2 (integer arithmetic for a cubic box, whose scales are 1)
+          const double den = ms[0] * kx * kx + ms[1] * ky * ky + ms[2] * kz * kz;
+          const double m2 = den > 0 ? ms[2] * kz * kz / den : 0.0;
           const double L[3] = {1.0, 1.5 * m2 - 0.5, (35.0 * m2 * m2 - 30.0 * m2 + 3.0) / 8.0};
           for (int i = 0; i < ne; ++i)
             for (int j = 0; j < ne; ++j) msum[((size_t)b * ne + i) * ne + j] += w * L[i] * L[j];
@@ -272,8 +332,8 @@ static pb3_status build_host(pb3_plan* p, const int grid[3], const double box[3]
   // power multipoles: per bin, the inverse of the discrete Fisher matrix
   // (1/2) sum_n L_i L_j (its 1/2 cancels the numerator's), times V / N_pix^2
   if (ne > 1) {
-    const double npix = (double)N * N * N;
-    const double sc = box[0] * box[0] * box[0] / (npix * npix);
+    const double np = (double)p->Nx * p->Ny * p->Nz;
+    const double sc = p->Lx * p->Ly * p->Lz / (np * np);
     p->pml_inv.assign((size_t)nb * ne * ne, 0.0);
     for (int b = 0; b < nb; ++b) {
       double a[3][6] = {};
@@ -325,20 +385,18 @@ static pb3_status build_host(pb3_plan* p, const int grid[3], const double box[3]
   p->geom.resize(nb);
   int64_t o1 = 0, o2 = 0;
   for (int b = 0; b < nb; ++b) {
-    int64_t top = p->thr[b + 1] - 1;
-    int kb = (int)std::floor(std::sqrt((double)std::max<int64_t>(top, 0)));
-    while ((int64_t)(kb + 1) * (kb + 1) <= top) ++kb;
-    while ((int64_t)kb * kb > top) --kb;
-    if (kb > N / 2) kb = N / 2;
+    const int kbx = axis_max(0, b + 1), kby = axis_max(1, b + 1), kbz = axis_max(2, b + 1);
     BinGeom g{};
-    g.kneg = kb;
-    g.kpos = (p->full && kb == N / 2) ? N / 2 - 1 : kb;
-    g.ly = g.kneg + g.kpos + 1;
-    g.kzn = kb + 1;
+    g.knegx = std::max(kbx, 0);
+    g.kposx = (p->fullx && kbx == p->Nx / 2) ? p->Nx / 2 - 1 : std::max(kbx, 0);
+    g.knegy = std::max(kby, 0);
+    g.kposy = (p->fully && kby == p->Ny / 2) ? p->Ny / 2 - 1 : std::max(kby, 0);
+    g.ly = g.knegy + g.kposy + 1;
+    g.kzn = std::max(kbz, 0) + 1;
     g.a1_off = o1;
     g.a2_off = o2;
-    o1 += (int64_t)p->M * g.ly * g.kzn;
-    o2 += (int64_t)p->M * p->M * g.kzn;
+    o1 += (int64_t)p->Mx * g.ly * g.kzn;
+    o2 += (int64_t)p->Mx * p->My * g.kzn;
     p->geom[b] = g;
   }
   p->a1_len = o1;
@@ -359,7 +417,7 @@ static pb3_status build_host(pb3_plan* p, const int grid[3], const double box[3]
     return PB3_EUNSUPPORTED;
   }
   p->trip = p->trip_all;
-  p->fused_ok = !(flags & PB3_FLAG_POWER_ONLY) && fused_supported(p->nb_pad / 16, p->M);
+  p->fused_ok = !(flags & PB3_FLAG_POWER_ONLY) && fused_supported(p->nb_pad / 16, p->Mz);
   p->fused = !(flags & PB3_FLAG_NO_FUSION) && p->fused_ok;
   p->contract_wgs = 512;
   p->part_len = (flags & PB3_FLAG_POWER_ONLY) ? 0 : mfma_tiles(p->nb_pad / 16) * 256;
@@ -369,13 +427,13 @@ static pb3_status build_host(pb3_plan* p, const int grid[3], const double box[3]
 size_t workspace_bytes(const pb3_plan* p) {
   size_t b = 0;
   const size_t A = 256;
-  b += align_up(sizeof(float2) * (size_t)p->N * p->N * p->Kz, A);
-  b += align_up(sizeof(float2) * (size_t)p->N * p->Lc * p->Kz, A);
-  b += align_up(sizeof(float2) * (size_t)p->Lc * p->Lc * p->Kz, A);
+  b += align_up(sizeof(float2) * (size_t)p->Nx * p->Ny * p->Kz, A);
+  b += align_up(sizeof(float2) * (size_t)p->Nx * p->Lcy * p->Kz, A);
+  b += align_up(sizeof(float2) * ncompact(*p), A);
   b += align_up(sizeof(float2) * (size_t)p->a1_len, A);
   b += align_up(sizeof(float2) * (size_t)p->a2_len, A);
   const bool has_g = !p->fused && !(p->flags & PB3_FLAG_POWER_ONLY);
-  b += has_g ? align_up(sizeof(float) * (size_t)p->nb * p->M * p->M * p->M, A) : 0;
+  b += has_g ? align_up(sizeof(float) * (size_t)p->nb * mpix(*p), A) : 0;
   b += align_up(sizeof(float) * (size_t)p->contract_wgs * p->part_len, A);
   b += align_up(sizeof(double) * (size_t)std::max(p->n_chunks, 1), A);
   b += align_up(sizeof(double) * (size_t)kReduceSlices * p->part_len, A);
@@ -394,13 +452,13 @@ Workspace carve(const pb3_plan* p, void* base, size_t bytes) {
     c += align_up(n, A);
     return (void*)r;
   };
-  w.f1 = (float2*)take(sizeof(float2) * (size_t)p->N * p->N * p->Kz);
-  w.f2 = (float2*)take(sizeof(float2) * (size_t)p->N * p->Lc * p->Kz);
-  w.dc = (float2*)take(sizeof(float2) * (size_t)p->Lc * p->Lc * p->Kz);
+  w.f1 = (float2*)take(sizeof(float2) * (size_t)p->Nx * p->Ny * p->Kz);
+  w.f2 = (float2*)take(sizeof(float2) * (size_t)p->Nx * p->Lcy * p->Kz);
+  w.dc = (float2*)take(sizeof(float2) * ncompact(*p));
   w.a1 = (float2*)take(sizeof(float2) * (size_t)p->a1_len);
   w.a2 = (float2*)take(sizeof(float2) * (size_t)p->a2_len);
   const bool has_g = !p->fused && !(p->flags & PB3_FLAG_POWER_ONLY);
-  w.g = has_g ? (float*)take(sizeof(float) * (size_t)p->nb * p->M * p->M * p->M) : nullptr;
+  w.g = has_g ? (float*)take(sizeof(float) * (size_t)p->nb * mpix(*p)) : nullptr;
   w.part = (float*)take(sizeof(float) * (size_t)p->contract_wgs * p->part_len);
   w.ppart = (double*)take(sizeof(double) * (size_t)std::max(p->n_chunks, 1));
   w.rsl = (double*)take(sizeof(double) * (size_t)kReduceSlices * p->part_len);
@@ -443,8 +501,14 @@ static std::string tune_key(const pb3_plan* p) {
   std::string arch = "unknown";
   if (hipGetDeviceProperties(&prop, p->device_id) == hipSuccess) arch = prop.gcnArchName;
   std::ostringstream k;
-  k << arch << " N" << p->N << " M" << p->M << " thr";
-  for (int64_t t : p->thr) k << ":" << t;
+  k << arch << " N" << p->Nx << "x" << p->Ny << "x" << p->Nz << " M" << p->Mx << "x" << p->My << "x" << p->Mz;
+  if (p->aniso) {
+    k << " L" << p->Lx << "x" << p->Ly << "x" << p->Lz << " e";
+    for (double e : p->edges) k << ":" << e;
+  } else {
+    k << " thr";
+    for (int64_t t : p->thr) k << ":" << t;
+  }
   return k.str();
 }
 
@@ -483,7 +547,7 @@ static pb3_status autotune(pb3_plan* p, int n_cu) {
   std::vector<Cand> cands;
   const int nq = p->nb_pad / 16;
   if (p->fused_ok) {
-    const int base = fused_grid(nq, p->M, n_cu);
+    const int base = fused_grid(nq, p->Mz, n_cu);
     for (int mult : {1, 2}) cands.push_back({true, base * mult});
   }
   for (int mult : {1, 2, 3, 4}) cands.push_back({false, n_cu * mult});
@@ -498,7 +562,7 @@ static pb3_status autotune(pb3_plan* p, int n_cu) {
   }
   p->fused = keep_fused;
   p->contract_wgs = keep_wgs;
-  const size_t n3 = (size_t)p->N * p->N * p->N;
+  const size_t n3 = npix(*p);
   const int nt = (int)(p->trip.size() / 3);
   void *ws = nullptr, *fld = nullptr, *bk = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -568,19 +632,22 @@ static pb3_status build_device(pb3_plan* p) {
   int n_cu = 0;
   e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, p->device_id);
   if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
-  p->contract_wgs = p->fused ? fused_grid(p->nb_pad / 16, p->M, n_cu) : mfma_grid(p->nb_pad / 16, n_cu);
+  p->contract_wgs = p->fused ? fused_grid(p->nb_pad / 16, p->Mz, n_cu) : mfma_grid(p->nb_pad / 16, n_cu);
   DeviceTables& d = p->d;
-  if ((st = upload(&d.lut, p->lut.data(), p->lut.size())) != PB3_OK) return st;
+  if ((st = upload(&d.bin3, p->bin3.data(), p->bin3.size())) != PB3_OK) return st;
   if ((st = upload(&d.modes, p->modes.data(), p->modes.size())) != PB3_OK) return st;
   if ((st = upload(&d.chunk, p->chunks.data(), p->chunks.size())) != PB3_OK) return st;
   if ((st = upload(&d.chunk_first, p->chunk_first.data(), p->chunk_first.size())) != PB3_OK) return st;
   if ((st = upload(&d.geom, p->geom.data(), p->geom.size())) != PB3_OK) return st;
   if ((st = upload(&d.trip_all, p->trip_all.data(), p->trip_all.size())) != PB3_OK) return st;
-  if ((st = upload_twiddles_f(&d.tw_n, p->N)) != PB3_OK) return st;
-  if ((st = upload_twiddles_f(&d.tw_m, p->M)) != PB3_OK) return st;
-  if ((st = upload_twiddles_d(&d.tw_m_d, p->M)) != PB3_OK) return st;
+  const int Ng[3] = {p->Nx, p->Ny, p->Nz}, Mg[3] = {p->Mx, p->My, p->Mz};
+  for (int a = 0; a < 3; ++a) {
+    if ((st = upload_twiddles_f(&d.tw_n[a], Ng[a])) != PB3_OK) return st;
+    if ((st = upload_twiddles_f(&d.tw_m[a], Mg[a])) != PB3_OK) return st;
+    if ((st = upload_twiddles_d(&d.tw_m_d[a], Mg[a])) != PB3_OK) return st;
+  }
   // FP32 inverse-pass tiles
-  int tbx = tile_width_x(p->M, false), tbz = tile_width_z(p->M, false);
+  int tbx = tile_width_x(p->Mx, false), tbz = tile_width_z(p->Mz, false);
   if (tbx <= 0 || tbz <= 0) {
     set_error("contraction grid not implemented");
     return PB3_EUNSUPPORTED;
@@ -594,9 +661,9 @@ static pb3_status build_device(pb3_plan* p) {
   p->tx = TileSet{d.tiles, (int)vx.size(), tbx};
   p->ty = TileSet{d.tiles + vx.size(), (int)vy.size(), tbx};
   p->tz = TileSet{d.tiles + vx.size() + vy.size(), (int)vz.size(), tbz};
-  // power normalisation V / (N^6 N_b)
-  const double V = p->L * p->L * p->L;
-  const double n3 = (double)p->N * p->N * p->N;
+  // power normalisation V / (N_pix^2 N_b)
+  const double V = p->Lx * p->Ly * p->Lz;
+  const double n3 = (double)p->Nx * p->Ny * p->Nz;
   std::vector<double> pks(p->nb);
   for (int b = 0; b < p->nb; ++b) pks[b] = V / (n3 * n3 * (double)p->nmodes[b]);
   if ((st = upload(&d.pk_scale, pks.data(), pks.size())) != PB3_OK) return st;
@@ -608,7 +675,7 @@ static pb3_status build_device(pb3_plan* p) {
   p->counts.clear();
   std::vector<int32_t> map;
   std::vector<double> fac;
-  const double m3 = (double)p->M * p->M * p->M;
+  const double m3 = (double)p->Mx * p->My * p->Mz;
   const double scale = V * V * (m3 * m3) / (n3 * n3 * n3);
   for (int t = 0; t < n_cand; ++t) {
     double T = std::nearbyint(raw[t]);
@@ -845,8 +912,26 @@ pb3_status pb3_plan_bind_workspace(pb3_plan* plan, void* dev, size_t bytes) {
 
 int pb3_n_bins(const pb3_plan* plan) { return plan ? plan->nb : 0; }
 int pb3_n_triplets(const pb3_plan* plan) { return plan ? (int)(plan->trip.size() / 3) : 0; }
-int pb3_grid(const pb3_plan* plan) { return plan ? plan->N : 0; }
-int pb3_contract_grid(const pb3_plan* plan) { return plan ? plan->M : 0; }
+int pb3_grid(const pb3_plan* plan) { return plan ? plan->Nx : 0; }
+int pb3_contract_grid(const pb3_plan* plan) { return plan ? plan->Mx : 0; }
+
+pb3_status pb3_grid3(const pb3_plan* plan, int* grid_out, int* contract_out) {
+  if (!plan || (!grid_out && !contract_out)) {
+    set_error("null argument");
+    return PB3_EINVAL;
+  }
+  if (grid_out) {
+    grid_out[0] = plan->Nx;
+    grid_out[1] = plan->Ny;
+    grid_out[2] = plan->Nz;
+  }
+  if (contract_out) {
+    contract_out[0] = plan->Mx;
+    contract_out[1] = plan->My;
+    contract_out[2] = plan->Mz;
+  }
+  return PB3_OK;
+}
 
 pb3_status pb3_plan_launch_shape(const pb3_plan* plan, int* fused_out, int* contract_wgs_out, int* tuned_out) {
   if (!plan) {
@@ -924,7 +1009,7 @@ pb3_status pb3_window_normalize(const pb3_plan* plan, const float* w_dev, double
     set_error("plan has no device state (created with PB3_FLAG_HOST_ONLY)");
     return PB3_EINVAL;
   }
-  const long n = (long)plan->N * plan->N * plan->N;
+  const long n = (long)npix(*plan);
   hipError_t e = launch_window(n, w_dev, pk_dev, plan->nb, bk_dev, (int)(plan->trip.size() / 3), scratch_dev,
                                (hipStream_t)stream);
   return e == hipSuccess ? PB3_OK : hip_fail(e, "window normalisation");
@@ -991,7 +1076,7 @@ pb3_status pb3_masked_power(pb3_plan* plan, const float* data_dev, const float* 
     set_error("plan has no device state (created with PB3_FLAG_HOST_ONLY)");
     return PB3_EINVAL;
   }
-  if (plan->M != plan->N) {
+  if (plan->Mx != plan->Nx || plan->My != plan->Ny || plan->Mz != plan->Nz) {
     set_error("the masked power spectrum needs the full grid (create the plan with PB3_FLAG_FULL_GRID)");
     return PB3_EINVAL;
   }
@@ -1029,7 +1114,7 @@ pb3_status pb3_masked_power(pb3_plan* plan, const float* data_dev, const float* 
 
 int pb3_n_ell(const pb3_plan* plan) { return plan ? plan->lmax / 2 + 1 : 0; }
 
-int pb3_weights_table_len(const pb3_plan* plan) { return plan ? (int)plan->thr[plan->nb] : 0; }
+int pb3_weights_table_len(const pb3_plan* plan) { return (plan && !plan->aniso) ? (int)plan->thr[plan->nb] : 0; }
 
 pb3_status pb3_plan_set_weights(pb3_plan* plan, int window_order, const double* pfid, int n_pfid, double nbar) {
   if (!plan || !plan->device) {
@@ -1040,6 +1125,10 @@ pb3_status pb3_plan_set_weights(pb3_plan* plan, int window_order, const double* 
   if (p->weighted) {
     set_error("weights are already set on this plan");
     return PB3_EINVAL;
+  }
+  if (p->aniso) {
+    set_error("weights take P_fid over integer |n|^2: a box with equal sides is needed");
+    return PB3_EUNSUPPORTED;
   }
   if (window_order < 0 || window_order > 3 || !(nbar >= 0.0)) {
     set_error("window order must be 0..3 and nbar >= 0");
@@ -1062,15 +1151,18 @@ pb3_status pb3_plan_set_weights(pb3_plan* plan, int window_order, const double* 
     set_error("the bispectrum shot-noise term needs a P_fid table (it serves as the power model)");
     return PB3_EINVAL;
   }
-  const int N = p->N;
-  const double V = p->L * p->L * p->L, n3 = (double)N * N * N;
-  // 1D window inverse per component and 1 / P_fid per |n|^2
-  std::vector<double> winv(N + 1, 1.0);
-  for (int k = -N / 2; k <= N / 2; ++k) {
-    if (window_order == 0 || k == 0) continue;
-    const double x = M_PI * k / N;
-    winv[k + N / 2] = std::pow(x / std::sin(x), window_order);
-  }
+  const double V = p->Lx * p->Ly * p->Lz, n3 = (double)p->Nx * p->Ny * p->Nz;
+  // 1D window inverse per component (axes x, y, z back to back, k in
+  // [-N_i/2, N_i/2] at off[i] + k) and 1 / P_fid per |n|^2
+  const int Ng[3] = {p->Nx, p->Ny, p->Nz};
+  const int off[3] = {p->Nx / 2, p->Nx + 1 + p->Ny / 2, p->Nx + p->Ny + 2 + p->Nz / 2};
+  std::vector<double> winv((size_t)p->Nx + p->Ny + p->Nz + 3, 1.0);
+  for (int a = 0; a < 3; ++a)
+    for (int k = -Ng[a] / 2; k <= Ng[a] / 2; ++k) {
+      if (window_order == 0 || k == 0) continue;
+      const double x = M_PI * k / Ng[a];
+      winv[off[a] + k] = std::pow(x / std::sin(x), window_order);
+    }
   p->pfid.assign(p->lut_len, 1.0);
   if (pfid)
     for (int j = 0; j < p->lut_len && j < n_pfid; ++j) p->pfid[j] = pfid[j] > 0.0 ? pfid[j] : 1.0;
@@ -1089,9 +1181,9 @@ pb3_status pb3_plan_set_weights(pb3_plan* plan, int window_order, const double* 
       const int32_t m = p->modes[i];
       const int idx = m & 0x7fffffff, w = m < 0 ? 1 : 2;
       const int kz = idx % p->Kz, cxy = idx / p->Kz;
-      const int ky = cxy % p->Lc - p->Kc, kx = cxy / p->Lc - p->Kc;
+      const int ky = cxy % p->Lcy - p->Kcy, kx = cxy / p->Lcy - p->Kcx;
       const int64_t n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
-      const double wi = winv[kx + N / 2] * winv[ky + N / 2] * winv[kz + N / 2];
+      const double wi = winv[off[0] + kx] * winv[off[1] + ky] * winv[off[2] + kz];
       const double q = 1.0 / p->pfid[n2];
       mw[i] = wi * wi * q * q;
       fish[b] += w * q * q;
@@ -1158,7 +1250,7 @@ pb3_status pb3_plan_set_weights(pb3_plan* plan, int window_order, const double* 
   // bispectrum: weighted triangle sums N_0 = sum 1/(P1 P2 P3), the shot-noise sums
   std::vector<double> n0, q;
   if ((st = compute_counts_fp64(*p, n0, nbar > 0.0 ? &q : nullptr)) != PB3_OK) return st;
-  const double m3 = (double)p->M * p->M * p->M;
+  const double m3 = (double)p->Mx * p->My * p->Mz;
   const double scale = V * V * (m3 * m3) / (n3 * n3 * n3);
   std::vector<double> fac, bias, mf;
   const int nt = (int)(p->trip.size() / 3);

@@ -35,16 +35,16 @@ struct BinTile {
   int32_t col0;
 };
 
-// Geometry of bin b's pruned spectrum: |kx|,|ky| <= kneg, kz in [0, kz_n),
-// with the positive side possibly one shorter (Nyquist) -- ky in
-// [-kneg, kpos], kz in [0, kz_n).
+// Geometry of bin b's pruned spectrum: kx in [-knegx, kposx], ky in
+// [-knegy, kposy], kz in [0, kzn) (the positive side one shorter than the
+// negative where it reaches the Nyquist index).
 struct BinGeom {
-  int32_t kneg;     // most negative component magnitude
-  int32_t kpos;     // most positive component
-  int32_t ly;       // kneg + kpos + 1
-  int32_t kzn;      // number of kz planes (kpos_z + 1)
-  int64_t a1_off;   // float2 offset of this bin's x-pass output  [M][ly][kzn]
-  int64_t a2_off;   // float2 offset of this bin's y-pass output  [M][M][kzn]
+  int32_t knegx, kposx;  // x extent
+  int32_t knegy, kposy;  // y extent
+  int32_t ly;            // knegy + kposy + 1
+  int32_t kzn;           // number of kz planes
+  int64_t a1_off;        // float2 offset of this bin's x-pass output  [Mx][ly][kzn]
+  int64_t a2_off;        // float2 offset of this bin's y-pass output  [Mx][My][kzn]
 };
 
 // A device tile table for one inverse pass and the tile width it was built for.
@@ -66,7 +66,7 @@ struct JobIO {
 };
 
 struct DeviceTables {
-  int8_t* lut = nullptr;          // bin of |n|^2 (int8, -1 outside), size lut_len
+  int8_t* bin3 = nullptr;         // bin of every compact mode [Lcx][Lcy][Kz] (int8, -1 outside)
   int32_t* modes = nullptr;       // compact D index of every binned half-spectrum mode (bit 31: weight 1)
   int32_t* chunk = nullptr;       // power chunks: (bin, start, end) triples
   int32_t* chunk_first = nullptr; // per bin: index of its first chunk (n_bins + 1 entries)
@@ -75,17 +75,17 @@ struct DeviceTables {
   int32_t* trip_all = nullptr;    // candidate triplets (3 ints each), simple contraction
   int32_t* out_map = nullptr;     // per kept triplet: index into one work-group's MFMA partial vector
   double* inv_counts = nullptr;   // per kept triplet: scale / T
-  double* pk_scale = nullptr;     // per bin: V / (N^6 N_b)
-  float2* tw_n = nullptr;         // W_N^j, j < N
-  float2* tw_m = nullptr;         // W_M^j
-  double2* tw_m_d = nullptr;      // FP64 twiddles for the count pass
+  double* pk_scale = nullptr;     // per bin: V / (N_pix^2 N_b)
+  float2* tw_n[3] = {};           // W_{N_i}^j, j < N_i, per axis x, y, z
+  float2* tw_m[3] = {};           // W_{M_i}^j
+  double2* tw_m_d[3] = {};        // FP64 twiddles for the count pass
   double* nmodes_d = nullptr;      // masked power: N_b as double (made on first use)
   double* pml_inv = nullptr;       // multipoles: per bin, inverse discrete Fisher x V / N_pix^2 [nb][n_ell^2]
   int32_t* ml_trips = nullptr;     // multipoles: (a, b, l nb + c) per l and kept triplet
   double* ml_fac = nullptr;        // multipoles: (2l + 1) V^2 M^6 / (N^9 T) per l and kept triplet
   int32_t* ml_map = nullptr;       // multipoles: identity map over kept triplets
   // weighted estimator (pb3_plan_set_weights); all null when unweighted
-  float* win_inv = nullptr;        // 1 / sinc(pi k / N)^p for k in [-N/2, N/2] (index k + N/2)
+  float* win_inv = nullptr;        // 1 / sinc(pi k / N_i)^p, k in [-N_i/2, N_i/2], axes x, y, z back to back
   float* pfid_inv = nullptr;       // 1 / P_fid over integer |n|^2 (lut_len entries)
   double* pfid_inv_d = nullptr;    // same in FP64 (weighted triangle counts)
   double* mode_w = nullptr;        // per power mode: 1 / (m^2 P_fid^2)
@@ -96,12 +96,12 @@ struct Workspace {
   void* base = nullptr;
   size_t bytes = 0;
   bool owned = false;
-  float2* f1 = nullptr;     // [N][N][Kz]
-  float2* f2 = nullptr;     // [N][Lc][Kz]
-  float2* dc = nullptr;     // [Lc][Lc][Kz]
+  float2* f1 = nullptr;     // [Nx][Ny][Kz]
+  float2* f2 = nullptr;     // [Nx][Lcy][Kz]
+  float2* dc = nullptr;     // [Lcx][Lcy][Kz]
   float2* a1 = nullptr;     // per-bin x-pass outputs
   float2* a2 = nullptr;     // per-bin y-pass outputs
-  float* g = nullptr;       // [nb][M^3] (separate z pass only)
+  float* g = nullptr;       // [nb][Mx My Mz] (separate z pass only)
   float* part = nullptr;    // contraction partials [work-group][tile*256]
   double* rsl = nullptr;    // reduction slices [kReduceSlices][tile*256]
   double* ppart = nullptr;  // power partials
@@ -119,20 +119,24 @@ struct Exec {
 }  // namespace pb3
 
 struct pb3_plan {
-  // geometry
-  int N = 0;
-  double L = 0;
+  // geometry: Nx x Ny x Nz cells on an Lx x Ly x Lz box
+  int Nx = 0, Ny = 0, Nz = 0;
+  double Lx = 0, Ly = 0, Lz = 0;
+  bool aniso = false;          // box sides differ: bins on FP64 k^2 in h/Mpc (else integer |n|^2)
   unsigned flags = 0;
   int nb = 0;
   int nb_pad = 0;  // bins rounded up to the contraction's 16-bin groups
-  std::vector<double> edges;   // k_f units
-  std::vector<int64_t> thr;    // smallest |n|^2 in bin b (b <= nb: thr[nb] = first |n|^2 above the top)
-  int K = 0;                   // max |n_i| over binned modes
-  bool full = false;           // compact spectrum == full spectrum (K reaches N/2)
-  int Kc = 0;                  // centred offset of the compact x/y index
-  int Lc = 0;                  // compact x/y length
+  std::vector<double> edges;   // k_f units (cubic box) or h/Mpc (anisotropic box)
+  std::vector<int64_t> thr;    // cubic box: smallest |n|^2 in bin b (thr[nb]: first |n|^2 above the top)
+  int Kx = 0, Ky = 0, Kzt = 0; // max |n_i| over binned modes, per axis
+  bool fullx = false, fully = false, fullz = false;  // compact extent == whole axis
+  int Kcx = 0, Kcy = 0;        // centred offsets of the compact x / y index
+  int Lcx = 0, Lcy = 0;        // compact x / y lengths
   int Kz = 0;                  // compact z length
-  int M = 0;                   // contraction grid
+  int Mx = 0, My = 0, Mz = 0;  // contraction grid
+  double kf2[3] = {0, 0, 0};   // (2 pi / L_i)^2
+  double msc[3] = {1, 1, 1};   // multipole scales: k_f,i^2 / k_f,z^2 (all exactly 1 for a cubic box)
+  std::vector<int8_t> bin3;    // bin of every compact mode [Lcx][Lcy][Kz]
   bool fused = false;          // inverse z pass fused into the contraction (no G in HBM)
   bool fused_ok = false;       // the fused kernel supports this plan
   int lmax = 0;                // highest multipole (0, 2 or 4)
@@ -143,7 +147,7 @@ struct pb3_plan {
   std::vector<double> pfid;    // P_fid over integer |n|^2 (weighted plans)
   std::vector<double> pml_inv; // per bin inverse discrete Fisher of the power multipoles, x V / N_pix^2
   int tuned = 0;               // launch shape: 0 default, 1 from the autotune cache, 2 measured
-  int lut_len = 0;
+  int lut_len = 0;             // cubic box: bin of |n|^2 for |n|^2 < lut_len
   std::vector<int8_t> lut;
   std::vector<int64_t> nmodes;
   std::vector<double> kmean;
@@ -174,6 +178,12 @@ struct pb3_plan {
 };
 
 namespace pb3 {
+
+// cells of the data grid and of the contraction grid
+inline size_t npix(const pb3_plan& p) { return (size_t)p.Nx * p.Ny * p.Nz; }
+inline size_t mpix(const pb3_plan& p) { return (size_t)p.Mx * p.My * p.Mz; }
+// compact spectrum entries
+inline size_t ncompact(const pb3_plan& p) { return (size_t)p.Lcx * p.Lcy * p.Kz; }
 
 void set_error(const std::string& msg);
 pb3_status hip_fail(hipError_t e, const char* what);
@@ -237,13 +247,14 @@ hipError_t launch_zcontract(const pb3_plan& p, const Exec& x, bool mixed, hipStr
 // n_jobs jobs whose buffers are wstride bytes apart
 // weighted: apply the plan's window / P_fid weights (estimator fields);
 // unit_w: per-|n|^2 weight of the unit fields (count pass, may be null)
-hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, const float2* dc, void* a1, const void* tw,
-                     const TileSet& ts, int n_jobs, size_t wstride, hipStream_t s, int ell = 0,
-                     const double* unit_w = nullptr, bool weighted = false);
-hipError_t run_inv_y(const pb3_plan& p, bool dbl, const void* a1, void* a2, const void* tw, const TileSet& ts,
-                     int n_jobs, size_t wstride, hipStream_t s);
-hipError_t run_inv_z(const pb3_plan& p, bool dbl, const void* a2, void* gout, const void* tw, const TileSet& ts,
-                     int n_jobs, size_t wstride, hipStream_t s);
+// (the FP32 or FP64 twiddles of the axis are the plan's)
+hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, const float2* dc, void* a1, const TileSet& ts,
+                     int n_jobs, size_t wstride, hipStream_t s, int ell = 0, const double* unit_w = nullptr,
+                     bool weighted = false);
+hipError_t run_inv_y(const pb3_plan& p, bool dbl, const void* a1, void* a2, const TileSet& ts, int n_jobs,
+                     size_t wstride, hipStream_t s);
+hipError_t run_inv_z(const pb3_plan& p, bool dbl, const void* a2, void* gout, const TileSet& ts, int n_jobs,
+                     size_t wstride, hipStream_t s);
 // tile widths of the inverse passes for FP32 (dbl = false) or FP64 lines
 int tile_width_x(int M, bool dbl);
 int tile_width_z(int M, bool dbl);

@@ -321,9 +321,9 @@ __global__ void __launch_bounds__(64) k_masked_solve(const double* __restrict__ 
 // compact index; then per bin P_l = sum_l' Finv[l][l'] p_l'.
 __global__ void __launch_bounds__(256) k_power_ml_chunks(const float2* __restrict__ dc,
                                                          const int32_t* __restrict__ modes,
-                                                         const int32_t* __restrict__ chunks, int Lc, int Kz, int Kc,
-                                                         int ne, double* __restrict__ part,
-                                                         const double* __restrict__ mw) {
+                                                         const int32_t* __restrict__ chunks, int Lcy, int Kz,
+                                                         int Kcx, int Kcy, double sx, double sy, int ne,
+                                                         double* __restrict__ part, const double* __restrict__ mw) {
   __shared__ double red[3][256];
   const int c = blockIdx.x;
   const int start = chunks[3 * c + 1], end = chunks[3 * c + 2];
@@ -333,8 +333,9 @@ __global__ void __launch_bounds__(256) k_power_ml_chunks(const float2* __restric
     const double w = (m < 0) ? 1.0 : 2.0;
     const int idx = m & 0x7fffffff;
     const int kz = idx % Kz, cxy = idx / Kz;
-    const int ky = cxy % Lc - Kc, kx = cxy / Lc - Kc;
-    const double n2 = (double)kx * kx + (double)ky * ky + (double)kz * kz;
+    const int ky = cxy % Lcy - Kcy, kx = cxy / Lcy - Kcx;
+    // k^2 / k_f,z^2 with the axis scales (exact integers for a cubic box)
+    const double n2 = sx * kx * kx + sy * ky * ky + (double)kz * kz;
     const double m2 = n2 > 0 ? (double)kz * kz / n2 : 0.0;
     const float2 v = dc[idx];
     const double p2 = w * (mw ? mw[i] : 1.0) * ((double)v.x * v.x + (double)v.y * v.y);
@@ -449,9 +450,9 @@ hipError_t launch_reduce(const pb3_plan& p, const Exec& x, hipStream_t s) {
 // Workspace: the plan's workspace, fields [nb][N^3], the compact A,
 // chunk partials, the Fisher sums [nb^2] and the data's box P [nb].
 size_t masked_workspace_bytes(const pb3_plan& p) {
-  const size_t A = 256, n3 = (size_t)p.N * p.N * p.N, nb = (size_t)p.nb;
+  const size_t A = 256, n3 = npix(p), nb = (size_t)p.nb;
   auto up = [&](size_t b) { return (b + A - 1) / A * A; };
-  const size_t dc = (size_t)p.Lc * p.Lc * p.Kz;
+  const size_t dc = ncompact(p);
   return up(workspace_bytes(&p)) + up(sizeof(float) * nb * n3) + up(sizeof(float2) * dc) +
          up(sizeof(double) * std::max(p.n_chunks, 1)) + up(sizeof(double) * nb * nb) + up(sizeof(double) * nb);
 }
@@ -469,7 +470,7 @@ pb3_status run_masked_power(pb3_plan& p, const float* data, const float* window,
                             double* pk_out, double* f_out, void* workspace, hipStream_t s) {
   pb3_status st = masked_tables(p);
   if (st != PB3_OK) return st;
-  const size_t A = 256, n3 = (size_t)p.N * p.N * p.N, dcn = (size_t)p.Lc * p.Lc * p.Kz;
+  const size_t A = 256, n3 = npix(p), dcn = ncompact(p);
   const int nb = p.nb, nt = nb * nb;
   auto up = [&](size_t b) { return (b + A - 1) / A * A; };
   char* c = (char*)workspace;
@@ -505,7 +506,7 @@ pb3_status run_masked_power(pb3_plan& p, const float* data, const float* window,
     // g_b = IDFT[Theta_b DFT[w a]] on the full grid
     if (!forward(grfs[i], window) || !chk(launch_inv_x(p, x, s), "masked power: inv_x") ||
         !chk(launch_inv_y(p, x, s), "masked power: inv_y") ||
-        !chk(run_inv_z(p, false, x.ws.a2, fields, p.d.tw_m, p.tz, 1, 0, s), "masked power: inv_z"))
+        !chk(run_inv_z(p, false, x.ws.a2, fields, p.tz, 1, 0, s), "masked power: inv_z"))
       return st;
     // row a: cross spectrum of DFT[w g_a] with A per bin
     for (int a = 0; a < nb; ++a) {
@@ -539,7 +540,7 @@ pb3_status run_masked_power(pb3_plan& p, const float* data, const float* window,
 constexpr int kMlWgs = 512;
 
 size_t multipoles_workspace_bytes(const pb3_plan& p) {
-  const size_t A = 256, m3 = (size_t)p.M * p.M * p.M, ne = (size_t)(p.lmax / 2 + 1);
+  const size_t A = 256, m3 = mpix(p), ne = (size_t)(p.lmax / 2 + 1);
   const size_t nt = p.trip.size() / 3;
   auto up = [&](size_t b) { return (b + A - 1) / A * A; };
   return up(workspace_bytes(&p)) + up(sizeof(float) * ne * p.nb * m3) + up(sizeof(double) * kMlWgs * std::max<size_t>(nt, 1)) +
@@ -548,7 +549,7 @@ size_t multipoles_workspace_bytes(const pb3_plan& p) {
 
 pb3_status run_multipoles(pb3_plan& p, const float* delta, double* pk_out, double* bk_out, pb3_precision prec,
                           void* workspace, hipStream_t s) {
-  const size_t A = 256, m3 = (size_t)p.M * p.M * p.M;
+  const size_t A = 256, m3 = mpix(p);
   const int ne = p.lmax / 2 + 1, nt = (int)(p.trip.size() / 3);
   auto up = [&](size_t b) { return (b + A - 1) / A * A; };
   char* c = (char*)workspace;
@@ -570,8 +571,8 @@ pb3_status run_multipoles(pb3_plan& p, const float* delta, double* pk_out, doubl
       !chk(launch_fwd_x(p, x, s), "multipoles: fwd_x"))
     return st;
   if (pk_out) {
-    hipLaunchKernelGGL(k_power_ml_chunks, dim3(p.n_chunks), dim3(256), 0, s, x.ws.dc, p.d.modes, p.d.chunk, p.Lc,
-                       p.Kz, p.Kc, ne, mpart, (const double*)p.d.mode_w);
+    hipLaunchKernelGGL(k_power_ml_chunks, dim3(p.n_chunks), dim3(256), 0, s, x.ws.dc, p.d.modes, p.d.chunk, p.Lcy,
+                       p.Kz, p.Kcx, p.Kcy, p.msc[0], p.msc[1], ne, mpart, (const double*)p.d.mode_w);
     if (!chk(hipGetLastError(), "multipoles: power")) return st;
     hipLaunchKernelGGL(k_power_ml_final, dim3((p.nb + 63) / 64), dim3(64), 0, s, mpart, p.d.chunk_first, p.nb, ne,
                        p.d.pml_inv, pk_out, p.pk_shift);
@@ -580,10 +581,10 @@ pb3_status run_multipoles(pb3_plan& p, const float* delta, double* pk_out, doubl
   if (!bk_out || nt == 0) return PB3_OK;
   for (int l = 0; l < ne; ++l) {
     float* gl = fields + (size_t)l * p.nb * m3;
-    if (!chk(run_inv_x(p, false, false, x.ws.dc, x.ws.a1, p.d.tw_m, p.tx, 1, 0, s, 2 * l, nullptr, true),
+    if (!chk(run_inv_x(p, false, false, x.ws.dc, x.ws.a1, p.tx, 1, 0, s, 2 * l, nullptr, true),
              "multipoles: inv_x") ||
         !chk(launch_inv_y(p, x, s), "multipoles: inv_y") ||
-        !chk(run_inv_z(p, false, x.ws.a2, gl, p.d.tw_m, p.tz, 1, 0, s), "multipoles: inv_z"))
+        !chk(run_inv_z(p, false, x.ws.a2, gl, p.tz, 1, 0, s), "multipoles: inv_z"))
       return st;
   }
   if (prec == PB3_MIXED_BF16X3) {
@@ -661,7 +662,7 @@ __global__ void k_lin_final(double* __restrict__ bk, const double* __restrict__ 
 static int lin_jobs(int n_sim) { return std::min(kMaxJobs, 2 * std::max(n_sim, 1)); }
 
 size_t linear_workspace_bytes(const pb3_plan& p, int n_sim) {
-  const size_t A = 256, n3 = (size_t)p.N * p.N * p.N, nt = std::max<size_t>(p.trip.size() / 3, 1);
+  const size_t A = 256, n3 = npix(p), nt = std::max<size_t>(p.trip.size() / 3, 1);
   auto up = [&](size_t b) { return (b + A - 1) / A * A; };
   const size_t J = (size_t)lin_jobs(n_sim);
   return J * up(workspace_bytes(&p)) + up(sizeof(float) * J * n3) + up(sizeof(double) * J * nt) +
@@ -670,7 +671,7 @@ size_t linear_workspace_bytes(const pb3_plan& p, int n_sim) {
 
 pb3_status run_bispectrum_linear(pb3_plan& p, const float* data, const float* const* sims, int n_sim, double* bk_out,
                                  pb3_precision prec, void* workspace, hipStream_t s) {
-  const size_t A = 256, n3 = (size_t)p.N * p.N * p.N;
+  const size_t A = 256, n3 = npix(p);
   const int nt = (int)(p.trip.size() / 3);
   auto up = [&](size_t b) { return (b + A - 1) / A * A; };
   const int J = lin_jobs(n_sim);
@@ -733,7 +734,7 @@ pb3_status compute_counts_fp64(pb3_plan& p, std::vector<double>& counts_out, std
   // unweighted ones; the triplet table of each extra sum moves one leg
   const int nf = q_out ? 2 * p.nb : p.nb;
   int32_t* qtrips = nullptr;
-  const long mvox = (long)p.M * p.M * p.M;
+  const long mvox = (long)mpix(p);
   const int nwg = 512;
   double2 *a1 = nullptr, *a2 = nullptr;
   double *h = nullptr, *part = nullptr, *out = nullptr;
@@ -763,7 +764,7 @@ pb3_status compute_counts_fp64(pb3_plan& p, std::vector<double>& counts_out, std
   if (e != hipSuccess) { st = hip_fail(e, "hipMemcpy"); goto done; }
   {
     // FP64 lines take twice the LDS: the count pass has its own tile tables
-    int tbx = tile_width_x(p.M, true), tbz = tile_width_z(p.M, true);
+    int tbx = tile_width_x(p.Mx, true), tbz = tile_width_z(p.Mz, true);
     if (tbx <= 0 || tbz <= 0) {
       st = PB3_EUNSUPPORTED;
       set_error("contraction grid not implemented");
@@ -791,11 +792,11 @@ pb3_status compute_counts_fp64(pb3_plan& p, std::vector<double>& counts_out, std
     for (int set = 0; set < (q_out ? 2 : 1); ++set) {
       const double* uw = set == 0 ? p.d.pfid_inv_d : nullptr;  // set 0: 1 / P_fid (null: unit), set 1: unit
       double* hs = h + (size_t)set * p.nb * mvox;
-      r = run_inv_x(p, true, true, nullptr, a1, p.d.tw_m_d, tsx, 1, 0, nullptr, 0, uw);
+      r = run_inv_x(p, true, true, nullptr, a1, tsx, 1, 0, nullptr, 0, uw);
       if (r != hipSuccess) { st = hip_fail(r, "count inverse x pass"); goto done; }
-      r = run_inv_y(p, true, a1, a2, p.d.tw_m_d, tsy, 1, 0, nullptr);
+      r = run_inv_y(p, true, a1, a2, tsy, 1, 0, nullptr);
       if (r != hipSuccess) { st = hip_fail(r, "count inverse y pass"); goto done; }
-      r = run_inv_z(p, true, a2, hs, p.d.tw_m_d, tsz, 1, 0, nullptr);
+      r = run_inv_z(p, true, a2, hs, tsz, 1, 0, nullptr);
       if (r != hipSuccess) { st = hip_fail(r, "count inverse z pass"); goto done; }
     }
     if (q_out) {
@@ -826,7 +827,7 @@ pb3_status compute_counts_fp64(pb3_plan& p, std::vector<double>& counts_out, std
     if (r != hipSuccess) { st = hip_fail(r, "count reduce"); goto done; }
     r = hipMemcpy(counts_out.data(), out, sizeof(double) * n_cand, hipMemcpyDeviceToHost);
     if (r != hipSuccess) { st = hip_fail(r, "count copy"); goto done; }
-    double m6 = (double)p.M * p.M * p.M;
+    double m6 = (double)p.Mx * p.My * p.Mz;
     m6 *= m6;
     for (auto& v : counts_out) v *= m6;
     if (q_out)

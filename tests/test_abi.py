@@ -22,7 +22,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libpb3.so not b
 def _header_symbols():
     txt = open(os.path.join(ROOT, "include", "pb3.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(pb3_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(pb3_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_exports_every_declared_symbol():
@@ -97,17 +97,45 @@ def test_plan_errors(n, edges, status):
     assert status in str(ei.value)
 
 
-def test_non_cubic_rejected():
+@pytest.mark.parametrize("shape,box,edges,hmpc", [
+    ((32, 48, 64), 1000.0, [1.0, 3.0, 5.0, 7.0, 9.0], False),
+    ((64, 48, 32), (1000.0, 800.0, 500.0), [0.01, 0.03, 0.05, 0.07, 0.09, 0.11], True),
+    ((192, 384, 192), (1015.8, 1911.0, 1057.7), list(0.005 + 0.01 * np.arange(13)), True)])
+def test_noncubic_host_plan_matches_oracle(shape, box, edges, hmpc):
+    """Host tables of a non-cubic plan: mode counts per bin and the triplet
+    list equal the non-cubic oracle's; the contraction grid is chosen per axis."""
+    from oracle import noncubic as nc
+
+    p = _plan(shape, box, edges, edges_hmpc=hmpc)
+    assert p.shape == tuple(shape)
+    e, kmean, nm = p.bins()
+    assert np.allclose(e, edges, rtol=0, atol=0)
+    assert np.array_equal(nm, nc.mode_counts(shape, box, edges))
+    assert np.array_equal(p.triplets, oracle.triangle_triplets(edges))
+    m = p.contract_grid
+    m3 = m if isinstance(m, tuple) else (m, m, m)
+    assert all(mi <= ni for mi, ni in zip(m3, shape))
+
+
+def test_noncubic_plan_errors():
     from paper_2404_07249_amd import _lib
 
     lib = _lib.load()
-    g = (C.c_int * 3)(32, 32, 64)
-    b = (C.c_double * 3)(1.0, 1.0, 1.0)
     e = (C.c_double * 2)(1.0, 3.0)
-    h = C.c_void_p()
-    st = lib.pb3_plan_create(g, b, e, 2, _lib.FLAG_HOST_ONLY, C.byref(h))
-    assert st == 1 and not h.value
-    assert b"cubic" in lib.pb3_last_error()
+
+    def create(grid, box, flags=0):
+        h = C.c_void_p()
+        st = lib.pb3_plan_create((C.c_int * 3)(*grid), (C.c_double * 3)(*box), e, 2, _lib.FLAG_HOST_ONLY | flags,
+                                 C.byref(h))
+        if h.value:
+            lib.pb3_plan_destroy(h)
+        return st, lib.pb3_last_error()
+
+    st, msg = create((32, 32, 64), (100.0, 100.0, 200.0))  # unequal sides need h/Mpc edges
+    assert st == 1 and b"h/Mpc" in msg
+    assert create((32, 30, 64), (100.0, 100.0, 100.0))[0] == 4  # 30 is not an implemented length
+    assert create((32, 33, 64), (100.0, 100.0, 100.0))[0] == 1  # odd
+    assert create((32, 48, 64), (100.0, 100.0, 100.0))[0] == 0
 
 
 def test_host_only_plan_refuses_compute():
