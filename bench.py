@@ -333,6 +333,47 @@ def linear_term_bench(d32, box, edges, n_sim: int = 8, reps: int = 5) -> dict:
             "workspace_gb": round(ws.numel() / 1e9, 2)}
 
 
+def noncubic_bench(reps: int = 10) -> dict:
+    """Non-cubic geometry: power multipoles l = 0, 2, 4 in 44 bins (132
+    bandpowers) on a survey-like 192 x 384 x 192 grid whose cells give
+    k_Ny ~ 0.6 h/Mpc on every axis, and P + B (mixed precision) on a
+    128 x 192 x 96 grid of a 1000 x 1500 x 750 Mpc/h box with 20 bins."""
+    import torch
+
+    import paper_2404_07249_amd as pb3
+    from synthetic import quadratic_field3
+
+    out = {}
+    shape, box = (192, 384, 192), (1005.3, 2010.6, 1005.3)
+    edges = 0.01 + 0.0125 * np.arange(45)
+    x = torch.from_numpy(quadratic_field3(shape, box, 1.0, 3).astype(np.float32)).cuda()
+    plan = pb3.Plan(shape, box, edges, edges_hmpc=True, power_only=True, lmax=4)
+    ws = torch.empty(int(plan._lib.pb3_multipoles_workspace_bytes(plan._h)), dtype=torch.uint8, device="cuda")
+    plan.multipoles(x, bispectrum=False, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.multipoles(x, bispectrum=False, workspace=ws)
+    torch.cuda.synchronize()
+    out["power_multipoles"] = {"grid": list(shape), "box": list(box), "bins": plan.n_bins, "n_ell": 3,
+                               "ms_per_call": round(1e3 * (time.perf_counter() - t0) / reps, 3)}
+    shape, box = (128, 192, 96), (1000.0, 1500.0, 750.0)
+    edges = 0.01 + 0.01 * np.arange(21)
+    x = torch.from_numpy(quadratic_field3(shape, box, 1.0, 4).astype(np.float32)).cuda()
+    plan = pb3.Plan(shape, box, edges, edges_hmpc=True)
+    plan.polyspectra(x, "mixed")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.polyspectra(x, "mixed")
+    torch.cuda.synchronize()
+    m = plan.contract_grid
+    out["polyspectra"] = {"grid": list(shape), "box": list(box), "bins": plan.n_bins, "triplets": plan.n_triplets,
+                          "contract_grid": list(m) if isinstance(m, tuple) else [m] * 3,
+                          "ms_per_call": round(1e3 * (time.perf_counter() - t0) / reps, 3)}
+    return out
+
+
 def p_launches(plan) -> int:
     """Kernel launches of one single P+B call (a one-job batch)."""
     import paper_2404_07249_amd as pb3
@@ -404,6 +445,7 @@ def main(argv=None):
     ap.add_argument("--no-autotune", action="store_true", help="default launch shapes instead of timed ones")
     ap.add_argument("--no-multipoles", action="store_true", help="skip the multipole measurement")
     ap.add_argument("--no-linear", action="store_true", help="skip the linear-term measurement")
+    ap.add_argument("--no-noncubic", action="store_true", help="skip the non-cubic geometry measurement")
     ap.add_argument("--serve-mc", type=int, default=8, help="random fields per serving request (0: windowed only)")
     ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests in the serving measurement (0 skips it; 2000 for the full stream)")
@@ -532,6 +574,8 @@ def main(argv=None):
         line["multipoles"] = multipoles_bench(d32, box, edges)
     if not args.no_linear:
         line["linear_term"] = linear_term_bench(d32, box, edges)
+    if not args.no_noncubic:
+        line["noncubic"] = noncubic_bench()
     if args.serve_requests > 0:
         line["serving"] = serving_bench(args.serve_requests, precision=main_p, n_mc=args.serve_mc)
     if not args.no_cpu_baseline:
