@@ -33,20 +33,29 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import noncubic as _nc
 from .multipoles import legendre, mu_grid
-from .polyspec import bin_of_modes, dft, freqs, idft, kmag2, triangle_counts, triangle_triplets
+from .polyspec import bin_of_modes, dft, freqs, idft, triangle_counts, triangle_triplets
 
 
-def window(n: int, order: int) -> np.ndarray:
-    """m(n) on the full DFT grid."""
-    f = freqs(n).astype(np.float64)
-    s = np.sinc(f / n)  # numpy sinc(x) = sin(pi x) / (pi x)
-    w1 = s**order
-    return w1[:, None, None] * w1[None, :, None] * w1[None, None, :]
+def _shape(n) -> tuple:
+    return tuple(int(v) for v in np.broadcast_to(np.asarray(n), (3,)))
 
 
-def _pfid_grid(n: int, pfid) -> np.ndarray:
-    k2 = kmag2(n)
+def window(n, order: int) -> np.ndarray:
+    """m(n) = prod_i sinc(pi n_i / N_i)^order on the full DFT grid of side n
+    (or shape (Nx, Ny, Nz))."""
+    w = [np.sinc(freqs(N).astype(np.float64) / N) ** order for N in _shape(n)]  # sinc(x) = sin(pi x)/(pi x)
+    return w[0][:, None, None] * w[1][None, :, None] * w[2][None, None, :]
+
+
+def _kmag2(shape) -> np.ndarray:
+    fx, fy, fz = (freqs(N) for N in shape)
+    return fx[:, None, None] ** 2 + fy[None, :, None] ** 2 + fz[None, None, :] ** 2
+
+
+def _pfid_grid(n, pfid) -> np.ndarray:
+    k2 = _kmag2(_shape(n))
     if pfid is None:
         return np.ones(k2.shape)
     tab = np.asarray(pfid, dtype=np.float64)
@@ -58,11 +67,11 @@ def _pfid_grid(n: int, pfid) -> np.ndarray:
 
 def weighted_power(delta, box: float, edges, order: int = 0, pfid=None, nbar: float = 0.0) -> np.ndarray:
     d = np.asarray(delta, dtype=np.float64)
-    n = d.shape[0]
-    npix, vol = float(n) ** 3, float(box) ** 3
+    n = d.shape  # any grid shape; a box with equal sides (P_fid over integer |n|^2)
+    npix, vol = float(d.size), float(box) ** 3
     D = dft(d) / window(n, order)
     P = _pfid_grid(n, pfid)
-    idx = bin_of_modes(n, edges)
+    idx = _nc.bin_of_modes(n, box, edges)
     nb = len(edges) - 1
     out = np.zeros(nb)
     for b in range(nb):
@@ -76,14 +85,14 @@ def weighted_bispectrum(delta, box: float, edges, order: int = 0, pfid=None, nba
     """(triplets, B, N_0, A) for the triangle-valid triplets with closed triangles;
     A is the same normalisation of sum_x |G~ G~ G~| (for tolerances)."""
     d = np.asarray(delta, dtype=np.float64)
-    n = d.shape[0]
-    npix, vol = float(n) ** 3, float(box) ** 3
+    n = d.shape
+    npix, vol = float(d.size), float(box) ** 3
     trips = triangle_triplets(edges)
-    T, _ = triangle_counts(n, edges, trips)
+    T, _ = _nc.triangle_counts(n, box, edges, trips)
     trips = trips[T > 0]
     P = _pfid_grid(n, pfid)
     D = dft(d) / (window(n, order) * P)
-    idx = bin_of_modes(n, edges)
+    idx = _nc.bin_of_modes(n, box, edges)
     nb = len(edges) - 1
     G = np.stack([idft(np.where(idx == b, D, 0.0)).real for b in range(nb)])
     Hw = np.stack([idft(np.where(idx == b, 1.0 / P, 0.0)).real for b in range(nb)])

@@ -493,7 +493,8 @@ static pb3_status ensure_workspace(pb3_plan* p) {
 // Launch-shape choice per plan: the inverse z pass fused into the
 // contraction or separate, and the number of contraction work-groups
 // (multiples of the CU count).  Each candidate runs the whole bispectrum
-// path a few times on a zero field; the fastest median wins.  Results are
+// path a few times on a zero field; the fastest median wins, except that the
+// default shape is kept unless another is more than 2% faster.  Results are
 // cached in a text file (PB3_AUTOTUNE_CACHE) keyed by device architecture,
 // grid, contraction grid and the bin thresholds.
 static std::string tune_key(const pb3_plan* p) {
@@ -576,7 +577,7 @@ static pb3_status autotune(pb3_plan* p, int n_cu) {
   if (st == PB3_OK && ((e = hipMemset(fld, 0, sizeof(float) * n3)) != hipSuccess ||
                        (e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess))
     st = hip_fail(e, "autotune set-up");
-  float best = 1e30f;
+  float best = 1e30f, def_ms = -1.f;
   Cand pick{keep_fused, keep_wgs};
   for (size_t ci = 0; ci < cands.size() && st == PB3_OK; ++ci) {
     p->fused = cands[ci].fused;
@@ -604,10 +605,17 @@ static pb3_status autotune(pb3_plan* p, int n_cu) {
     if (st != PB3_OK) break;
     std::sort(ms.begin(), ms.end());
     const float med = ms[ms.size() / 2];
+    if (cands[ci].fused == keep_fused && cands[ci].wgs == keep_wgs) def_ms = med;
     if (med < best) {
       best = med;
       pick = cands[ci];
     }
+  }
+  // keep the default shape unless another is clearly faster (the medians of
+  // nearly equal shapes swap from run to run)
+  if (st == PB3_OK && def_ms > 0.f && best > 0.98f * def_ms) {
+    pick = Cand{keep_fused, keep_wgs};
+    best = def_ms;
   }
   if (e0) hipEventDestroy(e0);
   if (e1) hipEventDestroy(e1);
