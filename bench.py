@@ -45,11 +45,11 @@ FP32_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 MEASURED_TRAFFIC = {
     ("contract", "mixed"): {
         "kernel": "k_zcontract<2, true, 192>",
-        "contract_wgs": 256,  # partial-vector writes scale with the work-group count
-        "fetch_kib": 138428.0, "write_kib": 11008.0, "fetch_factor": 2.0, "write_factor": 1.0,
+        "contract_wgs": 1024,  # partial-vector writes scale with the work-group count
+        "fetch_kib": 139900.7, "write_kib": 44032.0, "fetch_factor": 2.0, "write_factor": 1.0,
         "sources": {
             "paper_2404_07249_amd/csrc/contract_mfma.hip":
-                "117dfcfdc60b914768f59b635a290bf38b4c0fa3d921d5d68850fc25f3dcffca",
+                "c969e833078222d878ea9a21a69fbbf4a13314247a714c502d16debb415280c6",
             "paper_2404_07249_amd/csrc/fft_dev.h":
                 "445483e27faf3491134cb99e4822494520ab3d6b22f80871c30bdb01f5151c73",
             "paper_2404_07249_amd/csrc/job.h":

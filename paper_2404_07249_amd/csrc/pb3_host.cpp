@@ -548,7 +548,7 @@ static pb3_status autotune(pb3_plan* p, int n_cu) {
   std::vector<Cand> cands;
   const int nq = p->nb_pad / 16;
   if (p->fused_ok) {
-    const int base = fused_grid(nq, p->Mz, n_cu);
+    const int base = fused_grid(nq, p->Mz, (long)mpix(*p), n_cu);
     for (int mult : {1, 2}) cands.push_back({true, base * mult});
   }
   for (int mult : {1, 2, 3, 4}) cands.push_back({false, n_cu * mult});
@@ -640,7 +640,7 @@ static pb3_status build_device(pb3_plan* p) {
   int n_cu = 0;
   e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, p->device_id);
   if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
-  p->contract_wgs = p->fused ? fused_grid(p->nb_pad / 16, p->Mz, n_cu) : mfma_grid(p->nb_pad / 16, n_cu);
+  p->contract_wgs = p->fused ? fused_grid(p->nb_pad / 16, p->Mz, (long)mpix(*p), n_cu) : mfma_grid(p->nb_pad / 16, n_cu);
   DeviceTables& d = p->d;
   if ((st = upload(&d.bin3, p->bin3.data(), p->bin3.size())) != PB3_OK) return st;
   if ((st = upload(&d.modes, p->modes.data(), p->modes.size())) != PB3_OK) return st;

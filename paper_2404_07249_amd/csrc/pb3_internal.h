@@ -240,7 +240,7 @@ hipError_t launch_contract_cols(const pb3_plan& p, const Exec& x, const float* g
 int mfma_grid(int nq, int n_cu);
 // fused inverse z pass + contraction (contract_mfma.hip)
 bool fused_supported(int nq, int m);
-int fused_grid(int nq, int m, int n_cu);
+int fused_grid(int nq, int m, long mvox, int n_cu);
 hipError_t launch_zcontract(const pb3_plan& p, const Exec& x, bool mixed, hipStream_t s);
 // inverse passes (fft_passes.hip) on FP32 (dbl = false) or FP64 lines;
 // unit = the shell indicator instead of Theta_b D (count pass, FP64 only);
