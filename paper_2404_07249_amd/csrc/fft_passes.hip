@@ -23,6 +23,15 @@
 
 namespace pb3 {
 
+// Work-groups go to the 8 XCDs of the chip round-robin, each XCD with its
+// own L2.  The per-bin passes number their tiles so that neighbours share
+// cache lines (the column chunks of one row); this maps consecutive tiles
+// to work-groups of one XCD (b, b + 8, b + 16, ...), launched as 8 * per
+// work-groups of which those past the last tile return at once.
+constexpr int kXcds = 8;
+__host__ __device__ inline int xcd_tiles(int n) { return kXcds * ((n + kXcds - 1) / kXcds); }
+__device__ __forceinline__ int xcd_tile(int b, int n) { return (b % kXcds) * ((n + kXcds - 1) / kXcds) + b / kXcds; }
+
 // Strided passes: TB columns per work-group, TL threads per column.
 template <int N, int CS> struct ColShape {
   static constexpr int TL = fft2_threads(N);
@@ -128,7 +137,8 @@ struct WinOff {
 template <int M, typename Rl, bool UNIT>
 __global__ void __launch_bounds__(512) k_inv_x2(const float2* __restrict__ dc, typename Cx<Rl>::type* __restrict__ a1,
                                                 const BinGeom* __restrict__ geom, const BinTile* __restrict__ tiles,
-                                                const int8_t* __restrict__ bin3, int Kcx, int Kcy, int Lcy, int Kz,
+                                                int n_tiles, const int8_t* __restrict__ bin3, int Kcx, int Kcy,
+                                                int Lcy, int Kz,
                                                 const typename Cx<Rl>::type* __restrict__ tw, size_t wstride,
                                                 int ell, const float* __restrict__ winv, WinOff wo, float sx,
                                                 float sy, const float* __restrict__ pinv,
@@ -144,7 +154,9 @@ __global__ void __launch_bounds__(512) k_inv_x2(const float2* __restrict__ dc, t
   for (int e = tid; e < M; e += S::NT) tws[e] = tw[e];
   __syncthreads();
   const int tl = tid / TB, col = tid % TB;
-  const BinTile tile = tiles[blockIdx.x];
+  const int ti = xcd_tile(blockIdx.x, n_tiles);
+  if (ti >= n_tiles) return;  // whole work-group
+  const BinTile tile = tiles[ti];
   const int b = tile.bin;
   const BinGeom g = geom[b];
   const int jy = tile.col0 >> 8;
@@ -198,7 +210,8 @@ template <int M, typename Rl>
 __global__ void __launch_bounds__(512) k_inv_y2(const typename Cx<Rl>::type* __restrict__ a1,
                                                 typename Cx<Rl>::type* __restrict__ a2,
                                                 const BinGeom* __restrict__ geom, const BinTile* __restrict__ tiles,
-                                                const typename Cx<Rl>::type* __restrict__ tw, size_t wstride) {
+                                                int n_tiles, const typename Cx<Rl>::type* __restrict__ tw,
+                                                size_t wstride) {
   a1 = job_ptr(a1, wstride);
   a2 = job_ptr(a2, wstride);
   using C = typename Cx<Rl>::type;
@@ -210,7 +223,9 @@ __global__ void __launch_bounds__(512) k_inv_y2(const typename Cx<Rl>::type* __r
   for (int e = tid; e < M; e += S::NT) tws[e] = tw[e];
   __syncthreads();
   const int tl = tid / TB, col = tid % TB;
-  const BinTile tile = tiles[blockIdx.x];
+  const int ti = xcd_tile(blockIdx.x, n_tiles);
+  if (ti >= n_tiles) return;  // whole work-group
+  const BinTile tile = tiles[ti];
   const BinGeom g = geom[tile.bin];
   const int x = tile.col0 >> 8;
   {
@@ -238,7 +253,7 @@ __global__ void __launch_bounds__(512) k_inv_y2(const typename Cx<Rl>::type* __r
 template <int M, typename Rl>
 __global__ void __launch_bounds__(512) k_inv_z2(const typename Cx<Rl>::type* __restrict__ a2, Rl* __restrict__ gout,
                                                 const BinGeom* __restrict__ geom, const BinTile* __restrict__ tiles,
-                                                const typename Cx<Rl>::type* __restrict__ tw, Rl scale,
+                                                int n_tiles, const typename Cx<Rl>::type* __restrict__ tw, Rl scale,
                                                 int nlines, size_t wstride) {
   a2 = job_ptr(a2, wstride);
   gout = job_ptr(gout, wstride);
@@ -250,7 +265,9 @@ __global__ void __launch_bounds__(512) k_inv_z2(const typename Cx<Rl>::type* __r
   __shared__ C stage[TP * (M + 2)];  // input 2TP x kzn complex, then output 2TP x M reals
   const int tid = threadIdx.x;
   for (int e = tid; e < M; e += S::NT) tws[e] = tw[e];
-  const BinTile tile = tiles[blockIdx.x];
+  const int ti = xcd_tile(blockIdx.x, n_tiles);
+  if (ti >= n_tiles) return;  // whole work-group
+  const BinTile tile = tiles[ti];
   const BinGeom g = geom[tile.bin];
   const int kzn = g.kzn;
   const int line0 = tile.col0;
@@ -362,17 +379,17 @@ hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, const float2* dc, v
     if (dbl) {
       using S = ColShape<LL, 16>;
       if (unit)
-        hipLaunchKernelGGL((k_inv_x2<LL, double, true>), dim3(ts.n, 1, n_jobs), dim3(S::NT), 0, s, dc,
-                           (double2*)a1, p.d.geom, ts.d, p.d.bin3, p.Kcx, p.Kcy, p.Lcy, p.Kz, (const double2*)tw,
+        hipLaunchKernelGGL((k_inv_x2<LL, double, true>), dim3(xcd_tiles(ts.n), 1, n_jobs), dim3(S::NT), 0, s, dc,
+                           (double2*)a1, p.d.geom, ts.d, ts.n, p.d.bin3, p.Kcx, p.Kcy, p.Lcy, p.Kz, (const double2*)tw,
                            wstride, 0, (const float*)nullptr, wo, sx, sy, (const float*)nullptr, unit_w);
       else
         return hipErrorInvalidValue;
     } else {
       using S = ColShape<LL, 8>;
       if (unit) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((k_inv_x2<LL, float, false>), dim3(ts.n, 1, n_jobs), dim3(S::NT), 0, s, dc, (float2*)a1,
-                         p.d.geom, ts.d, p.d.bin3, p.Kcx, p.Kcy, p.Lcy, p.Kz, (const float2*)tw, wstride, ell, winv,
-                         wo, sx, sy, pinv, (const double*)nullptr);
+      hipLaunchKernelGGL((k_inv_x2<LL, float, false>), dim3(xcd_tiles(ts.n), 1, n_jobs), dim3(S::NT), 0, s, dc,
+                         (float2*)a1, p.d.geom, ts.d, ts.n, p.d.bin3, p.Kcx, p.Kcy, p.Lcy, p.Kz, (const float2*)tw,
+                         wstride, ell, winv, wo, sx, sy, pinv, (const double*)nullptr);
     }
     return hipGetLastError();
   });
@@ -386,12 +403,12 @@ hipError_t run_inv_y(const pb3_plan& p, bool dbl, const void* a1, void* a2, cons
   PB3_FFT_LEN(p.My, {
     if (dbl) {
       using S = ColShape<LL, 16>;
-      hipLaunchKernelGGL((k_inv_y2<LL, double>), dim3(ts.n, 1, n_jobs), dim3(S::NT), 0, s, (const double2*)a1,
-                         (double2*)a2, p.d.geom, ts.d, (const double2*)tw, wstride);
+      hipLaunchKernelGGL((k_inv_y2<LL, double>), dim3(xcd_tiles(ts.n), 1, n_jobs), dim3(S::NT), 0, s, (const double2*)a1,
+                         (double2*)a2, p.d.geom, ts.d, ts.n, (const double2*)tw, wstride);
     } else {
       using S = ColShape<LL, 8>;
-      hipLaunchKernelGGL((k_inv_y2<LL, float>), dim3(ts.n, 1, n_jobs), dim3(S::NT), 0, s, (const float2*)a1,
-                         (float2*)a2, p.d.geom, ts.d, (const float2*)tw, wstride);
+      hipLaunchKernelGGL((k_inv_y2<LL, float>), dim3(xcd_tiles(ts.n), 1, n_jobs), dim3(S::NT), 0, s, (const float2*)a1,
+                         (float2*)a2, p.d.geom, ts.d, ts.n, (const float2*)tw, wstride);
     }
     return hipGetLastError();
   });
@@ -408,13 +425,13 @@ hipError_t run_inv_z(const pb3_plan& p, bool dbl, const void* a2, void* gout, co
     if (dbl) {
       using S = PairShape<LL, 16>;
       if (ts.tb != 2 * S::TP) return hipErrorInvalidConfiguration;
-      hipLaunchKernelGGL((k_inv_z2<LL, double>), dim3(ts.n, 1, n_jobs), dim3(S::NT), 0, s, (const double2*)a2,
-                         (double*)gout, p.d.geom, ts.d, (const double2*)tw, sc, nlines, wstride);
+      hipLaunchKernelGGL((k_inv_z2<LL, double>), dim3(xcd_tiles(ts.n), 1, n_jobs), dim3(S::NT), 0, s, (const double2*)a2,
+                         (double*)gout, p.d.geom, ts.d, ts.n, (const double2*)tw, sc, nlines, wstride);
     } else {
       using S = PairShape<LL, 8>;
       if (ts.tb != 2 * S::TP) return hipErrorInvalidConfiguration;
-      hipLaunchKernelGGL((k_inv_z2<LL, float>), dim3(ts.n, 1, n_jobs), dim3(S::NT), 0, s, (const float2*)a2,
-                         (float*)gout, p.d.geom, ts.d, (const float2*)tw, (float)sc, nlines, wstride);
+      hipLaunchKernelGGL((k_inv_z2<LL, float>), dim3(xcd_tiles(ts.n), 1, n_jobs), dim3(S::NT), 0, s, (const float2*)a2,
+                         (float*)gout, p.d.geom, ts.d, ts.n, (const float2*)tw, (float)sc, nlines, wstride);
     }
     return hipGetLastError();
   });
