@@ -99,7 +99,7 @@ __global__ void __launch_bounds__(512) k_fwd_z2(const JobIO io, float2* __restri
 // out row c <- frequency f = c - Ko (kept when 0 <= c < Lo).
 template <int N>
 __global__ void __launch_bounds__(512) k_fwd_col2(const float2* __restrict__ in, float2* __restrict__ out, int n_inner,
-                                                  long in_outer, long out_outer, int Lo, int Ko,
+                                                  int n_outer, long in_outer, long out_outer, int Lo, int Ko,
                                                   const float2* __restrict__ tw, size_t wstride) {
   in = job_ptr(in, wstride);
   out = job_ptr(out, wstride);
@@ -107,14 +107,20 @@ __global__ void __launch_bounds__(512) k_fwd_col2(const float2* __restrict__ in,
   constexpr int TB = S::TB, LS = S::LS;
   __shared__ float2 tws[N];
   __shared__ float2 scr[TB * LS];
+  // tiles (outer, chunk of TB inner columns), chunks of one outer row next to
+  // each other and on one XCD (rows shorter than a cache line multiple share lines)
+  const int n_ck = (n_inner + TB - 1) / TB, n_t = n_ck * n_outer;
+  const int t = xcd_tile(blockIdx.x, n_t);
+  if (t >= n_t) return;  // whole work-group
+  const int ck = t % n_ck, outer = t / n_ck;
   const int tid = threadIdx.x;
   for (int e = tid; e < N; e += S::NT) tws[e] = tw[e];
   __syncthreads();
   const int tl = tid / TB, col = tid % TB;
-  const int inner = blockIdx.x * TB + col;
+  const int inner = ck * TB + col;
   const bool live = inner < n_inner;
-  const float2* src = in + (size_t)blockIdx.y * in_outer + (live ? inner : 0);
-  float2* dst = out + (size_t)blockIdx.y * out_outer + inner;
+  const float2* src = in + (size_t)outer * in_outer + (live ? inner : 0);
+  float2* dst = out + (size_t)outer * out_outer + inner;
   fft2_line<N, -1>(
       scr + col * LS, tl, tws, [&](int n) { return live ? src[(size_t)n * n_inner] : make_float2(0.f, 0.f); },
       [&](int k, float2 v) {
@@ -350,9 +356,9 @@ static hipError_t fwd_col(const Exec& x, int len, const float2* tw, int Lo, int 
                           int n_inner, long in_outer, long out_outer, int n_outer, hipStream_t s) {
   PB3_FFT_LEN(len, {
     using S = ColShape<LL, 8>;
-    dim3 grid((n_inner + S::TB - 1) / S::TB, n_outer, x.n_jobs);
-    hipLaunchKernelGGL(k_fwd_col2<LL>, grid, dim3(S::NT), 0, s, in, out, n_inner, in_outer, out_outer, Lo, Ko, tw,
-                       x.wstride);
+    dim3 grid(xcd_tiles((n_inner + S::TB - 1) / S::TB * n_outer), 1, x.n_jobs);
+    hipLaunchKernelGGL(k_fwd_col2<LL>, grid, dim3(S::NT), 0, s, in, out, n_inner, n_outer, in_outer, out_outer, Lo, Ko,
+                       tw, x.wstride);
     return hipGetLastError();
   });
   return hipErrorInvalidValue;
