@@ -51,15 +51,25 @@ __global__ void __launch_bounds__(256) k_power_chunks(const float2* __restrict__
   if (threadIdx.x == 0) part[c] = red[0];
 }
 
-__global__ void k_power_final(const double* __restrict__ part, const int32_t* __restrict__ chunk_first, int nb,
-                              const double* __restrict__ scale, const JobIO io, size_t wstride, double shift) {
+// One wave per bin: lane l sums the bin's chunks l, l + 64, ... and the
+// lanes combine in a fixed-order tree.
+__global__ void __launch_bounds__(64) k_power_final(const double* __restrict__ part,
+                                                    const int32_t* __restrict__ chunk_first, int nb,
+                                                    const double* __restrict__ scale, const JobIO io, size_t wstride,
+                                                    double shift) {
   part = job_ptr(part, wstride);
   double* __restrict__ pk = io.pk[blockIdx.z];
-  int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nb) return;
+  __shared__ double red[64];
+  const int b = blockIdx.x, l = threadIdx.x;
   double s = 0.0;
-  for (int c = chunk_first[b]; c < chunk_first[b + 1]; ++c) s += part[c];
-  pk[b] = s * scale[b] - shift;
+  for (int c = chunk_first[b] + l; c < chunk_first[b + 1]; c += 64) s += part[c];
+  red[l] = s;
+  __syncthreads();
+  for (int h = 32; h > 0; h >>= 1) {
+    if (l < h) red[l] += red[l + h];
+    __syncthreads();
+  }
+  if (l == 0) pk[b] = red[0] * scale[b] - shift;
 }
 
 // ------------------------------------------------ simple triplet contraction
@@ -139,17 +149,31 @@ __global__ void k_reduce(const Rl* __restrict__ part, int n_wg, int part_len, co
 
 // Two-stage form for the MFMA partials: slice s of the work-groups is
 // summed per element (FP64), then the slices per kept triplet.
+// Each thread takes four neighbouring elements (one 16-byte load per
+// work-group partial; part_len is a multiple of 256), each summed over the
+// slice's work-groups in order.
 __global__ void k_reduce_slices(const float* __restrict__ part, int n_wg, int part_len, double* __restrict__ rsl,
                                 size_t wstride) {
   part = job_ptr(part, wstride);
   rsl = job_ptr(rsl, wstride);
-  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int e = 4 * (blockIdx.x * blockDim.x + threadIdx.x);
   if (e >= part_len) return;
-  int s = blockIdx.y;
-  int w0 = (int)((long)n_wg * s / kReduceSlices), w1 = (int)((long)n_wg * (s + 1) / kReduceSlices);
-  double acc = 0.0;
-  for (int w = w0; w < w1; ++w) acc += (double)part[(size_t)w * part_len + e];
-  rsl[(size_t)s * part_len + e] = acc;
+  const int s = blockIdx.y;
+  const int w0 = (int)((long)n_wg * s / kReduceSlices), w1 = (int)((long)n_wg * (s + 1) / kReduceSlices);
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll 8
+  for (int w = w0; w < w1; ++w) {
+    const float4 v = *reinterpret_cast<const float4*>(part + (size_t)w * part_len + e);
+    a0 += (double)v.x;
+    a1 += (double)v.y;
+    a2 += (double)v.z;
+    a3 += (double)v.w;
+  }
+  double* __restrict__ o = rsl + (size_t)s * part_len + e;
+  o[0] = a0;
+  o[1] = a1;
+  o[2] = a2;
+  o[3] = a3;
 }
 
 __global__ void k_reduce_final(const double* __restrict__ rsl, int part_len, const int32_t* __restrict__ map,
@@ -385,8 +409,8 @@ hipError_t launch_power(const pb3_plan& p, const Exec& x, hipStream_t s) {
                      x.ws.ppart, x.wstride, (const double*)p.d.mode_w);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_power_final, dim3((p.nb + 63) / 64, 1, x.n_jobs), dim3(64), 0, s, x.ws.ppart,
-                     p.d.chunk_first, p.nb, p.d.pk_scale, x.io, x.wstride, p.pk_shift);
+  hipLaunchKernelGGL(k_power_final, dim3(p.nb, 1, x.n_jobs), dim3(64), 0, s, x.ws.ppart, p.d.chunk_first, p.nb,
+                     p.d.pk_scale, x.io, x.wstride, p.pk_shift);
   return hipGetLastError();
 }
 
@@ -432,7 +456,7 @@ hipError_t launch_contract(const pb3_plan& p, const Exec& x, pb3_precision prec,
 hipError_t launch_reduce(const pb3_plan& p, const Exec& x, hipStream_t s) {
   int n_out = (int)(p.trip.size() / 3);
   if (n_out == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce_slices, dim3((p.part_len + 255) / 256, kReduceSlices, x.n_jobs), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_reduce_slices, dim3((p.part_len / 4 + 255) / 256, kReduceSlices, x.n_jobs), dim3(256), 0, s,
                      x.ws.part, p.contract_wgs, p.part_len, x.ws.rsl, x.wstride);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -593,7 +617,7 @@ pb3_status run_multipoles(pb3_plan& p, const float* delta, double* pk_out, doubl
       if (!chk(launch_contract_cols(p, x, fields, l ? fields + (size_t)l * p.nb * m3 : nullptr, true, s),
                "multipoles: contraction"))
         return st;
-      hipLaunchKernelGGL(k_reduce_slices, dim3((p.part_len + 255) / 256, kReduceSlices, 1), dim3(256), 0, s,
+      hipLaunchKernelGGL(k_reduce_slices, dim3((p.part_len / 4 + 255) / 256, kReduceSlices, 1), dim3(256), 0, s,
                          x.ws.part, p.contract_wgs, p.part_len, x.ws.rsl, (size_t)0);
       if (!chk(hipGetLastError(), "multipoles: reduce")) return st;
       JobIO io{};
