@@ -459,62 +459,129 @@ __device__ __forceinline__ void contract_line_group(const LineStage<NQ, M>& st, 
   }
 }
 
-// Producer: build the stage for one line.  ptid in [0, kProducerThreads).
-template <int NQ, bool MIXED, int M>
-__device__ __forceinline__ void produce_line(LineStage<NQ, M>& st, const float2* __restrict__ a2,
-                                             const BinGeom* __restrict__ geom, int nb, long line,
-                                             const float2* tws, float2* scr, int ptid, float scale,
-                                             const SplitSel& sel) {
-  constexpr int TL = fft2_threads(M), NSLOT = kProducerThreads / TL;
+// Producer side.  The 256 producer threads form slots of fft2_threads(M)
+// lanes; slot t transforms the bin pair (2t, 2t + 1) of every line, packed
+// as one complex line F_2t + i F_2t+1 (both real after the transform).
+// The pair's geometry is read once.  In mixed precision the raw inputs of
+// the next line are fetched into registers while the current line is
+// transformed; the FP32 groups (12 waves, fewer registers per wave) fetch
+// each line just before its transform.
+template <int M> struct PairSrc {
+  static constexpr int R1 = fft2_r1(M), R2 = fft2_r2(M);
+  const float2* x0;  // bin 2t's y-pass output, lines of s0 planes
+  const float2* x1;  // bin 2t + 1's (bin 2t's when there is none)
+  int s0, s1;
+  int k0n, k1n;      // kz planes of each bin (k1n = 0: no second bin)
+  bool on;           // the slot holds a pair
+  float2 r0[R1], r1[R1];
+};
+
+template <int M>
+__device__ __forceinline__ void pair_init(PairSrc<M>& ps, const float2* a2, const BinGeom* __restrict__ geom,
+                                          int nb, int slot, bool live) {
+  const int npairs = (nb + 1) / 2;
+  ps.on = live && slot < npairs;
+  ps.x0 = ps.x1 = a2;
+  ps.s0 = ps.s1 = ps.k0n = ps.k1n = 0;
+  if (ps.on) {
+    const BinGeom g0 = geom[2 * slot];
+    const bool has1 = 2 * slot + 1 < nb;
+    const BinGeom g1 = has1 ? geom[2 * slot + 1] : g0;
+    ps.x0 = a2 + g0.a2_off;
+    ps.x1 = a2 + g1.a2_off;
+    ps.s0 = g0.kzn;
+    ps.s1 = g1.kzn;
+    ps.k0n = g0.kzn;
+    ps.k1n = has1 ? g1.kzn : 0;
+  }
+}
+
+// Raw inputs of one line for a phase-1 lane: plane n = tl + R2 j comes from
+// plane n (n < kzn) or, conjugated when combined, from plane M - n
+// (M - n < kzn) of the half-spectrum; otherwise it is zero.
+// MASKED (the FP32 groups, short of registers): loads under lane masks
+// leave the zero planes zero; the plane bounds are re-read on each call so
+// that no derived index stays in registers across the line loop.
+// Otherwise every lane loads (plane 0 stands in for a zero plane, so that
+// every address lies in the line) and the combine selects; fewer
+// instructions wait on the loads, which suits fetching a line ahead.
+template <int M, bool MASKED>
+__device__ __forceinline__ void pair_fetch(PairSrc<M>& ps, long line, int tl) {
+  constexpr int R1 = PairSrc<M>::R1, R2 = PairSrc<M>::R2;
+  if (!ps.on || tl >= R2) return;
+  const float2* p0 = ps.x0 + line * ps.s0;
+  const float2* p1 = ps.x1 + line * ps.s1;
+  int k0n = ps.k0n, k1n = ps.k1n;
+  if constexpr (MASKED) asm volatile("" : "+v"(k0n), "+v"(k1n));
+#pragma unroll
+  for (int j = 0; j < R1; ++j) {
+    const int k = tl + R2 * j, m = M - k;
+    if constexpr (MASKED) {
+      float2 a = make_float2(0.f, 0.f), c = make_float2(0.f, 0.f);
+      if (k < k0n) a = p0[k];
+      else if (m < k0n) a = p0[m];
+      if (k < k1n) c = p1[k];
+      else if (m < k1n) c = p1[m];
+      ps.r0[j] = a;
+      ps.r1[j] = c;
+    } else {
+      ps.r0[j] = p0[k < k0n ? k : (m < k0n ? m : 0)];
+      ps.r1[j] = p1[k < k1n ? k : (m < k1n ? m : 0)];
+    }
+  }
+}
+
+// Build the stage for one line from the fetched inputs; next >= 0 starts the
+// fetch of that line once phase 1 has taken these.
+template <int NQ, bool MIXED, int M, bool MASKED>
+__device__ __forceinline__ void produce_line(LineStage<NQ, M>& st, PairSrc<M>& ps, long next, const float2* tws,
+                                             float2* scr, int slot, int tl, float scale, const SplitSel& sel) {
   constexpr int R1 = fft2_r1(M), R2 = fft2_r2(M);
   constexpr int PF = LineStage<NQ, M>::PF, PH = LineStage<NQ, M>::PH;
-  const int slot = ptid / TL, tl = ptid % TL;
-  const int npairs = (nb + 1) / 2;
-  for (int pr = slot; pr < npairs; pr += NSLOT) {
-    const int b0 = 2 * pr, b1 = 2 * pr + 1;
-    const BinGeom g0 = geom[b0];
-    const bool has1 = b1 < nb;
-    const BinGeom g1 = has1 ? geom[b1] : g0;
-    const float2* x0 = a2 + g0.a2_off + line * g0.kzn;
-    const float2* x1 = a2 + g1.a2_off + line * g1.kzn;
-    const int k0n = g0.kzn, k1n = has1 ? g1.kzn : 0;
-    fft2_line_wave<M, 1>(
-        scr + slot * (M + 1), tl, tws,
-        [&](int k) {
-          float2 a = make_float2(0.f, 0.f), c = make_float2(0.f, 0.f);
+  if (!ps.on) return;
+  const int b0 = 2 * slot, b1 = 2 * slot + 1;
+  fft2_line_wave<M, 1>(
+      scr + slot * R1 * (R2 + 1), tl, tws,
+      [&](int j, int k) {
+        float2 a = ps.r0[j], c = ps.r1[j];
+        if constexpr (MASKED) {
+          if (k >= ps.k0n) a.y = -a.y;  // mirrored plane (or zero)
+          if (k >= ps.k1n) c.y = -c.y;
+        } else {
           const int m = M - k;
-          if (k < k0n) a = x0[k];
-          else if (m < k0n) { a = x0[m]; a.y = -a.y; }
-          if (k < k1n) c = x1[k];
-          else if (m < k1n) { c = x1[m]; c.y = -c.y; }
-          return make_float2(a.x - c.y, a.y + c.x);  // F_b + i F_{b+1}
-        },
-        [&](int k1, const float2 (&u)[R2]) {
+          if (k >= ps.k0n) a = (m < ps.k0n) ? make_float2(a.x, -a.y) : make_float2(0.f, 0.f);
+          if (k >= ps.k1n) c = (m < ps.k1n) ? make_float2(c.x, -c.y) : make_float2(0.f, 0.f);
+        }
+        return make_float2(a.x - c.y, a.y + c.x);  // F_b + i F_{b+1}
+      },
+      [&]() {
+        if (next >= 0) pair_fetch<M, MASKED>(ps, next, tl);
+      },
+      [&](int k1, const float2 (&u)[R2]) {
 #pragma unroll
-          for (int k2 = 0; k2 < R2; k2 += 2) {
-            const int z0 = k1 + R1 * k2, z1 = z0 + R1;
-            float r0 = u[k2].x * scale, r1 = u[k2 + 1].x * scale;
-            float i0 = u[k2].y * scale, i1 = u[k2 + 1].y * scale;
-            st.f[b0 * PF + z0] = r0;
-            st.f[b0 * PF + z1] = r1;
-            st.f[b1 * PF + z0] = i0;
-            st.f[b1 * PF + z1] = i1;
-            if constexpr (MIXED) {
-              float rv[8] = {r0, r1, i0, i1, 0.f, 0.f, 0.f, 0.f};
-              bf16x8_t h8, l8;
-              split8(rv, h8, l8, sel);
-              st.hi[b0 * PH + z0] = h8[0];
-              st.hi[b0 * PH + z1] = h8[1];
-              st.hi[b1 * PH + z0] = h8[2];
-              st.hi[b1 * PH + z1] = h8[3];
-              st.lo[b0 * PH + z0] = l8[0];
-              st.lo[b0 * PH + z1] = l8[1];
-              st.lo[b1 * PH + z0] = l8[2];
-              st.lo[b1 * PH + z1] = l8[3];
-            }
+        for (int k2 = 0; k2 < R2; k2 += 2) {
+          const int z0 = k1 + R1 * k2, z1 = z0 + R1;
+          float r0 = u[k2].x * scale, r1 = u[k2 + 1].x * scale;
+          float i0 = u[k2].y * scale, i1 = u[k2 + 1].y * scale;
+          st.f[b0 * PF + z0] = r0;
+          st.f[b0 * PF + z1] = r1;
+          st.f[b1 * PF + z0] = i0;
+          st.f[b1 * PF + z1] = i1;
+          if constexpr (MIXED) {
+            float rv[8] = {r0, r1, i0, i1, 0.f, 0.f, 0.f, 0.f};
+            bf16x8_t h8, l8;
+            split8(rv, h8, l8, sel);
+            st.hi[b0 * PH + z0] = h8[0];
+            st.hi[b0 * PH + z1] = h8[1];
+            st.hi[b1 * PH + z0] = h8[2];
+            st.hi[b1 * PH + z1] = h8[3];
+            st.lo[b0 * PH + z0] = l8[0];
+            st.lo[b0 * PH + z1] = l8[1];
+            st.lo[b1 * PH + z0] = l8[2];
+            st.lo[b1 * PH + z1] = l8[3];
           }
-        });
-  }
+        }
+      });
 }
 
 template <int NQ, bool MIXED, int M>
@@ -529,26 +596,22 @@ __global__ void __launch_bounds__(fused_threads(MIXED)) k_zcontract(const float2
   constexpr int NT = n_tiles(NQ);
   constexpr int NTMAX = max_group_tiles<NQ, K0, K1>();
   constexpr int TL = fft2_threads(M), NSLOT = kProducerThreads / TL;
+  static_assert(2 * NSLOT >= 16 * NQ, "one bin pair per producer slot");
   constexpr int STAGE_BYTES = (int)sizeof(LineStage<NQ, M>);
   constexpr int RED_BYTES = NT * 256 * 4;
   constexpr int MAIN = 2 * STAGE_BYTES > RED_BYTES ? 2 * STAGE_BYTES : RED_BYTES;
   __shared__ __align__(16) unsigned char smem[MAIN];
   __shared__ float2 tws[M];
-  __shared__ float2 scr[NSLOT * (M + 1)];
+  __shared__ float2 scr[NSLOT * fft2_r1(M) * (fft2_r2(M) + 1)];
   LineStage<NQ, M>* stage = reinterpret_cast<LineStage<NQ, M>*>(smem);
   float* red = reinterpret_cast<float*>(smem);
   const int tid = threadIdx.x;
   constexpr int FW = fused_waves(MIXED), NTHR = fused_threads(MIXED), NCON = fused_consumers(MIXED);
   const bool producer = tid >= NCON;
   const int lane = tid & 63, wave = tid >> 6;
-  const int gi = wave / FW, wig = wave % FW;
-  const int i = lane & 15, grp = lane >> 4;
   SplitSel sel;
   __builtin_memcpy(&sel.lo, &sel_lo, 4);
   __builtin_memcpy(&sel.hi, &sel_hi, 4);
-  f32x4_t acc[NTMAX];
-#pragma unroll
-  for (int t = 0; t < NTMAX; ++t) acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
   // zero both stages (rows of padding bins stay zero), twiddles to LDS
   for (int e = tid; e < 2 * STAGE_BYTES / 4; e += NTHR) reinterpret_cast<float*>(smem)[e] = 0.f;
   for (int e = tid; e < M; e += NTHR) tws[e] = tw[e];
@@ -557,14 +620,36 @@ __global__ void __launch_bounds__(fused_threads(MIXED)) k_zcontract(const float2
   long l1 = l0 + lpw;
   if (l1 > nlines) l1 = nlines;
   const int n = l1 > l0 ? (int)(l1 - l0) : 0;
-  if (producer && n > 0) produce_line<NQ, MIXED, M>(stage[0], a2, geom, nb, l0, tws, scr, tid - NCON, scale, sel);
-  __syncthreads();
-  for (int m = 0; m < n; ++m) {
-    if (producer) {
-      if (m + 1 < n)
-        produce_line<NQ, MIXED, M>(stage[(m + 1) & 1], a2, geom, nb, l0 + m + 1, tws, scr, tid - NCON,
-                                   scale, sel);
-    } else {
+  // Producer and consumer waves run separate loops, so that neither holds
+  // the other's registers, with the same barrier count (1 + n + FW).
+  if (producer) {
+    const int pslot = (tid - NCON) / TL, ptl = (tid - NCON) % TL;
+    PairSrc<M> ps;
+    pair_init<M>(ps, a2, geom, nb, pslot, n > 0);
+    constexpr bool AHEAD = MIXED;  // fetch a line ahead (see PairSrc)
+    if (ps.on) {
+      pair_fetch<M, !AHEAD>(ps, l0, ptl);
+      produce_line<NQ, MIXED, M, !AHEAD>(stage[0], ps, AHEAD && n > 1 ? l0 + 1 : -1, tws, scr, pslot, ptl, scale,
+                                         sel);
+    }
+    __syncthreads();
+    for (int m = 0; m < n; ++m) {
+      if (m + 1 < n) {
+        if constexpr (!AHEAD) pair_fetch<M, true>(ps, l0 + m + 1, ptl);
+        produce_line<NQ, MIXED, M, !AHEAD>(stage[(m + 1) & 1], ps, AHEAD && m + 2 < n ? l0 + m + 2 : -1, tws, scr,
+                                           pslot, ptl, scale, sel);
+      }
+      __syncthreads();
+    }
+    for (int w = 0; w < FW; ++w) __syncthreads();
+  } else {
+    const int gi = wave / FW, wig = wave % FW;
+    const int i = lane & 15, grp = lane >> 4;
+    f32x4_t acc[NTMAX];
+#pragma unroll
+    for (int t = 0; t < NTMAX; ++t) acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    __syncthreads();
+    for (int m = 0; m < n; ++m) {
       const LineStage<NQ, M>& cur = stage[m & 1];
       switch (gi) {
         case 0: contract_line_group<NQ, MIXED, K0, K1, 0, M>(cur, i, grp, wig, acc, sel); break;
@@ -572,20 +657,20 @@ __global__ void __launch_bounds__(fused_threads(MIXED)) k_zcontract(const float2
         case 2: contract_line_group<NQ, MIXED, K0, K1, 2, M>(cur, i, grp, wig, acc, sel); break;
         default: contract_line_group<NQ, MIXED, K0, K1, 3, M>(cur, i, grp, wig, acc, sel); break;
       }
+      __syncthreads();
     }
-    __syncthreads();
-  }
-  // fixed-order sum of the waves of each group in LDS (reuses the stages)
-  for (int w = 0; w < FW; ++w) {
-    if (!producer && wig == w) {
-      switch (gi) {
-        case 0: reduce_group<NQ, K0, K1, 0>(red, acc, w, i, grp); break;
-        case 1: reduce_group<NQ, K0, K1, 1>(red, acc, w, i, grp); break;
-        case 2: reduce_group<NQ, K0, K1, 2>(red, acc, w, i, grp); break;
-        default: reduce_group<NQ, K0, K1, 3>(red, acc, w, i, grp); break;
+    // fixed-order sum of the waves of each group in LDS (reuses the stages)
+    for (int w = 0; w < FW; ++w) {
+      if (wig == w) {
+        switch (gi) {
+          case 0: reduce_group<NQ, K0, K1, 0>(red, acc, w, i, grp); break;
+          case 1: reduce_group<NQ, K0, K1, 1>(red, acc, w, i, grp); break;
+          case 2: reduce_group<NQ, K0, K1, 2>(red, acc, w, i, grp); break;
+          default: reduce_group<NQ, K0, K1, 3>(red, acc, w, i, grp); break;
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
   float* dst = part + (size_t)blockIdx.x * part_len;
   for (int e = tid; e < NT * 256; e += NTHR) dst[e] = red[e];

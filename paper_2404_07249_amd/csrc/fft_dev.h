@@ -234,15 +234,24 @@ __device__ __forceinline__ void fft2_line(C* s, int tl, const C* __restrict__ tw
 // Wave-synchronous variant for lines whose max(R1, R2) threads sit in one
 // wavefront: the LDS exchange is ordered by a wavefront-scope fence instead
 // of a work-group barrier, so other waves of the group never wait on it.
-// Phase 2 hands thread k1 its whole row u[k2] (output index k1 + R1 k2).
-template <int N, int S, typename C, typename LoadF, typename RowF>
-__device__ __forceinline__ void fft2_line_wave(C* s, int tl, const C* __restrict__ tw, LoadF&& load, RowF&& row) {
-  constexpr int R1 = fft2_r1(N), R2 = fft2_r2(N);
+// load(j, n) gives input n = tl + R2 j of thread tl < R2; mid() runs on
+// every thread once phase 1 has taken its inputs (a caller can issue the
+// next line's loads there).  Phase 2 hands thread k1 its whole row u[k2]
+// (output index k1 + R1 k2).  The exchange rows are R2 + 1 apart so that
+// phase 2's strided reads fall in distinct LDS banks; s holds R1 (R2 + 1)
+// elements.
+template <int N, int S, typename C, typename LoadF, typename MidF, typename RowF>
+__device__ __forceinline__ void fft2_line_wave(C* s, int tl, const C* __restrict__ tw, LoadF&& load, MidF&& mid,
+                                               RowF&& row) {
+  constexpr int R1 = fft2_r1(N), R2 = fft2_r2(N), RP = R2 + 1;
   static_assert(64 % fft2_threads(N) == 0, "line must fit in one wavefront");
+  C v[R1];
   if (tl < R2) {
-    C v[R1];
 #pragma unroll
-    for (int j = 0; j < R1; ++j) v[j] = load(tl + R2 * j);
+    for (int j = 0; j < R1; ++j) v[j] = load(j, tl + R2 * j);
+  }
+  mid();
+  if (tl < R2) {
     dft<R1, S>(v);
 #pragma unroll
     for (int k1 = 1; k1 < R1; ++k1) {
@@ -250,7 +259,7 @@ __device__ __forceinline__ void fft2_line_wave(C* s, int tl, const C* __restrict
       v[k1] = (S < 0) ? cmul(v[k1], w) : cmulc(v[k1], w);
     }
 #pragma unroll
-    for (int k1 = 0; k1 < R1; ++k1) s[k1 * R2 + tl] = v[k1];
+    for (int k1 = 0; k1 < R1; ++k1) s[k1 * RP + tl] = v[k1];
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -258,7 +267,7 @@ __device__ __forceinline__ void fft2_line_wave(C* s, int tl, const C* __restrict
   if (tl < R1) {
     C u[R2];
 #pragma unroll
-    for (int t = 0; t < R2; ++t) u[t] = s[tl * R2 + t];
+    for (int t = 0; t < R2; ++t) u[t] = s[tl * RP + t];
     dft<R2, S>(u);
     row(tl, u);
   }
