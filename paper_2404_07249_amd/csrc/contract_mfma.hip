@@ -248,6 +248,21 @@ __device__ __forceinline__ void reduce_group(float* red, const f32x4_t (&acc)[NT
     }
 }
 
+// Single-wave groups: the wave's tiles go straight from its accumulators to
+// the chunk's partial vector (the same layout reduce_group builds), and the
+// accumulators restart at zero.
+template <int NQ, int K0, int K1, int G, int NTMAX>
+__device__ __forceinline__ void flush_group(float* __restrict__ dst, f32x4_t (&acc)[NTMAX], int i, int grp) {
+  using R = GroupRange<NQ, K0, K1, G>;
+  float* r = dst + R::t0 * 256;
+#pragma unroll
+  for (int t = 0; t < R::nt; ++t) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r[t * 256 + (4 * grp + q) * 16 + i] = acc[t][q];
+    acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  }
+}
+
 template <int NQ, int K0, int K1> constexpr int max_group_tiles() {
   int m = GroupRange<NQ, K0, K1, 0>::nt;
   m = GroupRange<NQ, K0, K1, 1>::nt > m ? GroupRange<NQ, K0, K1, 1>::nt : m;
@@ -589,7 +604,8 @@ __global__ void __launch_bounds__(fused_threads(MIXED)) k_zcontract(const float2
                                                              const BinGeom* __restrict__ geom, int nb,
                                                              const float2* __restrict__ tw, float scale, long lpw,
                                                              float* __restrict__ part, int part_len, unsigned sel_lo,
-                                                             unsigned sel_hi, size_t wstride, long nlines) {
+                                                             unsigned sel_hi, size_t wstride, long nlines, int cpw,
+                                                             int n_chunks) {
   a2 = job_ptr(a2, wstride);
   part = job_ptr(part, wstride);
   constexpr int K0 = 0, K1 = n_pair_blocks(NQ);
@@ -616,12 +632,17 @@ __global__ void __launch_bounds__(fused_threads(MIXED)) k_zcontract(const float2
   for (int e = tid; e < 2 * STAGE_BYTES / 4; e += NTHR) reinterpret_cast<float*>(smem)[e] = 0.f;
   for (int e = tid; e < M; e += NTHR) tws[e] = tw[e];
   __syncthreads();
-  const long l0 = (long)blockIdx.x * lpw;
-  long l1 = l0 + lpw;
+  // chunks [c0, c0 + cc) of lpw lines each, one partial vector per chunk
+  // (several chunks per work-group only with single-wave groups)
+  const int c0 = blockIdx.x * cpw;
+  const int cc = n_chunks - c0 < cpw ? n_chunks - c0 : cpw;
+  const long l0 = (long)c0 * lpw;
+  long l1 = (long)(c0 + cc) * lpw;
   if (l1 > nlines) l1 = nlines;
   const int n = l1 > l0 ? (int)(l1 - l0) : 0;
+  constexpr int TAIL = FW == 1 ? 0 : FW;  // barriers of the LDS sum of a group's waves
   // Producer and consumer waves run separate loops, so that neither holds
-  // the other's registers, with the same barrier count (1 + n + FW).
+  // the other's registers, with the same barrier count (1 + n + TAIL).
   if (producer) {
     const int pslot = (tid - NCON) / TL, ptl = (tid - NCON) % TL;
     PairSrc<M> ps;
@@ -641,7 +662,7 @@ __global__ void __launch_bounds__(fused_threads(MIXED)) k_zcontract(const float2
       }
       __syncthreads();
     }
-    for (int w = 0; w < FW; ++w) __syncthreads();
+    for (int w = 0; w < TAIL; ++w) __syncthreads();
   } else {
     const int gi = wave / FW, wig = wave % FW;
     const int i = lane & 15, grp = lane >> 4;
@@ -649,18 +670,34 @@ __global__ void __launch_bounds__(fused_threads(MIXED)) k_zcontract(const float2
 #pragma unroll
     for (int t = 0; t < NTMAX; ++t) acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
     __syncthreads();
-    for (int m = 0; m < n; ++m) {
-      const LineStage<NQ, M>& cur = stage[m & 1];
-      switch (gi) {
-        case 0: contract_line_group<NQ, MIXED, K0, K1, 0, M>(cur, i, grp, wig, acc, sel); break;
-        case 1: contract_line_group<NQ, MIXED, K0, K1, 1, M>(cur, i, grp, wig, acc, sel); break;
-        case 2: contract_line_group<NQ, MIXED, K0, K1, 2, M>(cur, i, grp, wig, acc, sel); break;
-        default: contract_line_group<NQ, MIXED, K0, K1, 3, M>(cur, i, grp, wig, acc, sel); break;
+    int gm = 0;  // line index within the work-group (stage parity)
+    for (int c = 0; c < cc; ++c) {
+      const long cl0 = (long)(c0 + c) * lpw;
+      long cl1 = cl0 + lpw;
+      if (cl1 > nlines) cl1 = nlines;
+      const int nc = cl1 > cl0 ? (int)(cl1 - cl0) : 0;
+      for (int m = 0; m < nc; ++m, ++gm) {
+        const LineStage<NQ, M>& cur = stage[gm & 1];
+        switch (gi) {
+          case 0: contract_line_group<NQ, MIXED, K0, K1, 0, M>(cur, i, grp, wig, acc, sel); break;
+          case 1: contract_line_group<NQ, MIXED, K0, K1, 1, M>(cur, i, grp, wig, acc, sel); break;
+          case 2: contract_line_group<NQ, MIXED, K0, K1, 2, M>(cur, i, grp, wig, acc, sel); break;
+          default: contract_line_group<NQ, MIXED, K0, K1, 3, M>(cur, i, grp, wig, acc, sel); break;
+        }
+        __syncthreads();
       }
-      __syncthreads();
+      if constexpr (FW == 1) {
+        float* dst = part + (size_t)(c0 + c) * part_len;
+        switch (gi) {
+          case 0: flush_group<NQ, K0, K1, 0>(dst, acc, i, grp); break;
+          case 1: flush_group<NQ, K0, K1, 1>(dst, acc, i, grp); break;
+          case 2: flush_group<NQ, K0, K1, 2>(dst, acc, i, grp); break;
+          default: flush_group<NQ, K0, K1, 3>(dst, acc, i, grp); break;
+        }
+      }
     }
     // fixed-order sum of the waves of each group in LDS (reuses the stages)
-    for (int w = 0; w < FW; ++w) {
+    for (int w = 0; w < TAIL; ++w) {
       if (wig == w) {
         switch (gi) {
           case 0: reduce_group<NQ, K0, K1, 0>(red, acc, w, i, grp); break;
@@ -672,8 +709,10 @@ __global__ void __launch_bounds__(fused_threads(MIXED)) k_zcontract(const float2
       __syncthreads();
     }
   }
-  float* dst = part + (size_t)blockIdx.x * part_len;
-  for (int e = tid; e < NT * 256; e += NTHR) dst[e] = red[e];
+  if constexpr (FW > 1) {
+    float* dst = part + (size_t)c0 * part_len;
+    for (int e = tid; e < NT * 256; e += NTHR) dst[e] = red[e];
+  }
 }
 
 template <int NQ, bool MIXED, int M>
@@ -682,9 +721,16 @@ static hipError_t launch_fused_m(const pb3_plan& p, const Exec& x, hipStream_t s
   const long lpw = (nlines + p.contract_wgs - 1) / p.contract_wgs;
   const unsigned sel_lo = 0x0000BF80u, sel_hi = 0xBF800000u;
   const float scale = (float)(1.0 / ((double)p.Mx * p.My * p.Mz));
-  hipLaunchKernelGGL((k_zcontract<NQ, MIXED, M>), dim3(p.contract_wgs, 1, x.n_jobs), dim3(fused_threads(MIXED)), 0, s,
+  // With single-wave groups a work-group takes up to 4 consecutive chunks
+  // (one start-up per CU instead of one per chunk) while the grid still
+  // covers every CU; the partial vectors are the same.
+  int cpw = 1;
+  if (fused_waves(MIXED) == 1 && p.n_cu > 0)
+    while (cpw < 4 && p.contract_wgs % (2 * cpw) == 0 && p.contract_wgs / (2 * cpw) >= p.n_cu) cpw *= 2;
+  const int n_wg = (p.contract_wgs + cpw - 1) / cpw;
+  hipLaunchKernelGGL((k_zcontract<NQ, MIXED, M>), dim3(n_wg, 1, x.n_jobs), dim3(fused_threads(MIXED)), 0, s,
                      x.ws.a2, p.d.geom, p.nb, p.d.tw_m[2], scale, lpw, x.ws.part, p.part_len, sel_lo, sel_hi,
-                     x.wstride, nlines);
+                     x.wstride, nlines, cpw, p.contract_wgs);
   return hipGetLastError();
 }
 

@@ -640,6 +640,7 @@ static pb3_status build_device(pb3_plan* p) {
   int n_cu = 0;
   e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, p->device_id);
   if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+  p->n_cu = n_cu;
   p->contract_wgs = p->fused ? fused_grid(p->nb_pad / 16, p->Mz, (long)mpix(*p), n_cu) : mfma_grid(p->nb_pad / 16, n_cu);
   DeviceTables& d = p->d;
   if ((st = upload(&d.bin3, p->bin3.data(), p->bin3.size())) != PB3_OK) return st;

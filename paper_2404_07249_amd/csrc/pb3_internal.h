@@ -162,8 +162,9 @@ struct pb3_plan {
   std::vector<int32_t> chunk_first;
   pb3::TileSet tx{}, ty{}, tz{};   // FP32 inverse-pass tiles (device)
   // contraction
-  int contract_wgs = 0;
+  int contract_wgs = 0;        // partial vectors (accumulation chunks) of the contraction
   int part_len = 0;            // floats per work-group partial vector (MFMA tiles * 256)
+  int n_cu = 0;                // compute units of the plan's device
   pb3_precision last_prec = PB3_FP32;
   bool device = false;
   int device_id = 0;
