@@ -45,13 +45,13 @@ FP32_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 MEASURED_TRAFFIC = {
     ("contract", "mixed"): {
         "kernel": "k_zcontract<2, true, 192>",
-        "contract_wgs": 1024,  # partial-vector writes scale with the work-group count
-        "fetch_kib": 139900.7, "write_kib": 44032.0, "fetch_factor": 2.0, "write_factor": 1.0,
+        "contract_wgs": 1024,  # partial-vector writes scale with the accumulation-chunk count
+        "fetch_kib": 138472.3, "write_kib": 44032.0, "fetch_factor": 2.0, "write_factor": 1.0,
         "sources": {
             "paper_2404_07249_amd/csrc/contract_mfma.hip":
-                "c969e833078222d878ea9a21a69fbbf4a13314247a714c502d16debb415280c6",
+                "fee7d5b48fd53aa82ce5479b1d64583e379c61770c9570a556f304e8631303df",
             "paper_2404_07249_amd/csrc/fft_dev.h":
-                "445483e27faf3491134cb99e4822494520ab3d6b22f80871c30bdb01f5151c73",
+                "1a6048a01650ed48e8e213de4c409daa938b10ac9a8b67f686e1d7b785d53a88",
             "paper_2404_07249_amd/csrc/job.h":
                 "0f3d39c847bc50252698d89b0082866e4ca72f6f435cacd590aacb25667591d2",
         },
