@@ -45,6 +45,13 @@ Parity status of each function (what pins it is in ``tests/test_oracle.py``):
                            grids (cubic and anisotropic boxes); P of Gaussian
                            fields and the tree-level B of quadratic fields on
                            an anisotropic box average to their expectations.
+* ``bk_fisher`` (bispectrum multipoles with the discrete ideal Fisher matrix
+                           and the degeneracy factors) pinned: the separable
+                           Fisher blocks, N_l and numerators equal explicit
+                           loops over closed triangles in every degeneracy
+                           case; l_max = 0 gives the monopole estimator; on
+                           an alias-free grid the blocks approach the
+                           continuum diagonal form.
 """
 
 from .polyspec import (  # noqa: F401
@@ -74,3 +81,4 @@ from . import multipoles  # noqa: F401,E402
 from . import weighted  # noqa: F401,E402
 from . import injection  # noqa: F401,E402
 from . import noncubic  # noqa: F401,E402
+from . import bk_fisher  # noqa: F401,E402

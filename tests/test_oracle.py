@@ -898,3 +898,63 @@ def test_weighted_noncubic_grid_deconvolves_per_axis():
         trips, B, _, _ = wt.weighted_bispectrum(dw, box, edges, order, const)
         assert np.array_equal(trips, res.triplets)
         assert np.allclose(B, res.bk, rtol=1e-8, atol=1e-10 * np.abs(res.bk).max())
+
+
+# --------------------------------------------- bispectrum multipole Fisher
+def test_bk_fisher_separable_sums_equal_triangle_loops():
+    """The separable forms of the discrete ideal Fisher blocks (eq.
+    bk-fish-ideal), of N_l (eq. N-ell-def, through the tensor expansion of
+    (u2 . u3)^p) and of the numerators (eq. bk-num-ideal) equal explicit
+    loops over the closed triangles, in all four bin-degeneracy cases
+    (a < b < c, a = b < c, a < b = c, a = b = c), for l, l' <= 4."""
+    from oracle import bk_fisher as bf
+
+    n, box, edges = 8, 500.0, np.array([1.0, 2.0, 3.0, 4.0])
+    trips, Ft, Delta, T, Nl = bf.fisher_blocks(n, edges, 4)
+    assert sorted({bf._case(*t) for t in trips}) == [0, 1, 2, 3]
+    Fb, Nb, Tb = bf.brute_blocks(n, edges, trips, 4)
+    assert np.array_equal(T, Tb)
+    assert np.abs(Ft - Fb).max() <= 1e-12 * np.abs(Fb).max()
+    assert np.abs(Nl - Nb).max() <= 1e-12 * np.abs(Nb).max()
+    assert all(np.abs(F - F.T).max() <= 1e-12 * np.abs(F).max() for F in Ft)  # symmetric blocks
+    d = quadratic_field(n, box, 1.0, 3)
+    nt = bf.numerators(d, box, edges, trips, 4)
+    nb = bf.brute_numerators(d, box, edges, trips, 4)
+    assert np.abs(nt - nb).max() <= 1e-12 * np.abs(nb).max()
+    # Delta of eq. (Delta-alpha-def) in each case
+    for t, (a, b, c) in enumerate(trips):
+        r = Nl[t] / T[t]
+        want = {0: np.ones(3), 1: 2 * np.ones(3), 2: 1 + r, 3: 2 * (1 + 2 * r)}[bf._case(a, b, c)]
+        assert np.allclose(Delta[t], want, rtol=0, atol=1e-14)
+
+
+def test_bk_fisher_limits():
+    """l_max = 0 gives the monopole estimator exactly (Delta and the
+    permutation factor cancel); the per-triplet mixing R y of the eq.
+    (ideal-bk) multipoles equals Delta Ft^+ nt; on an alias-free grid the
+    blocks approach the continuum form diag(Delta_l T / (2l+1)) of eq.
+    (bk-fish-ideal2)."""
+    from oracle import bk_fisher as bf
+    from oracle import multipoles as mp
+
+    d = quadratic_field(16, 600.0, 1.0, 5)
+    e = np.array([1.0, 3.0, 5.0, 7.0])
+    tr0, b0 = bf.bispectrum_multipoles_fisher(d, 600.0, e, 0)
+    ref = oracle.bispectrum(d, 600.0, e)
+    assert np.array_equal(tr0, ref.triplets)
+    assert np.abs(b0[0] - ref.bk).max() <= 1e-12 * np.abs(ref.bk).max()
+    tr, b = bf.bispectrum_multipoles_fisher(d, 600.0, e, 4)
+    _, y = mp.bispectrum_multipoles(d, 600.0, e, 4)
+    trips, Ft, Delta, T, _ = bf.fisher_blocks(16, e, 4)
+    R = bf.mixing(Ft, Delta, T, 4)
+    by = np.einsum("tij,jt->it", R, y)
+    assert np.abs(by - b).max() <= 1e-12 * np.abs(b).max()
+    # continuum: 48^3, bins up to 13 k_f (3 x 12 < 48, no aliased closures)
+    trips, Ft, Delta, T, _ = bf.fisher_blocks(48, np.array([4.0, 7.0, 10.0, 13.0]), 4)
+    ells = np.array([0, 2, 4])
+    for t in range(len(trips)):
+        s = np.sqrt(Delta[t] * T[t] / (2 * ells + 1))
+        M = Ft[t] / np.outer(s, s)
+        assert np.abs(np.diag(M) - 1).max() < 0.08
+        assert np.abs(M - np.diag(np.diag(M))).max() < 0.05
+        assert M[0, 0] == pytest.approx(1.0, abs=1e-12)
