@@ -77,6 +77,8 @@ typedef enum {
                                        bin thresholds).  Overrides PB3_FLAG_NO_FUSION. */
 #define PB3_FLAG_LMAX2        0x200u /* multipoles up to l = 2 (pb3_multipoles) */
 #define PB3_FLAG_LMAX4        0x400u /* multipoles up to l = 4 (pb3_multipoles) */
+#define PB3_FLAG_BK_FISHER    0x800u /* with PB3_FLAG_LMAX2/4: bispectrum multipoles normalised by
+                                        the discrete ideal Fisher matrix (see pb3_multipoles) */
 #define PB3_FLAG_POWER_ONLY   0x100u /* power spectra only (pb3_power, pb3_masked_power): no
                                         triplets, no triangle counts, no contraction buffers;
                                         pb3_bispectrum and batches refuse such a plan */
@@ -252,6 +254,15 @@ pb3_status pb3_plan_set_weights(pb3_plan* plan, int window_order, const double* 
  *               g_{c,l} = IDFT[Theta_c L_l(mu) D]  -- eq. (ideal-bk), the Legendre weight on
  *               k_3 (the mode in the largest bin), evaluated through the separable
  *               form of Sec. IV.D.1 (l = 0 is pb3_bispectrum's B).
+ *   With PB3_FLAG_BK_FISHER the bispectrum multipoles are instead
+ *   b = F^-1 b^num with the discrete ideal Fisher matrix of eq. (bk-fish-ideal)
+ *   and the degeneracy factors Delta of eq. (Delta-alpha-def) (N_l of eq.
+ *   (N-ell-def) summed on the grid): per kept triplet an n_ell x n_ell block,
+ *   applied as b = R B above, R = Delta Ft^+ diag(T / (2l+1)), Ft the block
+ *   without its 1/(Delta Delta') and Ft^+ its pseudo-inverse (eigenvalues
+ *   below 1e-12 of the largest dropped).  The blocks are summed in FP64 at
+ *   plan creation (weighted unit fields on the contraction grid).  Such plans
+ *   need equal box sides and refuse pb3_plan_set_weights.
  * pb3_n_ell gives the number of multipoles (lmax/2 + 1).  pk_dev: n_ell x n_bins
  * float64 (row l/2), bk_dev: n_ell x n_trip float64; either may be NULL (not
  * both).  prec: PB3_MIXED_BF16X3 runs the contraction on the matrix cores
@@ -262,6 +273,10 @@ pb3_status pb3_plan_set_weights(pb3_plan* plan, int window_order, const double* 
  * plan asked for B; at creation: a bin whose modes cannot separate the
  * multipoles), PB3_ENOMEM (workspace too small), PB3_EDEVICE. */
 int pb3_n_ell(const pb3_plan* plan);
+/* The per-triplet mixing blocks R of a PB3_FLAG_BK_FISHER plan, host copy:
+ * mix_out holds n_trip x n_ell x n_ell doubles (row l/2, column l'/2).
+ * Errors: PB3_EINVAL (null arguments, plan without the flag). */
+pb3_status pb3_multipole_mixing(const pb3_plan* plan, double* mix_out);
 size_t pb3_multipoles_workspace_bytes(const pb3_plan* plan);
 pb3_status pb3_multipoles(pb3_plan* plan, const float* delta_dev, double* pk_dev, double* bk_dev,
                           pb3_precision prec, void* workspace_dev, size_t workspace_bytes, void* stream);

@@ -35,6 +35,12 @@ Separable forms (Sec. IV.D.1): for even weights f, g, h,
 sum f(n1) g(n2) h(n3) over closed triangles = N_pix^2 sum_x F G H with
 F = IDFT[Theta_a f] etc.; N_l goes through the tensor expansion
 (u . v)^p = sum_{|alpha| = p} p!/alpha! u^alpha v^alpha.
+
+Reading (the paper is silent on it): a mode with a Nyquist component
+(|n_i| = N/2) has two representatives, +N/2 and -N/2, whose directions
+differ; in N_l such a mode takes the average over its representatives, so
+odd powers of a Nyquist component vanish.  (mu^2 and the Legendre weights
+do not depend on the choice.)
 """
 
 from __future__ import annotations
@@ -111,8 +117,13 @@ def fisher_blocks(n: int, edges, lmax: int):
         if p > 2 * (lmax // 2) and p > 2:
             break
         acc = np.zeros(len(trips))
+        nyq = np.abs(np.stack(np.broadcast_arrays(*(freqs(n)[ix] for ix in (
+            np.s_[:, None, None], np.s_[None, :, None], np.s_[None, None, :]))))) == n // 2
         for al in _multi_indices(p):
             w = u[0] ** al[0] * u[1] ** al[1] * u[2] ** al[2]
+            for ax in range(3):  # odd power of a Nyquist component: average of +-N/2 is zero
+                if al[ax] % 2:
+                    w = np.where(nyq[ax], 0.0, w)
             Hw = _weighted_unit_fields(n, edges, w)
             coef = math.factorial(p) / (math.factorial(al[0]) * math.factorial(al[1]) * math.factorial(al[2]))
             acc += coef * tri(H, Hw, Hw)
@@ -187,6 +198,13 @@ def bispectrum_multipoles_fisher(delta: np.ndarray, box: float, edges, lmax: int
     return trips, b
 
 
+def _representatives(k: np.ndarray, n: int):
+    """The integer vectors that represent mode k: each Nyquist component
+    (|k_i| = N/2) as +N/2 and as -N/2."""
+    opts = [(c, -c) if abs(c) == n // 2 else (c,) for c in k]
+    return [np.array(v, dtype=np.float64) for v in itertools.product(*opts)]
+
+
 def brute_blocks(n: int, edges, trips, lmax: int):
     """Ft, Delta-free N_l and T by explicit loops over closed triangles
     (small grids only): (Ft [nt, ne, ne], Nl [nt, ne], T [nt])."""
@@ -214,10 +232,15 @@ def brute_blocks(n: int, edges, trips, lmax: int):
                 k1, k2, k3 = vec(i1), vec(i2), vec(i3)
                 r1, r2, r3 = (np.sqrt(k @ k) for k in (k1, k2, k3))
                 m1, m2, m3 = k1[2] / r1, k2[2] / r2, k3[2] / r3
-                c23 = (k2 @ k3) / (r2 * r3)
                 T[t] += 1.0
+                # N_l: average over the representatives +-N/2 of Nyquist components
+                v2s, v3s = _representatives(k2, n), _representatives(k3, n)
                 for i, l in enumerate(ells):
-                    Nl[t, i] += legendre(l, c23)
+                    acc = 0.0
+                    for v2 in v2s:
+                        for v3 in v3s:
+                            acc += legendre(l, (v2 @ v3) / (r2 * r3))
+                    Nl[t, i] += acc / (len(v2s) * len(v3s))
                     for j, lp in enumerate(ells):
                         L3 = legendre(l, m3)
                         if case == 0:

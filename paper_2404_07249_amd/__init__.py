@@ -59,6 +59,7 @@ class Plan:
         autotune: bool = False,
         power_only: bool = False,
         lmax: int = 0,
+        bk_fisher: bool = False,
     ):
         lib = _lib.load()
         self._lib = lib
@@ -81,6 +82,7 @@ class Plan:
         if lmax not in (0, 2, 4):
             raise ValueError("lmax must be 0, 2 or 4")
         flags |= {0: 0, 2: _lib.FLAG_LMAX2, 4: _lib.FLAG_LMAX4}[lmax]
+        flags |= _lib.FLAG_BK_FISHER if bk_fisher else 0
         h = C.c_void_p()
         _lib.check(
             lib.pb3_plan_create(g, b, e.ctypes.data_as(C.POINTER(C.c_double)), int(e.size), flags, C.byref(h))
@@ -301,6 +303,15 @@ class Plan:
     @property
     def n_ell(self) -> int:
         return int(self._lib.pb3_n_ell(self._h))
+
+    def multipole_mixing(self) -> np.ndarray:
+        """Per-triplet blocks R [n_trip, n_ell, n_ell] that map the eq.
+        (ideal-bk) multipoles to the Fisher-normalised ones (plans made with
+        ``bk_fisher=True``)."""
+        ne, nt = self.n_ell, self.n_triplets
+        out = np.zeros((nt, ne, ne), dtype=np.float64)
+        _lib.check(self._lib.pb3_multipole_mixing(self._h, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
 
     def multipoles(self, delta, power: bool = True, bispectrum: bool = True, precision: str = "mixed",
                    workspace=None, stream=None):

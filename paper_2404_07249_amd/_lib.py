@@ -22,6 +22,7 @@ FLAG_AUTOTUNE = 0x80
 FLAG_POWER_ONLY = 0x100
 FLAG_LMAX2 = 0x200
 FLAG_LMAX4 = 0x400
+FLAG_BK_FISHER = 0x800
 BATCH_GRAPH = 0x1
 WINDOW_SCRATCH = 514
 BATCH_EXT_WORKSPACE = 0x2
@@ -58,6 +59,7 @@ SIGNATURES = [
      [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p), C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
       C.c_size_t, C.c_void_p]),
     ("pb3_n_ell", C.c_int, [C.c_void_p]),
+    ("pb3_multipole_mixing", C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     ("pb3_weights_table_len", C.c_int, [C.c_void_p]),
     ("pb3_plan_set_weights", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_double]),
     ("pb3_multipoles_workspace_bytes", C.c_size_t, [C.c_void_p]),

@@ -140,6 +140,20 @@ __global__ void __launch_bounds__(512) k_fwd_col2(const float2* __restrict__ in,
 struct WinOff {
   int x, y, z;  // offsets of k = 0 of each axis in the window table
 };
+
+__device__ __forceinline__ double legendre_m2(int l, double m2) {
+  switch (l) {
+    case 2: return 1.5 * m2 - 0.5;
+    case 4: return (35.0 * m2 * m2 - 30.0 * m2 + 3.0) * 0.125;
+    default: return 1.0;
+  }
+}
+__device__ __forceinline__ double ipow(double x, int e) {
+  double r = 1.0;
+  for (int i = 0; i < e; ++i) r *= x;
+  return r;
+}
+
 template <int M, typename Rl, bool UNIT>
 __global__ void __launch_bounds__(512) k_inv_x2(const float2* __restrict__ dc, typename Cx<Rl>::type* __restrict__ a1,
                                                 const BinGeom* __restrict__ geom, const BinTile* __restrict__ tiles,
@@ -148,7 +162,7 @@ __global__ void __launch_bounds__(512) k_inv_x2(const float2* __restrict__ dc, t
                                                 const typename Cx<Rl>::type* __restrict__ tw, size_t wstride,
                                                 int ell, const float* __restrict__ winv, WinOff wo, float sx,
                                                 float sy, const float* __restrict__ pinv,
-                                                const double* __restrict__ uw) {
+                                                const double* __restrict__ uw, AngW aw) {
   dc = job_ptr(dc, wstride);
   a1 = job_ptr(a1, wstride);
   using C = typename Cx<Rl>::type;
@@ -180,7 +194,18 @@ __global__ void __launch_bounds__(512) k_inv_x2(const float2* __restrict__ dc, t
           const size_t ci = kx != 0x40000000 ? ((size_t)(kx + Kcx) * Lcy + (ky + Kcy)) * Kz + kz : 0;
           if (live && kx != 0x40000000 && bin3[ci] == b) {
             if constexpr (UNIT) {
-              v = cx<C>(Rl(uw ? uw[kx * kx + ky * ky + kz * kz] : 1.0), Rl(0));  // 1 / P_fid in the weighted count
+              double w = uw ? uw[kx * kx + ky * ky + kz * kz] : 1.0;  // 1 / P_fid in the weighted count
+              if (aw.l1 | aw.l2 | aw.ex | aw.ey | aw.ez) {
+                // physical wave-vector in units of k_f,z (exact integers for equal box sides)
+                const double fx = sqrt((double)sx) * kx, fy = sqrt((double)sy) * ky, fz = (double)kz;
+                const double k2 = fx * fx + fy * fy + fz * fz, r = sqrt(k2);
+                w *= legendre_m2(aw.l1, fz * fz / k2) * legendre_m2(aw.l2, fz * fz / k2);
+                w *= ipow(fx / r, aw.ex) * ipow(fy / r, aw.ey) * ipow(fz / r, aw.ez);
+                if (((aw.ex & 1) && abs(kx) == aw.hx) || ((aw.ey & 1) && abs(ky) == aw.hy) ||
+                    ((aw.ez & 1) && kz == aw.hz))
+                  w = 0.0;
+              }
+              v = cx<C>(Rl(w), Rl(0));
             } else {
               float2 d = dc[ci];
               if (winv || pinv) {  // weighted estimator: D / (m P_fid)
@@ -374,7 +399,8 @@ hipError_t launch_fwd_x(const pb3_plan& p, const Exec& x, hipStream_t s) {
 }
 
 hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, const float2* dc, void* a1, const TileSet& ts,
-                     int n_jobs, size_t wstride, hipStream_t s, int ell, const double* unit_w, bool weighted) {
+                     int n_jobs, size_t wstride, hipStream_t s, int ell, const double* unit_w, bool weighted,
+                     AngW aw) {
   const float* winv = weighted ? p.d.win_inv : nullptr;
   const float* pinv = weighted ? p.d.pfid_inv : nullptr;
   const WinOff wo{p.Nx / 2, p.Nx + 1 + p.Ny / 2, p.Nx + p.Ny + 2 + p.Nz / 2};
@@ -387,7 +413,7 @@ hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, const float2* dc, v
       if (unit)
         hipLaunchKernelGGL((k_inv_x2<LL, double, true>), dim3(xcd_tiles(ts.n), 1, n_jobs), dim3(S::NT), 0, s, dc,
                            (double2*)a1, p.d.geom, ts.d, ts.n, p.d.bin3, p.Kcx, p.Kcy, p.Lcy, p.Kz, (const double2*)tw,
-                           wstride, 0, (const float*)nullptr, wo, sx, sy, (const float*)nullptr, unit_w);
+                           wstride, 0, (const float*)nullptr, wo, sx, sy, (const float*)nullptr, unit_w, aw);
       else
         return hipErrorInvalidValue;
     } else {
@@ -395,7 +421,7 @@ hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, const float2* dc, v
       if (unit) return hipErrorInvalidValue;
       hipLaunchKernelGGL((k_inv_x2<LL, float, false>), dim3(xcd_tiles(ts.n), 1, n_jobs), dim3(S::NT), 0, s, dc,
                          (float2*)a1, p.d.geom, ts.d, ts.n, p.d.bin3, p.Kcx, p.Kcy, p.Lcy, p.Kz, (const float2*)tw,
-                         wstride, ell, winv, wo, sx, sy, pinv, (const double*)nullptr);
+                         wstride, ell, winv, wo, sx, sy, pinv, (const double*)nullptr, AngW{});
     }
     return hipGetLastError();
   });

@@ -118,7 +118,7 @@ static void free_device(pb3_plan* p) {
                   d.out_map,   d.inv_counts, d.pk_scale,  d.tw_n[0],     d.tw_n[1],   d.tw_n[2],   d.tw_m[0],
                   d.tw_m[1],   d.tw_m[2],    d.tw_m_d[0], d.tw_m_d[1],   d.tw_m_d[2], d.nmodes_d,  d.pml_inv,
                   d.ml_trips,  d.ml_fac,     d.ml_map,    d.win_inv,     d.pfid_inv,  d.pfid_inv_d, d.mode_w,
-                  d.bk_bias};
+                  d.bk_bias,   d.bk_mix};
   for (void* q : ptrs)
     if (q) hipFree(q);
   d = DeviceTables{};
@@ -170,6 +170,16 @@ static pb3_status build_host(pb3_plan* p, const int grid[3], const double box[3]
   if (p->aniso && !(flags & PB3_FLAG_EDGES_HMPC)) {
     set_error("a box with unequal sides needs bin edges in h/Mpc (PB3_FLAG_EDGES_HMPC)");
     return PB3_EINVAL;
+  }
+  if (flags & PB3_FLAG_BK_FISHER) {
+    if (!(flags & (PB3_FLAG_LMAX2 | PB3_FLAG_LMAX4)) || (flags & PB3_FLAG_POWER_ONLY)) {
+      set_error("PB3_FLAG_BK_FISHER needs bispectrum multipoles (PB3_FLAG_LMAX2 or PB3_FLAG_LMAX4, not power-only)");
+      return PB3_EINVAL;
+    }
+    if (p->aniso) {
+      set_error("the bispectrum multipole Fisher matrix is implemented for boxes with equal sides");
+      return PB3_EUNSUPPORTED;
+    }
   }
   for (int a = 0; a < 3; ++a) {
     const double kf = 2.0 * M_PI / box[a];
@@ -727,6 +737,10 @@ static pb3_status build_device(pb3_plan* p) {
     if ((st = upload(&d.ml_trips, mt.data(), mt.size())) != PB3_OK) return st;
     if ((st = upload(&d.ml_fac, mf.data(), mf.size())) != PB3_OK) return st;
     if ((st = upload(&d.ml_map, mm.data(), mm.size())) != PB3_OK) return st;
+    if (p->flags & PB3_FLAG_BK_FISHER) {
+      if ((st = compute_bk_mixing(*p, p->bk_mix)) != PB3_OK) return st;
+      if ((st = upload(&d.bk_mix, p->bk_mix.data(), p->bk_mix.size())) != PB3_OK) return st;
+    }
   }
   if (p->flags & PB3_FLAG_STAGE_TIMING) {
     p->ev.assign((size_t)pb3_plan::kTimingRing * ST_COUNT * 2, nullptr);
@@ -1123,6 +1137,19 @@ pb3_status pb3_masked_power(pb3_plan* plan, const float* data_dev, const float* 
 
 int pb3_n_ell(const pb3_plan* plan) { return plan ? plan->lmax / 2 + 1 : 0; }
 
+pb3_status pb3_multipole_mixing(const pb3_plan* plan, double* mix_out) {
+  if (!plan || !mix_out) {
+    set_error("null argument");
+    return PB3_EINVAL;
+  }
+  if (!(plan->flags & PB3_FLAG_BK_FISHER) || plan->bk_mix.empty()) {
+    set_error("the plan has no bispectrum multipole Fisher matrix (device plan with PB3_FLAG_BK_FISHER)");
+    return PB3_EINVAL;
+  }
+  std::copy(plan->bk_mix.begin(), plan->bk_mix.end(), mix_out);
+  return PB3_OK;
+}
+
 int pb3_weights_table_len(const pb3_plan* plan) { return (plan && !plan->aniso) ? (int)plan->thr[plan->nb] : 0; }
 
 pb3_status pb3_plan_set_weights(pb3_plan* plan, int window_order, const double* pfid, int n_pfid, double nbar) {
@@ -1137,6 +1164,10 @@ pb3_status pb3_plan_set_weights(pb3_plan* plan, int window_order, const double* 
   }
   if (p->aniso) {
     set_error("weights take P_fid over integer |n|^2: a box with equal sides is needed");
+    return PB3_EUNSUPPORTED;
+  }
+  if (p->flags & PB3_FLAG_BK_FISHER) {
+    set_error("weights are not implemented with the bispectrum multipole Fisher matrix (PB3_FLAG_BK_FISHER)");
     return PB3_EUNSUPPORTED;
   }
   if (window_order < 0 || window_order > 3 || !(nbar >= 0.0)) {

@@ -90,6 +90,7 @@ struct DeviceTables {
   double* pfid_inv_d = nullptr;    // same in FP64 (weighted triangle counts)
   double* mode_w = nullptr;        // per power mode: 1 / (m^2 P_fid^2)
   double* bk_bias = nullptr;       // per kept triplet: shot-noise bispectrum
+  double* bk_mix = nullptr;        // bispectrum multipole Fisher: per kept triplet [n_ell][n_ell] (else null)
 };
 
 struct Workspace {
@@ -146,6 +147,7 @@ struct pb3_plan {
   double pk_shift = 0;         // subtracted from P (shot noise 1 / nbar)
   std::vector<double> pfid;    // P_fid over integer |n|^2 (weighted plans)
   std::vector<double> pml_inv; // per bin inverse discrete Fisher of the power multipoles, x V / N_pix^2
+  std::vector<double> bk_mix;  // bispectrum multipole Fisher mixing per kept triplet [n_ell][n_ell] (or empty)
   int tuned = 0;               // launch shape: 0 default, 1 from the autotune cache, 2 measured
   int lut_len = 0;             // cubic box: bin of |n|^2 for |n|^2 < lut_len
   std::vector<int8_t> lut;
@@ -217,6 +219,7 @@ hipError_t launch_window(long n, const float* w, double* pk, int nb, double* bk,
 // q_out (may be null) receives the shot-noise sums of the weighted estimator
 // sum over closed triangles of 1/(P_2 P_3) + 1/(P_1 P_3) + 1/(P_1 P_2).
 pb3_status compute_counts_fp64(pb3_plan& p, std::vector<double>& counts_out, std::vector<double>* q_out = nullptr);
+pb3_status compute_bk_mixing(pb3_plan& p, std::vector<double>& mix_out);
 // masked power spectrum with the Monte Carlo Fisher matrix (pb3_kernels.hip)
 size_t masked_workspace_bytes(const pb3_plan& p);
 // multipoles (pb3_kernels.hip)
@@ -249,9 +252,17 @@ hipError_t launch_zcontract(const pb3_plan& p, const Exec& x, bool mixed, hipStr
 // weighted: apply the plan's window / P_fid weights (estimator fields);
 // unit_w: per-|n|^2 weight of the unit fields (count pass, may be null)
 // (the FP32 or FP64 twiddles of the axis are the plan's)
+// Angular weight of the FP64 unit fields: L_l1(mu) L_l2(mu) u_x^ex u_y^ey u_z^ez
+// with u = k / |k| and mu = u_z (all zero: no angular weight).  A mode with
+// a Nyquist component (|k_i| = h_i, half the grid) takes the average over its
+// representatives +-h_i, so an odd power of that component gives zero.
+struct AngW {
+  int l1 = 0, l2 = 0, ex = 0, ey = 0, ez = 0;
+  int hx = -1, hy = -1, hz = -1;
+};
 hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, const float2* dc, void* a1, const TileSet& ts,
                      int n_jobs, size_t wstride, hipStream_t s, int ell = 0, const double* unit_w = nullptr,
-                     bool weighted = false);
+                     bool weighted = false, AngW aw = AngW{});
 hipError_t run_inv_y(const pb3_plan& p, bool dbl, const void* a1, void* a2, const TileSet& ts, int n_jobs,
                      size_t wstride, hipStream_t s);
 hipError_t run_inv_z(const pb3_plan& p, bool dbl, const void* a2, void* gout, const TileSet& ts, int n_jobs,

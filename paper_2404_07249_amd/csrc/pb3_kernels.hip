@@ -16,6 +16,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+
 #include "job.h"
 #include "pb3_internal.h"
 
@@ -571,6 +574,8 @@ size_t multipoles_workspace_bytes(const pb3_plan& p) {
          up(sizeof(double) * std::max(p.n_chunks, 1) * ne);
 }
 
+__global__ void k_ml_mix(double* __restrict__ bk, const double* __restrict__ R, int nt, int ne);
+
 pb3_status run_multipoles(pb3_plan& p, const float* delta, double* pk_out, double* bk_out, pb3_precision prec,
                           void* workspace, hipStream_t s) {
   const size_t A = 256, m3 = mpix(p);
@@ -627,17 +632,21 @@ pb3_status run_multipoles(pb3_plan& p, const float* delta, double* pk_out, doubl
                          l == 0 ? (const double*)p.d.bk_bias : nullptr);
       if (!chk(hipGetLastError(), "multipoles: reduce")) return st;
     }
-    return PB3_OK;
+  } else {
+    for (int l = 0; l < ne; ++l) {
+      if (!chk(contract_simple<float>(fields, ne * p.nb, (long)m3, p.d.ml_trips + (size_t)3 * l * nt, nt, kMlWgs,
+                                      part, s),
+               "multipoles: contraction"))
+        return st;
+      hipLaunchKernelGGL((k_reduce<double>), dim3((nt + 255) / 256), dim3(256), 0, s, part, kMlWgs, nt, p.d.ml_map,
+                         p.d.ml_fac + (size_t)l * nt, nt, bk_out + (size_t)l * nt,
+                         l == 0 ? (const double*)p.d.bk_bias : nullptr);
+      if (!chk(hipGetLastError(), "multipoles: reduce")) return st;
+    }
   }
-  for (int l = 0; l < ne; ++l) {
-    if (!chk(contract_simple<float>(fields, ne * p.nb, (long)m3, p.d.ml_trips + (size_t)3 * l * nt, nt, kMlWgs, part,
-                                    s),
-             "multipoles: contraction"))
-      return st;
-    hipLaunchKernelGGL((k_reduce<double>), dim3((nt + 255) / 256), dim3(256), 0, s, part, kMlWgs, nt, p.d.ml_map,
-                       p.d.ml_fac + (size_t)l * nt, nt, bk_out + (size_t)l * nt,
-                       l == 0 ? (const double*)p.d.bk_bias : nullptr);
-    if (!chk(hipGetLastError(), "multipoles: reduce")) return st;
+  if (p.d.bk_mix) {  // the discrete Fisher matrix of the bispectrum multipoles
+    hipLaunchKernelGGL(k_ml_mix, dim3((nt + 255) / 256), dim3(256), 0, s, bk_out, (const double*)p.d.bk_mix, nt, ne);
+    if (!chk(hipGetLastError(), "multipoles: Fisher")) return st;
   }
   return PB3_OK;
 }
@@ -867,6 +876,277 @@ done:
   hipFree(map);
   hipFree(tiles);
   return st;
+}
+
+
+// ------------------------------------- bispectrum multipole Fisher matrix
+// Per kept triplet t = (a, b, c) and l, l' in {0, 2, .., lmax}, sums over
+// the closed triangles n1 + n2 + n3 = 0 (mod M) with n1 in a, n2 in b,
+// n3 in c (mu_i = n_i,z / |n_i|, u_i = n_i / |n_i|):
+// * the discrete ideal Fisher block of eq. (bk-fish-ideal) without its
+//   1 / (Delta_l Delta_l'): Ft_{l l'} = sum L_l(mu_3) P_l' with, from the
+//   permutations of the k's that keep every k_i in its bin,
+//   P_l' = L_l'(mu_3) (a < b < c), 2 L_l'(mu_3) (a = b < c),
+//   L_l'(mu_3) + L_l'(mu_2) (a < b = c), 2 [L_l'(mu_1) + L_l'(mu_2) + L_l'(mu_3)] (a = b = c);
+// * the degeneracy factors of eq. (Delta-alpha-def), Delta_l = 1, 2,
+//   1 + N_l/N_0, 2 (1 + 2 N_l/N_0) in the same cases, N_l = sum L_l(u_2 . u_3)
+//   (eq. N-ell-def on the grid), N_0 = T.
+// Every sum is separable: sum w1(n1) w2(n2) w3(n3) = M^6 sum_x H1_a H2_b H3_c
+// with FP64 unit fields H_b = IDFT[Theta_b w]; N_l goes through
+// (u_2 . u_3)^p = sum_{|alpha| = p} p!/alpha! u_2^alpha u_3^alpha, a mode
+// with a Nyquist component taking the average over its representatives.  Both
+// cross terms of a = b = c equal the (mu_3, mu_2) one (relabel n1 <-> n2).
+// Output per triplet: R = Delta Ft^+ diag(T / (2l'+1)), Ft^+ the
+// pseudo-inverse of the symmetric block (eigenvalues below 1e-12 of the
+// largest dropped), so that b = F^-1 b^num = R y maps the eq. (ideal-bk)
+// multipoles y_l = (2l+1) nt_l / T to the Fisher-normalised ones.
+
+// Eigen-decomposition of a symmetric n x n matrix (n <= 3) by cyclic Jacobi
+// rotations, then the pseudo-inverse.
+static void pinv_sym(int n, const double* F, double* out) {
+  double A[9], V[9];
+  for (int i = 0; i < n * n; ++i) A[i] = 0.5 * (F[i] + F[(i % n) * n + i / n]);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) V[i * n + j] = i == j ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 64; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        tot += A[i * n + j] * A[i * n + j];
+        if (i != j) off += A[i * n + j] * A[i * n + j];
+      }
+    if (off <= 1e-32 * tot) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[p * n + q];
+        if (apq == 0.0) continue;
+        const double th = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < n; ++k) {  // A <- A J
+          const double akp = A[k * n + p], akq = A[k * n + q];
+          A[k * n + p] = c * akp - sn * akq;
+          A[k * n + q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // A <- J^T A
+          const double apk = A[p * n + k], aqk = A[q * n + k];
+          A[p * n + k] = c * apk - sn * aqk;
+          A[q * n + k] = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {  // V <- V J
+          const double vkp = V[k * n + p], vkq = V[k * n + q];
+          V[k * n + p] = c * vkp - sn * vkq;
+          V[k * n + q] = sn * vkp + c * vkq;
+        }
+      }
+  }
+  double big = 0.0;
+  for (int i = 0; i < n; ++i) big = std::max(big, std::fabs(A[i * n + i]));
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < n; ++k) {
+        const double w = A[k * n + k];
+        if (std::fabs(w) > 1e-12 * big) acc += V[i * n + k] * V[j * n + k] / w;
+      }
+      out[i * n + j] = acc;
+    }
+}
+
+pb3_status compute_bk_mixing(pb3_plan& p, std::vector<double>& mix_out) {
+  const int nt = (int)(p.trip.size() / 3), nb = p.nb, ne = p.lmax / 2 + 1;
+  mix_out.assign((size_t)nt * ne * ne, 0.0);
+  if (nt == 0) return PB3_OK;
+  const long mvox = (long)mpix(p);
+  const int nwg = 512;
+  double2 *a1 = nullptr, *a2 = nullptr;
+  double *h = nullptr, *part = nullptr, *out = nullptr;
+  int32_t *map = nullptr, *trips = nullptr;
+  BinTile* tiles = nullptr;
+  TileSet tsx{}, tsy{}, tsz{};
+  hipError_t e;
+  pb3_status st = PB3_OK;
+  double m6 = (double)p.Mx * p.My * p.Mz;
+  m6 *= m6;
+  const int ells[3] = {0, 2, 4};
+  std::vector<double> d33((size_t)ne * ne * nt), x32((size_t)ne * ne * nt), c2(nt, 0.0), c4(nt, 0.0), tmp(nt);
+  auto alloc = [&](void** ptr, size_t bytes) {
+    e = hipMalloc(ptr, bytes);
+    return e == hipSuccess;
+  };
+  // three field sets: unit fields, and two weighted ones
+  auto slot = [&](int k) { return h + (size_t)k * nb * mvox; };
+  auto build = [&](int k, AngW aw) -> pb3_status {
+    hipError_t r = run_inv_x(p, true, true, nullptr, a1, tsx, 1, 0, nullptr, 0, nullptr, false, aw);
+    if (r != hipSuccess) return hip_fail(r, "Fisher inverse x pass");
+    r = run_inv_y(p, true, a1, a2, tsy, 1, 0, nullptr);
+    if (r != hipSuccess) return hip_fail(r, "Fisher inverse y pass");
+    r = run_inv_z(p, true, a2, slot(k), tsz, 1, 0, nullptr);
+    if (r != hipSuccess) return hip_fail(r, "Fisher inverse z pass");
+    return PB3_OK;
+  };
+  // M^6 sum_x H_{sa}[a] H_{sb}[b] H_{sc}[c] for every kept triplet
+  auto sum3 = [&](int sa, int sb, int sc, std::vector<double>& res) -> pb3_status {
+    std::vector<int32_t> tb(3 * (size_t)nt);
+    for (int t = 0; t < nt; ++t) {
+      tb[3 * t] = sa * nb + p.trip[3 * t];
+      tb[3 * t + 1] = sb * nb + p.trip[3 * t + 1];
+      tb[3 * t + 2] = sc * nb + p.trip[3 * t + 2];
+    }
+    hipError_t r = hipMemcpy(trips, tb.data(), sizeof(int32_t) * tb.size(), hipMemcpyHostToDevice);
+    if (r != hipSuccess) return hip_fail(r, "hipMemcpy");
+    r = contract_simple<double>(h, 3 * nb, mvox, trips, nt, nwg, part, nullptr);
+    if (r != hipSuccess) return hip_fail(r, "Fisher contraction");
+    hipLaunchKernelGGL((k_reduce<double>), dim3((nt + 255) / 256), dim3(256), 0, nullptr, part, nwg, nt, map,
+                       (const double*)nullptr, nt, out, (const double*)nullptr);
+    r = hipGetLastError();
+    if (r != hipSuccess) return hip_fail(r, "Fisher reduce");
+    r = hipMemcpy(res.data(), out, sizeof(double) * nt, hipMemcpyDeviceToHost);
+    if (r != hipSuccess) return hip_fail(r, "Fisher copy");
+    for (auto& v : res) v *= m6;
+    return PB3_OK;
+  };
+  std::vector<int32_t> idmap(nt);
+  for (int i = 0; i < nt; ++i) idmap[i] = i;
+  if (!alloc((void**)&a1, sizeof(double2) * p.a1_len) || !alloc((void**)&a2, sizeof(double2) * p.a2_len) ||
+      !alloc((void**)&h, sizeof(double) * 3 * (size_t)nb * mvox) ||
+      !alloc((void**)&trips, sizeof(int32_t) * 3 * (size_t)nt) ||
+      !alloc((void**)&part, sizeof(double) * (size_t)nwg * nt) || !alloc((void**)&out, sizeof(double) * nt) ||
+      !alloc((void**)&map, sizeof(int32_t) * nt)) {
+    st = PB3_ENOMEM;
+    set_error("device allocation failed while computing the bispectrum multipole Fisher matrix");
+    goto done;
+  }
+  e = hipMemcpy(map, idmap.data(), sizeof(int32_t) * nt, hipMemcpyHostToDevice);
+  if (e != hipSuccess) { st = hip_fail(e, "hipMemcpy"); goto done; }
+  {
+    int tbx = tile_width_x(p.Mx, true), tbz = tile_width_z(p.Mz, true);
+    if (tbx <= 0 || tbz <= 0) {
+      st = PB3_EUNSUPPORTED;
+      set_error("contraction grid not implemented");
+      goto done;
+    }
+    std::vector<BinTile> vx, vy, vz;
+    build_tiles(p, tbx, tbz, vx, vy, vz);
+    size_t ntile = vx.size() + vy.size() + vz.size();
+    if (!alloc((void**)&tiles, sizeof(BinTile) * (ntile ? ntile : 1))) {
+      st = PB3_ENOMEM;
+      set_error("device allocation failed while computing the bispectrum multipole Fisher matrix");
+      goto done;
+    }
+    std::vector<BinTile> all(vx);
+    all.insert(all.end(), vy.begin(), vy.end());
+    all.insert(all.end(), vz.begin(), vz.end());
+    e = hipMemcpy(tiles, all.data(), sizeof(BinTile) * ntile, hipMemcpyHostToDevice);
+    if (e != hipSuccess) { st = hip_fail(e, "hipMemcpy"); goto done; }
+    tsx = TileSet{tiles, (int)vx.size(), tbx};
+    tsy = TileSet{tiles + vx.size(), (int)vy.size(), tbx};
+    tsz = TileSet{tiles + vx.size() + vy.size(), (int)vz.size(), tbz};
+  }
+  if ((st = build(0, AngW{})) != PB3_OK) goto done;
+  // Legendre products on the third leg (d33) and the (mu_3, mu_2) cross terms (x32)
+  for (int i = 0; i < ne && st == PB3_OK; ++i)
+    for (int j = i; j < ne && st == PB3_OK; ++j) {
+      double* dij = d33.data() + ((size_t)i * ne + j) * nt;
+      double* xij = x32.data() + ((size_t)i * ne + j) * nt;
+      if (i == 0 && j == 0) {
+        for (int t = 0; t < nt; ++t) dij[t] = xij[t] = p.counts[t];
+        continue;
+      }
+      AngW w;
+      w.l1 = ells[i];
+      w.l2 = ells[j];
+      if ((st = build(1, w)) != PB3_OK) break;
+      if ((st = sum3(0, 0, 1, tmp)) != PB3_OK) break;
+      std::copy(tmp.begin(), tmp.end(), dij);
+      // legs: unit on a, L_l' on b, L_l on c
+      AngW wi, wj;
+      wi.l1 = ells[i];
+      wj.l1 = ells[j];
+      int si = 0, sj;
+      if (i > 0) {
+        if ((st = build(1, wi)) != PB3_OK) break;
+        si = 1;
+      }
+      if (j == i) {
+        sj = si;
+      } else {
+        if ((st = build(2, wj)) != PB3_OK) break;
+        sj = 2;
+      }
+      if ((st = sum3(0, sj, si, tmp)) != PB3_OK) break;
+      std::copy(tmp.begin(), tmp.end(), xij);
+    }
+  if (st != PB3_OK) goto done;
+  // sum (u_2 . u_3)^p for p = 2 (and 4)
+  for (int pw = 2; pw <= (ne > 2 ? 4 : 2) && st == PB3_OK; pw += 2)
+    for (int ex = 0; ex <= pw && st == PB3_OK; ++ex)
+      for (int ey = 0; ex + ey <= pw && st == PB3_OK; ++ey) {
+        const int ez = pw - ex - ey;
+        AngW w;
+        w.ex = ex;
+        w.ey = ey;
+        w.ez = ez;
+        w.hx = p.Mx / 2;
+        w.hy = p.My / 2;
+        w.hz = p.Mz / 2;
+        auto fact = [](int k) {
+          double f = 1.0;
+          for (int i = 2; i <= k; ++i) f *= i;
+          return f;
+        };
+        const double coef = fact(pw) / (fact(ex) * fact(ey) * fact(ez));
+        if ((st = build(1, w)) != PB3_OK) break;
+        if ((st = sum3(0, 1, 1, tmp)) != PB3_OK) break;
+        std::vector<double>& acc = pw == 2 ? c2 : c4;
+        for (int t = 0; t < nt; ++t) acc[t] += coef * tmp[t];
+      }
+  if (st != PB3_OK) goto done;
+  for (int t = 0; t < nt; ++t) {
+    const int a = p.trip[3 * t], b = p.trip[3 * t + 1], c = p.trip[3 * t + 2];
+    const int cs = (a == b && b == c) ? 3 : (a == b) ? 1 : (b == c) ? 2 : 0;
+    const double T = p.counts[t];
+    double F[9], Fi[9], Dl[3];
+    for (int i = 0; i < ne; ++i) {
+      const double nl = ells[i] == 0 ? T : ells[i] == 2 ? 1.5 * c2[t] - 0.5 * T
+                                                        : (35.0 * c4[t] - 30.0 * c2[t] + 3.0 * T) / 8.0;
+      const double r = nl / T;
+      Dl[i] = cs == 0 ? 1.0 : cs == 1 ? 2.0 : cs == 2 ? 1.0 + r : 2.0 * (1.0 + 2.0 * r);
+      for (int j = 0; j < ne; ++j) {
+        const int lo = std::min(i, j), hi = std::max(i, j);
+        const double dd = d33[((size_t)lo * ne + hi) * nt + t], xx = x32[((size_t)lo * ne + hi) * nt + t];
+        F[i * ne + j] = cs == 0 ? dd : cs == 1 ? 2.0 * dd : cs == 2 ? dd + xx : 2.0 * (dd + 2.0 * xx);
+      }
+    }
+    pinv_sym(ne, F, Fi);
+    for (int i = 0; i < ne; ++i)
+      for (int j = 0; j < ne; ++j)
+        mix_out[((size_t)t * ne + i) * ne + j] = Dl[i] * Fi[i * ne + j] * T / (2.0 * ells[j] + 1.0);
+  }
+done:
+  hipFree(a1);
+  hipFree(a2);
+  hipFree(h);
+  hipFree(part);
+  hipFree(out);
+  hipFree(map);
+  hipFree(trips);
+  hipFree(tiles);
+  return st;
+}
+
+// b[l][t] <- sum_l' R[t][l][l'] y[l'][t] in place (one thread per triplet).
+__global__ void k_ml_mix(double* __restrict__ bk, const double* __restrict__ R, int nt, int ne) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  double y[3], b[3];
+  for (int l = 0; l < ne; ++l) y[l] = bk[(size_t)l * nt + t];
+  for (int l = 0; l < ne; ++l) {
+    double acc = 0.0;
+    for (int j = 0; j < ne; ++j) acc += R[((size_t)t * ne + l) * ne + j] * y[j];
+    b[l] = acc;
+  }
+  for (int l = 0; l < ne; ++l) bk[(size_t)l * nt + t] = b[l];
 }
 
 }  // namespace pb3

@@ -906,10 +906,11 @@ def test_bk_fisher_separable_sums_equal_triangle_loops():
     bk-fish-ideal), of N_l (eq. N-ell-def, through the tensor expansion of
     (u2 . u3)^p) and of the numerators (eq. bk-num-ideal) equal explicit
     loops over the closed triangles, in all four bin-degeneracy cases
-    (a < b < c, a = b < c, a < b = c, a = b = c), for l, l' <= 4."""
+    (a < b < c, a = b < c, a < b = c, a = b = c), for l, l' <= 4, with
+    Nyquist modes in the last bin (directions averaged over +-N/2)."""
     from oracle import bk_fisher as bf
 
-    n, box, edges = 8, 500.0, np.array([1.0, 2.0, 3.0, 4.0])
+    n, box, edges = 8, 500.0, np.array([1.0, 2.0, 3.0, 4.0, 5.0])  # the last bin holds Nyquist modes
     trips, Ft, Delta, T, Nl = bf.fisher_blocks(n, edges, 4)
     assert sorted({bf._case(*t) for t in trips}) == [0, 1, 2, 3]
     Fb, Nb, Tb = bf.brute_blocks(n, edges, trips, 4)
