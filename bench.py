@@ -49,7 +49,7 @@ MEASURED_TRAFFIC = {
         "fetch_kib": 138472.3, "write_kib": 44032.0, "fetch_factor": 2.0, "write_factor": 1.0,
         "sources": {
             "paper_2404_07249_amd/csrc/contract_mfma.hip":
-                "fee7d5b48fd53aa82ce5479b1d64583e379c61770c9570a556f304e8631303df",
+                "7a32d987869f6e3f939e42bf785745c262dc0d4a233a92a76c331ea72ac9b376",
             "paper_2404_07249_amd/csrc/fft_dev.h":
                 "1a6048a01650ed48e8e213de4c409daa938b10ac9a8b67f686e1d7b785d53a88",
             "paper_2404_07249_amd/csrc/job.h":

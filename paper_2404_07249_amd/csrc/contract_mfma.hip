@@ -21,9 +21,10 @@
 // takes hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16 with FP32
 // accumulation.  FP32: v_mfma_f32_16x16x4_f32 on the unsplit values.
 //
-// Each wave accumulates its K-steps in FP32 registers; the work-group's
-// waves are summed in LDS in a fixed order and written as one FP32 partial
-// per work-group; the fixed-order FP64 reduction over work-groups follows.
+// Each wave accumulates its K-steps in FP32 registers over one chunk of
+// voxels; the chunk's tiles are written as one FP32 partial vector (summed
+// over a group's waves in LDS in a fixed order when a group has several),
+// and the fixed-order FP64 reduction over chunks follows.
 
 #include <hip/hip_runtime.h>
 
@@ -434,8 +435,8 @@ static hipError_t launch_nq(const float* g, long mvox, int n_wg, long vpw, float
 // Contraction waves per group: in mixed precision one (4 waves beside the
 // 4 producers; 8 waves per work-group leave each wave the registers of two
 // waves per SIMD, so neither the FFT nor the tile accumulators spill, where
-// two per group spill and run about 6% slower); in FP32 two, whose second
-// wave hides the dependent chains of the 8x more numerous FP32 MFMAs.
+// two per group spill and run slower); in FP32 two, whose second wave hides
+// the dependent chains of the 8x more numerous FP32 MFMAs.
 constexpr int kProducerThreads = 256;
 constexpr int fused_waves(bool mixed) { return mixed ? 1 : 2; }
 constexpr int fused_consumers(bool mixed) { return 64 * kGroups * fused_waves(mixed); }
@@ -746,12 +747,12 @@ static hipError_t launch_fused_nq(const pb3_plan& p, const Exec& x, hipStream_t 
   }
 }
 
-// Work-groups of the fused kernel: enough that each covers about
-// kFusedVoxPerWg voxels, between one and four times the resident count.
-// Each work-group's FP32 MFMA accumulators then sum a bounded number of
-// products (at 256^3 x 30 bins, 1024 work-groups: max |dB|/A 1.8e-7 in
-// mixed precision against 5.5e-7 with 256), at a few per cent more time for
-// the extra partial vectors.
+// Accumulation chunks (partial vectors) of the fused kernel: enough that
+// each covers about kFusedVoxPerWg voxels, between one and four times the
+// resident work-group count.  Each chunk's FP32 MFMA accumulators then sum
+// a bounded number of products (at 256^3 x 30 bins, 1024 chunks: max
+// |dB|/A 1.8e-7 in mixed precision against 5.5e-7 with 256), at a few per
+// cent more time for the extra partial vectors.
 constexpr long kFusedVoxPerWg = 6912;
 int fused_grid(int nq, int m, long mvox, int n_cu) {
   int per = 1;
