@@ -203,7 +203,9 @@ constexpr int fft2_r1(int n) {
 constexpr int fft2_r2(int n) { return n / fft2_r1(n); }
 constexpr int fft2_threads(int n) { return fft2_r1(n) > fft2_r2(n) ? fft2_r1(n) : fft2_r2(n); }
 
-template <int N, int S, typename C, typename LoadF, typename StoreF>
+// OVER: phase 2 reads its inputs, then a second work-group barrier lets
+// store() write into s itself (the caller may alias its output with s).
+template <int N, int S, bool OVER = false, typename C, typename LoadF, typename StoreF>
 __device__ __forceinline__ void fft2_line(C* s, int tl, const C* __restrict__ tw, LoadF&& load, StoreF&& store) {
   constexpr int R1 = fft2_r1(N), R2 = fft2_r2(N);
   static_assert(R1 * R2 == N, "bad factorisation");
@@ -221,10 +223,13 @@ __device__ __forceinline__ void fft2_line(C* s, int tl, const C* __restrict__ tw
     for (int k1 = 0; k1 < R1; ++k1) s[k1 * R2 + tl] = v[k1];
   }
   __syncthreads();
+  C u[R2];
   if (tl < R1) {
-    C u[R2];
 #pragma unroll
     for (int t = 0; t < R2; ++t) u[t] = s[tl * R2 + t];
+  }
+  if constexpr (OVER) __syncthreads();
+  if (tl < R1) {
     dft<R2, S>(u);
 #pragma unroll
     for (int k2 = 0; k2 < R2; ++k2) store(tl + R1 * k2, u[k2]);

@@ -56,8 +56,7 @@ __global__ void __launch_bounds__(512) k_fwd_z2(const JobIO io, float2* __restri
   using S = PairShape<N, 8>;
   constexpr int TL = S::TL, TP = S::TP, LS = S::LS;
   __shared__ float2 tws[N];
-  __shared__ float2 scr[TP * LS];
-  __shared__ float2 zb[TP * LS];
+  __shared__ float2 scr[TP * LS];  // the FFT exchange, then the spectra
   const int tid = threadIdx.x;
   for (int e = tid; e < N; e += S::NT) tws[e] = tw[e];
   __syncthreads();
@@ -68,8 +67,8 @@ __global__ void __launch_bounds__(512) k_fwd_z2(const JobIO io, float2* __restri
   const float* xa = delta + off;
   const float* xb = xa + N;
   const float* wa = io.window ? io.window + off : nullptr;  // optional window multiplying the field
-  float2* z = zb + pl * LS;
-  fft2_line<N, -1>(
+  float2* z = scr + pl * LS;
+  fft2_line<N, -1, true>(
       scr + pl * LS, tl, tws,
       [&](int n) {
         if (!live) return make_float2(0.f, 0.f);
@@ -87,7 +86,7 @@ __global__ void __launch_bounds__(512) k_fwd_z2(const JobIO io, float2* __restri
   if (nl > 2 * TP) nl = 2 * TP;
   for (int e = tid; e < nl * Kz; e += S::NT) {
     int ll = e / Kz, k = e % Kz;
-    const float2* zz = zb + (ll >> 1) * LS;
+    const float2* zz = scr + (ll >> 1) * LS;
     float2 a = zz[k % N], b = zz[(N - k) % N];
     float2 o = (ll & 1) == 0 ? make_float2(0.5f * (a.x + b.x), 0.5f * (a.y - b.y))
                              : make_float2(0.5f * (a.y + b.y), 0.5f * (b.x - a.x));
