@@ -10,7 +10,7 @@ the input field is resident in HBM before timing starts.
 Workload: 256^3 grid, L = 2000 Mpc/h, 30 bins of width 2 k_f from k_f
 (3035 triangle-valid triplets), d = g + f_NL (g^2 - <g^2>) with f_NL = 1.
 
-Prints ONE JSON line (rank 0).  ``--gpus`` above 1 is refused: this build
+Prints ONE JSON line (rank 0).  ``--gpus`` above 1 is refused: the library
 runs on one GPU.
 """
 
@@ -456,7 +456,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(
-            json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported", "n_gpus": args.gpus}),
+            json.dumps({"error": "the library runs on one GPU; --gpus above 1 is not supported", "n_gpus": args.gpus}),
             flush=True,
         )
         return 2
