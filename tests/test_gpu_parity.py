@@ -322,3 +322,29 @@ def test_autotune_with_cache(torch_cuda, tmp_path, monkeypatch):
     for prec in PRECS:
         pk, bk = [t.cpu().numpy() for t in p2.polyspectra(_gpu(torch, d), prec)]
         _check_pb(res, pk, bk, p2.triplets, f"tuned {prec}")
+
+
+@pytest.mark.parametrize(
+    "n,nbins",
+    [
+        (32, 1),   # one bin, one triplet (0, 0, 0)
+        (32, 2),   # two bins in one 16-bin group, mostly padding
+        (48, 16),  # one full 16-bin group, no padding
+        (64, 17),  # a second group holding a single bin
+        (96, 32),  # two full groups, the largest fused contraction
+    ],
+)
+def test_bin_count_edges(torch_cuda, n, nbins):
+    """Bin counts at the edges of the 16-bin MFMA groups (bins of width
+    k_f from k_f), fused and separate z pass, both precisions; triangle
+    counts exact."""
+    torch = torch_cuda
+    box = 1000.0
+    edges = 1.0 + np.arange(nbins + 1, dtype=np.float64)
+    d = quadratic_field(n, box, 1.0, 700 + nbins).astype(np.float32)
+    res = oracle.bispectrum(d.astype(np.float64), box, edges)
+    for prec in PRECS:
+        for fuse in (True, False):
+            plan, pk, bk = _run_case(torch, n, box, edges, d, prec, fuse=fuse)
+            _check_pb(res, pk, bk, plan.triplets, f"{prec} fuse={fuse}")
+            assert np.array_equal(plan.norm()[1].astype(np.int64), res.counts)
