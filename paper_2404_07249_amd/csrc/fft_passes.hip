@@ -130,12 +130,14 @@ __global__ void __launch_bounds__(512) k_fwd_col2(const float2* __restrict__ in,
 }
 
 // ---------------------------------------------------------- inverse x
-// Per bin b, one work-group per (row jy of the bin's rectangle, chunk of TB
-// columns kz); the chunks of one row have consecutive tile indices, so they
-// run together and their partial cache lines combine.  The kx line of
-// Theta_b D (Theta_b alone when UNIT) enters at FFT positions kx mod M.
-// A mode belongs to the bin when the plan's per-mode table bin3 says so.
-// Output a1_b[x][jy][jz].  Tile col0 = row * 256 + first column.
+// Per bin b, one work-group per chunk of TB consecutive columns jy * kzn +
+// kz of the bin's (ky, kz) rectangle, taken in row-major order so that no
+// lane idles at the end of a short row; consecutive chunks have consecutive
+// tile indices, so they run together and their partial cache lines combine.
+// The kx line of Theta_b D (Theta_b alone when UNIT) enters at FFT
+// positions kx mod M.  A mode belongs to the bin when the plan's per-mode
+// table bin3 says so; bin3 carries one more entry, "no bin", at index nb3.
+// Output a1_b[x][jy][jz].  Tile col0 = first column.
 struct WinOff {
   int x, y, z;  // offsets of k = 0 of each axis in the window table
 };
@@ -161,7 +163,7 @@ __global__ void __launch_bounds__(512) k_inv_x2(const float2* __restrict__ dc, t
                                                 const typename Cx<Rl>::type* __restrict__ tw, size_t wstride,
                                                 int ell, const float* __restrict__ winv, WinOff wo, float sx,
                                                 float sy, const float* __restrict__ pinv,
-                                                const double* __restrict__ uw, AngW aw) {
+                                                const double* __restrict__ uw, AngW aw, size_t nb3) {
   dc = job_ptr(dc, wstride);
   a1 = job_ptr(a1, wstride);
   using C = typename Cx<Rl>::type;
@@ -178,13 +180,38 @@ __global__ void __launch_bounds__(512) k_inv_x2(const float2* __restrict__ dc, t
   const BinTile tile = tiles[ti];
   const int b = tile.bin;
   const BinGeom g = geom[b];
-  const int jy = tile.col0 >> 8;
-  const int ky = jy - g.knegy;
   const int ncol = g.ly * g.kzn;
   {
-    const int kz = (tile.col0 & 255) + col;
-    const bool live = kz < g.kzn;
-    C* dst = a1 + g.a1_off + (size_t)jy * g.kzn + kz;
+    const int c = tile.col0 + col;  // column jy * kzn + kz of the bin's block
+    const bool live = c < ncol;
+    const int jy = c / g.kzn, kz = c - jy * g.kzn;
+    const int ky = jy - g.knegy;
+    C* dst = a1 + g.a1_off + c;
+    auto store = [&](int x, C v) {
+      if (live) dst[(size_t)x * ncol] = v;
+    };
+    if constexpr (!UNIT) {
+      if (!winv && !pinv && !ell) {
+        // Plain spectra: every lane makes both lookups unconditionally (off
+        // the bin's rectangle it reads the table's trailing "no bin" entry
+        // and value 0) and masks the value by a multiplication, so the
+        // loads of a line are in flight together rather than one element
+        // after another.  Every compact entry holds a finite value.
+        fft2_line<M, 1>(
+            scr + col * LS, tl, tws,
+            [&](int n) {
+              const int kx = n <= g.kposx ? n : (n >= M - g.knegx ? n - M : 0x40000000);
+              const bool in = live && kx != 0x40000000;
+              const size_t ci = in ? ((size_t)(kx + Kcx) * Lcy + (ky + Kcy)) * Kz + kz : 0;
+              const int bb = bin3[in ? ci : nb3];
+              const float2 d = dc[ci];
+              const float m = bb == b ? 1.f : 0.f;
+              return cx<C>(Rl(fmaf(d.x, m, 0.f)), Rl(fmaf(d.y, m, 0.f)));
+            },
+            store);
+        return;
+      }
+    }
     fft2_line<M, 1>(
         scr + col * LS, tl, tws,
         [&](int n) {
@@ -226,9 +253,7 @@ __global__ void __launch_bounds__(512) k_inv_x2(const float2* __restrict__ dc, t
           }
           return v;
         },
-        [&](int x, C v) {
-          if (live) dst[(size_t)x * ncol] = v;
-        });
+        store);
   }
 }
 
@@ -412,7 +437,7 @@ hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, const float2* dc, v
       if (unit)
         hipLaunchKernelGGL((k_inv_x2<LL, double, true>), dim3(xcd_tiles(ts.n), 1, n_jobs), dim3(S::NT), 0, s, dc,
                            (double2*)a1, p.d.geom, ts.d, ts.n, p.d.bin3, p.Kcx, p.Kcy, p.Lcy, p.Kz, (const double2*)tw,
-                           wstride, 0, (const float*)nullptr, wo, sx, sy, (const float*)nullptr, unit_w, aw);
+                           wstride, 0, (const float*)nullptr, wo, sx, sy, (const float*)nullptr, unit_w, aw, ncompact(p));
       else
         return hipErrorInvalidValue;
     } else {
@@ -420,7 +445,7 @@ hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, const float2* dc, v
       if (unit) return hipErrorInvalidValue;
       hipLaunchKernelGGL((k_inv_x2<LL, float, false>), dim3(xcd_tiles(ts.n), 1, n_jobs), dim3(S::NT), 0, s, dc,
                          (float2*)a1, p.d.geom, ts.d, ts.n, p.d.bin3, p.Kcx, p.Kcy, p.Lcy, p.Kz, (const float2*)tw,
-                         wstride, ell, winv, wo, sx, sy, pinv, (const double*)nullptr, AngW{});
+                         wstride, ell, winv, wo, sx, sy, pinv, (const double*)nullptr, AngW{}, ncompact(p));
     }
     return hipGetLastError();
   });

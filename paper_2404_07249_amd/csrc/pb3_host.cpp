@@ -51,9 +51,8 @@ void build_tiles(const pb3_plan& p, int tbxy, int tbz, std::vector<BinTile>& vx,
   vz.clear();
   for (int b = 0; b < p.nb; ++b) {
     const BinGeom& g = p.geom[b];
-    // x pass: (row jy, column chunk); y pass: (x-plane, column chunk)
-    for (int jy = 0; jy < g.ly; ++jy)
-      for (int c = 0; c < g.kzn; c += tbxy) vx.push_back(BinTile{b, jy * 256 + c});
+    // x pass: chunk of the flattened (jy, kz) columns; y pass: (x-plane, column chunk)
+    for (int c = 0; c < g.ly * g.kzn; c += tbxy) vx.push_back(BinTile{b, c});
     for (int x = 0; x < p.Mx; ++x)
       for (int c = 0; c < g.kzn; c += tbxy) vy.push_back(BinTile{b, x * 256 + c});
     int nz = p.Mx * p.My;
@@ -294,7 +293,7 @@ static pb3_status build_host(pb3_plan* p, const int grid[3], const double box[3]
   // modes of the compact half spectrum, per bin
   std::vector<std::vector<int32_t>> per(nb);
   p->nmodes.assign(nb, 0);
-  p->bin3.assign(ncompact(*p), (int8_t)-1);
+  p->bin3.assign(ncompact(*p) + 1, (int8_t)-1);  // a trailing "no bin" entry
   p->lmax = (flags & PB3_FLAG_LMAX4) ? 4 : (flags & PB3_FLAG_LMAX2) ? 2 : 0;
   const int ne = p->lmax / 2 + 1;
   std::vector<double> msum((size_t)nb * ne * ne, 0.0);  // per bin: sum over its modes of L_i L_j

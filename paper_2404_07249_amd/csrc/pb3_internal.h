@@ -66,7 +66,7 @@ struct JobIO {
 };
 
 struct DeviceTables {
-  int8_t* bin3 = nullptr;         // bin of every compact mode [Lcx][Lcy][Kz] (int8, -1 outside)
+  int8_t* bin3 = nullptr;         // bin of every compact mode [Lcx][Lcy][Kz] (int8, -1 outside), then one -1
   int32_t* modes = nullptr;       // compact D index of every binned half-spectrum mode (bit 31: weight 1)
   int32_t* chunk = nullptr;       // power chunks: (bin, start, end) triples
   int32_t* chunk_first = nullptr; // per bin: index of its first chunk (n_bins + 1 entries)
@@ -137,7 +137,7 @@ struct pb3_plan {
   int Mx = 0, My = 0, Mz = 0;  // contraction grid
   double kf2[3] = {0, 0, 0};   // (2 pi / L_i)^2
   double msc[3] = {1, 1, 1};   // multipole scales: k_f,i^2 / k_f,z^2 (all exactly 1 for a cubic box)
-  std::vector<int8_t> bin3;    // bin of every compact mode [Lcx][Lcy][Kz]
+  std::vector<int8_t> bin3;    // bin of every compact mode [Lcx][Lcy][Kz], then a trailing -1
   bool fused = false;          // inverse z pass fused into the contraction (no G in HBM)
   bool fused_ok = false;       // the fused kernel supports this plan
   int lmax = 0;                // highest multipole (0, 2 or 4)
