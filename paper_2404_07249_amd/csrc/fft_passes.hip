@@ -258,15 +258,16 @@ __global__ void __launch_bounds__(512) k_inv_x2(const float2* __restrict__ dc, t
 }
 
 // ---------------------------------------------------------- inverse y
-// Per bin, one work-group per (x-plane, chunk of TB columns jz), chunks of
-// a plane consecutive; inverse transform along y.  Tile col0 = x * 256 +
-// first column.
+// Per bin, one work-group per chunk of TB consecutive columns x * kzn + jz
+// of the bin's mx planes (a chunk may span two planes, so no lane idles at
+// the end of a plane); consecutive chunks on one XCD.  Inverse transform
+// along y.  Tile col0 = first column.
 template <int M, typename Rl>
 __global__ void __launch_bounds__(512) k_inv_y2(const typename Cx<Rl>::type* __restrict__ a1,
                                                 typename Cx<Rl>::type* __restrict__ a2,
                                                 const BinGeom* __restrict__ geom, const BinTile* __restrict__ tiles,
                                                 int n_tiles, const typename Cx<Rl>::type* __restrict__ tw,
-                                                size_t wstride) {
+                                                size_t wstride, int mx) {
   a1 = job_ptr(a1, wstride);
   a2 = job_ptr(a2, wstride);
   using C = typename Cx<Rl>::type;
@@ -282,10 +283,10 @@ __global__ void __launch_bounds__(512) k_inv_y2(const typename Cx<Rl>::type* __r
   if (ti >= n_tiles) return;  // whole work-group
   const BinTile tile = tiles[ti];
   const BinGeom g = geom[tile.bin];
-  const int x = tile.col0 >> 8;
   {
-    const int jz = (tile.col0 & 255) + col;
-    const bool live = jz < g.kzn;
+    const int c = tile.col0 + col;  // column x * kzn + jz
+    const bool live = c < mx * g.kzn;
+    const int x = c / g.kzn, jz = c - x * g.kzn;
     const C* src = a1 + g.a1_off + ((size_t)x * g.ly + g.knegy) * g.kzn + jz;  // ky = 0 row
     C* dst = a2 + g.a2_off + (size_t)x * M * g.kzn + jz;
     fft2_line<M, 1>(
@@ -460,11 +461,11 @@ hipError_t run_inv_y(const pb3_plan& p, bool dbl, const void* a1, void* a2, cons
     if (dbl) {
       using S = ColShape<LL, 16>;
       hipLaunchKernelGGL((k_inv_y2<LL, double>), dim3(xcd_tiles(ts.n), 1, n_jobs), dim3(S::NT), 0, s, (const double2*)a1,
-                         (double2*)a2, p.d.geom, ts.d, ts.n, (const double2*)tw, wstride);
+                         (double2*)a2, p.d.geom, ts.d, ts.n, (const double2*)tw, wstride, p.Mx);
     } else {
       using S = ColShape<LL, 8>;
       hipLaunchKernelGGL((k_inv_y2<LL, float>), dim3(xcd_tiles(ts.n), 1, n_jobs), dim3(S::NT), 0, s, (const float2*)a1,
-                         (float2*)a2, p.d.geom, ts.d, ts.n, (const float2*)tw, wstride);
+                         (float2*)a2, p.d.geom, ts.d, ts.n, (const float2*)tw, wstride, p.Mx);
     }
     return hipGetLastError();
   });

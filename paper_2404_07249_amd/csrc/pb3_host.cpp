@@ -51,10 +51,9 @@ void build_tiles(const pb3_plan& p, int tbxy, int tbz, std::vector<BinTile>& vx,
   vz.clear();
   for (int b = 0; b < p.nb; ++b) {
     const BinGeom& g = p.geom[b];
-    // x pass: chunk of the flattened (jy, kz) columns; y pass: (x-plane, column chunk)
+    // x pass: chunks of the flattened (jy, kz) columns; y pass: of the flattened (x, kz) columns
     for (int c = 0; c < g.ly * g.kzn; c += tbxy) vx.push_back(BinTile{b, c});
-    for (int x = 0; x < p.Mx; ++x)
-      for (int c = 0; c < g.kzn; c += tbxy) vy.push_back(BinTile{b, x * 256 + c});
+    for (int c = 0; c < p.Mx * g.kzn; c += tbxy) vy.push_back(BinTile{b, c});
     int nz = p.Mx * p.My;
     for (int c = 0; c < nz; c += tbz) vz.push_back(BinTile{b, c});
   }
