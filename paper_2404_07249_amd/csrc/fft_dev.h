@@ -193,10 +193,14 @@ template <int R, int S, typename C> __device__ __forceinline__ void dft(C* v) {
 // Length N = R1 * R2.  Phase 1: thread t < R2 of the line takes inputs
 // n = t + R2 j (j < R1) in registers, runs a DFT of length R1 over j,
 // multiplies output k1 by exp(S 2 pi i t k1 / N) and writes it to the
-// line's LDS scratch s[k1 R2 + t].  Phase 2: thread k1 < R1 reads
-// s[k1 R2 + t] (t < R2), runs a DFT of length R2 over t and delivers
+// line's LDS scratch s[k1 RS + t].  Phase 2: thread k1 < R1 reads
+// s[k1 RS + t] (t < R2), runs a DFT of length R2 over t and delivers
 // output k = k1 + R1 k2.  One LDS exchange, one barrier (every thread of
 // the work-group must call it).  tw holds W_N^m = exp(-2 pi i m / N).
+// The exchange rows sit RS = R2 + PAD apart and s holds R1 RS elements:
+// where a line's threads are consecutive lanes, PAD = 1 puts phase 2's
+// reads (stride RS) in distinct LDS banks, which rows of a power-of-two
+// R2 would not.
 constexpr int fft2_r1(int n) {
   return n == 16 ? 4 : n == 24 ? 8 : n == 32 ? 8 : n == 64 ? 8 : 16;
 }
@@ -205,9 +209,9 @@ constexpr int fft2_threads(int n) { return fft2_r1(n) > fft2_r2(n) ? fft2_r1(n) 
 
 // OVER: phase 2 reads its inputs, then a second work-group barrier lets
 // store() write into s itself (the caller may alias its output with s).
-template <int N, int S, bool OVER = false, typename C, typename LoadF, typename StoreF>
+template <int N, int S, bool OVER = false, int PAD = 0, typename C, typename LoadF, typename StoreF>
 __device__ __forceinline__ void fft2_line(C* s, int tl, const C* __restrict__ tw, LoadF&& load, StoreF&& store) {
-  constexpr int R1 = fft2_r1(N), R2 = fft2_r2(N);
+  constexpr int R1 = fft2_r1(N), R2 = fft2_r2(N), RS = R2 + PAD;
   static_assert(R1 * R2 == N, "bad factorisation");
   if (tl < R2) {
     C v[R1];
@@ -220,13 +224,13 @@ __device__ __forceinline__ void fft2_line(C* s, int tl, const C* __restrict__ tw
       v[k1] = (S < 0) ? cmul(v[k1], w) : cmulc(v[k1], w);
     }
 #pragma unroll
-    for (int k1 = 0; k1 < R1; ++k1) s[k1 * R2 + tl] = v[k1];
+    for (int k1 = 0; k1 < R1; ++k1) s[k1 * RS + tl] = v[k1];
   }
   __syncthreads();
   C u[R2];
   if (tl < R1) {
 #pragma unroll
-    for (int t = 0; t < R2; ++t) u[t] = s[tl * R2 + t];
+    for (int t = 0; t < R2; ++t) u[t] = s[tl * RS + t];
   }
   if constexpr (OVER) __syncthreads();
   if (tl < R1) {

@@ -39,21 +39,37 @@ template <int N, int CS> struct ColShape {
   static constexpr int LS = N + 1;  // odd LDS stride between columns
   static constexpr int NT = TB * TL;
 };
-// z passes: TP pairs of lines per work-group, TL threads per pair.
-template <int N, int CS> struct PairShape {
+// z passes: TP pairs of lines per work-group, TL threads per pair (in
+// consecutive lanes).  A pair's LDS line holds the FFT exchange, its rows
+// R2 + PAD apart (PAD as in fft2_line), and in the forward pass the N
+// outputs.
+template <int N, int CS, int PAD = 0> struct PairShape {
   static constexpr int TL = fft2_threads(N);
   static constexpr int TP = ((CS == 8 ? 256 : 128) / TL) < 1 ? 1 : ((CS == 8 ? 256 : 128) / TL);
-  static constexpr int LS = N + 1;
+  static constexpr int EX = fft2_r1(N) * (fft2_r2(N) + PAD);
+  static constexpr int LS = (EX > N ? EX : N) + 1;
   static constexpr int NT = TP * TL;
 };
 
 // ------------------------------------------------------------ forward z
+// The forward pass pads its exchange rows where unpadded rows of float2
+// would put phase 2's reads four or more to an LDS bank (N = 128, 256, 384;
+// at 256^3, rows of 16 values, eight to a bank: 35 -> 25 us).  Elsewhere
+// the padding would only cost occupancy.  The inverse pass does not pad:
+// at M = 192 its conflict is two-way and the padding would cost its FP64
+// form a work-group per CU.
+constexpr int fwd_z_pad(int n) {
+  const int stride = 2 * fft2_r2(n);  // dwords between the rows phase 2 reads
+  int g = 1;
+  while (g < 64 && stride % (2 * g) == 0) g *= 2;
+  return fft2_r1(n) >= 4 * (64 / g) ? 1 : 0;
+}
 template <int N>
 __global__ void __launch_bounds__(512) k_fwd_z2(const JobIO io, float2* __restrict__ f1, size_t wstride,
                                                 int n_pairs, int Kz, const float2* __restrict__ tw) {
   const float* __restrict__ delta = io.delta[blockIdx.z];
   f1 = job_ptr(f1, wstride);
-  using S = PairShape<N, 8>;
+  using S = PairShape<N, 8, fwd_z_pad(N)>;
   constexpr int TL = S::TL, TP = S::TP, LS = S::LS;
   __shared__ float2 tws[N];
   __shared__ float2 scr[TP * LS];  // the FFT exchange, then the spectra
@@ -68,7 +84,7 @@ __global__ void __launch_bounds__(512) k_fwd_z2(const JobIO io, float2* __restri
   const float* xb = xa + N;
   const float* wa = io.window ? io.window + off : nullptr;  // optional window multiplying the field
   float2* z = scr + pl * LS;
-  fft2_line<N, -1, true>(
+  fft2_line<N, -1, true, fwd_z_pad(N)>(
       scr + pl * LS, tl, tws,
       [&](int n) {
         if (!live) return make_float2(0.f, 0.f);
@@ -393,7 +409,7 @@ int tile_width_z(int M, bool dbl) {
 hipError_t launch_fwd_z(const pb3_plan& p, const Exec& x, hipStream_t s) {
   const int n_pairs = p.Nx * p.Ny / 2;
   PB3_FFT_LEN(p.Nz, {
-    using S = PairShape<LL, 8>;
+    using S = PairShape<LL, 8, fwd_z_pad(LL)>;
     hipLaunchKernelGGL(k_fwd_z2<LL>, dim3((n_pairs + S::TP - 1) / S::TP, 1, x.n_jobs), dim3(S::NT), 0, s, x.io,
                        x.ws.f1, x.wstride, n_pairs, p.Kz, p.d.tw_n[2]);
     return hipGetLastError();
