@@ -212,7 +212,8 @@ __global__ void __launch_bounds__(512) k_inv_x2(const float2* __restrict__ dc, t
         // the bin's rectangle it reads the table's trailing "no bin" entry
         // and value 0) and masks the value by a multiplication, so the
         // loads of a line are in flight together rather than one element
-        // after another.  Every compact entry holds a finite value.
+        // after another.  The forward pass writes every compact entry, so
+        // a masked-out value is finite whenever the field is.
         fft2_line<M, 1>(
             scr + col * LS, tl, tws,
             [&](int n) {
