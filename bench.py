@@ -51,7 +51,7 @@ MEASURED_TRAFFIC = {
             "paper_2404_07249_amd/csrc/contract_mfma.hip":
                 "7a32d987869f6e3f939e42bf785745c262dc0d4a233a92a76c331ea72ac9b376",
             "paper_2404_07249_amd/csrc/fft_dev.h":
-                "956cefe23b38dd7e774f4606bb925537a80f1027ed4c94f7bcbc4191c17c6989",
+                "df3b6d76c6673e67d4b39f61aa79139393ef94214581251510d14c1ded1023f4",
             "paper_2404_07249_amd/csrc/job.h":
                 "0f3d39c847bc50252698d89b0082866e4ca72f6f435cacd590aacb25667591d2",
         },

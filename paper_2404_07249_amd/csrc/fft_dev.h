@@ -209,9 +209,10 @@ constexpr int fft2_threads(int n) { return fft2_r1(n) > fft2_r2(n) ? fft2_r1(n) 
 
 // OVER: phase 2 reads its inputs, then a second work-group barrier lets
 // store() write into s itself (the caller may alias its output with s).
-template <int N, int S, bool OVER = false, int PAD = 0, typename C, typename LoadF, typename StoreF>
+// R1F, when set, replaces the default first radix fft2_r1(N) (R2 = N / R1F).
+template <int N, int S, bool OVER = false, int PAD = 0, int R1F = 0, typename C, typename LoadF, typename StoreF>
 __device__ __forceinline__ void fft2_line(C* s, int tl, const C* __restrict__ tw, LoadF&& load, StoreF&& store) {
-  constexpr int R1 = fft2_r1(N), R2 = fft2_r2(N), RS = R2 + PAD;
+  constexpr int R1 = R1F ? R1F : fft2_r1(N), R2 = N / R1, RS = R2 + PAD;
   static_assert(R1 * R2 == N, "bad factorisation");
   if (tl < R2) {
     C v[R1];

@@ -39,37 +39,23 @@ template <int N, int CS> struct ColShape {
   static constexpr int LS = N + 1;  // odd LDS stride between columns
   static constexpr int NT = TB * TL;
 };
-// z passes: TP pairs of lines per work-group, TL threads per pair (in
-// consecutive lanes).  A pair's LDS line holds the FFT exchange, its rows
-// R2 + PAD apart (PAD as in fft2_line), and in the forward pass the N
-// outputs.
-template <int N, int CS, int PAD = 0> struct PairShape {
+// z passes: TP pairs of lines per work-group, TL threads per pair.
+template <int N, int CS> struct PairShape {
   static constexpr int TL = fft2_threads(N);
   static constexpr int TP = ((CS == 8 ? 256 : 128) / TL) < 1 ? 1 : ((CS == 8 ? 256 : 128) / TL);
-  static constexpr int EX = fft2_r1(N) * (fft2_r2(N) + PAD);
-  static constexpr int LS = (EX > N ? EX : N) + 1;
+  static constexpr int LS = N + 1;
   static constexpr int NT = TP * TL;
 };
 
 // ------------------------------------------------------------ forward z
-// The forward pass pads its exchange rows where unpadded rows of float2
-// would put phase 2's reads four or more to an LDS bank (N = 128, 256, 384;
-// at 256^3, rows of 16 values, eight to a bank: 35 -> 25 us).  Elsewhere
-// the padding would only cost occupancy.  The inverse pass does not pad:
-// at M = 192 its conflict is two-way and the padding would cost its FP64
-// form a work-group per CU.
-constexpr int fwd_z_pad(int n) {
-  const int stride = 2 * fft2_r2(n);  // dwords between the rows phase 2 reads
-  int g = 1;
-  while (g < 64 && stride % (2 * g) == 0) g *= 2;
-  return fft2_r1(n) >= 4 * (64 / g) ? 1 : 0;
-}
+// Pair form, for the short lines (N < 64): two real lines as one complex
+// line of length N.
 template <int N>
 __global__ void __launch_bounds__(512) k_fwd_z2(const JobIO io, float2* __restrict__ f1, size_t wstride,
                                                 int n_pairs, int Kz, const float2* __restrict__ tw) {
   const float* __restrict__ delta = io.delta[blockIdx.z];
   f1 = job_ptr(f1, wstride);
-  using S = PairShape<N, 8, fwd_z_pad(N)>;
+  using S = PairShape<N, 8>;
   constexpr int TL = S::TL, TP = S::TP, LS = S::LS;
   __shared__ float2 tws[N];
   __shared__ float2 scr[TP * LS];  // the FFT exchange, then the spectra
@@ -84,7 +70,7 @@ __global__ void __launch_bounds__(512) k_fwd_z2(const JobIO io, float2* __restri
   const float* xb = xa + N;
   const float* wa = io.window ? io.window + off : nullptr;  // optional window multiplying the field
   float2* z = scr + pl * LS;
-  fft2_line<N, -1, true, fwd_z_pad(N)>(
+  fft2_line<N, -1, true>(
       scr + pl * LS, tl, tws,
       [&](int n) {
         if (!live) return make_float2(0.f, 0.f);
@@ -107,6 +93,75 @@ __global__ void __launch_bounds__(512) k_fwd_z2(const JobIO io, float2* __restri
     float2 o = (ll & 1) == 0 ? make_float2(0.5f * (a.x + b.x), 0.5f * (a.y - b.y))
                              : make_float2(0.5f * (a.y + b.y), 0.5f * (b.x - a.x));
     f1[(size_t)(line0 + ll) * Kz + k] = o;
+  }
+}
+
+// Half-length form, for N = 32 H' with H' in {2, 3, 4, 6, 8, 12}: a real
+// line x of length N is the complex line z[m] = x[2m] + i x[2m+1] of length
+// H = N/2.  With Z = DFT_H[z] (indices mod H), the even and odd samples
+// have the spectra E[k] = (Z[k] + conj Z[H-k]) / 2 and
+// O[k] = -i (Z[k] - conj Z[H-k]) / 2, and X[k] = E[k] + W_N^k O[k] for
+// k < Kz.  The line FFT takes R2 = 16 loaders, so the 16 threads of a line
+// read 128 contiguous bytes per load (the pair form reads 64), and its
+// exchange rows are padded (PAD = 1) so that phase 2's reads fall in
+// distinct LDS banks.  16 lines per work-group.
+template <int N> struct HalfShape {
+  static constexpr int H = N / 2, R2 = 16, R1 = H / 16;
+  static constexpr int TL = 16, NL = 16, NT = TL * NL;
+  static constexpr int EX = R1 * (R2 + 1);
+  static constexpr int LS = (EX > H ? EX : H) + 1;
+};
+constexpr bool half_form(int n) { return n == 64 || n == 96 || n == 128 || n == 192 || n == 256 || n == 384; }
+template <int N>
+__global__ void __launch_bounds__(256) k_fwd_zh(const JobIO io, float2* __restrict__ f1, size_t wstride, int n_lines,
+                                                int Kz, const float2* __restrict__ tw) {
+  const float* __restrict__ delta = io.delta[blockIdx.z];
+  f1 = job_ptr(f1, wstride);
+  using S = HalfShape<N>;
+  constexpr int H = S::H, TL = S::TL, NL = S::NL, LS = S::LS;
+  __shared__ float2 tws[N];  // W_N^m
+  __shared__ float2 twh[H];  // W_H^m = W_N^(2m)
+  __shared__ float2 scr[NL * LS];  // the FFT exchange, then Z
+  const int tid = threadIdx.x;
+  for (int e = tid; e < N; e += S::NT) {
+    const float2 w = tw[e];
+    tws[e] = w;
+    if (!(e & 1)) twh[e >> 1] = w;
+  }
+  __syncthreads();
+  const int ln = tid / TL, tl = tid % TL;
+  const int line = blockIdx.x * NL + ln;
+  const bool live = line < n_lines;
+  const size_t off = (size_t)(live ? line : 0) * N;
+  const float2* z = reinterpret_cast<const float2*>(delta + off);
+  const float2* wz = io.window ? reinterpret_cast<const float2*>(io.window + off) : nullptr;  // optional window
+  float2* zl = scr + ln * LS;
+  fft2_line<H, -1, true, 1, S::R1>(
+      zl, tl, twh,
+      [&](int m) {
+        if (!live) return make_float2(0.f, 0.f);
+        float2 v = z[m];
+        if (wz) {
+          const float2 w = wz[m];
+          v.x *= w.x;
+          v.y *= w.y;
+        }
+        return v;
+      },
+      [&](int k, float2 v) { zl[k] = v; });
+  __syncthreads();
+  const int line0 = blockIdx.x * NL;
+  int nl = n_lines - line0;
+  if (nl > NL) nl = NL;
+  for (int e = tid; e < nl * Kz; e += S::NT) {
+    const int ll = e / Kz, k = e % Kz;
+    const float2* zz = scr + ll * LS;
+    const int kh = k % H;
+    const float2 a = zz[kh], b = zz[(H - kh) % H];
+    const float ex = 0.5f * (a.x + b.x), ey = 0.5f * (a.y - b.y);   // E[k]
+    const float ox = 0.5f * (a.y + b.y), oy = -0.5f * (a.x - b.x);  // O[k]
+    const float2 w = tws[k];                                        // k < Kz <= N/2 + 1
+    f1[(size_t)(line0 + ll) * Kz + k] = make_float2(ex + w.x * ox - w.y * oy, ey + w.x * oy + w.y * ox);
   }
 }
 
@@ -410,10 +465,23 @@ int tile_width_z(int M, bool dbl) {
 hipError_t launch_fwd_z(const pb3_plan& p, const Exec& x, hipStream_t s) {
   const int n_pairs = p.Nx * p.Ny / 2;
   PB3_FFT_LEN(p.Nz, {
-    using S = PairShape<LL, 8, fwd_z_pad(LL)>;
-    hipLaunchKernelGGL(k_fwd_z2<LL>, dim3((n_pairs + S::TP - 1) / S::TP, 1, x.n_jobs), dim3(S::NT), 0, s, x.io,
-                       x.ws.f1, x.wstride, n_pairs, p.Kz, p.d.tw_n[2]);
-    return hipGetLastError();
+    if constexpr (half_form(LL)) {
+      const int n_lines = p.Nx * p.Ny;
+      using S = HalfShape<LL>;
+      hipLaunchKernelGGL(k_fwd_zh<LL>, dim3((n_lines + S::NL - 1) / S::NL, 1, x.n_jobs), dim3(S::NT), 0, s, x.io,
+                         x.ws.f1, x.wstride, n_lines, p.Kz, p.d.tw_n[2]);
+      return hipGetLastError();
+    }
+    break;
+  });
+  PB3_FFT_LEN(p.Nz, {
+    if constexpr (!half_form(LL)) {
+      using S = PairShape<LL, 8>;
+      hipLaunchKernelGGL(k_fwd_z2<LL>, dim3((n_pairs + S::TP - 1) / S::TP, 1, x.n_jobs), dim3(S::NT), 0, s, x.io,
+                         x.ws.f1, x.wstride, n_pairs, p.Kz, p.d.tw_n[2]);
+      return hipGetLastError();
+    }
+    break;
   });
   return hipErrorInvalidValue;
 }
