@@ -795,11 +795,13 @@ template <typename W>
 static pb3_status enqueue_w(const pb3_plan& p, const Exec& x, bool do_pk, bool do_bk, pb3_precision prec,
                             hipStream_t s, W&& wrap) {
   pb3_status st;
+  // with both spectra, the power spectrum's per-bin sums run in the reduction's launch
+  const bool merge = do_pk && do_bk && !p.trip.empty();
   if ((st = wrap(ST_FWD_Z, "fwd_z", [&] { return launch_fwd_z(p, x, s); })) != PB3_OK) return st;
   if ((st = wrap(ST_FWD_Y, "fwd_y", [&] { return launch_fwd_y(p, x, s); })) != PB3_OK) return st;
   if ((st = wrap(ST_FWD_X, "fwd_x", [&] { return launch_fwd_x(p, x, s); })) != PB3_OK) return st;
   if (do_pk) {
-    if ((st = wrap(ST_POWER, "power", [&] { return launch_power(p, x, s); })) != PB3_OK) return st;
+    if ((st = wrap(ST_POWER, "power", [&] { return launch_power(p, x, s, !merge); })) != PB3_OK) return st;
   }
   if (do_bk) {
     if ((st = wrap(ST_INV_X, "inv_x", [&] { return launch_inv_x(p, x, s); })) != PB3_OK) return st;
@@ -812,7 +814,7 @@ static pb3_status enqueue_w(const pb3_plan& p, const Exec& x, bool do_pk, bool d
       if ((st = wrap(ST_INV_Z, "inv_z", [&] { return launch_inv_z(p, x, s); })) != PB3_OK) return st;
       if ((st = wrap(ST_CONTRACT, "contract", [&] { return launch_contract(p, x, prec, s); })) != PB3_OK) return st;
     }
-    if ((st = wrap(ST_REDUCE, "reduce", [&] { return launch_reduce(p, x, s); })) != PB3_OK) return st;
+    if ((st = wrap(ST_REDUCE, "reduce", [&] { return launch_reduce(p, x, s, merge); })) != PB3_OK) return st;
   }
   return PB3_OK;
 }
@@ -827,7 +829,7 @@ pb3_status enqueue(const pb3_plan& p, const Exec& x, bool do_pk, bool do_bk, pb3
 // kernel launches of one enqueue (for reporting)
 int launches_per_sequence(const pb3_plan& p, bool do_pk, bool do_bk) {
   int n = 3;
-  if (do_pk) n += 2;
+  if (do_pk) n += (do_bk && !p.trip.empty()) ? 1 : 2;
   if (do_bk) {
     n += 2 + 2;
     if (p.fused) n += 1;

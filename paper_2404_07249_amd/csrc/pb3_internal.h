@@ -203,12 +203,14 @@ int launches_per_sequence(const pb3_plan& p, bool do_pk, bool do_bk);
 hipError_t launch_fwd_z(const pb3_plan& p, const Exec& x, hipStream_t s);
 hipError_t launch_fwd_y(const pb3_plan& p, const Exec& x, hipStream_t s);
 hipError_t launch_fwd_x(const pb3_plan& p, const Exec& x, hipStream_t s);
-hipError_t launch_power(const pb3_plan& p, const Exec& x, hipStream_t s);
+// final = false leaves the per-bin sums to launch_reduce(..., with_pk = true).
+hipError_t launch_power(const pb3_plan& p, const Exec& x, hipStream_t s, bool final);
 hipError_t launch_inv_x(const pb3_plan& p, const Exec& x, hipStream_t s);
 hipError_t launch_inv_y(const pb3_plan& p, const Exec& x, hipStream_t s);
 hipError_t launch_inv_z(const pb3_plan& p, const Exec& x, hipStream_t s);
 hipError_t launch_contract(const pb3_plan& p, const Exec& x, pb3_precision prec, hipStream_t s);
-hipError_t launch_reduce(const pb3_plan& p, const Exec& x, hipStream_t s);
+// with_pk: also the power spectrum's per-bin sums (after launch_power(..., false)).
+hipError_t launch_reduce(const pb3_plan& p, const Exec& x, hipStream_t s, bool with_pk);
 // window moments and P / <w^2>, B / <w^3> (scratch: 2 + 2 kWindowBlocks doubles;
 // scratch[0..1] receive <w^2>, <w^3>)
 hipError_t launch_window(long n, const float* w, double* pk, int nb, double* bk, int nt, double* scratch,

@@ -55,25 +55,42 @@ __global__ void __launch_bounds__(256) k_power_chunks(const float2* __restrict__
 }
 
 // One wave per bin: lane l sums the bin's chunks l, l + 64, ... and the
-// lanes combine in a fixed-order tree.
-__global__ void __launch_bounds__(64) k_power_final(const double* __restrict__ part,
-                                                    const int32_t* __restrict__ chunk_first, int nb,
-                                                    const double* __restrict__ scale, const JobIO io, size_t wstride,
-                                                    double shift) {
-  part = job_ptr(part, wstride);
-  double* __restrict__ pk = io.pk[blockIdx.z];
-  __shared__ double red[64];
-  const int b = blockIdx.x, l = threadIdx.x;
+// lanes combine in a fixed-order tree in red[64] (the wave's own).  Every
+// thread of the work-group calls it (it holds work-group barriers); a wave
+// with valid = false takes part in the barriers only.
+__device__ __forceinline__ void power_bin_final(const double* __restrict__ part, const int32_t* __restrict__ chunk_first,
+                                                int b, bool valid, double* red, const double* __restrict__ scale,
+                                                double shift, double* __restrict__ pk) {
+  const int l = threadIdx.x & 63;
   double s = 0.0;
-  for (int c = chunk_first[b] + l; c < chunk_first[b + 1]; c += 64) s += part[c];
+  if (valid)
+    for (int c = chunk_first[b] + l; c < chunk_first[b + 1]; c += 64) s += part[c];
   red[l] = s;
   __syncthreads();
   for (int h = 32; h > 0; h >>= 1) {
     if (l < h) red[l] += red[l + h];
     __syncthreads();
   }
-  if (l == 0) pk[b] = red[0] * scale[b] - shift;
+  if (valid && l == 0) pk[b] = red[0] * scale[b] - shift;
 }
+
+__global__ void __launch_bounds__(64) k_power_final(const double* __restrict__ part,
+                                                    const int32_t* __restrict__ chunk_first, int nb,
+                                                    const double* __restrict__ scale, const JobIO io, size_t wstride,
+                                                    double shift) {
+  __shared__ double red[64];
+  power_bin_final(job_ptr(part, wstride), chunk_first, blockIdx.x, true, red, scale, shift, io.pk[blockIdx.z]);
+}
+
+// The power spectrum's last step inside the bispectrum's final launch, when
+// one call computes both: blocks past the reduction's take four bins each.
+struct PowerFinal {
+  const double* part = nullptr;  // chunk partials (per job at the workspace stride)
+  const int32_t* chunk_first = nullptr;
+  const double* scale = nullptr;
+  double shift = 0.0;
+  int nb = 0;
+};
 
 // ------------------------------------------------ simple triplet contraction
 // Reference-structure contraction: every work-group takes a contiguous
@@ -179,9 +196,17 @@ __global__ void k_reduce_slices(const float* __restrict__ part, int n_wg, int pa
   o[3] = a3;
 }
 
-__global__ void k_reduce_final(const double* __restrict__ rsl, int part_len, const int32_t* __restrict__ map,
-                               const double* __restrict__ fac, int n_out, const JobIO io, size_t wstride,
-                               const double* __restrict__ bias) {
+__global__ void __launch_bounds__(256) k_reduce_final(const double* __restrict__ rsl, int part_len,
+                                                      const int32_t* __restrict__ map, const double* __restrict__ fac,
+                                                      int n_out, const JobIO io, size_t wstride,
+                                                      const double* __restrict__ bias, int n_red, PowerFinal pf) {
+  if ((int)blockIdx.x >= n_red) {
+    __shared__ double red[256];
+    const int b = ((int)blockIdx.x - n_red) * 4 + (int)(threadIdx.x >> 6);
+    power_bin_final(job_ptr(pf.part, wstride), pf.chunk_first, b, b < pf.nb, red + (threadIdx.x & ~63u), pf.scale,
+                    pf.shift, io.pk[blockIdx.z]);
+    return;
+  }
   rsl = job_ptr(rsl, wstride);
   double* __restrict__ out = io.bk[blockIdx.z];
   int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -407,11 +432,11 @@ hipError_t launch_window(long n, const float* w, double* pk, int nb, double* bk,
   return hipGetLastError();
 }
 
-hipError_t launch_power(const pb3_plan& p, const Exec& x, hipStream_t s) {
+hipError_t launch_power(const pb3_plan& p, const Exec& x, hipStream_t s, bool final) {
   hipLaunchKernelGGL(k_power_chunks, dim3(p.n_chunks, 1, x.n_jobs), dim3(256), 0, s, x.ws.dc, p.d.modes, p.d.chunk,
                      x.ws.ppart, x.wstride, (const double*)p.d.mode_w);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !final) return e;
   hipLaunchKernelGGL(k_power_final, dim3(p.nb, 1, x.n_jobs), dim3(64), 0, s, x.ws.ppart, p.d.chunk_first, p.nb,
                      p.d.pk_scale, x.io, x.wstride, p.pk_shift);
   return hipGetLastError();
@@ -456,15 +481,18 @@ hipError_t launch_contract(const pb3_plan& p, const Exec& x, pb3_precision prec,
   return launch_contract_mfma(p, x, prec == PB3_MIXED_BF16X3, s);
 }
 
-hipError_t launch_reduce(const pb3_plan& p, const Exec& x, hipStream_t s) {
+hipError_t launch_reduce(const pb3_plan& p, const Exec& x, hipStream_t s, bool with_pk) {
   int n_out = (int)(p.trip.size() / 3);
   if (n_out == 0) return hipSuccess;
+  const int n_red = (n_out + 255) / 256;
+  PowerFinal pf;
+  if (with_pk) pf = PowerFinal{x.ws.ppart, p.d.chunk_first, p.d.pk_scale, p.pk_shift, p.nb};
   hipLaunchKernelGGL(k_reduce_slices, dim3((p.part_len / 4 + 255) / 256, kReduceSlices, x.n_jobs), dim3(256), 0, s,
                      x.ws.part, p.contract_wgs, p.part_len, x.ws.rsl, x.wstride);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce_final, dim3((n_out + 255) / 256, 1, x.n_jobs), dim3(256), 0, s, x.ws.rsl, p.part_len,
-                     p.d.out_map, p.d.inv_counts, n_out, x.io, x.wstride, (const double*)p.d.bk_bias);
+  hipLaunchKernelGGL(k_reduce_final, dim3(n_red + (pf.nb + 3) / 4, 1, x.n_jobs), dim3(256), 0, s, x.ws.rsl, p.part_len,
+                     p.d.out_map, p.d.inv_counts, n_out, x.io, x.wstride, (const double*)p.d.bk_bias, n_red, pf);
   return hipGetLastError();
 }
 
@@ -548,7 +576,7 @@ pb3_status run_masked_power(pb3_plan& p, const float* data, const float* window,
   }
   // numerator from the data's box power spectrum, then the solve
   x.io.pk[0] = pbox;
-  if (!forward(data, nullptr) || !chk(launch_power(p, x, s), "masked power: power")) return st;
+  if (!forward(data, nullptr) || !chk(launch_power(p, x, s, true), "masked power: power")) return st;
   const double scale = 0.5 / ((double)n3 * n_grf);
   hipLaunchKernelGGL(k_masked_solve, dim3(1), dim3(64), sizeof(double) * nb * (nb + 1), s, acc, scale, pbox,
                      p.d.nmodes_d, nb, pk_out, f_out);
@@ -629,7 +657,7 @@ pb3_status run_multipoles(pb3_plan& p, const float* delta, double* pk_out, doubl
       io.bk[0] = bk_out + (size_t)l * nt;
       hipLaunchKernelGGL(k_reduce_final, dim3((nt + 255) / 256, 1, 1), dim3(256), 0, s, x.ws.rsl, p.part_len,
                          p.d.out_map, p.d.ml_fac + (size_t)l * nt, nt, io, (size_t)0,
-                         l == 0 ? (const double*)p.d.bk_bias : nullptr);
+                         l == 0 ? (const double*)p.d.bk_bias : nullptr, (nt + 255) / 256, PowerFinal{});
       if (!chk(hipGetLastError(), "multipoles: reduce")) return st;
     }
   } else {

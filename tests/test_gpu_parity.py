@@ -201,11 +201,21 @@ def test_translation_invariance_full_size(torch_cuda):
     assert np.all(np.abs(bk1[pick] - bk2[pick]) <= lim)
 
 
-def test_power_alone_equals_polyspectra_and_streams(torch_cuda):
+@pytest.mark.parametrize("case", ["c1", "48^3x13"])
+def test_power_alone_equals_polyspectra_and_streams(torch_cuda, case):
+    """P from a power-only call (its own final launch) equals P from a P + B
+    call (per-bin sums inside the bispectrum's final launch) bit for bit,
+    also with a bin count that leaves part of the last four-bin block idle
+    and in a batch."""
     import paper_2404_07249_amd as pb3
 
     torch = torch_cuda
-    d, cfg = field_for("c1")
+    if case == "c1":
+        d, cfg = field_for("c1")
+    else:
+        cfg = {"n": 48, "box": 900.0, "edges": kf_edges(13)}
+        d = quadratic_field(48, 900.0, 1.0, 48013).astype(np.float32)
+    _say(f"[case] power alone vs polyspectra {case}")
     plan = pb3.Plan(cfg["n"], cfg["box"], cfg["edges"], ext_workspace=True)
     ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
     plan.bind_workspace(ws)
@@ -219,6 +229,13 @@ def test_power_alone_equals_polyspectra_and_streams(torch_cuda):
     bk_c = plan.bispectrum(x)
     torch.cuda.synchronize()
     assert np.array_equal(bk_b.cpu().numpy(), bk_c.cpu().numpy())
+    if case != "c1":
+        other = pb3.Plan(cfg["n"], cfg["box"], cfg["edges"])
+        xs = [x, 0.5 * x, x * x]
+        bt = pb3.Batch([other] * len(xs))
+        pks, _ = bt.run(xs, precision="mixed")
+        for i, xi in enumerate(xs):
+            assert np.array_equal(pks[i].cpu().numpy(), other.power(xi).cpu().numpy()), i
 
 
 def test_argument_errors_on_device(torch_cuda):
