@@ -41,36 +41,78 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
 typedef float f2_t __attribute__((ext_vector_type(2)));
 typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2_t;
 
+// Tile layouts.  A pair block (p, q, s) is 16 pair rows: row i pairs bin
+// 16 p + i with bin 16 q + ((i - s) mod 16); a tile is a pair block against
+// one 16-bin column block; cmask holds the block's column blocks.
+//   kLayoutAB: every pair a <= b (p <= q; s = 0..8 inside a group, 0..15
+//     across two), columns c >= 16 q.  Every triplet is read at (pair
+//     (a, b), column c), as the column operand must be for the multipoles,
+//     whose Legendre weight sits on the c leg.
+//   kLayoutDiag: only the pairs inside one group (p = q), against every
+//     column block.  S_abc is symmetric, and a triplet a <= b <= c always has
+//     two bins in one group when there are at most two groups (with three,
+//     the triplets with a, b, c in groups 0, 1, 2 take the cross blocks
+//     (0, 1, s) against column block 2).  At two groups this is 18 pair
+//     blocks and 36 tiles instead of 34 and 43: fewer pair products to form
+//     and split on the VALU, fewer MFMAs.
+constexpr int kLayoutAB = 0, kLayoutDiag = 1;
+
 struct PairBlock {
   int p, q, s;
+  unsigned cmask;
 };
 
-constexpr PairBlock pair_block(int nq, int k) {
-  for (int p = 0; p < nq; ++p)
-    for (int q = p; q < nq; ++q) {
-      int ns = (p == q) ? 9 : 16;
-      if (k < ns) return PairBlock{p, q, k};
-      k -= ns;
+constexpr unsigned all_cols(int nq) { return (1u << nq) - 1u; }
+constexpr unsigned cols_from(int nq, int q) { return all_cols(nq) & ~((1u << q) - 1u); }
+
+constexpr PairBlock pair_block(int L, int nq, int k) {
+  if (L == kLayoutAB) {
+    for (int p = 0; p < nq; ++p)
+      for (int q = p; q < nq; ++q) {
+        int ns = (p == q) ? 9 : 16;
+        if (k < ns) return PairBlock{p, q, k, cols_from(nq, q)};
+        k -= ns;
+      }
+  } else {
+    // group 0, then (nq == 3) the cross blocks of groups 0 and 1, then the
+    // other groups
+    for (int p = 0; p < nq; ++p) {
+      if (k < 9) return PairBlock{p, p, k, all_cols(nq)};
+      k -= 9;
+      if (p == 0 && nq == 3) {
+        if (k < 16) return PairBlock{0, 1, k, 1u << 2};
+        k -= 16;
+      }
     }
-  return PairBlock{-1, -1, -1};
+  }
+  return PairBlock{-1, -1, -1, 0u};
 }
-constexpr int n_pair_blocks(int nq) { return nq * 9 + (nq * (nq - 1) / 2) * 16; }
+constexpr int n_pair_blocks(int L, int nq) {
+  return L == kLayoutAB ? nq * 9 + (nq * (nq - 1) / 2) * 16 : nq * 9 + (nq == 3 ? 16 : 0);
+}
+constexpr int popc(unsigned m) { return m ? (int)(m & 1u) + popc(m >> 1) : 0; }
 // tiles (pair block x column block) in pair blocks [0, k)
-constexpr int tiles_before(int nq, int k) {
+constexpr int tiles_before(int L, int nq, int k) {
   int t = 0;
-  for (int j = 0; j < k; ++j) t += nq - pair_block(nq, j).q;
+  for (int j = 0; j < k; ++j) t += popc(pair_block(L, nq, j).cmask);
   return t;
 }
-constexpr int n_tiles(int nq) { return tiles_before(nq, n_pair_blocks(nq)); }
+constexpr int n_tiles(int L, int nq) { return tiles_before(L, nq, n_pair_blocks(L, nq)); }
+// tile offset of column block cb within its pair block
+constexpr int col_rank(unsigned cmask, int cb) { return popc(cmask & ((1u << cb) - 1u)); }
 
-// Pair-block ranges processed by one launch ("group"); at most ~48 tiles
-// of accumulators per wave.
-constexpr int n_groups(int nq) { return nq <= 2 ? 1 : 3; }
-constexpr int group_begin(int nq, int g) {
-  if (nq <= 2) return g == 0 ? 0 : n_pair_blocks(nq);
-  // nq == 3 pair blocks in order: (0,0)9 (0,1)16 (0,2)16 (1,1)9 (1,2)16 (2,2)9
-  // tiles per block: 3, 2, 1, 2, 1, 1 -> groups of 43, 32, 43 tiles
-  return g == 0 ? 0 : g == 1 ? 9 + 8 : g == 2 ? 9 + 16 + 16 : n_pair_blocks(nq);
+// Pair-block ranges processed by one launch ("group") of the tile-staged
+// kernel; at most ~54 tiles of accumulators per launch.
+constexpr int n_groups(int L, int nq) { return nq <= 2 ? 1 : (L == kLayoutAB ? 3 : 2); }
+constexpr int group_begin(int L, int nq, int g) {
+  if (nq <= 2) return g == 0 ? 0 : n_pair_blocks(L, nq);
+  if (L == kLayoutAB) {
+    // nq == 3 pair blocks in order: (0,0)9 (0,1)16 (0,2)16 (1,1)9 (1,2)16 (2,2)9
+    // tiles per block: 3, 2, 1, 2, 1, 1 -> groups of 43, 32, 43 tiles
+    return g == 0 ? 0 : g == 1 ? 9 + 8 : g == 2 ? 9 + 16 + 16 : n_pair_blocks(L, nq);
+  }
+  // (0,0)9 x 3 + (0,1)16 x 1 = 43 tiles, then (1,1)9 + (2,2)9 x 3 = 54 tiles
+  return g == 0 ? 0 : g == 1 ? 25 : n_pair_blocks(L, nq);
 }
 
 __device__ __forceinline__ float ror16(float x, int s) {
@@ -120,13 +162,13 @@ __device__ __forceinline__ void split8(const float* v, bf16x8_t& hi, bf16x8_t& l
   }
 }
 
-template <int NQ, bool MIXED, int K, int K1, int T0>
+template <int NQ, int L, bool MIXED, int K, int K1, int T0>
 __device__ __forceinline__ void do_blocks(const float (&gv)[NQ][8], const bf16x8_t (&bh)[NQ], const bf16x8_t (&bl)[NQ],
                                           f32x4_t* acc, const SplitSel& sel) {
 #pragma clang fp contract(off)
   if constexpr (K < K1) {
-    constexpr PairBlock pb = pair_block(NQ, K);
-    constexpr int tb = tiles_before(NQ, K) - T0;
+    constexpr PairBlock pb = pair_block(L, NQ, K);
+    constexpr int tb = tiles_before(L, NQ, K) - T0;
     float a[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) a[j] = gv[pb.p][j] * ror16(gv[pb.q][j], pb.s);
@@ -134,20 +176,23 @@ __device__ __forceinline__ void do_blocks(const float (&gv)[NQ][8], const bf16x8
       bf16x8_t ah, al;
       split8(a, ah, al, sel);
 #pragma unroll
-      for (int cb = pb.q; cb < NQ; ++cb) {
-        f32x4_t c = acc[tb + cb - pb.q];
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[cb], c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[cb], c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[cb], c, 0, 0, 0);
-        acc[tb + cb - pb.q] = c;
+      for (int cb = 0; cb < NQ; ++cb) {
+        if ((pb.cmask >> cb) & 1u) {
+          const int t = tb + col_rank(pb.cmask, cb);
+          f32x4_t c = acc[t];
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[cb], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[cb], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[cb], c, 0, 0, 0);
+          acc[t] = c;
+        }
       }
-      do_blocks<NQ, MIXED, K + 1, K1, T0>(gv, bh, bl, acc, sel);
+      do_blocks<NQ, L, MIXED, K + 1, K1, T0>(gv, bh, bl, acc, sel);
     } else {
       // FP32: interleave this block's MFMA chains with the next block's so
       // consecutive MFMAs do not wait on the same accumulator
       constexpr bool PAIRED = K + 1 < K1;
-      constexpr PairBlock pn = pair_block(NQ, PAIRED ? K + 1 : K);
-      constexpr int tn = tiles_before(NQ, PAIRED ? K + 1 : K) - T0;
+      constexpr PairBlock pn = pair_block(L, NQ, PAIRED ? K + 1 : K);
+      constexpr int tn = tiles_before(L, NQ, PAIRED ? K + 1 : K) - T0;
       float an[8];
       if constexpr (PAIRED) {
 #pragma unroll
@@ -156,15 +201,21 @@ __device__ __forceinline__ void do_blocks(const float (&gv)[NQ][8], const bf16x8
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
 #pragma unroll
-        for (int cb = pb.q; cb < NQ; ++cb)
-          acc[tb + cb - pb.q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], gv[cb][j], acc[tb + cb - pb.q], 0, 0, 0);
+        for (int cb = 0; cb < NQ; ++cb)
+          if ((pb.cmask >> cb) & 1u) {
+            const int t = tb + col_rank(pb.cmask, cb);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], gv[cb][j], acc[t], 0, 0, 0);
+          }
         if constexpr (PAIRED) {
 #pragma unroll
-          for (int cb = pn.q; cb < NQ; ++cb)
-            acc[tn + cb - pn.q] = __builtin_amdgcn_mfma_f32_16x16x4f32(an[j], gv[cb][j], acc[tn + cb - pn.q], 0, 0, 0);
+          for (int cb = 0; cb < NQ; ++cb)
+            if ((pn.cmask >> cb) & 1u) {
+              const int t = tn + col_rank(pn.cmask, cb);
+              acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(an[j], gv[cb][j], acc[t], 0, 0, 0);
+            }
         }
       }
-      do_blocks<NQ, MIXED, (PAIRED ? K + 2 : K + 1), K1, T0>(gv, bh, bl, acc, sel);
+      do_blocks<NQ, L, MIXED, (PAIRED ? K + 2 : K + 1), K1, T0>(gv, bh, bl, acc, sel);
     }
   }
 }
@@ -172,18 +223,29 @@ __device__ __forceinline__ void do_blocks(const float (&gv)[NQ][8], const bf16x8
 // Pair blocks [k0, k1) are shared out between NG wave groups that stream
 // the same voxels; boundaries balance an estimated cost per block (its
 // split on the VALU plus its tiles on the matrix core).
-constexpr int block_cost(int nq, int k) { return 96 + 48 * (nq - pair_block(nq, k).q); }
-constexpr int group_bound(int nq, int k0, int k1, int ng, int g) {
+constexpr int block_cost(int L, int nq, int k) { return 96 + 48 * popc(pair_block(L, nq, k).cmask); }
+constexpr int group_bound(int L, int nq, int k0, int k1, int ng, int g) {
   if (g <= 0) return k0;
   if (g >= ng) return k1;
   int total = 0;
-  for (int k = k0; k < k1; ++k) total += block_cost(nq, k);
+  for (int k = k0; k < k1; ++k) total += block_cost(L, nq, k);
   int acc = 0;
   for (int k = k0; k < k1; ++k) {
     if (acc * ng >= total * g) return k;
-    acc += block_cost(nq, k);
+    acc += block_cost(L, nq, k);
   }
   return k1;
+}
+// union of the column blocks and of the row groups of pair blocks [b, e)
+constexpr unsigned range_cols(int L, int nq, int b, int e) {
+  unsigned m = 0u;
+  for (int k = b; k < e; ++k) m |= pair_block(L, nq, k).cmask;
+  return m;
+}
+constexpr unsigned range_rows(int L, int nq, int b, int e) {
+  unsigned m = 0u;
+  for (int k = b; k < e; ++k) m |= (1u << pair_block(L, nq, k).p) | (1u << pair_block(L, nq, k).q);
+  return m;
 }
 
 // One launch covers pair blocks [K0, K1) (tiles [T0, T1)), shared out
@@ -205,40 +267,43 @@ template <int NQ> struct TileStage {
   __bf16 lo[16 * NQ * kPitchH];
 };
 
-template <int NQ, int K0, int K1, int G> struct GroupRange {
-  static constexpr int b = group_bound(NQ, K0, K1, kGroups, G);
-  static constexpr int e = group_bound(NQ, K0, K1, kGroups, G + 1);
-  static constexpr int t0 = tiles_before(NQ, b) - tiles_before(NQ, K0);  // offset in this launch's tiles
-  static constexpr int nt = tiles_before(NQ, e) - tiles_before(NQ, b);
-  static constexpr int qmin = b < e ? pair_block(NQ, b).q : NQ;         // lowest column block used
+template <int NQ, int L, int K0, int K1, int G> struct GroupRange {
+  static constexpr int b = group_bound(L, NQ, K0, K1, kGroups, G);
+  static constexpr int e = group_bound(L, NQ, K0, K1, kGroups, G + 1);
+  static constexpr int t0 = tiles_before(L, NQ, b) - tiles_before(L, NQ, K0);  // offset in this launch's tiles
+  static constexpr int nt = tiles_before(L, NQ, e) - tiles_before(L, NQ, b);
+  static constexpr unsigned cols = range_cols(L, NQ, b, e);  // column blocks used
+  static constexpr unsigned rows = range_rows(L, NQ, b, e);  // groups whose FP32 fields form the pairs
 };
 
-template <int NQ, bool MIXED, int K0, int K1, int G, int NTMAX>
+template <int NQ, int L, bool MIXED, int K0, int K1, int G, int NTMAX>
 __device__ __forceinline__ void contract_tile(const TileStage<NQ>& st, int i, int grp, int wig, f32x4_t (&acc)[NTMAX],
                                               const SplitSel& sel) {
-  using R = GroupRange<NQ, K0, K1, G>;
+  using R = GroupRange<NQ, L, K0, K1, G>;
   float gv[NQ][8];
   bf16x8_t bh[NQ], bl[NQ];
   const int off = 32 * wig + 8 * grp;
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
-    const float4* pf = reinterpret_cast<const float4*>(st.f + (16 * q + i) * kPitchF + off);
-    float4 x0 = pf[0], x1 = pf[1];
-    gv[q][0] = x0.x; gv[q][1] = x0.y; gv[q][2] = x0.z; gv[q][3] = x0.w;
-    gv[q][4] = x1.x; gv[q][5] = x1.y; gv[q][6] = x1.z; gv[q][7] = x1.w;
+    if (((R::rows | (MIXED ? 0u : R::cols)) >> q) & 1u) {
+      const float4* pf = reinterpret_cast<const float4*>(st.f + (16 * q + i) * kPitchF + off);
+      float4 x0 = pf[0], x1 = pf[1];
+      gv[q][0] = x0.x; gv[q][1] = x0.y; gv[q][2] = x0.z; gv[q][3] = x0.w;
+      gv[q][4] = x1.x; gv[q][5] = x1.y; gv[q][6] = x1.z; gv[q][7] = x1.w;
+    }
     if constexpr (MIXED) {
-      if (q >= R::qmin) {
+      if ((R::cols >> q) & 1u) {
         bh[q] = *reinterpret_cast<const bf16x8_t*>(st.hi + (16 * q + i) * kPitchH + off);
         bl[q] = *reinterpret_cast<const bf16x8_t*>(st.lo + (16 * q + i) * kPitchH + off);
       }
     }
   }
-  do_blocks<NQ, MIXED, R::b, R::e, tiles_before(NQ, R::b)>(gv, bh, bl, acc, sel);
+  do_blocks<NQ, L, MIXED, R::b, R::e, tiles_before(L, NQ, R::b)>(gv, bh, bl, acc, sel);
 }
 
-template <int NQ, int K0, int K1, int G, int NTMAX>
+template <int NQ, int L, int K0, int K1, int G, int NTMAX>
 __device__ __forceinline__ void reduce_group(float* red, const f32x4_t (&acc)[NTMAX], int w, int i, int grp) {
-  using R = GroupRange<NQ, K0, K1, G>;
+  using R = GroupRange<NQ, L, K0, K1, G>;
   float* r = red + R::t0 * 256;
 #pragma unroll
   for (int t = 0; t < R::nt; ++t)
@@ -252,9 +317,9 @@ __device__ __forceinline__ void reduce_group(float* red, const f32x4_t (&acc)[NT
 // Single-wave groups: the wave's tiles go straight from its accumulators to
 // the chunk's partial vector (the same layout reduce_group builds), and the
 // accumulators restart at zero.
-template <int NQ, int K0, int K1, int G, int NTMAX>
+template <int NQ, int L, int K0, int K1, int G, int NTMAX>
 __device__ __forceinline__ void flush_group(float* __restrict__ dst, f32x4_t (&acc)[NTMAX], int i, int grp) {
-  using R = GroupRange<NQ, K0, K1, G>;
+  using R = GroupRange<NQ, L, K0, K1, G>;
   float* r = dst + R::t0 * 256;
 #pragma unroll
   for (int t = 0; t < R::nt; ++t) {
@@ -264,11 +329,11 @@ __device__ __forceinline__ void flush_group(float* __restrict__ dst, f32x4_t (&a
   }
 }
 
-template <int NQ, int K0, int K1> constexpr int max_group_tiles() {
-  int m = GroupRange<NQ, K0, K1, 0>::nt;
-  m = GroupRange<NQ, K0, K1, 1>::nt > m ? GroupRange<NQ, K0, K1, 1>::nt : m;
-  m = GroupRange<NQ, K0, K1, 2>::nt > m ? GroupRange<NQ, K0, K1, 2>::nt : m;
-  m = GroupRange<NQ, K0, K1, 3>::nt > m ? GroupRange<NQ, K0, K1, 3>::nt : m;
+template <int NQ, int L, int K0, int K1> constexpr int max_group_tiles() {
+  int m = GroupRange<NQ, L, K0, K1, 0>::nt;
+  m = GroupRange<NQ, L, K0, K1, 1>::nt > m ? GroupRange<NQ, L, K0, K1, 1>::nt : m;
+  m = GroupRange<NQ, L, K0, K1, 2>::nt > m ? GroupRange<NQ, L, K0, K1, 2>::nt : m;
+  m = GroupRange<NQ, L, K0, K1, 3>::nt > m ? GroupRange<NQ, L, K0, K1, 3>::nt : m;
   return m < 1 ? 1 : m;
 }
 
@@ -323,7 +388,7 @@ __device__ __forceinline__ void tile_store(TileStage<NQ>& st, const TileRegs<NQ>
   }
 }
 
-template <int NQ, bool MIXED, int K0, int K1>
+template <int NQ, int L, bool MIXED, int K0, int K1>
 __global__ void __launch_bounds__(kContractThreads) k_contract_mfma(const float* __restrict__ g, long mvox, long vpw,
                                                                     float* __restrict__ part, int part_len,
                                                                     unsigned sel_lo, unsigned sel_hi,
@@ -333,9 +398,9 @@ __global__ void __launch_bounds__(kContractThreads) k_contract_mfma(const float*
   const bool cols = gc != nullptr;  // separate column fields (mixed precision only)
   g = job_ptr(g, wstride);
   part = job_ptr(part, wstride);
-  constexpr int T0 = tiles_before(NQ, K0);
-  constexpr int T1 = tiles_before(NQ, K1);
-  constexpr int NTMAX = max_group_tiles<NQ, K0, K1>();
+  constexpr int T0 = tiles_before(L, NQ, K0);
+  constexpr int T1 = tiles_before(L, NQ, K1);
+  constexpr int NTMAX = max_group_tiles<NQ, L, K0, K1>();
   constexpr int RED = (T1 - T0) * 256;
   constexpr int STAGE_FLOATS = (2 * sizeof(TileStage<NQ>) + 3) / 4;
   __shared__ __align__(16) float smem[RED > STAGE_FLOATS ? RED : STAGE_FLOATS];
@@ -370,10 +435,10 @@ __global__ void __launch_bounds__(kContractThreads) k_contract_mfma(const float*
     }
     const TileStage<NQ>& cur = stage[m & 1];
     switch (gi) {
-      case 0: contract_tile<NQ, MIXED, K0, K1, 0>(cur, i, grp, wig, acc, sel); break;
-      case 1: contract_tile<NQ, MIXED, K0, K1, 1>(cur, i, grp, wig, acc, sel); break;
-      case 2: contract_tile<NQ, MIXED, K0, K1, 2>(cur, i, grp, wig, acc, sel); break;
-      default: contract_tile<NQ, MIXED, K0, K1, 3>(cur, i, grp, wig, acc, sel); break;
+      case 0: contract_tile<NQ, L, MIXED, K0, K1, 0>(cur, i, grp, wig, acc, sel); break;
+      case 1: contract_tile<NQ, L, MIXED, K0, K1, 1>(cur, i, grp, wig, acc, sel); break;
+      case 2: contract_tile<NQ, L, MIXED, K0, K1, 2>(cur, i, grp, wig, acc, sel); break;
+      default: contract_tile<NQ, L, MIXED, K0, K1, 3>(cur, i, grp, wig, acc, sel); break;
     }
     if (more) tile_store<NQ, MIXED>(stage[(m + 1) & 1], regs, cols ? regc : regs, sel);
     __syncthreads();
@@ -382,10 +447,10 @@ __global__ void __launch_bounds__(kContractThreads) k_contract_mfma(const float*
   for (int w = 0; w < kWavesPerGroup; ++w) {
     if (wig == w) {
       switch (gi) {
-        case 0: reduce_group<NQ, K0, K1, 0>(red, acc, w, i, grp); break;
-        case 1: reduce_group<NQ, K0, K1, 1>(red, acc, w, i, grp); break;
-        case 2: reduce_group<NQ, K0, K1, 2>(red, acc, w, i, grp); break;
-        default: reduce_group<NQ, K0, K1, 3>(red, acc, w, i, grp); break;
+        case 0: reduce_group<NQ, L, K0, K1, 0>(red, acc, w, i, grp); break;
+        case 1: reduce_group<NQ, L, K0, K1, 1>(red, acc, w, i, grp); break;
+        case 2: reduce_group<NQ, L, K0, K1, 2>(red, acc, w, i, grp); break;
+        default: reduce_group<NQ, L, K0, K1, 3>(red, acc, w, i, grp); break;
       }
     }
     __syncthreads();
@@ -394,26 +459,28 @@ __global__ void __launch_bounds__(kContractThreads) k_contract_mfma(const float*
   for (int e = threadIdx.x; e < RED; e += kContractThreads) dst[e] = red[e];
 }
 
-template <int NQ, bool MIXED, int G>
+template <int NQ, int L, bool MIXED, int G>
 static hipError_t launch_group(const float* g, long mvox, int n_wg, long vpw, float* part, int part_len, int n_jobs,
                                size_t wstride, int nb, const float* gc, hipStream_t s) {
-  constexpr int K0 = group_begin(NQ, G), K1 = group_begin(NQ, G + 1);
+  constexpr int K0 = group_begin(L, NQ, G), K1 = group_begin(L, NQ, G + 1);
   // bf16 pairs (element 0 in the low half): (-1, 0) and (0, -1)
   const unsigned sel_lo = 0x0000BF80u, sel_hi = 0xBF800000u;
-  hipLaunchKernelGGL((k_contract_mfma<NQ, MIXED, K0, K1>), dim3(n_wg, 1, n_jobs), dim3(kContractThreads), 0, s, g,
+  hipLaunchKernelGGL((k_contract_mfma<NQ, L, MIXED, K0, K1>), dim3(n_wg, 1, n_jobs), dim3(kContractThreads), 0, s, g,
                      mvox, vpw, part, part_len, sel_lo, sel_hi, wstride, nb, gc);
   return hipGetLastError();
 }
 
-template <int NQ, bool MIXED>
+template <int NQ, int L, bool MIXED>
 static hipError_t launch_nq(const float* g, long mvox, int n_wg, long vpw, float* part, int part_len, int n_jobs,
                             size_t wstride, int nb, const float* gc, hipStream_t s) {
-  hipError_t e = launch_group<NQ, MIXED, 0>(g, mvox, n_wg, vpw, part, part_len, n_jobs, wstride, nb, gc, s);
-  if constexpr (n_groups(NQ) > 1) {
+  hipError_t e = launch_group<NQ, L, MIXED, 0>(g, mvox, n_wg, vpw, part, part_len, n_jobs, wstride, nb, gc, s);
+  if constexpr (n_groups(L, NQ) > 1) {
     if (e == hipSuccess)
-      e = launch_group<NQ, MIXED, 1>(g, mvox, n_wg, vpw, part, part_len, n_jobs, wstride, nb, gc, s);
+      e = launch_group<NQ, L, MIXED, 1>(g, mvox, n_wg, vpw, part, part_len, n_jobs, wstride, nb, gc, s);
+  }
+  if constexpr (n_groups(L, NQ) > 2) {
     if (e == hipSuccess)
-      e = launch_group<NQ, MIXED, 2>(g, mvox, n_wg, vpw, part, part_len, n_jobs, wstride, nb, gc, s);
+      e = launch_group<NQ, L, MIXED, 2>(g, mvox, n_wg, vpw, part, part_len, n_jobs, wstride, nb, gc, s);
   }
   return e;
 }
@@ -449,10 +516,10 @@ template <int NQ, int M> struct LineStage {
   __bf16 lo[16 * NQ * PH];
 };
 
-template <int NQ, bool MIXED, int K0, int K1, int G, int M, int NTMAX>
+template <int NQ, int L, bool MIXED, int K0, int K1, int G, int M, int NTMAX>
 __device__ __forceinline__ void contract_line_group(const LineStage<NQ, M>& st, int i, int grp, int wig,
                                                     f32x4_t (&acc)[NTMAX], const SplitSel& sel) {
-  using R = GroupRange<NQ, K0, K1, G>;
+  using R = GroupRange<NQ, L, K0, K1, G>;
   constexpr int PF = LineStage<NQ, M>::PF, PH = LineStage<NQ, M>::PH;
   for (int ks = wig; ks < M / 32; ks += fused_waves(MIXED)) {
     const int off = 32 * ks + 8 * grp;
@@ -460,18 +527,20 @@ __device__ __forceinline__ void contract_line_group(const LineStage<NQ, M>& st, 
     bf16x8_t bh[NQ], bl[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      const float4* pf = reinterpret_cast<const float4*>(st.f + (16 * q + i) * PF + off);
-      float4 x0 = pf[0], x1 = pf[1];
-      gv[q][0] = x0.x; gv[q][1] = x0.y; gv[q][2] = x0.z; gv[q][3] = x0.w;
-      gv[q][4] = x1.x; gv[q][5] = x1.y; gv[q][6] = x1.z; gv[q][7] = x1.w;
+      if (((R::rows | (MIXED ? 0u : R::cols)) >> q) & 1u) {
+        const float4* pf = reinterpret_cast<const float4*>(st.f + (16 * q + i) * PF + off);
+        float4 x0 = pf[0], x1 = pf[1];
+        gv[q][0] = x0.x; gv[q][1] = x0.y; gv[q][2] = x0.z; gv[q][3] = x0.w;
+        gv[q][4] = x1.x; gv[q][5] = x1.y; gv[q][6] = x1.z; gv[q][7] = x1.w;
+      }
       if constexpr (MIXED) {
-        if (q >= R::qmin) {
+        if ((R::cols >> q) & 1u) {
           bh[q] = *reinterpret_cast<const bf16x8_t*>(st.hi + (16 * q + i) * PH + off);
           bl[q] = *reinterpret_cast<const bf16x8_t*>(st.lo + (16 * q + i) * PH + off);
         }
       }
     }
-    do_blocks<NQ, MIXED, R::b, R::e, tiles_before(NQ, R::b)>(gv, bh, bl, acc, sel);
+    do_blocks<NQ, L, MIXED, R::b, R::e, tiles_before(L, NQ, R::b)>(gv, bh, bl, acc, sel);
   }
 }
 
@@ -609,9 +678,10 @@ __global__ void __launch_bounds__(fused_threads(MIXED)) k_zcontract(const float2
                                                              int n_chunks) {
   a2 = job_ptr(a2, wstride);
   part = job_ptr(part, wstride);
-  constexpr int K0 = 0, K1 = n_pair_blocks(NQ);
-  constexpr int NT = n_tiles(NQ);
-  constexpr int NTMAX = max_group_tiles<NQ, K0, K1>();
+  constexpr int L = kLayoutDiag;
+  constexpr int K0 = 0, K1 = n_pair_blocks(L, NQ);
+  constexpr int NT = n_tiles(L, NQ);
+  constexpr int NTMAX = max_group_tiles<NQ, L, K0, K1>();
   constexpr int TL = fft2_threads(M), NSLOT = kProducerThreads / TL;
   static_assert(2 * NSLOT >= 16 * NQ, "one bin pair per producer slot");
   constexpr int STAGE_BYTES = (int)sizeof(LineStage<NQ, M>);
@@ -680,20 +750,20 @@ __global__ void __launch_bounds__(fused_threads(MIXED)) k_zcontract(const float2
       for (int m = 0; m < nc; ++m, ++gm) {
         const LineStage<NQ, M>& cur = stage[gm & 1];
         switch (gi) {
-          case 0: contract_line_group<NQ, MIXED, K0, K1, 0, M>(cur, i, grp, wig, acc, sel); break;
-          case 1: contract_line_group<NQ, MIXED, K0, K1, 1, M>(cur, i, grp, wig, acc, sel); break;
-          case 2: contract_line_group<NQ, MIXED, K0, K1, 2, M>(cur, i, grp, wig, acc, sel); break;
-          default: contract_line_group<NQ, MIXED, K0, K1, 3, M>(cur, i, grp, wig, acc, sel); break;
+          case 0: contract_line_group<NQ, L, MIXED, K0, K1, 0, M>(cur, i, grp, wig, acc, sel); break;
+          case 1: contract_line_group<NQ, L, MIXED, K0, K1, 1, M>(cur, i, grp, wig, acc, sel); break;
+          case 2: contract_line_group<NQ, L, MIXED, K0, K1, 2, M>(cur, i, grp, wig, acc, sel); break;
+          default: contract_line_group<NQ, L, MIXED, K0, K1, 3, M>(cur, i, grp, wig, acc, sel); break;
         }
         __syncthreads();
       }
       if constexpr (FW == 1) {
         float* dst = part + (size_t)(c0 + c) * part_len;
         switch (gi) {
-          case 0: flush_group<NQ, K0, K1, 0>(dst, acc, i, grp); break;
-          case 1: flush_group<NQ, K0, K1, 1>(dst, acc, i, grp); break;
-          case 2: flush_group<NQ, K0, K1, 2>(dst, acc, i, grp); break;
-          default: flush_group<NQ, K0, K1, 3>(dst, acc, i, grp); break;
+          case 0: flush_group<NQ, L, K0, K1, 0>(dst, acc, i, grp); break;
+          case 1: flush_group<NQ, L, K0, K1, 1>(dst, acc, i, grp); break;
+          case 2: flush_group<NQ, L, K0, K1, 2>(dst, acc, i, grp); break;
+          default: flush_group<NQ, L, K0, K1, 3>(dst, acc, i, grp); break;
         }
       }
     }
@@ -701,10 +771,10 @@ __global__ void __launch_bounds__(fused_threads(MIXED)) k_zcontract(const float2
     for (int w = 0; w < TAIL; ++w) {
       if (wig == w) {
         switch (gi) {
-          case 0: reduce_group<NQ, K0, K1, 0>(red, acc, w, i, grp); break;
-          case 1: reduce_group<NQ, K0, K1, 1>(red, acc, w, i, grp); break;
-          case 2: reduce_group<NQ, K0, K1, 2>(red, acc, w, i, grp); break;
-          default: reduce_group<NQ, K0, K1, 3>(red, acc, w, i, grp); break;
+          case 0: reduce_group<NQ, L, K0, K1, 0>(red, acc, w, i, grp); break;
+          case 1: reduce_group<NQ, L, K0, K1, 1>(red, acc, w, i, grp); break;
+          case 2: reduce_group<NQ, L, K0, K1, 2>(red, acc, w, i, grp); break;
+          default: reduce_group<NQ, L, K0, K1, 3>(red, acc, w, i, grp); break;
         }
       }
       __syncthreads();
@@ -787,38 +857,47 @@ hipError_t launch_zcontract(const pb3_plan& p, const Exec& x, bool mixed, hipStr
   return hipErrorInvalidValue;
 }
 
-int mfma_tiles(int nq) {
-  switch (nq) {
-    case 1: return n_tiles(1);
-    case 2: return n_tiles(2);
-    case 3: return n_tiles(3);
-    default: return -1;
-  }
+int mfma_tiles(bool ab, int nq) {
+  const int L = ab ? kLayoutAB : kLayoutDiag;
+  return nq >= 1 && nq <= 3 ? n_tiles(L, nq) : -1;
 }
 
-// (tile, row) of the pair (a, b), a <= b, and the tile list order.
-int mfma_locate(int nq, int a, int b, int c) {
-  int p = a / 16, q = b / 16, ia = a % 16, ib = b % 16;
+// Partial-vector index of triplet (a, b, c), a <= b <= c: its tile, row and
+// column (-1 if the layout does not produce it).  kLayoutAB reads it at
+// (pair (a, b), column c); kLayoutDiag at (pair (a, b), column c) when a
+// and b share a group, else at (pair (b, c), column a) when b and c do,
+// else (three groups) at the cross pair (a, b) against column c.
+int mfma_locate(bool ab, int nq, int a, int b, int c) {
+  const int L = ab ? kLayoutAB : kLayoutDiag;
+  int x = a, y = b, z = c;
+  if (!ab && a / 16 != b / 16 && b / 16 == c / 16) {
+    x = b;
+    y = c;
+    z = a;
+  }
+  const int p = x / 16, q = y / 16, ix = x % 16, iy = y % 16;
   int row, s;
   if (p == q) {
-    int d = ((ia - ib) % 16 + 16) % 16;
+    const int d = ((ix - iy) % 16 + 16) % 16;
     if (d <= 8) {
-      row = ia;
+      row = ix;
       s = d;
     } else {
-      row = ib;
+      row = iy;
       s = 16 - d;
     }
   } else {
-    row = ia;
-    s = ((ia - ib) % 16 + 16) % 16;
+    row = ix;
+    s = ((ix - iy) % 16 + 16) % 16;
   }
-  int cb = c / 16, col = c % 16;
-  if (cb < q) return -1;
-  int npb = n_pair_blocks(nq);
+  const int cb = z / 16, col = z % 16;
+  const int npb = n_pair_blocks(L, nq);
   for (int k = 0; k < npb; ++k) {
-    PairBlock pb = pair_block(nq, k);
-    if (pb.p == p && pb.q == q && pb.s == s) return (tiles_before(nq, k) + (cb - q)) * 256 + row * 16 + col;
+    const PairBlock pb = pair_block(L, nq, k);
+    if (pb.p == p && pb.q == q && pb.s == s) {
+      if (!((pb.cmask >> cb) & 1u)) return -1;
+      return (tiles_before(L, nq, k) + col_rank(pb.cmask, cb)) * 256 + row * 16 + col;
+    }
   }
   return -1;
 }
@@ -827,18 +906,19 @@ int mfma_locate(int nq, int a, int b, int c) {
 int mfma_grid(int nq, int n_cu) {
   int per = 1;
   hipError_t e = hipErrorInvalidValue;
+  constexpr int L = kLayoutDiag;
   switch (nq) {
     case 1:
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per, (const void*)k_contract_mfma<1, true, 0, 9>, kContractThreads, 0);
+          &per, (const void*)k_contract_mfma<1, L, true, 0, group_begin(L, 1, 1)>, kContractThreads, 0);
       break;
     case 2:
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per, (const void*)k_contract_mfma<2, true, 0, 34>, kContractThreads, 0);
+          &per, (const void*)k_contract_mfma<2, L, true, 0, group_begin(L, 2, 1)>, kContractThreads, 0);
       break;
     default:
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per, (const void*)k_contract_mfma<3, true, 0, 17>, kContractThreads, 0);
+          &per, (const void*)k_contract_mfma<3, L, true, 0, group_begin(L, 3, 1)>, kContractThreads, 0);
       break;
   }
   if (e != hipSuccess || per < 1) per = 1;
@@ -847,27 +927,44 @@ int mfma_grid(int nq, int n_cu) {
 }
 
 hipError_t launch_contract_mfma(const pb3_plan& p, const Exec& x, bool mixed, hipStream_t s) {
-  return launch_contract_cols(p, x, x.ws.g, nullptr, mixed, s);
+  return launch_contract_cols(p, x, x.ws.g, nullptr, mixed, false, s);
 }
 
+// ab = false (the bispectrum): kLayoutDiag into partial vectors of
+// p.part_len floats; ab = true (column fields gc, or the fields g
+// themselves when gc is null): kLayoutAB into vectors of p.part_len_ab.
+
 hipError_t launch_contract_cols(const pb3_plan& p, const Exec& x, const float* g, const float* gc, bool mixed,
-                                hipStream_t s) {
-  if (gc && !mixed) return hipErrorInvalidValue;  // separate column fields: bf16 column operand only
+                                bool ab, hipStream_t s) {
+  if ((gc && !ab) || (gc && !mixed)) return hipErrorInvalidValue;  // column fields: bf16 operand, layout AB
   const long mvox = (long)mpix(p);
   const int nq = p.nb_pad / 16;
   const int n_wg = p.contract_wgs;
   long vpw = (mvox + n_wg - 1) / n_wg;
   vpw = (vpw + kTileVox - 1) / kTileVox * kTileVox;
   float* part = x.ws.part;
-  const int pl = p.part_len, nj = x.n_jobs;
+  const int nj = x.n_jobs;
   const size_t ws = x.wstride;
+  if (ab) {
+    if (!mixed) return hipErrorInvalidValue;
+    constexpr int L = kLayoutAB;
+    const int pl = p.part_len_ab;
+    switch (nq) {
+      case 1: return launch_nq<1, L, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s);
+      case 2: return launch_nq<2, L, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s);
+      case 3: return launch_nq<3, L, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  constexpr int L = kLayoutDiag;
+  const int pl = p.part_len;
   switch (nq) {
-    case 1: return mixed ? launch_nq<1, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s)
-                         : launch_nq<1, false>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s);
-    case 2: return mixed ? launch_nq<2, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s)
-                         : launch_nq<2, false>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s);
-    case 3: return mixed ? launch_nq<3, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s)
-                         : launch_nq<3, false>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s);
+    case 1: return mixed ? launch_nq<1, L, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s)
+                         : launch_nq<1, L, false>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s);
+    case 2: return mixed ? launch_nq<2, L, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s)
+                         : launch_nq<2, L, false>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s);
+    case 3: return mixed ? launch_nq<3, L, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s)
+                         : launch_nq<3, L, false>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s);
     default: return hipErrorInvalidValue;
   }
 }

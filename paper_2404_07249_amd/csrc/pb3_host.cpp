@@ -116,7 +116,7 @@ static void free_device(pb3_plan* p) {
                   d.out_map,   d.inv_counts, d.pk_scale,  d.tw_n[0],     d.tw_n[1],   d.tw_n[2],   d.tw_m[0],
                   d.tw_m[1],   d.tw_m[2],    d.tw_m_d[0], d.tw_m_d[1],   d.tw_m_d[2], d.nmodes_d,  d.pml_inv,
                   d.ml_trips,  d.ml_fac,     d.ml_map,    d.win_inv,     d.pfid_inv,  d.pfid_inv_d, d.mode_w,
-                  d.bk_bias,   d.bk_mix};
+                  d.bk_bias,   d.bk_mix,     d.out_map_ab};
   for (void* q : ptrs)
     if (q) hipFree(q);
   d = DeviceTables{};
@@ -428,9 +428,13 @@ static pb3_status build_host(pb3_plan* p, const int grid[3], const double box[3]
   p->fused_ok = !(flags & PB3_FLAG_POWER_ONLY) && fused_supported(p->nb_pad / 16, p->Mz);
   p->fused = !(flags & PB3_FLAG_NO_FUSION) && p->fused_ok;
   p->contract_wgs = 512;
-  p->part_len = (flags & PB3_FLAG_POWER_ONLY) ? 0 : mfma_tiles(p->nb_pad / 16) * 256;
+  p->part_len = (flags & PB3_FLAG_POWER_ONLY) ? 0 : mfma_tiles(false, p->nb_pad / 16) * 256;
+  p->part_len_ab = (flags & PB3_FLAG_POWER_ONLY) || p->lmax == 0 ? 0 : mfma_tiles(true, p->nb_pad / 16) * 256;
   return PB3_OK;
 }
+
+// floats per partial vector of the longer of the two contraction layouts
+static size_t part_max(const pb3_plan& p) { return (size_t)std::max(p.part_len, p.part_len_ab); }
 
 size_t workspace_bytes(const pb3_plan* p) {
   size_t b = 0;
@@ -442,9 +446,9 @@ size_t workspace_bytes(const pb3_plan* p) {
   b += align_up(sizeof(float2) * (size_t)p->a2_len, A);
   const bool has_g = !p->fused && !(p->flags & PB3_FLAG_POWER_ONLY);
   b += has_g ? align_up(sizeof(float) * (size_t)p->nb * mpix(*p), A) : 0;
-  b += align_up(sizeof(float) * (size_t)p->contract_wgs * p->part_len, A);
+  b += align_up(sizeof(float) * (size_t)p->contract_wgs * part_max(*p), A);
   b += align_up(sizeof(double) * (size_t)std::max(p->n_chunks, 1), A);
-  b += align_up(sizeof(double) * (size_t)kReduceSlices * p->part_len, A);
+  b += align_up(sizeof(double) * (size_t)kReduceSlices * part_max(*p), A);
   return b;
 }
 
@@ -467,9 +471,9 @@ Workspace carve(const pb3_plan* p, void* base, size_t bytes) {
   w.a2 = (float2*)take(sizeof(float2) * (size_t)p->a2_len);
   const bool has_g = !p->fused && !(p->flags & PB3_FLAG_POWER_ONLY);
   w.g = has_g ? (float*)take(sizeof(float) * (size_t)p->nb * mpix(*p)) : nullptr;
-  w.part = (float*)take(sizeof(float) * (size_t)p->contract_wgs * p->part_len);
+  w.part = (float*)take(sizeof(float) * (size_t)p->contract_wgs * part_max(*p));
   w.ppart = (double*)take(sizeof(double) * (size_t)std::max(p->n_chunks, 1));
-  w.rsl = (double*)take(sizeof(double) * (size_t)kReduceSlices * p->part_len);
+  w.rsl = (double*)take(sizeof(double) * (size_t)kReduceSlices * part_max(*p));
   return w;
 }
 
@@ -690,7 +694,7 @@ static pb3_status build_device(pb3_plan* p) {
   const int n_cand = (int)(p->trip_all.size() / 3);
   p->trip.clear();
   p->counts.clear();
-  std::vector<int32_t> map;
+  std::vector<int32_t> map, map_ab;
   std::vector<double> fac;
   const double m3 = (double)p->Mx * p->My * p->Mz;
   const double scale = V * V * (m3 * m3) / (n3 * n3 * n3);
@@ -709,15 +713,25 @@ static pb3_status build_device(pb3_plan* p) {
     }
     for (int k = 0; k < 3; ++k) p->trip.push_back(p->trip_all[3 * t + k]);
     p->counts.push_back(T);
-    int loc = mfma_locate(p->nb_pad / 16, p->trip_all[3 * t], p->trip_all[3 * t + 1], p->trip_all[3 * t + 2]);
+    const int a = p->trip_all[3 * t], b = p->trip_all[3 * t + 1], c = p->trip_all[3 * t + 2];
+    int loc = mfma_locate(false, p->nb_pad / 16, a, b, c);
     if (loc < 0 || loc >= p->part_len) {
       set_error("internal: triplet not covered by the contraction tiles");
       return PB3_EDEVICE;
     }
     map.push_back(loc);
+    if (p->part_len_ab > 0) {
+      loc = mfma_locate(true, p->nb_pad / 16, a, b, c);
+      if (loc < 0 || loc >= p->part_len_ab) {
+        set_error("internal: triplet not covered by the column-field contraction tiles");
+        return PB3_EDEVICE;
+      }
+      map_ab.push_back(loc);
+    }
     fac.push_back(scale / T);
   }
   if ((st = upload(&d.out_map, map.data(), map.size())) != PB3_OK) return st;
+  if (!map_ab.empty() && (st = upload(&d.out_map_ab, map_ab.data(), map_ab.size())) != PB3_OK) return st;
   if ((st = upload(&d.inv_counts, fac.data(), fac.size())) != PB3_OK) return st;
   if (p->lmax > 0) {
     const int ne = p->lmax / 2 + 1, nt = (int)(p->trip.size() / 3);

@@ -74,6 +74,7 @@ struct DeviceTables {
   BinTile* tiles = nullptr;       // all FP32 inverse-pass tiles (x, then y, then z)
   int32_t* trip_all = nullptr;    // candidate triplets (3 ints each), simple contraction
   int32_t* out_map = nullptr;     // per kept triplet: index into one work-group's MFMA partial vector
+  int32_t* out_map_ab = nullptr;  // the same for pairs against separate column fields (multipoles)
   double* inv_counts = nullptr;   // per kept triplet: scale / T
   double* pk_scale = nullptr;     // per bin: V / (N_pix^2 N_b)
   float2* tw_n[3] = {};           // W_{N_i}^j, j < N_i, per axis x, y, z
@@ -165,7 +166,8 @@ struct pb3_plan {
   pb3::TileSet tx{}, ty{}, tz{};   // FP32 inverse-pass tiles (device)
   // contraction
   int contract_wgs = 0;        // partial vectors (accumulation chunks) of the contraction
-  int part_len = 0;            // floats per work-group partial vector (MFMA tiles * 256)
+  int part_len = 0;            // floats per partial vector of the bispectrum's contraction (its MFMA tiles * 256)
+  int part_len_ab = 0;         // the same for pairs against separate column fields (multipoles)
   int n_cu = 0;                // compute units of the plan's device
   pb3_precision last_prec = PB3_FP32;
   bool device = false;
@@ -236,13 +238,17 @@ pb3_status run_bispectrum_linear(pb3_plan& p, const float* data, const float* co
                                  pb3_precision prec, void* workspace, hipStream_t s);
 // MFMA contraction (contract_mfma.hip): tiles for nq 16-bin groups, the
 // partial-vector index of triplet (a, b, c) (-1 if not produced), launch
-int mfma_tiles(int nq);
-int mfma_locate(int nq, int a, int b, int c);
+// ab = true: every pair a <= b against columns c (separate column fields);
+// ab = false: the bispectrum's layout (pairs inside a 16-bin group)
+int mfma_tiles(bool ab, int nq);
+int mfma_locate(bool ab, int nq, int a, int b, int c);
 hipError_t launch_contract_mfma(const pb3_plan& p, const Exec& x, bool mixed, hipStream_t s);
 // pairs of the fields g against columns of the fields gc (nb bins each, M^3
-// voxels, gc != nullptr: mixed precision only) into x.ws.part
+// voxels; gc == nullptr: g itself) into x.ws.part.  ab = true: every pair
+// a <= b against columns c >= its group (mixed precision only; the
+// multipoles), else the bispectrum's layout (gc must be null).
 hipError_t launch_contract_cols(const pb3_plan& p, const Exec& x, const float* g, const float* gc, bool mixed,
-                                hipStream_t s);
+                                bool ab, hipStream_t s);
 int mfma_grid(int nq, int n_cu);
 // fused inverse z pass + contraction (contract_mfma.hip)
 bool fused_supported(int nq, int m);

@@ -647,16 +647,16 @@ pb3_status run_multipoles(pb3_plan& p, const float* delta, double* pk_out, doubl
   if (prec == PB3_MIXED_BF16X3) {
     // MFMA: pairs of G against columns of g_l, the plan's reduction with (2l + 1) / T
     for (int l = 0; l < ne; ++l) {
-      if (!chk(launch_contract_cols(p, x, fields, l ? fields + (size_t)l * p.nb * m3 : nullptr, true, s),
+      if (!chk(launch_contract_cols(p, x, fields, l ? fields + (size_t)l * p.nb * m3 : nullptr, true, true, s),
                "multipoles: contraction"))
         return st;
-      hipLaunchKernelGGL(k_reduce_slices, dim3((p.part_len / 4 + 255) / 256, kReduceSlices, 1), dim3(256), 0, s,
-                         x.ws.part, p.contract_wgs, p.part_len, x.ws.rsl, (size_t)0);
+      hipLaunchKernelGGL(k_reduce_slices, dim3((p.part_len_ab / 4 + 255) / 256, kReduceSlices, 1), dim3(256), 0, s,
+                         x.ws.part, p.contract_wgs, p.part_len_ab, x.ws.rsl, (size_t)0);
       if (!chk(hipGetLastError(), "multipoles: reduce")) return st;
       JobIO io{};
       io.bk[0] = bk_out + (size_t)l * nt;
-      hipLaunchKernelGGL(k_reduce_final, dim3((nt + 255) / 256, 1, 1), dim3(256), 0, s, x.ws.rsl, p.part_len,
-                         p.d.out_map, p.d.ml_fac + (size_t)l * nt, nt, io, (size_t)0,
+      hipLaunchKernelGGL(k_reduce_final, dim3((nt + 255) / 256, 1, 1), dim3(256), 0, s, x.ws.rsl, p.part_len_ab,
+                         p.d.out_map_ab, p.d.ml_fac + (size_t)l * nt, nt, io, (size_t)0,
                          l == 0 ? (const double*)p.d.bk_bias : nullptr, (nt + 255) / 256, PowerFinal{});
       if (!chk(hipGetLastError(), "multipoles: reduce")) return st;
     }
