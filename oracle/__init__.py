@@ -4,7 +4,8 @@ TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()``
 and the ``cpu_baseline`` leg of ``bench.py``, never by the product package.
 It shares no code with the HIP path.
 
-Parity status of each function (what pins it is in ``tests/test_oracle.py``):
+Parity status of each function (what pins it is in ``tests/test_oracle.py``
+and ``tests/test_oracle_pins.py``):
 
 * ``power_spectrum``       pinned: Parseval, plane-wave closed form,
                            invariances, statistical recovery of the input P.
@@ -14,6 +15,11 @@ Parity status of each function (what pins it is in ``tests/test_oracle.py``):
 * ``bispectrum``           pinned: brute-force k-triplet sums, plane-wave
                            closed form, invariances, Gaussian null and the
                            tree-level bispectrum of a quadratic field.
+* ``triplet_sums_sample``, ``count_sample`` (a triplet subset, for large
+                           grids) pinned: equal to the full ``bispectrum``
+                           entries (sums, absolute sums, exact counts) on
+                           32^3 and 64^3 fields, a = b = c included; a
+                           shuffled bin remap fails the check.
 * ``windowed_polyspectra`` pinned: unbiased means for a field with local
                            2- and 3-point functions under random windows.
 * ``masked`` (Monte Carlo Fisher of the masked power spectrum) pinned: the
@@ -32,8 +38,13 @@ Parity status of each function (what pins it is in ``tests/test_oracle.py``):
                            sums equal explicit mode-triangle loops; constant
                            P_fid reduces to the unweighted estimators; window
                            deconvolution undoes a window applied in Fourier
-                           space; Poisson noise of a uniform field is removed
-                           on average from P and B.
+                           space; the window sinc(pi n / N)^p equals the
+                           average over a particle's position in its cell of
+                           the DFT of explicit NGP / CIC / TSC assignment
+                           (Gauss-Legendre quadrature, every n incl. Nyquist;
+                           a wrong argument or exponent fails); Poisson noise
+                           of a uniform field is removed on average from P
+                           and B.
 * ``injection`` (expectation under an injected bispectrum) pinned: the
                            separable bin average equals explicit loops over
                            closed triangles; the oracle estimator's linear
