@@ -140,7 +140,10 @@ pb3_status pb3_get_triplets(const pb3_plan* plan, int32_t* abc_out);
 pb3_status pb3_norm(const pb3_plan* plan, int64_t* n_modes_out, double* counts_out);
 
 /* P_b for every bin.  delta_dev: N^3 float32, C order (x slowest, z
- * fastest), device memory.  pk_dev: n_bins float64, device memory, (Mpc/h)^3. */
+ * fastest), device memory, 8-byte aligned (the forward pass reads pairs of
+ * values; PB3_EINVAL otherwise; the same holds for every field argument
+ * below: data, windows, random fields, simulations and batch fields).
+ * pk_dev: n_bins float64, device memory, (Mpc/h)^3. */
 pb3_status pb3_power(pb3_plan* plan, const float* delta_dev, double* pk_dev, void* stream);
 
 /* B_abc for every plan triplet: bk_dev n_trip float64 device memory,

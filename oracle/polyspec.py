@@ -51,6 +51,10 @@ from __future__ import annotations
 import math
 import os
 
+import concurrent.futures as _cf
+
+import threadpoolctl as _tpc
+
 import numpy as np
 
 try:  # scipy's pocketfft takes a worker count; numpy's does not
@@ -93,6 +97,22 @@ def idft(x: np.ndarray) -> np.ndarray:
     if _sfft is not None:
         return _sfft.ifftn(x, workers=_workers())
     return np.fft.ifftn(x)
+
+
+def rdft(x: np.ndarray) -> np.ndarray:
+    """The k_z = 0..n/2 half of the unnormalised 3D DFT of real data (library step)."""
+    x = np.asarray(x, dtype=np.float64)
+    if _sfft is not None:
+        return _sfft.rfftn(x, workers=_workers())
+    return np.fft.rfftn(x)
+
+
+def irdft(x: np.ndarray, n: int) -> np.ndarray:
+    """Real inverse 3D DFT (1/N_pix normalisation) of a Hermitian spectrum
+    given by its k_z = 0..n/2 half, on an n^3 grid (library step)."""
+    if _sfft is not None:
+        return _sfft.irfftn(x, s=(n, n, n), workers=_workers())
+    return np.fft.irfftn(x, s=(n, n, n))
 
 
 def freqs(n: int) -> np.ndarray:
@@ -167,23 +187,33 @@ def power_spectrum(delta: np.ndarray, box: float, edges) -> np.ndarray:
     return vol / npix**2 * sums / cnt
 
 
+def _half(x: np.ndarray) -> np.ndarray:
+    """The k_z >= 0 half (k_z = 0..n/2) of a full n^3 Fourier-grid array."""
+    return x[:, :, : x.shape[2] // 2 + 1]
+
+
 def filtered_fields(delta: np.ndarray, edges, bins=None) -> np.ndarray:
-    """G_b = Re IDFT[Theta_b D] for b in ``bins`` (all bins by default)."""
+    """G_b = Re IDFT[Theta_b D] for b in ``bins`` (all bins by default).
+
+    Theta_b D is Hermitian for real delta (Theta_b depends on |n| only), so
+    its inverse DFT is real and is taken from the k_z >= 0 half by the
+    library's real inverse transform."""
     d = np.asarray(delta, dtype=np.float64)
     n = d.shape[0]
-    D = dft(d)
-    idx = bin_of_modes(n, edges)
+    D = rdft(d)
+    idx = _half(bin_of_modes(n, edges))
     nb = len(edges) - 1
     bins = range(nb) if bins is None else bins
-    return np.stack([idft(np.where(idx == b, D, 0.0)).real for b in bins])
+    return np.stack([irdft(D * (idx == b), n) for b in bins])
 
 
 def unit_fields(n: int, edges, bins=None) -> np.ndarray:
-    """H_b = Re IDFT[Theta_b] for b in ``bins`` (all bins by default)."""
-    idx = bin_of_modes(n, edges)
+    """H_b = Re IDFT[Theta_b] for b in ``bins`` (all bins by default), via
+    the real inverse transform of the k_z >= 0 half as above."""
+    idx = _half(bin_of_modes(n, edges))
     nb = len(edges) - 1
     bins = range(nb) if bins is None else bins
-    return np.stack([idft((idx == b).astype(np.float64)).real for b in bins])
+    return np.stack([irdft((idx == b).astype(np.float64), n) for b in bins])
 
 
 def triple_sums(fields: np.ndarray, trips: np.ndarray, absolute: bool = False):
@@ -191,21 +221,45 @@ def triple_sums(fields: np.ndarray, trips: np.ndarray, absolute: bool = False):
     return _triple_sums(fields, trips, absolute)
 
 
-def _triple_sums(fields: np.ndarray, trips: np.ndarray, absolute: bool = False):
-    """sum_x F_a F_b F_c for each triplet (and optionally sum_x |F_a F_b F_c|)."""
+def _triple_sums(fields: np.ndarray, trips: np.ndarray, absolute: bool = False, chunk: int = 4096):
+    """sum_x F_a F_b F_c for each triplet (and optionally sum_x |F_a F_b F_c|).
+
+    The voxel sum is taken over contiguous chunks of voxels.  In a chunk
+    every pair product F_a F_b the triplets use is formed once (rows of P),
+    and S = P F^T (a matrix product) holds sum_x F_a F_b F_c for every such
+    pair and every bin c, of which the triplets' entries are taken; the
+    chunk sums are added in voxel order.  Chunks are evaluated by a thread
+    pool (each writes only its own row of partial sums), so the result does
+    not depend on the threads.
+    """
     nb = fields.shape[0]
     flat = fields.reshape(nb, -1)
+    trips = np.asarray(trips, dtype=np.int64).reshape(-1, 3)
+    pairs = sorted(set((int(a), int(b)) for a, b, _ in trips))
+    pid = {p: i for i, p in enumerate(pairs)}
+    pa = np.array([p[0] for p in pairs], dtype=np.int64)
+    pb = np.array([p[1] for p in pairs], dtype=np.int64)
+    rows = np.array([pid[(int(a), int(b))] for a, b, _ in trips], dtype=np.int64)
+    cols = trips[:, 2]
+    starts = list(range(0, flat.shape[1], chunk))
+    part = np.zeros((len(starts), len(trips)))
+    parta = np.zeros((len(starts), len(trips))) if absolute else None
+
+    def one(k):
+        f = np.ascontiguousarray(flat[:, starts[k]:starts[k] + chunk])
+        P = f[pa] * f[pb]
+        part[k] = (P @ f.T)[rows, cols]
+        if absolute:
+            parta[k] = (np.abs(P) @ np.abs(f).T)[rows, cols]
+
+    with _tpc.threadpool_limits(1), _cf.ThreadPoolExecutor(_workers()) as ex:
+        list(ex.map(one, range(len(starts))))
     s = np.zeros(len(trips))
     sa = np.zeros(len(trips)) if absolute else None
-    cache_key = None
-    pair = None
-    for t, (a, b, c) in enumerate(trips):
-        if (a, b) != cache_key:
-            pair = flat[a] * flat[b]
-            cache_key = (a, b)
-        s[t] = float(np.dot(pair, flat[c]))
+    for k in range(len(starts)):
+        s += part[k]
         if absolute:
-            sa[t] = float(np.abs(pair * flat[c]).sum())
+            sa += parta[k]
     return s, sa
 
 

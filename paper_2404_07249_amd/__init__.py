@@ -36,6 +36,18 @@ def _stream_handle(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
+def _on_stream(tensor, stream):
+    """Mark a tensor this module allocated (an output or a temporary
+    workspace) as used by ``stream``: torch's caching allocator then does not
+    hand its memory to another allocation until the work queued on that
+    stream so far has finished, even when it was allocated on another one."""
+    import torch
+
+    if stream is not None and tensor is not None and stream != torch.cuda.current_stream(tensor.device):
+        tensor.record_stream(stream)
+    return tensor
+
+
 class Plan:
     """Plan for one grid / box / binning (``pb3_plan``).
 
@@ -171,19 +183,21 @@ class Plan:
             raise TypeError("delta must be a CUDA tensor")
         if delta.dtype != torch.float32 or tuple(delta.shape) != shape or not delta.is_contiguous():
             raise ValueError(f"delta must be a contiguous float32 tensor of shape {shape}")
+        if delta.data_ptr() % 8 != 0:  # the forward pass reads pairs of values
+            raise ValueError("delta must start at an 8-byte aligned address")
 
-    def _out(self, out, count, like):
+    def _out(self, out, count, like, stream=None):
         import torch
 
         if out is None:
-            return torch.empty(count, dtype=torch.float64, device=like.device)
+            return _on_stream(torch.empty(count, dtype=torch.float64, device=like.device), stream)
         if out.dtype != torch.float64 or out.numel() < count or not out.is_contiguous() or out.device != like.device:
             raise ValueError("out must be a contiguous float64 tensor on the field's device")
         return out
 
     def power(self, delta, out=None, stream=None):
         self._check_field(delta)
-        pk = self._out(out, self.n_bins, delta)
+        pk = self._out(out, self.n_bins, delta, stream)
         _lib.check(
             self._lib.pb3_power(self._h, C.c_void_p(delta.data_ptr()), C.c_void_p(pk.data_ptr()), _stream_handle(stream))
         )
@@ -191,7 +205,7 @@ class Plan:
 
     def bispectrum(self, delta, precision: str = "fp32", out=None, stream=None):
         self._check_field(delta)
-        bk = self._out(out, self.n_triplets, delta)
+        bk = self._out(out, self.n_triplets, delta, stream)
         _lib.check(
             self._lib.pb3_bispectrum(
                 self._h, C.c_void_p(delta.data_ptr()), C.c_void_p(bk.data_ptr()), _PREC[precision],
@@ -202,8 +216,8 @@ class Plan:
 
     def polyspectra(self, delta, precision: str = "fp32", pk_out=None, bk_out=None, stream=None):
         self._check_field(delta)
-        pk = self._out(pk_out, self.n_bins, delta)
-        bk = self._out(bk_out, self.n_triplets, delta)
+        pk = self._out(pk_out, self.n_bins, delta, stream)
+        bk = self._out(bk_out, self.n_triplets, delta, stream)
         _lib.check(
             self._lib.pb3_polyspectra(
                 self._h, C.c_void_p(delta.data_ptr()), C.c_void_p(pk.data_ptr()), C.c_void_p(bk.data_ptr()),
@@ -221,7 +235,7 @@ class Plan:
         if pk is None and bk is None:
             raise ValueError("nothing to normalise")
         if scratch is None:
-            scratch = torch.empty(_lib.WINDOW_SCRATCH, dtype=torch.float64, device=window.device)
+            scratch = _on_stream(torch.empty(_lib.WINDOW_SCRATCH, dtype=torch.float64, device=window.device), stream)
         elif scratch.dtype != torch.float64 or scratch.numel() < _lib.WINDOW_SCRATCH:
             raise ValueError("scratch must hold PB3_WINDOW_SCRATCH float64 values")
         _lib.check(self._lib.pb3_window_normalize(
@@ -244,12 +258,13 @@ class Plan:
         self._check_field(window)
         for g in grfs:
             self._check_field(g)
-        pk = self._out(pk_out, self.n_bins, data)
+        pk = self._out(pk_out, self.n_bins, data, stream)
         nb = self.n_bins
-        fm = fisher_out if fisher_out is not None else torch.empty((nb, nb), dtype=torch.float64,
-                                                                   device=data.device)
+        fm = fisher_out if fisher_out is not None else _on_stream(
+            torch.empty((nb, nb), dtype=torch.float64, device=data.device), stream)
         if workspace is None:
-            workspace = torch.empty(self.masked_workspace_bytes, dtype=torch.uint8, device=data.device)
+            workspace = _on_stream(torch.empty(self.masked_workspace_bytes, dtype=torch.uint8, device=data.device),
+                                   stream)
         ga = (C.c_void_p * len(grfs))(*[g.data_ptr() for g in grfs])
         _lib.check(self._lib.pb3_masked_power(
             self._h, C.c_void_p(data.data_ptr()), C.c_void_p(window.data_ptr()), ga, len(grfs),
@@ -269,9 +284,10 @@ class Plan:
         self._check_field(data)
         for g in sims:
             self._check_field(g)
-        bk = self._out(out, self.n_triplets, data)
+        bk = self._out(out, self.n_triplets, data, stream)
         if workspace is None:
-            workspace = torch.empty(self.linear_workspace_bytes(len(sims)), dtype=torch.uint8, device=data.device)
+            workspace = _on_stream(
+                torch.empty(self.linear_workspace_bytes(len(sims)), dtype=torch.uint8, device=data.device), stream)
         sa = (C.c_void_p * len(sims))(*[g.data_ptr() for g in sims])
         _lib.check(self._lib.pb3_bispectrum_linear(
             self._h, C.c_void_p(data.data_ptr()), sa, len(sims), C.c_void_p(bk.data_ptr()), _PREC[precision],
@@ -323,9 +339,11 @@ class Plan:
         ne = self.n_ell
         pk = torch.empty((ne, self.n_bins), dtype=torch.float64, device=delta.device) if power else None
         bk = torch.empty((ne, self.n_triplets), dtype=torch.float64, device=delta.device) if bispectrum else None
+        _on_stream(pk, stream)
+        _on_stream(bk, stream)
         if workspace is None:
             nbytes = int(self._lib.pb3_multipoles_workspace_bytes(self._h))
-            workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=delta.device)
+            workspace = _on_stream(torch.empty(max(nbytes, 1), dtype=torch.uint8, device=delta.device), stream)
         _lib.check(self._lib.pb3_multipoles(
             self._h, C.c_void_p(delta.data_ptr()), C.c_void_p(pk.data_ptr() if pk is not None else 0),
             C.c_void_p(bk.data_ptr() if bk is not None else 0), _PREC[precision], C.c_void_p(workspace.data_ptr()),
@@ -413,12 +431,14 @@ class Batch:
         pks = bks = None
         if power:
             pks = pk_outs if pk_outs is not None else [
-                torch.empty(p.n_bins, dtype=torch.float64, device=d.device) for p, d in zip(self.plans, deltas)]
+                _on_stream(torch.empty(p.n_bins, dtype=torch.float64, device=d.device), stream)
+                for p, d in zip(self.plans, deltas)]
             for p, o, d in zip(self.plans, pks, deltas):
                 p._out(o, p.n_bins, d)
         if bispectrum:
             bks = bk_outs if bk_outs is not None else [
-                torch.empty(p.n_triplets, dtype=torch.float64, device=d.device) for p, d in zip(self.plans, deltas)]
+                _on_stream(torch.empty(p.n_triplets, dtype=torch.float64, device=d.device), stream)
+                for p, d in zip(self.plans, deltas)]
             for p, o, d in zip(self.plans, bks, deltas):
                 p._out(o, p.n_triplets, d)
         da = _ptr_array([d.data_ptr() for d in deltas])
@@ -435,7 +455,8 @@ def bispectrum_batched(plans, deltas, precision: str = "mixed", stream=None):
     lib = _lib.load()
     for p, d in zip(plans, deltas):
         p._check_field(d)
-    outs = [torch.empty(p.n_triplets, dtype=torch.float64, device=d.device) for p, d in zip(plans, deltas)]
+    outs = [_on_stream(torch.empty(p.n_triplets, dtype=torch.float64, device=d.device), stream)
+            for p, d in zip(plans, deltas)]
     _lib.check(lib.pb3_bispectrum_batched(
         _ptr_array([p._h.value for p in plans]), _ptr_array([d.data_ptr() for d in deltas]),
         _ptr_array([o.data_ptr() for o in outs]), len(plans), _PREC[precision], _stream_handle(stream)))

@@ -325,8 +325,8 @@ pb3_status pb3_batch_run(pb3_batch* batch, const float* const* deltas, double* c
     return PB3_EINVAL;
   }
   for (int j = 0; j < batch->n_jobs; ++j) {
-    if (!deltas[j] || (pk && !pk[j]) || (bk && !bk[j])) {
-      set_error("null device pointer for job " + std::to_string(j));
+    if (!deltas[j] || (pk && !pk[j]) || (bk && !bk[j]) || ((uintptr_t)deltas[j] & 7u) != 0) {
+      set_error("null (or not 8-byte aligned) device pointer for job " + std::to_string(j));
       return PB3_EINVAL;
     }
   }

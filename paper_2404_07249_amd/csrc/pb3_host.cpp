@@ -852,6 +852,15 @@ int launches_per_sequence(const pb3_plan& p, bool do_pk, bool do_bk) {
   return n;
 }
 
+// Field pointers: the forward z pass reads pairs of float32 values.
+pb3_status check_field_ptr(const void* p, const char* what) {
+  if (((uintptr_t)p & 7u) != 0) {
+    set_error(std::string(what) + " must be 8-byte aligned");
+    return PB3_EINVAL;
+  }
+  return PB3_OK;
+}
+
 pb3_status check_prec(pb3_precision prec) {
   if (prec != PB3_FP32 && prec != PB3_MIXED_BF16X3) {
     set_error("unknown precision");
@@ -867,6 +876,7 @@ static pb3_status run(pb3_plan* p, const float* delta, double* pk, double* bk, p
     set_error("null device pointer");
     return PB3_EINVAL;
   }
+  if ((st = check_field_ptr(delta, "delta")) != PB3_OK) return st;
   if (bk && (p->flags & PB3_FLAG_POWER_ONLY)) {
     set_error("plan was created with PB3_FLAG_POWER_ONLY (no bispectrum tables)");
     return PB3_EINVAL;
@@ -1065,6 +1075,9 @@ pb3_status pb3_bispectrum_linear(pb3_plan* plan, const float* data_dev, const fl
     set_error("null argument");
     return PB3_EINVAL;
   }
+  if (check_field_ptr(data_dev, "data") != PB3_OK) return PB3_EINVAL;
+  for (int i = 0; i < n_sim; ++i)
+    if (sims_dev[i] && check_field_ptr(sims_dev[i], "each simulation") != PB3_OK) return PB3_EINVAL;
   if (!plan->device) {
     set_error("plan has no device state (created with PB3_FLAG_HOST_ONLY)");
     return PB3_EINVAL;
@@ -1109,6 +1122,10 @@ pb3_status pb3_masked_power(pb3_plan* plan, const float* data_dev, const float* 
     set_error("null argument");
     return PB3_EINVAL;
   }
+  if (check_field_ptr(data_dev, "data") != PB3_OK || check_field_ptr(window_dev, "window") != PB3_OK)
+    return PB3_EINVAL;
+  for (int i = 0; i < n_grf; ++i)
+    if (grfs_dev[i] && check_field_ptr(grfs_dev[i], "each random field") != PB3_OK) return PB3_EINVAL;
   if (!plan->device) {
     set_error("plan has no device state (created with PB3_FLAG_HOST_ONLY)");
     return PB3_EINVAL;
@@ -1343,6 +1360,7 @@ pb3_status pb3_multipoles(pb3_plan* plan, const float* delta_dev, double* pk_dev
     set_error("null argument");
     return PB3_EINVAL;
   }
+  if (check_field_ptr(delta_dev, "delta") != PB3_OK) return PB3_EINVAL;
   if (!plan->device || plan->lmax == 0) {
     set_error("multipoles need a device plan created with PB3_FLAG_LMAX2 or PB3_FLAG_LMAX4");
     return PB3_EINVAL;

@@ -197,6 +197,8 @@ pb3_status hip_fail(hipError_t e, const char* what);
 size_t workspace_bytes(const pb3_plan* p);
 Workspace carve(const pb3_plan* p, void* base, size_t bytes);
 pb3_status check_prec(pb3_precision prec);
+// PB3_EINVAL unless p is 8-byte aligned (what names the argument in the error)
+pb3_status check_field_ptr(const void* p, const char* what);
 // the whole launch sequence of one plan for the jobs of x, on stream s
 pb3_status enqueue(const pb3_plan& p, const Exec& x, bool do_pk, bool do_bk, pb3_precision prec, hipStream_t s);
 int launches_per_sequence(const pb3_plan& p, bool do_pk, bool do_bk);

@@ -127,37 +127,6 @@ def test_full_grid_flag_matches_reduced_grid(torch_cuda):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-def test_config3_256cubed_sampled(torch_cuda, prec):
-    """Headline size: P for every bin and B on a sample of triplets the
-    oracle computes one by one (only the filtered fields they touch)."""
-    torch = torch_cuda
-    d, cfg = field_for("c3")
-    plan, pk, bk = _run_case(torch, cfg["n"], cfg["box"], cfg["edges"], d, prec)
-    assert plan.contract_grid == 192
-    trips = plan.triplets
-    assert len(trips) == 3035
-    pk_ref = oracle.power_spectrum(d.astype(np.float64), cfg["box"], cfg["edges"])
-    assert np.all(np.abs(pk - pk_ref) <= P_RTOL * np.abs(pk_ref))
-    # sample triplets drawn from 8 of the 30 bins (the oracle only builds the
-    # filtered fields of those bins), always including the extreme bins
-    rng = np.random.default_rng(0)
-    bins = set(rng.choice(np.arange(1, 29), 6, replace=False).tolist()) | {0, 29}
-    cand = [i for i, t in enumerate(trips) if set(t.tolist()) <= bins]
-    pick = np.array(sorted(rng.choice(cand, min(16, len(cand)), replace=False)))
-    sample = trips[pick]
-    s, sa = oracle.triplet_sums_sample(d.astype(np.float64), cfg["edges"], sample)
-    T = oracle.count_sample(cfg["n"], cfg["edges"], sample)
-    _, cnt = plan.norm()
-    assert np.array_equal(cnt[pick].astype(np.int64), T)
-    n3 = float(cfg["n"]) ** 3
-    scale = cfg["box"] ** 6 / n3
-    bref = scale * s / T
-    aref = scale * sa / T
-    lim = B_RTOL * np.abs(bref) + B_ATOL_A * aref
-    assert np.all(np.abs(bk[pick] - bref) <= lim), np.abs(bk[pick] - bref) / aref
-
-
-@pytest.mark.parametrize("prec", PRECS)
 def test_determinism_and_exact_scaling(torch_cuda, prec):
     """Fixed-order reductions: repeated calls are bitwise equal, and 2*delta
     gives exactly 4 P and 8 B (power-of-two scaling is exact in binary FP,
@@ -174,31 +143,6 @@ def test_determinism_and_exact_scaling(torch_cuda, prec):
     pk3, bk3 = [t.cpu().numpy() for t in plan.polyspectra(2 * x, prec)]
     assert np.array_equal(pk3, 4 * pk1)
     assert np.array_equal(bk3, 8 * bk1)
-
-
-def test_translation_invariance_full_size(torch_cuda):
-    """An integer-voxel translation leaves P and B unchanged; at 256^3 each
-    run must stay within the parity bound, so the two differ by at most
-    twice it (A from the oracle on sampled triplets)."""
-    import paper_2404_07249_amd as pb3
-
-    torch = torch_cuda
-    d, cfg = field_for("c3")
-    plan = pb3.Plan(cfg["n"], cfg["box"], cfg["edges"])
-    pk1, bk1 = [t.cpu().numpy() for t in plan.polyspectra(_gpu(torch, d))]
-    pk2, bk2 = [t.cpu().numpy() for t in plan.polyspectra(_gpu(torch, np.roll(d, (17, -3, 101), axis=(0, 1, 2))))]
-    assert np.all(np.abs(pk1 - pk2) <= 2 * P_RTOL * np.abs(pk1))
-    trips = plan.triplets
-    rng = np.random.default_rng(1)
-    bins = set(rng.choice(np.arange(0, 30), 6, replace=False).tolist())
-    cand = [i for i, t in enumerate(trips) if set(t.tolist()) <= bins]
-    pick = np.array(sorted(rng.choice(cand, min(24, len(cand)), replace=False)))
-    s, sa = oracle.triplet_sums_sample(d.astype(np.float64), cfg["edges"], trips[pick])
-    _, cnt = plan.norm()
-    scale = cfg["box"] ** 6 / float(cfg["n"]) ** 3
-    aref = scale * sa / cnt[pick]
-    lim = 2 * (B_RTOL * np.abs(bk1[pick]) + B_ATOL_A * aref)
-    assert np.all(np.abs(bk1[pick] - bk2[pick]) <= lim)
 
 
 @pytest.mark.parametrize("case", ["c1", "48^3x13"])

@@ -15,6 +15,7 @@ import sys
 import numpy as np
 import pytest
 
+from _gates import multipole_gain, multipole_power_gate
 from oracle import weighted as wt
 from synthetic import kf_edges, pk_model, quadratic_field
 
@@ -143,7 +144,16 @@ def test_weighted_multipoles_match_oracle(torch_cuda, prec):
     pk, bk = [t.cpu().numpy() for t in plan.multipoles(torch.from_numpy(d).cuda(), precision=prec)]
     d64 = d.astype(np.float64)
     pref = wt.weighted_power_multipoles(d64, box, edges, lmax, order, tab, nbar)
-    assert np.all(np.abs(pk - pref) <= 1e-4 * np.abs(pref[0] + 1 / nbar)[None, :]), np.abs(pk - pref).max()
+    # the gain of the P_fid-weighted Fisher matrix; the scale is the monopole before the 1/nbar subtraction
+    from oracle.polyspec import bin_of_modes
+
+    k2 = (np.fft.fftfreq(n, 1.0 / n)[:, None, None] ** 2 + np.fft.fftfreq(n, 1.0 / n)[None, :, None] ** 2
+          + np.fft.fftfreq(n, 1.0 / n)[None, None, :] ** 2).round().astype(np.int64)
+    pfid = np.asarray(tab, dtype=np.float64)[np.minimum(k2, len(tab) - 1)]
+    gain = multipole_gain(bin_of_modes(n, edges), mu_grid(n) ** 2, len(edges) - 1, lmax, weight=pfid ** -2.0)
+    gate = multipole_power_gate(gain, pref[0] + 1 / nbar)
+    assert np.all(np.abs(pk - pref) <= gate), (np.abs(pk - pref) / gate).max()
+    assert np.all(np.abs(pk[0] - pref[0]) <= 1e-5 * np.abs(pref[0] + 1 / nbar))
     trips, bref = wt.weighted_bispectrum_multipoles(d64, box, edges, lmax, order, tab, nbar)
     assert np.array_equal(trips, plan.triplets)
     _, _, _, A = wt.weighted_bispectrum(d64, box, edges, order, tab, nbar)
