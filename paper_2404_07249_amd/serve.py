@@ -15,7 +15,9 @@ bispectrum on their own grid and binning.  The server
   requests overlaps on the device, and retires it when its completion
   event has fired, freeing the slot and the memory;
 * with simulations attached, gives B the linear term of the numerator
-  (Monte Carlo average, Sec. IV.C) before normalising;
+  (Monte Carlo average, Sec. IV.C) before normalising (such requests
+  batch only with each other, and their batch computes P alone: B comes
+  from the linear-term call);
 * normalises masked requests by the window moments (P / <w^2>,
   B / <w^3>: the conventional windowed estimators of Sec. III.D.2 and
   Sec. IV.D.2), and, when the request brings random fields, also returns
@@ -84,6 +86,7 @@ class Completed:
     done: float = 0.0
     batch_size: int = 0
     message: str = ""
+    mc_ms: float = 0.0  # device time of the Monte Carlo masked power spectrum (random fields), if any
 
     @property
     def latency(self) -> float:
@@ -112,6 +115,7 @@ class _Running:
     nbytes: int
     admitted: float
     pool_key: tuple
+    mc_events: list = field(default_factory=list)  # per request: (start, end) events of the MC call, or None
 
 
 @dataclass
@@ -270,7 +274,7 @@ class Server:
                 for r in list(self.queue)[1:]:
                     if len(group) >= _MAX_JOBS_PER_LAUNCH:
                         break
-                    if self._plan_key(r) == key and r.precision == head.precision:
+                    if self._plan_key(r) == key and r.precision == head.precision and bool(r.sims) == bool(head.sims):
                         nb = self._req_bytes(plan, r)
                         if self.bytes_in_use + used + nb > self.budget:
                             break
@@ -296,20 +300,27 @@ class Server:
             batch.bind_workspace(ws)
             pks = [torch.empty(plan.n_bins, dtype=torch.float64, device="cuda") for _ in group]
             bks = [torch.empty(plan.n_triplets, dtype=torch.float64, device="cuda") for _ in group]
-            batch.run([r.data for r in group], group[0].precision, pk_outs=pks, bk_outs=bks, stream=stream)
-            scratch, unw = [], []
+            with_sims = bool(group[0].sims)  # a group is all with or all without simulations
+            batch.run([r.data for r in group], group[0].precision, pk_outs=pks, bk_outs=None if with_sims else bks,
+                      bispectrum=not with_sims, stream=stream)
+            scratch, unw, mc_ev = [], [], []
             for r, pk, bk in zip(group, pks, bks):
                 mc = None
                 if r.sims:
-                    # B again with the linear term (replaces the batch's B)
+                    # B with the linear term (the batch computed P only)
                     lws = torch.empty(plan.linear_workspace_bytes(len(r.sims)), dtype=torch.uint8, device="cuda")
                     plan.bispectrum_linear(r.data, r.sims, r.precision, out=bk, workspace=lws, stream=stream)
+                ev_mc = None
                 if r.grfs:
                     # before the window normalisation, which rescales pk in place
                     full = self.full_plan_for(r.grid, r.box, r.edges)
                     mws = torch.empty(full.masked_workspace_bytes, dtype=torch.uint8, device="cuda")
+                    ev_mc = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                    ev_mc[0].record(stream)
                     mc = full.masked_power(r.data, r.window, r.grfs, workspace=mws, stream=stream)
+                    ev_mc[1].record(stream)
                 unw.append(mc)
+                mc_ev.append(ev_mc)
                 if r.window is not None:
                     sc = torch.empty(_lib.WINDOW_SCRATCH, dtype=torch.float64, device="cuda")
                     plan.window_normalize(r.window, pk, bk, scratch=sc, stream=stream)
@@ -318,11 +329,11 @@ class Server:
                     scratch.append(None)
             ev = torch.cuda.Event()
             ev.record(stream)
-        self.running.append(_Running(group, slot, batch, ws, pks, bks, scratch, unw, ev, nbytes, now, pkey))
+        self.running.append(_Running(group, slot, batch, ws, pks, bks, scratch, unw, ev, nbytes, now, pkey, mc_ev))
         self.bytes_in_use += nbytes
         st = self.stats
         st.admitted += len(group)
-        st.launches += batch.launches()
+        st.launches += batch.launches(True, not group[0].sims)
         st.batch_sizes.append(len(group))
         st.max_in_flight = max(st.max_in_flight, len(self.running))
         st.bytes_peak = max(st.bytes_peak, self.bytes_in_use)
@@ -333,13 +344,14 @@ class Server:
             if not run.event.query():
                 continue
             now = time.perf_counter()
-            for r, pk, bk, sc, mc in zip(run.reqs, run.pks, run.bks, run.scratch, run.unw):
+            for r, pk, bk, sc, mc, me in zip(run.reqs, run.pks, run.bks, run.scratch, run.unw, run.mc_events):
                 self.done[r.rid] = Completed(
                     r.rid, "ok", pk=pk.cpu().numpy(), bk=bk.cpu().numpy(),
                     moments=None if sc is None else sc[:2].cpu().numpy(),
                     pk_unwindowed=None if mc is None else mc[0].cpu().numpy(),
                     fisher=None if mc is None else mc[1].cpu().numpy(),
-                    arrival=r.arrival, admitted=run.admitted, done=now, batch_size=len(run.reqs))
+                    arrival=r.arrival, admitted=run.admitted, done=now, batch_size=len(run.reqs),
+                    mc_ms=0.0 if me is None else float(me[0].elapsed_time(me[1])))
                 n += 1
             self.running.remove(run)
             self.free_slots.append(run.slot)
@@ -375,6 +387,11 @@ class Server:
             "max_in_flight_batches": self.stats.max_in_flight,
             "max_queue": self.stats.max_queue,
             "mean_batch_size": float(np.mean(self.stats.batch_sizes)) if self.stats.batch_sizes else 0.0,
+            # device time of the Monte Carlo masked power spectrum per request, and its share of the
+            # requests' total service time (admission to completion)
+            "mc_ms": {"p50": float(np.percentile([c.mc_ms for c in res], 50)),
+                      "p99": float(np.percentile([c.mc_ms for c in res], 99))},
+            "mc_share_of_service": float(sum(c.mc_ms for c in res) / max(1e-9, 1e3 * sum(c.service for c in res))),
             "peak_bytes": self.stats.bytes_peak,
             "plans": len(self.plans),
         }
