@@ -345,6 +345,23 @@ int pb3_batch_groups(const pb3_batch* batch);
 pb3_status pb3_bispectrum_batched(pb3_plan* const* plans, const float* const* deltas, double* const* bk_outs,
                                   int n_jobs, pb3_precision prec, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the power
+ * spectrum of pb3_power, with its workspace (forward-pass outputs, compact
+ * spectrum, per-chunk sums: 8 Nx (Ny + Lcy) Kz + 8 Lcx Lcy Kz bytes and a
+ * few KB, with Lcx, Lcy, Kz the compact extents of the binned modes) in a
+ * static device array of 64 MiB that the library holds on every GPU it runs
+ * on until the process ends, instead of the plan's workspace (which it
+ * neither needs nor touches, so a plan made with PB3_FLAG_EXT_WORKSPACE may
+ * skip binding one).  Same arguments and output as pb3_power; calls no
+ * hipMalloc, hipFree or other allocating routine.  PB3_EUNSUPPORTED, with
+ * the bytes needed in pb3_last_error(), when the plan needs more than the
+ * array holds (54 MB at 256^3 with 30 bins of width 2 k_f fits; a 384^3
+ * grid with 40 such bins does not).  All calls on one GPU share the array:
+ * calls that overlap on one GPU (other streams, other threads) race and
+ * must be serialised by the caller. */
+pb3_status pb3_power_noalloc(pb3_plan* plan, const float* delta_dev, double* pk_dev, void* stream);
+
 const char* pb3_status_string(pb3_status s);
 const char* pb3_last_error(void);
 

@@ -203,6 +203,17 @@ class Plan:
         )
         return pk
 
+    def power_noalloc(self, delta, out, stream=None):
+        """``pb3_power_noalloc``: P into the caller's ``out`` (n_bins float64)
+        with the library's static scratch; allocates nothing."""
+        self._check_field(delta)
+        if out is None:
+            raise ValueError("power_noalloc needs an output tensor (it allocates nothing)")
+        pk = self._out(out, self.n_bins, delta)
+        _lib.check(self._lib.pb3_power_noalloc(self._h, C.c_void_p(delta.data_ptr()), C.c_void_p(pk.data_ptr()),
+                                               _stream_handle(stream)))
+        return pk
+
     def bispectrum(self, delta, precision: str = "fp32", out=None, stream=None):
         self._check_field(delta)
         bk = self._out(out, self.n_triplets, delta, stream)

@@ -78,6 +78,7 @@ SIGNATURES = [
     ("pb3_batch_groups", C.c_int, [C.c_void_p]),
     ("pb3_bispectrum_batched", C.c_int,
      [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_void_p]),
+    ("pb3_power_noalloc", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("pb3_status_string", C.c_char_p, [C.c_int]),
     ("pb3_last_error", C.c_char_p, []),
 ]
