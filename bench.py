@@ -100,17 +100,27 @@ def stage_work(plan_info: dict, precision: str) -> dict:
     w["inv_x"] = ("hbm", sum(ly * ly * kzn * c8 + m * ly * kzn * c8 for ly, kzn in geom))
     w["inv_y"] = ("hbm", sum(m * ly * kzn * c8 + m * m * kzn * c8 for ly, kzn in geom))
     w["inv_z"] = ("hbm", sum(m * m * kzn * c8 + m**3 * f4 for ly, kzn in geom))
-    # the recast GEMM: every pair a <= b against every c, over the M^3 voxels
+    # the method's work (eq. beta-def): per voxel one product per pair a <= b
+    # and a multiply-add per triangle-valid triplet
     n_pairs = nb * (nb + 1) // 2
-    w["contract"] = ("flops", 2.0 * n_pairs * nb * m**3)
+    w["contract"] = ("flops", float(n_pairs + 2 * plan_info["n_trip"]) * m**3)
     w["reduce"] = ("hbm", 0)
     return w
 
 
+def dense_gemm_flops(plan_info: dict) -> float:
+    """Flops of the contraction recast as a dense GEMM (every pair a <= b
+    against every bin c over the M^3 voxels): what the matrix cores would
+    execute without the triangle condition, for comparison only."""
+    nb, m = plan_info["nb"], plan_info["M"]
+    return 2.0 * (nb * (nb + 1) // 2) * nb * m**3
+
+
 def stage_rates(work: dict, stages: dict, precision: str) -> dict:
     """Achieved rate of every timed stage against its roofline: GB/s of
-    algorithmic bytes for the HBM-bound passes, TFLOP/s of the recast GEMM
-    for the contraction (which also carries the fused inverse z pass)."""
+    algorithmic bytes for the HBM-bound passes, TFLOP/s of the method's
+    contraction work for the contraction (which also carries the fused
+    inverse z pass)."""
     out = {}
     for k, (kind, amount) in work.items():
         ms = stages.get(k, (0.0, 0))[0]
@@ -404,36 +414,67 @@ def plan_geometry(n, box, edges):
         kpos = n // 2 - 1 if (full and kb == n // 2) else kb
         geom.append((kb + kpos + 1, kb + 1))
     _, _, nm = hp.bins()
-    return dict(N=n, M=m, Kz=kz, Lc=lc, nb=len(e) - 1, geom=geom, n_modes_half=int((nm.sum() + 1) // 2))
+    return dict(N=n, M=m, Kz=kz, Lc=lc, nb=len(e) - 1, geom=geom, n_modes_half=int((nm.sum() + 1) // 2),
+                n_trip=hp.n_triplets)
 
 
-def cpu_baseline(d32: np.ndarray, box: float, edges, n_trip_full: int, sample_trips: int = 300) -> dict:
-    """The FP64 oracle on the host cores: the forward FFT, the power
-    spectrum and all filtered fields in full, and the triplet sums for the
-    first ``sample_trips`` triplets, scaled to the full triplet count."""
+def copy_calibration() -> int:
+    """A plain device copy of exactly 256 MiB in and 256 MiB out, three
+    times: rocprofv3's FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of this
+    copy calibrate the traffic counters of the kernels."""
+    import torch
+
+    n = 256 * 1024 * 1024 // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_each_way": 4 * n, "copies": 3}), flush=True)
+    return 0
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(d32: np.ndarray, box: float, edges) -> dict:
+    """The FP64 oracle on the host cores for one whole field of the workload:
+    forward FFT, P(k), every filtered field and the triplet sums of every
+    triangle-valid triplet (the per-field estimator; the data-independent
+    triangle counts are plan-time work and not timed)."""
     import oracle
 
-    os.environ.setdefault("ORACLE_FFT_WORKERS", str(_cores()))
+    threads = min(_cores(), int(os.environ.get("OMP_NUM_THREADS", _cores())))
+    os.environ["ORACLE_FFT_WORKERS"] = str(threads)
     d = d32.astype(np.float64)
+    trips = oracle.triangle_triplets(edges)
     t0 = time.perf_counter()
     oracle.power_spectrum(d, box, edges)
     G = oracle.filtered_fields(d, edges)
     t_fft = time.perf_counter() - t0
-    trips = oracle.triangle_triplets(edges)[:sample_trips]
-    t1 = time.perf_counter()
     oracle.triple_sums(G, trips)
-    t_c = time.perf_counter() - t1
-    per = t_fft + t_c * (n_trip_full / len(trips))
+    per = time.perf_counter() - t0
     return {
         "value": 1.0 / per,
         "unit": "bispectra/s",
-        "cores": _cores(),
+        "cores": threads,
         "kind": "oracle",
         "sample": (
-            f"one 256^3 field: FP64 forward FFT, P(k) and all {len(edges) - 1} filtered fields in full "
-            f"({t_fft:.2f} s), triplet sums for the first {len(trips)} of {n_trip_full} triplets "
-            f"({t_c:.2f} s) scaled to all; FFTs on {_cores()} threads, triplet sums numpy/BLAS"
+            f"one whole 256^3 field: FP64 forward FFT, P(k), all {len(edges) - 1} filtered fields ({t_fft:.2f} s) "
+            f"and the sums of all {len(trips)} triplets ({per - t_fft:.2f} s); {threads} threads "
+            "(FFT workers and the triplet-sum thread pool)"
         ),
+        "seconds": per,
+        "cpu_model": _cpu_model(),
+        "nproc": os.cpu_count(),
     }
 
 
@@ -451,9 +492,13 @@ def main(argv=None):
     ap.add_argument("--no-linear", action="store_true", help="skip the linear-term measurement")
     ap.add_argument("--no-noncubic", action="store_true", help="skip the non-cubic geometry measurement")
     ap.add_argument("--serve-mc", type=int, default=8, help="random fields per serving request (0: windowed only)")
-    ap.add_argument("--serve-requests", type=int, default=200,
-                    help="requests in the serving measurement (0 skips it; 2000 for the full stream)")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests in the serving measurement (0 skips it)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy three times (calibrates the traffic counters)")
     args = ap.parse_args(argv)
+    if args.copy_calibration:
+        return copy_calibration()
     if args.gpus != 1:
         print(
             json.dumps({"error": "the library runs on one GPU; --gpus above 1 is not supported", "n_gpus": args.gpus}),
@@ -473,6 +518,7 @@ def main(argv=None):
     plan = pb3.Plan(n, box, edges, autotune=not args.no_autotune)
     tplan = pb3.Plan(n, box, edges, stage_timing=True, autotune=not args.no_autotune)
     info = plan_geometry(n, box, edges)
+    info["n_trip"] = plan.n_triplets
     x = torch.from_numpy(d32).cuda()
     pk = torch.empty(plan.n_bins, dtype=torch.float64, device="cuda")
     bk = torch.empty(plan.n_triplets, dtype=torch.float64, device="cuda")
@@ -528,8 +574,12 @@ def main(argv=None):
     if kind == "flops":
         peak = BF16_PEAK_TFLOPS if main_p == "mixed" else FP32_MFMA_PEAK_TFLOPS
         achieved = amount / (ms * 1e-3) / 1e12
+        dense = dense_gemm_flops(info) / (ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": measured_traffic(dom, main_p, plan.launch_shape["contract_wgs"])}
+                "traffic": measured_traffic(dom, main_p, plan.launch_shape["contract_wgs"]),
+                "work": "(pairs a<=b + 2 x triplets) x M^3 flops per launch (eq. beta-def)",
+                "dense_equivalent": {"TFLOP/s": dense, "frac": dense / peak,
+                                     "work": "2 x pairs x bins x M^3 (every pair against every bin)"}}
     else:
         achieved = amount / (ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -584,7 +634,7 @@ def main(argv=None):
     if args.serve_requests > 0:
         line["serving"] = serving_bench(args.serve_requests, precision=main_p, n_mc=args.serve_mc)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(d32, box, edges, plan.n_triplets)
+        line["cpu_baseline"] = cpu_baseline(d32, box, edges)
     print(json.dumps(line), flush=True)
     return 0
 
