@@ -6,7 +6,8 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpb3.so")
+# PB3_LIBRARY names another build of the same library (the sanitizer build)
+LIB_PATH = os.environ.get("PB3_LIBRARY") or os.path.join(_HERE, "libpb3.so")
 
 PB3_OK = 0
 STATUS = {0: "PB3_OK", 1: "PB3_EINVAL", 2: "PB3_ENOMEM", 3: "PB3_EDEVICE", 4: "PB3_EUNSUPPORTED", 5: "PB3_EBUSY"}
