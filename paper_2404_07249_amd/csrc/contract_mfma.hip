@@ -581,66 +581,90 @@ __device__ __forceinline__ void pair_init(PairSrc<M>& ps, const float2* a2, cons
   }
 }
 
+// Which inputs j of a phase-1 lane (plane n = tl + R2 j, tl < R2) can be
+// nonzero when every bin keeps fewer than KB planes (kzn <= KB - 1; KB = 0:
+// no bound): plane n itself (n < kzn) or its mirror M - n (M - n < kzn).
+// On an alias-free contraction grid (M > 3 K) kzn <= M / 3 + 1, so at
+// M = 192 inputs j = 0..5 can only be direct planes, j = 10..15 only
+// mirrored ones, and j = 6..9 are always zero: no load, no select.
+template <int M, int KB> struct PlaneKinds {
+  static constexpr int R2 = fft2_r2(M);
+  static constexpr bool direct(int j) { return KB == 0 || R2 * j < KB; }
+  static constexpr bool mirror(int j) { return KB == 0 || M - R2 * j - (R2 - 1) < KB; }
+};
+
 // Raw inputs of one line for a phase-1 lane: plane n = tl + R2 j comes from
 // plane n (n < kzn) or, conjugated when combined, from plane M - n
-// (M - n < kzn) of the half-spectrum; otherwise it is zero.
+// (M - n < kzn) of the half-spectrum; otherwise it is zero.  The plane
+// bounds are re-read on each call, so that no comparison derived from them
+// is kept across the line loop (the compiler would hold them as lane masks
+// in scalar registers and spill those).
 // MASKED (the FP32 groups, short of registers): loads under lane masks
-// leave the zero planes zero; the plane bounds are re-read on each call so
-// that no derived index stays in registers across the line loop.
-// Otherwise every lane loads (plane 0 stands in for a zero plane, so that
-// every address lies in the line) and the combine selects; fewer
-// instructions wait on the loads, which suits fetching a line ahead.
-template <int M, bool MASKED>
+// leave the zero planes zero.  Otherwise every lane loads (plane 0 stands
+// in for a zero plane, so that every address lies in the line) and the
+// combine selects; fewer instructions wait on the loads, which suits
+// fetching a line ahead.
+template <int M, bool MASKED, int KB>
 __device__ __forceinline__ void pair_fetch(PairSrc<M>& ps, long line, int tl) {
+  using PK = PlaneKinds<M, KB>;
   constexpr int R1 = PairSrc<M>::R1, R2 = PairSrc<M>::R2;
   if (!ps.on || tl >= R2) return;
   const float2* p0 = ps.x0 + line * ps.s0;
   const float2* p1 = ps.x1 + line * ps.s1;
   int k0n = ps.k0n, k1n = ps.k1n;
-  if constexpr (MASKED) asm volatile("" : "+v"(k0n), "+v"(k1n));
+  asm volatile("" : "+v"(k0n), "+v"(k1n));
 #pragma unroll
   for (int j = 0; j < R1; ++j) {
     const int k = tl + R2 * j, m = M - k;
+    const bool d = PK::direct(j), r = PK::mirror(j);
+    if (!d && !r) continue;  // never loaded, never read
     if constexpr (MASKED) {
       float2 a = make_float2(0.f, 0.f), c = make_float2(0.f, 0.f);
-      if (k < k0n) a = p0[k];
-      else if (m < k0n) a = p0[m];
-      if (k < k1n) c = p1[k];
-      else if (m < k1n) c = p1[m];
+      if (d && k < k0n) a = p0[k];
+      else if (r && m < k0n) a = p0[m];
+      if (d && k < k1n) c = p1[k];
+      else if (r && m < k1n) c = p1[m];
       ps.r0[j] = a;
       ps.r1[j] = c;
     } else {
-      ps.r0[j] = p0[k < k0n ? k : (m < k0n ? m : 0)];
-      ps.r1[j] = p1[k < k1n ? k : (m < k1n ? m : 0)];
+      ps.r0[j] = p0[(d && k < k0n) ? k : ((r && m < k0n) ? m : 0)];
+      ps.r1[j] = p1[(d && k < k1n) ? k : ((r && m < k1n) ? m : 0)];
     }
   }
 }
 
 // Build the stage for one line from the fetched inputs; next >= 0 starts the
 // fetch of that line once phase 1 has taken these.
-template <int NQ, bool MIXED, int M, bool MASKED>
+template <int NQ, bool MIXED, int M, bool MASKED, int KB>
 __device__ __forceinline__ void produce_line(LineStage<NQ, M>& st, PairSrc<M>& ps, long next, const float2* tws,
                                              float2* scr, int slot, int tl, float scale, const SplitSel& sel) {
+  using PK = PlaneKinds<M, KB>;
   constexpr int R1 = fft2_r1(M), R2 = fft2_r2(M);
   constexpr int PF = LineStage<NQ, M>::PF, PH = LineStage<NQ, M>::PH;
   if (!ps.on) return;
   const int b0 = 2 * slot, b1 = 2 * slot + 1;
+  int k0n = ps.k0n, k1n = ps.k1n;  // re-read per line (see pair_fetch)
+  asm volatile("" : "+v"(k0n), "+v"(k1n));
   fft2_line_wave<M, 1>(
       scr + slot * R1 * (R2 + 1), tl, tws,
       [&](int j, int k) {
+        const bool d = PK::direct(j), r = PK::mirror(j);
+        if (!d && !r) return make_float2(0.f, 0.f);
         float2 a = ps.r0[j], c = ps.r1[j];
         if constexpr (MASKED) {
-          if (k >= ps.k0n) a.y = -a.y;  // mirrored plane (or zero)
-          if (k >= ps.k1n) c.y = -c.y;
+          if (!d || k >= k0n) a.y = -a.y;  // mirrored plane (or zero)
+          if (!d || k >= k1n) c.y = -c.y;
         } else {
           const int m = M - k;
-          if (k >= ps.k0n) a = (m < ps.k0n) ? make_float2(a.x, -a.y) : make_float2(0.f, 0.f);
-          if (k >= ps.k1n) c = (m < ps.k1n) ? make_float2(c.x, -c.y) : make_float2(0.f, 0.f);
+          const bool a_d = d && k < k0n, c_d = d && k < k1n;
+          const bool a_r = r && m < k0n, c_r = r && m < k1n;
+          if (!a_d) a = a_r ? make_float2(a.x, -a.y) : make_float2(0.f, 0.f);
+          if (!c_d) c = c_r ? make_float2(c.x, -c.y) : make_float2(0.f, 0.f);
         }
         return make_float2(a.x - c.y, a.y + c.x);  // F_b + i F_{b+1}
       },
       [&]() {
-        if (next >= 0) pair_fetch<M, MASKED>(ps, next, tl);
+        if (next >= 0) pair_fetch<M, MASKED, KB>(ps, next, tl);
       },
       [&](int k1, const float2 (&u)[R2]) {
 #pragma unroll
@@ -669,7 +693,8 @@ __device__ __forceinline__ void produce_line(LineStage<NQ, M>& st, PairSrc<M>& p
       });
 }
 
-template <int NQ, bool MIXED, int M>
+// KB: every bin keeps fewer than KB z planes (0: no bound; see PlaneKinds).
+template <int NQ, bool MIXED, int M, int KB>
 __global__ void __launch_bounds__(fused_threads(MIXED)) k_zcontract(const float2* __restrict__ a2,
                                                              const BinGeom* __restrict__ geom, int nb,
                                                              const float2* __restrict__ tw, float scale, long lpw,
@@ -720,16 +745,16 @@ __global__ void __launch_bounds__(fused_threads(MIXED)) k_zcontract(const float2
     pair_init<M>(ps, a2, geom, nb, pslot, n > 0);
     constexpr bool AHEAD = MIXED;  // fetch a line ahead (see PairSrc)
     if (ps.on) {
-      pair_fetch<M, !AHEAD>(ps, l0, ptl);
-      produce_line<NQ, MIXED, M, !AHEAD>(stage[0], ps, AHEAD && n > 1 ? l0 + 1 : -1, tws, scr, pslot, ptl, scale,
-                                         sel);
+      pair_fetch<M, !AHEAD, KB>(ps, l0, ptl);
+      produce_line<NQ, MIXED, M, !AHEAD, KB>(stage[0], ps, AHEAD && n > 1 ? l0 + 1 : -1, tws, scr, pslot, ptl,
+                                             scale, sel);
     }
     __syncthreads();
     for (int m = 0; m < n; ++m) {
       if (m + 1 < n) {
-        if constexpr (!AHEAD) pair_fetch<M, true>(ps, l0 + m + 1, ptl);
-        produce_line<NQ, MIXED, M, !AHEAD>(stage[(m + 1) & 1], ps, AHEAD && m + 2 < n ? l0 + m + 2 : -1, tws, scr,
-                                           pslot, ptl, scale, sel);
+        if constexpr (!AHEAD) pair_fetch<M, true, KB>(ps, l0 + m + 1, ptl);
+        produce_line<NQ, MIXED, M, !AHEAD, KB>(stage[(m + 1) & 1], ps, AHEAD && m + 2 < n ? l0 + m + 2 : -1, tws,
+                                               scr, pslot, ptl, scale, sel);
       }
       __syncthreads();
     }
@@ -799,9 +824,16 @@ static hipError_t launch_fused_m(const pb3_plan& p, const Exec& x, hipStream_t s
   if (fused_waves(MIXED) == 1 && p.n_cu > 0)
     while (cpw < 4 && p.contract_wgs % (2 * cpw) == 0 && p.contract_wgs / (2 * cpw) >= p.n_cu) cpw *= 2;
   const int n_wg = (p.contract_wgs + cpw - 1) / cpw;
-  hipLaunchKernelGGL((k_zcontract<NQ, MIXED, M>), dim3(n_wg, 1, x.n_jobs), dim3(fused_threads(MIXED)), 0, s,
-                     x.ws.a2, p.d.geom, p.nb, p.d.tw_m[2], scale, lpw, x.ws.part, p.part_len, sel_lo, sel_hi,
-                     x.wstride, nlines, cpw, p.contract_wgs);
+  // every bin keeps at most Kz planes; on an alias-free grid Kz <= M / 3 + 1
+  constexpr int KB = M / 3 + 2;
+  if (p.Kz < KB)
+    hipLaunchKernelGGL((k_zcontract<NQ, MIXED, M, KB>), dim3(n_wg, 1, x.n_jobs), dim3(fused_threads(MIXED)), 0, s,
+                       x.ws.a2, p.d.geom, p.nb, p.d.tw_m[2], scale, lpw, x.ws.part, p.part_len, sel_lo, sel_hi,
+                       x.wstride, nlines, cpw, p.contract_wgs);
+  else
+    hipLaunchKernelGGL((k_zcontract<NQ, MIXED, M, 0>), dim3(n_wg, 1, x.n_jobs), dim3(fused_threads(MIXED)), 0, s,
+                       x.ws.a2, p.d.geom, p.nb, p.d.tw_m[2], scale, lpw, x.ws.part, p.part_len, sel_lo, sel_hi,
+                       x.wstride, nlines, cpw, p.contract_wgs);
   return hipGetLastError();
 }
 
@@ -829,13 +861,13 @@ int fused_grid(int nq, int m, long mvox, int n_cu) {
   hipError_t e = hipErrorInvalidValue;
   const void* fn = nullptr;
   if (nq == 1) {
-    fn = m == 32 ? (const void*)k_zcontract<1, true, 32> : m == 64 ? (const void*)k_zcontract<1, true, 64>
-       : m == 96 ? (const void*)k_zcontract<1, true, 96> : m == 128 ? (const void*)k_zcontract<1, true, 128>
-                 : (const void*)k_zcontract<1, true, 192>;
+    fn = m == 32 ? (const void*)k_zcontract<1, true, 32, 0> : m == 64 ? (const void*)k_zcontract<1, true, 64, 0>
+       : m == 96 ? (const void*)k_zcontract<1, true, 96, 0> : m == 128 ? (const void*)k_zcontract<1, true, 128, 0>
+                 : (const void*)k_zcontract<1, true, 192, 0>;
   } else {
-    fn = m == 32 ? (const void*)k_zcontract<2, true, 32> : m == 64 ? (const void*)k_zcontract<2, true, 64>
-       : m == 96 ? (const void*)k_zcontract<2, true, 96> : m == 128 ? (const void*)k_zcontract<2, true, 128>
-                 : (const void*)k_zcontract<2, true, 192>;
+    fn = m == 32 ? (const void*)k_zcontract<2, true, 32, 0> : m == 64 ? (const void*)k_zcontract<2, true, 64, 0>
+       : m == 96 ? (const void*)k_zcontract<2, true, 96, 0> : m == 128 ? (const void*)k_zcontract<2, true, 128, 0>
+                 : (const void*)k_zcontract<2, true, 192, 0>;
   }
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, fused_threads(true), 0);
   if (e != hipSuccess || per < 1) per = 1;
