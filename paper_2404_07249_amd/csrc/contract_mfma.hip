@@ -48,14 +48,21 @@ typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2_t;
 //     across two), columns c >= 16 q.  Every triplet is read at (pair
 //     (a, b), column c), as the column operand must be for the multipoles,
 //     whose Legendre weight sits on the c leg.
-//   kLayoutDiag: only the pairs inside one group (p = q), against every
-//     column block.  S_abc is symmetric, and a triplet a <= b <= c always has
-//     two bins in one group when there are at most two groups (with three,
-//     the triplets with a, b, c in groups 0, 1, 2 take the cross blocks
-//     (0, 1, s) against column block 2).  At two groups this is 18 pair
-//     blocks and 36 tiles instead of 34 and 43: fewer pair products to form
-//     and split on the VALU, fewer MFMAs.
+//   kLayoutDiag: only the pairs inside one group (p = q).  S_abc is
+//     symmetric, and a triplet a <= b <= c always has two bins in one group
+//     when there are at most two groups (with three, the triplets with a,
+//     b, c in groups 0, 1, 2 take the cross blocks (0, 1, s) against column
+//     block 2).  A triplet with two bins in group p and one in group q != p
+//     is read at the pair in p against column block q, so blocks (p, p, s)
+//     take every other group's column block.  A triplet with all three bins
+//     in group p: their positions cut the 16-cycle into three arcs that sum
+//     to 16, so some pair is at most 5 apart, and it is read at that pair;
+//     blocks (p, p, s) take their own column block only for s <= 5 (with
+//     one group, blocks s = 6..8 are not formed at all).  At two groups
+//     this is 18 pair blocks and 30 tiles instead of 34 and 43: fewer pair
+//     products to form and split on the VALU, fewer MFMAs.
 constexpr int kLayoutAB = 0, kLayoutDiag = 1;
+constexpr int kDiagOwnMaxS = 5;  // largest pair separation a one-group triplet needs (16 / 3 rounded down)
 
 struct PairBlock {
   int p, q, s;
@@ -76,9 +83,10 @@ constexpr PairBlock pair_block(int L, int nq, int k) {
   } else {
     // group 0, then (nq == 3) the cross blocks of groups 0 and 1, then the
     // other groups
+    const int ns = nq == 1 ? kDiagOwnMaxS + 1 : 9;
     for (int p = 0; p < nq; ++p) {
-      if (k < 9) return PairBlock{p, p, k, all_cols(nq)};
-      k -= 9;
+      if (k < ns) return PairBlock{p, p, k, k <= kDiagOwnMaxS ? all_cols(nq) : all_cols(nq) & ~(1u << p)};
+      k -= ns;
       if (p == 0 && nq == 3) {
         if (k < 16) return PairBlock{0, 1, k, 1u << 2};
         k -= 16;
@@ -88,7 +96,8 @@ constexpr PairBlock pair_block(int L, int nq, int k) {
   return PairBlock{-1, -1, -1, 0u};
 }
 constexpr int n_pair_blocks(int L, int nq) {
-  return L == kLayoutAB ? nq * 9 + (nq * (nq - 1) / 2) * 16 : nq * 9 + (nq == 3 ? 16 : 0);
+  return L == kLayoutAB ? nq * 9 + (nq * (nq - 1) / 2) * 16
+                        : (nq == 1 ? kDiagOwnMaxS + 1 : nq * 9 + (nq == 3 ? 16 : 0));
 }
 constexpr int popc(unsigned m) { return m ? (int)(m & 1u) + popc(m >> 1) : 0; }
 // tiles (pair block x column block) in pair blocks [0, k)
@@ -111,7 +120,7 @@ constexpr int group_begin(int L, int nq, int g) {
     // tiles per block: 3, 2, 1, 2, 1, 1 -> groups of 43, 32, 43 tiles
     return g == 0 ? 0 : g == 1 ? 9 + 8 : g == 2 ? 9 + 16 + 16 : n_pair_blocks(L, nq);
   }
-  // (0,0)9 x 3 + (0,1)16 x 1 = 43 tiles, then (1,1)9 + (2,2)9 x 3 = 54 tiles
+  // (0,0) 6 x 3 + 3 x 2, (0,1) 16 x 1: 40 tiles, then (1,1) and (2,2): 48 tiles
   return g == 0 ? 0 : g == 1 ? 25 : n_pair_blocks(L, nq);
 }
 
@@ -896,16 +905,34 @@ int mfma_tiles(bool ab, int nq) {
 
 // Partial-vector index of triplet (a, b, c), a <= b <= c: its tile, row and
 // column (-1 if the layout does not produce it).  kLayoutAB reads it at
-// (pair (a, b), column c); kLayoutDiag at (pair (a, b), column c) when a
-// and b share a group, else at (pair (b, c), column a) when b and c do,
-// else (three groups) at the cross pair (a, b) against column c.
+// (pair (a, b), column c).  kLayoutDiag: all three in one group, at the
+// pair of the smallest separation against the third bin; else at (pair
+// (a, b), column c) when a and b share a group, at (pair (b, c), column a)
+// when b and c do, and (three groups) at the cross pair (a, b) against c.
 int mfma_locate(bool ab, int nq, int a, int b, int c) {
   const int L = ab ? kLayoutAB : kLayoutDiag;
   int x = a, y = b, z = c;
-  if (!ab && a / 16 != b / 16 && b / 16 == c / 16) {
-    x = b;
-    y = c;
-    z = a;
+  auto sep = [](int u, int v) {  // cyclic separation of two positions in a 16-bin group
+    const int d = ((u - v) % 16 + 16) % 16;
+    return d <= 8 ? d : 16 - d;
+  };
+  if (!ab) {
+    if (a / 16 == b / 16 && b / 16 == c / 16) {
+      // all in one group: the pair at the smallest separation (at most 5)
+      const int sab = sep(a, b), sac = sep(a, c), sbc = sep(b, c);
+      if (sac < sab && sac <= sbc) {
+        y = c;
+        z = b;
+      } else if (sbc < sab && sbc < sac) {
+        x = b;
+        y = c;
+        z = a;
+      }
+    } else if (a / 16 != b / 16 && b / 16 == c / 16) {
+      x = b;
+      y = c;
+      z = a;
+    }
   }
   const int p = x / 16, q = y / 16, ix = x % 16, iy = y % 16;
   int row, s;
