@@ -233,17 +233,22 @@ __device__ __forceinline__ void do_blocks(const float (&gv)[NQ][8], const bf16x8
 // the same voxels; boundaries balance an estimated cost per block (its
 // split on the VALU plus its tiles on the matrix core).
 constexpr int block_cost(int L, int nq, int k) { return 96 + 48 * popc(pair_block(L, nq, k).cmask); }
+// (boundary g: the block edge whose running cost is nearest g/ng of the total)
 constexpr int group_bound(int L, int nq, int k0, int k1, int ng, int g) {
   if (g <= 0) return k0;
   if (g >= ng) return k1;
   int total = 0;
   for (int k = k0; k < k1; ++k) total += block_cost(L, nq, k);
-  int acc = 0;
-  for (int k = k0; k < k1; ++k) {
-    if (acc * ng >= total * g) return k;
-    acc += block_cost(L, nq, k);
+  int acc = 0, best = k0, best_err = total * ng + 1;
+  for (int k = k0; k <= k1; ++k) {
+    const int err = acc * ng > total * g ? acc * ng - total * g : total * g - acc * ng;
+    if (err < best_err) {
+      best_err = err;
+      best = k;
+    }
+    if (k < k1) acc += block_cost(L, nq, k);
   }
-  return k1;
+  return best;
 }
 // union of the column blocks and of the row groups of pair blocks [b, e)
 constexpr unsigned range_cols(int L, int nq, int b, int e) {
