@@ -44,12 +44,25 @@ FP32_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # figure is dropped (null) once their hash differs.
 MEASURED_TRAFFIC = {
     ("contract", "mixed"): {
-        "kernel": "k_zcontract<2, true, 192>",
+        "kernel": "k_zcontract<2, true, 192, 66>",
         "contract_wgs": 1024,  # partial-vector writes scale with the accumulation-chunk count
-        "fetch_kib": 138472.3, "write_kib": 44032.0, "fetch_factor": 2.0, "write_factor": 1.0,
+        "fetch_kib": 138396.2, "write_kib": 30720.0, "fetch_factor": 2.0, "write_factor": 1.0,
         "sources": {
             "paper_2404_07249_amd/csrc/contract_mfma.hip":
-                "7a32d987869f6e3f939e42bf785745c262dc0d4a233a92a76c331ea72ac9b376",
+                "f856260e00766fa0483fccfd971444be3785b27b6f54b6fd072553c45a232daa",
+            "paper_2404_07249_amd/csrc/fft_dev.h":
+                "df3b6d76c6673e67d4b39f61aa79139393ef94214581251510d14c1ded1023f4",
+            "paper_2404_07249_amd/csrc/job.h":
+                "0f3d39c847bc50252698d89b0082866e4ca72f6f435cacd590aacb25667591d2",
+        },
+    },
+    ("contract", "fp32"): {
+        "kernel": "k_zcontract<2, false, 192, 66>",
+        "contract_wgs": 1024,
+        "fetch_kib": 139862.5, "write_kib": 30720.0, "fetch_factor": 2.0, "write_factor": 1.0,
+        "sources": {
+            "paper_2404_07249_amd/csrc/contract_mfma.hip":
+                "f856260e00766fa0483fccfd971444be3785b27b6f54b6fd072553c45a232daa",
             "paper_2404_07249_amd/csrc/fft_dev.h":
                 "df3b6d76c6673e67d4b39f61aa79139393ef94214581251510d14c1ded1023f4",
             "paper_2404_07249_amd/csrc/job.h":
