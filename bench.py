@@ -509,9 +509,15 @@ def main(argv=None):
                     help="requests in the serving measurement (0 skips it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (calibrates the traffic counters)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only run the batched-workload measurement (default launch shapes) and print its JSON")
     args = ap.parse_args(argv)
     if args.copy_calibration:
         return copy_calibration()
+    if args.batched_only:
+        r = batched_bench(reps=5, warmup=2, precision=args.precision, autotune=False)
+        print(json.dumps({"batched": r}), flush=True)
+        return 0
     if args.gpus != 1:
         print(
             json.dumps({"error": "the library runs on one GPU; --gpus above 1 is not supported", "n_gpus": args.gpus}),
