@@ -234,7 +234,8 @@ __global__ void __launch_bounds__(512) k_inv_x2(const float2* __restrict__ dc, t
                                                 const typename Cx<Rl>::type* __restrict__ tw, size_t wstride,
                                                 int ell, const float* __restrict__ winv, WinOff wo, float sx,
                                                 float sy, const float* __restrict__ pinv,
-                                                const double* __restrict__ uw, AngW aw, size_t nb3) {
+                                                const double* __restrict__ uw, AngW aw, size_t nb3,
+                                                double* __restrict__ ppart, int kz_nyq) {
   dc = job_ptr(dc, wstride);
   a1 = job_ptr(a1, wstride);
   using C = typename Cx<Rl>::type;
@@ -269,6 +270,12 @@ __global__ void __launch_bounds__(512) k_inv_x2(const float2* __restrict__ dc, t
         // loads of a line are in flight together rather than one element
         // after another.  The forward pass writes every compact entry, so
         // a masked-out value is finite whenever the field is.
+        // With ppart, the lanes also sum |Theta_b D|^2 over the modes they
+        // gather: each of the bin's modes lies in exactly one column of
+        // one of its tiles, so the tiles' sums are the power spectrum's
+        // numerator (eq. pk-limit), weight 2 for the half spectrum's
+        // modes whose conjugate is not stored.
+        double pacc = 0.0;
         fft2_line<M, 1>(
             scr + col * LS, tl, tws,
             [&](int n) {
@@ -278,9 +285,28 @@ __global__ void __launch_bounds__(512) k_inv_x2(const float2* __restrict__ dc, t
               const int bb = bin3[in ? ci : nb3];
               const float2 d = dc[ci];
               const float m = bb == b ? 1.f : 0.f;
-              return cx<C>(Rl(fmaf(d.x, m, 0.f)), Rl(fmaf(d.y, m, 0.f)));
+              const float vx = fmaf(d.x, m, 0.f), vy = fmaf(d.y, m, 0.f);
+              if (ppart) pacc += (double)vx * vx + (double)vy * vy;
+              return cx<C>(Rl(vx), Rl(vy));
             },
             store);
+        if (ppart) {
+          // fixed-order sum over the work-group: butterfly within each
+          // wave, then the waves in order
+          static_assert(S::NT % 64 == 0, "whole wavefronts");
+          __shared__ double wsum[S::NT / 64];
+          double v = pacc * ((kz == 0 || kz == kz_nyq) ? 1.0 : 2.0);
+#pragma unroll
+          for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+          if ((tid & 63) == 0) wsum[tid >> 6] = v;
+          __syncthreads();
+          if (tid == 0) {
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < S::NT / 64; ++w) t += wsum[w];
+            job_ptr(ppart, wstride)[ti] = t;
+          }
+        }
         return;
       }
     }
@@ -510,7 +536,7 @@ hipError_t launch_fwd_x(const pb3_plan& p, const Exec& x, hipStream_t s) {
 
 hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, const float2* dc, void* a1, const TileSet& ts,
                      int n_jobs, size_t wstride, hipStream_t s, int ell, const double* unit_w, bool weighted,
-                     AngW aw) {
+                     AngW aw, double* ppart) {
   const float* winv = weighted ? p.d.win_inv : nullptr;
   const float* pinv = weighted ? p.d.pfid_inv : nullptr;
   const WinOff wo{p.Nx / 2, p.Nx + 1 + p.Ny / 2, p.Nx + p.Ny + 2 + p.Nz / 2};
@@ -523,15 +549,18 @@ hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, const float2* dc, v
       if (unit)
         hipLaunchKernelGGL((k_inv_x2<LL, double, true>), dim3(xcd_tiles(ts.n), 1, n_jobs), dim3(S::NT), 0, s, dc,
                            (double2*)a1, p.d.geom, ts.d, ts.n, p.d.bin3, p.Kcx, p.Kcy, p.Lcy, p.Kz, (const double2*)tw,
-                           wstride, 0, (const float*)nullptr, wo, sx, sy, (const float*)nullptr, unit_w, aw, ncompact(p));
+                           wstride, 0, (const float*)nullptr, wo, sx, sy, (const float*)nullptr, unit_w, aw, ncompact(p),
+                           (double*)nullptr, -1);
       else
         return hipErrorInvalidValue;
     } else {
       using S = ColShape<LL, 8>;
       if (unit) return hipErrorInvalidValue;
+      if (ppart && (winv || pinv || ell)) return hipErrorInvalidValue;  // the power sums take plain spectra
       hipLaunchKernelGGL((k_inv_x2<LL, float, false>), dim3(xcd_tiles(ts.n), 1, n_jobs), dim3(S::NT), 0, s, dc,
                          (float2*)a1, p.d.geom, ts.d, ts.n, p.d.bin3, p.Kcx, p.Kcy, p.Lcy, p.Kz, (const float2*)tw,
-                         wstride, ell, winv, wo, sx, sy, pinv, (const double*)nullptr, AngW{}, ncompact(p));
+                         wstride, ell, winv, wo, sx, sy, pinv, (const double*)nullptr, AngW{}, ncompact(p), ppart,
+                         p.fullz ? p.Nz / 2 : -1);
     }
     return hipGetLastError();
   });
@@ -580,8 +609,8 @@ hipError_t run_inv_z(const pb3_plan& p, bool dbl, const void* a2, void* gout, co
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_inv_x(const pb3_plan& p, const Exec& x, hipStream_t s) {
-  return run_inv_x(p, false, false, x.ws.dc, x.ws.a1, p.tx, x.n_jobs, x.wstride, s, 0, nullptr, true);
+hipError_t launch_inv_x(const pb3_plan& p, const Exec& x, hipStream_t s, double* ppart) {
+  return run_inv_x(p, false, false, x.ws.dc, x.ws.a1, p.tx, x.n_jobs, x.wstride, s, 0, nullptr, true, AngW{}, ppart);
 }
 hipError_t launch_inv_y(const pb3_plan& p, const Exec& x, hipStream_t s) {
   return run_inv_y(p, false, x.ws.a1, x.ws.a2, p.ty, x.n_jobs, x.wstride, s);

@@ -116,7 +116,7 @@ static void free_device(pb3_plan* p) {
                   d.out_map,   d.inv_counts, d.pk_scale,  d.tw_n[0],     d.tw_n[1],   d.tw_n[2],   d.tw_m[0],
                   d.tw_m[1],   d.tw_m[2],    d.tw_m_d[0], d.tw_m_d[1],   d.tw_m_d[2], d.nmodes_d,  d.pml_inv,
                   d.ml_trips,  d.ml_fac,     d.ml_map,    d.win_inv,     d.pfid_inv,  d.pfid_inv_d, d.mode_w,
-                  d.bk_bias,   d.bk_mix,     d.out_map_ab};
+                  d.bk_bias,   d.bk_mix,     d.out_map_ab, d.xtile_first};
   for (void* q : ptrs)
     if (q) hipFree(q);
   d = DeviceTables{};
@@ -436,6 +436,20 @@ static pb3_status build_host(pb3_plan* p, const int grid[3], const double box[3]
 // floats per partial vector of the longer of the two contraction layouts
 static size_t part_max(const pb3_plan& p) { return (size_t)std::max(p.part_len, p.part_len_ab); }
 
+int n_x_tiles(const pb3_plan& p) {
+  const int tb = tile_width_x(p.Mx, false);
+  if (tb <= 0) return 0;
+  int n = 0;
+  for (int b = 0; b < p.nb && b < (int)p.geom.size(); ++b) n += (p.geom[b].ly * p.geom[b].kzn + tb - 1) / tb;
+  return n;
+}
+// power partials: one per chunk of the mode lists, or one per inverse-x tile
+static size_t ppart_len(const pb3_plan& p) { return (size_t)std::max({p.n_chunks, n_x_tiles(p), 1}); }
+
+bool power_folded(const pb3_plan& p, bool do_pk, bool do_bk) {
+  return do_pk && do_bk && !p.trip.empty() && !p.d.mode_w && !p.d.win_inv && !p.d.pfid_inv;
+}
+
 size_t workspace_bytes(const pb3_plan* p) {
   size_t b = 0;
   const size_t A = 256;
@@ -447,7 +461,7 @@ size_t workspace_bytes(const pb3_plan* p) {
   const bool has_g = !p->fused && !(p->flags & PB3_FLAG_POWER_ONLY);
   b += has_g ? align_up(sizeof(float) * (size_t)p->nb * mpix(*p), A) : 0;
   b += align_up(sizeof(float) * (size_t)p->contract_wgs * part_max(*p), A);
-  b += align_up(sizeof(double) * (size_t)std::max(p->n_chunks, 1), A);
+  b += align_up(sizeof(double) * ppart_len(*p), A);
   b += align_up(sizeof(double) * (size_t)kReduceSlices * part_max(*p), A);
   return b;
 }
@@ -472,7 +486,7 @@ Workspace carve(const pb3_plan* p, void* base, size_t bytes) {
   const bool has_g = !p->fused && !(p->flags & PB3_FLAG_POWER_ONLY);
   w.g = has_g ? (float*)take(sizeof(float) * (size_t)p->nb * mpix(*p)) : nullptr;
   w.part = (float*)take(sizeof(float) * (size_t)p->contract_wgs * part_max(*p));
-  w.ppart = (double*)take(sizeof(double) * (size_t)std::max(p->n_chunks, 1));
+  w.ppart = (double*)take(sizeof(double) * ppart_len(*p));
   w.rsl = (double*)take(sizeof(double) * (size_t)kReduceSlices * part_max(*p));
   return w;
 }
@@ -680,6 +694,13 @@ static pb3_status build_device(pb3_plan* p) {
   all.insert(all.end(), vz.begin(), vz.end());
   if ((st = upload(&d.tiles, all.data(), all.size())) != PB3_OK) return st;
   p->tx = TileSet{d.tiles, (int)vx.size(), tbx};
+  {
+    // the inverse-x tiles are in bin order: per bin, the index of its first
+    std::vector<int32_t> xf(p->nb + 1, (int32_t)vx.size());
+    for (int t = (int)vx.size() - 1; t >= 0; --t) xf[vx[t].bin] = t;
+    for (int b = p->nb - 1; b >= 0; --b) xf[b] = std::min(xf[b], xf[b + 1]);
+    if ((st = upload(&d.xtile_first, xf.data(), xf.size())) != PB3_OK) return st;
+  }
   p->ty = TileSet{d.tiles + vx.size(), (int)vy.size(), tbx};
   p->tz = TileSet{d.tiles + vx.size() + vy.size(), (int)vz.size(), tbz};
   // power normalisation V / (N_pix^2 N_b)
@@ -809,16 +830,20 @@ template <typename W>
 static pb3_status enqueue_w(const pb3_plan& p, const Exec& x, bool do_pk, bool do_bk, pb3_precision prec,
                             hipStream_t s, W&& wrap) {
   pb3_status st;
-  // with both spectra, the power spectrum's per-bin sums run in the reduction's launch
+  // with both spectra, the power spectrum's per-bin sums run in the reduction's launch; for
+  // unweighted plans the inverse x pass takes the sums over the modes it gathers anyway
   const bool merge = do_pk && do_bk && !p.trip.empty();
+  const bool fold = power_folded(p, do_pk, do_bk);
   if ((st = wrap(ST_FWD_Z, "fwd_z", [&] { return launch_fwd_z(p, x, s); })) != PB3_OK) return st;
   if ((st = wrap(ST_FWD_Y, "fwd_y", [&] { return launch_fwd_y(p, x, s); })) != PB3_OK) return st;
   if ((st = wrap(ST_FWD_X, "fwd_x", [&] { return launch_fwd_x(p, x, s); })) != PB3_OK) return st;
-  if (do_pk) {
+  if (do_pk && !fold) {
     if ((st = wrap(ST_POWER, "power", [&] { return launch_power(p, x, s, !merge); })) != PB3_OK) return st;
   }
   if (do_bk) {
-    if ((st = wrap(ST_INV_X, "inv_x", [&] { return launch_inv_x(p, x, s); })) != PB3_OK) return st;
+    if ((st = wrap(ST_INV_X, "inv_x", [&] { return launch_inv_x(p, x, s, fold ? x.ws.ppart : nullptr); })) !=
+        PB3_OK)
+      return st;
     if ((st = wrap(ST_INV_Y, "inv_y", [&] { return launch_inv_y(p, x, s); })) != PB3_OK) return st;
     if (p.fused) {
       if ((st = wrap(ST_CONTRACT, "contract",
@@ -828,7 +853,7 @@ static pb3_status enqueue_w(const pb3_plan& p, const Exec& x, bool do_pk, bool d
       if ((st = wrap(ST_INV_Z, "inv_z", [&] { return launch_inv_z(p, x, s); })) != PB3_OK) return st;
       if ((st = wrap(ST_CONTRACT, "contract", [&] { return launch_contract(p, x, prec, s); })) != PB3_OK) return st;
     }
-    if ((st = wrap(ST_REDUCE, "reduce", [&] { return launch_reduce(p, x, s, merge); })) != PB3_OK) return st;
+    if ((st = wrap(ST_REDUCE, "reduce", [&] { return launch_reduce(p, x, s, merge, fold); })) != PB3_OK) return st;
   }
   return PB3_OK;
 }
@@ -843,7 +868,7 @@ pb3_status enqueue(const pb3_plan& p, const Exec& x, bool do_pk, bool do_bk, pb3
 // kernel launches of one enqueue (for reporting)
 int launches_per_sequence(const pb3_plan& p, bool do_pk, bool do_bk) {
   int n = 3;
-  if (do_pk) n += (do_bk && !p.trip.empty()) ? 1 : 2;
+  if (do_pk && !power_folded(p, do_pk, do_bk)) n += (do_bk && !p.trip.empty()) ? 1 : 2;
   if (do_bk) {
     n += 2 + 2;
     if (p.fused) n += 1;

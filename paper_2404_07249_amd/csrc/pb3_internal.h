@@ -70,6 +70,7 @@ struct DeviceTables {
   int32_t* modes = nullptr;       // compact D index of every binned half-spectrum mode (bit 31: weight 1)
   int32_t* chunk = nullptr;       // power chunks: (bin, start, end) triples
   int32_t* chunk_first = nullptr; // per bin: index of its first chunk (n_bins + 1 entries)
+  int32_t* xtile_first = nullptr; // per bin: index of its first inverse-x tile (n_bins + 1 entries)
   BinGeom* geom = nullptr;        // per bin
   BinTile* tiles = nullptr;       // all FP32 inverse-pass tiles (x, then y, then z)
   int32_t* trip_all = nullptr;    // candidate triplets (3 ints each), simple contraction
@@ -106,7 +107,7 @@ struct Workspace {
   float* g = nullptr;       // [nb][Mx My Mz] (separate z pass only)
   float* part = nullptr;    // contraction partials [work-group][tile*256]
   double* rsl = nullptr;    // reduction slices [kReduceSlices][tile*256]
-  double* ppart = nullptr;  // power partials
+  double* ppart = nullptr;  // power partials (per chunk of a bin's mode list, or per inverse-x tile)
 };
 
 // Execution context of one launch sequence: job 0's workspace, the stride
@@ -209,12 +210,17 @@ hipError_t launch_fwd_y(const pb3_plan& p, const Exec& x, hipStream_t s);
 hipError_t launch_fwd_x(const pb3_plan& p, const Exec& x, hipStream_t s);
 // final = false leaves the per-bin sums to launch_reduce(..., with_pk = true).
 hipError_t launch_power(const pb3_plan& p, const Exec& x, hipStream_t s, bool final);
-hipError_t launch_inv_x(const pb3_plan& p, const Exec& x, hipStream_t s);
+hipError_t launch_inv_x(const pb3_plan& p, const Exec& x, hipStream_t s, double* ppart = nullptr);
 hipError_t launch_inv_y(const pb3_plan& p, const Exec& x, hipStream_t s);
 hipError_t launch_inv_z(const pb3_plan& p, const Exec& x, hipStream_t s);
 hipError_t launch_contract(const pb3_plan& p, const Exec& x, pb3_precision prec, hipStream_t s);
 // with_pk: also the power spectrum's per-bin sums (after launch_power(..., false)).
-hipError_t launch_reduce(const pb3_plan& p, const Exec& x, hipStream_t s, bool with_pk);
+hipError_t launch_reduce(const pb3_plan& p, const Exec& x, hipStream_t s, bool with_pk, bool pk_folded);
+// With both spectra of an unweighted plan, the power spectrum's per-bin
+// sums are taken by the inverse x pass (one FP64 partial per tile) and
+// finished in the reduction's launch.
+bool power_folded(const pb3_plan& p, bool do_pk, bool do_bk);
+int n_x_tiles(const pb3_plan& p);
 // window moments and P / <w^2>, B / <w^3> (scratch: 2 + 2 kWindowBlocks doubles;
 // scratch[0..1] receive <w^2>, <w^3>)
 hipError_t launch_window(long n, const float* w, double* pk, int nb, double* bk, int nt, double* scratch,
@@ -260,7 +266,8 @@ hipError_t launch_zcontract(const pb3_plan& p, const Exec& x, bool mixed, hipStr
 // unit = the shell indicator instead of Theta_b D (count pass, FP64 only);
 // n_jobs jobs whose buffers are wstride bytes apart
 // weighted: apply the plan's window / P_fid weights (estimator fields);
-// unit_w: per-|n|^2 weight of the unit fields (count pass, may be null)
+// unit_w: per-|n|^2 weight of the unit fields (count pass, may be null);
+// ppart: FP32 unweighted spectra only, one FP64 power partial per tile (may be null)
 // (the FP32 or FP64 twiddles of the axis are the plan's)
 // Angular weight of the FP64 unit fields: L_l1(mu) L_l2(mu) u_x^ex u_y^ey u_z^ez
 // with u = k / |k| and mu = u_z (all zero: no angular weight).  A mode with
@@ -272,7 +279,7 @@ struct AngW {
 };
 hipError_t run_inv_x(const pb3_plan& p, bool dbl, bool unit, const float2* dc, void* a1, const TileSet& ts,
                      int n_jobs, size_t wstride, hipStream_t s, int ell = 0, const double* unit_w = nullptr,
-                     bool weighted = false, AngW aw = AngW{});
+                     bool weighted = false, AngW aw = AngW{}, double* ppart = nullptr);
 hipError_t run_inv_y(const pb3_plan& p, bool dbl, const void* a1, void* a2, const TileSet& ts, int n_jobs,
                      size_t wstride, hipStream_t s);
 hipError_t run_inv_z(const pb3_plan& p, bool dbl, const void* a2, void* gout, const TileSet& ts, int n_jobs,

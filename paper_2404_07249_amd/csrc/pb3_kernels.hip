@@ -481,12 +481,13 @@ hipError_t launch_contract(const pb3_plan& p, const Exec& x, pb3_precision prec,
   return launch_contract_mfma(p, x, prec == PB3_MIXED_BF16X3, s);
 }
 
-hipError_t launch_reduce(const pb3_plan& p, const Exec& x, hipStream_t s, bool with_pk) {
+hipError_t launch_reduce(const pb3_plan& p, const Exec& x, hipStream_t s, bool with_pk, bool pk_folded) {
   int n_out = (int)(p.trip.size() / 3);
   if (n_out == 0) return hipSuccess;
   const int n_red = (n_out + 255) / 256;
   PowerFinal pf;
-  if (with_pk) pf = PowerFinal{x.ws.ppart, p.d.chunk_first, p.d.pk_scale, p.pk_shift, p.nb};
+  // the power partials are per chunk of a bin's mode list, or per inverse-x tile when that pass took them
+  if (with_pk) pf = PowerFinal{x.ws.ppart, pk_folded ? p.d.xtile_first : p.d.chunk_first, p.d.pk_scale, p.pk_shift, p.nb};
   hipLaunchKernelGGL(k_reduce_slices, dim3((p.part_len / 4 + 255) / 256, kReduceSlices, x.n_jobs), dim3(256), 0, s,
                      x.ws.part, p.contract_wgs, p.part_len, x.ws.rsl, x.wstride);
   hipError_t e = hipGetLastError();

@@ -70,9 +70,12 @@ def _alone(server, torch, r):
     import paper_2404_07249_amd as pb3
 
     solo = pb3.Plan(r.grid, r.box, r.edges)  # own workspace, same geometry
-    pk, bk = solo.polyspectra(r.data, r.precision)
     if r.sims:
+        # the server runs such requests' P as a power-only call and B with the linear term
+        pk = solo.power(r.data)
         bk = solo.bispectrum_linear(r.data, r.sims, r.precision)
+    else:
+        pk, bk = solo.polyspectra(r.data, r.precision)
     if r.window is not None:
         solo.window_normalize(r.window, pk, bk)
     torch.cuda.synchronize()
