@@ -54,6 +54,15 @@ typedef enum {
   PB3_EBUSY = 5          /* reserved */
 } pb3_status;
 
+/* Failure handling: every entry point returns a status and never aborts; a
+ * call that fails for want of memory frees what it allocated and leaves the
+ * plan or batch as it was (a plan creation that fails returns no plan).
+ * Test hook: with the environment variable PB3_FAIL_ALLOC_AT=n, the n-th
+ * device allocation of the library, counted from when that value was first
+ * seen, fails as out of memory, which the call reports as PB3_ENOMEM.  A
+ * changed value restarts the count; text after the number is ignored, so
+ * "3:a" and "3:b" both arm the third allocation. */
+
 typedef enum {
   PB3_FP32 = 0,          /* FP32 FFTs and FP32 MFMA contraction */
   PB3_MIXED_BF16X3 = 1   /* FP32 FFTs, contraction as split-BF16 (hi*hi + hi*lo + lo*hi) MFMA, FP32 accumulation */

@@ -10,6 +10,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("PB3_LIBRARY") or os.path.join(_HERE, "libpb3.so")
 
 PB3_OK = 0
+PB3_EINVAL, PB3_ENOMEM, PB3_EDEVICE, PB3_EUNSUPPORTED = 1, 2, 3, 4
 STATUS = {0: "PB3_OK", 1: "PB3_EINVAL", 2: "PB3_ENOMEM", 3: "PB3_EDEVICE", 4: "PB3_EUNSUPPORTED", 5: "PB3_EBUSY"}
 
 FLAG_EDGES_HMPC = 0x1

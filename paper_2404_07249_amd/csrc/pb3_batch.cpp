@@ -270,7 +270,7 @@ pb3_status pb3_batch_create(pb3_plan* const* plans, int n_jobs, unsigned flags, 
     st = hip_fail(e, "hipEventCreateWithFlags");
   if (st == PB3_OK && !(flags & PB3_BATCH_EXT_WORKSPACE)) {
     void* base = nullptr;
-    e = hipMalloc(&base, b->ws_bytes);
+    e = dev_malloc(&base, b->ws_bytes);
     if (e != hipSuccess) {
       set_error("batch workspace hipMalloc of " + std::to_string(b->ws_bytes) + " bytes: " + hipGetErrorString(e));
       st = PB3_ENOMEM;

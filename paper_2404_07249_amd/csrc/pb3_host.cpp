@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <new>
 #include <sstream>
 #include <string>
@@ -24,7 +25,28 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 
 pb3_status hip_fail(hipError_t e, const char* what) {
   set_error(std::string(what) + ": " + hipGetErrorString(e));
-  return PB3_EDEVICE;
+  return e == hipErrorOutOfMemory ? PB3_ENOMEM : PB3_EDEVICE;
+}
+
+hipError_t dev_malloc(void** ptr, size_t bytes) {
+  static std::mutex mu;
+  static std::string seen;
+  static long count = 0;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    const char* v = std::getenv("PB3_FAIL_ALLOC_AT");
+    const std::string cur = v ? v : "";
+    if (cur != seen) {
+      seen = cur;
+      count = 0;
+    }
+    const long at = cur.empty() ? 0 : std::atol(cur.c_str());
+    if (at > 0 && ++count == at) {
+      *ptr = nullptr;
+      return hipErrorOutOfMemory;
+    }
+  }
+  return hipMalloc(ptr, bytes);
 }
 
 static bool len_supported(int n) {
@@ -78,7 +100,7 @@ static std::vector<double> twiddles(int n) {
 }
 
 template <typename T> static pb3_status dalloc(T** ptr, size_t count) {
-  hipError_t e = hipMalloc((void**)ptr, sizeof(T) * (count ? count : 1));
+  hipError_t e = dev_malloc((void**)ptr, sizeof(T) * (count ? count : 1));
   if (e != hipSuccess) {
     *ptr = nullptr;
     set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
@@ -506,7 +528,7 @@ static pb3_status ensure_workspace(pb3_plan* p) {
   }
   size_t bytes = workspace_bytes(p);
   void* base = nullptr;
-  hipError_t e = hipMalloc(&base, bytes);
+  hipError_t e = dev_malloc(&base, bytes);
   if (e != hipSuccess) {
     set_error("workspace hipMalloc of " + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
     return PB3_ENOMEM;
@@ -595,8 +617,8 @@ static pb3_status autotune(pb3_plan* p, int n_cu) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   pb3_status st = PB3_OK;
   hipError_t e;
-  if ((e = hipMalloc(&ws, ws_max)) != hipSuccess || (e = hipMalloc(&fld, sizeof(float) * n3)) != hipSuccess ||
-      (e = hipMalloc(&bk, sizeof(double) * std::max(nt, 1))) != hipSuccess) {
+  if ((e = dev_malloc(&ws, ws_max)) != hipSuccess || (e = dev_malloc(&fld, sizeof(float) * n3)) != hipSuccess ||
+      (e = dev_malloc(&bk, sizeof(double) * std::max(nt, 1))) != hipSuccess) {
     st = PB3_ENOMEM;
     set_error("autotune allocation failed");
   }
@@ -1259,13 +1281,13 @@ pb3_status pb3_plan_set_weights(pb3_plan* plan, int window_order, const double* 
       const double x = M_PI * k / Ng[a];
       winv[off[a] + k] = std::pow(x / std::sin(x), window_order);
     }
-  p->pfid.assign(p->lut_len, 1.0);
+  std::vector<double> pf(p->lut_len, 1.0);
   if (pfid)
-    for (int j = 0; j < p->lut_len && j < n_pfid; ++j) p->pfid[j] = pfid[j] > 0.0 ? pfid[j] : 1.0;
+    for (int j = 0; j < p->lut_len && j < n_pfid; ++j) pf[j] = pfid[j] > 0.0 ? pfid[j] : 1.0;
   std::vector<float> winv_f(winv.begin(), winv.end()), pinv_f(p->lut_len);
   std::vector<double> pinv_d(p->lut_len);
   for (int j = 0; j < p->lut_len; ++j) {
-    pinv_d[j] = 1.0 / p->pfid[j];
+    pinv_d[j] = 1.0 / pf[j];
     pinv_f[j] = (float)pinv_d[j];
   }
   // power: per-mode weight 1 / (m^2 P_fid^2) and the weighted Fisher per bin
@@ -1280,7 +1302,7 @@ pb3_status pb3_plan_set_weights(pb3_plan* plan, int window_order, const double* 
       const int ky = cxy % p->Lcy - p->Kcy, kx = cxy / p->Lcy - p->Kcx;
       const int64_t n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
       const double wi = winv[off[0] + kx] * winv[off[1] + ky] * winv[off[2] + kz];
-      const double q = 1.0 / p->pfid[n2];
+      const double q = 1.0 / pf[n2];
       mw[i] = wi * wi * q * q;
       fish[b] += w * q * q;
       if (ne > 1) {
@@ -1293,27 +1315,7 @@ pb3_status pb3_plan_set_weights(pb3_plan* plan, int window_order, const double* 
   }
   std::vector<double> pks(nb);
   for (int b = 0; b < nb; ++b) pks[b] = V / (n3 * n3 * fish[b]);
-  pb3_status st;
-  DeviceTables& d = p->d;
-  if ((st = upload(&d.win_inv, winv_f.data(), winv_f.size())) != PB3_OK) return st;
-  if ((st = upload(&d.pfid_inv, pinv_f.data(), pinv_f.size())) != PB3_OK) return st;
-  if ((st = upload(&d.pfid_inv_d, pinv_d.data(), pinv_d.size())) != PB3_OK) return st;
-  if ((st = upload(&d.mode_w, mw.data(), mw.size())) != PB3_OK) return st;
-  hipError_t e = hipMemcpy(d.pk_scale, pks.data(), sizeof(double) * nb, hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
-  if (window_order == 0) {  // no window: keep the per-component table out of the kernels
-    hipFree(d.win_inv);
-    d.win_inv = nullptr;
-  }
-  if (!pfid) {
-    hipFree(d.pfid_inv);
-    d.pfid_inv = nullptr;
-    hipFree(d.pfid_inv_d);
-    d.pfid_inv_d = nullptr;
-  }
-  p->window_order = window_order;
-  p->nbar = nbar;
-  p->pk_shift = nbar > 0.0 ? 1.0 / nbar : 0.0;
+  std::vector<double> pml(p->pml_inv);
   if (ne > 1) {  // weighted discrete Fisher of the power multipoles
     const double sc = V / (n3 * n3);
     for (int b = 0; b < nb; ++b) {
@@ -1336,42 +1338,78 @@ pb3_status pb3_plan_set_weights(pb3_plan* plan, int window_order, const double* 
           }
       }
       for (int i = 0; i < ne; ++i)
-        for (int j = 0; j < ne; ++j) p->pml_inv[((size_t)b * ne + i) * ne + j] = sc * a[i][ne + j];
+        for (int j = 0; j < ne; ++j) pml[((size_t)b * ne + i) * ne + j] = sc * a[i][ne + j];
     }
-    e = hipMemcpy(d.pml_inv, p->pml_inv.data(), sizeof(double) * p->pml_inv.size(), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
   }
-  p->weighted = true;
-  if (p->flags & PB3_FLAG_POWER_ONLY || p->trip.empty()) return PB3_OK;
-  // bispectrum: weighted triangle sums N_0 = sum 1/(P1 P2 P3), the shot-noise sums
-  std::vector<double> n0, q;
-  if ((st = compute_counts_fp64(*p, n0, nbar > 0.0 ? &q : nullptr)) != PB3_OK) return st;
-  const double m3 = (double)p->Mx * p->My * p->Mz;
-  const double scale = V * V * (m3 * m3) / (n3 * n3 * n3);
-  std::vector<double> fac, bias, mf;
+  // Everything that can fail on allocation comes first, into new tables;
+  // the plan changes only once all of it has succeeded.
+  pb3_status st;
+  DeviceTables& d = p->d;
+  float *t_win = nullptr, *t_pinv = nullptr;
+  double *t_pinv_d = nullptr, *t_mw = nullptr, *t_bias = nullptr;
+  auto drop = [&](pb3_status r) {
+    for (void* q : {(void*)t_win, (void*)t_pinv, (void*)t_pinv_d, (void*)t_mw, (void*)t_bias})
+      if (q) hipFree(q);
+    return r;
+  };
+  if ((window_order != 0 && (st = upload(&t_win, winv_f.data(), winv_f.size())) != PB3_OK) ||
+      (pfid && (st = upload(&t_pinv, pinv_f.data(), pinv_f.size())) != PB3_OK) ||
+      (pfid && (st = upload(&t_pinv_d, pinv_d.data(), pinv_d.size())) != PB3_OK) ||
+      (st = upload(&t_mw, mw.data(), mw.size())) != PB3_OK)
+    return drop(st);
+  const bool with_bk = !(p->flags & PB3_FLAG_POWER_ONLY) && !p->trip.empty();
   const int nt = (int)(p->trip.size() / 3);
-  for (int t = 0, kept = 0; t < (int)(p->trip_all.size() / 3) && kept < nt; ++t) {
-    if (p->trip_all[3 * t] != p->trip[3 * kept] || p->trip_all[3 * t + 1] != p->trip[3 * kept + 1] ||
-        p->trip_all[3 * t + 2] != p->trip[3 * kept + 2])
-      continue;  // dropped (no closed triangle)
-    fac.push_back(scale / n0[t]);
-    bias.push_back(nbar > 0.0 ? q[t] / n0[t] / nbar - 2.0 / (nbar * nbar) : 0.0);
-    p->counts[kept] = n0[t];
-    ++kept;
+  std::vector<double> fac, bias, counts(p->counts);
+  if (with_bk) {
+    // bispectrum: weighted triangle sums N_0 = sum 1/(P1 P2 P3), the shot-noise sums
+    std::vector<double> n0, q;
+    d.pfid_inv_d = t_pinv_d;  // the count pass reads the weights from the plan's tables
+    st = compute_counts_fp64(*p, n0, nbar > 0.0 ? &q : nullptr);
+    d.pfid_inv_d = nullptr;
+    if (st != PB3_OK) return drop(st);
+    const double m3 = (double)p->Mx * p->My * p->Mz;
+    const double scale = V * V * (m3 * m3) / (n3 * n3 * n3);
+    for (int t = 0, kept = 0; t < (int)(p->trip_all.size() / 3) && kept < nt; ++t) {
+      if (p->trip_all[3 * t] != p->trip[3 * kept] || p->trip_all[3 * t + 1] != p->trip[3 * kept + 1] ||
+          p->trip_all[3 * t + 2] != p->trip[3 * kept + 2])
+        continue;  // dropped (no closed triangle)
+      fac.push_back(scale / n0[t]);
+      bias.push_back(nbar > 0.0 ? q[t] / n0[t] / nbar - 2.0 / (nbar * nbar) : 0.0);
+      counts[kept] = n0[t];
+      ++kept;
+    }
+    if ((int)fac.size() != nt) {
+      set_error("internal: weighted triangle sums do not match the triplet list");
+      return drop(PB3_EDEVICE);
+    }
+    if (nbar > 0.0 && (st = upload(&t_bias, bias.data(), bias.size())) != PB3_OK) return drop(st);
   }
-  if ((int)fac.size() != nt) {
-    set_error("internal: weighted triangle sums do not match the triplet list");
-    return PB3_EDEVICE;
+  // commit
+  hipError_t e = hipMemcpy(d.pk_scale, pks.data(), sizeof(double) * nb, hipMemcpyHostToDevice);
+  if (e == hipSuccess && ne > 1)
+    e = hipMemcpy(d.pml_inv, pml.data(), sizeof(double) * pml.size(), hipMemcpyHostToDevice);
+  std::vector<double> mf;
+  if (e == hipSuccess && with_bk) {
+    e = hipMemcpy(d.inv_counts, fac.data(), sizeof(double) * nt, hipMemcpyHostToDevice);
+    if (e == hipSuccess && p->lmax > 0) {
+      for (int l = 0; l < ne; ++l)
+        for (int t = 0; t < nt; ++t) mf.push_back((4 * l + 1) * fac[t]);
+      e = hipMemcpy(d.ml_fac, mf.data(), sizeof(double) * mf.size(), hipMemcpyHostToDevice);
+    }
   }
-  e = hipMemcpy(d.inv_counts, fac.data(), sizeof(double) * nt, hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
-  if (nbar > 0.0 && (st = upload(&d.bk_bias, bias.data(), bias.size())) != PB3_OK) return st;
-  if (p->lmax > 0) {
-    for (int l = 0; l < ne; ++l)
-      for (int t = 0; t < nt; ++t) mf.push_back((4 * l + 1) * fac[t]);
-    e = hipMemcpy(d.ml_fac, mf.data(), sizeof(double) * mf.size(), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
-  }
+  if (e != hipSuccess) return drop(hip_fail(e, "hipMemcpy"));
+  d.win_inv = t_win;
+  d.pfid_inv = t_pinv;
+  d.pfid_inv_d = t_pinv_d;
+  d.mode_w = t_mw;
+  if (t_bias) d.bk_bias = t_bias;
+  p->pfid = std::move(pf);
+  p->pml_inv = std::move(pml);
+  p->counts = std::move(counts);
+  p->window_order = window_order;
+  p->nbar = nbar;
+  p->pk_shift = nbar > 0.0 ? 1.0 / nbar : 0.0;
+  p->weighted = true;
   return PB3_OK;
 }
 

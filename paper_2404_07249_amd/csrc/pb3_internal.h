@@ -193,6 +193,12 @@ inline size_t ncompact(const pb3_plan& p) { return (size_t)p.Lcx * p.Lcy * p.Kz;
 
 void set_error(const std::string& msg);
 pb3_status hip_fail(hipError_t e, const char* what);
+// Every device allocation of the library goes through dev_malloc.  Test
+// hook: with PB3_FAIL_ALLOC_AT=n in the environment, the n-th allocation
+// counted from when that value was first seen fails with
+// hipErrorOutOfMemory (a changed value restarts the count; text after the
+// number is ignored).
+hipError_t dev_malloc(void** ptr, size_t bytes);
 
 // plan workspace (pb3_host.cpp): size and layout at base
 size_t workspace_bytes(const pb3_plan* p);

@@ -516,9 +516,14 @@ size_t masked_workspace_bytes(const pb3_plan& p) {
 static pb3_status masked_tables(pb3_plan& p) {
   if (p.d.nmodes_d) return PB3_OK;
   std::vector<double> nm(p.nmodes.begin(), p.nmodes.end());
-  hipError_t e = hipMalloc((void**)&p.d.nmodes_d, sizeof(double) * p.nb);
-  if (e == hipSuccess) e = hipMemcpy(p.d.nmodes_d, nm.data(), sizeof(double) * p.nb, hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(e, "masked power tables");
+  double* t = nullptr;
+  hipError_t e = dev_malloc((void**)&t, sizeof(double) * p.nb);
+  if (e == hipSuccess) e = hipMemcpy(t, nm.data(), sizeof(double) * p.nb, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (t) hipFree(t);
+    return hip_fail(e, "masked power tables");
+  }
+  p.d.nmodes_d = t;
   return PB3_OK;
 }
 
@@ -806,7 +811,7 @@ pb3_status compute_counts_fp64(pb3_plan& p, std::vector<double>& counts_out, std
   hipError_t e;
   pb3_status st = PB3_OK;
   auto alloc = [&](void** ptr, size_t bytes) {
-    e = hipMalloc(ptr, bytes);
+    e = dev_malloc(ptr, bytes);
     return e == hipSuccess;
   };
   std::vector<int32_t> idmap(n_cand);
@@ -1000,7 +1005,7 @@ pb3_status compute_bk_mixing(pb3_plan& p, std::vector<double>& mix_out) {
   const int ells[3] = {0, 2, 4};
   std::vector<double> d33((size_t)ne * ne * nt), x32((size_t)ne * ne * nt), c2(nt, 0.0), c4(nt, 0.0), tmp(nt);
   auto alloc = [&](void** ptr, size_t bytes) {
-    e = hipMalloc(ptr, bytes);
+    e = dev_malloc(ptr, bytes);
     return e == hipSuccess;
   };
   // three field sets: unit fields, and two weighted ones
