@@ -112,6 +112,11 @@ typedef enum {
  * data-independent, Sec. IV.D.1), on the default stream, synchronously.
  * The contraction grid is chosen per axis (the smallest implemented length
  * above 3 K_i, K_i the largest |n_i| of a binned mode, else N_i).
+ * With the environment variable PB3_PLAN_CACHE naming a directory, the
+ * counts (and, with PB3_FLAG_BK_FISHER, the multipole mixing blocks) are
+ * read from a file there keyed by device architecture, grids and bins, and
+ * written there after they are computed; a file whose key, length or
+ * checksum does not match is ignored and rewritten.
  * Errors: PB3_EINVAL (bad grid/box/edges, a bin with no modes, strict-mode
  * empty triplet, unequal box sides without h/Mpc edges), PB3_EUNSUPPORTED
  * (grid length, more than 2^31 - 1 cells or > 48 bins), PB3_ENOMEM,

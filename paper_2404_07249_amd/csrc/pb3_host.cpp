@@ -15,6 +15,8 @@
 #include <string>
 #include <vector>
 
+#include <unistd.h>
+
 #include "pb3_internal.h"
 
 namespace pb3 {
@@ -579,6 +581,75 @@ static bool tune_lookup(const std::string& path, const std::string& key, int& fu
   return found;
 }
 
+// ------------------------------------------------------------ plan cache
+// The data-independent artefacts of a plan, the triangle counts T of every
+// candidate triplet (eq. N-ell-def at l = 0) and, with PB3_FLAG_BK_FISHER,
+// the multipole mixing blocks, can be kept on disk: with PB3_PLAN_CACHE
+// naming a directory, plan creation reads them from a file keyed by the
+// device architecture, the grids, the bins (and the box when its sides
+// differ), and writes that file after computing them.  A file whose key,
+// length or checksum does not match is ignored and rewritten.  Weighted
+// sums (pb3_plan_set_weights) depend on the caller's P_fid and are not
+// cached.
+static uint64_t fnv1a(const void* data, size_t n, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* c = (const unsigned char*)data;
+  for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  return h;
+}
+
+static std::string cache_file(const char* dir, const std::string& key, const char* what) {
+  char name[64];
+  std::snprintf(name, sizeof name, "/pb3_%s_%016llx.bin", what, (unsigned long long)fnv1a(key.data(), key.size()));
+  return std::string(dir) + name;
+}
+
+static const char kCacheMagic[] = "PB3PLAN1";
+
+static bool cache_read(const std::string& key, const char* what, std::vector<double>& v, size_t n) {
+  const char* dir = std::getenv("PB3_PLAN_CACHE");
+  if (!dir || !*dir) return false;
+  std::ifstream f(cache_file(dir, key, what), std::ios::binary);
+  if (!f) return false;
+  std::string magic, k, w;
+  if (!std::getline(f, magic) || magic != kCacheMagic || !std::getline(f, k) || k != key || !std::getline(f, w) ||
+      w != what)
+    return false;
+  uint64_t len = 0, sum = 0;
+  if (!f.read((char*)&len, sizeof len) || len != n) return false;
+  std::vector<double> t(n);
+  if (n && !f.read((char*)t.data(), sizeof(double) * n)) return false;
+  if (!f.read((char*)&sum, sizeof sum)) return false;
+  uint64_t h = fnv1a(key.data(), key.size());
+  h = fnv1a(t.data(), sizeof(double) * n, h);
+  if (h != sum) return false;
+  v.swap(t);
+  return true;
+}
+
+static void cache_write(const std::string& key, const char* what, const std::vector<double>& v) {
+  const char* dir = std::getenv("PB3_PLAN_CACHE");
+  if (!dir || !*dir) return;
+  const std::string path = cache_file(dir, key, what);
+  const std::string tmp = path + ".tmp" + std::to_string((long)getpid());
+  {
+    std::ofstream f(tmp, std::ios::binary | std::ios::trunc);
+    if (!f) return;
+    const uint64_t len = v.size();
+    uint64_t h = fnv1a(key.data(), key.size());
+    h = fnv1a(v.data(), sizeof(double) * v.size(), h);
+    f << kCacheMagic << "\n" << key << "\n" << what << "\n";
+    f.write((const char*)&len, sizeof len);
+    f.write((const char*)v.data(), sizeof(double) * v.size());
+    f.write((const char*)&h, sizeof h);
+    if (!f) {
+      f.close();
+      std::remove(tmp.c_str());
+      return;
+    }
+  }
+  if (std::rename(tmp.c_str(), path.c_str()) != 0) std::remove(tmp.c_str());  // whole files only
+}
+
 static pb3_status autotune(pb3_plan* p, int n_cu) {
   const char* path = std::getenv("PB3_AUTOTUNE_CACHE");
   const std::string key = tune_key(p);
@@ -733,8 +804,12 @@ static pb3_status build_device(pb3_plan* p) {
   if ((st = upload(&d.pk_scale, pks.data(), pks.size())) != PB3_OK) return st;
   // triangle counts in FP64 on the contraction grid
   std::vector<double> raw;
-  if (!(p->flags & PB3_FLAG_POWER_ONLY) && (st = compute_counts_fp64(*p, raw)) != PB3_OK) return st;
   const int n_cand = (int)(p->trip_all.size() / 3);
+  const std::string ckey = tune_key(p);
+  if (!(p->flags & PB3_FLAG_POWER_ONLY) && !cache_read(ckey, "counts", raw, (size_t)n_cand)) {
+    if ((st = compute_counts_fp64(*p, raw)) != PB3_OK) return st;
+    cache_write(ckey, "counts", raw);
+  }
   p->trip.clear();
   p->counts.clear();
   std::vector<int32_t> map, map_ab;
@@ -793,7 +868,11 @@ static pb3_status build_device(pb3_plan* p) {
     if ((st = upload(&d.ml_fac, mf.data(), mf.size())) != PB3_OK) return st;
     if ((st = upload(&d.ml_map, mm.data(), mm.size())) != PB3_OK) return st;
     if (p->flags & PB3_FLAG_BK_FISHER) {
-      if ((st = compute_bk_mixing(*p, p->bk_mix)) != PB3_OK) return st;
+      const std::string mkey = ckey + " lmax" + std::to_string(p->lmax);
+      if (!cache_read(mkey, "mixing", p->bk_mix, (size_t)nt * ne * ne)) {
+        if ((st = compute_bk_mixing(*p, p->bk_mix)) != PB3_OK) return st;
+        cache_write(mkey, "mixing", p->bk_mix);
+      }
       if ((st = upload(&d.bk_mix, p->bk_mix.data(), p->bk_mix.size())) != PB3_OK) return st;
     }
   }
