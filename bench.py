@@ -247,14 +247,18 @@ def serving_bench(n_requests: int = 200, rate: float = 20.0, budget_gb: float = 
     def make_request(q, arrival):
         n = q["n"]
         with torch.cuda.stream(client):
+            # one allocation per request for its window, data and random fields (four sizes in all,
+            # which the caching allocator reuses without fragmenting)
+            buf = torch.empty((2 + n_mc, n, n, n), dtype=torch.float32, device="cuda")
+            w, data = buf[0], buf[1]
             gen.manual_seed(q["window_seed"])
-            holes = torch.rand((n, n, n), generator=gen, device="cuda") < 0.95
-            w = (spheres[n] & holes).to(torch.float32)
-            data = pool[n][q["field_seed"] % len(pool[n])] * w
+            torch.rand((n, n, n), generator=gen, device="cuda", out=data)
+            torch.logical_and(spheres[n], data < 0.95, out=w)
+            torch.mul(pool[n][q["field_seed"] % len(pool[n])], w, out=data)
             grfs = []
             for j in range(n_mc):
                 gen.manual_seed(30000 + 8 * max(q["rid"], 0) + j)
-                grfs.append(torch.randn((n, n, n), generator=gen, device="cuda"))
+                grfs.append(torch.randn((n, n, n), generator=gen, device="cuda", out=buf[2 + j]))
             ev = torch.cuda.Event()
             ev.record(client)
         return Request(rid=q["rid"], grid=n, box=box, edges=q["edges"], data=data, window=w,
@@ -285,6 +289,11 @@ def serving_bench(n_requests: int = 200, rate: float = 20.0, budget_gb: float = 
         if srv.poll() == 0:
             time.sleep(5e-5)
     out = srv.summary()
+    ms = torch.cuda.memory_stats()
+    # allocator retries free the cached blocks and synchronize the device (a stall for every stream in flight)
+    out["allocator"] = {"alloc_retries": int(ms.get("num_alloc_retries", 0)),
+                        "device_allocs": int(ms.get("num_device_alloc", 0)),
+                        "reserved_peak_gb": round(ms.get("reserved_bytes.all.peak", 0) / 2**30, 2)}
     slow = sorted((c for c in srv.done.values() if c.status == "ok"), key=lambda c: -c.latency)[:5]
     by_rid = {q["rid"]: q for q in sched}
     out["slowest"] = [dict(rid=c.rid, grid=by_rid[c.rid]["n"], bins=by_rid[c.rid]["n_bins"],

@@ -8,7 +8,12 @@ bispectrum on their own grid and binning.  The server
   the FP64 triangle counts are computed once and reused by every request
   with that geometry;
 * admits requests in arrival order while a slot is free and the HBM the
-  job needs (its workspace and outputs) fits the budget; queued requests
+  job needs (its workspace and outputs) fits the budget; that memory is a
+  range of one device allocation of the whole budget, taken first-fit and
+  given back when the batch retires, so serving makes no device
+  allocation per request (a caching allocator fed a stream of mixed sizes
+  fragments, and when it runs short it frees its cache, which waits for
+  all work in flight); queued requests
   with the same plan as the one being admitted join it in one batched
   launch sequence (up to 8 jobs share the launches);
 * runs every admitted batch on its own slot stream, so work of different
@@ -116,6 +121,50 @@ class _Running:
     admitted: float
     pool_key: tuple
     mc_events: list = field(default_factory=list)  # per request: (start, end) events of the MC call, or None
+    block: int = -1  # offset of the batch's range in the arena
+
+
+class _Arena:
+    """First-fit ranges of one device allocation (256-byte aligned)."""
+
+    ALIGN = 256
+
+    def __init__(self, torch, nbytes: int):
+        self.buf = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device="cuda")
+        self.free = [(0, self.buf.numel())]  # (offset, size), sorted, coalesced
+
+    @classmethod
+    def up(cls, n: int) -> int:
+        return (max(int(n), 1) + cls.ALIGN - 1) // cls.ALIGN * cls.ALIGN
+
+    def take(self, n: int):
+        n = self.up(n)
+        for i, (o, sz) in enumerate(self.free):
+            if sz >= n:
+                if sz == n:
+                    del self.free[i]
+                else:
+                    self.free[i] = (o + n, sz - n)
+                return o
+        return None
+
+    def give(self, off: int, n: int):
+        n = self.up(n)
+        self.free.append((off, n))
+        self.free.sort()
+        merged = []
+        for o, sz in self.free:
+            if merged and merged[-1][0] + merged[-1][1] == o:
+                merged[-1] = (merged[-1][0], merged[-1][1] + sz)
+            else:
+                merged.append((o, sz))
+        self.free = merged
+
+    def view(self, off: int, n: int, dtype=None, shape=None):
+        t = self.buf[off:off + int(n)]
+        if dtype is not None:
+            t = t.view(dtype)
+        return t if shape is None else t.view(shape)
 
 
 @dataclass
@@ -152,6 +201,7 @@ class Server:
         self.plans: dict = {}
         self.full_plans: dict = {}  # full-grid power-only plans for the Monte Carlo Fisher matrix
         self.pool: dict = {}  # (plan key, jobs) -> idle Batch objects (no workspace held)
+        self.arena: _Arena | None = None  # the budget, allocated at the first admission
         self.bytes_in_use = 0
         self.stats = _Stats()
 
@@ -176,18 +226,53 @@ class Server:
     def _plan_key(req: Request):
         return (int(req.grid), float(req.box), tuple(np.asarray(req.edges, dtype=np.float64).tolist()))
 
+    def _layout(self, plan: Plan, group: list):
+        """Ranges (offset, bytes) within a batch's block of everything the
+        batch holds while it runs: the jobs' workspaces, outputs and window
+        scratch, and one Monte Carlo and one linear-term workspace, which
+        the jobs use in turn on the slot stream.  Returns (ranges, bytes)."""
+        up = _Arena.up
+        lay, off = {}, 0
+
+        def take(key, n):
+            nonlocal off
+            lay[key] = (off, int(n))
+            off += up(n)
+
+        nb, nt = plan.n_bins, plan.n_triplets
+        take("ws", len(group) * int(plan.workspace_bytes))
+        mws = lws = 0
+        for j, r in enumerate(group):
+            take(("pk", j), 8 * nb)
+            take(("bk", j), 8 * nt)
+            if r.window is not None:
+                take(("sc", j), 8 * _lib.WINDOW_SCRATCH)
+            if r.grfs:
+                take(("pu", j), 8 * nb)
+                take(("F", j), 8 * nb * nb)
+                mws = max(mws, int(self.full_plan_for(r.grid, r.box, r.edges).masked_workspace_bytes))
+            if r.sims:
+                lws = max(lws, int(plan.linear_workspace_bytes(len(r.sims))))
+        if mws:
+            take("mws", mws)
+        if lws:
+            take("lws", lws)
+        return lay, off
+
     def job_bytes(self, plan: Plan, masked: bool, full: Plan | None = None) -> int:
-        """HBM one job holds while it runs: its workspace, outputs, the
-        window scratch and, with random fields, the Monte Carlo workspace."""
-        out = 8 * (plan.n_bins + plan.n_triplets)
-        scr = 8 * _lib.WINDOW_SCRATCH if masked else 0
-        mc = 0 if full is None else int(full.masked_workspace_bytes) + 8 * plan.n_bins * (plan.n_bins + 1) + 512
-        return int(plan.workspace_bytes) + out + scr + mc + 512
+        """HBM one job holds while it runs (its workspace, outputs, the
+        window scratch and, with a full-grid plan for random fields, the
+        Monte Carlo workspace and outputs), in 256-byte aligned ranges."""
+        up = _Arena.up
+        nb = plan.n_bins
+        n = up(plan.workspace_bytes) + up(8 * nb) + up(8 * plan.n_triplets)
+        n += up(8 * _lib.WINDOW_SCRATCH) if masked else 0
+        if full is not None:
+            n += up(8 * nb) + up(8 * nb * nb) + up(full.masked_workspace_bytes)
+        return n
 
     def _req_bytes(self, plan: Plan, r: Request) -> int:
-        full = self.full_plan_for(r.grid, r.box, r.edges) if r.grfs else None
-        lin = plan.linear_workspace_bytes(len(r.sims)) + 256 if r.sims else 0
-        return self.job_bytes(plan, r.window is not None, full) + lin
+        return self._layout(plan, [r])[1]
 
     # ----------------------------------------------------------- submit
     def submit(self, req: Request):
@@ -266,6 +351,8 @@ class Server:
                 continue
             if self.bytes_in_use + need_one > self.budget:
                 break  # wait for memory (arrival order is kept)
+            if self.arena is None:
+                self.arena = _Arena(torch, self.budget)
             # the head plus queued requests of the same plan and precision
             group = [head]
             used = need_one
@@ -275,16 +362,23 @@ class Server:
                     if len(group) >= _MAX_JOBS_PER_LAUNCH:
                         break
                     if self._plan_key(r) == key and r.precision == head.precision and bool(r.sims) == bool(head.sims):
-                        nb = self._req_bytes(plan, r)
-                        if self.bytes_in_use + used + nb > self.budget:
+                        more = self._layout(plan, group + [r])[1]
+                        if self.bytes_in_use + more > self.budget:
                             break
                         group.append(r)
-                        used += nb
+                        used = more
+            block = self.arena.take(used)
+            while block is None and len(group) > 1:  # free bytes enough, but not in one range
+                group.pop()
+                used = self._layout(plan, group)[1]
+                block = self.arena.take(used)
+            if block is None:
+                break  # wait until retiring batches give ranges back
             for r in group:
                 self.queue.remove(r)
-            self._launch(plan, group, used)
+            self._launch(plan, group, used, block)
 
-    def _launch(self, plan: Plan, group: list, nbytes: int):
+    def _launch(self, plan: Plan, group: list, nbytes: int, block: int):
         torch = self.torch
         slot = self.free_slots.pop(0)
         stream = self.streams[slot]
@@ -292,44 +386,54 @@ class Server:
         pkey = (self._plan_key(group[0]), len(group))
         idle = self.pool.get(pkey)
         batch = idle.pop() if idle else Batch([plan] * len(group), ext_workspace=True)
+        lay, total = self._layout(plan, group)
+        assert total == nbytes and batch.workspace_bytes <= lay["ws"][1]
+
+        def view(key, dtype=None, shape=None):
+            o, n = lay[key]
+            return self.arena.view(block + o, n, dtype, shape)
+
+        f64 = torch.float64
+        nb = plan.n_bins
         with torch.cuda.stream(stream):
             for r in group:
                 if r.ready is not None:
                     stream.wait_event(r.ready)
-            ws = torch.empty(max(batch.workspace_bytes, 1), dtype=torch.uint8, device="cuda")
+            ws = view("ws")
             batch.bind_workspace(ws)
-            pks = [torch.empty(plan.n_bins, dtype=torch.float64, device="cuda") for _ in group]
-            bks = [torch.empty(plan.n_triplets, dtype=torch.float64, device="cuda") for _ in group]
+            pks = [view(("pk", j), f64) for j in range(len(group))]
+            bks = [view(("bk", j), f64) for j in range(len(group))]
             with_sims = bool(group[0].sims)  # a group is all with or all without simulations
             batch.run([r.data for r in group], group[0].precision, pk_outs=pks, bk_outs=None if with_sims else bks,
                       bispectrum=not with_sims, stream=stream)
             scratch, unw, mc_ev = [], [], []
-            for r, pk, bk in zip(group, pks, bks):
+            for j, (r, pk, bk) in enumerate(zip(group, pks, bks)):
                 mc = None
                 if r.sims:
                     # B with the linear term (the batch computed P only)
-                    lws = torch.empty(plan.linear_workspace_bytes(len(r.sims)), dtype=torch.uint8, device="cuda")
-                    plan.bispectrum_linear(r.data, r.sims, r.precision, out=bk, workspace=lws, stream=stream)
+                    plan.bispectrum_linear(r.data, r.sims, r.precision, out=bk, workspace=view("lws"), stream=stream)
                 ev_mc = None
                 if r.grfs:
                     # before the window normalisation, which rescales pk in place
                     full = self.full_plan_for(r.grid, r.box, r.edges)
-                    mws = torch.empty(full.masked_workspace_bytes, dtype=torch.uint8, device="cuda")
                     ev_mc = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                     ev_mc[0].record(stream)
-                    mc = full.masked_power(r.data, r.window, r.grfs, workspace=mws, stream=stream)
+                    mc = full.masked_power(r.data, r.window, r.grfs, pk_out=view(("pu", j), f64),
+                                           fisher_out=view(("F", j), f64, (nb, nb)), workspace=view("mws"),
+                                           stream=stream)
                     ev_mc[1].record(stream)
                 unw.append(mc)
                 mc_ev.append(ev_mc)
                 if r.window is not None:
-                    sc = torch.empty(_lib.WINDOW_SCRATCH, dtype=torch.float64, device="cuda")
+                    sc = view(("sc", j), f64)
                     plan.window_normalize(r.window, pk, bk, scratch=sc, stream=stream)
                     scratch.append(sc)
                 else:
                     scratch.append(None)
             ev = torch.cuda.Event()
             ev.record(stream)
-        self.running.append(_Running(group, slot, batch, ws, pks, bks, scratch, unw, ev, nbytes, now, pkey, mc_ev))
+        self.running.append(_Running(group, slot, batch, ws, pks, bks, scratch, unw, ev, nbytes, now, pkey, mc_ev,
+                                     block))
         self.bytes_in_use += nbytes
         st = self.stats
         st.admitted += len(group)
@@ -355,6 +459,7 @@ class Server:
                 n += 1
             self.running.remove(run)
             self.free_slots.append(run.slot)
+            self.arena.give(run.block, run.nbytes)
             self.bytes_in_use -= run.nbytes
             self.pool.setdefault(run.pool_key, []).append(run.batch)
         return n
