@@ -11,7 +11,9 @@ and ``tests/test_oracle_pins.py``):
                            invariances, statistical recovery of the input P.
 * ``triangle_triplets``    pinned: the 196 (= 2 x 98) configurations printed
                            for 8 bins in the bispectrum validation set-up.
-* ``triangle_counts``      pinned: brute-force mode counting, integrality.
+* ``triangle_counts``      pinned: brute-force mode counting, integrality,
+                           and the continuum Bessel-integral N_0 (end of
+                           Sec. IV.D.1) within the shells' discreteness.
 * ``bispectrum``           pinned: brute-force k-triplet sums, plane-wave
                            closed form, invariances, Gaussian null and the
                            tree-level bispectrum of a quadratic field.
