@@ -46,10 +46,10 @@ MEASURED_TRAFFIC = {
     ("contract", "mixed"): {
         "kernel": "k_zcontract<2, true, 192, 66>",
         "contract_wgs": 1024,  # partial-vector writes scale with the accumulation-chunk count
-        "fetch_kib": 138396.2, "write_kib": 30720.0, "fetch_factor": 2.0, "write_factor": 1.0,
+        "fetch_kib": 138396.4, "write_kib": 30720.0, "fetch_factor": 2.0, "write_factor": 1.0,
         "sources": {
             "paper_2404_07249_amd/csrc/contract_mfma.hip":
-                "f856260e00766fa0483fccfd971444be3785b27b6f54b6fd072553c45a232daa",
+                "65998adccbf658cdc540bffb526d8d8dd14d1b1faeab7d4f30c89d9da1658518",
             "paper_2404_07249_amd/csrc/fft_dev.h":
                 "df3b6d76c6673e67d4b39f61aa79139393ef94214581251510d14c1ded1023f4",
             "paper_2404_07249_amd/csrc/job.h":
@@ -59,10 +59,10 @@ MEASURED_TRAFFIC = {
     ("contract", "fp32"): {
         "kernel": "k_zcontract<2, false, 192, 66>",
         "contract_wgs": 1024,
-        "fetch_kib": 139862.5, "write_kib": 30720.0, "fetch_factor": 2.0, "write_factor": 1.0,
+        "fetch_kib": 139862.6, "write_kib": 30720.0, "fetch_factor": 2.0, "write_factor": 1.0,
         "sources": {
             "paper_2404_07249_amd/csrc/contract_mfma.hip":
-                "f856260e00766fa0483fccfd971444be3785b27b6f54b6fd072553c45a232daa",
+                "65998adccbf658cdc540bffb526d8d8dd14d1b1faeab7d4f30c89d9da1658518",
             "paper_2404_07249_amd/csrc/fft_dev.h":
                 "df3b6d76c6673e67d4b39f61aa79139393ef94214581251510d14c1ded1023f4",
             "paper_2404_07249_amd/csrc/job.h":
