@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "fft_dev.h"
 #include "job.h"
@@ -61,8 +62,28 @@ typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2_t;
 //     one group, blocks s = 6..8 are not formed at all).  At two groups
 //     this is 18 pair blocks and 30 tiles instead of 34 and 43: fewer pair
 //     products to form and split on the VALU, fewer MFMAs.
-constexpr int kLayoutAB = 0, kLayoutDiag = 1;
+//   kLayoutDiag8, kLayoutDiag4: kLayoutDiag for plans whose last group
+//     holds at most 8 or 4 real bins (the rest are zero padding).  Its pairs
+//     are then at most r - 1 apart (r = 8 or 4), so only blocks s < r are
+//     formed for it, and its one-group triplets, whose closest pair is at
+//     most (r - 1) / 2 apart, need its own column block only for those s.
+//     At 17-20 bins this is 13 pair blocks and 21 tiles, at 21-24 bins 17
+//     and 27, instead of 18 and 30.
+constexpr int kLayoutAB = 0, kLayoutDiag = 1, kLayoutDiag8 = 2, kLayoutDiag4 = 3;
 constexpr int kDiagOwnMaxS = 5;  // largest pair separation a one-group triplet needs (16 / 3 rounded down)
+
+// Real bins the last group of a Diag layout may hold, and its pair blocks
+// (separations 0 .. n-1) and the separations that take its own column block.
+constexpr int diag_cap(int L) { return L == kLayoutDiag4 ? 4 : L == kLayoutDiag8 ? 8 : 16; }
+constexpr int diag_min(int a, int b) { return a < b ? a : b; }
+constexpr int diag_blocks(int L, int nq, int p) {
+  const int r = p == nq - 1 ? diag_cap(L) : 16;
+  return nq == 1 ? diag_min(kDiagOwnMaxS, (r - 1) / 2) + 1 : diag_min(9, r);
+}
+constexpr int diag_own_max(int L, int nq, int p) {
+  const int r = p == nq - 1 ? diag_cap(L) : 16;
+  return diag_min(kDiagOwnMaxS, (r - 1) / 2);
+}
 
 struct PairBlock {
   int p, q, s;
@@ -83,9 +104,10 @@ constexpr PairBlock pair_block(int L, int nq, int k) {
   } else {
     // group 0, then (nq == 3) the cross blocks of groups 0 and 1, then the
     // other groups
-    const int ns = nq == 1 ? kDiagOwnMaxS + 1 : 9;
     for (int p = 0; p < nq; ++p) {
-      if (k < ns) return PairBlock{p, p, k, k <= kDiagOwnMaxS ? all_cols(nq) : all_cols(nq) & ~(1u << p)};
+      const int ns = diag_blocks(L, nq, p);
+      if (k < ns)
+        return PairBlock{p, p, k, k <= diag_own_max(L, nq, p) ? all_cols(nq) : all_cols(nq) & ~(1u << p)};
       k -= ns;
       if (p == 0 && nq == 3) {
         if (k < 16) return PairBlock{0, 1, k, 1u << 2};
@@ -96,8 +118,10 @@ constexpr PairBlock pair_block(int L, int nq, int k) {
   return PairBlock{-1, -1, -1, 0u};
 }
 constexpr int n_pair_blocks(int L, int nq) {
-  return L == kLayoutAB ? nq * 9 + (nq * (nq - 1) / 2) * 16
-                        : (nq == 1 ? kDiagOwnMaxS + 1 : nq * 9 + (nq == 3 ? 16 : 0));
+  if (L == kLayoutAB) return nq * 9 + (nq * (nq - 1) / 2) * 16;
+  int n = nq == 3 ? 16 : 0;
+  for (int p = 0; p < nq; ++p) n += diag_blocks(L, nq, p);
+  return n;
 }
 constexpr int popc(unsigned m) { return m ? (int)(m & 1u) + popc(m >> 1) : 0; }
 // tiles (pair block x column block) in pair blocks [0, k)
@@ -120,8 +144,8 @@ constexpr int group_begin(int L, int nq, int g) {
     // tiles per block: 3, 2, 1, 2, 1, 1 -> groups of 43, 32, 43 tiles
     return g == 0 ? 0 : g == 1 ? 9 + 8 : g == 2 ? 9 + 16 + 16 : n_pair_blocks(L, nq);
   }
-  // (0,0) 6 x 3 + 3 x 2, (0,1) 16 x 1: 40 tiles, then (1,1) and (2,2): 48 tiles
-  return g == 0 ? 0 : g == 1 ? 25 : n_pair_blocks(L, nq);
+  // (0,0) 6 x 3 + 3 x 2, (0,1) 16 x 1: 40 tiles, then (1,1) and (2,2): at most 48 tiles
+  return g == 0 ? 0 : g == 1 ? diag_blocks(L, nq, 0) + 16 : n_pair_blocks(L, nq);
 }
 
 __device__ __forceinline__ float ror16(float x, int s) {
@@ -726,7 +750,7 @@ __device__ __forceinline__ void produce_line(LineStage<NQ, M>& st, PairSrc<M>& p
 }
 
 // KB: every bin keeps fewer than KB z planes (0: no bound; see PlaneKinds).
-template <int NQ, bool MIXED, int M, int KB>
+template <int NQ, int L, bool MIXED, int M, int KB>
 __global__ void __launch_bounds__(fused_threads(MIXED)) k_zcontract(const float2* __restrict__ a2,
                                                              const BinGeom* __restrict__ geom, int nb,
                                                              const float2* __restrict__ tw, float scale, long lpw,
@@ -735,7 +759,6 @@ __global__ void __launch_bounds__(fused_threads(MIXED)) k_zcontract(const float2
                                                              int n_chunks) {
   a2 = job_ptr(a2, wstride);
   part = job_ptr(part, wstride);
-  constexpr int L = kLayoutDiag;
   constexpr int K0 = 0, K1 = n_pair_blocks(L, NQ);
   constexpr int NT = n_tiles(L, NQ);
   constexpr int NTMAX = max_group_tiles<NQ, L, K0, K1>();
@@ -843,7 +866,7 @@ __global__ void __launch_bounds__(fused_threads(MIXED)) k_zcontract(const float2
   }
 }
 
-template <int NQ, bool MIXED, int M>
+template <int NQ, int L, bool MIXED, int M>
 static hipError_t launch_fused_m(const pb3_plan& p, const Exec& x, hipStream_t s) {
   const long nlines = (long)p.Mx * p.My;  // z lines of length M = Mz
   const long lpw = (nlines + p.contract_wgs - 1) / p.contract_wgs;
@@ -859,26 +882,31 @@ static hipError_t launch_fused_m(const pb3_plan& p, const Exec& x, hipStream_t s
   // every bin keeps at most Kz planes; on an alias-free grid Kz <= M / 3 + 1
   constexpr int KB = M / 3 + 2;
   if (p.Kz < KB)
-    hipLaunchKernelGGL((k_zcontract<NQ, MIXED, M, KB>), dim3(n_wg, 1, x.n_jobs), dim3(fused_threads(MIXED)), 0, s,
+    hipLaunchKernelGGL((k_zcontract<NQ, L, MIXED, M, KB>), dim3(n_wg, 1, x.n_jobs), dim3(fused_threads(MIXED)), 0, s,
                        x.ws.a2, p.d.geom, p.nb, p.d.tw_m[2], scale, lpw, x.ws.part, p.part_len, sel_lo, sel_hi,
                        x.wstride, nlines, cpw, p.contract_wgs);
   else
-    hipLaunchKernelGGL((k_zcontract<NQ, MIXED, M, 0>), dim3(n_wg, 1, x.n_jobs), dim3(fused_threads(MIXED)), 0, s,
+    hipLaunchKernelGGL((k_zcontract<NQ, L, MIXED, M, 0>), dim3(n_wg, 1, x.n_jobs), dim3(fused_threads(MIXED)), 0, s,
                        x.ws.a2, p.d.geom, p.nb, p.d.tw_m[2], scale, lpw, x.ws.part, p.part_len, sel_lo, sel_hi,
                        x.wstride, nlines, cpw, p.contract_wgs);
   return hipGetLastError();
 }
 
-template <int NQ, bool MIXED>
+template <int NQ, int L, bool MIXED>
 static hipError_t launch_fused_nq(const pb3_plan& p, const Exec& x, hipStream_t s) {
   switch (p.Mz) {
-    case 32: return launch_fused_m<NQ, MIXED, 32>(p, x, s);
-    case 64: return launch_fused_m<NQ, MIXED, 64>(p, x, s);
-    case 96: return launch_fused_m<NQ, MIXED, 96>(p, x, s);
-    case 128: return launch_fused_m<NQ, MIXED, 128>(p, x, s);
-    case 192: return launch_fused_m<NQ, MIXED, 192>(p, x, s);
+    case 32: return launch_fused_m<NQ, L, MIXED, 32>(p, x, s);
+    case 64: return launch_fused_m<NQ, L, MIXED, 64>(p, x, s);
+    case 96: return launch_fused_m<NQ, L, MIXED, 96>(p, x, s);
+    case 128: return launch_fused_m<NQ, L, MIXED, 128>(p, x, s);
+    case 192: return launch_fused_m<NQ, L, MIXED, 192>(p, x, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <int NQ, int L>
+static hipError_t launch_fused_l(const pb3_plan& p, const Exec& x, bool mixed, hipStream_t s) {
+  return mixed ? launch_fused_nq<NQ, L, true>(p, x, s) : launch_fused_nq<NQ, L, false>(p, x, s);
 }
 
 // Accumulation chunks (partial vectors) of the fused kernel: enough that
@@ -893,13 +921,15 @@ int fused_grid(int nq, int m, long mvox, int n_cu) {
   hipError_t e = hipErrorInvalidValue;
   const void* fn = nullptr;
   if (nq == 1) {
-    fn = m == 32 ? (const void*)k_zcontract<1, true, 32, 0> : m == 64 ? (const void*)k_zcontract<1, true, 64, 0>
-       : m == 96 ? (const void*)k_zcontract<1, true, 96, 0> : m == 128 ? (const void*)k_zcontract<1, true, 128, 0>
-                 : (const void*)k_zcontract<1, true, 192, 0>;
+    constexpr int L = kLayoutDiag;
+    fn = m == 32 ? (const void*)k_zcontract<1, L, true, 32, 0> : m == 64 ? (const void*)k_zcontract<1, L, true, 64, 0>
+       : m == 96 ? (const void*)k_zcontract<1, L, true, 96, 0> : m == 128 ? (const void*)k_zcontract<1, L, true, 128, 0>
+                 : (const void*)k_zcontract<1, L, true, 192, 0>;
   } else {
-    fn = m == 32 ? (const void*)k_zcontract<2, true, 32, 0> : m == 64 ? (const void*)k_zcontract<2, true, 64, 0>
-       : m == 96 ? (const void*)k_zcontract<2, true, 96, 0> : m == 128 ? (const void*)k_zcontract<2, true, 128, 0>
-                 : (const void*)k_zcontract<2, true, 192, 0>;
+    constexpr int L = kLayoutDiag;
+    fn = m == 32 ? (const void*)k_zcontract<2, L, true, 32, 0> : m == 64 ? (const void*)k_zcontract<2, L, true, 64, 0>
+       : m == 96 ? (const void*)k_zcontract<2, L, true, 96, 0> : m == 128 ? (const void*)k_zcontract<2, L, true, 128, 0>
+                 : (const void*)k_zcontract<2, L, true, 192, 0>;
   }
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, fused_threads(true), 0);
   if (e != hipSuccess || per < 1) per = 1;
@@ -914,15 +944,29 @@ bool fused_supported(int nq, int m) {
   return nq >= 1 && nq <= 2 && (m == 32 || m == 64 || m == 96 || m == 128 || m == 192);
 }
 
+// The bispectrum's tile layout for nb bins: trimmed when the last 16-bin
+// group holds at most 8 or 4 real bins.
+static int diag_layout(int nb) {
+  const int nq = (nb + 15) / 16, r = nb - 16 * (nq - 1);
+  return r <= 4 ? kLayoutDiag4 : r <= 8 ? kLayoutDiag8 : kLayoutDiag;
+}
+
 hipError_t launch_zcontract(const pb3_plan& p, const Exec& x, bool mixed, hipStream_t s) {
-  const int nq = p.nb_pad / 16;
-  if (nq == 1) return mixed ? launch_fused_nq<1, true>(p, x, s) : launch_fused_nq<1, false>(p, x, s);
-  if (nq == 2) return mixed ? launch_fused_nq<2, true>(p, x, s) : launch_fused_nq<2, false>(p, x, s);
+  const int nq = p.nb_pad / 16, l = diag_layout(p.nb);
+  if (nq == 1)
+    return l == kLayoutDiag4   ? launch_fused_l<1, kLayoutDiag4>(p, x, mixed, s)
+           : l == kLayoutDiag8 ? launch_fused_l<1, kLayoutDiag8>(p, x, mixed, s)
+                               : launch_fused_l<1, kLayoutDiag>(p, x, mixed, s);
+  if (nq == 2)
+    return l == kLayoutDiag4   ? launch_fused_l<2, kLayoutDiag4>(p, x, mixed, s)
+           : l == kLayoutDiag8 ? launch_fused_l<2, kLayoutDiag8>(p, x, mixed, s)
+                               : launch_fused_l<2, kLayoutDiag>(p, x, mixed, s);
   return hipErrorInvalidValue;
 }
 
-int mfma_tiles(bool ab, int nq) {
-  const int L = ab ? kLayoutAB : kLayoutDiag;
+int mfma_tiles(bool ab, int nb) {
+  const int nq = (nb + 15) / 16;
+  const int L = ab ? kLayoutAB : diag_layout(nb);
   return nq >= 1 && nq <= 3 ? n_tiles(L, nq) : -1;
 }
 
@@ -932,8 +976,9 @@ int mfma_tiles(bool ab, int nq) {
 // pair of the smallest separation against the third bin; else at (pair
 // (a, b), column c) when a and b share a group, at (pair (b, c), column a)
 // when b and c do, and (three groups) at the cross pair (a, b) against c.
-int mfma_locate(bool ab, int nq, int a, int b, int c) {
-  const int L = ab ? kLayoutAB : kLayoutDiag;
+int mfma_locate(bool ab, int nb, int a, int b, int c) {
+  const int nq = (nb + 15) / 16;
+  const int L = ab ? kLayoutAB : diag_layout(nb);
   int x = a, y = b, z = c;
   auto sep = [](int u, int v) {  // cyclic separation of two positions in a 16-bin group
     const int d = ((u - v) % 16 + 16) % 16;
@@ -1038,17 +1083,22 @@ hipError_t launch_contract_cols(const pb3_plan& p, const Exec& x, const float* g
       default: return hipErrorInvalidValue;
     }
   }
-  constexpr int L = kLayoutDiag;
-  const int pl = p.part_len;
-  switch (nq) {
-    case 1: return mixed ? launch_nq<1, L, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s)
-                         : launch_nq<1, L, false>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s);
-    case 2: return mixed ? launch_nq<2, L, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s)
-                         : launch_nq<2, L, false>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s);
-    case 3: return mixed ? launch_nq<3, L, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s)
-                         : launch_nq<3, L, false>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s);
-    default: return hipErrorInvalidValue;
-  }
+  const int pl = p.part_len, l = diag_layout(p.nb);
+  auto run = [&](auto lc) -> hipError_t {
+    constexpr int L = decltype(lc)::value;
+    switch (nq) {
+      case 1: return mixed ? launch_nq<1, L, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s)
+                           : launch_nq<1, L, false>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s);
+      case 2: return mixed ? launch_nq<2, L, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s)
+                           : launch_nq<2, L, false>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s);
+      case 3: return mixed ? launch_nq<3, L, true>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s)
+                           : launch_nq<3, L, false>(g, mvox, n_wg, vpw, part, pl, nj, ws, p.nb, gc, s);
+      default: return hipErrorInvalidValue;
+    }
+  };
+  if (l == kLayoutDiag4) return run(std::integral_constant<int, kLayoutDiag4>{});
+  if (l == kLayoutDiag8) return run(std::integral_constant<int, kLayoutDiag8>{});
+  return run(std::integral_constant<int, kLayoutDiag>{});
 }
 
 }  // namespace pb3

@@ -452,8 +452,8 @@ static pb3_status build_host(pb3_plan* p, const int grid[3], const double box[3]
   p->fused_ok = !(flags & PB3_FLAG_POWER_ONLY) && fused_supported(p->nb_pad / 16, p->Mz);
   p->fused = !(flags & PB3_FLAG_NO_FUSION) && p->fused_ok;
   p->contract_wgs = 512;
-  p->part_len = (flags & PB3_FLAG_POWER_ONLY) ? 0 : mfma_tiles(false, p->nb_pad / 16) * 256;
-  p->part_len_ab = (flags & PB3_FLAG_POWER_ONLY) || p->lmax == 0 ? 0 : mfma_tiles(true, p->nb_pad / 16) * 256;
+  p->part_len = (flags & PB3_FLAG_POWER_ONLY) ? 0 : mfma_tiles(false, p->nb) * 256;
+  p->part_len_ab = (flags & PB3_FLAG_POWER_ONLY) || p->lmax == 0 ? 0 : mfma_tiles(true, p->nb) * 256;
   return PB3_OK;
 }
 
@@ -832,14 +832,14 @@ static pb3_status build_device(pb3_plan* p) {
     for (int k = 0; k < 3; ++k) p->trip.push_back(p->trip_all[3 * t + k]);
     p->counts.push_back(T);
     const int a = p->trip_all[3 * t], b = p->trip_all[3 * t + 1], c = p->trip_all[3 * t + 2];
-    int loc = mfma_locate(false, p->nb_pad / 16, a, b, c);
+    int loc = mfma_locate(false, p->nb, a, b, c);
     if (loc < 0 || loc >= p->part_len) {
       set_error("internal: triplet not covered by the contraction tiles");
       return PB3_EDEVICE;
     }
     map.push_back(loc);
     if (p->part_len_ab > 0) {
-      loc = mfma_locate(true, p->nb_pad / 16, a, b, c);
+      loc = mfma_locate(true, p->nb, a, b, c);
       if (loc < 0 || loc >= p->part_len_ab) {
         set_error("internal: triplet not covered by the column-field contraction tiles");
         return PB3_EDEVICE;

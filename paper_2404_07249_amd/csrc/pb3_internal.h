@@ -254,8 +254,8 @@ pb3_status run_bispectrum_linear(pb3_plan& p, const float* data, const float* co
 // partial-vector index of triplet (a, b, c) (-1 if not produced), launch
 // ab = true: every pair a <= b against columns c (separate column fields);
 // ab = false: the bispectrum's layout (pairs inside a 16-bin group)
-int mfma_tiles(bool ab, int nq);
-int mfma_locate(bool ab, int nq, int a, int b, int c);
+int mfma_tiles(bool ab, int nb);
+int mfma_locate(bool ab, int nb, int a, int b, int c);
 hipError_t launch_contract_mfma(const pb3_plan& p, const Exec& x, bool mixed, hipStream_t s);
 // pairs of the fields g against columns of the fields gc (nb bins each, M^3
 // voxels; gc == nullptr: g itself) into x.ws.part.  ab = true: every pair

@@ -196,3 +196,26 @@ def test_multipole_plans_on_host():
     assert pb3.Plan(32, 500.0, np.array([1.0, 1.2]), host_only=True, lmax=2).n_ell == 2
     with pytest.raises(ValueError):
         pb3.Plan(32, 500.0, kf_edges(6), host_only=True, lmax=3)
+
+
+def test_contraction_tiles_hold_every_triplet_once():
+    """Host logic of the MFMA tile layouts (the library's internal C++
+    functions, called directly): for every bin count the kernels support,
+    each triplet a <= b <= c has one partial-vector slot inside the tiles,
+    no two triplets share one, and the layouts that trim a last 16-bin group
+    of at most 4 or 8 real bins use fewer tiles than the full one."""
+    lib = C.CDLL(LIB)
+    loc = getattr(lib, "_ZN3pb311mfma_locateEbiiii")
+    loc.restype, loc.argtypes = C.c_int, [C.c_bool, C.c_int, C.c_int, C.c_int, C.c_int]
+    til = getattr(lib, "_ZN3pb310mfma_tilesEbi")
+    til.restype, til.argtypes = C.c_int, [C.c_bool, C.c_int]
+    for nb in range(1, 49):
+        for ab in (False, True):
+            nt = til(ab, nb)
+            slots = [loc(ab, nb, a, b, c) for a in range(nb) for b in range(a, nb) for c in range(b, nb)]
+            assert min(slots) >= 0 and max(slots) < 256 * nt, (nb, ab)
+            assert len(set(slots)) == len(slots), (nb, ab)
+    full = {1: 6, 2: 30, 3: 88}  # tiles of the untrimmed layout per group count
+    for nb, want in [(4, 2), (8, 4), (16, 6), (17, 21), (20, 21), (21, 27), (24, 27), (25, 30), (32, 30),
+                     (36, 74), (40, 84), (41, 88)]:
+        assert til(False, nb) == want <= full[(nb + 15) // 16], nb

@@ -298,6 +298,19 @@ def test_autotune_with_cache(torch_cuda, tmp_path, monkeypatch):
         (48, 16),  # one full 16-bin group, no padding
         (64, 17),  # a second group holding a single bin
         (96, 32),  # two full groups, the largest fused contraction
+        # the layouts that trim a last group of at most 4 or 8 real bins, at their edges
+        (32, 4),
+        (32, 5),
+        (48, 8),
+        (48, 9),
+        (64, 20),
+        (64, 21),
+        (64, 24),
+        (64, 25),
+        (64, 36),  # three groups (separate z pass only)
+        (64, 37),
+        (64, 40),
+        (64, 41),
     ],
 )
 def test_bin_count_edges(torch_cuda, n, nbins):
