@@ -627,8 +627,11 @@ __device__ __forceinline__ void pair_init(PairSrc<M>& ps, const float2* a2, cons
 // mirrored ones, and j = 6..9 are always zero: no load, no select.
 template <int M, int KB> struct PlaneKinds {
   static constexpr int R2 = fft2_r2(M);
-  static constexpr bool direct(int j) { return KB == 0 || R2 * j < KB; }
-  static constexpr bool mirror(int j) { return KB == 0 || M - R2 * j - (R2 - 1) < KB; }
+  // without a bound (KB = 0, the full grid) a bin keeps at most M / 2 + 1
+  // planes, so only the inputs j around n = M / 2 can be either
+  static constexpr int B = KB > 0 ? KB : M / 2 + 2;
+  static constexpr bool direct(int j) { return R2 * j < B; }
+  static constexpr bool mirror(int j) { return M - R2 * j - (R2 - 1) < B; }
 };
 
 // Raw inputs of one line for a phase-1 lane: plane n = tl + R2 j comes from
@@ -639,10 +642,11 @@ template <int M, int KB> struct PlaneKinds {
 // in scalar registers and spill those).
 // MASKED (the FP32 groups, short of registers): loads under lane masks
 // leave the zero planes zero.  Otherwise every lane loads, which suits
-// fetching a line ahead: with a plane bound (KB > 0) an input past the
-// bin's planes reads a zero kept in global memory, so the combine needs no
-// select (11% fewer producer instructions than selecting after the load);
-// without one, plane 0 stands in for a zero plane and the combine selects.
+// fetching a line ahead: an input that can only be a direct plane or only a
+// mirrored one reads a zero kept in global memory when it is past the bin's
+// planes, so the combine needs no select (11% fewer producer instructions
+// than selecting after the load); an input that can be either (around
+// n = M / 2 on the full grid) selects, with plane 0 standing in for zero.
 // zero input of the fused producer (read only)
 __device__ float2 kZeroPlane[1];
 
@@ -668,10 +672,9 @@ __device__ __forceinline__ void pair_fetch(PairSrc<M>& ps, long line, int tl) {
       else if (r && m < k1n) c = p1[m];
       ps.r0[j] = a;
       ps.r1[j] = c;
-    } else if constexpr (KB > 0) {
-      // each input is direct-only or mirror-only: an input past the bin's
-      // planes reads the zero constant, so the combine needs no select
-      static_assert(KB == 0 || 2 * KB < M + 1 - R2, "direct and mirror inputs are exclusive");
+    } else if (d != r) {
+      // a direct-only or mirror-only input: past the bin's planes it reads
+      // the zero constant, so the combine needs no select
       const int i0 = d ? k : m;
       const float2* q0 = i0 < k0n ? p0 + i0 : kZeroPlane;
       const float2* q1 = i0 < k1n ? p1 + i0 : kZeroPlane;
@@ -702,7 +705,7 @@ __device__ __forceinline__ void produce_line(LineStage<NQ, M>& st, PairSrc<M>& p
         const bool d = PK::direct(j), r = PK::mirror(j);
         if (!d && !r) return make_float2(0.f, 0.f);
         float2 a = ps.r0[j], c = ps.r1[j];
-        if constexpr (!MASKED && KB > 0) {
+        if (!MASKED && d != r) {
           // zero past the planes (see pair_fetch); mirrored inputs are conjugated
           if (d) return make_float2(a.x - c.y, a.y + c.x);
           return make_float2(a.x + c.y, c.x - a.y);
@@ -879,8 +882,10 @@ static hipError_t launch_fused_m(const pb3_plan& p, const Exec& x, hipStream_t s
   if (fused_waves(MIXED) == 1 && p.n_cu > 0)
     while (cpw < 4 && p.contract_wgs % (2 * cpw) == 0 && p.contract_wgs / (2 * cpw) >= p.n_cu) cpw *= 2;
   const int n_wg = (p.contract_wgs + cpw - 1) / cpw;
-  // every bin keeps at most Kz planes; on an alias-free grid Kz <= M / 3 + 1
+  // every bin keeps at most Kz planes; on an alias-free grid Kz <= M / 3 + 1,
+  // and on any grid Kz <= M / 2 + 1 (the producer's plane kinds assume it)
   constexpr int KB = M / 3 + 2;
+  if (p.Kz > M / 2 + 1) return hipErrorInvalidValue;
   if (p.Kz < KB)
     hipLaunchKernelGGL((k_zcontract<NQ, L, MIXED, M, KB>), dim3(n_wg, 1, x.n_jobs), dim3(fused_threads(MIXED)), 0, s,
                        x.ws.a2, p.d.geom, p.nb, p.d.tw_m[2], scale, lpw, x.ws.part, p.part_len, sel_lo, sel_hi,
