@@ -49,7 +49,7 @@ MEASURED_TRAFFIC = {
         "fetch_kib": 138396.3, "write_kib": 30720.0, "fetch_factor": 2.0, "write_factor": 1.0,
         "sources": {
             "paper_2404_07249_amd/csrc/contract_mfma.hip":
-                "69a28d9d8a618e834529146167a2ce8cff8ae549fd3f0effb6c26606ca3d660a",
+                "58cac322b7af6b6528e9c5c3b9300c9fb662ff2965665db28b481203ac96f393",
             "paper_2404_07249_amd/csrc/fft_dev.h":
                 "df3b6d76c6673e67d4b39f61aa79139393ef94214581251510d14c1ded1023f4",
             "paper_2404_07249_amd/csrc/job.h":
@@ -62,7 +62,7 @@ MEASURED_TRAFFIC = {
         "fetch_kib": 139862.5, "write_kib": 30720.0, "fetch_factor": 2.0, "write_factor": 1.0,
         "sources": {
             "paper_2404_07249_amd/csrc/contract_mfma.hip":
-                "69a28d9d8a618e834529146167a2ce8cff8ae549fd3f0effb6c26606ca3d660a",
+                "58cac322b7af6b6528e9c5c3b9300c9fb662ff2965665db28b481203ac96f393",
             "paper_2404_07249_amd/csrc/fft_dev.h":
                 "df3b6d76c6673e67d4b39f61aa79139393ef94214581251510d14c1ded1023f4",
             "paper_2404_07249_amd/csrc/job.h":

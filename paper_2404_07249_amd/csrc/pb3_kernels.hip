@@ -54,36 +54,43 @@ __global__ void __launch_bounds__(256) k_power_chunks(const float2* __restrict__
   if (threadIdx.x == 0) part[c] = red[0];
 }
 
-// One wave per bin: lane l sums the bin's chunks l, l + 64, ... and the
-// lanes combine in a fixed-order tree in red[64] (the wave's own).  Every
-// thread of the work-group calls it (it holds work-group barriers); a wave
-// with valid = false takes part in the barriers only.
+// One work-group of 256 threads per bin: thread l sums the bin's partials
+// l, l + 256, ..., four loads in flight per round, and the threads combine
+// in a fixed-order tree in red[256].  The bins with the most partials have
+// a few hundred, so one round of loads covers them.
 __device__ __forceinline__ void power_bin_final(const double* __restrict__ part, const int32_t* __restrict__ chunk_first,
-                                                int b, bool valid, double* red, const double* __restrict__ scale,
-                                                double shift, double* __restrict__ pk) {
-  const int l = threadIdx.x & 63;
+                                                int b, double* red, const double* __restrict__ scale, double shift,
+                                                double* __restrict__ pk) {
+  constexpr int NT = 256;
+  const int l = threadIdx.x;
+  const int first = chunk_first[b], last = chunk_first[b + 1];
   double s = 0.0;
-  if (valid)
-    for (int c = chunk_first[b] + l; c < chunk_first[b + 1]; c += 64) s += part[c];
+  for (int c = first + l; c < last; c += 4 * NT) {
+    double v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = c + k * NT < last ? part[c + k * NT] : 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s += v[k];
+  }
   red[l] = s;
   __syncthreads();
-  for (int h = 32; h > 0; h >>= 1) {
+  for (int h = NT / 2; h > 0; h >>= 1) {
     if (l < h) red[l] += red[l + h];
     __syncthreads();
   }
-  if (valid && l == 0) pk[b] = red[0] * scale[b] - shift;
+  if (l == 0) pk[b] = red[0] * scale[b] - shift;
 }
 
-__global__ void __launch_bounds__(64) k_power_final(const double* __restrict__ part,
-                                                    const int32_t* __restrict__ chunk_first, int nb,
-                                                    const double* __restrict__ scale, const JobIO io, size_t wstride,
-                                                    double shift) {
-  __shared__ double red[64];
-  power_bin_final(job_ptr(part, wstride), chunk_first, blockIdx.x, true, red, scale, shift, io.pk[blockIdx.z]);
+__global__ void __launch_bounds__(256) k_power_final(const double* __restrict__ part,
+                                                     const int32_t* __restrict__ chunk_first, int nb,
+                                                     const double* __restrict__ scale, const JobIO io, size_t wstride,
+                                                     double shift) {
+  __shared__ double red[256];
+  power_bin_final(job_ptr(part, wstride), chunk_first, blockIdx.x, red, scale, shift, io.pk[blockIdx.z]);
 }
 
 // The power spectrum's last step inside the bispectrum's final launch, when
-// one call computes both: blocks past the reduction's take four bins each.
+// one call computes both: blocks past the reduction's take one bin each.
 struct PowerFinal {
   const double* part = nullptr;  // chunk partials (per job at the workspace stride)
   const int32_t* chunk_first = nullptr;
@@ -202,9 +209,8 @@ __global__ void __launch_bounds__(256) k_reduce_final(const double* __restrict__
                                                       const double* __restrict__ bias, int n_red, PowerFinal pf) {
   if ((int)blockIdx.x >= n_red) {
     __shared__ double red[256];
-    const int b = ((int)blockIdx.x - n_red) * 4 + (int)(threadIdx.x >> 6);
-    power_bin_final(job_ptr(pf.part, wstride), pf.chunk_first, b, b < pf.nb, red + (threadIdx.x & ~63u), pf.scale,
-                    pf.shift, io.pk[blockIdx.z]);
+    power_bin_final(job_ptr(pf.part, wstride), pf.chunk_first, (int)blockIdx.x - n_red, red, pf.scale, pf.shift,
+                    io.pk[blockIdx.z]);
     return;
   }
   rsl = job_ptr(rsl, wstride);
@@ -437,7 +443,7 @@ hipError_t launch_power(const pb3_plan& p, const Exec& x, hipStream_t s, bool fi
                      x.ws.ppart, x.wstride, (const double*)p.d.mode_w);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !final) return e;
-  hipLaunchKernelGGL(k_power_final, dim3(p.nb, 1, x.n_jobs), dim3(64), 0, s, x.ws.ppart, p.d.chunk_first, p.nb,
+  hipLaunchKernelGGL(k_power_final, dim3(p.nb, 1, x.n_jobs), dim3(256), 0, s, x.ws.ppart, p.d.chunk_first, p.nb,
                      p.d.pk_scale, x.io, x.wstride, p.pk_shift);
   return hipGetLastError();
 }
@@ -492,7 +498,7 @@ hipError_t launch_reduce(const pb3_plan& p, const Exec& x, hipStream_t s, bool w
                      x.ws.part, p.contract_wgs, p.part_len, x.ws.rsl, x.wstride);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce_final, dim3(n_red + (pf.nb + 3) / 4, 1, x.n_jobs), dim3(256), 0, s, x.ws.rsl, p.part_len,
+  hipLaunchKernelGGL(k_reduce_final, dim3(n_red + pf.nb, 1, x.n_jobs), dim3(256), 0, s, x.ws.rsl, p.part_len,
                      p.d.out_map, p.d.inv_counts, n_out, x.io, x.wstride, (const double*)p.d.bk_bias, n_red, pf);
   return hipGetLastError();
 }
