@@ -17,6 +17,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "fft_dev.h"
 #include "job.h"
 #include "pb3_internal.h"
@@ -208,6 +210,7 @@ __global__ void __launch_bounds__(512) k_fwd_col2(const float2* __restrict__ in,
 // The kx line of Theta_b D (Theta_b alone when UNIT) enters at FFT
 // positions kx mod M.  A mode belongs to the bin when the plan's per-mode
 // table bin3 says so; bin3 carries one more entry, "no bin", at index nb3.
+// In a cubic box the plain path tests n2lo <= |n|^2 < n2hi instead.
 // Output a1_b[x][jy][jz].  Tile col0 = first column.
 struct WinOff {
   int x, y, z;  // offsets of k = 0 of each axis in the window table
@@ -275,21 +278,37 @@ __global__ void __launch_bounds__(512) k_inv_x2(const float2* __restrict__ dc, t
         // one of its tiles, so the tiles' sums are the power spectrum's
         // numerator (eq. pk-limit), weight 2 for the half spectrum's
         // modes whose conjugate is not stored.
+        // In a cubic box the membership is the integer test n2lo <= |n|^2 <
+        // n2hi, the same modes as the table's, with no table reads.
         double pacc = 0.0;
-        fft2_line<M, 1>(
-            scr + col * LS, tl, tws,
-            [&](int n) {
-              const int kx = n <= g.kposx ? n : (n >= M - g.knegx ? n - M : 0x40000000);
-              const bool in = live && kx != 0x40000000;
-              const size_t ci = in ? ((size_t)(kx + Kcx) * Lcy + (ky + Kcy)) * Kz + kz : 0;
-              const int bb = bin3[in ? ci : nb3];
-              const float2 d = dc[ci];
-              const float m = bb == b ? 1.f : 0.f;
-              const float vx = fmaf(d.x, m, 0.f), vy = fmaf(d.y, m, 0.f);
-              if (ppart) pacc += (double)vx * vx + (double)vy * vy;
-              return cx<C>(Rl(vx), Rl(vy));
-            },
-            store);
+        const int r2 = ky * ky + kz * kz;
+        auto gather = [&](auto by_n2) {
+          fft2_line<M, 1>(
+              scr + col * LS, tl, tws,
+              [&](int n) {
+                const int kx = n <= g.kposx ? n : (n >= M - g.knegx ? n - M : 0x40000000);
+                const bool in = live && kx != 0x40000000;
+                const size_t ci = in ? ((size_t)(kx + Kcx) * Lcy + (ky + Kcy)) * Kz + kz : 0;
+                bool inb;
+                if constexpr (decltype(by_n2)::value) {
+                  const int kxi = in ? kx : 0;
+                  const int n2 = kxi * kxi + r2;
+                  inb = in && n2 >= g.n2lo && n2 < g.n2hi;
+                } else {
+                  inb = bin3[in ? ci : nb3] == b;
+                }
+                const float2 d = dc[ci];
+                const float m = inb ? 1.f : 0.f;
+                const float vx = fmaf(d.x, m, 0.f), vy = fmaf(d.y, m, 0.f);
+                if (ppart) pacc += (double)vx * vx + (double)vy * vy;
+                return cx<C>(Rl(vx), Rl(vy));
+              },
+              store);
+        };
+        if (g.n2lo >= 0)
+          gather(std::true_type{});
+        else
+          gather(std::false_type{});
         if (ppart) {
           // fixed-order sum over the work-group: butterfly within each
           // wave, then the waves in order

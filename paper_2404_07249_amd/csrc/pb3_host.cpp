@@ -425,6 +425,8 @@ static pb3_status build_host(pb3_plan* p, const int grid[3], const double box[3]
     g.kposy = (p->fully && kby == p->Ny / 2) ? p->Ny / 2 - 1 : std::max(kby, 0);
     g.ly = g.knegy + g.kposy + 1;
     g.kzn = std::max(kbz, 0) + 1;
+    g.n2lo = p->aniso ? -1 : (int32_t)p->thr[b];
+    g.n2hi = p->aniso ? -1 : (int32_t)p->thr[b + 1];
     g.a1_off = o1;
     g.a2_off = o2;
     o1 += (int64_t)p->Mx * g.ly * g.kzn;

@@ -43,6 +43,7 @@ struct BinGeom {
   int32_t knegy, kposy;  // y extent
   int32_t ly;            // knegy + kposy + 1
   int32_t kzn;           // number of kz planes
+  int32_t n2lo, n2hi;    // cubic box: the bin's modes are n2lo <= |n|^2 < n2hi (n2lo < 0: use the per-mode table)
   int64_t a1_off;        // float2 offset of this bin's x-pass output  [Mx][ly][kzn]
   int64_t a2_off;        // float2 offset of this bin's y-pass output  [Mx][My][kzn]
 };
