@@ -140,7 +140,7 @@ static void free_device(pb3_plan* p) {
                   d.out_map,   d.inv_counts, d.pk_scale,  d.tw_n[0],     d.tw_n[1],   d.tw_n[2],   d.tw_m[0],
                   d.tw_m[1],   d.tw_m[2],    d.tw_m_d[0], d.tw_m_d[1],   d.tw_m_d[2], d.nmodes_d,  d.pml_inv,
                   d.ml_trips,  d.ml_fac,     d.ml_map,    d.win_inv,     d.pfid_inv,  d.pfid_inv_d, d.mode_w,
-                  d.bk_bias,   d.bk_mix,     d.out_map_ab, d.xtile_first};
+                  d.bk_bias,   d.bk_mix,     d.out_map_ab, d.xtile_first, d.out_inv};
   for (void* q : ptrs)
     if (q) hipFree(q);
   d = DeviceTables{};
@@ -851,6 +851,12 @@ static pb3_status build_device(pb3_plan* p) {
     fac.push_back(scale / T);
   }
   if ((st = upload(&d.out_map, map.data(), map.size())) != PB3_OK) return st;
+  {
+    // the inverse map: the reduction's slice sums are stored in triplet order
+    std::vector<int32_t> inv((size_t)p->part_len, -1);
+    for (size_t t = 0; t < map.size(); ++t) inv[(size_t)map[t]] = (int32_t)t;
+    if ((st = upload(&d.out_inv, inv.data(), inv.size())) != PB3_OK) return st;
+  }
   if (!map_ab.empty() && (st = upload(&d.out_map_ab, map_ab.data(), map_ab.size())) != PB3_OK) return st;
   if ((st = upload(&d.inv_counts, fac.data(), fac.size())) != PB3_OK) return st;
   if (p->lmax > 0) {

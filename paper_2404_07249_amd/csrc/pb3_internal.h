@@ -77,6 +77,7 @@ struct DeviceTables {
   int32_t* trip_all = nullptr;    // candidate triplets (3 ints each), simple contraction
   int32_t* out_map = nullptr;     // per kept triplet: index into one work-group's MFMA partial vector
   int32_t* out_map_ab = nullptr;  // the same for pairs against separate column fields (multipoles)
+  int32_t* out_inv = nullptr;     // per element of a partial vector: the kept triplet read there, or -1
   double* inv_counts = nullptr;   // per kept triplet: scale / T
   double* pk_scale = nullptr;     // per bin: V / (N_pix^2 N_b)
   float2* tw_n[3] = {};           // W_{N_i}^j, j < N_i, per axis x, y, z

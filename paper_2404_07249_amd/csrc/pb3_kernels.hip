@@ -89,8 +89,9 @@ __global__ void __launch_bounds__(256) k_power_final(const double* __restrict__ 
   power_bin_final(job_ptr(part, wstride), chunk_first, blockIdx.x, red, scale, shift, io.pk[blockIdx.z]);
 }
 
-// The power spectrum's last step inside the bispectrum's final launch, when
-// one call computes both: blocks past the reduction's take one bin each.
+// The power spectrum's last step inside the bispectrum's slice reduction,
+// when one call computes both: rows of blocks past the slices take one bin
+// each.
 struct PowerFinal {
   const double* part = nullptr;  // chunk partials (per job at the workspace stride)
   const int32_t* chunk_first = nullptr;
@@ -178,49 +179,65 @@ __global__ void k_reduce(const Rl* __restrict__ part, int n_wg, int part_len, co
 // summed per element (FP64), then the slices per kept triplet.
 // Each thread takes four neighbouring elements (one 16-byte load per
 // work-group partial; part_len is a multiple of 256), each summed over the
-// slice's work-groups in order.
-__global__ void k_reduce_slices(const float* __restrict__ part, int n_wg, int part_len, double* __restrict__ rsl,
-                                size_t wstride) {
+// slice's work-groups in order.  With inv (element -> kept triplet or -1)
+// the slice sums are stored in triplet order, rsl[s][t], so that the final
+// launch reads them without a gather; otherwise every element, rsl[s][e].
+// Rows of blocks past the slices finish the power spectrum (one bin per
+// block), whose per-tile partials are complete when this launch starts.
+__global__ void __launch_bounds__(256) k_reduce_slices(const float* __restrict__ part, int n_wg, int part_len,
+                                                       double* __restrict__ rsl, size_t wstride,
+                                                       const int32_t* __restrict__ inv, int n_out, PowerFinal pf,
+                                                       const JobIO io) {
+  if ((int)blockIdx.y >= kReduceSlices) {
+    const int b = ((int)blockIdx.y - kReduceSlices) * (int)gridDim.x + (int)blockIdx.x;
+    if (b >= pf.nb) return;  // whole work-group
+    __shared__ double red[256];
+    power_bin_final(job_ptr(pf.part, wstride), pf.chunk_first, b, red, pf.scale, pf.shift, io.pk[blockIdx.z]);
+    return;
+  }
   part = job_ptr(part, wstride);
   rsl = job_ptr(rsl, wstride);
   const int e = 4 * (blockIdx.x * blockDim.x + threadIdx.x);
   if (e >= part_len) return;
   const int s = blockIdx.y;
   const int w0 = (int)((long)n_wg * s / kReduceSlices), w1 = (int)((long)n_wg * (s + 1) / kReduceSlices);
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 8
   for (int w = w0; w < w1; ++w) {
     const float4 v = *reinterpret_cast<const float4*>(part + (size_t)w * part_len + e);
-    a0 += (double)v.x;
-    a1 += (double)v.y;
-    a2 += (double)v.z;
-    a3 += (double)v.w;
+    a[0] += (double)v.x;
+    a[1] += (double)v.y;
+    a[2] += (double)v.z;
+    a[3] += (double)v.w;
   }
-  double* __restrict__ o = rsl + (size_t)s * part_len + e;
-  o[0] = a0;
-  o[1] = a1;
-  o[2] = a2;
-  o[3] = a3;
+  if (inv) {
+    const int4 t = *reinterpret_cast<const int4*>(inv + e);
+    double* __restrict__ o = rsl + (size_t)s * n_out;
+    if (t.x >= 0) o[t.x] = a[0];
+    if (t.y >= 0) o[t.y] = a[1];
+    if (t.z >= 0) o[t.z] = a[2];
+    if (t.w >= 0) o[t.w] = a[3];
+  } else {
+    double* __restrict__ o = rsl + (size_t)s * part_len + e;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o[k] = a[k];
+  }
 }
 
-__global__ void __launch_bounds__(256) k_reduce_final(const double* __restrict__ rsl, int part_len,
+// Per kept triplet t: the slices in order, rsl[s][map[t]] (map given, slice
+// stride part_len) or rsl[s][t] (no map, slice stride n_out).
+__global__ void __launch_bounds__(256) k_reduce_final(const double* __restrict__ rsl, int stride,
                                                       const int32_t* __restrict__ map, const double* __restrict__ fac,
                                                       int n_out, const JobIO io, size_t wstride,
-                                                      const double* __restrict__ bias, int n_red, PowerFinal pf) {
-  if ((int)blockIdx.x >= n_red) {
-    __shared__ double red[256];
-    power_bin_final(job_ptr(pf.part, wstride), pf.chunk_first, (int)blockIdx.x - n_red, red, pf.scale, pf.shift,
-                    io.pk[blockIdx.z]);
-    return;
-  }
+                                                      const double* __restrict__ bias) {
   rsl = job_ptr(rsl, wstride);
   double* __restrict__ out = io.bk[blockIdx.z];
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_out) return;
-  int idx = map[t];
+  const int idx = map ? map[t] : t;
   double acc = 0.0;
 #pragma unroll
-  for (int s = 0; s < kReduceSlices; ++s) acc += rsl[(size_t)s * part_len + idx];
+  for (int s = 0; s < kReduceSlices; ++s) acc += rsl[(size_t)s * stride + idx];
   out[t] = acc * fac[t] - (bias ? bias[t] : 0.0);
 }
 
@@ -490,16 +507,17 @@ hipError_t launch_contract(const pb3_plan& p, const Exec& x, pb3_precision prec,
 hipError_t launch_reduce(const pb3_plan& p, const Exec& x, hipStream_t s, bool with_pk, bool pk_folded) {
   int n_out = (int)(p.trip.size() / 3);
   if (n_out == 0) return hipSuccess;
-  const int n_red = (n_out + 255) / 256;
   PowerFinal pf;
   // the power partials are per chunk of a bin's mode list, or per inverse-x tile when that pass took them
   if (with_pk) pf = PowerFinal{x.ws.ppart, pk_folded ? p.d.xtile_first : p.d.chunk_first, p.d.pk_scale, p.pk_shift, p.nb};
-  hipLaunchKernelGGL(k_reduce_slices, dim3((p.part_len / 4 + 255) / 256, kReduceSlices, x.n_jobs), dim3(256), 0, s,
-                     x.ws.part, p.contract_wgs, p.part_len, x.ws.rsl, x.wstride);
+  const int gx = (p.part_len / 4 + 255) / 256;
+  const int pk_rows = (pf.nb + gx - 1) / gx;
+  hipLaunchKernelGGL(k_reduce_slices, dim3(gx, kReduceSlices + pk_rows, x.n_jobs), dim3(256), 0, s, x.ws.part,
+                     p.contract_wgs, p.part_len, x.ws.rsl, x.wstride, (const int32_t*)p.d.out_inv, n_out, pf, x.io);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce_final, dim3(n_red + pf.nb, 1, x.n_jobs), dim3(256), 0, s, x.ws.rsl, p.part_len,
-                     p.d.out_map, p.d.inv_counts, n_out, x.io, x.wstride, (const double*)p.d.bk_bias, n_red, pf);
+  hipLaunchKernelGGL(k_reduce_final, dim3((n_out + 255) / 256, 1, x.n_jobs), dim3(256), 0, s, x.ws.rsl, n_out,
+                     (const int32_t*)nullptr, p.d.inv_counts, n_out, x.io, x.wstride, (const double*)p.d.bk_bias);
   return hipGetLastError();
 }
 
@@ -663,13 +681,14 @@ pb3_status run_multipoles(pb3_plan& p, const float* delta, double* pk_out, doubl
                "multipoles: contraction"))
         return st;
       hipLaunchKernelGGL(k_reduce_slices, dim3((p.part_len_ab / 4 + 255) / 256, kReduceSlices, 1), dim3(256), 0, s,
-                         x.ws.part, p.contract_wgs, p.part_len_ab, x.ws.rsl, (size_t)0);
+                         x.ws.part, p.contract_wgs, p.part_len_ab, x.ws.rsl, (size_t)0, (const int32_t*)nullptr, 0,
+                         PowerFinal{}, JobIO{});
       if (!chk(hipGetLastError(), "multipoles: reduce")) return st;
       JobIO io{};
       io.bk[0] = bk_out + (size_t)l * nt;
       hipLaunchKernelGGL(k_reduce_final, dim3((nt + 255) / 256, 1, 1), dim3(256), 0, s, x.ws.rsl, p.part_len_ab,
-                         p.d.out_map_ab, p.d.ml_fac + (size_t)l * nt, nt, io, (size_t)0,
-                         l == 0 ? (const double*)p.d.bk_bias : nullptr, (nt + 255) / 256, PowerFinal{});
+                         (const int32_t*)p.d.out_map_ab, p.d.ml_fac + (size_t)l * nt, nt, io, (size_t)0,
+                         l == 0 ? (const double*)p.d.bk_bias : nullptr);
       if (!chk(hipGetLastError(), "multipoles: reduce")) return st;
     }
   } else {
