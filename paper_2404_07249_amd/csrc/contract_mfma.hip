@@ -582,7 +582,17 @@ __device__ __forceinline__ void contract_line_group(const LineStage<NQ, M>& st, 
   }
 }
 
-// Producer side.  The 256 producer threads form slots of fft2_threads(M)
+// The producer's line factorisation M = R1 x R2: phase 1 runs R2 lanes of
+// R1-point DFTs, phase 2 R1 lanes of R2-point DFTs, in a slot of 8 or 16
+// lanes.  At M = 96 the default 16 x 6 gives each loading lane a 16-point
+// DFT and 16 inputs with 10 of the slot's lanes idle; 8 x 12 halves the
+// loads and twiddles per lane.
+constexpr int zr1(int m) { return m == 96 ? 8 : fft2_r1(m); }
+constexpr int zr2(int m) { return m / zr1(m); }
+constexpr int zthreads(int m) { return (zr1(m) > zr2(m) ? zr1(m) : zr2(m)) <= 8 ? 8 : 16; }
+static_assert(zr1(192) <= 16 && zr2(192) <= 16 && zr1(96) * zr2(96) == 96, "producer slots of at most 16 lanes");
+
+// Producer side.  The 256 producer threads form slots of zthreads(M)
 // lanes; slot t transforms the bin pair (2t, 2t + 1) of every line, packed
 // as one complex line F_2t + i F_2t+1 (both real after the transform).
 // The pair's geometry is read once.  In mixed precision the raw inputs of
@@ -590,7 +600,7 @@ __device__ __forceinline__ void contract_line_group(const LineStage<NQ, M>& st, 
 // transformed; the FP32 groups (12 waves, fewer registers per wave) fetch
 // each line just before its transform.
 template <int M> struct PairSrc {
-  static constexpr int R1 = fft2_r1(M), R2 = fft2_r2(M);
+  static constexpr int R1 = zr1(M), R2 = zr2(M);
   const float2* x0;  // bin 2t's y-pass output, lines of s0 planes
   const float2* x1;  // bin 2t + 1's (bin 2t's when there is none)
   int s0, s1;
@@ -626,7 +636,7 @@ __device__ __forceinline__ void pair_init(PairSrc<M>& ps, const float2* a2, cons
 // M = 192 inputs j = 0..5 can only be direct planes, j = 10..15 only
 // mirrored ones, and j = 6..9 are always zero: no load, no select.
 template <int M, int KB> struct PlaneKinds {
-  static constexpr int R2 = fft2_r2(M);
+  static constexpr int R2 = zr2(M);
   // without a bound (KB = 0, the full grid) a bin keeps at most M / 2 + 1
   // planes, so only the inputs j around n = M / 2 can be either
   static constexpr int B = KB > 0 ? KB : M / 2 + 2;
@@ -693,13 +703,13 @@ template <int NQ, bool MIXED, int M, bool MASKED, int KB>
 __device__ __forceinline__ void produce_line(LineStage<NQ, M>& st, PairSrc<M>& ps, long next, const float2* tws,
                                              float2* scr, int slot, int tl, float scale, const SplitSel& sel) {
   using PK = PlaneKinds<M, KB>;
-  constexpr int R1 = fft2_r1(M), R2 = fft2_r2(M);
+  constexpr int R1 = zr1(M), R2 = zr2(M);
   constexpr int PF = LineStage<NQ, M>::PF, PH = LineStage<NQ, M>::PH;
   if (!ps.on) return;
   const int b0 = 2 * slot, b1 = 2 * slot + 1;
   int k0n = ps.k0n, k1n = ps.k1n;  // re-read per line (see pair_fetch)
   asm volatile("" : "+v"(k0n), "+v"(k1n));
-  fft2_line_wave<M, 1>(
+  fft2_line_wave<M, 1, zr1(M)>(
       scr + slot * R1 * (R2 + 1), tl, tws,
       [&](int j, int k) {
         const bool d = PK::direct(j), r = PK::mirror(j);
@@ -765,14 +775,14 @@ __global__ void __launch_bounds__(fused_threads(MIXED)) k_zcontract(const float2
   constexpr int K0 = 0, K1 = n_pair_blocks(L, NQ);
   constexpr int NT = n_tiles(L, NQ);
   constexpr int NTMAX = max_group_tiles<NQ, L, K0, K1>();
-  constexpr int TL = fft2_threads(M), NSLOT = kProducerThreads / TL;
+  constexpr int TL = zthreads(M), NSLOT = kProducerThreads / TL;
   static_assert(2 * NSLOT >= 16 * NQ, "one bin pair per producer slot");
   constexpr int STAGE_BYTES = (int)sizeof(LineStage<NQ, M>);
   constexpr int RED_BYTES = NT * 256 * 4;
   constexpr int MAIN = 2 * STAGE_BYTES > RED_BYTES ? 2 * STAGE_BYTES : RED_BYTES;
   __shared__ __align__(16) unsigned char smem[MAIN];
   __shared__ float2 tws[M];
-  __shared__ float2 scr[NSLOT * fft2_r1(M) * (fft2_r2(M) + 1)];
+  __shared__ float2 scr[NSLOT * zr1(M) * (zr2(M) + 1)];
   LineStage<NQ, M>* stage = reinterpret_cast<LineStage<NQ, M>*>(smem);
   float* red = reinterpret_cast<float*>(smem);
   const int tid = threadIdx.x;

@@ -249,12 +249,14 @@ __device__ __forceinline__ void fft2_line(C* s, int tl, const C* __restrict__ tw
 // next line's loads there).  Phase 2 hands thread k1 its whole row u[k2]
 // (output index k1 + R1 k2).  The exchange rows are R2 + 1 apart so that
 // phase 2's strided reads fall in distinct LDS banks; s holds R1 (R2 + 1)
-// elements.
-template <int N, int S, typename C, typename LoadF, typename MidF, typename RowF>
+// elements.  R1F, when set, replaces the default first radix fft2_r1(N)
+// (R2 = N / R1F); the caller's slot of lanes must hold max(R1, R2) of them
+// inside one wavefront.
+template <int N, int S, int R1F = 0, typename C, typename LoadF, typename MidF, typename RowF>
 __device__ __forceinline__ void fft2_line_wave(C* s, int tl, const C* __restrict__ tw, LoadF&& load, MidF&& mid,
                                                RowF&& row) {
-  constexpr int R1 = fft2_r1(N), R2 = fft2_r2(N), RP = R2 + 1;
-  static_assert(64 % fft2_threads(N) == 0, "line must fit in one wavefront");
+  constexpr int R1 = R1F ? R1F : fft2_r1(N), R2 = N / R1, RP = R2 + 1;
+  static_assert(R1 * R2 == N && R1 <= 64 && R2 <= 64, "line must fit in one wavefront");
   C v[R1];
   if (tl < R2) {
 #pragma unroll

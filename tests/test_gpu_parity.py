@@ -126,6 +126,30 @@ def test_full_grid_flag_matches_reduced_grid(torch_cuda):
     _check_pb(res, pk2, bk2, p2.triplets, "full grid")
 
 
+@pytest.mark.parametrize(
+    "n,nbins,m",
+    [
+        (128, 15, 96),  # alias-free contraction grid of 96 points (bounded kz planes)
+        (96, 17, 96),   # the full 96-point grid (every plane up to the Nyquist one)
+        (128, 24, 128),
+        (64, 19, 64),
+    ],
+)
+def test_fused_producer_line_lengths(torch_cuda, n, nbins, m):
+    """The fused kernel's z transforms at each line factorisation of its
+    producer (96 points as 12 x 8, 128 as 16 x 8, 64 as 8 x 8), on the
+    alias-free and the full grid, both precisions, against the oracle."""
+    torch = torch_cuda
+    box = 2000.0
+    edges = kf_edges(nbins)
+    d = quadratic_field(n, box, 1.0, 900 + nbins).astype(np.float32)
+    res = oracle.bispectrum(d.astype(np.float64), box, edges)
+    for prec in PRECS:
+        plan, pk, bk = _run_case(torch, n, box, edges, d, prec, fuse=True)
+        assert plan.contract_grid == m
+        _check_pb(res, pk, bk, plan.triplets, f"{prec} n={n} bins={nbins}")
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_determinism_and_exact_scaling(torch_cuda, prec):
     """Fixed-order reductions: repeated calls are bitwise equal, and 2*delta
