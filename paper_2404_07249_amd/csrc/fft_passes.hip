@@ -481,6 +481,106 @@ __global__ void __launch_bounds__(512) k_inv_z2(const typename Cx<Rl>::type* __r
     reinterpret_cast<C*>(dst)[e] = reinterpret_cast<const C*>(outr)[e];
 }
 
+// ------------------------------------------- z round trip (masked power)
+// For the Monte Carlo Fisher matrix of the masked power spectrum: per z
+// line and bin, the inverse z transform of the inverse y pass's output (the
+// filtered field g_b on the full grid), times the window w on the line,
+// then the forward z transform of w g_b kept at kz < Kz: the forward z pass
+// of DFT[w g_b] without g_b ever leaving the chip.  Both transforms take
+// the half-length form (N = 2H, real lines as complex lines of H points):
+//   inverse: with X[k + H] = conj X[H - k] (X real-valued in z),
+//     Z[k] = (X[k] + conj X[H - k]) + i W_N^-k (X[k] - conj X[H - k]),
+//     z = IDFT_H[Z] (unnormalised) gives x[2m] = Re z[m], x[2m + 1] = Im z[m];
+//   forward: as in the forward z pass above.
+// A slot of 16 lanes owns one line for all bins; the window of its line is
+// read once into registers, and the next bin's inputs are fetched while the
+// current bin is transformed.  Output f1 [nb][lines][Kz].
+template <int N>
+__global__ void __launch_bounds__(256) k_zround(const float2* __restrict__ a2, float2* __restrict__ f1,
+                                                const float* __restrict__ w, const BinGeom* __restrict__ geom, int nb,
+                                                const float2* __restrict__ tw, float scale, int nlines, int Kz) {
+  constexpr int H = N / 2, R2 = 16, R1 = H / 16, TL = 16, NL = 16, EX = R1 * (R2 + 1);
+  static_assert(R1 * 16 == H && R1 <= 16, "half-length lines of 16 x R1 points");
+  __shared__ float2 tws[N];  // W_N^m
+  __shared__ float2 twh[H];  // W_H^m = W_N^(2m)
+  __shared__ float2 xs[NL * EX];  // per line: the FFT exchange
+  __shared__ float2 ys[NL * EX];  // per line: w x between the transforms, then the spectrum Z
+  const int tid = threadIdx.x;
+  for (int e = tid; e < N; e += NL * TL) {
+    const float2 v = tw[e];
+    tws[e] = v;
+    if (!(e & 1)) twh[e >> 1] = v;
+  }
+  __syncthreads();
+  const int ln = tid / TL, tl = tid % TL;
+  const int line = blockIdx.x * NL + ln;
+  if (line >= nlines) return;  // whole slot; no work-group barrier follows
+  float2* xl = xs + ln * EX;
+  float2* yl = ys + ln * EX;
+  // the window at x[2m], x[2m + 1] for this lane's forward inputs m = tl + 16 j
+  float2 wv[R1];
+  const float2* wl = reinterpret_cast<const float2*>(w + (size_t)line * N);
+#pragma unroll
+  for (int j = 0; j < R1; ++j) wv[j] = wl[tl + R2 * j];
+  // X[m] and X[H - m] of this lane's inverse inputs m = tl + 16 j (zero past the bin's planes)
+  float2 xa[R1], xc[R1];
+  auto fetch = [&](int b) {
+    const BinGeom g = geom[b];
+    const int kzn = g.kzn;
+    const float2* X = a2 + g.a2_off + (size_t)line * kzn;
+#pragma unroll
+    for (int j = 0; j < R1; ++j) {
+      const int m = tl + R2 * j;
+      xa[j] = m < kzn ? X[m] : make_float2(0.f, 0.f);
+      xc[j] = H - m < kzn ? X[H - m] : make_float2(0.f, 0.f);
+    }
+  };
+  fetch(0);
+  for (int b = 0; b < nb; ++b) {
+    fft2_line_wave<H, 1, R1>(
+        xl, tl, twh,
+        [&](int j, int m) {
+          const float2 a = xa[j], c = xc[j];                    // conj of c taken below
+          const float2 e = make_float2(a.x + c.x, a.y - c.y);  // X[m] + conj X[H - m]
+          const float2 d = make_float2(a.x - c.x, a.y + c.y);  // X[m] - conj X[H - m]
+          const float2 t = tws[m];                              // W_N^m; times its conjugate below
+          const float2 o = make_float2(d.x * t.x + d.y * t.y, d.y * t.x - d.x * t.y);
+          return make_float2(e.x - o.y, e.y + o.x);  // E' + i O'
+        },
+        [&] {
+          if (b + 1 < nb) fetch(b + 1);
+        },
+        [&](int k1, const float2 (&u)[R2]) {
+#pragma unroll
+          for (int k2 = 0; k2 < R2; ++k2) yl[k1 + R1 * k2] = make_float2(u[k2].x * scale, u[k2].y * scale);
+        });
+    fft2_line_wave<H, -1, R1>(
+        xl, tl, twh,
+        [&](int j, int m) {
+          const float2 v = yl[m];
+          return make_float2(v.x * wv[j].x, v.y * wv[j].y);
+        },
+        [] {},
+        [&](int k1, const float2 (&u)[R2]) {
+#pragma unroll
+          for (int k2 = 0; k2 < R2; ++k2) yl[k1 + R1 * k2] = u[k2];
+        });
+    float2* dst = f1 + (size_t)b * ((size_t)nlines * Kz) + (size_t)line * Kz;
+    for (int k = tl; k < Kz; k += TL) {
+      const int kh = k % H;
+      const float2 a = yl[kh], c = yl[(H - kh) % H];
+      const float ex = 0.5f * (a.x + c.x), ey = 0.5f * (a.y - c.y);   // E[k]
+      const float ox = 0.5f * (a.y + c.y), oy = -0.5f * (a.x - c.x);  // O[k]
+      const float2 t = tws[k];                                        // k < Kz <= N/2 + 1
+      dst[k] = make_float2(ex + t.x * ox - t.y * oy, ey + t.x * oy + t.y * ox);
+    }
+    // the next bin's transforms write these rows again
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
 // ================================================================ launchers
 
 #define PB3_FFT_LEN(len, ...)                          \
@@ -624,6 +724,25 @@ hipError_t run_inv_z(const pb3_plan& p, bool dbl, const void* a2, void* gout, co
                          (float*)gout, p.d.geom, ts.d, ts.n, (const float2*)tw, (float)sc, nlines, wstride);
     }
     return hipGetLastError();
+  });
+  return hipErrorInvalidValue;
+}
+
+bool zround_supported(const pb3_plan& p) {
+  return p.Mx == p.Nx && p.My == p.Ny && p.Mz == p.Nz && half_form(p.Nz);
+}
+
+hipError_t run_zround(const pb3_plan& p, const float2* a2, const float* window, float2* f1, hipStream_t s) {
+  if (!zround_supported(p)) return hipErrorInvalidValue;
+  const int nlines = p.Nx * p.Ny;
+  const float sc = (float)(1.0 / ((double)p.Mx * p.My * p.Mz));
+  PB3_FFT_LEN(p.Nz, {
+    if constexpr (half_form(LL)) {
+      hipLaunchKernelGGL(k_zround<LL>, dim3((nlines + 15) / 16), dim3(256), 0, s, a2, f1, window, p.d.geom, p.nb,
+                         p.d.tw_n[2], sc, nlines, p.Kz);
+      return hipGetLastError();
+    }
+    break;
   });
   return hipErrorInvalidValue;
 }

@@ -292,6 +292,11 @@ hipError_t run_inv_y(const pb3_plan& p, bool dbl, const void* a1, void* a2, cons
                      size_t wstride, hipStream_t s);
 hipError_t run_inv_z(const pb3_plan& p, bool dbl, const void* a2, void* gout, const TileSet& ts, int n_jobs,
                      size_t wstride, hipStream_t s);
+// z round trip of the masked power spectrum's Monte Carlo: per bin, the inverse z
+// pass, times the window, then the forward z pass kept at kz < Kz (full grid,
+// z lengths of the half-length form)
+bool zround_supported(const pb3_plan& p);
+hipError_t run_zround(const pb3_plan& p, const float2* a2, const float* window, float2* f1, hipStream_t s);
 // tile widths of the inverse passes for FP32 (dbl = false) or FP64 lines
 int tile_width_x(int M, bool dbl);
 int tile_width_z(int M, bool dbl);

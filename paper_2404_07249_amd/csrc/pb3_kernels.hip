@@ -325,13 +325,15 @@ __global__ void __launch_bounds__(256) k_cross_chunks(const float2* __restrict__
   if (threadIdx.x == 0) part[c] = red[0];
 }
 
-__global__ void k_cross_final(const double* __restrict__ part, const int32_t* __restrict__ chunk_first, int nb,
-                              double* __restrict__ row) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+// Row a = blockIdx.y of the Fisher sums: part holds n_chunks partials per row.
+__global__ void k_cross_final(const double* __restrict__ part, int n_chunks, const int32_t* __restrict__ chunk_first,
+                              int nb, double* __restrict__ acc) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x, a = blockIdx.y;
   if (b >= nb) return;
+  const double* pa = part + (size_t)a * n_chunks;
   double s = 0.0;
-  for (int c = chunk_first[b]; c < chunk_first[b + 1]; ++c) s += part[c];
-  row[b] += s;
+  for (int c = chunk_first[b]; c < chunk_first[b + 1]; ++c) s += pa[c];
+  acc[(size_t)a * nb + b] += s;
 }
 
 __global__ void k_fill_zero(double* __restrict__ x, int n) {
@@ -524,17 +526,26 @@ hipError_t launch_reduce(const pb3_plan& p, const Exec& x, hipStream_t s, bool w
 // ------------------------------------------- masked power spectrum (MC)
 // Per random field a:  g_b = IDFT[Theta_b DFT[w a]] for every bin (inverse
 // passes on the full grid), A = DFT[a] (compact), and for every bin a the
-// compact DFT of w g_a (the window applied in the forward z pass), whose
-// cross spectrum with A over bin b's modes is the Fourier-space dot
-// product of the Fisher estimate (Q^asym_b[a] = Theta_b A).
-// Workspace: the plan's workspace, fields [nb][N^3], the compact A,
-// chunk partials, the Fisher sums [nb^2] and the data's box P [nb].
+// compact DFT of w g_a, whose cross spectrum with A over bin b's modes is
+// the Fourier-space dot product of the Fisher estimate
+// (Q^asym_b[a] = Theta_b A).  The z direction of g_a -> DFT[w g_a] is one
+// kernel over all bins (inverse z, window, forward z kept at kz < Kz), so
+// the fields g_a never go to HBM; the y and x forward passes follow per bin.
+// (z lengths without the half-length form write g_a [nb][N^3] and run the
+// windowed forward z pass per bin instead.)
+// Workspace: the plan's workspace, the z-transformed w g_b [nb][Nx Ny][Kz]
+// (or g_b), the compact A, chunk partials, the Fisher sums [nb^2] and the
+// data's box P [nb].
+static size_t masked_field_bytes(const pb3_plan& p) {
+  return zround_supported(p) ? sizeof(float2) * (size_t)p.Nx * p.Ny * p.Kz : sizeof(float) * npix(p);
+}
+
 size_t masked_workspace_bytes(const pb3_plan& p) {
-  const size_t A = 256, n3 = npix(p), nb = (size_t)p.nb;
+  const size_t A = 256, nb = (size_t)p.nb;
   auto up = [&](size_t b) { return (b + A - 1) / A * A; };
   const size_t dc = ncompact(p);
-  return up(workspace_bytes(&p)) + up(sizeof(float) * nb * n3) + up(sizeof(float2) * dc) +
-         up(sizeof(double) * std::max(p.n_chunks, 1)) + up(sizeof(double) * nb * nb) + up(sizeof(double) * nb);
+  return up(workspace_bytes(&p)) + up(nb * masked_field_bytes(p)) + up(sizeof(float2) * dc) +
+         up(sizeof(double) * nb * std::max(p.n_chunks, 1)) + up(sizeof(double) * nb * nb) + up(sizeof(double) * nb);
 }
 
 static pb3_status masked_tables(pb3_plan& p) {
@@ -555,19 +566,20 @@ pb3_status run_masked_power(pb3_plan& p, const float* data, const float* window,
                             double* pk_out, double* f_out, void* workspace, hipStream_t s) {
   pb3_status st = masked_tables(p);
   if (st != PB3_OK) return st;
-  const size_t A = 256, n3 = npix(p), dcn = ncompact(p);
+  const size_t A = 256, n3 = npix(p), dcn = ncompact(p), fb = masked_field_bytes(p);
   const int nb = p.nb, nt = nb * nb;
+  const bool zr = zround_supported(p);
   auto up = [&](size_t b) { return (b + A - 1) / A * A; };
   char* c = (char*)workspace;
   Exec x;
   x.ws = carve(&p, c, workspace_bytes(&p));
   c += up(workspace_bytes(&p));
-  float* fields = (float*)c;
-  c += up(sizeof(float) * nb * n3);
+  char* fields = c;  // per bin: w g_b after the z round trip, or g_b
+  c += up(nb * fb);
   float2* dca = (float2*)c;
   c += up(sizeof(float2) * dcn);
-  double* cpart = (double*)c;
-  c += up(sizeof(double) * std::max(p.n_chunks, 1));
+  double* cpart = (double*)c;  // per row a: the chunk partials of its cross spectrum
+  c += up(sizeof(double) * nb * std::max(p.n_chunks, 1));
   double* acc = (double*)c;
   c += up(sizeof(double) * nt);
   double* pbox = (double*)c;
@@ -588,21 +600,31 @@ pb3_status run_masked_power(pb3_plan& p, const float* data, const float* window,
     if (!forward(grfs[i], nullptr)) return st;
     if (!chk(hipMemcpyAsync(dca, x.ws.dc, sizeof(float2) * dcn, hipMemcpyDeviceToDevice, s), "masked power: copy"))
       return st;
-    // g_b = IDFT[Theta_b DFT[w a]] on the full grid
+    // g_b = IDFT[Theta_b DFT[w a]] on the full grid; with the round trip, w g_b through z both ways
     if (!forward(grfs[i], window) || !chk(launch_inv_x(p, x, s), "masked power: inv_x") ||
-        !chk(launch_inv_y(p, x, s), "masked power: inv_y") ||
-        !chk(run_inv_z(p, false, x.ws.a2, fields, p.tz, 1, 0, s), "masked power: inv_z"))
+        !chk(launch_inv_y(p, x, s), "masked power: inv_y"))
+      return st;
+    if (zr ? !chk(run_zround(p, x.ws.a2, window, (float2*)fields, s), "masked power: z round trip")
+           : !chk(run_inv_z(p, false, x.ws.a2, (float*)fields, p.tz, 1, 0, s), "masked power: inv_z"))
       return st;
     // row a: cross spectrum of DFT[w g_a] with A per bin
     for (int a = 0; a < nb; ++a) {
-      if (!forward(fields + (size_t)a * n3, window)) return st;
+      if (zr) {
+        Exec xa = x;
+        xa.ws.f1 = (float2*)(fields + (size_t)a * fb);
+        if (!chk(launch_fwd_y(p, xa, s), "masked power: fwd_y") || !chk(launch_fwd_x(p, x, s), "masked power: fwd_x"))
+          return st;
+      } else if (!forward((const float*)(fields + (size_t)a * fb), window)) {
+        return st;
+      }
       hipLaunchKernelGGL(k_cross_chunks, dim3(p.n_chunks), dim3(256), 0, s, x.ws.dc, dca, p.d.modes, p.d.chunk,
-                         cpart);
-      if (!chk(hipGetLastError(), "masked power: cross")) return st;
-      hipLaunchKernelGGL(k_cross_final, dim3((nb + 63) / 64), dim3(64), 0, s, cpart, p.d.chunk_first, nb,
-                         acc + (size_t)a * nb);
+                         cpart + (size_t)a * p.n_chunks);
       if (!chk(hipGetLastError(), "masked power: cross")) return st;
     }
+    // all rows' per-bin sums at once, each in the order of its chunks
+    hipLaunchKernelGGL(k_cross_final, dim3((nb + 63) / 64, nb), dim3(64), 0, s, cpart, p.n_chunks, p.d.chunk_first, nb,
+                       acc);
+    if (!chk(hipGetLastError(), "masked power: cross")) return st;
   }
   // numerator from the data's box power spectrum, then the solve
   x.io.pk[0] = pbox;
