@@ -49,9 +49,9 @@ MEASURED_TRAFFIC = {
         "fetch_kib": 138396.3, "write_kib": 30720.0, "fetch_factor": 2.0, "write_factor": 1.0,
         "sources": {
             "paper_2404_07249_amd/csrc/contract_mfma.hip":
-                "58cac322b7af6b6528e9c5c3b9300c9fb662ff2965665db28b481203ac96f393",
+                "a644e279a7f4f7d5212951b136696c322771c75e980315e1a41750445b1bb553",
             "paper_2404_07249_amd/csrc/fft_dev.h":
-                "df3b6d76c6673e67d4b39f61aa79139393ef94214581251510d14c1ded1023f4",
+                "2752fa569bc89ad3a05efa2efbe4f4ec86f50a872389150178fca1ac9217f2e2",
             "paper_2404_07249_amd/csrc/job.h":
                 "0f3d39c847bc50252698d89b0082866e4ca72f6f435cacd590aacb25667591d2",
         },
@@ -62,9 +62,9 @@ MEASURED_TRAFFIC = {
         "fetch_kib": 139862.5, "write_kib": 30720.0, "fetch_factor": 2.0, "write_factor": 1.0,
         "sources": {
             "paper_2404_07249_amd/csrc/contract_mfma.hip":
-                "58cac322b7af6b6528e9c5c3b9300c9fb662ff2965665db28b481203ac96f393",
+                "a644e279a7f4f7d5212951b136696c322771c75e980315e1a41750445b1bb553",
             "paper_2404_07249_amd/csrc/fft_dev.h":
-                "df3b6d76c6673e67d4b39f61aa79139393ef94214581251510d14c1ded1023f4",
+                "2752fa569bc89ad3a05efa2efbe4f4ec86f50a872389150178fca1ac9217f2e2",
             "paper_2404_07249_amd/csrc/job.h":
                 "0f3d39c847bc50252698d89b0082866e4ca72f6f435cacd590aacb25667591d2",
         },
