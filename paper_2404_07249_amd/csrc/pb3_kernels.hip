@@ -303,10 +303,15 @@ __global__ void __launch_bounds__(256) k_window_apply(const double* __restrict__
 // w Re(conj(V) A) over one chunk of one bin's mode list in FP64 (w as in
 // the power kernel), then per bin over its chunks in order, accumulated
 // into row[b].
-__global__ void __launch_bounds__(256) k_cross_chunks(const float2* __restrict__ dv, const float2* __restrict__ da,
+// Row blockIdx.y of a group of Fisher rows: its compact spectrum dv_stride
+// values after the previous row's, its chunk partials gridDim.x after.
+__global__ void __launch_bounds__(256) k_cross_chunks(const float2* __restrict__ dv, size_t dv_stride,
+                                                      const float2* __restrict__ da,
                                                       const int32_t* __restrict__ modes,
                                                       const int32_t* __restrict__ chunks, double* __restrict__ part) {
   __shared__ double red[256];
+  dv += (size_t)blockIdx.y * dv_stride;
+  part += (size_t)blockIdx.y * gridDim.x;
   const int c = blockIdx.x;
   const int start = chunks[3 * c + 1], end = chunks[3 * c + 2];
   double acc = 0.0;
@@ -533,19 +538,29 @@ hipError_t launch_reduce(const pb3_plan& p, const Exec& x, hipStream_t s, bool w
 // the fields g_a never go to HBM; the y and x forward passes follow per bin.
 // (z lengths without the half-length form write g_a [nb][N^3] and run the
 // windowed forward z pass per bin instead.)
+// The y and x forward passes and the cross spectra of up to kMaskedGroup
+// bins share launches (grid z, resp. y, is the bin), each bin's arrays one
+// field slot apart.
 // Workspace: the plan's workspace, the z-transformed w g_b [nb][Nx Ny][Kz]
-// (or g_b), the compact A, chunk partials, the Fisher sums [nb^2] and the
-// data's box P [nb].
+// (or g_b), the y and x pass outputs of a group of bins, the compact A,
+// chunk partials, the Fisher sums [nb^2] and the data's box P [nb].
+constexpr int kMaskedGroup = 8;
+
 static size_t masked_field_bytes(const pb3_plan& p) {
   return zround_supported(p) ? sizeof(float2) * (size_t)p.Nx * p.Ny * p.Kz : sizeof(float) * npix(p);
+}
+
+static size_t masked_group_bytes(const pb3_plan& p) {
+  return zround_supported(p) ? 2 * (size_t)std::min(kMaskedGroup, p.nb) * masked_field_bytes(p) : 0;
 }
 
 size_t masked_workspace_bytes(const pb3_plan& p) {
   const size_t A = 256, nb = (size_t)p.nb;
   auto up = [&](size_t b) { return (b + A - 1) / A * A; };
   const size_t dc = ncompact(p);
-  return up(workspace_bytes(&p)) + up(nb * masked_field_bytes(p)) + up(sizeof(float2) * dc) +
-         up(sizeof(double) * nb * std::max(p.n_chunks, 1)) + up(sizeof(double) * nb * nb) + up(sizeof(double) * nb);
+  return up(workspace_bytes(&p)) + up(nb * masked_field_bytes(p)) + up(masked_group_bytes(p)) +
+         up(sizeof(float2) * dc) + up(sizeof(double) * nb * std::max(p.n_chunks, 1)) + up(sizeof(double) * nb * nb) +
+         up(sizeof(double) * nb);
 }
 
 static pb3_status masked_tables(pb3_plan& p) {
@@ -576,6 +591,8 @@ pb3_status run_masked_power(pb3_plan& p, const float* data, const float* window,
   c += up(workspace_bytes(&p));
   char* fields = c;  // per bin: w g_b after the z round trip, or g_b
   c += up(nb * fb);
+  char* grp = c;  // the y pass outputs of a group of bins, then their compact spectra
+  c += up(masked_group_bytes(p));
   float2* dca = (float2*)c;
   c += up(sizeof(float2) * dcn);
   double* cpart = (double*)c;  // per row a: the chunk partials of its cross spectrum
@@ -607,19 +624,29 @@ pb3_status run_masked_power(pb3_plan& p, const float* data, const float* window,
     if (zr ? !chk(run_zround(p, x.ws.a2, window, (float2*)fields, s), "masked power: z round trip")
            : !chk(run_inv_z(p, false, x.ws.a2, (float*)fields, p.tz, 1, 0, s), "masked power: inv_z"))
       return st;
-    // row a: cross spectrum of DFT[w g_a] with A per bin
-    for (int a = 0; a < nb; ++a) {
-      if (zr) {
-        Exec xa = x;
-        xa.ws.f1 = (float2*)(fields + (size_t)a * fb);
-        if (!chk(launch_fwd_y(p, xa, s), "masked power: fwd_y") || !chk(launch_fwd_x(p, x, s), "masked power: fwd_x"))
+    // rows a: cross spectra of DFT[w g_a] with A per bin
+    if (zr) {
+      for (int a0 = 0; a0 < nb; a0 += kMaskedGroup) {
+        Exec xg = x;
+        xg.n_jobs = std::min(kMaskedGroup, nb - a0);
+        xg.wstride = fb;
+        xg.ws.f1 = (float2*)(fields + (size_t)a0 * fb);
+        xg.ws.f2 = (float2*)grp;
+        xg.ws.dc = (float2*)(grp + (size_t)xg.n_jobs * fb);
+        if (!chk(launch_fwd_y(p, xg, s), "masked power: fwd_y") || !chk(launch_fwd_x(p, xg, s), "masked power: fwd_x"))
           return st;
-      } else if (!forward((const float*)(fields + (size_t)a * fb), window)) {
-        return st;
+        hipLaunchKernelGGL(k_cross_chunks, dim3(p.n_chunks, xg.n_jobs), dim3(256), 0, s, (const float2*)xg.ws.dc,
+                           fb / sizeof(float2), (const float2*)dca, p.d.modes, p.d.chunk,
+                           cpart + (size_t)a0 * p.n_chunks);
+        if (!chk(hipGetLastError(), "masked power: cross")) return st;
       }
-      hipLaunchKernelGGL(k_cross_chunks, dim3(p.n_chunks), dim3(256), 0, s, x.ws.dc, dca, p.d.modes, p.d.chunk,
-                         cpart + (size_t)a * p.n_chunks);
-      if (!chk(hipGetLastError(), "masked power: cross")) return st;
+    } else {
+      for (int a = 0; a < nb; ++a) {
+        if (!forward((const float*)(fields + (size_t)a * fb), window)) return st;
+        hipLaunchKernelGGL(k_cross_chunks, dim3(p.n_chunks), dim3(256), 0, s, (const float2*)x.ws.dc, (size_t)0,
+                           (const float2*)dca, p.d.modes, p.d.chunk, cpart + (size_t)a * p.n_chunks);
+        if (!chk(hipGetLastError(), "masked power: cross")) return st;
+      }
     }
     // all rows' per-bin sums at once, each in the order of its chunks
     hipLaunchKernelGGL(k_cross_final, dim3((nb + 63) / 64, nb), dim3(64), 0, s, cpart, p.n_chunks, p.d.chunk_first, nb,
