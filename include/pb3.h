@@ -200,12 +200,15 @@ pb3_status pb3_window_normalize(const pb3_plan* plan, const float* w_dev, double
  *   pk_dev     n_bins float64 output, (Mpc/h)^3
  *   fisher_dev n_bins x n_bins float64 output (row a, column b) or NULL
  *   workspace  >= pb3_masked_power_workspace_bytes, 256-byte aligned
- *              (n_bins N^3 floats of filtered fields plus the plan's FFT
- *              buffers and partial sums)
+ *              (per bin the windowed filtered field after its z transform,
+ *              n_bins N^2 Kz complex values, or n_bins N^3 floats of
+ *              filtered fields for N < 64; the y and x transforms of 8 bins;
+ *              the plan's FFT buffers and partial sums)
  * Enqueued on `stream`; the first call on a plan also uploads a small
  * table synchronously.  Errors: PB3_EINVAL (null argument, host-only plan,
- * plan without the full grid, n_grf < 1), PB3_EUNSUPPORTED (> 48 bins),
- * PB3_ENOMEM (workspace too small), PB3_EDEVICE. */
+ * plan without the full grid, n_grf < 1), PB3_EUNSUPPORTED (> 48 bins,
+ * unequal grid sides or box sides), PB3_ENOMEM (workspace too small),
+ * PB3_EDEVICE. */
 size_t pb3_masked_power_workspace_bytes(const pb3_plan* plan);
 pb3_status pb3_masked_power(pb3_plan* plan, const float* data_dev, const float* window_dev,
                             const float* const* grfs_dev, int n_grf, double* pk_dev, double* fisher_dev,

@@ -1285,6 +1285,10 @@ pb3_status pb3_masked_power(pb3_plan* plan, const float* data_dev, const float* 
     set_error("the masked power spectrum is implemented for at most 48 bins");
     return PB3_EUNSUPPORTED;
   }
+  if (plan->Nx != plan->Ny || plan->Ny != plan->Nz || plan->aniso) {
+    set_error("the masked power spectrum is implemented for cubic grids and boxes");
+    return PB3_EUNSUPPORTED;
+  }
   if (workspace_bytes_ < masked_workspace_bytes(*plan) || ((uintptr_t)workspace_dev) % 256) {
     set_error("workspace too small or not 256-byte aligned: need " +
               std::to_string(masked_workspace_bytes(*plan)) + " bytes");

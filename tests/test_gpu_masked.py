@@ -39,7 +39,16 @@ def _gpu(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
 
 
-@pytest.mark.parametrize("n,box,nbins,ngrf", [(24, 600.0, 5, 3), (64, 1000.0, 12, 4), (128, 2000.0, 16, 2)])
+@pytest.mark.parametrize(
+    "n,box,nbins,ngrf",
+    [
+        (24, 600.0, 5, 3),  # z lines below 64 points: the separate inverse and forward z passes
+        (64, 1000.0, 12, 4),  # the z round trip at every half-length line factorisation from here on
+        (96, 1500.0, 10, 3),
+        (128, 2000.0, 16, 2),
+        (192, 2000.0, 8, 2),
+    ],
+)
 def test_masked_power_matches_oracle(torch_cuda, n, box, nbins, ngrf):
     import paper_2404_07249_amd as pb3
 
@@ -61,6 +70,20 @@ def test_masked_power_matches_oracle(torch_cuda, n, box, nbins, ngrf):
     rtol = masked_power_rtol(F_ref)  # about 4e-5: F and p within 1e-5, Skeel condition number about 2
     assert rtol < 5e-5
     assert np.all(np.abs(pk - p_ref) <= rtol * np.abs(p_ref)), np.abs(pk / p_ref - 1).max()
+
+
+def test_masked_power_refuses_unequal_sides(torch_cuda):
+    """The masked estimator is implemented (and checked against the oracle)
+    for cubic grids only; other plans get PB3_EUNSUPPORTED."""
+    import paper_2404_07249_amd as pb3
+
+    torch = torch_cuda
+    shape = (64, 64, 96)
+    plan = pb3.Plan(shape, 1000.0, kf_edges(6), full_grid=True, power_only=True)
+    x = torch.zeros(shape, dtype=torch.float32, device="cuda")
+    ws = torch.empty(plan.masked_workspace_bytes, dtype=torch.uint8, device="cuda")
+    with pytest.raises(RuntimeError, match="cubic"):
+        plan.masked_power(x, x, [x], workspace=ws)
 
 
 def test_masked_power_without_window_is_box_estimator_in_expectation(torch_cuda):
