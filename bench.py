@@ -99,21 +99,15 @@ def _cores() -> int:
         return os.cpu_count() or 1
 
 
-def stage_work(plan_info: dict, precision: str, fused_zy: bool = False) -> dict:
+def stage_work(plan_info: dict, precision: str) -> dict:
     """Algorithmic bytes (HBM-bound stages) or flops (contraction) of one
-    launch of each stage, from the plan geometry.  With fused_zy the forward
-    z and y passes are one launch (timed as the z stage) that reads the field
-    and writes the y pass's output."""
+    launch of each stage, from the plan geometry."""
     n, kz, lc, m, nb = plan_info["N"], plan_info["Kz"], plan_info["Lc"], plan_info["M"], plan_info["nb"]
     geom = plan_info["geom"]
     c8, f4 = 8, 4
     w = {}
-    if fused_zy:
-        w["fwd_z"] = ("hbm", n**3 * f4 + n * lc * kz * c8)
-        w["fwd_y"] = ("hbm", 0)
-    else:
-        w["fwd_z"] = ("hbm", n**3 * f4 + n * n * kz * c8)
-        w["fwd_y"] = ("hbm", n * n * kz * c8 + n * lc * kz * c8)
+    w["fwd_z"] = ("hbm", n**3 * f4 + n * n * kz * c8)
+    w["fwd_y"] = ("hbm", n * n * kz * c8 + n * lc * kz * c8)
     w["fwd_x"] = ("hbm", n * lc * kz * c8 + lc * lc * kz * c8)
     w["power"] = ("hbm", plan_info["n_modes_half"] * (4 + c8))
     w["inv_x"] = ("hbm", sum(ly * ly * kzn * c8 + m * ly * kzn * c8 for ly, kzn in geom))
@@ -601,8 +595,7 @@ def main(argv=None):
     main_p = args.precision
     r = results[main_p]
     value = args.steps / r["dt_eager"]
-    # the y stage records no time when the library runs the z and y passes as one launch
-    work = stage_work(info, main_p, fused_zy=r["stages"].get("fwd_y", (0.0, 0))[0] <= 0)
+    work = stage_work(info, main_p)
     dom = max(r["stages"], key=lambda k: r["stages"][k][0])
     kind, amount = work[dom]
     ms = r["stages"][dom][0]

@@ -167,120 +167,6 @@ __global__ void __launch_bounds__(256) k_fwd_zh(const JobIO io, float2* __restri
   }
 }
 
-// ------------------------------------------------ forward z and y, fused
-// One work-group per x slab of a cubic grid: the z transforms of the slab's
-// N lines (the half-length form above, kept at kz < Kz) into a slab S in
-// LDS, then the y transform of each of its Kz columns in place, kept at the
-// centred-compact rows, and the slab written once: f2[x][kyc][kz].  f1
-// never goes to HBM.  A slot of 16 lanes takes one line (z) or one column
-// (y) at a time, wave-synchronously; each z slot fetches its next line while
-// it transforms the current one.  S rows are KZP = Kz | 1 values long, so
-// a column's lanes fall in distinct LDS banks.
-template <int N> struct ZyShape {
-  static constexpr int H = N / 2, R1Z = H / 16, NS = 32, NT = NS * 16;
-  static constexpr int R1Y = fft2_r1(N), R2Y = N / R1Y;
-  static constexpr int EXZ = R1Z * 17, EXY = R1Y * (R2Y + 1);
-  static constexpr int EXB = NS * EXZ > 16 * EXY ? NS * EXZ : 16 * EXY;  // float2, shared by the phases
-  static constexpr int LDS_MAX = 163840;
-  static constexpr int AVAIL = (LDS_MAX - 8 * (EXB + N + H)) / (8 * N);
-  static constexpr int KZM = AVAIL < N / 2 + 2 ? AVAIL : N / 2 + 2;  // longest S row
-};
-// Only where the N slabs fill the chip: with one work-group per slab and
-// per CU (the slab takes most of the LDS), smaller grids would leave CUs idle.
-constexpr bool zy_form(int n) { return n == 256; }
-
-template <int N>
-__global__ void __launch_bounds__(512) k_fwd_zy(const JobIO io, float2* __restrict__ f2, size_t wstride, int Kz,
-                                                int Lc, int Kc, const float2* __restrict__ tw) {
-  using S = ZyShape<N>;
-  constexpr int H = S::H, R1Z = S::R1Z, NS = S::NS, NT = S::NT, R1Y = S::R1Y, R2Y = S::R2Y;
-  static_assert(R1Z * 16 == H && R1Y <= 16 && R2Y <= 16, "16-lane slots");
-  static_assert(8 * (S::EXB + N + H + N * S::KZM) <= S::LDS_MAX, "LDS");
-  const float* __restrict__ delta = io.delta[blockIdx.z];
-  const float* __restrict__ win = io.window;
-  f2 = job_ptr(f2, wstride);
-  __shared__ float2 tws[N];  // W_N^m
-  __shared__ float2 twh[H];  // W_H^m = W_N^(2m)
-  __shared__ float2 ex[S::EXB];
-  __shared__ float2 sl[N * S::KZM];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < N; e += NT) {
-    const float2 w = tw[e];
-    tws[e] = w;
-    if (!(e & 1)) twh[e >> 1] = w;
-  }
-  __syncthreads();
-  const int kzp = Kz | 1;
-  const int x = blockIdx.x, ln = tid >> 4, tl = tid & 15;
-  {
-    float2* xl = ex + ln * S::EXZ;
-    float2 v[R1Z];  // this lane's inputs m = tl + 16 j of the line, as pairs of real samples
-    auto fetch = [&](int y) {
-      const size_t off = ((size_t)x * N + y) * N;
-      const float2* zl = reinterpret_cast<const float2*>(delta + off);
-      const float2* wl = win ? reinterpret_cast<const float2*>(win + off) : nullptr;  // optional window
-#pragma unroll
-      for (int j = 0; j < R1Z; ++j) {
-        float2 a = zl[tl + 16 * j];
-        if (wl) {
-          const float2 w = wl[tl + 16 * j];
-          a.x *= w.x;
-          a.y *= w.y;
-        }
-        v[j] = a;
-      }
-    };
-    fetch(ln);
-    for (int y = ln; y < N; y += NS) {
-      fft2_line_wave<H, -1, R1Z>(
-          xl, tl, twh, [&](int j, int) { return v[j]; },
-          [&] {
-            if (y + NS < N) fetch(y + NS);
-          },
-          [&](int k1, const float2 (&u)[16]) {
-#pragma unroll
-            for (int k2 = 0; k2 < 16; ++k2) xl[k1 + R1Z * k2] = u[k2];
-          });
-      float2* row = sl + y * kzp;
-      for (int k = tl; k < Kz; k += 16) {
-        const int kh = k % H;
-        const float2 a = xl[kh], b = xl[(H - kh) % H];
-        const float ex0 = 0.5f * (a.x + b.x), ey0 = 0.5f * (a.y - b.y);  // E[k]
-        const float ox = 0.5f * (a.y + b.y), oy = -0.5f * (a.x - b.x);   // O[k]
-        const float2 w = tws[k];                                         // k < Kz <= N/2 + 1
-        row[k] = make_float2(ex0 + w.x * ox - w.y * oy, ey0 + w.x * oy + w.y * ox);
-      }
-      // the next line's transform writes these exchange rows again
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-  }
-  __syncthreads();
-  if (ln < 16) {
-    float2* yx = ex + ln * S::EXY;
-    for (int kz = ln; kz < Kz; kz += 16) {
-      fft2_line_wave<N, -1>(
-          yx, tl, tws, [&](int, int n) { return sl[n * kzp + kz]; }, [] {},
-          [&](int k1, const float2 (&u)[R2Y]) {
-            // the column's inputs were all read in phase 1: its compact rows overwrite them
-#pragma unroll
-            for (int k2 = 0; k2 < R2Y; ++k2) {
-              const int k = k1 + R1Y * k2;
-              const int c = (k >= N - Kc ? k - N : k) + Kc;
-              if (c >= 0 && c < Lc) sl[c * kzp + kz] = u[k2];
-            }
-          });
-    }
-  }
-  __syncthreads();
-  float2* dst = f2 + (size_t)x * Lc * Kz;
-  for (int e = tid; e < Lc * Kz; e += NT) {
-    const int c = e / Kz, kz = e - c * Kz;
-    dst[e] = sl[c * kzp + kz];
-  }
-}
-
 // --------------------------------------------------- forward strided c2c
 // out row c <- frequency f = c - Ko (kept when 0 <= c < Lo).
 template <int N>
@@ -757,32 +643,6 @@ static hipError_t fwd_col(const Exec& x, int len, const float2* tw, int Lo, int 
   });
   return hipErrorInvalidValue;
 }
-bool fwd_zy_supported(const pb3_plan& p) {
-  if (p.Nx != p.Ny || p.Ny != p.Nz || !zy_form(p.Nz)) return false;
-  int kzm = 0;
-  PB3_FFT_LEN(p.Nz, {
-    if constexpr (zy_form(LL)) kzm = ZyShape<LL>::KZM;
-    break;
-  });
-  return (p.Kz | 1) <= kzm;
-}
-
-hipError_t launch_fwd_zy(const pb3_plan& p, const Exec& x, hipStream_t s) {
-  if (!fwd_zy_supported(p)) {
-    hipError_t e = launch_fwd_z(p, x, s);
-    return e != hipSuccess ? e : launch_fwd_y(p, x, s);
-  }
-  PB3_FFT_LEN(p.Nz, {
-    if constexpr (zy_form(LL)) {
-      hipLaunchKernelGGL(k_fwd_zy<LL>, dim3(p.Nx, 1, x.n_jobs), dim3(ZyShape<LL>::NT), 0, s, x.io, x.ws.f2,
-                         x.wstride, p.Kz, p.Lcy, p.Kcy, p.d.tw_n[2]);
-      return hipGetLastError();
-    }
-    break;
-  });
-  return hipErrorInvalidValue;
-}
-
 hipError_t launch_fwd_y(const pb3_plan& p, const Exec& x, hipStream_t s) {
   // f1[x][y][kz] -> f2[x][kyc][kz]
   return fwd_col(x, p.Ny, p.d.tw_n[1], p.Lcy, p.Kcy, x.ws.f1, x.ws.f2, p.Kz, (long)p.Ny * p.Kz, (long)p.Lcy * p.Kz,

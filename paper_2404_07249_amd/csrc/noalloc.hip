@@ -99,7 +99,8 @@ pb3_status pb3_power_noalloc(pb3_plan* plan, const float* delta_dev, double* pk_
   x.io.delta[0] = delta_dev;
   x.io.pk[0] = pk_dev;
   const hipStream_t s = (hipStream_t)stream;
-  if ((e = launch_fwd_zy(*plan, x, s)) != hipSuccess) return hip_fail(e, "fwd_zy");
+  if ((e = launch_fwd_z(*plan, x, s)) != hipSuccess) return hip_fail(e, "fwd_z");
+  if ((e = launch_fwd_y(*plan, x, s)) != hipSuccess) return hip_fail(e, "fwd_y");
   if ((e = launch_fwd_x(*plan, x, s)) != hipSuccess) return hip_fail(e, "fwd_x");
   if ((e = launch_power(*plan, x, s, true)) != hipSuccess) return hip_fail(e, "power");
   return PB3_OK;

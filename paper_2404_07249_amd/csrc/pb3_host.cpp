@@ -943,13 +943,8 @@ static pb3_status enqueue_w(const pb3_plan& p, const Exec& x, bool do_pk, bool d
   // unweighted plans the inverse x pass takes the sums over the modes it gathers anyway
   const bool merge = do_pk && do_bk && !p.trip.empty();
   const bool fold = power_folded(p, do_pk, do_bk);
-  if (fwd_zy_supported(p)) {
-    // one launch for both directions; the y stage records no time of its own
-    if ((st = wrap(ST_FWD_Z, "fwd_zy", [&] { return launch_fwd_zy(p, x, s); })) != PB3_OK) return st;
-  } else {
-    if ((st = wrap(ST_FWD_Z, "fwd_z", [&] { return launch_fwd_z(p, x, s); })) != PB3_OK) return st;
-    if ((st = wrap(ST_FWD_Y, "fwd_y", [&] { return launch_fwd_y(p, x, s); })) != PB3_OK) return st;
-  }
+  if ((st = wrap(ST_FWD_Z, "fwd_z", [&] { return launch_fwd_z(p, x, s); })) != PB3_OK) return st;
+  if ((st = wrap(ST_FWD_Y, "fwd_y", [&] { return launch_fwd_y(p, x, s); })) != PB3_OK) return st;
   if ((st = wrap(ST_FWD_X, "fwd_x", [&] { return launch_fwd_x(p, x, s); })) != PB3_OK) return st;
   if (do_pk && !fold) {
     if ((st = wrap(ST_POWER, "power", [&] { return launch_power(p, x, s, !merge); })) != PB3_OK) return st;
@@ -981,7 +976,7 @@ pb3_status enqueue(const pb3_plan& p, const Exec& x, bool do_pk, bool do_bk, pb3
 
 // kernel launches of one enqueue (for reporting)
 int launches_per_sequence(const pb3_plan& p, bool do_pk, bool do_bk) {
-  int n = fwd_zy_supported(p) ? 2 : 3;
+  int n = 3;
   if (do_pk && !power_folded(p, do_pk, do_bk)) n += (do_bk && !p.trip.empty()) ? 1 : 2;
   if (do_bk) {
     n += 2 + 2;

@@ -215,10 +215,6 @@ int launches_per_sequence(const pb3_plan& p, bool do_pk, bool do_bk);
 // kernel launchers (pb3_kernels.hip); all return hipGetLastError()
 hipError_t launch_fwd_z(const pb3_plan& p, const Exec& x, hipStream_t s);
 hipError_t launch_fwd_y(const pb3_plan& p, const Exec& x, hipStream_t s);
-// the forward z and y passes as one launch (one x slab per work-group) where the slab
-// fits in LDS and the slabs fill the chip (256^3 with Kz <= 61), else the two passes
-bool fwd_zy_supported(const pb3_plan& p);
-hipError_t launch_fwd_zy(const pb3_plan& p, const Exec& x, hipStream_t s);
 hipError_t launch_fwd_x(const pb3_plan& p, const Exec& x, hipStream_t s);
 // final = false leaves the per-bin sums to launch_reduce(..., with_pk = true).
 hipError_t launch_power(const pb3_plan& p, const Exec& x, hipStream_t s, bool final);

@@ -607,7 +607,8 @@ pb3_status run_masked_power(pb3_plan& p, const float* data, const float* window,
   auto forward = [&](const float* f, const float* w) {
     x.io.delta[0] = f;
     x.io.window = w;
-    return chk(launch_fwd_zy(p, x, s), "masked power: fwd_zy") && chk(launch_fwd_x(p, x, s), "masked power: fwd_x");
+    return chk(launch_fwd_z(p, x, s), "masked power: fwd_z") && chk(launch_fwd_y(p, x, s), "masked power: fwd_y") &&
+           chk(launch_fwd_x(p, x, s), "masked power: fwd_x");
   };
   hipLaunchKernelGGL(k_fill_zero, dim3((nt + 255) / 256), dim3(256), 0, s, acc, nt);
   if (!chk(hipGetLastError(), "masked power: clear")) return st;
@@ -702,7 +703,8 @@ pb3_status run_multipoles(pb3_plan& p, const float* delta, double* pk_out, doubl
     return r == hipSuccess;
   };
   x.io.delta[0] = delta;
-  if (!chk(launch_fwd_zy(p, x, s), "multipoles: fwd_zy") || !chk(launch_fwd_x(p, x, s), "multipoles: fwd_x"))
+  if (!chk(launch_fwd_z(p, x, s), "multipoles: fwd_z") || !chk(launch_fwd_y(p, x, s), "multipoles: fwd_y") ||
+      !chk(launch_fwd_x(p, x, s), "multipoles: fwd_x"))
     return st;
   if (pk_out) {
     hipLaunchKernelGGL(k_power_ml_chunks, dim3(p.n_chunks), dim3(256), 0, s, x.ws.dc, p.d.modes, p.d.chunk, p.Lcy,
