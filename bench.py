@@ -212,6 +212,39 @@ def batched_bench(reps: int = 10, warmup: int = 2, precision: str = "mixed", aut
     }
 
 
+def masked_bench(reps: int = 3, warmup: int = 2, n_mc: int = 8) -> dict:
+    """The masked power spectrum with its Monte Carlo Fisher matrix (the
+    dominant part of a serving request) on full-grid, power-only plans:
+    a random window of 95% ones, masked Gaussian data and n_mc white random
+    fields, all drawn on the device; ms per call."""
+    import torch
+
+    import paper_2404_07249_amd as pb3
+    from synthetic import kf_edges
+
+    out = {}
+    for n, nb in ((384, 40), (256, 30), (128, 20)):
+        plan = pb3.Plan(n, 2000.0, kf_edges(nb), full_grid=True, power_only=True)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(1)
+        w = (torch.rand((n, n, n), generator=g, device="cuda") < 0.95).float()
+        d = torch.randn((n, n, n), generator=g, device="cuda") * w
+        grfs = [torch.randn((n, n, n), generator=g, device="cuda") for _ in range(n_mc)]
+        ws = torch.empty(plan.masked_workspace_bytes, dtype=torch.uint8, device="cuda")
+        for _ in range(warmup):
+            plan.masked_power(d, w, grfs, workspace=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan.masked_power(d, w, grfs, workspace=ws)
+        torch.cuda.synchronize()
+        out[f"{n}^3x{nb}"] = {"ms_per_call": round(1e3 * (time.perf_counter() - t0) / reps, 2), "n_mc": n_mc,
+                              "workspace_gb": round(plan.masked_workspace_bytes / 1e9, 2)}
+        del grfs, ws, w, d
+        torch.cuda.empty_cache()
+    return out
+
+
 def serving_bench(n_requests: int = 200, rate: float = 20.0, budget_gb: float = 96.0, slots: int = 4,
                   precision: str = "mixed", n_mc: int = 8) -> dict:
     """Poisson request stream through the continuous-batching server: grids
@@ -520,12 +553,17 @@ def main(argv=None):
                     help="only run a plain 256 MiB device copy three times (calibrates the traffic counters)")
     ap.add_argument("--batched-only", action="store_true",
                     help="only run the batched-workload measurement (default launch shapes) and print its JSON")
+    ap.add_argument("--masked-only", action="store_true",
+                    help="only time the masked power spectrum with 8 Monte Carlo fields and print its JSON")
     args = ap.parse_args(argv)
     if args.copy_calibration:
         return copy_calibration()
     if args.batched_only:
         r = batched_bench(reps=5, warmup=2, precision=args.precision, autotune=False)
         print(json.dumps({"batched": r}), flush=True)
+        return 0
+    if args.masked_only:
+        print(json.dumps({"masked_power": masked_bench()}), flush=True)
         return 0
     if args.gpus != 1:
         print(
